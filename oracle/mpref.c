@@ -1,0 +1,714 @@
+/*
+ * mpref.c -- plain CPU oracle for double-double (DD), triple-double (TD) and
+ * quad-double (QD) matrix multiplication built from error-free transformations
+ * (Kouya, "Acceleration of multiple precision matrix multiplication based on
+ * multi-component floating-point arithmetic using AVX2", arXiv 2101.06584).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the library's product path links,
+ * loads or calls this file; only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg do.  It shares no source with the GPU code.
+ *
+ * It is deliberately scalar and unblocked: one multi-component number at a
+ * time, each operation in the order the paper prints it, so that a reader can
+ * check it against Algorithms 1-6 by eye.  Built with -ffp-contract=off and no
+ * fast-math: every '+', '-', '*' is one IEEE-754 binary64 operation in
+ * round-to-nearest-even, and fma() is the correctly rounded fused multiply-add.
+ *
+ * Readings of points the paper leaves open (TwoSum/QuickTwoSum/TwoProd bodies,
+ * ThreeSum, ThreeSum2, VecSum, VSEB(k), Renorm, the missing t3 line of the QD
+ * addition, the dead first line of the QD multiplication, the TD addition
+ * through the QD one, the GEMM summation order) are stated at each function.
+ *
+ * Parity pins: every function here is pinned by the CPU tests (exact rational
+ * invariants, error bounds against the exact result, closed forms, brute
+ * force on small inputs).  Parity unpinned: none.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define EXPORT __attribute__((visibility("default")))
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 2.1: error-free transformations.                                    */
+/* ------------------------------------------------------------------------ */
+
+/* QuickTwoSum (Dekker's Fast2Sum): s = fl(a+b), e = b - (s - a).  Exact
+ * (s + e == a + b) when exponent(a) >= exponent(b). */
+static void quick_two_sum(double a, double b, double *s, double *e)
+{
+    double sum = a + b;
+    double back = sum - a;
+    *e = b - back;
+    *s = sum;
+}
+
+/* TwoSum (Knuth), in the operation order spelled out lane by lane in the QD
+ * addition (Algorithm 5): s, v = s - a, u = s - v, w = a - u, u' = b - v,
+ * e = w + u'.  Always exact. */
+static void two_sum(double a, double b, double *s, double *e)
+{
+    double sum = a + b;
+    double v = sum - a;
+    double u = sum - v;
+    double w = a - u;
+    double u2 = b - v;
+    *e = w + u2;
+    *s = sum;
+}
+
+/* TwoProd with FMA: p = fl(ab), e = fma(a, b, -p) = ab - p exactly (barring
+ * underflow). */
+static void two_prod(double a, double b, double *p, double *e)
+{
+    double prod = a * b;
+    *e = fma(a, b, -prod);
+    *p = prod;
+}
+
+/* ThreeSum (a, b, c) -> (a', b', c'), three TwoSums, sum preserved exactly.
+ * Not printed in the paper; read as the three-term sum of the quad-double
+ * algorithms the paper builds on (its QD library reference). */
+static void three_sum(double *a, double *b, double *c)
+{
+    double t1, t2, t3;
+    two_sum(*a, *b, &t1, &t2);
+    two_sum(*c, t1, a, &t3);
+    two_sum(t2, t3, b, c);
+}
+
+/* ThreeSum2 (a, b, c) -> (a', b'): the first two TwoSums of ThreeSum, then a
+ * rounded add of the two error terms. */
+static void three_sum2(double *a, double *b, double c)
+{
+    double t1, t2, t3;
+    two_sum(*a, *b, &t1, &t2);
+    two_sum(c, t1, a, &t3);
+    *b = t2 + t3;
+}
+
+/* VecSum (Sec. 2.3, from the triple-word arithmetic the paper cites): a
+ * bottom-up chain of TwoSums, s = x[n-1]; for i = n-2..0:
+ * (s, e[i+1]) = TwoSum(x[i], s); e[0] = s.  Error-free.  x and e may alias. */
+static void vec_sum(const double *x, int n, double *e)
+{
+    double s = x[n - 1];
+    for (int i = n - 2; i >= 0; --i)
+        two_sum(x[i], s, &s, &e[i + 1]);
+    e[0] = s;
+}
+
+/* VSEB(k) ("VecSum with branch", Sec. 2.3): a top-down QuickTwoSum pass that
+ * keeps a partial sum while the rounding error is zero and emits it as the
+ * next output term otherwise; after k terms the rest is dropped.  Outputs not
+ * reached are zero.  The test "error != 0" treats -0 as zero. */
+static void vseb(const double *e, int n, double *r, int k)
+{
+    for (int q = 0; q < k; ++q)
+        r[q] = 0.0;
+    int j = 0;
+    double carry = e[0];
+    for (int i = 1; i < n; ++i) {
+        double s, t;
+        quick_two_sum(carry, e[i], &s, &t);
+        if (t != 0.0) {
+            r[j++] = s;
+            carry = t;
+            if (j == k)
+                return;
+        } else {
+            carry = s;
+        }
+    }
+    r[j] = carry;
+}
+
+/* Renorm (Sec. 2.4, "renormalization ... as simple loops"): five terms to a
+ * four-component number.
+ * Pass 1: bottom-up QuickTwoSum chain c4 -> c0 giving e[0..4].
+ * Pass 2: top-down, the pair (e0, e1) as produced by pass 1, then
+ * QuickTwoSum(carry, e[i]) for i = 2..4; a non-zero error term closes an
+ * output slot (the sum becomes that slot, the error the new carry).  When the
+ * third slot closes, the last slot takes the carry plus the remaining e's
+ * (plain adds, left to right).  Otherwise the carry fills the next open slot
+ * and later slots are zero. */
+static void renorm4(double c0, double c1, double c2, double c3, double c4, double r[4])
+{
+    double e[5];
+    double s;
+    quick_two_sum(c3, c4, &s, &e[4]);
+    quick_two_sum(c2, s, &s, &e[3]);
+    quick_two_sum(c1, s, &s, &e[2]);
+    quick_two_sum(c0, s, &s, &e[1]);
+    e[0] = s;
+
+    r[0] = r[1] = r[2] = r[3] = 0.0;
+    int j = 0;
+    double carry = 0.0;
+    for (int i = 1; i <= 4; ++i) {
+        double sv, t;
+        if (i == 1) {
+            sv = e[0];
+            t = e[1];
+        } else {
+            quick_two_sum(carry, e[i], &sv, &t);
+        }
+        if (t != 0.0) {
+            r[j++] = sv;
+            carry = t;
+            if (j == 3) {
+                double tail = carry;
+                for (int q = i + 1; q <= 4; ++q)
+                    tail = tail + e[q];
+                r[3] = tail;
+                return;
+            }
+        } else {
+            carry = sv;
+        }
+    }
+    r[j] = carry;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 2.2: DD addition (Algorithm 1) and multiplication (Algorithm 2).    */
+/* ------------------------------------------------------------------------ */
+
+static void dd_add(const double *x, const double *y, double *r)
+{
+    double s, e;
+    two_sum(x[0], y[0], &s, &e);
+    double w = x[1] + y[1];
+    e = e + w;
+    quick_two_sum(s, e, &r[0], &r[1]);
+}
+
+/* Algorithm 2: the two cross products are separate rounded multiplies and
+ * the sums separate rounded adds (no fused multiply-add there). */
+static void dd_mul(const double *x, const double *y, double *r)
+{
+    double p1, p2;
+    two_prod(x[0], y[0], &p1, &p2);
+    double w1 = x[0] * y[1];
+    double w2 = x[1] * y[0];
+    double w3 = w1 + w2;
+    p2 = p2 + w3;
+    quick_two_sum(p1, p2, &r[0], &r[1]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 2.4: QD addition (Algorithm 5) and multiplication (Algorithm 6).    */
+/* ------------------------------------------------------------------------ */
+
+/* Algorithm 5.  Four lane-wise TwoSums (x[i] + y[i] -> s_i, t_i), then the
+ * carries are folded in.  The listing uses t3 without defining it; it is the
+ * error term of the fourth lane, t3 = w3 + u3, like t0..t2. */
+static void qd_add(const double *x, const double *y, double *r)
+{
+    double s0 = x[0] + y[0], s1 = x[1] + y[1], s2 = x[2] + y[2], s3 = x[3] + y[3];
+    double v0 = s0 - x[0], v1 = s1 - x[1], v2 = s2 - x[2], v3 = s3 - x[3];
+    double u0 = s0 - v0, u1 = s1 - v1, u2 = s2 - v2, u3 = s3 - v3;
+    double w0 = x[0] - u0, w1 = x[1] - u1, w2 = x[2] - u2, w3 = x[3] - u3;
+    u0 = y[0] - v0;
+    u1 = y[1] - v1;
+    u2 = y[2] - v2;
+    u3 = y[3] - v3;
+    double t0 = w0 + u0, t1 = w1 + u1, t2 = w2 + u2, t3 = w3 + u3;
+
+    two_sum(s1, t0, &s1, &t0);
+    three_sum(&s2, &t0, &t1);
+    three_sum2(&s3, &t0, t2);
+    t0 = (t0 + t1) + t3;
+    renorm4(s0, s1, s2, s3, t0, r);
+}
+
+/* Algorithm 6.  The listing's first line (s0 = x0 + y0) is overwritten before
+ * any use and is omitted.  The O(eps^3) terms are added to s1 one at a time
+ * in the printed order, each a rounded multiply and a rounded add. */
+static void qd_mul(const double *x, const double *y, double *r)
+{
+    double p0, q0, p1, q1, p2, q2, p3, q3, p4, q4, p5, q5;
+    two_prod(x[0], y[0], &p0, &q0);
+    two_prod(x[0], y[1], &p1, &q1);
+    two_prod(x[1], y[0], &p2, &q2);
+    two_prod(x[0], y[2], &p3, &q3);
+    two_prod(x[1], y[1], &p4, &q4);
+    two_prod(x[2], y[0], &p5, &q5);
+
+    three_sum(&p1, &p2, &q0);
+    three_sum(&p2, &q1, &q2);
+    three_sum(&p3, &p4, &p5);
+
+    double s0, t0, s1, t1, s2;
+    two_sum(p2, p3, &s0, &t0);
+    two_sum(q1, p4, &s1, &t1);
+    s2 = q2 + p5;
+    two_sum(s1, t0, &s1, &t0);
+    s2 = s2 + (t0 + t1);
+
+    s1 = s1 + x[0] * y[3];
+    s1 = s1 + x[1] * y[2];
+    s1 = s1 + x[2] * y[1];
+    s1 = s1 + x[3] * y[0];
+    s1 = s1 + q0;
+    s1 = s1 + q3;
+    s1 = s1 + q4;
+    s1 = s1 + q5;
+    renorm4(p0, p1, s0, s1, s2, r);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 2.3: TD addition (TDaddq) and multiplication (Algorithm 4).         */
+/* ------------------------------------------------------------------------ */
+
+/* TDaddq: the QD addition applied to (x0, x1, x2, 0) and (y0, y1, y2, 0), the
+ * paper's default TD addition; the fourth output component is dropped. */
+static void td_addq(const double *x, const double *y, double *r)
+{
+    double xq[4] = {x[0], x[1], x[2], 0.0};
+    double yq[4] = {y[0], y[1], y[2], 0.0};
+    double rq[4];
+    qd_add(xq, yq, rq);
+    r[0] = rq[0];
+    r[1] = rq[1];
+    r[2] = rq[2];
+}
+
+/* Algorithm 4 ("fast" triple-word product).  b0..b2 are VecSum outputs, not
+ * operand components. */
+static void td_mul(const double *x, const double *y, double *r)
+{
+    double z00u, z00l, z01u, z01l, z10u, z10l;
+    two_prod(x[0], y[0], &z00u, &z00l);
+    two_prod(x[0], y[1], &z01u, &z01l);
+    two_prod(x[1], y[0], &z10u, &z10l);
+    double in3[3] = {z00l, z01u, z10u};
+    double b[3];
+    vec_sum(in3, 3, b);
+    double c = fma(x[1], y[1], b[2]);
+    double z31 = fma(x[0], y[2], z10l);
+    double z32 = fma(x[2], y[0], z01l);
+    double z3 = z31 + z32;
+    double s3 = c + z3;
+    double in4[4] = {z00u, b[0], b[1], s3};
+    double e[4];
+    vec_sum(in4, 4, e);
+    r[0] = e[0];
+    vseb(&e[1], 3, &r[1], 2);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Precision dispatch.                                                      */
+/* ------------------------------------------------------------------------ */
+
+static void mp_add(int P, const double *x, const double *y, double *r)
+{
+    if (P == 2)
+        dd_add(x, y, r);
+    else if (P == 3)
+        td_addq(x, y, r);
+    else
+        qd_add(x, y, r);
+}
+
+static void mp_mul(int P, const double *x, const double *y, double *r)
+{
+    if (P == 2)
+        dd_mul(x, y, r);
+    else if (P == 3)
+        td_mul(x, y, r);
+    else
+        qd_mul(x, y, r);
+}
+
+static int mp_is_zero(int P, const double *x)
+{
+    for (int c = 0; c < P; ++c)
+        if (x[c] != 0.0)
+            return 0;
+    return 1;
+}
+
+static int mp_is_one(int P, const double *x)
+{
+    if (x[0] != 1.0)
+        return 0;
+    for (int c = 1; c < P; ++c)
+        if (x[c] != 0.0)
+            return 0;
+    return 1;
+}
+
+static int is_trans(char t) { return t == 'T' || t == 't' || t == 'C' || t == 'c'; }
+
+/* op(A)(i, l) of a column-major component-plane matrix. */
+static void load_op(int P, char t, const double *A, int64_t ld, int64_t ps,
+                    int64_t i, int64_t l, double *out)
+{
+    int64_t off = is_trans(t) ? (l + i * ld) : (i + l * ld);
+    for (int c = 0; c < P; ++c)
+        out[c] = A[c * ps + off];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exported element-wise operations and primitives (for pinning).           */
+/* ------------------------------------------------------------------------ */
+
+/* r[i] = x[i] (+ or *) y[i] for i < n; planes at the given strides. */
+EXPORT void ref_vec(int P, int op, int64_t n, const double *x, int64_t sx,
+                    const double *y, int64_t sy, double *r, int64_t sr)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double a[4], b[4], o[4];
+        for (int c = 0; c < P; ++c) {
+            a[c] = x[c * sx + i];
+            b[c] = y[c * sy + i];
+        }
+        if (op == 0)
+            mp_add(P, a, b, o);
+        else
+            mp_mul(P, a, b, o);
+        for (int c = 0; c < P; ++c)
+            r[c * sr + i] = o[c];
+    }
+}
+
+/* Primitive under test, applied to n argument tuples stored argument-major
+ * (in[a * n + i]); results stored result-major (out[q * n + i]).
+ *   0 quick_two_sum(a,b)->(s,e)   1 two_sum(a,b)->(s,e)
+ *   2 two_prod(a,b)->(p,e)        3 three_sum(a,b,c)->(a,b,c)
+ *   4 three_sum2(a,b,c)->(a,b)    5 vec_sum(x0..x3)->(e0..e3)
+ *   6 vseb2(e0,e1,e2)->(r0,r1)    7 renorm4(c0..c4)->(r0..r3)
+ *   8 vseb3(e0..e5)->(r0,r1,r2)   9 vec_sum(x0..x2)->(e0..e2) */
+EXPORT int ref_prim(int which, int64_t n, const double *in, double *out)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double a[6], o[6];
+        switch (which) {
+        case 0:
+            quick_two_sum(in[i], in[n + i], &o[0], &o[1]);
+            out[i] = o[0]; out[n + i] = o[1];
+            break;
+        case 1:
+            two_sum(in[i], in[n + i], &o[0], &o[1]);
+            out[i] = o[0]; out[n + i] = o[1];
+            break;
+        case 2:
+            two_prod(in[i], in[n + i], &o[0], &o[1]);
+            out[i] = o[0]; out[n + i] = o[1];
+            break;
+        case 3:
+            a[0] = in[i]; a[1] = in[n + i]; a[2] = in[2 * n + i];
+            three_sum(&a[0], &a[1], &a[2]);
+            for (int q = 0; q < 3; ++q) out[q * n + i] = a[q];
+            break;
+        case 4:
+            a[0] = in[i]; a[1] = in[n + i]; a[2] = in[2 * n + i];
+            three_sum2(&a[0], &a[1], a[2]);
+            out[i] = a[0]; out[n + i] = a[1];
+            break;
+        case 5:
+            for (int q = 0; q < 4; ++q) a[q] = in[q * n + i];
+            vec_sum(a, 4, o);
+            for (int q = 0; q < 4; ++q) out[q * n + i] = o[q];
+            break;
+        case 6:
+            for (int q = 0; q < 3; ++q) a[q] = in[q * n + i];
+            vseb(a, 3, o, 2);
+            out[i] = o[0]; out[n + i] = o[1];
+            break;
+        case 7:
+            renorm4(in[i], in[n + i], in[2 * n + i], in[3 * n + i], in[4 * n + i], o);
+            for (int q = 0; q < 4; ++q) out[q * n + i] = o[q];
+            break;
+        case 8:
+            for (int q = 0; q < 6; ++q) a[q] = in[q * n + i];
+            vseb(a, 6, o, 3);
+            for (int q = 0; q < 3; ++q) out[q * n + i] = o[q];
+            break;
+        case 9:
+            for (int q = 0; q < 3; ++q) a[q] = in[q * n + i];
+            vec_sum(a, 3, o);
+            for (int q = 0; q < 3; ++q) out[q * n + i] = o[q];
+            break;
+        default:
+            return -1;
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 3, eqn (1): C = alpha op(A) op(B) + beta C, canonical order.        */
+/* ------------------------------------------------------------------------ */
+
+/* The paper computes c_ij as the sum over k of a_ik b_kj (eqn (1)) and leaves
+ * the in-block order open.  Reading: for every entry, one running sum
+ * acc = 0; for l = 0..k-1 ascending: acc = ADD(acc, MUL(a_il, b_lj)); then
+ *   beta == 0:          c = MUL(alpha, acc)            (C is not read)
+ *   otherwise:          c = ADD(MUL(alpha, acc), MUL(beta, c_old))
+ *   alpha == 0 or k==0: c = beta == 0 ? 0 : MUL(beta, c_old)
+ * and nothing is written when m == 0, n == 0, or (alpha == 0 or k == 0) and
+ * beta == 1.  Only rows row0 <= i < row1 are computed (row1 < 0: all). */
+static void epilogue(int P, const double *alpha, const double *acc, const double *beta,
+                     double *c_io, int alpha_or_k_zero)
+{
+    double t1[4], t2[4];
+    int beta_zero = mp_is_zero(P, beta);
+    if (alpha_or_k_zero) {
+        if (beta_zero) {
+            for (int c = 0; c < P; ++c) c_io[c] = 0.0;
+        } else {
+            mp_mul(P, beta, c_io, t2);
+            for (int c = 0; c < P; ++c) c_io[c] = t2[c];
+        }
+        return;
+    }
+    mp_mul(P, alpha, acc, t1);
+    if (beta_zero) {
+        for (int c = 0; c < P; ++c) c_io[c] = t1[c];
+    } else {
+        mp_mul(P, beta, c_io, t2);
+        mp_add(P, t1, t2, c_io);
+    }
+}
+
+EXPORT int ref_gemm(int P, char ta, char tb, int64_t m, int64_t n, int64_t k,
+                    const double *alpha, const double *A, int64_t lda, int64_t sa,
+                    const double *B, int64_t ldb, int64_t sb, const double *beta,
+                    double *C, int64_t ldc, int64_t sc, int64_t row0, int64_t row1,
+                    int nthreads)
+{
+    if (P < 2 || P > 4)
+        return -1;
+    if (row1 < 0 || row1 > m)
+        row1 = m;
+    if (row0 < 0)
+        row0 = 0;
+    int az = mp_is_zero(P, alpha) || k == 0;
+    if (m == 0 || n == 0 || (az && mp_is_one(P, beta)))
+        return 0;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#endif
+    int64_t rows = row1 - row0;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t idx = 0; idx < rows * n; ++idx) {
+        int64_t i = row0 + idx % rows;
+        int64_t j = idx / rows;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        if (!az) {
+            for (int64_t l = 0; l < k; ++l) {
+                double a[4], b[4], p[4], t[4];
+                load_op(P, ta, A, lda, sa, i, l, a);
+                load_op(P, tb == 'N' || tb == 'n' ? 'T' : 'N', B, ldb, sb, j, l, b);
+                mp_mul(P, a, b, p);
+                mp_add(P, acc, p, t);
+                for (int c = 0; c < P; ++c) acc[c] = t[c];
+            }
+        }
+        double cv[4];
+        for (int c = 0; c < P; ++c)
+            cv[c] = C[c * sc + i + j * ldc];
+        epilogue(P, alpha, acc, beta, cv, az);
+        for (int c = 0; c < P; ++c)
+            C[c * sc + i + j * ldc] = cv[c];
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Split (Ozaki-style) form: each operand entry is scaled by a power of two */
+/* per row of op(A) / column of op(B) and cut into s signed 7-bit digits;   */
+/* the digit products are exact integers, summed per anti-diagonal         */
+/* p + q = d (d = 2..s+1), then recombined into P components.  This form is */
+/* not in the paper; it reaches the paper's product by a different route    */
+/* and is held to the same componentwise error bound.                       */
+/* ------------------------------------------------------------------------ */
+
+/* Scale exponent of a row/column whose largest leading component has
+ * magnitude M: E = e + 1 with M = f 2^e, f in [1/2, 1), so that every entry
+ * divided by 2^E lies in (-1/2, 1/2).  An all-zero row/column gets E = 0. */
+static int32_t scale_exponent(double M)
+{
+    if (M == 0.0)
+        return 0;
+    int e;
+    frexp(M, &e);
+    return (int32_t)(e + 1);
+}
+
+/* Digits of x = value / 2^E (|x| < 1/2), p = 1..s:
+ *   re-sum the remainder with VecSum so its first component carries its
+ *   leading bits; d_p = rint(r0 * 2^(7p)); r0 = (r0 * 2^(7p) - d_p) * 2^(-7p).
+ * Every step is exact, |d_p| <= 64, and the remainder after s digits is at
+ * most 2^(-7s-1) (1 + 2^-40) in magnitude. */
+static void slice_one(int P, int s, const double *v, int32_t E, int8_t *digits, int64_t dstride)
+{
+    double r[4];
+    for (int c = 0; c < P; ++c)
+        r[c] = ldexp(v[c], -E);
+    for (int p = 1; p <= s; ++p) {
+        vec_sum(r, P, r);
+        double y = ldexp(r[0], 7 * p);
+        double d = nearbyint(y);
+        r[0] = ldexp(y - d, -7 * p);
+        digits[(int64_t)(p - 1) * dstride] = (int8_t)d;
+    }
+}
+
+/* Exponents of the rows of op(A) (count = m) or, with is_b, the columns of
+ * op(B) (count = n); k is the inner dimension. */
+EXPORT void ref_split_exponents(int P, char t, int is_b, int64_t count, int64_t k,
+                                const double *X, int64_t ld, int64_t ps, int32_t *E)
+{
+    (void)P;
+    for (int64_t i = 0; i < count; ++i) {
+        double M = 0.0;
+        for (int64_t l = 0; l < k; ++l) {
+            double v[4];
+            if (!is_b)
+                load_op(1, t, X, ld, ps, i, l, v);
+            else
+                load_op(1, (t == 'N' || t == 'n') ? 'T' : 'N', X, ld, ps, i, l, v);
+            double a = fabs(v[0]);
+            if (a > M)
+                M = a;
+        }
+        E[i] = scale_exponent(M);
+    }
+}
+
+/* Digits of op(A) rows / op(B) columns: D[(p-1) * count * k + i * k + l]. */
+EXPORT void ref_split_slices(int P, int s, char t, int is_b, int64_t count, int64_t k,
+                             const double *X, int64_t ld, int64_t ps, const int32_t *E,
+                             int8_t *D)
+{
+    for (int64_t i = 0; i < count; ++i)
+        for (int64_t l = 0; l < k; ++l) {
+            double v[4];
+            if (!is_b)
+                load_op(P, t, X, ld, ps, i, l, v);
+            else
+                load_op(P, (t == 'N' || t == 'n') ? 'T' : 'N', X, ld, ps, i, l, v);
+            slice_one(P, s, v, E[i], D + i * k + l, count * k);
+        }
+}
+
+/* Group g of the diagonals d = 2..s+1 holds d = 2+4g .. min(5+4g, s+1).
+ * x_g = sum over its diagonals of S_d 2^(7 (dlast - d)), an integer below
+ * 2^53 in magnitude, hence exact in binary64. */
+static int split_groups(int s) { return (s + 3) / 4; }
+
+/* Recombine the diagonal sums S[d-2], d = 2..s+1, of one entry into P
+ * components: term_g = x_g 2^(Ei + Fj - 7 dlast(g)), accumulated with the
+ * precision's own addition from the least significant group upward. */
+static void recombine(int P, int s, const int64_t *S, int32_t Ei, int32_t Fj, double *acc)
+{
+    for (int c = 0; c < P; ++c)
+        acc[c] = 0.0;
+    int G = split_groups(s);
+    for (int g = G - 1; g >= 0; --g) {
+        int d0 = 2 + 4 * g;
+        int d1 = d0 + 3 < s + 1 ? d0 + 3 : s + 1;
+        int64_t x = 0;
+        for (int d = d0; d <= d1; ++d)
+            x = x * 128 + S[d - 2];
+        double term[4] = {ldexp((double)x, Ei + Fj - 7 * d1), 0.0, 0.0, 0.0};
+        double t[4];
+        mp_add(P, acc, term, t);
+        for (int c = 0; c < P; ++c)
+            acc[c] = t[c];
+    }
+}
+
+/* Whole split-form GEMM for rows row0 <= i < row1 (row1 < 0: all).  Optional
+ * debug outputs (NULL to skip): E (m), F (n), S (s planes of m x n int64,
+ * column-major, only the computed rows written). */
+EXPORT int ref_gemm_split(int P, int s, char ta, char tb, int64_t m, int64_t n, int64_t k,
+                          const double *alpha, const double *A, int64_t lda, int64_t sa,
+                          const double *B, int64_t ldb, int64_t sb, const double *beta,
+                          double *C, int64_t ldc, int64_t sc, int64_t row0, int64_t row1,
+                          int nthreads, int32_t *E_out, int32_t *F_out, int64_t *S_out)
+{
+    if (P < 2 || P > 4 || s < 1 || s > 64)
+        return -1;
+    if (row1 < 0 || row1 > m)
+        row1 = m;
+    if (row0 < 0)
+        row0 = 0;
+    int az = mp_is_zero(P, alpha) || k == 0;
+    if (m == 0 || n == 0 || (az && mp_is_one(P, beta)))
+        return 0;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#endif
+    int64_t rows = row1 - row0;
+    int32_t *E = (int32_t *)calloc((size_t)(m > 0 ? m : 1), sizeof(int32_t));
+    int32_t *F = (int32_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int32_t));
+    int8_t *DA = NULL, *DB = NULL;
+    if (!az) {
+        DA = (int8_t *)malloc((size_t)s * rows * k);
+        DB = (int8_t *)malloc((size_t)s * n * k);
+        /* rows of op(A) in [row0, row1): offset the base to row0 */
+        const double *Ab = A + (is_trans(ta) ? row0 * lda : row0);
+        ref_split_exponents(P, ta, 0, rows, k, Ab, lda, sa, E + row0);
+        ref_split_exponents(P, tb, 1, n, k, B, ldb, sb, F);
+        ref_split_slices(P, s, ta, 0, rows, k, Ab, lda, sa, E + row0, DA);
+        ref_split_slices(P, s, tb, 1, n, k, B, ldb, sb, F, DB);
+    }
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t idx = 0; idx < rows * n; ++idx) {
+        int64_t ii = idx % rows, i = row0 + ii;
+        int64_t j = idx / rows;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        if (!az) {
+            int64_t S[64];
+            for (int d = 2; d <= s + 1; ++d) {
+                int64_t sum = 0;
+                for (int p = 1; p <= d - 1; ++p) {
+                    int q = d - p;
+                    const int8_t *da = DA + (int64_t)(p - 1) * rows * k + ii * k;
+                    const int8_t *db = DB + (int64_t)(q - 1) * n * k + j * k;
+                    for (int64_t l = 0; l < k; ++l)
+                        sum += (int64_t)da[l] * (int64_t)db[l];
+                }
+                S[d - 2] = sum;
+                if (S_out)
+                    S_out[(int64_t)(d - 2) * m * n + i + j * m] = sum;
+            }
+            recombine(P, s, S, E[i], F[j], acc);
+        }
+        double cv[4];
+        for (int c = 0; c < P; ++c)
+            cv[c] = C[c * sc + i + j * ldc];
+        epilogue(P, alpha, acc, beta, cv, az);
+        for (int c = 0; c < P; ++c)
+            C[c * sc + i + j * ldc] = cv[c];
+    }
+    if (E_out)
+        memcpy(E_out + row0, E + row0, (size_t)rows * sizeof(int32_t));
+    if (F_out)
+        memcpy(F_out, F, (size_t)n * sizeof(int32_t));
+    free(E);
+    free(F);
+    free(DA);
+    free(DB);
+    return 0;
+}
+
+EXPORT int ref_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

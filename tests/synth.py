@@ -1,0 +1,141 @@
+"""Seeded synthetic inputs for DD/TD/QD matrices, shared by the oracle tests,
+the GPU tests and the benchmark.
+
+This module only draws random numbers and lays them out; it performs none of
+the multi-component arithmetic under test (no TwoSum, no renormalisation).
+
+Storage convention ("component planes", the structure-of-arrays layout of
+Sec. 2.5 / Fig. 1): a P-component matrix with `rows` x `cols` entries is a
+float64 array of shape (P, cols, ld), ld >= rows.  Plane c holds component c
+(c = 0 most significant) of every entry in column-major order, so entry
+(i, j) of component c is arr[c, j, i].  The plane stride is cols * ld.
+
+Value distribution (the workloads of the benchmark section, Sec. 3, made
+random): component 0 is uniform in [-1, 1]; each further component is
+uniform in (-ulp/2, +ulp/2) of the component before it, i.e. the expansion
+is non-overlapping by construction and needs no renormalisation pass.
+"""
+from __future__ import annotations
+
+from fractions import Fraction
+import math
+
+import numpy as np
+
+SEED_BASE = 2101065840
+SLOT = {"A": 0, "B": 1, "C": 2, "alpha": 3, "beta": 4, "expA": 5, "expB": 6,
+        "samples": 7, "shapes": 8}
+PREC_P = {"dd": 2, "td": 3, "qd": 4}
+
+
+def seed_for(cfg: int, slot: str | int) -> int:
+    s = SLOT[slot] if isinstance(slot, str) else int(slot)
+    return SEED_BASE + 16 * int(cfg) + s
+
+
+def rng_for(cfg: int, slot: str | int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed_for(cfg, slot)))
+
+
+def _tail_components(rng, lead: np.ndarray, P: int) -> np.ndarray:
+    out = np.empty((P,) + lead.shape, dtype=np.float64)
+    out[0] = lead
+    for c in range(1, P):
+        half_ulp = 0.5 * np.spacing(np.abs(out[c - 1]))
+        v = rng.uniform(-1.0, 1.0, size=lead.shape)
+        out[c] = half_ulp * v          # |v| < 1 keeps |out[c]| < ulp/2
+    return out
+
+
+def mp_uniform(rng, P: int, shape) -> np.ndarray:
+    """P-component numbers, leading part uniform in [-1, 1]; shape (P, *shape)."""
+    lead = rng.uniform(-1.0, 1.0, size=shape)
+    return _tail_components(rng, lead, P)
+
+
+def mp_matrix(cfg: int, slot: str, P: int, rows: int, cols: int, ld: int | None = None,
+              exp_range: tuple[int, int] | None = None, exp_mode: str = "entry") -> np.ndarray:
+    """A (P, cols, ld) component-plane matrix.
+
+    exp_range=(lo, hi) multiplies every entry exactly by 2**e with e drawn
+    uniformly from the integers lo..hi: per entry (exp_mode="entry"), or one e
+    per row ("row") or per column ("col").
+    """
+    ld = rows if ld is None else ld
+    assert ld >= max(1, rows)
+    rng = rng_for(cfg, slot)
+    core = mp_uniform(rng, P, (cols, rows))          # column-major: [j][i]
+    if exp_range is not None:
+        erng = rng_for(cfg, "expA" if slot == "A" else "expB" if slot == "B" else 9)
+        lo, hi = exp_range
+        if exp_mode == "entry":
+            e = erng.integers(lo, hi + 1, size=(cols, rows))
+        elif exp_mode == "row":
+            e = np.broadcast_to(erng.integers(lo, hi + 1, size=(1, rows)), (cols, rows))
+        elif exp_mode == "col":
+            e = np.broadcast_to(erng.integers(lo, hi + 1, size=(cols, 1)), (cols, rows))
+        else:
+            raise ValueError(exp_mode)
+        core = np.ldexp(core, e[None, :, :].astype(np.int32))
+    out = np.zeros((P, cols, ld), dtype=np.float64)
+    out[:, :, :rows] = core
+    return out
+
+
+def mp_scalar(cfg: int, slot: str, P: int) -> np.ndarray:
+    rng = rng_for(cfg, slot)
+    return mp_uniform(rng, P, (1,))[:, 0].copy()
+
+
+def mp_one(P: int) -> np.ndarray:
+    v = np.zeros(P)
+    v[0] = 1.0
+    return v
+
+
+def mp_vector(seed: int, P: int, n: int) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return mp_uniform(rng, P, (n,))
+
+
+# ---------------------------------------------------------------------------
+# The fixed test matrices of the benchmark section (Sec. 3):
+#   A = [sqrt(5) (i + j - 1)],  B = [sqrt(3) (n - i)],  i, j = 1..n
+# Each entry is rounded to a P-component expansion by repeated round-to-nearest
+# of the exact remainder (Python's int/int true division is correctly rounded).
+# ---------------------------------------------------------------------------
+def sqrt_fraction(v: int, bits: int = 700) -> Fraction:
+    """sqrt(v) to within 2**-bits (floor), as an exact rational."""
+    return Fraction(math.isqrt(v << (2 * bits)), 1 << bits)
+
+
+def fraction_to_components(x: Fraction, P: int) -> list[float]:
+    comps = []
+    r = x
+    for _ in range(P):
+        c = float(r)                 # correctly rounded
+        comps.append(c)
+        r = r - Fraction(c)
+    return comps
+
+
+def paper_matrices(n: int, P: int):
+    """Column-major component planes (P, n, n) of the paper's A and B."""
+    r5 = sqrt_fraction(5)
+    r3 = sqrt_fraction(3)
+    a_vals = {t: fraction_to_components(r5 * t, P) for t in range(1, 2 * n)}
+    b_vals = {t: fraction_to_components(r3 * t, P) for t in range(0, n)}
+    A = np.zeros((P, n, n))
+    B = np.zeros((P, n, n))
+    for i in range(1, n + 1):
+        for j in range(1, n + 1):
+            A[:, j - 1, i - 1] = a_vals[i + j - 1]
+            B[:, j - 1, i - 1] = b_vals[n - i]
+    return A, B
+
+
+def paper_exact_entry(n: int, i: int) -> Fraction:
+    """Exact c_ij of the paper's product (independent of j), 1-based i:
+    sum_k sqrt5 (i+k-1) sqrt3 (n-k) = sqrt15 * n(n-1)(3i+n-2)/6."""
+    r15 = sqrt_fraction(15)
+    return r15 * Fraction(n * (n - 1) * (3 * i + n - 2), 6)

@@ -1,0 +1,273 @@
+/*
+ * mpgemm.h -- C ABI of libmpgemm: double-double (DD), triple-double (TD) and
+ * quad-double (QD) matrix multiplication on AMD Instinct MI355X (gfx950).
+ *
+ * The method is Kouya, "Acceleration of multiple precision matrix
+ * multiplication based on multi-component floating-point arithmetic using
+ * AVX2" (arXiv 2101.06584): numbers are unevaluated sums of P binary64
+ * components (P = 2 DD, 3 TD, 4 QD; Sec. 2, component 0 most significant),
+ * added and multiplied with the error-free-transformation algorithms of
+ * Sec. 2.2-2.4 (Algorithms 1, 2, 4, 5, 6; TD addition = QD addition with zero
+ * fourth components), and the product is eqn (1) of Sec. 3 extended to the
+ * BLAS form C = alpha op(A) op(B) + beta C of the Rgemm routine the paper
+ * benchmarks against.
+ *
+ * Storage (Sec. 2.5, Fig. 1: one array per component): every matrix is P
+ * column-major "component planes" of device memory.  Element (i, j) of
+ * component p of X is X[p * x_plane_stride + i + j * ldx].  Scalars alpha and
+ * beta are host arrays of P doubles.  All matrix pointers are device pointers
+ * owned by the caller; the library never frees or retains them.
+ *
+ * Semantics (as BLAS xGEMM):
+ *   op(X) = X for 'N'/'n', X^T for 'T'/'t'/'C'/'c' (real data: 'C' == 'T').
+ *   op(A) is m x k, op(B) is k x n, C is m x n.
+ *   Quick return (nothing launched) when m == 0, n == 0, or when alpha == 0
+ *   or k == 0 and beta == 1 exactly.  alpha == 0 or k == 0 otherwise gives
+ *   C = beta C (C = 0 when beta == 0).  When beta == 0, C is never read.
+ *   "== 0" means every component is zero; "== 1" means (1, 0, ..., 0).
+ *   C must not overlap A or B.
+ *
+ * Errors: 0 on success.  A negative value -i reports that the i-th argument
+ * (1-based, in signature order) is invalid; checks run on the host before
+ * any GPU work, in argument order, and never print or abort.  Positive
+ * values are runtime failures (MPGEMM_ERR_*), see mpgemm_strerror().
+ * Launches are asynchronous on `stream`; faults inside a kernel surface at
+ * the caller's next synchronisation.  No C++ exception crosses this ABI.
+ */
+#ifndef MPGEMM_H
+#define MPGEMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Positive error codes. */
+#define MPGEMM_ERR_HIP 1          /* a HIP runtime call or launch failed        */
+#define MPGEMM_ERR_WORKSPACE 2    /* split form: workspace missing or too small */
+#define MPGEMM_ERR_UNSUPPORTED 3  /* shape or option outside what a form does   */
+#define MPGEMM_ERR_GRAPH 4        /* hipGraph capture / instantiation failed    */
+#define MPGEMM_ERR_ALIAS 5        /* C overlaps A or B                          */
+#define MPGEMM_ERR_NOMEM 6        /* host or device allocation failed           */
+
+/* Precision ids (the number of binary64 components). */
+#define MPGEMM_DD 2
+#define MPGEMM_TD 3
+#define MPGEMM_QD 4
+
+/* Forms. */
+#define MPGEMM_FORM_PLAIN 0     /* FP64-VALU EFT kernel; bitwise equal to the
+                                   canonical ascending-k evaluation         */
+#define MPGEMM_FORM_SPLIT_I8 1  /* operands cut into signed 7-bit INT8 digits,
+                                   exact INT8 MFMA digit products, exact
+                                   recombination into P components          */
+#define MPGEMM_FORM_AUTO 2      /* tuned choice between the two (plain when
+                                   no workspace is given)                   */
+
+/* Options for the _ex entry points.  Zero-initialise and set what you need. */
+typedef struct mpgemm_opts {
+    int form;               /* MPGEMM_FORM_*                                   */
+    int slices;             /* split form: digits per operand entry s (1..40);
+                               0 = the precision's default (DD 16, TD 23, QD 30),
+                               enough for inputs of similar magnitude within a
+                               row of op(A) / column of op(B)              */
+    int tile;               /* kernel configuration id; -1 or 0.. = tuned/fixed */
+    int reserved;
+    void* workspace;        /* split form: device scratch owned by the caller  */
+    size_t workspace_bytes; /* its size; see mpgemm_workspace_bytes()          */
+} mpgemm_opts;
+
+/*
+ * C = alpha op(A) op(B) + beta C in DD (P = 2), TD (P = 3) and QD (P = 4),
+ * plain form.  Arguments, in order (error code -i names argument i):
+ *   1 transa, 2 transb: 'N','n','T','t','C','c'
+ *   3 m, 4 n, 5 k: >= 0
+ *   6 alpha: host pointer to P doubles (non-NULL)
+ *   7 A: device pointer (may be NULL only if A is not read: m, n or k == 0 or
+ *        alpha == 0); 8 lda >= max(1, rows of A) (m if 'N', else k);
+ *   9 a_plane_stride >= lda * (columns of A), so planes never overlap
+ *  10 B, 11 ldb >= max(1, rows of B) (k if 'N', else n), 12 b_plane_stride
+ *  13 beta: host pointer to P doubles (non-NULL)
+ *  14 C: device pointer (non-NULL when m, n > 0), 15 ldc >= max(1, m),
+ *  16 c_plane_stride >= ldc * n
+ *  17 stream: HIP stream the kernels are queued on (0 = null stream)
+ * The result is bitwise identical to evaluating, for every entry, one
+ * running sum acc = ADD(acc, MUL(op(A)_il, op(B)_lj)) for l = 0..k-1 and then
+ * ADD(MUL(alpha, acc), MUL(beta, c)) (MUL(alpha, acc) when beta == 0).
+ */
+int mpgemm_dd(char transa, char transb, int64_t m, int64_t n, int64_t k, const double* alpha,
+              const double* A, int64_t lda, int64_t a_plane_stride, const double* B, int64_t ldb,
+              int64_t b_plane_stride, const double* beta, double* C, int64_t ldc,
+              int64_t c_plane_stride, hipStream_t stream);
+int mpgemm_td(char transa, char transb, int64_t m, int64_t n, int64_t k, const double* alpha,
+              const double* A, int64_t lda, int64_t a_plane_stride, const double* B, int64_t ldb,
+              int64_t b_plane_stride, const double* beta, double* C, int64_t ldc,
+              int64_t c_plane_stride, hipStream_t stream);
+int mpgemm_qd(char transa, char transb, int64_t m, int64_t n, int64_t k, const double* alpha,
+              const double* A, int64_t lda, int64_t a_plane_stride, const double* B, int64_t ldb,
+              int64_t b_plane_stride, const double* beta, double* C, int64_t ldc,
+              int64_t c_plane_stride, hipStream_t stream);
+
+/*
+ * As above with options (argument 18, non-NULL; -18 if malformed).
+ * form = MPGEMM_FORM_SPLIT_I8: every row i of op(A) is scaled by 2^-E_i and
+ * every column j of op(B) by 2^-F_j (powers of two from the largest leading
+ * component), cut into s signed digits of 7 bits in [-64, 64]; the digit
+ * products of pairs (p, q) with p + q <= s + 1 are summed exactly in 32-bit
+ * integers on the INT8 matrix cores, one anti-diagonal p + q = d at a time,
+ * and recombined into P components with the precision's own addition.  Not
+ * the canonical evaluation order, so the result differs in the last bits;
+ * with enough digits its error stays within 8 (k+2) u (|alpha||A||B| +
+ * |beta||C|) componentwise.  Needs opts->workspace of at least
+ * mpgemm_workspace_bytes() bytes (device memory the caller owns; no
+ * allocation on this path).  Supported for k * s <= 2^19 (exact 32-bit
+ * accumulation); larger k returns MPGEMM_ERR_UNSUPPORTED.
+ */
+int mpgemm_dd_ex(char transa, char transb, int64_t m, int64_t n, int64_t k, const double* alpha,
+                 const double* A, int64_t lda, int64_t a_plane_stride, const double* B, int64_t ldb,
+                 int64_t b_plane_stride, const double* beta, double* C, int64_t ldc,
+                 int64_t c_plane_stride, hipStream_t stream, const mpgemm_opts* opts);
+int mpgemm_td_ex(char transa, char transb, int64_t m, int64_t n, int64_t k, const double* alpha,
+                 const double* A, int64_t lda, int64_t a_plane_stride, const double* B, int64_t ldb,
+                 int64_t b_plane_stride, const double* beta, double* C, int64_t ldc,
+                 int64_t c_plane_stride, hipStream_t stream, const mpgemm_opts* opts);
+int mpgemm_qd_ex(char transa, char transb, int64_t m, int64_t n, int64_t k, const double* alpha,
+                 const double* A, int64_t lda, int64_t a_plane_stride, const double* B, int64_t ldb,
+                 int64_t b_plane_stride, const double* beta, double* C, int64_t ldc,
+                 int64_t c_plane_stride, hipStream_t stream, const mpgemm_opts* opts);
+
+/* Workspace bytes the split form needs for this shape (0 for the plain form;
+ * slices 0 = default; tile -1 = the one the library would pick).  Returns 0
+ * for invalid arguments. */
+size_t mpgemm_workspace_bytes(int prec, int form, int64_t m, int64_t n, int64_t k, int slices,
+                              int tile);
+
+/*
+ * Element-wise vector operations of Sec. 2.5 (the DD/TD/QD "element-wise
+ * addition and multiplication of vectors"): r_i = x_i + y_i (add) or
+ * x_i * y_i (mul), i < n, with each vector stored as P planes of n doubles at
+ * plane strides sx, sy, sr (device pointers; r may equal x or y).
+ * Arguments: 1 n >= 0, 2 x, 3 sx >= n, 4 y, 5 sy >= n, 6 r, 7 sr >= n, 8 stream.
+ */
+int mp_vec_dd_add(int64_t n, const double* x, int64_t sx, const double* y, int64_t sy, double* r,
+                  int64_t sr, hipStream_t stream);
+int mp_vec_dd_mul(int64_t n, const double* x, int64_t sx, const double* y, int64_t sy, double* r,
+                  int64_t sr, hipStream_t stream);
+int mp_vec_td_add(int64_t n, const double* x, int64_t sx, const double* y, int64_t sy, double* r,
+                  int64_t sr, hipStream_t stream);
+int mp_vec_td_mul(int64_t n, const double* x, int64_t sx, const double* y, int64_t sy, double* r,
+                  int64_t sr, hipStream_t stream);
+int mp_vec_qd_add(int64_t n, const double* x, int64_t sx, const double* y, int64_t sy, double* r,
+                  int64_t sr, hipStream_t stream);
+int mp_vec_qd_mul(int64_t n, const double* x, int64_t sx, const double* y, int64_t sy, double* r,
+                  int64_t sr, hipStream_t stream);
+
+/*
+ * Batched GEMMs of uneven shapes in one persistent launch (plain form, same
+ * per-entry results as one mpgemm_*() call per problem).  A problem is the
+ * argument list of mpgemm_dd() as a struct; alpha/beta use the first P
+ * entries.  Problems must not write overlapping C regions.
+ */
+typedef struct mpgemm_problem {
+    char transa, transb;
+    int64_t m, n, k;
+    double alpha[4];
+    double beta[4];
+    const double* A;
+    int64_t lda, a_plane_stride;
+    const double* B;
+    int64_t ldb, b_plane_stride;
+    double* C;
+    int64_t ldc, c_plane_stride;
+} mpgemm_problem;
+
+typedef struct mpgemm_batch_plan mpgemm_batch_plan;  /* opaque */
+
+/*
+ * Build a plan: validates every problem (error -(1000 + index) for an
+ * invalid problem; its first bad field is not reported separately), orders
+ * tiles largest-k first, copies the descriptors to device memory owned by
+ * the plan, and captures the counter reset plus the persistent launch in a
+ * hipGraph.  Arguments: 1 prec (2, 3, 4), 2 count >= 0, 3 problems (host
+ * array of count), 4 opts (may be NULL; opts->tile selects the tile shape),
+ * 5 stream used for the upload, 6 out (receives the plan).
+ * The plan binds the device addresses in `problems`; their contents may
+ * change between runs.
+ */
+int mpgemm_batch_plan_create(int prec, int64_t count, const mpgemm_problem* problems,
+                             const mpgemm_opts* opts, hipStream_t stream,
+                             mpgemm_batch_plan** out);
+/* Replay the captured graph on `stream`. */
+int mpgemm_batch_plan_run(mpgemm_batch_plan* plan, hipStream_t stream);
+/* Same work as a direct launch (no graph) on `stream`. */
+int mpgemm_batch_plan_launch(mpgemm_batch_plan* plan, hipStream_t stream);
+/* Total tiles and the grid the plan launches (for reporting). */
+int mpgemm_batch_plan_info(const mpgemm_batch_plan* plan, int64_t* tiles, int* grid, int* tile_cfg);
+/* Free the plan's device memory and graph (after its last run completed). */
+int mpgemm_batch_plan_destroy(mpgemm_batch_plan* plan);
+
+/*
+ * Autotuner: times every kernel configuration of a form on a problem of the
+ * given shape (synthetic operands allocated by the tuner; not a hot path) and
+ * records the fastest for that precision / form / shape bucket (log2 of m, n,
+ * k).  Later calls with tile = -1 (or the non-_ex entry points) use it.
+ * Writes the chosen configuration id to *best (may be NULL).
+ */
+int mpgemm_autotune(int prec, int form, int64_t m, int64_t n, int64_t k, int slices,
+                    hipStream_t stream, int* best);
+/* Persist / restore the tuning table as a small text file (one entry per
+ * line: prec form log2m log2n log2k tile). */
+int mpgemm_autotune_save(const char* path);
+int mpgemm_autotune_load(const char* path);
+/* Number of configurations a form offers for a precision. */
+int mpgemm_num_configs(int prec, int form);
+
+/*
+ * Pick the slice count of the split form by an accuracy rule: on a block of
+ * up to 64 rows of op(A) it compares the split result for s = smin, smin+1,
+ * ... against the plain (canonical) result and returns the smallest s whose
+ * largest difference, relative to k u (|A||B|)_ij, is at most `target`
+ * (u = 2^-104 DD, 2^-150 TD, 2^-200 QD).  Scratch is allocated by the call.
+ * Same argument conventions as mpgemm_dd() for the matrices.
+ */
+int mpgemm_tune_slices(int prec, char transa, char transb, int64_t m, int64_t n, int64_t k,
+                       const double* A, int64_t lda, int64_t a_plane_stride, const double* B,
+                       int64_t ldb, int64_t b_plane_stride, double target, int smin, int smax,
+                       hipStream_t stream, int* s_out, double* ratio_out);
+
+/*
+ * Stages of the split form, exposed so each can be checked on its own.
+ * They operate on a workspace laid out by the library for (prec, m, n, k, s,
+ * tile); offsets (bytes) and padded sizes are reported by
+ * mpgemm_split_layout.  Digit planes are int8 [s][Mp][Kp] (op(A) rows) and
+ * [s][Np][Kp] (op(B) columns), K contiguous; exponents are int32 [Mp], [Np];
+ * anti-diagonal sums are int32 [s][Np][Mp] (d = 2..s+1, column-major).
+ */
+int mpgemm_split_layout(int prec, int64_t m, int64_t n, int64_t k, int slices, int tile,
+                        size_t* off_E, size_t* off_F, size_t* off_DA, size_t* off_DB,
+                        size_t* off_S, int64_t* Mp, int64_t* Np, int64_t* Kp);
+/* Run the stages up to and including `last` (1 = scale exponents, 2 = digit
+ * slicing, 3 = anti-diagonal sums, 4 = recombination and epilogue = the full
+ * product) with the same arguments as mpgemm_*_ex. */
+int mpgemm_split_stages(int prec, int last, char transa, char transb, int64_t m, int64_t n,
+                        int64_t k, const double* alpha, const double* A, int64_t lda,
+                        int64_t a_plane_stride, const double* B, int64_t ldb,
+                        int64_t b_plane_stride, const double* beta, double* C, int64_t ldc,
+                        int64_t c_plane_stride, hipStream_t stream, const mpgemm_opts* opts);
+
+/* Message for an error code; never NULL. */
+const char* mpgemm_strerror(int code);
+/* Library version string. */
+const char* mpgemm_version(void);
+/* Release library-owned state (tuning table).  Plans are freed separately. */
+void mpgemm_finalize(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPGEMM_H */

@@ -31,11 +31,12 @@ def lib():
         L.ref_prim.argtypes = [_int, _i64, C.c_void_p, C.c_void_p]
         L.ref_prim.restype = _int
         L.ref_gemm.argtypes = [_int, _ch, _ch, _i64, _i64, _i64, C.c_void_p, C.c_void_p, _i64, _i64,
-                               C.c_void_p, _i64, _i64, C.c_void_p, C.c_void_p, _i64, _i64, _i64, _i64, _int]
+                               C.c_void_p, _i64, _i64, C.c_void_p, C.c_void_p, _i64, _i64, _i64, _i64,
+                               _i64, _i64, _int]
         L.ref_gemm.restype = _int
         L.ref_gemm_split.argtypes = [_int, _int, _ch, _ch, _i64, _i64, _i64, C.c_void_p, C.c_void_p, _i64,
                                      _i64, C.c_void_p, _i64, _i64, C.c_void_p, C.c_void_p, _i64, _i64,
-                                     _i64, _i64, _int, C.c_void_p, C.c_void_p, C.c_void_p]
+                                     _i64, _i64, _i64, _i64, _int, C.c_void_p, C.c_void_p, C.c_void_p]
         L.ref_gemm_split.restype = _int
         L.ref_split_exponents.argtypes = [_int, _ch, _int, _i64, _i64, C.c_void_p, _i64, _i64, C.c_void_p]
         L.ref_split_exponents.restype = None
@@ -83,24 +84,27 @@ def vec(P: int, op: str, x: np.ndarray, y: np.ndarray) -> np.ndarray:
     return r
 
 
-def gemm(P, ta, tb, m, n, k, alpha, A, B, beta, C, rows=None, nthreads=0):
+def gemm(P, ta, tb, m, n, k, alpha, A, B, beta, C, rows=None, cols=None, nthreads=0):
     """C = alpha op(A) op(B) + beta C in the canonical order; returns a new C.
-    A, B, C are (P, cols, ld) component planes; rows=(r0, r1) limits the rows."""
+    A, B, C are (P, cols, ld) component planes; rows=(r0, r1) / cols=(c0, c1)
+    limit the computed block (the rest of C is returned unchanged)."""
     A = _f64(A)
     B = _f64(B)
     Cout = _f64(C).copy()
     alpha = _f64(alpha)
     beta = _f64(beta)
     r0, r1 = rows if rows is not None else (0, -1)
+    c0, c1 = cols if cols is not None else (0, -1)
     rc = lib().ref_gemm(P, ta.encode(), tb.encode(), m, n, k, _ptr(alpha), _ptr(A), A.shape[2],
                         A.shape[1] * A.shape[2], _ptr(B), B.shape[2], B.shape[1] * B.shape[2],
                         _ptr(beta), _ptr(Cout), Cout.shape[2], Cout.shape[1] * Cout.shape[2],
-                        r0, r1, nthreads)
+                        r0, r1, c0, c1, nthreads)
     assert rc == 0, rc
     return Cout
 
 
-def gemm_split(P, s, ta, tb, m, n, k, alpha, A, B, beta, C, rows=None, nthreads=0, debug=False):
+def gemm_split(P, s, ta, tb, m, n, k, alpha, A, B, beta, C, rows=None, cols=None, nthreads=0,
+               debug=False):
     """Split (sliced-integer) form; returns C, or (C, E, F, S) with debug=True
     (S: (s, n, m) int64 diagonal sums, column-major per diagonal)."""
     A = _f64(A)
@@ -109,13 +113,14 @@ def gemm_split(P, s, ta, tb, m, n, k, alpha, A, B, beta, C, rows=None, nthreads=
     alpha = _f64(alpha)
     beta = _f64(beta)
     r0, r1 = rows if rows is not None else (0, -1)
+    c0, c1 = cols if cols is not None else (0, -1)
     E = np.zeros(max(m, 1), dtype=np.int32)
     F = np.zeros(max(n, 1), dtype=np.int32)
     S = np.zeros((s, n, m), dtype=np.int64) if debug else None
     rc = lib().ref_gemm_split(P, s, ta.encode(), tb.encode(), m, n, k, _ptr(alpha), _ptr(A),
                               A.shape[2], A.shape[1] * A.shape[2], _ptr(B), B.shape[2],
                               B.shape[1] * B.shape[2], _ptr(beta), _ptr(Cout), Cout.shape[2],
-                              Cout.shape[1] * Cout.shape[2], r0, r1, nthreads,
+                              Cout.shape[1] * Cout.shape[2], r0, r1, c0, c1, nthreads,
                               _ptr(E) if debug else None, _ptr(F) if debug else None,
                               _ptr(S) if debug else None)
     assert rc == 0, rc

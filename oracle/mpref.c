@@ -454,7 +454,8 @@ EXPORT int ref_prim(int which, int64_t n, const double *in, double *out)
  *   otherwise:          c = ADD(MUL(alpha, acc), MUL(beta, c_old))
  *   alpha == 0 or k==0: c = beta == 0 ? 0 : MUL(beta, c_old)
  * and nothing is written when m == 0, n == 0, or (alpha == 0 or k == 0) and
- * beta == 1.  Only rows row0 <= i < row1 are computed (row1 < 0: all). */
+ * beta == 1.  Only rows row0 <= i < row1 and columns col0 <= j < col1 are
+ * computed (a negative end means "to the last"). */
 static void epilogue(int P, const double *alpha, const double *acc, const double *beta,
                      double *c_io, int alpha_or_k_zero)
 {
@@ -482,7 +483,7 @@ EXPORT int ref_gemm(int P, char ta, char tb, int64_t m, int64_t n, int64_t k,
                     const double *alpha, const double *A, int64_t lda, int64_t sa,
                     const double *B, int64_t ldb, int64_t sb, const double *beta,
                     double *C, int64_t ldc, int64_t sc, int64_t row0, int64_t row1,
-                    int nthreads)
+                    int64_t col0, int64_t col1, int nthreads)
 {
     if (P < 2 || P > 4)
         return -1;
@@ -490,6 +491,10 @@ EXPORT int ref_gemm(int P, char ta, char tb, int64_t m, int64_t n, int64_t k,
         row1 = m;
     if (row0 < 0)
         row0 = 0;
+    if (col1 < 0 || col1 > n)
+        col1 = n;
+    if (col0 < 0)
+        col0 = 0;
     int az = mp_is_zero(P, alpha) || k == 0;
     if (m == 0 || n == 0 || (az && mp_is_one(P, beta)))
         return 0;
@@ -497,11 +502,11 @@ EXPORT int ref_gemm(int P, char ta, char tb, int64_t m, int64_t n, int64_t k,
     if (nthreads > 0)
         omp_set_num_threads(nthreads);
 #endif
-    int64_t rows = row1 - row0;
+    int64_t rows = row1 - row0, cols = col1 - col0;
 #pragma omp parallel for schedule(dynamic, 1)
-    for (int64_t idx = 0; idx < rows * n; ++idx) {
+    for (int64_t idx = 0; idx < rows * cols; ++idx) {
         int64_t i = row0 + idx % rows;
-        int64_t j = idx / rows;
+        int64_t j = col0 + idx / rows;
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         if (!az) {
             for (int64_t l = 0; l < k; ++l) {
@@ -590,6 +595,7 @@ EXPORT void ref_split_slices(int P, int s, char t, int is_b, int64_t count, int6
                              const double *X, int64_t ld, int64_t ps, const int32_t *E,
                              int8_t *D)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < count; ++i)
         for (int64_t l = 0; l < k; ++l) {
             double v[4];
@@ -628,14 +634,16 @@ static void recombine(int P, int s, const int64_t *S, int32_t Ei, int32_t Fj, do
     }
 }
 
-/* Whole split-form GEMM for rows row0 <= i < row1 (row1 < 0: all).  Optional
- * debug outputs (NULL to skip): E (m), F (n), S (s planes of m x n int64,
- * column-major, only the computed rows written). */
+/* Whole split-form GEMM for rows row0 <= i < row1 and columns col0 <= j <
+ * col1 (negative end: to the last).  Optional debug outputs (NULL to skip):
+ * E (m), F (n), S (s planes of m x n int64, column-major; only the computed
+ * block written). */
 EXPORT int ref_gemm_split(int P, int s, char ta, char tb, int64_t m, int64_t n, int64_t k,
                           const double *alpha, const double *A, int64_t lda, int64_t sa,
                           const double *B, int64_t ldb, int64_t sb, const double *beta,
                           double *C, int64_t ldc, int64_t sc, int64_t row0, int64_t row1,
-                          int nthreads, int32_t *E_out, int32_t *F_out, int64_t *S_out)
+                          int64_t col0, int64_t col1, int nthreads, int32_t *E_out,
+                          int32_t *F_out, int64_t *S_out)
 {
     if (P < 2 || P > 4 || s < 1 || s > 64)
         return -1;
@@ -643,6 +651,10 @@ EXPORT int ref_gemm_split(int P, int s, char ta, char tb, int64_t m, int64_t n, 
         row1 = m;
     if (row0 < 0)
         row0 = 0;
+    if (col1 < 0 || col1 > n)
+        col1 = n;
+    if (col0 < 0)
+        col0 = 0;
     int az = mp_is_zero(P, alpha) || k == 0;
     if (m == 0 || n == 0 || (az && mp_is_one(P, beta)))
         return 0;
@@ -650,24 +662,25 @@ EXPORT int ref_gemm_split(int P, int s, char ta, char tb, int64_t m, int64_t n, 
     if (nthreads > 0)
         omp_set_num_threads(nthreads);
 #endif
-    int64_t rows = row1 - row0;
+    int64_t rows = row1 - row0, cols = col1 - col0;
     int32_t *E = (int32_t *)calloc((size_t)(m > 0 ? m : 1), sizeof(int32_t));
     int32_t *F = (int32_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int32_t));
     int8_t *DA = NULL, *DB = NULL;
     if (!az) {
         DA = (int8_t *)malloc((size_t)s * rows * k);
-        DB = (int8_t *)malloc((size_t)s * n * k);
-        /* rows of op(A) in [row0, row1): offset the base to row0 */
+        DB = (int8_t *)malloc((size_t)s * cols * k);
+        /* rows of op(A) in [row0, row1), columns of op(B) in [col0, col1) */
         const double *Ab = A + (is_trans(ta) ? row0 * lda : row0);
+        const double *Bb = B + (is_trans(tb) ? col0 : col0 * ldb);
         ref_split_exponents(P, ta, 0, rows, k, Ab, lda, sa, E + row0);
-        ref_split_exponents(P, tb, 1, n, k, B, ldb, sb, F);
+        ref_split_exponents(P, tb, 1, cols, k, Bb, ldb, sb, F + col0);
         ref_split_slices(P, s, ta, 0, rows, k, Ab, lda, sa, E + row0, DA);
-        ref_split_slices(P, s, tb, 1, n, k, B, ldb, sb, F, DB);
+        ref_split_slices(P, s, tb, 1, cols, k, Bb, ldb, sb, F + col0, DB);
     }
 #pragma omp parallel for schedule(dynamic, 1)
-    for (int64_t idx = 0; idx < rows * n; ++idx) {
+    for (int64_t idx = 0; idx < rows * cols; ++idx) {
         int64_t ii = idx % rows, i = row0 + ii;
-        int64_t j = idx / rows;
+        int64_t jj = idx / rows, j = col0 + jj;
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         if (!az) {
             int64_t S[64];
@@ -676,7 +689,7 @@ EXPORT int ref_gemm_split(int P, int s, char ta, char tb, int64_t m, int64_t n, 
                 for (int p = 1; p <= d - 1; ++p) {
                     int q = d - p;
                     const int8_t *da = DA + (int64_t)(p - 1) * rows * k + ii * k;
-                    const int8_t *db = DB + (int64_t)(q - 1) * n * k + j * k;
+                    const int8_t *db = DB + (int64_t)(q - 1) * cols * k + jj * k;
                     for (int64_t l = 0; l < k; ++l)
                         sum += (int64_t)da[l] * (int64_t)db[l];
                 }
@@ -696,7 +709,7 @@ EXPORT int ref_gemm_split(int P, int s, char ta, char tb, int64_t m, int64_t n, 
     if (E_out)
         memcpy(E_out + row0, E + row0, (size_t)rows * sizeof(int32_t));
     if (F_out)
-        memcpy(F_out, F, (size_t)n * sizeof(int32_t));
+        memcpy(F_out + col0, F + col0, (size_t)cols * sizeof(int32_t));
     free(E);
     free(F);
     free(DA);

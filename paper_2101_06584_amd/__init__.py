@@ -1,0 +1,8 @@
+"""DD/TD/QD (double-, triple-, quad-double) matrix multiplication for AMD
+Instinct MI355X (gfx950): error-free-transformation kernels on the FP64 vector
+ALUs, a split form on the INT8 matrix cores, a batched persistent form and an
+autotuner, behind the C ABI in include/mpgemm.h.  This package is the thin
+Python binding (PyTorch supplies device memory and streams)."""
+from .api import (BatchPlan, DEFAULT_SLICES, MPGemmError, PREC, alloc_workspace, autotune,  # noqa: F401
+                  autotune_load, autotune_save, gemm, gemm_raw, load, make_opts, num_configs,
+                  split_layout, split_stages, tune_slices, vec, vec_raw, version, workspace_bytes)

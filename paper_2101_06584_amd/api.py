@@ -1,0 +1,246 @@
+"""Python binding of libmpgemm with PyTorch used only for device memory and
+streams.  Matrices are float64 CUDA tensors of shape (P, cols, ld): P
+column-major component planes (element (i, j) of component p is t[p, j, i]),
+i.e. the library's storage with plane stride cols * ld.  Every call only
+marshals arguments; the work runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Sequence
+
+import torch
+
+from . import _lib
+
+PREC = {"dd": 2, "td": 3, "qd": 4, 2: 2, 3: 3, 4: 4}
+FORMS = {"plain": _lib.FORM_PLAIN, "split": _lib.FORM_SPLIT_I8, "auto": _lib.FORM_AUTO}
+DEFAULT_SLICES = {2: 16, 3: 23, 4: 30}
+_NAME = {2: "dd", 3: "td", 4: "qd"}
+
+
+class MPGemmError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: error {code}: {_lib.strerror(code)}")
+
+
+def load():
+    return _lib.load()
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != 0:
+        raise MPGemmError(rc, what)
+
+
+def _stream(stream) -> C.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _mat(t: torch.Tensor | None, P: int):
+    """(pointer, ld, plane stride) of a (P, cols, ld) component-plane tensor."""
+    if t is None:
+        return None, 1, 1
+    if t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError("matrices must be float64 CUDA tensors")
+    if t.dim() != 3 or t.shape[0] != P:
+        raise ValueError(f"expected shape (P={P}, cols, ld), got {tuple(t.shape)}")
+    if t.stride(2) != 1 or t.stride(1) < t.shape[2] and t.shape[1] > 1:
+        raise ValueError("component planes must be column-major with unit stride along rows")
+    ld = max(t.stride(1), 1) if t.shape[1] > 1 else max(t.shape[2], 1)
+    ps = t.stride(0) if P > 1 else ld * t.shape[1]
+    return C.c_void_p(t.data_ptr()), ld, ps
+
+
+def _scalar(v: Sequence[float], P: int):
+    vals = [float(x) for x in v] + [0.0] * (P - len(v))
+    return (C.c_double * P)(*vals[:P])
+
+
+def make_opts(form="plain", slices=0, tile=-1, workspace: torch.Tensor | None = None):
+    o = _lib.Opts()
+    o.form = FORMS[form] if isinstance(form, str) else int(form)
+    o.slices = int(slices)
+    o.tile = int(tile)
+    o.reserved = 0
+    if workspace is not None:
+        o.workspace = C.c_void_p(workspace.data_ptr())
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
+    else:
+        o.workspace = None
+        o.workspace_bytes = 0
+    return o
+
+
+def workspace_bytes(prec, form, m, n, k, slices=0, tile=-1) -> int:
+    P = PREC[prec]
+    f = FORMS[form] if isinstance(form, str) else int(form)
+    return int(_lib.load().mpgemm_workspace_bytes(P, f, m, n, k, slices, tile))
+
+
+def alloc_workspace(prec, m, n, k, slices=0, tile=-1, device=None) -> torch.Tensor:
+    nbytes = workspace_bytes(prec, "split", m, n, k, slices, tile)
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device or "cuda")
+
+
+def gemm_raw(prec, transa, transb, m, n, k, alpha, A, B, beta, C_, *, form=None, slices=0,
+             tile=-1, workspace=None, stream=None) -> int:
+    """Calls mpgemm_{dd,td,qd}[_ex]; returns the library's status code."""
+    P = PREC[prec]
+    L = _lib.load()
+    a, lda, sa = _mat(A, P)
+    b, ldb, sb = _mat(B, P)
+    c, ldc, sc = _mat(C_, P)
+    args = [transa.encode(), transb.encode(), m, n, k, _scalar(alpha, P), a, lda, sa, b, ldb, sb,
+            _scalar(beta, P), c, ldc, sc, _stream(stream)]
+    name = "mpgemm_" + _NAME[P]
+    if form is None:
+        return getattr(L, name)(*args)
+    return getattr(L, name + "_ex")(*args, C.byref(make_opts(form, slices, tile, workspace)))
+
+
+def gemm(prec, transa, transb, m, n, k, alpha, A, B, beta, C_, **kw) -> None:
+    """C_ = alpha op(A) op(B) + beta C_ (in place); raises on error."""
+    _check(gemm_raw(prec, transa, transb, m, n, k, alpha, A, B, beta, C_, **kw), "mpgemm")
+
+
+def vec_raw(prec, op, x, y, r, n=None, stream=None) -> int:
+    P = PREC[prec]
+    L = _lib.load()
+    n = x.shape[-1] if n is None else n
+    xs = x.stride(0) if P > 1 else n
+    ys = y.stride(0) if P > 1 else n
+    rs = r.stride(0) if P > 1 else n
+    fn = getattr(L, f"mp_vec_{_NAME[P]}_{op}")
+    return fn(n, C.c_void_p(x.data_ptr()), xs, C.c_void_p(y.data_ptr()), ys, C.c_void_p(r.data_ptr()),
+              rs, _stream(stream))
+
+
+def vec(prec, op, x, y, r, n=None, stream=None) -> None:
+    """r = x (+|*) y element-wise; x, y, r are (P, n) float64 CUDA tensors."""
+    _check(vec_raw(prec, op, x, y, r, n, stream), "mp_vec")
+
+
+def split_layout(prec, m, n, k, slices=0, tile=-1) -> dict:
+    L = _lib.load()
+    offs = [C.c_size_t() for _ in range(5)]
+    dims = [C.c_int64() for _ in range(3)]
+    rc = L.mpgemm_split_layout(PREC[prec], m, n, k, slices, tile, *[C.byref(o) for o in offs],
+                               *[C.byref(d) for d in dims])
+    _check(rc, "mpgemm_split_layout")
+    keys = ["E", "F", "DA", "DB", "S"]
+    out = {k_: o.value for k_, o in zip(keys, offs)}
+    out.update(Mp=dims[0].value, Np=dims[1].value, Kp=dims[2].value)
+    return out
+
+
+def split_stages(prec, last, transa, transb, m, n, k, alpha, A, B, beta, C_, *, slices=0, tile=-1,
+                 workspace=None, stream=None) -> None:
+    P = PREC[prec]
+    L = _lib.load()
+    a, lda, sa = _mat(A, P)
+    b, ldb, sb = _mat(B, P)
+    c, ldc, sc = _mat(C_, P)
+    o = make_opts("split", slices, tile, workspace)
+    rc = L.mpgemm_split_stages(P, last, transa.encode(), transb.encode(), m, n, k, _scalar(alpha, P),
+                               a, lda, sa, b, ldb, sb, _scalar(beta, P), c, ldc, sc, _stream(stream),
+                               C.byref(o))
+    _check(rc, "mpgemm_split_stages")
+
+
+class BatchPlan:
+    """Many GEMMs of one precision in one persistent launch, replayed from a
+    captured hipGraph (run) or launched directly (launch)."""
+
+    def __init__(self, prec, problems, tile=-1, stream=None):
+        """problems: sequence of dicts with keys transa, transb, m, n, k, alpha,
+        A, B, beta, C (tensors as for gemm())."""
+        self.P = PREC[prec]
+        L = _lib.load()
+        arr = (_lib.Problem * max(len(problems), 1))()
+        self._keep = []
+        for q, pr in enumerate(problems):
+            x = arr[q]
+            x.transa = pr.get("transa", "N").encode()
+            x.transb = pr.get("transb", "N").encode()
+            x.m, x.n, x.k = pr["m"], pr["n"], pr["k"]
+            al = list(pr["alpha"]) + [0.0] * 4
+            be = list(pr["beta"]) + [0.0] * 4
+            x.alpha = (C.c_double * 4)(*al[:4])
+            x.beta = (C.c_double * 4)(*be[:4])
+            a, x.lda, x.a_plane_stride = _mat(pr["A"], self.P)
+            b, x.ldb, x.b_plane_stride = _mat(pr["B"], self.P)
+            c, x.ldc, x.c_plane_stride = _mat(pr["C"], self.P)
+            x.A, x.B, x.C = a, b, c
+            self._keep.append((pr["A"], pr["B"], pr["C"]))
+        opts = make_opts("plain", 0, tile, None)
+        h = C.c_void_p()
+        rc = L.mpgemm_batch_plan_create(self.P, len(problems), arr, C.byref(opts), _stream(stream),
+                                        C.byref(h))
+        _check(rc, "mpgemm_batch_plan_create")
+        self._h = h
+
+    def run(self, stream=None):
+        _check(_lib.load().mpgemm_batch_plan_run(self._h, _stream(stream)), "batch run")
+
+    def launch(self, stream=None):
+        _check(_lib.load().mpgemm_batch_plan_launch(self._h, _stream(stream)), "batch launch")
+
+    def info(self):
+        t, g, c = C.c_int64(), C.c_int(), C.c_int()
+        _check(_lib.load().mpgemm_batch_plan_info(self._h, C.byref(t), C.byref(g), C.byref(c)), "info")
+        return {"tiles": t.value, "grid": g.value, "tile_cfg": c.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().mpgemm_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(prec, form, m, n, k, slices=0, stream=None) -> int:
+    best = C.c_int(-1)
+    f = FORMS[form] if isinstance(form, str) else int(form)
+    _check(_lib.load().mpgemm_autotune(PREC[prec], f, m, n, k, slices, _stream(stream), C.byref(best)),
+           "mpgemm_autotune")
+    return best.value
+
+
+def autotune_save(path: str) -> None:
+    _check(_lib.load().mpgemm_autotune_save(path.encode()), "autotune_save")
+
+
+def autotune_load(path: str) -> None:
+    _check(_lib.load().mpgemm_autotune_load(path.encode()), "autotune_load")
+
+
+def num_configs(prec, form) -> int:
+    f = FORMS[form] if isinstance(form, str) else int(form)
+    return int(_lib.load().mpgemm_num_configs(PREC[prec], f))
+
+
+def tune_slices(prec, transa, transb, m, n, k, A, B, target=1.0, smin=None, smax=40, stream=None):
+    """Smallest slice count whose split result on a block of rows stays within
+    target * k * u * (|A||B|)_ij of the plain result; returns (s, ratio)."""
+    P = PREC[prec]
+    smin = DEFAULT_SLICES[P] - 4 if smin is None else smin
+    a, lda, sa = _mat(A, P)
+    b, ldb, sb = _mat(B, P)
+    s = C.c_int()
+    r = C.c_double()
+    rc = _lib.load().mpgemm_tune_slices(P, transa.encode(), transb.encode(), m, n, k, a, lda, sa, b, ldb,
+                                        sb, float(target), int(smin), int(smax), _stream(stream),
+                                        C.byref(s), C.byref(r))
+    _check(rc, "mpgemm_tune_slices")
+    return s.value, r.value
+
+
+def version() -> str:
+    return _lib.load().mpgemm_version().decode()

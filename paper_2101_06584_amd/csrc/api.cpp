@@ -1,0 +1,630 @@
+// api.cpp -- the C ABI of libmpgemm (declared in include/mpgemm.h): argument
+// validation (host only, before any GPU work), quick returns, form and tile
+// dispatch, the batched plan with its captured hipGraph, the autotuner and the
+// slice-count rule.
+#include "mpgemm.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace mpg {
+int launch_split_stages(int P, int s, int cfg, int last, const GemmArgs& g, void* ws,
+                        hipStream_t st);
+int launch_fill(int P, double* X, int64_t plane, int64_t planes_stride, uint64_t seed,
+                hipStream_t st);
+int launch_absdot(const GemmArgs& g, double* out, hipStream_t st);
+int launch_diff_ratio(int P, int64_t m, int64_t n, const double* Cs, const double* Cr, int64_t ld,
+                      int64_t ps, const double* absab, double scale, double* out, hipStream_t st);
+}  // namespace mpg
+
+using namespace mpg;
+
+namespace {
+
+const int kDefaultSlices[5] = {0, 0, 16, 23, 30};
+const int kMaxSlices = 40;
+
+bool valid_trans(char t) {
+    return t == 'N' || t == 'n' || t == 'T' || t == 't' || t == 'C' || t == 'c';
+}
+bool is_trans(char t) { return t != 'N' && t != 'n'; }
+
+bool mp_zero(int P, const double* x) {
+    for (int p = 0; p < P; ++p)
+        if (x[p] != 0.0) return false;
+    return true;
+}
+bool mp_one(int P, const double* x) {
+    if (x[0] != 1.0) return false;
+    for (int p = 1; p < P; ++p)
+        if (x[p] != 0.0) return false;
+    return true;
+}
+
+// Byte range [lo, hi) touched by a component-plane matrix.
+void extent(const double* X, int P, int64_t rows, int64_t cols, int64_t ld, int64_t ps,
+            uintptr_t& lo, uintptr_t& hi) {
+    lo = (uintptr_t)X;
+    hi = lo + sizeof(double) * (size_t)((P - 1) * ps + (cols - 1) * ld + rows);
+}
+bool overlaps(uintptr_t a0, uintptr_t a1, uintptr_t b0, uintptr_t b1) { return a0 < b1 && b0 < a1; }
+
+// Validates in signature order; fills g.  Returns 0, a negative argument
+// index, or MPGEMM_ERR_ALIAS.
+int validate(int P, char ta, char tb, int64_t m, int64_t n, int64_t k, const double* alpha,
+             const double* A, int64_t lda, int64_t sa, const double* B, int64_t ldb, int64_t sb,
+             const double* beta, double* C, int64_t ldc, int64_t sc, GemmArgs& g) {
+    if (!valid_trans(ta)) return -1;
+    if (!valid_trans(tb)) return -2;
+    if (m < 0) return -3;
+    if (n < 0) return -4;
+    if (k < 0) return -5;
+    if (!alpha) return -6;
+    const int64_t nrowa = is_trans(ta) ? k : m, ncola = is_trans(ta) ? m : k;
+    const int64_t nrowb = is_trans(tb) ? n : k, ncolb = is_trans(tb) ? k : n;
+    const bool reads_ab = m > 0 && n > 0 && k > 0 && !mp_zero(P, alpha);
+    if (reads_ab && !A) return -7;
+    if (lda < std::max<int64_t>(1, nrowa)) return -8;
+    if (sa < lda * ncola) return -9;
+    if (reads_ab && !B) return -10;
+    if (ldb < std::max<int64_t>(1, nrowb)) return -11;
+    if (sb < ldb * ncolb) return -12;
+    if (!beta) return -13;
+    if (m > 0 && n > 0 && !C) return -14;
+    if (ldc < std::max<int64_t>(1, m)) return -15;
+    if (sc < ldc * n) return -16;
+    if (reads_ab) {
+        uintptr_t c0, c1, a0, a1, b0, b1;
+        extent(C, P, m, n, ldc, sc, c0, c1);
+        extent(A, P, nrowa, ncola, lda, sa, a0, a1);
+        extent(B, P, nrowb, ncolb, ldb, sb, b0, b1);
+        if (overlaps(c0, c1, a0, a1) || overlaps(c0, c1, b0, b1)) return MPGEMM_ERR_ALIAS;
+    }
+    g.m = m;
+    g.n = n;
+    g.k = k;
+    g.A = A;
+    g.lda = lda;
+    g.sa = sa;
+    g.B = B;
+    g.ldb = ldb;
+    g.sb = sb;
+    g.C = C;
+    g.ldc = ldc;
+    g.sc = sc;
+    g.ta = is_trans(ta) ? 1 : 0;
+    g.tb = is_trans(tb) ? 1 : 0;
+    for (int p = 0; p < 4; ++p) {
+        g.alpha[p] = p < P ? alpha[p] : 0.0;
+        g.beta[p] = p < P ? beta[p] : 0.0;
+    }
+    return 0;
+}
+
+int hip_rc(int e) { return e == 0 ? 0 : MPGEMM_ERR_HIP; }
+
+// ---- tuning table ---------------------------------------------------------
+
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int, int>, int> g_tune;
+
+int ilog2(int64_t x) {
+    int r = 0;
+    while (x > 1) {
+        x >>= 1;
+        ++r;
+    }
+    return r;
+}
+
+int tuned_tile(int P, int form, int64_t m, int64_t n, int64_t k) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(std::make_tuple(P, form, ilog2(m), ilog2(n), ilog2(k)));
+    return it == g_tune.end() ? -1 : it->second;
+}
+
+int split_default_config(int64_t m, int64_t n) {
+    // 128 x 128 tiles once they still give every CU a few workgroups
+    return (m * n >= (int64_t)1024 * 1024) ? 0 : 1;
+}
+
+int pick_tile(int P, int form, int64_t m, int64_t n, int64_t k, int requested) {
+    const int nconf = form == MPGEMM_FORM_SPLIT_I8 ? kSplitConfigs : kPlainConfigs;
+    if (requested >= 0 && requested < nconf) return requested;
+    const int t = tuned_tile(P, form, m, n, k);
+    if (t >= 0 && t < nconf) return t;
+    return form == MPGEMM_FORM_SPLIT_I8 ? split_default_config(m, n)
+                                        : plain_default_config(P, m, n, k);
+}
+
+bool split_k_ok(int64_t k, int s) { return (int64_t)s * k <= 524287; }
+
+int gemm_common(int P, char ta, char tb, int64_t m, int64_t n, int64_t k, const double* alpha,
+                const double* A, int64_t lda, int64_t sa, const double* B, int64_t ldb, int64_t sb,
+                const double* beta, double* C, int64_t ldc, int64_t sc, hipStream_t st,
+                const mpgemm_opts* opts, bool has_opts, int last_stage) {
+    GemmArgs g;
+    int rc = validate(P, ta, tb, m, n, k, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, g);
+    if (rc) return rc;
+    if (has_opts) {
+        if (!opts) return -18;
+        if (opts->form < 0 || opts->form > 2) return -18;
+        if (opts->slices < 0 || opts->slices > kMaxSlices) return -18;
+    }
+    if (m == 0 || n == 0) return 0;
+    const bool az = (k == 0) || mp_zero(P, alpha);
+    if (az && mp_one(P, beta)) return 0;
+    if (az) return hip_rc(launch_scale(P, g, st));
+
+    int form = has_opts ? opts->form : MPGEMM_FORM_PLAIN;
+    const int s = (has_opts && opts->slices > 0) ? opts->slices : kDefaultSlices[P];
+    const int req_tile = has_opts ? opts->tile : -1;
+    if (last_stage > 0) form = MPGEMM_FORM_SPLIT_I8;
+    if (form == MPGEMM_FORM_AUTO) {
+        const bool fits = opts->workspace &&
+                          opts->workspace_bytes >= split_workspace_bytes(
+                              P, m, n, k, s, pick_tile(P, MPGEMM_FORM_SPLIT_I8, m, n, k, -1));
+        form = (fits && split_k_ok(k, s) && m >= 256 && n >= 256 && k >= 256)
+                   ? MPGEMM_FORM_SPLIT_I8 : MPGEMM_FORM_PLAIN;
+    }
+    if (form == MPGEMM_FORM_PLAIN) {
+        const int cfg = pick_tile(P, form, m, n, k, req_tile);
+        return hip_rc(launch_plain(P, cfg, g, st));
+    }
+    if (!split_k_ok(k, s)) return MPGEMM_ERR_UNSUPPORTED;
+    const int cfg = pick_tile(P, MPGEMM_FORM_SPLIT_I8, m, n, k, req_tile);
+    const size_t need = split_workspace_bytes(P, m, n, k, s, cfg);
+    if (!opts->workspace || opts->workspace_bytes < need) return MPGEMM_ERR_WORKSPACE;
+    if ((uintptr_t)opts->workspace % 256 != 0) return MPGEMM_ERR_WORKSPACE;
+    return hip_rc(launch_split_stages(P, s, cfg, last_stage > 0 ? last_stage : 4, g, opts->workspace, st));
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+#define MPG_GEMM(NAME, P)                                                                          \
+    int NAME(char ta, char tb, int64_t m, int64_t n, int64_t k, const double* alpha,              \
+             const double* A, int64_t lda, int64_t sa, const double* B, int64_t ldb, int64_t sb,  \
+             const double* beta, double* C, int64_t ldc, int64_t sc, hipStream_t st) {            \
+        return gemm_common(P, ta, tb, m, n, k, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, st, \
+                           nullptr, false, 0);                                                    \
+    }                                                                                              \
+    int NAME##_ex(char ta, char tb, int64_t m, int64_t n, int64_t k, const double* alpha,         \
+                  const double* A, int64_t lda, int64_t sa, const double* B, int64_t ldb,          \
+                  int64_t sb, const double* beta, double* C, int64_t ldc, int64_t sc,             \
+                  hipStream_t st, const mpgemm_opts* opts) {                                       \
+        return gemm_common(P, ta, tb, m, n, k, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, st, \
+                           opts, true, 0);                                                        \
+    }
+
+MPG_GEMM(mpgemm_dd, 2)
+MPG_GEMM(mpgemm_td, 3)
+MPG_GEMM(mpgemm_qd, 4)
+#undef MPG_GEMM
+
+size_t mpgemm_workspace_bytes(int prec, int form, int64_t m, int64_t n, int64_t k, int slices,
+                              int tile) {
+    if (prec < 2 || prec > 4 || m < 0 || n < 0 || k < 0 || slices < 0 || slices > kMaxSlices)
+        return 0;
+    if (form == MPGEMM_FORM_PLAIN) return 0;
+    if (form != MPGEMM_FORM_SPLIT_I8 && form != MPGEMM_FORM_AUTO) return 0;
+    const int s = slices > 0 ? slices : kDefaultSlices[prec];
+    const int cfg = pick_tile(prec, MPGEMM_FORM_SPLIT_I8, m, n, k, tile);
+    return split_workspace_bytes(prec, m, n, k, s, cfg);
+}
+
+int mpgemm_split_layout(int prec, int64_t m, int64_t n, int64_t k, int slices, int tile,
+                        size_t* off_E, size_t* off_F, size_t* off_DA, size_t* off_DB,
+                        size_t* off_S, int64_t* Mp, int64_t* Np, int64_t* Kp) {
+    if (prec < 2 || prec > 4) return -1;
+    if (m < 0) return -2;
+    if (n < 0) return -3;
+    if (k < 0) return -4;
+    if (slices < 0 || slices > kMaxSlices) return -5;
+    const int s = slices > 0 ? slices : kDefaultSlices[prec];
+    const int cfg = pick_tile(prec, MPGEMM_FORM_SPLIT_I8, m, n, k, tile);
+    if (!off_E || !off_F || !off_DA || !off_DB || !off_S || !Mp || !Np || !Kp) return -7;
+    return split_layout(prec, m, n, k, s, cfg, off_E, off_F, off_DA, off_DB, off_S, Mp, Np, Kp);
+}
+
+int mpgemm_split_stages(int prec, int last, char ta, char tb, int64_t m, int64_t n, int64_t k,
+                        const double* alpha, const double* A, int64_t lda, int64_t sa,
+                        const double* B, int64_t ldb, int64_t sb, const double* beta, double* C,
+                        int64_t ldc, int64_t sc, hipStream_t st, const mpgemm_opts* opts) {
+    if (prec < 2 || prec > 4) return -1;
+    if (last < 1 || last > 4) return -2;
+    int rc = gemm_common(prec, ta, tb, m, n, k, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, st,
+                         opts, true, last);
+    // re-number argument errors of the shared part (shifted by the two leading args)
+    return rc < 0 ? rc - 2 : rc;
+}
+
+#define MPG_VEC(NAME, P, OP)                                                                     \
+    int NAME(int64_t n, const double* x, int64_t sx, const double* y, int64_t sy, double* r,     \
+             int64_t sr, hipStream_t st) {                                                       \
+        if (n < 0) return -1;                                                                    \
+        if (n > 0 && !x) return -2;                                                              \
+        if (sx < n) return -3;                                                                   \
+        if (n > 0 && !y) return -4;                                                              \
+        if (sy < n) return -5;                                                                   \
+        if (n > 0 && !r) return -6;                                                              \
+        if (sr < n) return -7;                                                                   \
+        if (n == 0) return 0;                                                                    \
+        return hip_rc(launch_vec(P, OP, n, x, sx, y, sy, r, sr, st));                            \
+    }
+MPG_VEC(mp_vec_dd_add, 2, 0)
+MPG_VEC(mp_vec_dd_mul, 2, 1)
+MPG_VEC(mp_vec_td_add, 3, 0)
+MPG_VEC(mp_vec_td_mul, 3, 1)
+MPG_VEC(mp_vec_qd_add, 4, 0)
+MPG_VEC(mp_vec_qd_mul, 4, 1)
+#undef MPG_VEC
+
+// ---- batched plan -----------------------------------------------------------
+
+struct mpgemm_batch_plan {
+    int P;
+    int cfg;
+    int64_t count;
+    int64_t tiles;
+    int grid;
+    void* d_desc;
+    unsigned* d_counter;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+int mpgemm_batch_plan_create(int prec, int64_t count, const mpgemm_problem* probs,
+                             const mpgemm_opts* opts, hipStream_t st, mpgemm_batch_plan** out) {
+    if (prec < 2 || prec > 4) return -1;
+    if (count < 0) return -2;
+    if (count > 0 && !probs) return -3;
+    if (!out) return -6;
+    *out = nullptr;
+    const int P = prec;
+    std::vector<GemmArgs> gs((size_t)count);
+    for (int64_t q = 0; q < count; ++q) {
+        const mpgemm_problem& pr = probs[q];
+        int rc = validate(P, pr.transa, pr.transb, pr.m, pr.n, pr.k, pr.alpha, pr.A, pr.lda,
+                          pr.a_plane_stride, pr.B, pr.ldb, pr.b_plane_stride, pr.beta, pr.C,
+                          pr.ldc, pr.c_plane_stride, gs[(size_t)q]);
+        if (rc) return rc == MPGEMM_ERR_ALIAS ? rc : (int)(-(1000 + q));
+    }
+    int cfg = (opts && opts->tile >= 0 && opts->tile < kPlainConfigs) ? opts->tile : -1;
+    if (cfg < 0) {
+        // tile shape for the typical problem of the batch
+        int64_t mm = 0, nn = 0, kk = 0;
+        for (const auto& g : gs) { mm += g.m; nn += g.n; kk += g.k; }
+        if (count > 0) { mm /= count; nn /= count; kk /= count; }
+        cfg = tuned_tile(P, 3, mm, nn, kk);      // form id 3: batched
+        if (cfg < 0) cfg = P == 2 ? 1 : (P == 3 ? 2 : 1);
+    }
+    // largest k first so the queue ends with the cheapest tiles
+    std::vector<int64_t> order((size_t)count);
+    for (int64_t q = 0; q < count; ++q) order[(size_t)q] = q;
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+        return gs[(size_t)a].k > gs[(size_t)b].k;
+    });
+    auto* plan = new (std::nothrow) mpgemm_batch_plan();
+    if (!plan) return MPGEMM_ERR_NOMEM;
+    plan->P = P;
+    plan->cfg = cfg;
+    plan->count = count;
+    const size_t bytes = std::max<size_t>(batch_desc_bytes(count), 256);
+    std::vector<char> host(bytes);
+    plan->tiles = batch_build_desc(P, cfg, count, gs.data(), order.data(), host.data());
+    plan->grid = (int)std::max<int64_t>(1, std::min<int64_t>(batch_max_grid(P, cfg), plan->tiles));
+    if (hipMalloc(&plan->d_desc, bytes) != hipSuccess) { delete plan; return MPGEMM_ERR_NOMEM; }
+    if (hipMalloc((void**)&plan->d_counter, 256) != hipSuccess) {
+        (void)hipFree(plan->d_desc);
+        delete plan;
+        return MPGEMM_ERR_NOMEM;
+    }
+    int err = 0;
+    if (hipMemcpyAsync(plan->d_desc, host.data(), bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        err = MPGEMM_ERR_HIP;
+    // capture counter reset + persistent launch on a private stream
+    hipStream_t cs = nullptr;
+    if (!err && hipStreamCreate(&cs) != hipSuccess) err = MPGEMM_ERR_GRAPH;
+    if (!err) {
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) err = MPGEMM_ERR_GRAPH;
+        else {
+            int lrc = launch_batch(P, cfg, count, plan->tiles, plan->d_desc, plan->d_counter, plan->grid, cs);
+            hipGraph_t gr = nullptr;
+            if (hipStreamEndCapture(cs, &gr) != hipSuccess || lrc) err = MPGEMM_ERR_GRAPH;
+            plan->graph = gr;
+            if (!err && hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0) != hipSuccess)
+                err = MPGEMM_ERR_GRAPH;
+        }
+        (void)hipStreamDestroy(cs);
+    }
+    if (err) {
+        mpgemm_batch_plan_destroy(plan);
+        return err;
+    }
+    *out = plan;
+    return 0;
+}
+
+int mpgemm_batch_plan_run(mpgemm_batch_plan* plan, hipStream_t st) {
+    if (!plan) return -1;
+    if (plan->tiles == 0) return 0;
+    return hipGraphLaunch(plan->exec, st) == hipSuccess ? 0 : MPGEMM_ERR_HIP;
+}
+
+int mpgemm_batch_plan_launch(mpgemm_batch_plan* plan, hipStream_t st) {
+    if (!plan) return -1;
+    if (plan->tiles == 0) return 0;
+    return hip_rc(launch_batch(plan->P, plan->cfg, plan->count, plan->tiles, plan->d_desc,
+                               plan->d_counter, plan->grid, st));
+}
+
+int mpgemm_batch_plan_info(const mpgemm_batch_plan* plan, int64_t* tiles, int* grid, int* tile_cfg) {
+    if (!plan) return -1;
+    if (tiles) *tiles = plan->tiles;
+    if (grid) *grid = plan->grid;
+    if (tile_cfg) *tile_cfg = plan->cfg;
+    return 0;
+}
+
+int mpgemm_batch_plan_destroy(mpgemm_batch_plan* plan) {
+    if (!plan) return -1;
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    if (plan->d_desc) (void)hipFree(plan->d_desc);
+    if (plan->d_counter) (void)hipFree(plan->d_counter);
+    delete plan;
+    return 0;
+}
+
+// ---- autotuner --------------------------------------------------------------
+
+int mpgemm_num_configs(int prec, int form) {
+    if (prec < 2 || prec > 4) return 0;
+    if (form == MPGEMM_FORM_PLAIN || form == 3) return kPlainConfigs;
+    if (form == MPGEMM_FORM_SPLIT_I8) return kSplitConfigs;
+    return 0;
+}
+
+static int time_config(int P, int form, int cfg, const GemmArgs& g, int s, void* ws, size_t wsb,
+                       hipStream_t st, float* ms_out) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return MPGEMM_ERR_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return MPGEMM_ERR_HIP; }
+    auto run = [&]() {
+        return form == MPGEMM_FORM_PLAIN ? launch_plain(P, cfg, g, st)
+                                         : launch_split(P, s, cfg, g, ws, wsb, st);
+    };
+    int rc = run();  // warm-up
+    float best = 1e30f;
+    for (int rep = 0; rep < 3 && !rc; ++rep) {
+        (void)hipEventRecord(e0, st);
+        rc = run();
+        (void)hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess) rc = MPGEMM_ERR_HIP;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        best = std::min(best, ms);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms_out = best;
+    return rc ? MPGEMM_ERR_HIP : 0;
+}
+
+int mpgemm_autotune(int prec, int form, int64_t m, int64_t n, int64_t k, int slices,
+                    hipStream_t st, int* best) {
+    if (prec < 2 || prec > 4) return -1;
+    if (form != MPGEMM_FORM_PLAIN && form != MPGEMM_FORM_SPLIT_I8) return -2;
+    if (m <= 0) return -3;
+    if (n <= 0) return -4;
+    if (k <= 0) return -5;
+    if (slices < 0 || slices > kMaxSlices) return -6;
+    const int P = prec;
+    const int s = slices > 0 ? slices : kDefaultSlices[P];
+    if (form == MPGEMM_FORM_SPLIT_I8 && !split_k_ok(k, s)) return MPGEMM_ERR_UNSUPPORTED;
+    double *A = nullptr, *B = nullptr, *C = nullptr;
+    void* ws = nullptr;
+    size_t wsb = 0;
+    const size_t na = (size_t)P * m * k, nb = (size_t)P * k * n, nc = (size_t)P * m * n;
+    int rc = 0;
+    if (hipMalloc((void**)&A, na * 8) != hipSuccess || hipMalloc((void**)&B, nb * 8) != hipSuccess ||
+        hipMalloc((void**)&C, nc * 8) != hipSuccess)
+        rc = MPGEMM_ERR_NOMEM;
+    if (!rc && form == MPGEMM_FORM_SPLIT_I8) {
+        for (int c = 0; c < kSplitConfigs; ++c) wsb = std::max(wsb, split_workspace_bytes(P, m, n, k, s, c));
+        if (hipMalloc(&ws, wsb) != hipSuccess) rc = MPGEMM_ERR_NOMEM;
+    }
+    if (!rc) rc = launch_fill(P, A, m * k, m * k, 11, st) ? MPGEMM_ERR_HIP : 0;
+    if (!rc) rc = launch_fill(P, B, k * n, k * n, 12, st) ? MPGEMM_ERR_HIP : 0;
+    int chosen = -1;
+    if (!rc) {
+        GemmArgs g{};
+        g.m = m; g.n = n; g.k = k;
+        g.A = A; g.lda = m; g.sa = m * k;
+        g.B = B; g.ldb = k; g.sb = k * n;
+        g.C = C; g.ldc = m; g.sc = m * n;
+        g.alpha[0] = 1.0;
+        float best_ms = 1e30f;
+        const int nconf = mpgemm_num_configs(P, form);
+        for (int c = 0; c < nconf && !rc; ++c) {
+            float ms = 0.f;
+            rc = time_config(P, form, c, g, s, ws, wsb, st, &ms);
+            if (!rc && ms < best_ms) { best_ms = ms; chosen = c; }
+        }
+    }
+    if (A) (void)hipFree(A);
+    if (B) (void)hipFree(B);
+    if (C) (void)hipFree(C);
+    if (ws) (void)hipFree(ws);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[std::make_tuple(P, form, ilog2(m), ilog2(n), ilog2(k))] = chosen;
+    }
+    if (best) *best = chosen;
+    return 0;
+}
+
+int mpgemm_autotune_save(const char* path) {
+    if (!path) return -1;
+    FILE* f = std::fopen(path, "w");
+    if (!f) return MPGEMM_ERR_HIP;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    std::fprintf(f, "# mpgemm tuning table v1 gfx950: prec form log2m log2n log2k tile\n");
+    for (const auto& kv : g_tune)
+        std::fprintf(f, "%d %d %d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first),
+                     std::get<2>(kv.first), std::get<3>(kv.first), std::get<4>(kv.first), kv.second);
+    std::fclose(f);
+    return 0;
+}
+
+int mpgemm_autotune_load(const char* path) {
+    if (!path) return -1;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return MPGEMM_ERR_HIP;
+    char line[256];
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    while (std::fgets(line, sizeof line, f)) {
+        if (line[0] == '#') continue;
+        int P, form, a, b, c, t;
+        if (std::sscanf(line, "%d %d %d %d %d %d", &P, &form, &a, &b, &c, &t) == 6 && P >= 2 && P <= 4 &&
+            t >= 0 && t < 16)
+            g_tune[std::make_tuple(P, form, a, b, c)] = t;
+    }
+    std::fclose(f);
+    return 0;
+}
+
+// ---- slice-count rule -------------------------------------------------------
+
+int mpgemm_tune_slices(int prec, char ta, char tb, int64_t m, int64_t n, int64_t k, const double* A,
+                       int64_t lda, int64_t sa, const double* B, int64_t ldb, int64_t sb,
+                       double target, int smin, int smax, hipStream_t st, int* s_out,
+                       double* ratio_out) {
+    // arguments: 1 prec, 2 transa, 3 transb, 4 m, 5 n, 6 k, 7 A, 8 lda, 9 a_plane_stride,
+    // 10 B, 11 ldb, 12 b_plane_stride, 13 target, 14 smin, 15 smax, 16 stream, 17 s_out
+    if (prec < 2 || prec > 4) return -1;
+    if (!valid_trans(ta)) return -2;
+    if (!valid_trans(tb)) return -3;
+    if (m < 0) return -4;
+    if (n < 0) return -5;
+    if (k < 0) return -6;
+    const int P = prec;
+    const int64_t nrowa = is_trans(ta) ? k : m, ncola = is_trans(ta) ? m : k;
+    const int64_t nrowb = is_trans(tb) ? n : k, ncolb = is_trans(tb) ? k : n;
+    const bool reads = m > 0 && n > 0 && k > 0;
+    if (reads && !A) return -7;
+    if (lda < std::max<int64_t>(1, nrowa)) return -8;
+    if (sa < lda * ncola) return -9;
+    if (reads && !B) return -10;
+    if (ldb < std::max<int64_t>(1, nrowb)) return -11;
+    if (sb < ldb * ncolb) return -12;
+    if (!(target > 0.0)) return -13;
+    if (smin < 1 || smin > kMaxSlices) return -14;
+    if (smax < smin || smax > kMaxSlices) return -15;
+    if (!s_out) return -17;
+    GemmArgs g{};
+    g.m = m; g.n = n; g.k = k;
+    g.A = A; g.lda = lda; g.sa = sa;
+    g.B = B; g.ldb = ldb; g.sb = sb;
+    g.ta = is_trans(ta) ? 1 : 0;
+    g.tb = is_trans(tb) ? 1 : 0;
+    g.alpha[0] = 1.0;
+    const int64_t R = std::min<int64_t>(m, 64);
+    const int64_t r0 = (m - R) / 2;
+    int rc;
+    if (m == 0 || n == 0 || k == 0) { *s_out = smin; if (ratio_out) *ratio_out = 0.0; return 0; }
+    if (!split_k_ok(k, smax)) return MPGEMM_ERR_UNSUPPORTED;
+    // the R x n sub-problem on rows r0.. of op(A)
+    GemmArgs sub = g;
+    sub.m = R;
+    sub.A = g.ta ? g.A + r0 * g.lda : g.A + r0;
+    sub.ldc = R;
+    sub.sc = R * n;
+    double *Cr = nullptr, *Cs = nullptr, *absab = nullptr, *ratio = nullptr;
+    void* ws = nullptr;
+    const size_t wsb = split_workspace_bytes(P, R, n, k, smax, 1);
+    rc = 0;
+    if (hipMalloc((void**)&Cr, 8 * (size_t)P * R * n) != hipSuccess ||
+        hipMalloc((void**)&Cs, 8 * (size_t)P * R * n) != hipSuccess ||
+        hipMalloc((void**)&absab, 8 * (size_t)R * n) != hipSuccess ||
+        hipMalloc((void**)&ratio, 8 * (size_t)R * n) != hipSuccess || hipMalloc(&ws, wsb) != hipSuccess)
+        rc = MPGEMM_ERR_NOMEM;
+    std::vector<double> host((size_t)R * n);
+    const double u = P == 2 ? std::ldexp(1.0, -104) : (P == 3 ? std::ldexp(1.0, -150) : std::ldexp(1.0, -200));
+    int chosen = smax;
+    double chosen_ratio = -1.0;
+    if (!rc) {
+        GemmArgs gr = sub;
+        gr.C = Cr;
+        rc = launch_plain(P, plain_default_config(P, R, n, k), gr, st) ? MPGEMM_ERR_HIP : 0;
+        if (!rc) rc = launch_absdot(sub, absab, st) ? MPGEMM_ERR_HIP : 0;
+    }
+    for (int s = smin; s <= smax && !rc; ++s) {
+        GemmArgs gs2 = sub;
+        gs2.C = Cs;
+        rc = launch_split(P, s, 1, gs2, ws, wsb, st) ? MPGEMM_ERR_HIP : 0;
+        if (!rc)
+            rc = launch_diff_ratio(P, R, n, Cs, Cr, R, R * n, absab, 1.0 / ((double)k * u), ratio, st)
+                     ? MPGEMM_ERR_HIP : 0;
+        if (!rc && (hipMemcpyAsync(host.data(), ratio, 8 * host.size(), hipMemcpyDeviceToHost, st) != hipSuccess ||
+                    hipStreamSynchronize(st) != hipSuccess))
+            rc = MPGEMM_ERR_HIP;
+        if (rc) break;
+        double mx = 0.0;
+        for (double v : host) mx = std::max(mx, v);
+        if (mx <= target) { chosen = s; chosen_ratio = mx; break; }
+        chosen_ratio = mx;
+    }
+    if (Cr) (void)hipFree(Cr);
+    if (Cs) (void)hipFree(Cs);
+    if (absab) (void)hipFree(absab);
+    if (ratio) (void)hipFree(ratio);
+    if (ws) (void)hipFree(ws);
+    if (rc) return rc;
+    *s_out = chosen;
+    if (ratio_out) *ratio_out = chosen_ratio;
+    return 0;
+}
+
+// ---- misc -------------------------------------------------------------------
+
+const char* mpgemm_strerror(int code) {
+    if (code == 0) return "success";
+    if (code < 0) return "invalid argument (the code is minus its 1-based position)";
+    switch (code) {
+    case MPGEMM_ERR_HIP: return "HIP runtime call or kernel launch failed";
+    case MPGEMM_ERR_WORKSPACE: return "split form: workspace missing, misaligned or too small";
+    case MPGEMM_ERR_UNSUPPORTED: return "shape or option not supported by this form";
+    case MPGEMM_ERR_GRAPH: return "hipGraph capture or instantiation failed";
+    case MPGEMM_ERR_ALIAS: return "C overlaps A or B";
+    case MPGEMM_ERR_NOMEM: return "allocation failed";
+    default: return "unknown error";
+    }
+}
+
+const char* mpgemm_version(void) { return "mpgemm 0.1.0 gfx950"; }
+
+void mpgemm_finalize(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+}
+
+}  // extern "C"

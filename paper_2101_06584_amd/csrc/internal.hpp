@@ -1,0 +1,67 @@
+// internal.hpp -- host-side declarations shared by the kernel translation
+// units and the C-ABI layer (not part of the public interface).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mpg {
+
+// One GEMM C = alpha op(A) op(B) + beta C on component planes (column-major
+// planes, plane strides sa/sb/sc in elements).
+struct GemmArgs {
+    int64_t m, n, k;
+    const double* A;
+    int64_t lda, sa;
+    const double* B;
+    int64_t ldb, sb;
+    double* C;
+    int64_t ldc, sc;
+    int ta, tb;            // 1 = transposed
+    double alpha[4];
+    double beta[4];
+};
+
+// Plain (FP64-VALU EFT) tile configurations.
+struct PlainConfig {
+    int tx, ty, tm, tn, bk;   // threads x/y, per-thread rows/cols, k tile
+};
+
+constexpr int kPlainConfigs = 4;
+PlainConfig plain_config(int P, int id);
+int plain_default_config(int P, int64_t m, int64_t n, int64_t k);
+
+// Launchers return a hipError_t value (0 on success).
+int launch_plain(int P, int cfg, const GemmArgs& g, hipStream_t st);
+int launch_scale(int P, const GemmArgs& g, hipStream_t st);   // alpha == 0 or k == 0
+int launch_vec(int P, int op, int64_t n, const double* x, int64_t sx, const double* y,
+               int64_t sy, double* r, int64_t sr, hipStream_t st);
+
+// Batched persistent form.  Device descriptor layout is private to the
+// kernel file; these helpers size and fill it.
+struct BatchProblemHost {
+    GemmArgs g;
+};
+size_t batch_desc_bytes(int64_t count);
+// Fills a host staging buffer with descriptors (tile prefix sums included);
+// returns total tile count.  order[] gives the processing order.
+int64_t batch_build_desc(int P, int cfg, int64_t count, const GemmArgs* probs, const int64_t* order,
+                         void* host_buf);
+int launch_batch(int P, int cfg, int64_t count, int64_t total_tiles, const void* dev_desc,
+                 unsigned* dev_counter, int grid, hipStream_t st);
+int batch_max_grid(int P, int cfg);
+
+// Split (sliced INT8, MFMA) form.
+struct SplitConfig {
+    int bm, bn;                 // output tile per workgroup
+};
+constexpr int kSplitConfigs = 2;
+SplitConfig split_config(int id);
+size_t split_workspace_bytes(int P, int64_t m, int64_t n, int64_t k, int s, int cfg);
+int launch_split(int P, int s, int cfg, const GemmArgs& g, void* ws, size_t ws_bytes,
+                 hipStream_t st);
+// Stage entry points for testing the split pipeline piece by piece.
+int split_layout(int P, int64_t m, int64_t n, int64_t k, int s, int cfg, size_t* offE, size_t* offF,
+                 size_t* offDA, size_t* offDB, size_t* offS, int64_t* Mp, int64_t* Np, int64_t* Kp);
+
+}  // namespace mpg

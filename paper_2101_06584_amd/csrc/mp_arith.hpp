@@ -1,0 +1,280 @@
+// mp_arith.hpp -- device-side double-double (P=2), triple-double (P=3) and
+// quad-double (P=4) arithmetic for gfx950, built from error-free
+// transformations on the FP64 vector ALUs.
+//
+// Every function reproduces, operation for operation, the sequences of the
+// paper (Kouya, arXiv 2101.06584): Sec. 2.1 (QuickTwoSum, TwoSum, TwoProd),
+// Algorithm 1 (DD add), Algorithm 2 (DD mul), Algorithm 4 (TD mul), Algorithm
+// 5 (QD add, also the default TD add "TDaddq" with zero fourth components)
+// and Algorithm 6 (QD mul), so a GEMM that keeps one sequential k-chain per
+// entry is bitwise reproducible.  The data-dependent branches of VSEB(k) and
+// Renorm are written as selects so a wavefront never diverges; the selected
+// values are exactly those the branching form produces.
+//
+// Compile with -ffp-contract=off: a contracted a*b+c would change results.
+#pragma once
+#pragma clang fp contract(off)
+
+#include <hip/hip_runtime.h>
+
+namespace mpg {
+
+template <int P>
+struct mp {
+    double c[P];
+};
+
+#define MPG_DEV __device__ __forceinline__
+
+// ---- Sec. 2.1 ------------------------------------------------------------
+
+// s = fl(a+b), e = b - (s - a); exact when exponent(a) >= exponent(b).
+MPG_DEV void quick_two_sum(double a, double b, double& s, double& e) {
+    double sum = a + b;
+    e = b - (sum - a);
+    s = sum;
+}
+
+// Knuth's TwoSum in the lane order of Algorithm 5: s, v, u, w, u', e.
+MPG_DEV void two_sum(double a, double b, double& s, double& e) {
+    double sum = a + b;
+    double v = sum - a;
+    double u = sum - v;
+    double w = a - u;
+    double u2 = b - v;
+    e = w + u2;
+    s = sum;
+}
+
+// p = fl(ab), e = ab - p exactly via the fused multiply-add.
+MPG_DEV void two_prod(double a, double b, double& p, double& e) {
+    double prod = a * b;
+    e = __builtin_fma(a, b, -prod);
+    p = prod;
+}
+
+// (a, b, c) <- exact three-term re-sum (three TwoSums).
+MPG_DEV void three_sum(double& a, double& b, double& c) {
+    double t1, t2, t3;
+    two_sum(a, b, t1, t2);
+    two_sum(c, t1, a, t3);
+    two_sum(t2, t3, b, c);
+}
+
+// (a, b) <- two leading terms; the two error terms rounded into b.
+MPG_DEV void three_sum2(double& a, double& b, double c) {
+    double t1, t2, t3;
+    two_sum(a, b, t1, t2);
+    two_sum(c, t1, a, t3);
+    b = t2 + t3;
+}
+
+// Five terms to four (Sec. 2.4's renormalisation "as simple loops"): a
+// bottom-up QuickTwoSum pass, then a top-down pass in which a non-zero
+// rounding error closes an output slot; when the third slot closes the last
+// one takes the carry plus what remains.  Unrolled, slot writes by select.
+MPG_DEV void renorm4(double c0, double c1, double c2, double c3, double c4,
+                     double& r0, double& r1, double& r2, double& r3) {
+    double s, e0, e1, e2, e3, e4;
+    quick_two_sum(c3, c4, s, e4);
+    quick_two_sum(c2, s, s, e3);
+    quick_two_sum(c1, s, s, e2);
+    quick_two_sum(c0, s, e0, e1);
+
+    // pair (e0, e1) as pass 1 produced it
+    bool k1 = (e1 != 0.0);
+    r0 = k1 ? e0 : 0.0;
+    r1 = 0.0;
+    r2 = 0.0;
+    r3 = 0.0;
+    double carry = k1 ? e1 : e0;
+    int j = k1 ? 1 : 0;
+
+    double sv, t;
+    quick_two_sum(carry, e2, sv, t);
+    bool k2 = (t != 0.0);
+    r0 = (k2 && j == 0) ? sv : r0;
+    r1 = (k2 && j == 1) ? sv : r1;
+    j += k2 ? 1 : 0;
+    carry = k2 ? t : sv;
+
+    quick_two_sum(carry, e3, sv, t);
+    bool k3 = (t != 0.0);
+    r0 = (k3 && j == 0) ? sv : r0;
+    r1 = (k3 && j == 1) ? sv : r1;
+    r2 = (k3 && j == 2) ? sv : r2;
+    j += k3 ? 1 : 0;
+    carry = k3 ? t : sv;
+    bool done = (j == 3);
+
+    // When the third slot closed at e3, the last slot is carry + e4, which is
+    // exactly the sum half of this QuickTwoSum.
+    quick_two_sum(carry, e4, sv, t);
+    bool k4 = !done && (t != 0.0);
+    r0 = (k4 && j == 0) ? sv : r0;
+    r1 = (k4 && j == 1) ? sv : r1;
+    r2 = (k4 && j == 2) ? sv : r2;
+    j += k4 ? 1 : 0;
+    carry = k4 ? t : sv;
+
+    r0 = (j == 0) ? carry : r0;
+    r1 = (j == 1) ? carry : r1;
+    r2 = (j == 2) ? carry : r2;
+    r3 = (j == 3) ? carry : r3;
+}
+
+// VSEB(2) on three terms (Sec. 2.3), as used by the TD product.  Cases of the
+// two QuickTwoSums' error terms (t1, t2):
+//   t1 != 0:           (s1, s2) with s2 from QuickTwoSum(t1, e3)
+//   t1 == 0, t2 != 0:  (s2, t2) with s2 from QuickTwoSum(s1, e3)
+//   t1 == 0, t2 == 0:  (s2, 0)
+MPG_DEV void vseb2(double e1, double e2, double e3, double& r1, double& r2) {
+    double s1, t1, s2, t2;
+    quick_two_sum(e1, e2, s1, t1);
+    bool k1 = (t1 != 0.0);
+    double carry = k1 ? t1 : s1;
+    quick_two_sum(carry, e3, s2, t2);
+    bool k2 = (t2 != 0.0);
+    r1 = k1 ? s1 : s2;
+    r2 = k1 ? s2 : (k2 ? t2 : 0.0);
+}
+
+// ---- Algorithm 1 / Algorithm 2 -------------------------------------------
+
+MPG_DEV mp<2> add(const mp<2>& x, const mp<2>& y) {
+    double s, e;
+    two_sum(x.c[0], y.c[0], s, e);
+    double w = x.c[1] + y.c[1];
+    e = e + w;
+    mp<2> r;
+    quick_two_sum(s, e, r.c[0], r.c[1]);
+    return r;
+}
+
+MPG_DEV mp<2> mul(const mp<2>& x, const mp<2>& y) {
+    double p1, p2;
+    two_prod(x.c[0], y.c[0], p1, p2);
+    double w1 = x.c[0] * y.c[1];
+    double w2 = x.c[1] * y.c[0];
+    double w3 = w1 + w2;
+    p2 = p2 + w3;
+    mp<2> r;
+    quick_two_sum(p1, p2, r.c[0], r.c[1]);
+    return r;
+}
+
+// ---- Algorithm 5 (QD add; t3 = w3 + u3 like the other lanes) ---------------
+
+MPG_DEV void qd_add_raw(double x0, double x1, double x2, double x3,
+                        double y0, double y1, double y2, double y3,
+                        double& r0, double& r1, double& r2, double& r3) {
+    double s0 = x0 + y0, s1 = x1 + y1, s2 = x2 + y2, s3 = x3 + y3;
+    double v0 = s0 - x0, v1 = s1 - x1, v2 = s2 - x2, v3 = s3 - x3;
+    double u0 = s0 - v0, u1 = s1 - v1, u2 = s2 - v2, u3 = s3 - v3;
+    double w0 = x0 - u0, w1 = x1 - u1, w2 = x2 - u2, w3 = x3 - u3;
+    u0 = y0 - v0;
+    u1 = y1 - v1;
+    u2 = y2 - v2;
+    u3 = y3 - v3;
+    double t0 = w0 + u0, t1 = w1 + u1, t2 = w2 + u2, t3 = w3 + u3;
+    two_sum(s1, t0, s1, t0);
+    three_sum(s2, t0, t1);
+    three_sum2(s3, t0, t2);
+    t0 = (t0 + t1) + t3;
+    renorm4(s0, s1, s2, s3, t0, r0, r1, r2, r3);
+}
+
+MPG_DEV mp<4> add(const mp<4>& x, const mp<4>& y) {
+    mp<4> r;
+    qd_add_raw(x.c[0], x.c[1], x.c[2], x.c[3], y.c[0], y.c[1], y.c[2], y.c[3],
+               r.c[0], r.c[1], r.c[2], r.c[3]);
+    return r;
+}
+
+// TDaddq: the QD addition with zero fourth components, fourth output dropped.
+MPG_DEV mp<3> add(const mp<3>& x, const mp<3>& y) {
+    mp<3> r;
+    double r3;
+    qd_add_raw(x.c[0], x.c[1], x.c[2], 0.0, y.c[0], y.c[1], y.c[2], 0.0,
+               r.c[0], r.c[1], r.c[2], r3);
+    (void)r3;
+    return r;
+}
+
+// ---- Algorithm 6 (QD mul; the listing's dead first line omitted) ----------
+
+MPG_DEV mp<4> mul(const mp<4>& x, const mp<4>& y) {
+    double p0, q0, p1, q1, p2, q2, p3, q3, p4, q4, p5, q5;
+    two_prod(x.c[0], y.c[0], p0, q0);
+    two_prod(x.c[0], y.c[1], p1, q1);
+    two_prod(x.c[1], y.c[0], p2, q2);
+    two_prod(x.c[0], y.c[2], p3, q3);
+    two_prod(x.c[1], y.c[1], p4, q4);
+    two_prod(x.c[2], y.c[0], p5, q5);
+    three_sum(p1, p2, q0);
+    three_sum(p2, q1, q2);
+    three_sum(p3, p4, p5);
+    double s0, t0, s1, t1, s2;
+    two_sum(p2, p3, s0, t0);
+    two_sum(q1, p4, s1, t1);
+    s2 = q2 + p5;
+    two_sum(s1, t0, s1, t0);
+    s2 = s2 + (t0 + t1);
+    // O(eps^3) terms, one rounded multiply and one rounded add each, in order
+    s1 = s1 + x.c[0] * y.c[3];
+    s1 = s1 + x.c[1] * y.c[2];
+    s1 = s1 + x.c[2] * y.c[1];
+    s1 = s1 + x.c[3] * y.c[0];
+    s1 = s1 + q0;
+    s1 = s1 + q3;
+    s1 = s1 + q4;
+    s1 = s1 + q5;
+    mp<4> r;
+    renorm4(p0, p1, s0, s1, s2, r.c[0], r.c[1], r.c[2], r.c[3]);
+    return r;
+}
+
+// ---- Algorithm 4 (TD "fast" product) --------------------------------------
+
+MPG_DEV mp<3> mul(const mp<3>& x, const mp<3>& y) {
+    double z00u, z00l, z01u, z01l, z10u, z10l;
+    two_prod(x.c[0], y.c[0], z00u, z00l);
+    two_prod(x.c[0], y.c[1], z01u, z01l);
+    two_prod(x.c[1], y.c[0], z10u, z10l);
+    // VecSum(z00l, z01u, z10u) -> (b0, b1, b2)
+    double b0, b1, b2, sv;
+    two_sum(z01u, z10u, sv, b2);
+    two_sum(z00l, sv, b0, b1);
+    double c = __builtin_fma(x.c[1], y.c[1], b2);
+    double z31 = __builtin_fma(x.c[0], y.c[2], z10l);
+    double z32 = __builtin_fma(x.c[2], y.c[0], z01l);
+    double z3 = z31 + z32;
+    double s3 = c + z3;
+    // VecSum(z00u, b0, b1, s3) -> (e0, e1, e2, e3)
+    double e0, e1, e2, e3;
+    two_sum(b1, s3, sv, e3);
+    two_sum(b0, sv, sv, e2);
+    two_sum(z00u, sv, e0, e1);
+    mp<3> r;
+    r.c[0] = e0;
+    vseb2(e1, e2, e3, r.c[1], r.c[2]);
+    return r;
+}
+
+template <int P>
+MPG_DEV mp<P> mp_zero() {
+    mp<P> r;
+#pragma unroll
+    for (int q = 0; q < P; ++q) r.c[q] = 0.0;
+    return r;
+}
+
+template <int P>
+MPG_DEV bool mp_is_zero(const mp<P>& x) {
+    bool z = true;
+#pragma unroll
+    for (int q = 0; q < P; ++q) z = z && (x.c[q] == 0.0);
+    return z;
+}
+
+}  // namespace mpg

@@ -1,0 +1,374 @@
+// plain_gemm.hip -- FP64-VALU error-free-transformation GEMM for gfx950:
+// C = alpha op(A) op(B) + beta C in DD / TD / QD on component planes.
+//
+// Method: eqn (1) of Sec. 3 with the DD/TD/QD additions and multiplications of
+// Algorithms 1-6.  Each output entry keeps one running P-component sum over
+// k in ascending order, so the result is bitwise independent of the tiling
+// (the paper's blocking with n_min = 32 likewise leaves each entry's chain
+// intact).  Tiles of op(A) and op(B) are staged through LDS one component
+// plane at a time; every thread owns a TM x TN block of P-component
+// accumulators.
+//
+// Also here: the element-wise vector kernels (Sec. 2.5's DD/TD/QD vector add
+// and multiply), the alpha == 0 / k == 0 scaling kernel and the persistent
+// batched kernel that reuses the same tile routine.
+#pragma clang fp contract(off)
+
+#include "internal.hpp"
+#include "mp_arith.hpp"
+
+namespace mpg {
+
+// ---------------------------------------------------------------------------
+// Tile routine
+// ---------------------------------------------------------------------------
+
+template <int P, int TX, int TY, int TM, int TN, int BK>
+struct PlainTile {
+    static constexpr int BM = TX * TM;
+    static constexpr int BN = TY * TN;
+    static constexpr int NT = TX * TY;
+    static constexpr int LDS_DOUBLES = P * BK * (BM + BN);
+
+    // Stage the k-tile [k0, k0 + BK) of op(A) rows [m0, m0 + BM) and op(B)
+    // columns [n0, n0 + BN) into LDS, zero-filling outside the matrices.
+    __device__ static void stage(const GemmArgs& g, int64_t m0, int64_t n0, int64_t k0,
+                                 double* As, double* Bs) {
+        const int tid = threadIdx.x;
+        for (int idx = tid; idx < BM * BK; idx += NT) {
+            int i, l;
+            if (!g.ta) { i = idx % BM; l = idx / BM; }
+            else       { l = idx % BK; i = idx / BK; }
+            const int64_t gi = m0 + i, gl = k0 + l;
+            const bool ok = (gi < g.m) && (gl < g.k);
+            const int64_t off = g.ta ? (gl + gi * g.lda) : (gi + gl * g.lda);
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+                As[(p * BK + l) * BM + i] = ok ? g.A[p * g.sa + off] : 0.0;
+        }
+        for (int idx = tid; idx < BN * BK; idx += NT) {
+            int j, l;
+            if (g.tb) { j = idx % BN; l = idx / BN; }
+            else      { l = idx % BK; j = idx / BK; }
+            const int64_t gj = n0 + j, gl = k0 + l;
+            const bool ok = (gj < g.n) && (gl < g.k);
+            const int64_t off = g.tb ? (gj + gl * g.ldb) : (gl + gj * g.ldb);
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+                Bs[(p * BK + l) * BN + j] = ok ? g.B[p * g.sb + off] : 0.0;
+        }
+    }
+
+    __device__ static void step(const double* As, const double* Bs, int kk, int tx, int ty,
+                                mp<P> (&acc)[TM][TN]) {
+        mp<P> a[TM], b[TN];
+#pragma unroll
+        for (int r = 0; r < TM; ++r)
+#pragma unroll
+            for (int p = 0; p < P; ++p) a[r].c[p] = As[(p * BK + kk) * BM + tx + r * TX];
+#pragma unroll
+        for (int c = 0; c < TN; ++c)
+#pragma unroll
+            for (int p = 0; p < P; ++p) b[c].c[p] = Bs[(p * BK + kk) * BN + ty + c * TY];
+#pragma unroll
+        for (int r = 0; r < TM; ++r)
+#pragma unroll
+            for (int c = 0; c < TN; ++c) acc[r][c] = add(acc[r][c], mul(a[r], b[c]));
+    }
+
+    __device__ static void run(const GemmArgs& g, const mp<P>& alpha, const mp<P>& beta,
+                               int64_t m0, int64_t n0, double* lds) {
+        double* As = lds;
+        double* Bs = lds + P * BK * BM;
+        const int tid = threadIdx.x;
+        const int tx = tid % TX, ty = tid / TX;
+        mp<P> acc[TM][TN];
+#pragma unroll
+        for (int r = 0; r < TM; ++r)
+#pragma unroll
+            for (int c = 0; c < TN; ++c) acc[r][c] = mp_zero<P>();
+
+        // alpha == 0 or k == 0: C = beta C (0 when beta == 0); nothing at all
+        // when additionally beta == 1
+        const bool az = (g.k == 0) || mp_is_zero(alpha);
+        const bool beta_zero = mp_is_zero(beta);
+        bool beta_one = beta.c[0] == 1.0;
+#pragma unroll
+        for (int p = 1; p < P; ++p) beta_one = beta_one && (beta.c[p] == 0.0);
+        if (az && beta_one) return;
+
+        const int64_t kend = az ? 0 : g.k;
+        for (int64_t k0 = 0; k0 < kend; k0 += BK) {
+            stage(g, m0, n0, k0, As, Bs);
+            __syncthreads();
+            const int64_t rem = g.k - k0;
+            if (rem >= BK) {
+#pragma unroll 2
+                for (int kk = 0; kk < BK; ++kk) step(As, Bs, kk, tx, ty, acc);
+            } else {
+                const int kb = (int)rem;
+                for (int kk = 0; kk < kb; ++kk) step(As, Bs, kk, tx, ty, acc);
+            }
+            __syncthreads();
+        }
+
+#pragma unroll
+        for (int r = 0; r < TM; ++r)
+#pragma unroll
+            for (int c = 0; c < TN; ++c) {
+                const int64_t i = m0 + tx + r * TX, j = n0 + ty + c * TY;
+                if (i < g.m && j < g.n) {
+                    const int64_t off = i + j * g.ldc;
+                    mp<P> t;
+                    if (az) {
+                        t = mp_zero<P>();
+                        if (!beta_zero) {
+                            mp<P> co;
+#pragma unroll
+                            for (int p = 0; p < P; ++p) co.c[p] = g.C[p * g.sc + off];
+                            t = mul(beta, co);
+                        }
+                    } else {
+                        t = mul(alpha, acc[r][c]);
+                        if (!beta_zero) {
+                            mp<P> co;
+#pragma unroll
+                            for (int p = 0; p < P; ++p) co.c[p] = g.C[p * g.sc + off];
+                            t = add(t, mul(beta, co));
+                        }
+                    }
+#pragma unroll
+                    for (int p = 0; p < P; ++p) g.C[p * g.sc + off] = t.c[p];
+                }
+            }
+    }
+};
+
+template <int P>
+__device__ __forceinline__ mp<P> load_scalar(const double* v) {
+    mp<P> r;
+#pragma unroll
+    for (int p = 0; p < P; ++p) r.c[p] = v[p];
+    return r;
+}
+
+template <int P, int TX, int TY, int TM, int TN, int BK>
+__global__ __launch_bounds__(TX * TY) void plain_gemm_kernel(GemmArgs g) {
+    using T = PlainTile<P, TX, TY, TM, TN, BK>;
+    __shared__ double lds[T::LDS_DOUBLES];
+    const mp<P> alpha = load_scalar<P>(g.alpha);
+    const mp<P> beta = load_scalar<P>(g.beta);
+    T::run(g, alpha, beta, (int64_t)blockIdx.x * T::BM, (int64_t)blockIdx.y * T::BN, lds);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent batched kernel: one launch, many GEMMs, a global tile queue.
+// ---------------------------------------------------------------------------
+
+struct BatchDesc {
+    GemmArgs g;
+    int64_t tile_begin;    // first global tile index of this problem
+    int64_t tiles_m;       // tiles along m
+};
+
+template <int P, int TX, int TY, int TM, int TN, int BK>
+__global__ __launch_bounds__(TX * TY) void batch_gemm_kernel(const BatchDesc* __restrict__ desc,
+                                                             int64_t count, int64_t total_tiles,
+                                                             unsigned* counter) {
+    using T = PlainTile<P, TX, TY, TM, TN, BK>;
+    __shared__ double lds[T::LDS_DOUBLES];
+    __shared__ int64_t s_tile;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int64_t t = s_tile;
+        __syncthreads();
+        if (t >= total_tiles) break;   // every wave of the block sees the same t
+        // last problem whose tile_begin <= t
+        int64_t lo = 0, hi = count - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (desc[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
+        }
+        const BatchDesc& d = desc[lo];
+        const int64_t local = t - d.tile_begin;
+        const int64_t tm = local % d.tiles_m, tn = local / d.tiles_m;
+        const mp<P> alpha = load_scalar<P>(d.g.alpha);
+        const mp<P> beta = load_scalar<P>(d.g.beta);
+        T::run(d.g, alpha, beta, tm * T::BM, tn * T::BN, lds);
+    }
+}
+
+__global__ void reset_counter_kernel(unsigned* counter) { *counter = 0u; }
+
+// ---------------------------------------------------------------------------
+// alpha == 0 or k == 0: C = beta C, or 0 when beta == 0 (C then not read).
+// ---------------------------------------------------------------------------
+
+template <int P>
+__global__ void scale_kernel(GemmArgs g) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= g.m * g.n) return;
+    const int64_t i = idx % g.m, j = idx / g.m;
+    const int64_t off = i + j * g.ldc;
+    const mp<P> beta = load_scalar<P>(g.beta);
+    mp<P> t = mp_zero<P>();
+    if (!mp_is_zero(beta)) {
+        mp<P> co;
+#pragma unroll
+        for (int p = 0; p < P; ++p) co.c[p] = g.C[p * g.sc + off];
+        t = mul(beta, co);
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) g.C[p * g.sc + off] = t.c[p];
+}
+
+// ---------------------------------------------------------------------------
+// Element-wise r = x + y or x * y over component planes (Sec. 2.5).
+// ---------------------------------------------------------------------------
+
+template <int P, int OP>
+__global__ void vec_kernel(int64_t n, const double* __restrict__ x, int64_t sx,
+                           const double* __restrict__ y, int64_t sy, double* __restrict__ r,
+                           int64_t sr) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        mp<P> a, b;
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            a.c[p] = x[p * sx + i];
+            b.c[p] = y[p * sy + i];
+        }
+        const mp<P> o = OP == 0 ? add(a, b) : mul(a, b);
+#pragma unroll
+        for (int p = 0; p < P; ++p) r[p * sr + i] = o.c[p];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Configuration table and launchers.
+// ---------------------------------------------------------------------------
+
+// Tile configurations (P, id, TX, TY, TM, TN, BK); the single list below
+// generates the config table and both dispatch switches.
+#define MPG_PLAIN_LIST(X)          \
+    X(2, 0, 16, 16, 4, 4, 16)      \
+    X(2, 1, 16, 16, 2, 2, 16)      \
+    X(2, 2, 16, 16, 4, 2, 16)      \
+    X(2, 3, 16, 8, 4, 4, 16)       \
+    X(3, 0, 16, 16, 2, 2, 16)      \
+    X(3, 1, 16, 16, 4, 2, 16)      \
+    X(3, 2, 16, 16, 1, 2, 16)      \
+    X(3, 3, 16, 16, 2, 4, 16)      \
+    X(4, 0, 16, 16, 2, 2, 16)      \
+    X(4, 1, 16, 16, 1, 2, 16)      \
+    X(4, 2, 16, 16, 2, 1, 16)      \
+    X(4, 3, 16, 16, 1, 1, 16)
+
+PlainConfig plain_config(int P, int id) {
+#define MPG_CFG(PP, ID, TX, TY, TM, TN, BK) \
+    if (P == PP && id == ID) return PlainConfig{TX, TY, TM, TN, BK};
+    MPG_PLAIN_LIST(MPG_CFG)
+#undef MPG_CFG
+    return PlainConfig{0, 0, 0, 0, 0};
+}
+
+int plain_default_config(int P, int64_t m, int64_t n, int64_t k) {
+    (void)k;
+    // small problems: smaller tiles so the grid still covers the 256 CUs
+    const int64_t mn = m * n;
+    if (P == 2) return mn >= (int64_t)1536 * 1536 ? 0 : 1;
+    if (P == 3) return mn >= (int64_t)1024 * 1024 ? 0 : 2;
+    return mn >= (int64_t)1024 * 1024 ? 0 : 1;
+}
+
+template <int P, int TX, int TY, int TM, int TN, int BK>
+static int launch_plain_t(const GemmArgs& g, hipStream_t st) {
+    using T = PlainTile<P, TX, TY, TM, TN, BK>;
+    const int64_t gx = (g.m + T::BM - 1) / T::BM;
+    const int64_t gy = (g.n + T::BN - 1) / T::BN;
+    if (gx > 0x7fffffffLL || gy > 65535) return (int)hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((plain_gemm_kernel<P, TX, TY, TM, TN, BK>), dim3((unsigned)gx, (unsigned)gy),
+                       dim3(T::NT), 0, st, g);
+    return (int)hipGetLastError();
+}
+
+template <int P, int TX, int TY, int TM, int TN, int BK>
+static int launch_batch_t(int64_t count, int64_t total, const void* desc, unsigned* counter,
+                          int grid, hipStream_t st) {
+    using T = PlainTile<P, TX, TY, TM, TN, BK>;
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, counter);
+    hipLaunchKernelGGL((batch_gemm_kernel<P, TX, TY, TM, TN, BK>), dim3(grid), dim3(T::NT), 0, st,
+                       (const BatchDesc*)desc, count, total, counter);
+    return (int)hipGetLastError();
+}
+
+int launch_plain(int P, int cfg, const GemmArgs& g, hipStream_t st) {
+#define MPG_CASE(PP, ID, TX, TY, TM, TN, BK) \
+    if (P == PP && cfg == ID) return launch_plain_t<PP, TX, TY, TM, TN, BK>(g, st);
+    MPG_PLAIN_LIST(MPG_CASE)
+#undef MPG_CASE
+    return (int)hipErrorInvalidValue;
+}
+
+int launch_batch(int P, int cfg, int64_t count, int64_t total_tiles, const void* desc,
+                 unsigned* counter, int grid, hipStream_t st) {
+#define MPG_CASE(PP, ID, TX, TY, TM, TN, BK)                                                \
+    if (P == PP && cfg == ID)                                                               \
+        return launch_batch_t<PP, TX, TY, TM, TN, BK>(count, total_tiles, desc, counter, grid, st);
+    MPG_PLAIN_LIST(MPG_CASE)
+#undef MPG_CASE
+    return (int)hipErrorInvalidValue;
+}
+
+int batch_max_grid(int P, int cfg) {
+    // enough resident workgroups to cover every CU a few times over; blocks
+    // beyond residency simply find the queue drained and exit
+    (void)P;
+    (void)cfg;
+    return 256 * 4;
+}
+
+size_t batch_desc_bytes(int64_t count) { return (size_t)count * sizeof(BatchDesc); }
+
+int64_t batch_build_desc(int P, int cfg, int64_t count, const GemmArgs* probs, const int64_t* order,
+                         void* host_buf) {
+    const PlainConfig c = plain_config(P, cfg);
+    const int64_t BM = c.tx * c.tm, BN = c.ty * c.tn;
+    BatchDesc* d = (BatchDesc*)host_buf;
+    int64_t tiles = 0;
+    for (int64_t q = 0; q < count; ++q) {
+        const GemmArgs& g = probs[order ? order[q] : q];
+        d[q].g = g;
+        d[q].tile_begin = tiles;
+        d[q].tiles_m = (g.m + BM - 1) / BM;
+        tiles += d[q].tiles_m * ((g.n + BN - 1) / BN);
+    }
+    return tiles;
+}
+
+int launch_scale(int P, const GemmArgs& g, hipStream_t st) {
+    const int64_t total = g.m * g.n;
+    const int64_t blocks = (total + 255) / 256;
+    if (blocks > 0x7fffffffLL) return (int)hipErrorInvalidConfiguration;
+    if (P == 2) hipLaunchKernelGGL(scale_kernel<2>, dim3((unsigned)blocks), dim3(256), 0, st, g);
+    else if (P == 3) hipLaunchKernelGGL(scale_kernel<3>, dim3((unsigned)blocks), dim3(256), 0, st, g);
+    else hipLaunchKernelGGL(scale_kernel<4>, dim3((unsigned)blocks), dim3(256), 0, st, g);
+    return (int)hipGetLastError();
+}
+
+int launch_vec(int P, int op, int64_t n, const double* x, int64_t sx, const double* y, int64_t sy,
+               double* r, int64_t sr, hipStream_t st) {
+    if (n <= 0) return 0;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 256 * 64) blocks = 256 * 64;
+    const dim3 gr((unsigned)blocks), bl(256);
+#define MPG_VEC(PP, OO) hipLaunchKernelGGL((vec_kernel<PP, OO>), gr, bl, 0, st, n, x, sx, y, sy, r, sr)
+    if (P == 2) { if (op == 0) MPG_VEC(2, 0); else MPG_VEC(2, 1); }
+    else if (P == 3) { if (op == 0) MPG_VEC(3, 0); else MPG_VEC(3, 1); }
+    else { if (op == 0) MPG_VEC(4, 0); else MPG_VEC(4, 1); }
+#undef MPG_VEC
+    return (int)hipGetLastError();
+}
+
+}  // namespace mpg

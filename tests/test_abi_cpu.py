@@ -1,0 +1,142 @@
+"""The C-ABI library on a machine without a GPU: it loads, exports every
+symbol include/mpgemm.h declares, and rejects invalid arguments on the host
+(in argument order, before any GPU work)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_2101_06584_amd as mp
+from paper_2101_06584_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "mpgemm.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = set(re.findall(r"\b((?:mpgemm|mp_vec)_\w+)\s*\(", txt))
+    return names
+
+
+def test_library_loads_and_exports_header_symbols():
+    L = mp.load()
+    names = header_symbols()
+    assert len(names) >= 25
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(_lib.EXPORTS) == names
+
+
+def test_strerror_and_version():
+    L = mp.load()
+    assert L.mpgemm_version().startswith(b"mpgemm")
+    for code in (0, -3, 1, 2, 3, 4, 5, 6, 99):
+        assert L.mpgemm_strerror(code)
+
+
+D2 = C.c_double * 2
+ONE = D2(1.0, 0.0)
+ZERO = D2(0.0, 0.0)
+FAKE_A = C.c_void_p(0x10000000)
+FAKE_B = C.c_void_p(0x20000000)
+FAKE_C = C.c_void_p(0x30000000)
+
+
+def call(**kw):
+    a = dict(ta=b"N", tb=b"N", m=4, n=5, k=6, alpha=ONE, A=FAKE_A, lda=4, sa=24, B=FAKE_B, ldb=6,
+             sb=30, beta=ZERO, C=FAKE_C, ldc=4, sc=20)
+    a.update(kw)
+    return mp.load().mpgemm_dd(a["ta"], a["tb"], a["m"], a["n"], a["k"], a["alpha"], a["A"], a["lda"],
+                               a["sa"], a["B"], a["ldb"], a["sb"], a["beta"], a["C"], a["ldc"], a["sc"],
+                               None)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(ta=b"X"), -1), (dict(tb=b"Q"), -2), (dict(m=-1), -3), (dict(n=-1), -4), (dict(k=-1), -5),
+    (dict(alpha=None), -6), (dict(A=None), -7), (dict(lda=3), -8), (dict(sa=23), -9),
+    (dict(B=None), -10), (dict(ldb=5), -11), (dict(sb=29), -12), (dict(beta=None), -13),
+    (dict(C=None), -14), (dict(ldc=3), -15), (dict(sc=19), -16),
+    (dict(ta=b"T", lda=4), -8),          # op(A) = A^T: A is k x m, needs lda >= 6
+    (dict(tb=b"t", ldb=4), -11),         # op(B) = B^T: B is n x k, needs ldb >= 5
+    (dict(ta=b"X", m=-1), -1),           # first invalid argument wins
+])
+def test_invalid_arguments(kw, code):
+    assert call(**kw) == code
+
+
+def test_quick_returns_need_no_gpu():
+    # m == 0 / n == 0: nothing to do, pointers never touched
+    assert call(m=0, A=None, C=None, ldc=1, sc=5, lda=1, sa=6) == 0
+    assert call(n=0, B=None, C=None, sc=0, sb=0, ldb=6) == 0
+    # alpha == 0 and beta == 1: quick return; A/B may be NULL
+    assert call(alpha=ZERO, beta=ONE, A=None, B=None) == 0
+    # k == 0 and beta == 1
+    assert call(k=0, beta=ONE, A=None, B=None, lda=4, sa=0, ldb=1, sb=5) == 0
+
+
+def test_aliasing_rejected():
+    assert call(C=FAKE_A) == _lib.ERR_ALIAS
+
+
+def test_ex_options_validated():
+    L = mp.load()
+    o = mp.make_opts("split", slices=41)
+    rc = L.mpgemm_dd_ex(b"N", b"N", 4, 5, 6, ONE, FAKE_A, 4, 24, FAKE_B, 6, 30, ZERO, FAKE_C, 4, 20,
+                        None, C.byref(o))
+    assert rc == -18
+    o = mp.make_opts("split", slices=16)          # no workspace
+    rc = L.mpgemm_dd_ex(b"N", b"N", 4, 5, 6, ONE, FAKE_A, 4, 24, FAKE_B, 6, 30, ZERO, FAKE_C, 4, 20,
+                        None, C.byref(o))
+    assert rc == _lib.ERR_WORKSPACE
+    o = mp.make_opts("split", slices=40)          # k * s beyond exact int32 accumulation
+    rc = L.mpgemm_dd_ex(b"N", b"N", 4, 5, 20000, ONE, FAKE_A, 4, 80000, FAKE_B, 20000, 100000, ZERO,
+                        FAKE_C, 4, 20, None, C.byref(o))
+    assert rc == _lib.ERR_UNSUPPORTED
+
+
+def test_vec_validation():
+    L = mp.load()
+    assert L.mp_vec_td_add(-1, None, 0, None, 0, None, 0, None) == -1
+    assert L.mp_vec_td_add(10, None, 10, FAKE_B, 10, FAKE_C, 10, None) == -2
+    assert L.mp_vec_qd_mul(10, FAKE_A, 9, FAKE_B, 10, FAKE_C, 10, None) == -3
+    assert L.mp_vec_dd_mul(0, None, 0, None, 0, None, 0, None) == 0
+
+
+def test_workspace_bytes_and_layout():
+    L = mp.load()
+    assert L.mpgemm_workspace_bytes(2, 0, 100, 100, 100, 0, -1) == 0
+    b = L.mpgemm_workspace_bytes(2, 1, 100, 100, 100, 16, -1)
+    lay = mp.split_layout(2, 100, 100, 100, 16)
+    assert lay["Mp"] % 64 == 0 and lay["Np"] % 64 == 0 and lay["Kp"] % 64 == 0
+    assert lay["S"] + 4 * 16 * lay["Mp"] * lay["Np"] <= b
+    assert lay["DA"] >= lay["F"] + 4 * lay["Np"]
+    assert L.mpgemm_workspace_bytes(5, 1, 1, 1, 1, 0, -1) == 0
+    assert mp.num_configs(2, "plain") >= 2 and mp.num_configs(4, "split") >= 1
+
+
+def test_batch_plan_validation():
+    L = mp.load()
+    h = C.c_void_p()
+    assert L.mpgemm_batch_plan_create(7, 0, None, None, None, C.byref(h)) == -1
+    assert L.mpgemm_batch_plan_create(2, -1, None, None, None, C.byref(h)) == -2
+    assert L.mpgemm_batch_plan_create(2, 3, None, None, None, C.byref(h)) == -3
+    arr = (_lib.Problem * 2)()
+    for x in arr:
+        x.transa = b"N"; x.transb = b"N"; x.m = 4; x.n = 4; x.k = 4
+        x.alpha[0] = 1.0
+        x.A, x.lda, x.a_plane_stride = FAKE_A, 4, 16
+        x.B, x.ldb, x.b_plane_stride = FAKE_B, 4, 16
+        x.C, x.ldc, x.c_plane_stride = FAKE_C, 4, 16
+    arr[1].ldc = 2
+    assert L.mpgemm_batch_plan_create(2, 2, arr, None, None, C.byref(h)) == -1001
+
+
+def test_tune_slices_validation():
+    L = mp.load()
+    s, r = C.c_int(), C.c_double()
+    assert L.mpgemm_tune_slices(2, b"N", b"N", 4, 4, 4, FAKE_A, 4, 16, FAKE_B, 4, 16, 0.0, 10, 20,
+                                None, C.byref(s), C.byref(r)) == -13
+    assert L.mpgemm_tune_slices(2, b"N", b"N", 4, 4, 4, FAKE_A, 4, 16, FAKE_B, 4, 16, 1.0, 10, 5,
+                                None, C.byref(s), C.byref(r)) == -15

@@ -243,8 +243,9 @@ int mpgemm_tune_slices(int prec, char transa, char transb, int64_t m, int64_t n,
  * Stages of the split form, exposed so each can be checked on its own.
  * They operate on a workspace laid out by the library for (prec, m, n, k, s,
  * tile); offsets (bytes) and padded sizes are reported by
- * mpgemm_split_layout.  Digit planes are int8 [s][Mp][Kp] (op(A) rows) and
- * [s][Np][Kp] (op(B) columns), K contiguous; exponents are int32 [Mp], [Np];
+ * mpgemm_split_layout.  Digit planes are int8 [s][Kp/64][Mp][64] (op(A) rows)
+ * and [s][Kp/64][Np][64] (op(B) columns): digit p of entry (r, l) is at
+ * ((p-1) (Kp/64) + l/64) Rp 64 + r 64 + l % 64; exponents are int32 [Mp], [Np];
  * anti-diagonal sums are int32 [s][Np][Mp] (d = 2..s+1, column-major).
  */
 int mpgemm_split_layout(int prec, int64_t m, int64_t n, int64_t k, int slices, int tile,

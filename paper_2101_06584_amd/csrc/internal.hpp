@@ -54,8 +54,9 @@ int batch_max_grid(int P, int cfg);
 // Split (sliced INT8, MFMA) form.
 struct SplitConfig {
     int bm, bn;                 // output tile per workgroup
+    int g;                      // diagonals accumulated at once
 };
-constexpr int kSplitConfigs = 2;
+constexpr int kSplitConfigs = 4;
 SplitConfig split_config(int id);
 size_t split_workspace_bytes(int P, int64_t m, int64_t n, int64_t k, int s, int cfg);
 int launch_split(int P, int s, int cfg, const GemmArgs& g, void* ws, size_t ws_bytes,

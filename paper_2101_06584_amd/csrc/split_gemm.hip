@@ -37,8 +37,10 @@ static constexpr int kSliceTile = 32;      // slicing kernel: 32 rows x 32 k per
 static inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// {bm, bn}: output tile of one MFMA workgroup (4 waves in 2 x 2).
-static const SplitConfig kSplit[kSplitConfigs] = {{128, 128}, {64, 64}};
+// {bm, bn, g}: output tile of one MFMA workgroup (4 waves in 2 x 2) and the
+// number of diagonals accumulated at once.
+static const SplitConfig kSplit[kSplitConfigs] = {{128, 128, 4}, {64, 64, 8}, {128, 128, 3},
+                                                  {64, 64, 16}};
 
 SplitConfig split_config(int id) { return kSplit[id]; }
 
@@ -119,10 +121,13 @@ __global__ __launch_bounds__(256) void exponent_rows_wave_kernel(const double* _
 }
 
 // ---------------------------------------------------------------------------
-// Stage 2: digits.  Output plane p (0-based digit p+1) of D: D[p][r][l] with
-// row length Kp; zero outside count x k.  Each block stages a 32 x 32 tile of
-// the P component planes through LDS so that both the reads (along whichever
-// index is contiguous) and the byte-plane writes (along l) are coalesced.
+// Stage 2: digits.  Digit p (1-based) of entry (r, l) goes to
+// D[((p-1) * (Kp/64) + l/64) * Rp * 64 + r * 64 + l % 64]: per digit plane,
+// k-tiles of 64 are outermost, so the 64-byte k-slices of all rows of one
+// k-tile are contiguous and a workgroup's tile (BM rows x 64) is one block.
+// Zero outside count x k.  Each block stages a 32 x 32 tile of the P
+// component planes through LDS so that both the reads (along whichever index
+// is contiguous) and the byte-plane writes (along l) are coalesced.
 // ---------------------------------------------------------------------------
 
 template <int P>
@@ -168,7 +173,7 @@ __global__ __launch_bounds__(256) void slice_kernel(const double* __restrict__ X
         double rem[P];
 #pragma unroll
         for (int p = 0; p < P; ++p) rem[p] = ldexp(tile[p][rr][ll], -Ei);
-        int8_t* out = D + gr * Kp + gl;
+        int8_t* out = D + (gl / kTileK) * Rp * kTileK + gr * kTileK + (gl % kTileK);
         const int64_t plane = Rp * Kp;
         for (int p = 1; p <= s; ++p) {
             vec_sum_inplace<P>(rem);
@@ -183,11 +188,17 @@ __global__ __launch_bounds__(256) void slice_kernel(const double* __restrict__ X
 // ---------------------------------------------------------------------------
 // Stage 3: anti-diagonal sums on the INT8 matrix cores.
 //
-// Workgroup = 4 waves in 2 x 2, each wave a (BM/2) x (BN/2) block of 32 x 32
-// MFMA tiles.  The flat step sequence (d, p, k-tile) for d = 2..s+1,
-// p = 1..d-1 (q = d - p), k-tile = 0..Kp/64-1 is double-buffered through LDS
-// (A_p rows and B_q columns, K contiguous, 64 + 16 bytes per row).  When a
-// diagonal's last step is done the int32 accumulators are written to S_d.
+// Workgroup = 4 waves in 2 x 2 over a BM x BN output tile; each wave holds a
+// (BM/2) x (BN/2) block of 32 x 32 MFMA tiles for G diagonals at once.
+// Diagonals are processed in groups [d0, d1] (d1 = min(d0 + G - 1, s + 1)).
+// Within a group and a 64-wide k-tile the pairs (p, q) are visited with p
+// descending from d1 - 1 to 1: the step for p loads digit slice A_p and the
+// single new slice B_{d1 - p}; the pairs of that step are (p, d1 - p - j),
+// j = 0..G-1 (while q >= 1 and d1 - j >= d0), and B_{d1-p-j} is exactly the
+// slice loaded j steps earlier.  So every step moves two slice tiles and feeds
+// up to G pairs, and the accumulator of pair j is always diagonal d1 - j.
+// Slices are double/ring-buffered in LDS (A: 2 slots, B: G + 1 slots, rows
+// padded to 80 bytes), with global loads issued two steps ahead.
 //
 // v_mfma_i32_32x32x32_i8: lane L supplies A row (L % 32) and B column (L % 32),
 // 16 consecutive k bytes starting at 16 (L / 32) of the 32-wide k step (the
@@ -195,18 +206,6 @@ __global__ __launch_bounds__(256) void slice_kernel(const double* __restrict__ X
 // element (row, col) with col = L % 32 and row = 8 (v / 4) + 4 (L / 32) + v % 4
 // is held in accumulator register v.
 // ---------------------------------------------------------------------------
-
-template <int BM, int BN>
-struct DiagTile {
-    static constexpr int WM = BM / 2, WN = BN / 2;      // wave block
-    static constexpr int FM = WM / 32, FN = WN / 32;    // MFMA tiles per wave
-    static constexpr int ROW = kTileK + kLdsPad;        // LDS row bytes
-    static constexpr int A_BYTES = BM * ROW, B_BYTES = BN * ROW;
-    static constexpr int A_CHUNKS = BM * kTileK / 16;   // 16-byte chunks per tile
-    static constexpr int B_CHUNKS = BN * kTileK / 16;
-    static constexpr int A_PER_T = (A_CHUNKS + 255) / 256;
-    static constexpr int B_PER_T = (B_CHUNKS + 255) / 256;
-};
 
 // Tile order: blocks dispatched to the same XCD (blockIdx % 8) take
 // consecutive logical tiles, and logical tiles walk 8-row groups so a
@@ -229,14 +228,27 @@ __device__ __forceinline__ bool diag_tile_coords(int64_t tiles_m, int64_t tiles_
     return true;
 }
 
-template <int BM, int BN>
-__global__ __launch_bounds__(256) void diag_mfma_kernel(const int8_t* __restrict__ DA,
-                                                        const int8_t* __restrict__ DB,
-                                                        int32_t* __restrict__ S, int64_t Mp,
-                                                        int64_t Np, int64_t Kp, int s) {
-    using T = DiagTile<BM, BN>;
-    __shared__ __attribute__((aligned(16))) int8_t As[2][T::A_BYTES];
-    __shared__ __attribute__((aligned(16))) int8_t Bs[2][T::B_BYTES];
+template <int BM, int BN, int G>
+struct DiagWin {
+    static constexpr int WM = BM / 2, WN = BN / 2;       // wave block
+    static constexpr int FM = WM / 32, FN = WN / 32;     // MFMA tiles per wave
+    static constexpr int ROW = kTileK + kLdsPad;         // LDS row bytes
+    static constexpr int NA = 2, NB = G + 1;             // LDS slots
+    static constexpr int A_SLOT = BM * ROW, B_SLOT = BN * ROW;
+    static constexpr int A_CHUNKS = BM * kTileK / 16, B_CHUNKS = BN * kTileK / 16;
+    static constexpr int A_PER_T = (A_CHUNKS + 255) / 256, B_PER_T = (B_CHUNKS + 255) / 256;
+    static constexpr int LDS_BYTES = NA * A_SLOT + NB * B_SLOT;
+};
+
+template <int BM, int BN, int G>
+__global__ __launch_bounds__(256, 1) void diag_mfma_kernel(const int8_t* __restrict__ DA,
+                                                           const int8_t* __restrict__ DB,
+                                                           int32_t* __restrict__ S, int64_t Mp,
+                                                           int64_t Np, int64_t Kp, int s) {
+    using T = DiagWin<BM, BN, G>;
+    __shared__ __attribute__((aligned(16))) int8_t lds[T::LDS_BYTES];
+    int8_t* As = lds;
+    int8_t* Bs = lds + T::NA * T::A_SLOT;
 
     int64_t tm, tn;
     if (!diag_tile_coords(Mp / BM, Np / BN, tm, tn)) return;
@@ -244,108 +256,151 @@ __global__ __launch_bounds__(256) void diag_mfma_kernel(const int8_t* __restrict
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
     const int wm = wave & 1, wn = wave >> 1;
-    const int64_t ktiles = Kp / kTileK;
-    const int64_t planeA = Mp * Kp, planeB = Np * Kp;
+    const int64_t nkt = Kp / kTileK;
+    const int last_d = s + 1;
 
-    v4i ra[T::A_PER_T], rb[T::B_PER_T];
+    // step cursors: (d0, d1, kt, p); advance = next p (descending), then next
+    // k-tile, then next group; past the last step the cursor stays put (so the
+    // prefetch of a step that does not exist re-reads valid data)
+    auto advance = [&](int& d0, int& d1, int64_t& kt, int& p) -> bool {
+        if (p > 1) { --p; return true; }
+        if (kt + 1 < nkt) { ++kt; p = d1 - 1; return true; }
+        if (d1 + 1 > last_d) return false;
+        kt = 0;
+        d0 = d1 + 1;
+        d1 = min(d0 + G - 1, last_d);
+        p = d1 - 1;
+        return true;
+    };
 
-    auto gload = [&](int p, int q, int64_t kt) {
-        const int8_t* a = DA + (int64_t)(p - 1) * planeA + m0 * Kp + kt * kTileK;
-        const int8_t* b = DB + (int64_t)(q - 1) * planeB + n0 * Kp + kt * kTileK;
+    static_assert(T::A_CHUNKS % 256 == 0 && T::B_CHUNKS % 256 == 0, "tile loads split evenly");
+    // two register sets for the global -> LDS staging; the loop below is
+    // unrolled by two so each set is picked at compile time (a run-time index
+    // into a register array would force a wait after every load)
+    v4i ra0[T::A_PER_T], rb0[T::B_PER_T], ra1[T::A_PER_T], rb1[T::B_PER_T];
+    // slice tile (digit p, k-tile kt) of rows m0.. is the contiguous block at
+    // DA + ((p-1) nkt + kt) Mp 64 + m0 64
+    auto gload = [&](v4i (&ra)[T::A_PER_T], v4i (&rb)[T::B_PER_T], int p, int q, int64_t kt) {
+        const v4i* a = (const v4i*)(DA + (((int64_t)(p - 1) * nkt + kt) * Mp + m0) * kTileK);
+        const v4i* b = (const v4i*)(DB + (((int64_t)(q - 1) * nkt + kt) * Np + n0) * kTileK);
+#pragma unroll
+        for (int h = 0; h < T::A_PER_T; ++h) ra[h] = a[t + 256 * h];
+#pragma unroll
+        for (int h = 0; h < T::B_PER_T; ++h) rb[h] = b[t + 256 * h];
+    };
+    auto sstore = [&](const v4i (&ra)[T::A_PER_T], const v4i (&rb)[T::B_PER_T], int sa, int sb) {
 #pragma unroll
         for (int h = 0; h < T::A_PER_T; ++h) {
             const int c = t + 256 * h;
-            if (c < T::A_CHUNKS)
-                ra[h] = *(const v4i*)(a + (int64_t)(c >> 2) * Kp + (c & 3) * 16);
+            *(v4i*)(&As[sa * T::A_SLOT + (c >> 2) * T::ROW + (c & 3) * 16]) = ra[h];
         }
 #pragma unroll
         for (int h = 0; h < T::B_PER_T; ++h) {
             const int c = t + 256 * h;
-            if (c < T::B_CHUNKS)
-                rb[h] = *(const v4i*)(b + (int64_t)(c >> 2) * Kp + (c & 3) * 16);
-        }
-    };
-    auto sstore = [&](int buf) {
-#pragma unroll
-        for (int h = 0; h < T::A_PER_T; ++h) {
-            const int c = t + 256 * h;
-            if (c < T::A_CHUNKS) *(v4i*)(&As[buf][(c >> 2) * T::ROW + (c & 3) * 16]) = ra[h];
-        }
-#pragma unroll
-        for (int h = 0; h < T::B_PER_T; ++h) {
-            const int c = t + 256 * h;
-            if (c < T::B_CHUNKS) *(v4i*)(&Bs[buf][(c >> 2) * T::ROW + (c & 3) * 16]) = rb[h];
+            *(v4i*)(&Bs[sb * T::B_SLOT + (c >> 2) * T::ROW + (c & 3) * 16]) = rb[h];
         }
     };
 
-    v16i acc[T::FM][T::FN];
+    v16i acc[G][T::FM][T::FN];
 #pragma unroll
-    for (int i = 0; i < T::FM; ++i)
+    for (int j = 0; j < G; ++j)
 #pragma unroll
-        for (int j = 0; j < T::FN; ++j) acc[i][j] = v16i{0};
+        for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+            for (int jj = 0; jj < T::FN; ++jj) acc[j][i][jj] = v16i{0};
 
-    // step cursor
-    int d = 2, p = 1;
-    int64_t kt = 0;
-    gload(p, d - p, kt);
-    sstore(0);
+    // cursor of the step being computed (c*), of the next (f*); the one after
+    // (n*) is derived in each iteration
+    int cd0 = 2, cd1 = min(2 + G - 1, last_d), cp = cd1 - 1;
+    int64_t ckt = 0;
+    int fd0 = cd0, fd1 = cd1, fp = cp;
+    int64_t fkt = ckt;
+    gload(ra0, rb0, cp, cd1 - cp, ckt);
+    sstore(ra0, rb0, 0, 0);
+    bool f_valid = advance(fd0, fd1, fkt, fp);
+    gload(ra1, rb1, fp, fd1 - fp, fkt);
     __syncthreads();
-    int buf = 0;
-    for (;;) {
-        // successor step
-        int nd = d, np = p;
-        int64_t nkt = kt + 1;
-        if (nkt == ktiles) {
-            nkt = 0;
-            ++np;
-            if (np == nd) { ++nd; np = 1; }
-        }
-        const bool has_next = nd <= s + 1;
-        if (has_next) gload(np, nd - np, nkt);
 
-        // MFMAs on the current buffer
-#pragma unroll
-        for (int ks = 0; ks < kTileK / 32; ++ks) {
-            v4i fa[T::FM], fb[T::FN];
-            const int kb = ks * 32 + (lane >> 5) * 16;
-#pragma unroll
-            for (int i = 0; i < T::FM; ++i)
-                fa[i] = *(const v4i*)(&As[buf][(wm * T::WM + i * 32 + (lane & 31)) * T::ROW + kb]);
-#pragma unroll
-            for (int j = 0; j < T::FN; ++j)
-                fb[j] = *(const v4i*)(&Bs[buf][(wn * T::WN + j * 32 + (lane & 31)) * T::ROW + kb]);
-#pragma unroll
-            for (int i = 0; i < T::FM; ++i)
-#pragma unroll
-                for (int j = 0; j < T::FN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[i], fb[j], acc[i][j], 0, 0, 0);
-        }
+    // one pipeline iteration: prefetch step+2 into set SET, compute `step`,
+    // move step+1 (set 1-SET) into LDS.  Returns true after the last step.
+    auto iteration = [&](v4i (&raL)[T::A_PER_T], v4i (&rbL)[T::B_PER_T],
+                         const v4i (&raS)[T::A_PER_T], const v4i (&rbS)[T::B_PER_T],
+                         int64_t step) -> bool {
+        int nd0 = fd0, nd1 = fd1, np = fp;
+        int64_t nkt2 = fkt;
+        const bool n_valid = f_valid && advance(nd0, nd1, nkt2, np);
+        gload(raL, rbL, np, nd1 - np, nkt2);
 
-        // end of a diagonal: write S_d and clear the accumulators
-        if (nd != d) {
-            int32_t* Sd = S + (int64_t)(d - 2) * Np * Mp;
+        // pairs (cp, cd1 - cp - j): valid while j <= d1 - d0 and q >= 1
+        {
+            const int nv = min(cd1 - cd0 + 1, cd1 - cp);
+            const int sa = (int)(step % T::NA);
+            const int arow = wm * T::WM + (lane & 31), brow = wn * T::WN + (lane & 31);
+            const int kb = (lane >> 5) * 16;
+            v4i fa[2][T::FM];
 #pragma unroll
-            for (int i = 0; i < T::FM; ++i)
+            for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
-                for (int j = 0; j < T::FN; ++j) {
-                    const int64_t col = n0 + wn * T::WN + j * 32 + (lane & 31);
-                    const int64_t rowb = m0 + wm * T::WM + i * 32 + 4 * (lane >> 5);
+                for (int i = 0; i < T::FM; ++i)
+                    fa[ks][i] = *(const v4i*)(&As[sa * T::A_SLOT + (arow + i * 32) * T::ROW + ks * 32 + kb]);
 #pragma unroll
-                    for (int v4 = 0; v4 < 4; ++v4) {
-                        v4i o = {acc[i][j][4 * v4 + 0], acc[i][j][4 * v4 + 1], acc[i][j][4 * v4 + 2],
-                                 acc[i][j][4 * v4 + 3]};
-                        *(v4i*)(Sd + col * Mp + rowb + 8 * v4) = o;
-                    }
-                    acc[i][j] = v16i{0};
+            for (int j = 0; j < G; ++j) {
+                if (j < nv) {
+                    const int sb = (int)((step + T::NB - j) % T::NB);
+                    v4i fb[2][T::FN];
+#pragma unroll
+                    for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+                        for (int jj = 0; jj < T::FN; ++jj)
+                            fb[ks][jj] = *(const v4i*)(&Bs[sb * T::B_SLOT + (brow + jj * 32) * T::ROW +
+                                                           ks * 32 + kb]);
+#pragma unroll
+                    for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+                        for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+                            for (int jj = 0; jj < T::FN; ++jj)
+                                acc[j][i][jj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                                    fa[ks][i], fb[ks][jj], acc[j][i][jj], 0, 0, 0);
                 }
+            }
         }
-        if (!has_next) break;
-        sstore(buf ^ 1);
+
+        // end of a group: write S_d for its diagonals, clear the accumulators
+        if (cp == 1 && ckt == nkt - 1) {
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                if (cd1 - j >= cd0) {
+                    int32_t* Sd = S + (int64_t)(cd1 - j - 2) * Np * Mp;
+#pragma unroll
+                    for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+                        for (int jj = 0; jj < T::FN; ++jj) {
+                            const int64_t col = n0 + wn * T::WN + jj * 32 + (lane & 31);
+                            const int64_t rowb = m0 + wm * T::WM + i * 32 + 4 * (lane >> 5);
+#pragma unroll
+                            for (int v4 = 0; v4 < 4; ++v4) {
+                                v4i o = {acc[j][i][jj][4 * v4 + 0], acc[j][i][jj][4 * v4 + 1],
+                                         acc[j][i][jj][4 * v4 + 2], acc[j][i][jj][4 * v4 + 3]};
+                                *(v4i*)(Sd + col * Mp + rowb + 8 * v4) = o;
+                            }
+                            acc[j][i][jj] = v16i{0};
+                        }
+                }
+            }
+        }
+
+        if (!f_valid) return true;
+        sstore(raS, rbS, (int)((step + 1) % T::NA), (int)((step + 1) % T::NB));
         __syncthreads();
-        buf ^= 1;
-        d = nd;
-        p = np;
-        kt = nkt;
+        cd0 = fd0; cd1 = fd1; cp = fp; ckt = fkt;
+        fd0 = nd0; fd1 = nd1; fp = np; fkt = nkt2; f_valid = n_valid;
+        return false;
+    };
+
+    for (int64_t step = 0;; step += 2) {
+        if (iteration(ra0, rb0, ra1, rb1, step)) break;
+        if (iteration(ra1, rb1, ra0, rb0, step + 1)) break;
     }
 }
 
@@ -430,12 +485,16 @@ static int launch_diag(int cfg, const int8_t* DA, const int8_t* DB, int32_t* S, 
     const int64_t tiles = (Mp / c.bm) * (Np / c.bn);
     const int64_t grid = (tiles + 7) / 8 * 8;
     if (grid > 0x7fffffffLL) return (int)hipErrorInvalidConfiguration;
-    if (cfg == 0)
-        hipLaunchKernelGGL((diag_mfma_kernel<128, 128>), dim3((unsigned)grid), dim3(256), 0, st, DA, DB,
-                           S, Mp, Np, Kp, s);
-    else
-        hipLaunchKernelGGL((diag_mfma_kernel<64, 64>), dim3((unsigned)grid), dim3(256), 0, st, DA, DB, S,
-                           Mp, Np, Kp, s);
+#define MPG_DIAG(BM, BN, G)                                                                   \
+    hipLaunchKernelGGL((diag_mfma_kernel<BM, BN, G>), dim3((unsigned)grid), dim3(256), 0, st, DA, DB, \
+                       S, Mp, Np, Kp, s)
+    switch (cfg) {
+    case 0: MPG_DIAG(128, 128, 4); break;
+    case 1: MPG_DIAG(64, 64, 8); break;
+    case 2: MPG_DIAG(128, 128, 3); break;
+    default: MPG_DIAG(64, 64, 16); break;
+    }
+#undef MPG_DIAG
     return (int)hipGetLastError();
 }
 

@@ -9,7 +9,8 @@
 // and Algorithm 6 (QD mul), so a GEMM that keeps one sequential k-chain per
 // entry is bitwise reproducible.  The data-dependent branches of VSEB(k) and
 // Renorm are written as selects so a wavefront never diverges; the selected
-// values are exactly those the branching form produces.
+// values are exactly those the branching form produces.  The GEMM inner step
+// (tile_mac) adds a wave-uniform fast path for the common branch outcome.
 //
 // Compile with -ffp-contract=off: a contracted a*b+c would change results.
 #pragma once
@@ -163,11 +164,18 @@ MPG_DEV mp<2> mul(const mp<2>& x, const mp<2>& y) {
     return r;
 }
 
-// ---- Algorithm 5 (QD add; t3 = w3 + u3 like the other lanes) ---------------
+// ---- Algorithms 4, 5, 6: the terms before the final Renorm / VSEB(2) ------
+//
+// Algorithm 5 (QD add): the listing uses t3 without defining it; it is the
+// error term of the fourth lane, t3 = w3 + u3, like t0..t2.
+// Algorithm 6 (QD mul): the listing's first line (s0 = x0 + y0) is
+// overwritten before any use and is omitted; the O(eps^3) terms are added to
+// s1 one at a time in the printed order, each a rounded multiply and add.
+// Algorithm 4 (TD mul): b0..b2 are VecSum outputs, not operand components.
 
-MPG_DEV void qd_add_raw(double x0, double x1, double x2, double x3,
-                        double y0, double y1, double y2, double y3,
-                        double& r0, double& r1, double& r2, double& r3) {
+// Terms of Algorithm 5 before its Renorm (c0..c4).
+MPG_DEV void qd_add_terms(double x0, double x1, double x2, double x3, double y0, double y1,
+                          double y2, double y3, double (&c)[5]) {
     double s0 = x0 + y0, s1 = x1 + y1, s2 = x2 + y2, s3 = x3 + y3;
     double v0 = s0 - x0, v1 = s1 - x1, v2 = s2 - x2, v3 = s3 - x3;
     double u0 = s0 - v0, u1 = s1 - v1, u2 = s2 - v2, u3 = s3 - v3;
@@ -181,29 +189,15 @@ MPG_DEV void qd_add_raw(double x0, double x1, double x2, double x3,
     three_sum(s2, t0, t1);
     three_sum2(s3, t0, t2);
     t0 = (t0 + t1) + t3;
-    renorm4(s0, s1, s2, s3, t0, r0, r1, r2, r3);
+    c[0] = s0;
+    c[1] = s1;
+    c[2] = s2;
+    c[3] = s3;
+    c[4] = t0;
 }
 
-MPG_DEV mp<4> add(const mp<4>& x, const mp<4>& y) {
-    mp<4> r;
-    qd_add_raw(x.c[0], x.c[1], x.c[2], x.c[3], y.c[0], y.c[1], y.c[2], y.c[3],
-               r.c[0], r.c[1], r.c[2], r.c[3]);
-    return r;
-}
-
-// TDaddq: the QD addition with zero fourth components, fourth output dropped.
-MPG_DEV mp<3> add(const mp<3>& x, const mp<3>& y) {
-    mp<3> r;
-    double r3;
-    qd_add_raw(x.c[0], x.c[1], x.c[2], 0.0, y.c[0], y.c[1], y.c[2], 0.0,
-               r.c[0], r.c[1], r.c[2], r3);
-    (void)r3;
-    return r;
-}
-
-// ---- Algorithm 6 (QD mul; the listing's dead first line omitted) ----------
-
-MPG_DEV mp<4> mul(const mp<4>& x, const mp<4>& y) {
+// Terms of Algorithm 6 before its Renorm (c0..c4).
+MPG_DEV void qd_mul_terms(const mp<4>& x, const mp<4>& y, double (&c)[5]) {
     double p0, q0, p1, q1, p2, q2, p3, q3, p4, q4, p5, q5;
     two_prod(x.c[0], y.c[0], p0, q0);
     two_prod(x.c[0], y.c[1], p1, q1);
@@ -220,7 +214,6 @@ MPG_DEV mp<4> mul(const mp<4>& x, const mp<4>& y) {
     s2 = q2 + p5;
     two_sum(s1, t0, s1, t0);
     s2 = s2 + (t0 + t1);
-    // O(eps^3) terms, one rounded multiply and one rounded add each, in order
     s1 = s1 + x.c[0] * y.c[3];
     s1 = s1 + x.c[1] * y.c[2];
     s1 = s1 + x.c[2] * y.c[1];
@@ -229,19 +222,19 @@ MPG_DEV mp<4> mul(const mp<4>& x, const mp<4>& y) {
     s1 = s1 + q3;
     s1 = s1 + q4;
     s1 = s1 + q5;
-    mp<4> r;
-    renorm4(p0, p1, s0, s1, s2, r.c[0], r.c[1], r.c[2], r.c[3]);
-    return r;
+    c[0] = p0;
+    c[1] = p1;
+    c[2] = s0;
+    c[3] = s1;
+    c[4] = s2;
 }
 
-// ---- Algorithm 4 (TD "fast" product) --------------------------------------
-
-MPG_DEV mp<3> mul(const mp<3>& x, const mp<3>& y) {
+// Terms of Algorithm 4 before its VSEB(2): (e0, e1, e2, e3).
+MPG_DEV void td_mul_terms(const mp<3>& x, const mp<3>& y, double (&e)[4]) {
     double z00u, z00l, z01u, z01l, z10u, z10l;
     two_prod(x.c[0], y.c[0], z00u, z00l);
     two_prod(x.c[0], y.c[1], z01u, z01l);
     two_prod(x.c[1], y.c[0], z10u, z10l);
-    // VecSum(z00l, z01u, z10u) -> (b0, b1, b2)
     double b0, b1, b2, sv;
     two_sum(z01u, z10u, sv, b2);
     two_sum(z00l, sv, b0, b1);
@@ -250,15 +243,201 @@ MPG_DEV mp<3> mul(const mp<3>& x, const mp<3>& y) {
     double z32 = __builtin_fma(x.c[2], y.c[0], z01l);
     double z3 = z31 + z32;
     double s3 = c + z3;
-    // VecSum(z00u, b0, b1, s3) -> (e0, e1, e2, e3)
-    double e0, e1, e2, e3;
-    two_sum(b1, s3, sv, e3);
-    two_sum(b0, sv, sv, e2);
-    two_sum(z00u, sv, e0, e1);
-    mp<3> r;
-    r.c[0] = e0;
-    vseb2(e1, e2, e3, r.c[1], r.c[2]);
+    two_sum(b1, s3, sv, e[3]);
+    two_sum(b0, sv, sv, e[2]);
+    two_sum(z00u, sv, e[0], e[1]);
+}
+
+// ---- the finished operations ------------------------------------------------
+
+MPG_DEV mp<4> add(const mp<4>& x, const mp<4>& y) {
+    double t[5];
+    qd_add_terms(x.c[0], x.c[1], x.c[2], x.c[3], y.c[0], y.c[1], y.c[2], y.c[3], t);
+    mp<4> r;
+    renorm4(t[0], t[1], t[2], t[3], t[4], r.c[0], r.c[1], r.c[2], r.c[3]);
     return r;
+}
+
+// TDaddq: the QD addition with zero fourth components, fourth output dropped.
+MPG_DEV mp<3> add(const mp<3>& x, const mp<3>& y) {
+    double t[5];
+    qd_add_terms(x.c[0], x.c[1], x.c[2], 0.0, y.c[0], y.c[1], y.c[2], 0.0, t);
+    mp<3> r;
+    double r3;
+    renorm4(t[0], t[1], t[2], t[3], t[4], r.c[0], r.c[1], r.c[2], r3);
+    (void)r3;
+    return r;
+}
+
+MPG_DEV mp<4> mul(const mp<4>& x, const mp<4>& y) {
+    double t[5];
+    qd_mul_terms(x, y, t);
+    mp<4> r;
+    renorm4(t[0], t[1], t[2], t[3], t[4], r.c[0], r.c[1], r.c[2], r.c[3]);
+    return r;
+}
+
+MPG_DEV mp<3> mul(const mp<3>& x, const mp<3>& y) {
+    double e[4];
+    td_mul_terms(x, y, e);
+    mp<3> r;
+    r.c[0] = e[0];
+    vseb2(e[1], e[2], e[3], r.c[1], r.c[2]);
+    return r;
+}
+
+// ---- Tile multiply-accumulate with a wave-uniform fast path ---------------
+//
+// The data-dependent branches of Renorm and VSEB(2) almost always take one
+// path on non-degenerate data: every QuickTwoSum error of the second pass is
+// non-zero, so each output slot closes in turn.  That path needs no selects:
+//   Renorm:  r = (e0, s(e1+e2), s(t+e3), t' + e4)
+//   VSEB(2): r = (s(e1+e2), s(t+e3))
+// For a whole TM x TN register tile the terms before the final Renorm/VSEB are
+// computed first; if every lane of the wave took the common path for every
+// entry, its results are used, otherwise the select form recomputes the
+// finish from the same terms.  Either way the values are exactly those of the
+// general algorithm.
+
+MPG_DEV bool renorm4_fast(double c0, double c1, double c2, double c3, double c4, double& r0,
+                          double& r1, double& r2, double& r3) {
+    double s, e0, e1, e2, e3, e4;
+    quick_two_sum(c3, c4, s, e4);
+    quick_two_sum(c2, s, s, e3);
+    quick_two_sum(c1, s, s, e2);
+    quick_two_sum(c0, s, e0, e1);
+    double sv2, t2, sv3, t3;
+    quick_two_sum(e1, e2, sv2, t2);
+    quick_two_sum(t2, e3, sv3, t3);
+    r0 = e0;
+    r1 = sv2;
+    r2 = sv3;
+    r3 = t3 + e4;
+    return (e1 != 0.0) && (t2 != 0.0) && (t3 != 0.0);
+}
+
+// The first three outputs of Renorm (all a TD result keeps): when the first
+// two slots close, the third is sv3 if its error is non-zero and otherwise
+// the sum of the carry sv3 with e4 (whether or not that sum then closes the
+// slot, which only decides the dropped fourth output).
+MPG_DEV bool renorm3_fast(double c0, double c1, double c2, double c3, double c4, double& r0,
+                          double& r1, double& r2) {
+    double s, e0, e1, e2, e3, e4;
+    quick_two_sum(c3, c4, s, e4);
+    quick_two_sum(c2, s, s, e3);
+    quick_two_sum(c1, s, s, e2);
+    quick_two_sum(c0, s, e0, e1);
+    double sv2, t2, sv3, t3;
+    quick_two_sum(e1, e2, sv2, t2);
+    quick_two_sum(t2, e3, sv3, t3);
+    r0 = e0;
+    r1 = sv2;
+    r2 = (t3 != 0.0) ? sv3 : sv3 + e4;
+    return (e1 != 0.0) && (t2 != 0.0);
+}
+
+MPG_DEV bool vseb2_fast(double e1, double e2, double e3, double& r1, double& r2) {
+    double s1, t1, s2, t2;
+    quick_two_sum(e1, e2, s1, t1);
+    quick_two_sum(t1, e3, s2, t2);
+    r1 = s1;
+    r2 = s2;
+    return t1 != 0.0;
+}
+
+// acc[r][c] = ADD(acc[r][c], MUL(a[r], b[c])) for a TM x TN tile.
+template <int TM, int TN>
+MPG_DEV void tile_mac(mp<2> (&acc)[TM][TN], const mp<2> (&a)[TM], const mp<2> (&b)[TN]) {
+#pragma unroll
+    for (int r = 0; r < TM; ++r)
+#pragma unroll
+        for (int c = 0; c < TN; ++c) acc[r][c] = add(acc[r][c], mul(a[r], b[c]));
+}
+
+template <int TM, int TN>
+MPG_DEV void tile_mac(mp<4> (&acc)[TM][TN], const mp<4> (&a)[TM], const mp<4> (&b)[TN]) {
+    double t[TM][TN][5];
+    mp<4> prod[TM][TN];
+    bool ok = true;
+#pragma unroll
+    for (int r = 0; r < TM; ++r)
+#pragma unroll
+        for (int c = 0; c < TN; ++c) {
+            qd_mul_terms(a[r], b[c], t[r][c]);
+            ok = renorm4_fast(t[r][c][0], t[r][c][1], t[r][c][2], t[r][c][3], t[r][c][4],
+                              prod[r][c].c[0], prod[r][c].c[1], prod[r][c].c[2], prod[r][c].c[3]) && ok;
+        }
+    if (!__all(ok)) {
+#pragma unroll
+        for (int r = 0; r < TM; ++r)
+#pragma unroll
+            for (int c = 0; c < TN; ++c)
+                renorm4(t[r][c][0], t[r][c][1], t[r][c][2], t[r][c][3], t[r][c][4], prod[r][c].c[0],
+                        prod[r][c].c[1], prod[r][c].c[2], prod[r][c].c[3]);
+    }
+    ok = true;
+#pragma unroll
+    for (int r = 0; r < TM; ++r)
+#pragma unroll
+        for (int c = 0; c < TN; ++c) {
+            qd_add_terms(acc[r][c].c[0], acc[r][c].c[1], acc[r][c].c[2], acc[r][c].c[3],
+                         prod[r][c].c[0], prod[r][c].c[1], prod[r][c].c[2], prod[r][c].c[3], t[r][c]);
+            ok = renorm4_fast(t[r][c][0], t[r][c][1], t[r][c][2], t[r][c][3], t[r][c][4],
+                              acc[r][c].c[0], acc[r][c].c[1], acc[r][c].c[2], acc[r][c].c[3]) && ok;
+        }
+    if (!__all(ok)) {
+#pragma unroll
+        for (int r = 0; r < TM; ++r)
+#pragma unroll
+            for (int c = 0; c < TN; ++c)
+                renorm4(t[r][c][0], t[r][c][1], t[r][c][2], t[r][c][3], t[r][c][4], acc[r][c].c[0],
+                        acc[r][c].c[1], acc[r][c].c[2], acc[r][c].c[3]);
+    }
+}
+
+template <int TM, int TN>
+MPG_DEV void tile_mac(mp<3> (&acc)[TM][TN], const mp<3> (&a)[TM], const mp<3> (&b)[TN]) {
+    double e[TM][TN][4];
+    mp<3> prod[TM][TN];
+    bool ok = true;
+#pragma unroll
+    for (int r = 0; r < TM; ++r)
+#pragma unroll
+        for (int c = 0; c < TN; ++c) {
+            td_mul_terms(a[r], b[c], e[r][c]);
+            prod[r][c].c[0] = e[r][c][0];
+            ok = vseb2_fast(e[r][c][1], e[r][c][2], e[r][c][3], prod[r][c].c[1], prod[r][c].c[2]) && ok;
+        }
+    if (!__all(ok)) {
+#pragma unroll
+        for (int r = 0; r < TM; ++r)
+#pragma unroll
+            for (int c = 0; c < TN; ++c)
+                vseb2(e[r][c][1], e[r][c][2], e[r][c][3], prod[r][c].c[1], prod[r][c].c[2]);
+    }
+    double t[TM][TN][5];
+    ok = true;
+#pragma unroll
+    for (int r = 0; r < TM; ++r)
+#pragma unroll
+        for (int c = 0; c < TN; ++c) {
+            // TDaddq: Algorithm 5 with zero fourth components, fourth output dropped
+            qd_add_terms(acc[r][c].c[0], acc[r][c].c[1], acc[r][c].c[2], 0.0, prod[r][c].c[0],
+                         prod[r][c].c[1], prod[r][c].c[2], 0.0, t[r][c]);
+            ok = renorm3_fast(t[r][c][0], t[r][c][1], t[r][c][2], t[r][c][3], t[r][c][4],
+                              acc[r][c].c[0], acc[r][c].c[1], acc[r][c].c[2]) && ok;
+        }
+    if (!__all(ok)) {
+#pragma unroll
+        for (int r = 0; r < TM; ++r)
+#pragma unroll
+            for (int c = 0; c < TN; ++c) {
+                double r3;
+                renorm4(t[r][c][0], t[r][c][1], t[r][c][2], t[r][c][3], t[r][c][4], acc[r][c].c[0],
+                        acc[r][c].c[1], acc[r][c].c[2], r3);
+                (void)r3;
+            }
+    }
 }
 
 template <int P>

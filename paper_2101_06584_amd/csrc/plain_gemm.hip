@@ -70,10 +70,7 @@ struct PlainTile {
         for (int c = 0; c < TN; ++c)
 #pragma unroll
             for (int p = 0; p < P; ++p) b[c].c[p] = Bs[(p * BK + kk) * BN + ty + c * TY];
-#pragma unroll
-        for (int r = 0; r < TM; ++r)
-#pragma unroll
-            for (int c = 0; c < TN; ++c) acc[r][c] = add(acc[r][c], mul(a[r], b[c]));
+        tile_mac<TM, TN>(acc, a, b);
     }
 
     __device__ static void run(const GemmArgs& g, const mp<P>& alpha, const mp<P>& beta,

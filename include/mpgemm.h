@@ -72,7 +72,7 @@ extern "C" {
 typedef struct mpgemm_opts {
     int form;               /* MPGEMM_FORM_*                                   */
     int slices;             /* split form: digits per operand entry s (1..40);
-                               0 = the precision's default (DD 16, TD 23, QD 30),
+                               0 = the precision's default (DD 16, TD 23, QD 31),
                                enough for inputs of similar magnitude within a
                                row of op(A) / column of op(B)              */
     int tile;               /* kernel configuration id; -1 or 0.. = tuned/fixed */
@@ -243,8 +243,8 @@ int mpgemm_tune_slices(int prec, char transa, char transb, int64_t m, int64_t n,
  * Stages of the split form, exposed so each can be checked on its own.
  * They operate on a workspace laid out by the library for (prec, m, n, k, s,
  * tile); offsets (bytes) and padded sizes are reported by
- * mpgemm_split_layout.  Digit planes are int8 [s][Kp/64][Mp][64] (op(A) rows)
- * and [s][Kp/64][Np][64] (op(B) columns): digit p of entry (r, l) is at
+ * mpgemm_split_layout.  Digit planes are int8 [s][Kp/64][Mp][64] (op(A)
+ * rows) and [s][Kp/64][Np][64] (op(B) columns): digit p of entry (r, l) is at
  * ((p-1) (Kp/64) + l/64) Rp 64 + r 64 + l % 64; exponents are int32 [Mp], [Np];
  * anti-diagonal sums are int32 [s][Np][Mp] (d = 2..s+1, column-major).
  */

@@ -15,7 +15,7 @@ from . import _lib
 
 PREC = {"dd": 2, "td": 3, "qd": 4, 2: 2, 3: 3, 4: 4}
 FORMS = {"plain": _lib.FORM_PLAIN, "split": _lib.FORM_SPLIT_I8, "auto": _lib.FORM_AUTO}
-DEFAULT_SLICES = {2: 16, 3: 23, 4: 30}
+DEFAULT_SLICES = {2: 16, 3: 23, 4: 31}
 _NAME = {2: "dd", 3: "td", 4: "qd"}
 
 

@@ -22,6 +22,8 @@
 // Every stage is deterministic, so results are reproducible bit for bit.
 #pragma clang fp contract(off)
 
+#include <utility>
+
 #include "internal.hpp"
 #include "mp_arith.hpp"
 
@@ -30,7 +32,7 @@ namespace mpg {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-static constexpr int kTileK = 64;          // k bytes per pipeline step
+static constexpr int kTileK = 64;          // k bytes per pipeline step (and k-tile width)
 static constexpr int kLdsPad = 16;         // row padding (bytes) against bank conflicts
 static constexpr int kSliceTile = 32;      // slicing kernel: 32 rows x 32 k per block
 
@@ -39,8 +41,8 @@ static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // {bm, bn, g}: output tile of one MFMA workgroup (4 waves in 2 x 2) and the
 // number of diagonals accumulated at once.
-static const SplitConfig kSplit[kSplitConfigs] = {{128, 128, 4}, {64, 64, 8}, {128, 128, 3},
-                                                  {64, 64, 16}};
+static const SplitConfig kSplit[kSplitConfigs] = {{128, 128, 4}, {64, 64, 8}, {128, 128, 2},
+                                                  {64, 64, 4}};
 
 SplitConfig split_config(int id) { return kSplit[id]; }
 
@@ -195,10 +197,10 @@ __global__ __launch_bounds__(256) void slice_kernel(const double* __restrict__ X
 // descending from d1 - 1 to 1: the step for p loads digit slice A_p and the
 // single new slice B_{d1 - p}; the pairs of that step are (p, d1 - p - j),
 // j = 0..G-1 (while q >= 1 and d1 - j >= d0), and B_{d1-p-j} is exactly the
-// slice loaded j steps earlier.  So every step moves two slice tiles and feeds
-// up to G pairs, and the accumulator of pair j is always diagonal d1 - j.
-// Slices are double/ring-buffered in LDS (A: 2 slots, B: G + 1 slots, rows
-// padded to 80 bytes), with global loads issued two steps ahead.
+// slice loaded j steps earlier.  So each step moves two slice tiles through
+// LDS (double-buffered, rows padded to 80 bytes) and feeds up to G pairs; the
+// B fragments of the last G steps stay in a register window, the accumulator
+// of pair j is always diagonal d1 - j, and global loads run two steps ahead.
 //
 // v_mfma_i32_32x32x32_i8: lane L supplies A row (L % 32) and B column (L % 32),
 // 16 consecutive k bytes starting at 16 (L / 32) of the 32-wide k step (the
@@ -233,12 +235,19 @@ struct DiagWin {
     static constexpr int WM = BM / 2, WN = BN / 2;       // wave block
     static constexpr int FM = WM / 32, FN = WN / 32;     // MFMA tiles per wave
     static constexpr int ROW = kTileK + kLdsPad;         // LDS row bytes
-    static constexpr int NA = 2, NB = G + 1;             // LDS slots
+    static constexpr int CPR = kTileK / 16;              // 16-byte chunks per row
+    static constexpr int KS = kTileK / 32;               // MFMA k-substeps per step
     static constexpr int A_SLOT = BM * ROW, B_SLOT = BN * ROW;
     static constexpr int A_CHUNKS = BM * kTileK / 16, B_CHUNKS = BN * kTileK / 16;
     static constexpr int A_PER_T = (A_CHUNKS + 255) / 256, B_PER_T = (B_CHUNKS + 255) / 256;
-    static constexpr int LDS_BYTES = NA * A_SLOT + NB * B_SLOT;
+    static constexpr int LDS_BYTES = 2 * A_SLOT + 2 * B_SLOT;
+    static constexpr int U = (G % 2 == 0) ? G : 2 * G;   // unroll: register sets x window
 };
+
+template <typename F, int... I>
+__device__ __forceinline__ bool diag_unrolled(F&& f, std::integer_sequence<int, I...>) {
+    return (... || f(std::integral_constant<int, I>{}));
+}
 
 template <int BM, int BN, int G>
 __global__ __launch_bounds__(256, 1) void diag_mfma_kernel(const int8_t* __restrict__ DA,
@@ -246,9 +255,10 @@ __global__ __launch_bounds__(256, 1) void diag_mfma_kernel(const int8_t* __restr
                                                            int32_t* __restrict__ S, int64_t Mp,
                                                            int64_t Np, int64_t Kp, int s) {
     using T = DiagWin<BM, BN, G>;
+    static_assert(T::A_CHUNKS % 256 == 0 && T::B_CHUNKS % 256 == 0, "tile loads split evenly");
     __shared__ __attribute__((aligned(16))) int8_t lds[T::LDS_BYTES];
     int8_t* As = lds;
-    int8_t* Bs = lds + T::NA * T::A_SLOT;
+    int8_t* Bs = lds + 2 * T::A_SLOT;
 
     int64_t tm, tn;
     if (!diag_tile_coords(Mp / BM, Np / BN, tm, tn)) return;
@@ -258,6 +268,8 @@ __global__ __launch_bounds__(256, 1) void diag_mfma_kernel(const int8_t* __restr
     const int wm = wave & 1, wn = wave >> 1;
     const int64_t nkt = Kp / kTileK;
     const int last_d = s + 1;
+    const int arow = wm * T::WM + (lane & 31), brow = wn * T::WN + (lane & 31);
+    const int kb = (lane >> 5) * 16;
 
     // step cursors: (d0, d1, kt, p); advance = next p (descending), then next
     // k-tile, then next group; past the last step the cursor stays put (so the
@@ -273,10 +285,8 @@ __global__ __launch_bounds__(256, 1) void diag_mfma_kernel(const int8_t* __restr
         return true;
     };
 
-    static_assert(T::A_CHUNKS % 256 == 0 && T::B_CHUNKS % 256 == 0, "tile loads split evenly");
-    // two register sets for the global -> LDS staging; the loop below is
-    // unrolled by two so each set is picked at compile time (a run-time index
-    // into a register array would force a wait after every load)
+    // two register sets for the global -> LDS staging, picked at compile time
+    // (a run-time index into a register array would force a wait per load)
     v4i ra0[T::A_PER_T], rb0[T::B_PER_T], ra1[T::A_PER_T], rb1[T::B_PER_T];
     // slice tile (digit p, k-tile kt) of rows m0.. is the contiguous block at
     // DA + ((p-1) nkt + kt) Mp 64 + m0 64
@@ -288,16 +298,16 @@ __global__ __launch_bounds__(256, 1) void diag_mfma_kernel(const int8_t* __restr
 #pragma unroll
         for (int h = 0; h < T::B_PER_T; ++h) rb[h] = b[t + 256 * h];
     };
-    auto sstore = [&](const v4i (&ra)[T::A_PER_T], const v4i (&rb)[T::B_PER_T], int sa, int sb) {
+    auto sstore = [&](const v4i (&ra)[T::A_PER_T], const v4i (&rb)[T::B_PER_T], int slot) {
 #pragma unroll
         for (int h = 0; h < T::A_PER_T; ++h) {
             const int c = t + 256 * h;
-            *(v4i*)(&As[sa * T::A_SLOT + (c >> 2) * T::ROW + (c & 3) * 16]) = ra[h];
+            *(v4i*)(&As[slot * T::A_SLOT + (c / T::CPR) * T::ROW + (c % T::CPR) * 16]) = ra[h];
         }
 #pragma unroll
         for (int h = 0; h < T::B_PER_T; ++h) {
             const int c = t + 256 * h;
-            *(v4i*)(&Bs[sb * T::B_SLOT + (c >> 2) * T::ROW + (c & 3) * 16]) = rb[h];
+            *(v4i*)(&Bs[slot * T::B_SLOT + (c / T::CPR) * T::ROW + (c % T::CPR) * 16]) = rb[h];
         }
     };
 
@@ -308,61 +318,56 @@ __global__ __launch_bounds__(256, 1) void diag_mfma_kernel(const int8_t* __restr
         for (int i = 0; i < T::FM; ++i)
 #pragma unroll
             for (int jj = 0; jj < T::FN; ++jj) acc[j][i][jj] = v16i{0};
+    v4i wb[G][T::KS][T::FN];   // B fragments of the last G steps, slot = step % G
 
-    // cursor of the step being computed (c*), of the next (f*); the one after
-    // (n*) is derived in each iteration
     int cd0 = 2, cd1 = min(2 + G - 1, last_d), cp = cd1 - 1;
     int64_t ckt = 0;
     int fd0 = cd0, fd1 = cd1, fp = cp;
     int64_t fkt = ckt;
     gload(ra0, rb0, cp, cd1 - cp, ckt);
-    sstore(ra0, rb0, 0, 0);
+    sstore(ra0, rb0, 0);
     bool f_valid = advance(fd0, fd1, fkt, fp);
     gload(ra1, rb1, fp, fd1 - fp, fkt);
     __syncthreads();
 
-    // one pipeline iteration: prefetch step+2 into set SET, compute `step`,
-    // move step+1 (set 1-SET) into LDS.  Returns true after the last step.
-    auto iteration = [&](v4i (&raL)[T::A_PER_T], v4i (&rbL)[T::B_PER_T],
-                         const v4i (&raS)[T::A_PER_T], const v4i (&rbS)[T::B_PER_T],
-                         int64_t step) -> bool {
+    // one pipeline iteration for step = base + SLOT: prefetch step + 2,
+    // compute step, move step + 1 into LDS.  Returns true after the last step.
+    auto iteration = [&](auto slot_c, int64_t base) -> bool {
+        constexpr int SLOT = decltype(slot_c)::value;
+        constexpr int SET = SLOT & 1;           // == step % 2 (U is even)
+        constexpr int W = SLOT % G;             // == step % G (U is a multiple of G)
+        auto& raL = SET ? ra1 : ra0;
+        auto& rbL = SET ? rb1 : rb0;
+        auto& raS = SET ? ra0 : ra1;
+        auto& rbS = SET ? rb0 : rb1;
         int nd0 = fd0, nd1 = fd1, np = fp;
         int64_t nkt2 = fkt;
         const bool n_valid = f_valid && advance(nd0, nd1, nkt2, np);
         gload(raL, rbL, np, nd1 - np, nkt2);
 
+        v4i fa[T::KS][T::FM];
+#pragma unroll
+        for (int ks = 0; ks < T::KS; ++ks) {
+#pragma unroll
+            for (int i = 0; i < T::FM; ++i)
+                fa[ks][i] = *(const v4i*)(&As[SET * T::A_SLOT + (arow + i * 32) * T::ROW + ks * 32 + kb]);
+#pragma unroll
+            for (int jj = 0; jj < T::FN; ++jj)
+                wb[W][ks][jj] = *(const v4i*)(&Bs[SET * T::B_SLOT + (brow + jj * 32) * T::ROW + ks * 32 + kb]);
+        }
         // pairs (cp, cd1 - cp - j): valid while j <= d1 - d0 and q >= 1
-        {
-            const int nv = min(cd1 - cd0 + 1, cd1 - cp);
-            const int sa = (int)(step % T::NA);
-            const int arow = wm * T::WM + (lane & 31), brow = wn * T::WN + (lane & 31);
-            const int kb = (lane >> 5) * 16;
-            v4i fa[2][T::FM];
+        const int nv = min(cd1 - cd0 + 1, cd1 - cp);
 #pragma unroll
-            for (int ks = 0; ks < 2; ++ks)
+        for (int j = 0; j < G; ++j) {
+            if (j < nv) {
 #pragma unroll
-                for (int i = 0; i < T::FM; ++i)
-                    fa[ks][i] = *(const v4i*)(&As[sa * T::A_SLOT + (arow + i * 32) * T::ROW + ks * 32 + kb]);
+                for (int ks = 0; ks < T::KS; ++ks)
 #pragma unroll
-            for (int j = 0; j < G; ++j) {
-                if (j < nv) {
-                    const int sb = (int)((step + T::NB - j) % T::NB);
-                    v4i fb[2][T::FN];
-#pragma unroll
-                    for (int ks = 0; ks < 2; ++ks)
+                    for (int i = 0; i < T::FM; ++i)
 #pragma unroll
                         for (int jj = 0; jj < T::FN; ++jj)
-                            fb[ks][jj] = *(const v4i*)(&Bs[sb * T::B_SLOT + (brow + jj * 32) * T::ROW +
-                                                           ks * 32 + kb]);
-#pragma unroll
-                    for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-                        for (int i = 0; i < T::FM; ++i)
-#pragma unroll
-                            for (int jj = 0; jj < T::FN; ++jj)
-                                acc[j][i][jj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                                    fa[ks][i], fb[ks][jj], acc[j][i][jj], 0, 0, 0);
-                }
+                            acc[j][i][jj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                                fa[ks][i], wb[(W - j + G) % G][ks][jj], acc[j][i][jj], 0, 0, 0);
             }
         }
 
@@ -391,16 +396,18 @@ __global__ __launch_bounds__(256, 1) void diag_mfma_kernel(const int8_t* __restr
         }
 
         if (!f_valid) return true;
-        sstore(raS, rbS, (int)((step + 1) % T::NA), (int)((step + 1) % T::NB));
+        sstore(raS, rbS, SET ^ 1);
         __syncthreads();
         cd0 = fd0; cd1 = fd1; cp = fp; ckt = fkt;
         fd0 = nd0; fd1 = nd1; fp = np; fkt = nkt2; f_valid = n_valid;
+        (void)base;
         return false;
     };
 
-    for (int64_t step = 0;; step += 2) {
-        if (iteration(ra0, rb0, ra1, rb1, step)) break;
-        if (iteration(ra1, rb1, ra0, rb0, step + 1)) break;
+    for (int64_t base = 0;; base += T::U) {
+        if (diag_unrolled([&](auto sc) { return iteration(sc, base); },
+                          std::make_integer_sequence<int, T::U>{}))
+            break;
     }
 }
 
@@ -491,8 +498,8 @@ static int launch_diag(int cfg, const int8_t* DA, const int8_t* DB, int32_t* S, 
     switch (cfg) {
     case 0: MPG_DIAG(128, 128, 4); break;
     case 1: MPG_DIAG(64, 64, 8); break;
-    case 2: MPG_DIAG(128, 128, 3); break;
-    default: MPG_DIAG(64, 64, 16); break;
+    case 2: MPG_DIAG(128, 128, 2); break;
+    default: MPG_DIAG(64, 64, 4); break;
     }
 #undef MPG_DIAG
     return (int)hipGetLastError();

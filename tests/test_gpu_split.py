@@ -27,11 +27,12 @@ def workspace_views(ws, lay, s):
     Mp, Np, Kp = lay["Mp"], lay["Np"], lay["Kp"]
     E = raw[lay["E"]: lay["E"] + 4 * Mp].view(np.int32)
     F = raw[lay["F"]: lay["F"] + 4 * Np].view(np.int32)
-    # digit planes are k-tile-major: [s][Kp/64][rows][64]
-    nkt = Kp // 64
-    DA = raw[lay["DA"]: lay["DA"] + s * Mp * Kp].view(np.int8).reshape(s, nkt, Mp, 64)
+    # digit planes are k-tile-major: [s][Kp/KT][rows][KT], KT = 64
+    KT = 64
+    nkt = Kp // KT
+    DA = raw[lay["DA"]: lay["DA"] + s * Mp * Kp].view(np.int8).reshape(s, nkt, Mp, KT)
     DA = DA.transpose(0, 2, 1, 3).reshape(s, Mp, Kp)
-    DB = raw[lay["DB"]: lay["DB"] + s * Np * Kp].view(np.int8).reshape(s, nkt, Np, 64)
+    DB = raw[lay["DB"]: lay["DB"] + s * Np * Kp].view(np.int8).reshape(s, nkt, Np, KT)
     DB = DB.transpose(0, 2, 1, 3).reshape(s, Np, Kp)
     S = raw[lay["S"]: lay["S"] + 4 * s * Np * Mp].view(np.int32).reshape(s, Np, Mp)
     return E, F, DA, DB, S

@@ -41,7 +41,8 @@ PAPER_CONTEXT = {
     "QD": {"seconds": 153.63, "2mnk/s": 8.95e8, "hw": "Core i9-10900X, 10 threads, Strassen+AVX2"},
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_plain_qd_4096.txt")
-ROOFLINE_SOURCES = ["paper_2101_06584_amd/csrc/plain_gemm.hip", "paper_2101_06584_amd/csrc/mp_arith.hpp"]
+ROOFLINE_SOURCES = ["paper_2101_06584_amd/csrc/plain_gemm.hip", "paper_2101_06584_amd/csrc/mp_arith.hpp",
+                    "paper_2101_06584_amd/csrc/tile_order.hpp"]
 
 
 def source_hash(paths):

@@ -16,6 +16,7 @@
 
 #include "internal.hpp"
 #include "mp_arith.hpp"
+#include "tile_order.hpp"
 
 namespace mpg {
 
@@ -153,9 +154,12 @@ template <int P, int TX, int TY, int TM, int TN, int BK>
 __global__ __launch_bounds__(TX * TY) void plain_gemm_kernel(GemmArgs g) {
     using T = PlainTile<P, TX, TY, TM, TN, BK>;
     __shared__ double lds[T::LDS_DOUBLES];
+    int64_t tm, tn;
+    if (!xcd_tile_coords<8>(blockIdx.x, (g.m + T::BM - 1) / T::BM, (g.n + T::BN - 1) / T::BN, tm, tn))
+        return;
     const mp<P> alpha = load_scalar<P>(g.alpha);
     const mp<P> beta = load_scalar<P>(g.beta);
-    T::run(g, alpha, beta, (int64_t)blockIdx.x * T::BM, (int64_t)blockIdx.y * T::BN, lds);
+    T::run(g, alpha, beta, tm * T::BM, tn * T::BN, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -282,11 +286,10 @@ int plain_default_config(int P, int64_t m, int64_t n, int64_t k) {
 template <int P, int TX, int TY, int TM, int TN, int BK>
 static int launch_plain_t(const GemmArgs& g, hipStream_t st) {
     using T = PlainTile<P, TX, TY, TM, TN, BK>;
-    const int64_t gx = (g.m + T::BM - 1) / T::BM;
-    const int64_t gy = (g.n + T::BN - 1) / T::BN;
-    if (gx > 0x7fffffffLL || gy > 65535) return (int)hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((plain_gemm_kernel<P, TX, TY, TM, TN, BK>), dim3((unsigned)gx, (unsigned)gy),
-                       dim3(T::NT), 0, st, g);
+    const int64_t grid = xcd_grid(((g.m + T::BM - 1) / T::BM) * ((g.n + T::BN - 1) / T::BN));
+    if (grid > 0x7fffffffLL) return (int)hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((plain_gemm_kernel<P, TX, TY, TM, TN, BK>), dim3((unsigned)grid), dim3(T::NT),
+                       0, st, g);
     return (int)hipGetLastError();
 }
 

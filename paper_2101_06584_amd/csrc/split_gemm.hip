@@ -26,6 +26,7 @@
 
 #include "internal.hpp"
 #include "mp_arith.hpp"
+#include "tile_order.hpp"
 
 namespace mpg {
 
@@ -209,27 +210,6 @@ __global__ __launch_bounds__(256) void slice_kernel(const double* __restrict__ X
 // is held in accumulator register v.
 // ---------------------------------------------------------------------------
 
-// Tile order: blocks dispatched to the same XCD (blockIdx % 8) take
-// consecutive logical tiles, and logical tiles walk 8-row groups so a
-// run of them shares op(A) row panels and op(B) column panels in that
-// XCD's L2.
-__device__ __forceinline__ bool diag_tile_coords(int64_t tiles_m, int64_t tiles_n, int64_t& tm,
-                                                 int64_t& tn) {
-    const int64_t total = tiles_m * tiles_n;
-    const int64_t per_xcd = (total + 7) / 8;
-    const int64_t bid = blockIdx.x;
-    const int64_t logical = (bid % 8) * per_xcd + bid / 8;
-    if (logical >= total) return false;
-    const int64_t GM = 8;
-    const int64_t group = logical / (GM * tiles_n);
-    const int64_t first_m = group * GM;
-    const int64_t gsize = (tiles_m - first_m) < GM ? (tiles_m - first_m) : GM;
-    const int64_t in_group = logical - group * GM * tiles_n;
-    tm = first_m + in_group % gsize;
-    tn = in_group / gsize;
-    return true;
-}
-
 template <int BM, int BN, int G>
 struct DiagWin {
     static constexpr int WM = BM / 2, WN = BN / 2;       // wave block
@@ -261,7 +241,7 @@ __global__ __launch_bounds__(256, 1) void diag_mfma_kernel(const int8_t* __restr
     int8_t* Bs = lds + 2 * T::A_SLOT;
 
     int64_t tm, tn;
-    if (!diag_tile_coords(Mp / BM, Np / BN, tm, tn)) return;
+    if (!xcd_tile_coords<8>(blockIdx.x, Mp / BM, Np / BN, tm, tn)) return;
     const int64_t m0 = tm * BM, n0 = tn * BN;
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
@@ -489,8 +469,7 @@ static int launch_slices(int P, const double* X, int64_t rs, int64_t ls, int64_t
 static int launch_diag(int cfg, const int8_t* DA, const int8_t* DB, int32_t* S, int64_t Mp,
                        int64_t Np, int64_t Kp, int s, hipStream_t st) {
     const SplitConfig c = kSplit[cfg];
-    const int64_t tiles = (Mp / c.bm) * (Np / c.bn);
-    const int64_t grid = (tiles + 7) / 8 * 8;
+    const int64_t grid = xcd_grid((Mp / c.bm) * (Np / c.bn));
     if (grid > 0x7fffffffLL) return (int)hipErrorInvalidConfiguration;
 #define MPG_DIAG(BM, BN, G)                                                                   \
     hipLaunchKernelGGL((diag_mfma_kernel<BM, BN, G>), dim3((unsigned)grid), dim3(256), 0, st, DA, DB, \

@@ -1,15 +1,22 @@
-"""Benchmark: square DD / TD / QD GEMM C = alpha A B + beta C on one MI355X.
+"""Benchmark: DD / TD / QD GEMM C = alpha A B + beta C on one MI355X.
 
-One step = the whole hot path over one batch of synthetic input: for each
-precision (DD, TD, QD) the plain FP64-VALU EFT GEMM and the split INT8-MFMA
-GEMM (scale scan, digit slicing, anti-diagonal MFMA sums, recombination and
-epilogue) on the same m = n = k = 4096 operands with random alpha, beta and C.
-`value` is the whole step's throughput in 2mnk/s (six GEMMs per step).
+One step = the whole hot path over one batch of synthetic input:
+  * for each precision (DD, TD, QD), m = n = k = 4096 with random alpha, beta
+    and C: the plain FP64-VALU EFT GEMM and the split INT8-MFMA GEMM (scale
+    scan, digit slicing, anti-diagonal MFMA sums, recombination, epilogue);
+  * the batched persistent form: 512 DD and 512 TD GEMMs with m, n, k uniform
+    in 16..512, each set one replay of its captured hipGraph;
+with tile configurations from the autotuner's table.  `value` is the step's
+total 2mnk divided by its time.
 
-Prints ONE JSON line (rank 0).  Extra fields: per-GEMM breakdown with the
-measured error against the exact product on sampled entries (split vs
-plain "at the same error"), the roofline of the dominant kernel, and the
-CPU oracle timed on this host's cores.
+Prints ONE JSON line.  Extra fields: per-part breakdown with the measured
+error against the exact product on sampled entries (split vs plain "at the
+same error"), the batched form against one launch per problem, the
+roofline of the dominant kernel, and the CPU oracle on this host's cores.
+
+Other workloads (separate JSON lines): --config 3 (QD n = 2048, entries
+u 2^e with e in -30..30 per entry, both forms, slice count from the accuracy
+rule) and --config 4 (DD n = 8192, both forms).
 """
 from __future__ import annotations
 
@@ -27,12 +34,16 @@ METRIC = "DD/TD/QD GEMM 2mnk/s, % FP64 peak; Ozaki-MFMA vs plain EFT at same err
 FP64_PEAK = 78.6e12            # MI355X FP64 vector, FLOP/s (FMA = 2)
 FP64_ISSUE = 256 * 64 * 2.4e9  # FP64 lane-instructions per second (256 CU x 64 lanes x 2.4 GHz)
 INT8_PEAK = 5.0e15             # MI355X dense INT8 MFMA, OP/s
-# FP64 operations per multiply-add of the paper's algorithms (MUL + ADD):
-#   DD: Algorithm 2 (9 instr, 10 flops) + Algorithm 1 (11)          -> 20 instr, 21 flops
-#   TD: Algorithm 4 (47 instr, 53 flops) + TDaddq = Algorithm 5 (85) -> 132 instr, 138 flops
-#   QD: Algorithm 6 (121 instr, 127 flops) + Algorithm 5 (85)        -> 206 instr, 212 flops
-INSTR_PER_MAC = {2: 20, 3: 132, 4: 206}
-FLOPS_PER_MAC = {2: 21, 3: 138, 4: 212}
+# FP64 operations per multiply-add as the algorithms execute them (MUL + ADD,
+# common branch of Renorm/VSEB):
+#   DD: Algorithm 2 (9 ops, 1 of them an FMA) + Algorithm 1 (11)              -> 20 ops, 21 flops
+#   TD: Algorithm 4 (47 ops, 6 FMA) + TDaddq = Algorithm 5 on (x0,x1,x2,0) and
+#       (y0,y1,y2,0) (82 ops, of which the 6 on the all-zero fourth lane
+#       fold to constants)                                                 -> 123 ops, 129 flops
+#   QD: Algorithm 6 (121 ops, 6 FMA) + Algorithm 5 (82: 4 lane TwoSums 24,
+#       TwoSum 6, ThreeSum 18, ThreeSum2 13, 2 adds, Renorm 19)           -> 203 ops, 209 flops
+INSTR_PER_MAC = {2: 20, 3: 123, 4: 203}
+FLOPS_PER_MAC = {2: 21, 3: 129, 4: 209}
 NAME = {2: "DD", 3: "TD", 4: "QD"}
 PAPER_CONTEXT = {
     "note": "paper's CPU seconds for C := AB, n = 4096 (AVX2 + OpenMP); other hardware, context only",
@@ -41,6 +52,7 @@ PAPER_CONTEXT = {
     "QD": {"seconds": 153.63, "2mnk/s": 8.95e8, "hw": "Core i9-10900X, 10 threads, Strassen+AVX2"},
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_plain_qd_4096.txt")
+SAME_ERROR_TARGET = 1e-6       # slice rule target for "split at the same error as plain"
 ROOFLINE_SOURCES = ["paper_2101_06584_amd/csrc/plain_gemm.hip", "paper_2101_06584_amd/csrc/mp_arith.hpp",
                     "paper_2101_06584_amd/csrc/tile_order.hpp"]
 
@@ -83,6 +95,8 @@ def parse():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds for the CPU baseline")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run a plain device copy of 1 GiB first (counter calibration)")
+    ap.add_argument("--no-batched", action="store_true", help="leave the batched sets out")
+    ap.add_argument("--config", type=int, default=0, help="3 or 4: the other workloads")
     return ap.parse_args()
 
 
@@ -103,6 +117,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
+    if args.config in (3, 4):
+        return other_config(args, mp, synth, dev, stream)
     n = args.n
     precs = [int(p) for p in args.prec.split(",")]
     forms = args.forms.split(",")
@@ -135,7 +151,27 @@ def main():
         devd[P] = d
     torch.cuda.synchronize()
 
+    # batched sets (config 5's shape mix): DD and TD, 512 problems each
+    batched = {}
+    if not args.no_batched:
+        for P in (2, 3):
+            hp = synth.batch_problems(5, P, 512, 16, 512)
+            dp = []
+            for pr in hp:
+                q = dict(pr)
+                q["A"] = torch.from_numpy(pr["A"]).to(dev)
+                q["B"] = torch.from_numpy(pr["B"]).to(dev)
+                q["C"] = torch.from_numpy(pr["C"]).to(dev)
+                dp.append(q)
+            plan = mp.BatchPlan(P, dp, stream=stream)
+            work = sum(2.0 * q["m"] * q["n"] * q["k"] for q in dp)
+            batched[P] = {"plan": plan, "probs": dp, "work": work, "host": hp}
+        torch.cuda.synchronize()
+
     def run(P, f):
+        if f == "batched":
+            batched[P]["plan"].run(stream=stream)
+            return
         d = devd[P]
         if f == "plain":
             mp.gemm(P, "N", "N", n, n, n, d["alpha"], d["A"], d["B"], d["beta"], d["C_plain"],
@@ -161,8 +197,10 @@ def main():
                 devd[P]["C_" + f].copy_(devd[P]["C0"])
         torch.cuda.synchronize()
 
-    # ---- warmup + timed steps; per-GEMM events on the launch stream ----
-    order = [(P, f) for P in precs for f in forms]
+    # ---- warmup + timed steps; per-part events on the launch stream ----
+    order = [(P, f) for P in precs for f in forms] + [(P, "batched") for P in sorted(batched)]
+    part_work = {key: (batched[key[0]]["work"] if key[1] == "batched" else 2.0 * n ** 3)
+                 for key in order}
     for _ in range(args.warmup):
         for P, f in order:
             run(P, f)
@@ -185,16 +223,21 @@ def main():
     wall = time.perf_counter() - t0
     total_ms = start_all.elapsed_time(end_all)
     ms_per_step = total_ms / args.steps
-    work_per_step = 2.0 * n * n * n * len(order)
+    work_per_step = sum(part_work.values())
     value = work_per_step / (ms_per_step * 1e-3)
 
     breakdown = {}
     for key in order:
         P, f = key
         ms = float(np.mean([a.elapsed_time(b) for a, b in ev[key]]))
-        rate = 2.0 * n ** 3 / (ms * 1e-3)
+        rate = part_work[key] / (ms * 1e-3)
         item = {"ms": round(ms, 3), "2mnk/s": rate}
-        if f == "plain":
+        if f == "batched":
+            info = batched[P]["plan"].info()
+            item.update(problems=len(batched[P]["probs"]), tiles=info["tiles"],
+                        tile_cfg=info["tile_cfg"], grid=info["grid"])
+            item.update(separate_launches(mp, P, batched[P], stream))
+        elif f == "plain":
             item["fp64_peak_frac"] = n ** 3 * FLOPS_PER_MAC[P] / (ms * 1e-3) / FP64_PEAK
             item["fp64_issue_frac"] = n ** 3 * INSTR_PER_MAC[P] / (ms * 1e-3) / FP64_ISSUE
         else:
@@ -220,14 +263,20 @@ def main():
                     "flops_per_launch": flops,
                     "traffic": read_traffic() if (dom_P == 4 and n == 4096) else None}
 
+    for P in batched:
+        batched[P]["plan"].close()
+
     out = {
         "metric": METRIC, "value": value, "unit": "2mnk/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64+i8", "data": "synthetic",
         "config": {"workload": f"square DD/TD/QD GEMM C = alpha*A*B + beta*C, m=n=k={n}, "
-                               "random alpha/beta/C; plain EFT and split INT8-MFMA forms per step",
+                               "random alpha/beta/C, plain EFT and split INT8-MFMA forms; plus "
+                               "batched DD and TD sets of 512 GEMMs with m,n,k ~ U[16,512] "
+                               "(one hipGraph replay each)",
                    "m": n, "n": n, "k": n, "precisions": [NAME[P] for P in precs], "forms": forms,
-                   "gemms_per_step": len(order), "parallelism": "single GPU"},
+                   "batched_sets": [NAME[P] for P in sorted(batched)],
+                   "parts_per_step": len(order), "parallelism": "single GPU"},
         "breakdown": breakdown,
         "roofline": roofline,
         "wall_s_timed": round(wall, 3),
@@ -236,19 +285,130 @@ def main():
 
     # ---- CPU oracle on this host's cores (bounded sample) ----
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(host, precs, forms, n, devd, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(host, precs, forms, n, devd, args.cpu_budget, batched)
 
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(host, precs, forms, n, devd, budget):
-    """The oracle, as it stands, on a block of rows of each of the step's
-    GEMMs; the step's 2mnk/s is extrapolated from the per-GEMM sampled rates."""
+def separate_launches(mp, P, b, stream):
+    """The same batched set as one plain launch per problem (not in the step)."""
+    import torch
+    for _ in range(2):
+        for q in b["probs"]:
+            mp.gemm(P, q["transa"], q["transb"], q["m"], q["n"], q["k"], q["alpha"], q["A"], q["B"],
+                    q["beta"], q["C"], stream=stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for q in b["probs"]:
+        mp.gemm(P, q["transa"], q["transb"], q["m"], q["n"], q["k"], q["alpha"], q["A"], q["B"],
+                q["beta"], q["C"], stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    return {"separate_launches_ms": round(ms, 3), "separate_launches_2mnk/s": b["work"] / (ms * 1e-3)}
+
+
+def other_config(args, mp, synth, dev, stream):
+    """--config 3: QD n = 2048 with exponent spread, both forms, slices from the
+    accuracy rule; --config 4: DD n = 8192, both forms.  One JSON line."""
+    import numpy as np
+    import torch
+    from tests.exact import GemmChecker, sample_entries
+    cfg = args.config
+    if cfg == 3:
+        P, n, spread = 4, 2048, (-30, 30)
+    else:
+        P, n, spread = 2, 8192, None
+    A = synth.mp_matrix(cfg, "A", P, n, n, exp_range=spread)
+    B = synth.mp_matrix(cfg, "B", P, n, n, exp_range=spread)
+    one, zero = synth.mp_one(P), np.zeros(P)
+    dA = torch.from_numpy(A).to(dev)
+    dB = torch.from_numpy(B).to(dev)
+    forms = args.forms.split(",")
+    if cfg == 3:
+        # "same error": the smallest s whose result on a block of rows stays
+        # within 1e-6 k u (|A||B|)_ij of the plain (canonical) result
+        s, rule_ratio = mp.tune_slices(P, "N", "N", n, n, n, dA, dB, target=SAME_ERROR_TARGET,
+                                       smin=28, smax=40, stream=stream)
+    else:
+        s, rule_ratio = mp.DEFAULT_SLICES[P], None
+    ws = mp.alloc_workspace(P, n, n, n, s, device=dev) if "split" in forms else None
+    parts = {}
+    chk = None if args.no_check else GemmChecker(P, "N", "N", n, n, n, one, A, B, zero,
+                                                 np.zeros((P, 1, 1)))
+    ents = sample_entries(synth.rng_for(cfg, "samples"), n, n, 1024)
+    for f in forms:
+        dC = torch.zeros((P, n, n), dtype=torch.float64, device=dev)
+        kw = dict(form="split", slices=s, workspace=ws) if f == "split" else dict(form="plain")
+        call = lambda: mp.gemm(P, "N", "N", n, n, n, one, dA, dB, zero, dC, stream=stream, **kw)  # noqa: E731
+        for _ in range(args.warmup):
+            call()
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(args.steps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            call()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        ms = float(np.median(times))
+        item = {"ms": round(ms, 3), "2mnk/s": 2.0 * n ** 3 / (ms * 1e-3)}
+        if f == "split":
+            item["slices"] = s
+            item["int8_ops_frac"] = s * (s + 1) / 2 * 2.0 * n ** 3 / (ms * 1e-3) / INT8_PEAK
+        else:
+            item["fp64_peak_frac"] = n ** 3 * FLOPS_PER_MAC[P] / (ms * 1e-3) / FP64_PEAK
+        if chk is not None:
+            r = chk.ratios(dC.cpu().numpy(), ents)
+            item["err_ratio_max"] = float(r.max())
+            item["err_ratio_median"] = float(np.median(r))
+        parts[f"{NAME[P]}_{f}"] = item
+    total_ms = sum(v["ms"] for v in parts.values())
+    workload = ("QD GEMM m=n=k=2048, entries u*2^e, e ~ U{-30..30} per entry, both forms, slices "
+                "from the accuracy rule" if cfg == 3 else "DD GEMM m=n=k=8192, both forms")
+    out = {"metric": METRIC, "value": 2.0 * n ** 3 * len(parts) / (total_ms * 1e-3), "unit": "2mnk/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(total_ms, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64+i8", "data": "synthetic",
+           "config": {"workload": workload, "m": n, "n": n, "k": n, "precision": NAME[P],
+                      "samples": len(ents) if chk is not None else 0,
+                      "err_ratio_unit": "|C - C*| / (k u (|A||B|)_ij), u = 2^-104 DD / 2^-200 QD"},
+           "breakdown": parts}
+    if rule_ratio is not None:
+        out["slice_rule"] = {"slices": s, "max_diff_vs_plain_on_64_rows": rule_ratio,
+                             "target": SAME_ERROR_TARGET}
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(host, precs, forms, n, devd, budget, batched):
+    """The oracle, as it stands, on a block of each of the step's large GEMMs
+    and on the first problems of each batched set; the step's 2mnk/s is
+    extrapolated from the per-part sampled rates."""
     import oracle
     threads = oracle.num_threads()
-    per = budget / max(1, len(precs) * len(forms))
+    per = budget / max(1, len(precs) * len(forms) + len(batched))
     est_total = 0.0
+    total_work = 0.0
     parts = []
+    for P, b in sorted(batched.items()):
+        t0 = time.perf_counter()
+        done = 0.0
+        cnt = 0
+        for q in b["host"]:
+            oracle.gemm(P, q["transa"], q["transb"], q["m"], q["n"], q["k"], q["alpha"], q["A"],
+                        q["B"], q["beta"], q["C"])
+            done += 2.0 * q["m"] * q["n"] * q["k"]
+            cnt += 1
+            if time.perf_counter() - t0 > per / 2:
+                break
+        rate = done / (time.perf_counter() - t0)
+        est_total += b["work"] / rate
+        total_work += b["work"]
+        parts.append(f"{NAME[P]}-batched: first {cnt} problems ({rate:.3g} 2mnk/s)")
     for P in precs:
         A, B, C, alpha, beta = host[P]
         for f in forms:
@@ -272,11 +432,13 @@ def cpu_baseline(host, precs, forms, n, devd, budget):
                 t = once(rows, cols)
             rate = 2.0 * rows * cols * n / t
             est_total += 2.0 * n ** 3 / rate
+            total_work += 2.0 * n ** 3
             parts.append(f"{NAME[P]}-{f}: {rows}x{cols} block ({rate:.3g} 2mnk/s)")
-    value = len(precs) * len(forms) * 2.0 * n ** 3 / est_total
+    value = total_work / est_total
     return {"value": value, "unit": "2mnk/s", "cores": threads, "kind": "oracle",
-            "sample": "per GEMM of the step, a block of rows x columns of C (all k) timed and the "
-                      "full n^3 extrapolated: " + "; ".join(parts)}
+            "sample": "per large GEMM of the step a block of rows x columns of C (all k), per "
+                      "batched set its first problems, each timed and extrapolated to the part's "
+                      "full 2mnk: " + "; ".join(parts)}
 
 
 if __name__ == "__main__":

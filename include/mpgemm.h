@@ -219,6 +219,15 @@ int mpgemm_batch_plan_destroy(mpgemm_batch_plan* plan);
  */
 int mpgemm_autotune(int prec, int form, int64_t m, int64_t n, int64_t k, int slices,
                     hipStream_t stream, int* best);
+/* Batched form: times every tile configuration on these problems (plans are
+ * built and destroyed by the call; the problems' C buffers are overwritten)
+ * and records the fastest under form id 3 for the problems' mean shape.
+ * Arguments as mpgemm_batch_plan_create; *best (may be NULL) gets the id. */
+int mpgemm_batch_autotune(int prec, int64_t count, const mpgemm_problem* problems,
+                          hipStream_t stream, int* best);
+/* Record a configuration for a precision / form (0 plain, 1 split, 3 batched)
+ * / shape bucket directly (e.g. from a table produced elsewhere). */
+int mpgemm_autotune_set(int prec, int form, int64_t m, int64_t n, int64_t k, int tile);
 /* Persist / restore the tuning table as a small text file (one entry per
  * line: prec form log2m log2n log2k tile). */
 int mpgemm_autotune_save(const char* path);

@@ -150,6 +150,26 @@ def split_stages(prec, last, transa, transb, m, n, k, alpha, A, B, beta, C_, *, 
     _check(rc, "mpgemm_split_stages")
 
 
+def _problem_array(P, problems):
+    arr = (_lib.Problem * max(len(problems), 1))()
+    keep = []
+    for q, pr in enumerate(problems):
+        x = arr[q]
+        x.transa = pr.get("transa", "N").encode()
+        x.transb = pr.get("transb", "N").encode()
+        x.m, x.n, x.k = pr["m"], pr["n"], pr["k"]
+        al = list(pr["alpha"]) + [0.0] * 4
+        be = list(pr["beta"]) + [0.0] * 4
+        x.alpha = (C.c_double * 4)(*al[:4])
+        x.beta = (C.c_double * 4)(*be[:4])
+        a, x.lda, x.a_plane_stride = _mat(pr["A"], P)
+        b, x.ldb, x.b_plane_stride = _mat(pr["B"], P)
+        c, x.ldc, x.c_plane_stride = _mat(pr["C"], P)
+        x.A, x.B, x.C = a, b, c
+        keep.append((pr["A"], pr["B"], pr["C"]))
+    return arr, keep
+
+
 class BatchPlan:
     """Many GEMMs of one precision in one persistent launch, replayed from a
     captured hipGraph (run) or launched directly (launch)."""
@@ -159,22 +179,7 @@ class BatchPlan:
         A, B, beta, C (tensors as for gemm())."""
         self.P = PREC[prec]
         L = _lib.load()
-        arr = (_lib.Problem * max(len(problems), 1))()
-        self._keep = []
-        for q, pr in enumerate(problems):
-            x = arr[q]
-            x.transa = pr.get("transa", "N").encode()
-            x.transb = pr.get("transb", "N").encode()
-            x.m, x.n, x.k = pr["m"], pr["n"], pr["k"]
-            al = list(pr["alpha"]) + [0.0] * 4
-            be = list(pr["beta"]) + [0.0] * 4
-            x.alpha = (C.c_double * 4)(*al[:4])
-            x.beta = (C.c_double * 4)(*be[:4])
-            a, x.lda, x.a_plane_stride = _mat(pr["A"], self.P)
-            b, x.ldb, x.b_plane_stride = _mat(pr["B"], self.P)
-            c, x.ldc, x.c_plane_stride = _mat(pr["C"], self.P)
-            x.A, x.B, x.C = a, b, c
-            self._keep.append((pr["A"], pr["B"], pr["C"]))
+        arr, self._keep = _problem_array(self.P, problems)
         opts = make_opts("plain", 0, tile, None)
         h = C.c_void_p()
         rc = L.mpgemm_batch_plan_create(self.P, len(problems), arr, C.byref(opts), _stream(stream),
@@ -213,6 +218,22 @@ def autotune(prec, form, m, n, k, slices=0, stream=None) -> int:
     return best.value
 
 
+def batch_autotune(prec, problems, stream=None) -> int:
+    """Time every tile configuration of the batched form on these problems
+    (their C buffers are overwritten) and record the fastest."""
+    P = PREC[prec]
+    arr, keep = _problem_array(P, problems)
+    best = C.c_int(-1)
+    _check(_lib.load().mpgemm_batch_autotune(P, len(problems), arr, _stream(stream), C.byref(best)),
+           "mpgemm_batch_autotune")
+    return best.value
+
+
+def autotune_set(prec, form, m, n, k, tile) -> None:
+    f = FORMS[form] if isinstance(form, str) else int(form)
+    _check(_lib.load().mpgemm_autotune_set(PREC[prec], f, m, n, k, tile), "autotune_set")
+
+
 def autotune_save(path: str) -> None:
     _check(_lib.load().mpgemm_autotune_save(path.encode()), "autotune_save")
 
@@ -221,8 +242,11 @@ def autotune_load(path: str) -> None:
     _check(_lib.load().mpgemm_autotune_load(path.encode()), "autotune_load")
 
 
+FORMS_ALL = dict(FORMS, batched=3)
+
+
 def num_configs(prec, form) -> int:
-    f = FORMS[form] if isinstance(form, str) else int(form)
+    f = FORMS_ALL[form] if isinstance(form, str) else int(form)
     return int(_lib.load().mpgemm_num_configs(PREC[prec], f))
 
 

@@ -486,6 +486,64 @@ int mpgemm_autotune(int prec, int form, int64_t m, int64_t n, int64_t k, int sli
     return 0;
 }
 
+int mpgemm_autotune_set(int prec, int form, int64_t m, int64_t n, int64_t k, int tile) {
+    if (prec < 2 || prec > 4) return -1;
+    if (form != MPGEMM_FORM_PLAIN && form != MPGEMM_FORM_SPLIT_I8 && form != 3) return -2;
+    if (m <= 0) return -3;
+    if (n <= 0) return -4;
+    if (k <= 0) return -5;
+    if (tile < 0 || tile >= mpgemm_num_configs(prec, form)) return -6;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[std::make_tuple(prec, form, ilog2(m), ilog2(n), ilog2(k))] = tile;
+    return 0;
+}
+
+int mpgemm_batch_autotune(int prec, int64_t count, const mpgemm_problem* probs, hipStream_t st,
+                          int* best) {
+    if (prec < 2 || prec > 4) return -1;
+    if (count <= 0) return -2;
+    if (!probs) return -3;
+    int64_t mm = 0, nn = 0, kk = 0;
+    for (int64_t q = 0; q < count; ++q) { mm += probs[q].m; nn += probs[q].n; kk += probs[q].k; }
+    mm = std::max<int64_t>(1, mm / count);
+    nn = std::max<int64_t>(1, nn / count);
+    kk = std::max<int64_t>(1, kk / count);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return MPGEMM_ERR_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return MPGEMM_ERR_HIP; }
+    int chosen = -1, rc = 0;
+    float best_ms = 1e30f;
+    for (int c = 0; c < kPlainConfigs && !rc; ++c) {
+        mpgemm_opts o{};
+        o.tile = c;
+        mpgemm_batch_plan* plan = nullptr;
+        rc = mpgemm_batch_plan_create(prec, count, probs, &o, st, &plan);
+        if (rc) break;
+        rc = mpgemm_batch_plan_run(plan, st);     // warm-up
+        float bms = 1e30f;
+        for (int rep = 0; rep < 3 && !rc; ++rep) {
+            (void)hipEventRecord(e0, st);
+            rc = mpgemm_batch_plan_run(plan, st);
+            (void)hipEventRecord(e1, st);
+            if (hipEventSynchronize(e1) != hipSuccess) rc = MPGEMM_ERR_HIP;
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            bms = std::min(bms, ms);
+        }
+        mpgemm_batch_plan_destroy(plan);
+        if (!rc && bms < best_ms) { best_ms = bms; chosen = c; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[std::make_tuple(prec, 3, ilog2(mm), ilog2(nn), ilog2(kk))] = chosen;
+    }
+    if (best) *best = chosen;
+    return 0;
+}
+
 int mpgemm_autotune_save(const char* path) {
     if (!path) return -1;
     FILE* f = std::fopen(path, "w");

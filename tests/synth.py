@@ -41,7 +41,11 @@ def _tail_components(rng, lead: np.ndarray, P: int) -> np.ndarray:
     out = np.empty((P,) + lead.shape, dtype=np.float64)
     out[0] = lead
     for c in range(1, P):
-        half_ulp = 0.5 * np.spacing(np.abs(out[c - 1]))
+        # half an ulp of a normal x = f 2^e (f in [1/2, 1)) is 2^(e - 54);
+        # components here are never subnormal, and a zero gets a zero tail
+        prev = out[c - 1]
+        _, e = np.frexp(prev)
+        half_ulp = np.where(prev == 0.0, 0.0, np.ldexp(1.0, e - 54))
         v = rng.uniform(-1.0, 1.0, size=lead.shape)
         out[c] = half_ulp * v          # |v| < 1 keeps |out[c]| < ulp/2
     return out
@@ -139,3 +143,28 @@ def paper_exact_entry(n: int, i: int) -> Fraction:
     sum_k sqrt5 (i+k-1) sqrt3 (n-k) = sqrt15 * n(n-1)(3i+n-2)/6."""
     r15 = sqrt_fraction(15)
     return r15 * Fraction(n * (n - 1) * (3 * i + n - 2), 6)
+
+
+def batch_problems(cfg: int, P: int, count: int, lo: int, hi: int):
+    """`count` GEMM problems with m, n, k drawn uniformly from lo..hi (slot
+    "shapes"); operands drawn like mp_matrix in one pass (slots A, B, C) and
+    cut per problem.  alpha = 1, beta = 0 (C = A B), transposes 'N'."""
+    shapes = rng_for(cfg, "shapes").integers(lo, hi + 1, size=(count, 3))
+    sizes = [(int(m) * int(k), int(k) * int(n), int(m) * int(n)) for m, n, k in shapes]
+    pools = {}
+    for slot, idx in (("A", 0), ("B", 1), ("C", 2)):
+        total = sum(s[idx] for s in sizes)
+        rows = (total + 1023) // 1024            # drawn as rows of 1024 (faster in numpy)
+        pools[slot] = mp_uniform(rng_for(cfg, slot), P, (rows, 1024)).reshape(P, -1)[:, :total]
+    off = [0, 0, 0]
+    out = []
+    for (m, n, k), sz in zip(shapes, sizes):
+        m, n, k = int(m), int(n), int(k)
+        mats = []
+        for idx, (slot, rows, cols) in enumerate((("A", m, k), ("B", k, n), ("C", m, n))):
+            flat = pools[slot][:, off[idx]:off[idx] + sz[idx]]
+            off[idx] += sz[idx]
+            mats.append(np.ascontiguousarray(flat.reshape(P, cols, rows)))
+        out.append(dict(transa="N", transb="N", m=m, n=n, k=k, A=mats[0], B=mats[1], C=mats[2],
+                        alpha=mp_one(P), beta=np.zeros(P)))
+    return out

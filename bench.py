@@ -117,12 +117,6 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
-    if args.config in (3, 4):
-        return other_config(args, mp, synth, dev, stream)
-    n = args.n
-    precs = [int(p) for p in args.prec.split(",")]
-    forms = args.forms.split(",")
-
     if args.copy_calib:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
         src.fill_(1.0)
@@ -130,6 +124,11 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.config in (3, 4):
+        return other_config(args, mp, synth, dev, stream)
+    n = args.n
+    precs = [int(p) for p in args.prec.split(",")]
+    forms = args.forms.split(",")
 
     # ---- inputs (config: square n, random alpha/beta, C like A and B) ----
     host = {}

@@ -34,15 +34,15 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
 static constexpr int kTileK = 64;          // k bytes per pipeline step (and k-tile width)
-static constexpr int kLdsPad = 16;         // row padding (bytes) against bank conflicts
 static constexpr int kSliceTile = 32;      // slicing kernel: 32 rows x 32 k per block
 
 static inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // {bm, bn, g}: output tile of one MFMA workgroup (4 waves in 2 x 2) and the
-// number of diagonals accumulated at once.
-static const SplitConfig kSplit[kSplitConfigs] = {{128, 128, 4}, {64, 64, 8}, {128, 128, 2},
+// number of diagonals accumulated at once (the LDS ring depth is fixed per
+// configuration in launch_diag).
+static const SplitConfig kSplit[kSplitConfigs] = {{128, 128, 2}, {64, 64, 8}, {128, 64, 4},
                                                   {64, 64, 4}};
 
 SplitConfig split_config(int id) { return kSplit[id]; }
@@ -191,17 +191,25 @@ __global__ __launch_bounds__(256) void slice_kernel(const double* __restrict__ X
 // ---------------------------------------------------------------------------
 // Stage 3: anti-diagonal sums on the INT8 matrix cores.
 //
-// Workgroup = 4 waves in 2 x 2 over a BM x BN output tile; each wave holds a
-// (BM/2) x (BN/2) block of 32 x 32 MFMA tiles for G diagonals at once.
-// Diagonals are processed in groups [d0, d1] (d1 = min(d0 + G - 1, s + 1)).
-// Within a group and a 64-wide k-tile the pairs (p, q) are visited with p
-// descending from d1 - 1 to 1: the step for p loads digit slice A_p and the
-// single new slice B_{d1 - p}; the pairs of that step are (p, d1 - p - j),
-// j = 0..G-1 (while q >= 1 and d1 - j >= d0), and B_{d1-p-j} is exactly the
-// slice loaded j steps earlier.  So each step moves two slice tiles through
-// LDS (double-buffered, rows padded to 80 bytes) and feeds up to G pairs; the
-// B fragments of the last G steps stay in a register window, the accumulator
-// of pair j is always diagonal d1 - j, and global loads run two steps ahead.
+// One workgroup (4 waves in 2 x 2) owns a BM x BN block of every S_d and
+// accumulates G diagonals at once: diagonals are processed in groups
+// [d0, d1] (d1 = min(d0 + G - 1, s + 1)).  Within a group and a 64-wide
+// k-tile the pairs (p, q) are visited with p descending from d1 - 1 to 1: the
+// step for p brings in digit slice A_p and the single new slice B_{d1 - p};
+// its pairs are (p, d1 - p - j), j = 0..G-1 (while q >= 1 and d1 - j >= d0),
+// and B_{d1-p-j} is exactly the slice of j steps earlier.  Each wave keeps
+// the B fragments of the last G steps in a register window, so a step reads
+// one A and one B fragment from LDS and feeds up to G pairs; the accumulator
+// of pair j is always diagonal d1 - j.
+//
+// Staging: the tiles of a step (BM x 64 and BN x 64 bytes) are copied from
+// HBM straight into LDS by 16-byte direct-to-LDS loads, D steps deep in a
+// ring, so no register holds data in flight; a wave waits for its own copies
+// of the step it computes (vector-memory counter) and then meets the others
+// at a barrier.  A 16-byte chunk c of tile row r sits at LDS chunk
+// c ^ ((r / 4) mod 4) of that row: a direct-to-LDS load writes 64 consecutive
+// chunks, so each lane gathers the global chunk that belongs to its slot, and
+// the fragment reads below (32 rows, one chunk each) hit distinct banks.
 //
 // v_mfma_i32_32x32x32_i8: lane L supplies A row (L % 32) and B column (L % 32),
 // 16 consecutive k bytes starting at 16 (L / 32) of the 32-wide k step (the
@@ -210,18 +218,18 @@ __global__ __launch_bounds__(256) void slice_kernel(const double* __restrict__ X
 // is held in accumulator register v.
 // ---------------------------------------------------------------------------
 
-template <int BM, int BN, int G>
-struct DiagWin {
+template <int BM, int BN, int G, int D>
+struct DiagDma {
     static constexpr int WM = BM / 2, WN = BN / 2;       // wave block
     static constexpr int FM = WM / 32, FN = WN / 32;     // MFMA tiles per wave
-    static constexpr int ROW = kTileK + kLdsPad;         // LDS row bytes
-    static constexpr int CPR = kTileK / 16;              // 16-byte chunks per row
     static constexpr int KS = kTileK / 32;               // MFMA k-substeps per step
-    static constexpr int A_SLOT = BM * ROW, B_SLOT = BN * ROW;
-    static constexpr int A_CHUNKS = BM * kTileK / 16, B_CHUNKS = BN * kTileK / 16;
-    static constexpr int A_PER_T = (A_CHUNKS + 255) / 256, B_PER_T = (B_CHUNKS + 255) / 256;
-    static constexpr int LDS_BYTES = 2 * A_SLOT + 2 * B_SLOT;
-    static constexpr int U = (G % 2 == 0) ? G : 2 * G;   // unroll: register sets x window
+    static constexpr int A_BYTES = BM * kTileK, B_BYTES = BN * kTileK;
+    static constexpr int STAGE = A_BYTES + B_BYTES;
+    static constexpr int A_LOADS = A_BYTES / 4096, B_LOADS = B_BYTES / 4096;  // per thread
+    static constexpr int PER_STEP = A_LOADS + B_LOADS;   // vector-memory ops per step
+    static constexpr int LDS_BYTES = D * STAGE;
+    static_assert(A_BYTES % 4096 == 0 && B_BYTES % 4096 == 0, "tiles split into 1 KiB wave copies");
+    static_assert(PER_STEP * (D - 2) <= 63, "vector-memory counter range");
 };
 
 template <typename F, int... I>
@@ -229,16 +237,44 @@ __device__ __forceinline__ bool diag_unrolled(F&& f, std::integer_sequence<int, 
     return (... || f(std::integral_constant<int, I>{}));
 }
 
-template <int BM, int BN, int G>
-__global__ __launch_bounds__(256, 1) void diag_mfma_kernel(const int8_t* __restrict__ DA,
+template <int N, typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {   // f(0), ..., f(N - 1) as constants
+    static_for_impl<N>(f, std::make_integer_sequence<int, N>{});
+}
+
+// LDS offset of 16-byte chunk c (0..3) of tile row r (64-byte rows).
+__device__ __forceinline__ int swz(int r, int c) { return r * kTileK + ((c ^ ((r >> 2) & 3)) << 4); }
+
+// Wait until at most N vector-memory operations of this wave are pending and
+// its LDS reads are done, then meet the other waves; a compiler barrier too.
+template <int N>
+__device__ __forceinline__ void wait_vm_barrier() {
+    static_assert(N >= 0 && N <= 63, "vmcnt range");
+    asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
+}
+
+__device__ __forceinline__ void wait_vm_all() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
+
+// Steps of one pass (group with top diagonal d1, one k-tile): d1 - 1 real
+// steps, padded to a multiple of u.
+__device__ __forceinline__ int pass_len(int d1, int u) { return (d1 - 1 + u - 1) / u * u; }
+
+template <int BM, int BN, int G, int D>
+__global__ __launch_bounds__(256, 2) void diag_mfma_kernel(const int8_t* __restrict__ DA,
                                                            const int8_t* __restrict__ DB,
                                                            int32_t* __restrict__ S, int64_t Mp,
                                                            int64_t Np, int64_t Kp, int s) {
-    using T = DiagWin<BM, BN, G>;
-    static_assert(T::A_CHUNKS % 256 == 0 && T::B_CHUNKS % 256 == 0, "tile loads split evenly");
-    __shared__ __attribute__((aligned(16))) int8_t lds[T::LDS_BYTES];
-    int8_t* As = lds;
-    int8_t* Bs = lds + 2 * T::A_SLOT;
+    using T = DiagDma<BM, BN, G, D>;
+    // every pass is a multiple of U steps, so the window slot (step % G) and
+    // the ring slot (step % D) are compile-time constants in an unrolled block
+    constexpr int U = G / gcd_c(G, D) * D;
+    __shared__ __attribute__((aligned(1024))) int8_t lds[T::LDS_BYTES];
 
     int64_t tm, tn;
     if (!xcd_tile_coords<8>(blockIdx.x, Mp / BM, Np / BN, tm, tn)) return;
@@ -246,49 +282,78 @@ __global__ __launch_bounds__(256, 1) void diag_mfma_kernel(const int8_t* __restr
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
     const int wm = wave & 1, wn = wave >> 1;
-    const int64_t nkt = Kp / kTileK;
+    const int wave_lds = __builtin_amdgcn_readfirstlane(wave) * 1024;
+    const int nkt = (int)(Kp / kTileK);
     const int last_d = s + 1;
-    const int arow = wm * T::WM + (lane & 31), brow = wn * T::WN + (lane & 31);
-    const int kb = (lane >> 5) * 16;
 
-    // step cursors: (d0, d1, kt, p); advance = next p (descending), then next
-    // k-tile, then next group; past the last step the cursor stays put (so the
-    // prefetch of a step that does not exist re-reads valid data)
-    auto advance = [&](int& d0, int& d1, int64_t& kt, int& p) -> bool {
-        if (p > 1) { --p; return true; }
-        if (kt + 1 < nkt) { ++kt; p = d1 - 1; return true; }
-        if (d1 + 1 > last_d) return false;
-        kt = 0;
-        d0 = d1 + 1;
-        d1 = min(d0 + G - 1, last_d);
-        p = d1 - 1;
-        return true;
-    };
+    // byte strides between digit slices and between k-tiles of one slice
+    const int64_t sliceA = (int64_t)nkt * Mp * kTileK, sliceB = (int64_t)nkt * Np * kTileK;
+    const int64_t ktA = Mp * kTileK, ktB = Np * kTileK;
+    const int8_t* const A0 = DA + m0 * kTileK;
+    const int8_t* const B0 = DB + n0 * kTileK;
 
-    // two register sets for the global -> LDS staging, picked at compile time
-    // (a run-time index into a register array would force a wait per load)
-    v4i ra0[T::A_PER_T], rb0[T::B_PER_T], ra1[T::A_PER_T], rb1[T::B_PER_T];
-    // slice tile (digit p, k-tile kt) of rows m0.. is the contiguous block at
-    // DA + ((p-1) nkt + kt) Mp 64 + m0 64
-    auto gload = [&](v4i (&ra)[T::A_PER_T], v4i (&rb)[T::B_PER_T], int p, int q, int64_t kt) {
-        const v4i* a = (const v4i*)(DA + (((int64_t)(p - 1) * nkt + kt) * Mp + m0) * kTileK);
-        const v4i* b = (const v4i*)(DB + (((int64_t)(q - 1) * nkt + kt) * Np + n0) * kTileK);
+    // global byte offset (within a tile) that this lane copies for its h-th
+    // 1 KiB slot: LDS chunk u = t + 256 h -> row u / 4, LDS slot u % 4,
+    // global chunk (u % 4) ^ ((row / 4) % 4)
+    constexpr int NL = T::A_LOADS > T::B_LOADS ? T::A_LOADS : T::B_LOADS;
+    int gofs[NL];
 #pragma unroll
-        for (int h = 0; h < T::A_PER_T; ++h) ra[h] = a[t + 256 * h];
+    for (int h = 0; h < NL; ++h) {
+        const int u = t + 256 * h;
+        const int r = u >> 2;
+        gofs[h] = r * kTileK + (((u & 3) ^ ((r >> 2) & 3)) << 4);
+    }
+    // LDS offsets of this lane's fragments (relative to a stage)
+    int aofs[T::KS][T::FM], bofs[T::KS][T::FN];
 #pragma unroll
-        for (int h = 0; h < T::B_PER_T; ++h) rb[h] = b[t + 256 * h];
+    for (int ks = 0; ks < T::KS; ++ks) {
+#pragma unroll
+        for (int i = 0; i < T::FM; ++i) aofs[ks][i] = swz(wm * T::WM + i * 32 + (lane & 31), 2 * ks + (lane >> 5));
+#pragma unroll
+        for (int jj = 0; jj < T::FN; ++jj)
+            bofs[ks][jj] = T::A_BYTES + swz(wn * T::WN + jj * 32 + (lane & 31), 2 * ks + (lane >> 5));
+    }
+
+    // Fetch cursor: step fr of the pass (fd1, fkt) of length fL, and the
+    // addresses of its tiles.  Step r of a pass copies A_p, p = d1 - 1 - r,
+    // and B_{r+1}; the slice tile (digit p, k-tile kt) of rows m0.. is the
+    // contiguous block at DA + ((p-1) nkt + kt) Mp 64 + m0 64.  Padding steps
+    // re-copy the last real tiles, and past the last pass the cursor starts
+    // over, so every step issues the same number of copies (all in bounds).
+    int fd1 = min(G + 1, last_d), fr = 0, fkt = 0;
+    int fL = pass_len(fd1, U);
+    const int8_t* fa = A0 + (int64_t)(fd1 - 2) * sliceA;
+    const int8_t* fb = B0;
+    auto fnext = [&]() __attribute__((always_inline)) {
+        if (++fr < fL) {
+            if (fr <= fd1 - 2) {
+                fa -= sliceA;
+                fb += sliceB;
+            }
+            return;
+        }
+        fr = 0;
+        if (++fkt == nkt) {
+            fkt = 0;
+            fd1 = (fd1 == last_d) ? min(G + 1, last_d) : min(fd1 + G, last_d);
+            fL = pass_len(fd1, U);
+        }
+        fa = A0 + (int64_t)(fd1 - 2) * sliceA + (int64_t)fkt * ktA;
+        fb = B0 + (int64_t)fkt * ktB;
     };
-    auto sstore = [&](const v4i (&ra)[T::A_PER_T], const v4i (&rb)[T::B_PER_T], int slot) {
+    auto issue = [&](auto rslot) __attribute__((always_inline)) {   // copy into ring slot R
+        constexpr int R = decltype(rslot)::value;
+        int8_t* la = lds + R * T::STAGE + wave_lds;
 #pragma unroll
-        for (int h = 0; h < T::A_PER_T; ++h) {
-            const int c = t + 256 * h;
-            *(v4i*)(&As[slot * T::A_SLOT + (c / T::CPR) * T::ROW + (c % T::CPR) * 16]) = ra[h];
-        }
+        for (int h = 0; h < T::A_LOADS; ++h)
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(fa + gofs[h]),
+                                             (__attribute__((address_space(3))) void*)(la + 4096 * h), 16, 0, 0);
 #pragma unroll
-        for (int h = 0; h < T::B_PER_T; ++h) {
-            const int c = t + 256 * h;
-            *(v4i*)(&Bs[slot * T::B_SLOT + (c / T::CPR) * T::ROW + (c % T::CPR) * 16]) = rb[h];
-        }
+        for (int h = 0; h < T::B_LOADS; ++h)
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(fb + gofs[h]),
+                                             (__attribute__((address_space(3))) void*)(la + T::A_BYTES + 4096 * h),
+                                             16, 0, 0);
+        fnext();
     };
 
     v16i acc[G][T::FM][T::FN];
@@ -300,95 +365,90 @@ __global__ __launch_bounds__(256, 1) void diag_mfma_kernel(const int8_t* __restr
             for (int jj = 0; jj < T::FN; ++jj) acc[j][i][jj] = v16i{0};
     v4i wb[G][T::KS][T::FN];   // B fragments of the last G steps, slot = step % G
 
-    int cd0 = 2, cd1 = min(2 + G - 1, last_d), cp = cd1 - 1;
-    int64_t ckt = 0;
-    int fd0 = cd0, fd1 = cd1, fp = cp;
-    int64_t fkt = ckt;
-    gload(ra0, rb0, cp, cd1 - cp, ckt);
-    sstore(ra0, rb0, 0);
-    bool f_valid = advance(fd0, fd1, fkt, fp);
-    gload(ra1, rb1, fp, fd1 - fp, fkt);
-    __syncthreads();
+    // prologue: steps 0 .. D-2 into ring slots 0 .. D-2 (a pass has >= D steps)
+    static_for<D - 1>([&](auto r) __attribute__((always_inline)) { issue(r); });
 
-    // one pipeline iteration for step = base + SLOT: prefetch step + 2,
-    // compute step, move step + 1 into LDS.  Returns true after the last step.
-    auto iteration = [&](auto slot_c, int64_t base) -> bool {
-        constexpr int SLOT = decltype(slot_c)::value;
-        constexpr int SET = SLOT & 1;           // == step % 2 (U is even)
-        constexpr int W = SLOT % G;             // == step % G (U is a multiple of G)
-        auto& raL = SET ? ra1 : ra0;
-        auto& rbL = SET ? rb1 : rb0;
-        auto& raS = SET ? ra0 : ra1;
-        auto& rbS = SET ? rb0 : rb1;
-        int nd0 = fd0, nd1 = fd1, np = fp;
-        int64_t nkt2 = fkt;
-        const bool n_valid = f_valid && advance(nd0, nd1, nkt2, np);
-        gload(raL, rbL, np, nd1 - np, nkt2);
+    // compute cursor: pass (cd0, cd1, ckt) of length cL, block start r0
+    int cd0 = 2, cd1 = min(G + 1, last_d), ckt = 0;
+    int cL = pass_len(cd1, U);
+    for (;;) {
+        const int gsz = cd1 - cd0 + 1;
+        for (int r0 = 0; r0 < cL; r0 += U) {
+            static_for<U>([&](auto rrc) __attribute__((always_inline)) {
+                constexpr int rr = decltype(rrc)::value;
+                constexpr int W = rr % G, R = rr % D, RF = (rr + D - 1) % D;
+                // this step's tiles are in; every wave is past the previous
+                // step, whose ring slot RF is refilled now
+                wait_vm_barrier<T::PER_STEP * (D - 2)>();
+                issue(std::integral_constant<int, RF>{});
 
-        v4i fa[T::KS][T::FM];
+                const int8_t* st = lds + R * T::STAGE;
+                v4i fa_[T::KS][T::FM];
 #pragma unroll
-        for (int ks = 0; ks < T::KS; ++ks) {
+                for (int ks = 0; ks < T::KS; ++ks) {
 #pragma unroll
-            for (int i = 0; i < T::FM; ++i)
-                fa[ks][i] = *(const v4i*)(&As[SET * T::A_SLOT + (arow + i * 32) * T::ROW + ks * 32 + kb]);
+                    for (int i = 0; i < T::FM; ++i) fa_[ks][i] = *(const v4i*)(st + aofs[ks][i]);
 #pragma unroll
-            for (int jj = 0; jj < T::FN; ++jj)
-                wb[W][ks][jj] = *(const v4i*)(&Bs[SET * T::B_SLOT + (brow + jj * 32) * T::ROW + ks * 32 + kb]);
+                    for (int jj = 0; jj < T::FN; ++jj) wb[W][ks][jj] = *(const v4i*)(st + bofs[ks][jj]);
+                }
+                // step r: pairs (p, r + 1 - j), j < nv, with p = d1 - 1 - r;
+                // pair j uses the B fragments of j steps earlier and adds to
+                // S_{d1 - j}; padding steps (p < 1) have none
+                const int r = r0 + rr;
+                const int nv = (r <= cd1 - 2) ? min(gsz, r + 1) : 0;
+#pragma unroll
+                for (int j = 0; j < G; ++j) {
+                    if (j < nv) {
+#pragma unroll
+                        for (int ks = 0; ks < T::KS; ++ks)
+#pragma unroll
+                            for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+                                for (int jj = 0; jj < T::FN; ++jj)
+                                    acc[j][i][jj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                                        fa_[ks][i], wb[(W - j + G) % G][ks][jj], acc[j][i][jj], 0, 0, 0);
+                    }
+                }
+            });
         }
-        // pairs (cp, cd1 - cp - j): valid while j <= d1 - d0 and q >= 1
-        const int nv = min(cd1 - cd0 + 1, cd1 - cp);
-#pragma unroll
-        for (int j = 0; j < G; ++j) {
-            if (j < nv) {
-#pragma unroll
-                for (int ks = 0; ks < T::KS; ++ks)
-#pragma unroll
-                    for (int i = 0; i < T::FM; ++i)
-#pragma unroll
-                        for (int jj = 0; jj < T::FN; ++jj)
-                            acc[j][i][jj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                                fa[ks][i], wb[(W - j + G) % G][ks][jj], acc[j][i][jj], 0, 0, 0);
-            }
-        }
+        if (++ckt < nkt) continue;
 
         // end of a group: write S_d for its diagonals, clear the accumulators
-        if (cp == 1 && ckt == nkt - 1) {
 #pragma unroll
-            for (int j = 0; j < G; ++j) {
-                if (cd1 - j >= cd0) {
-                    int32_t* Sd = S + (int64_t)(cd1 - j - 2) * Np * Mp;
+        for (int j = 0; j < G; ++j) {
+            if (j < gsz) {
+                int32_t* Sd = S + (int64_t)(cd1 - j - 2) * Np * Mp;
 #pragma unroll
-                    for (int i = 0; i < T::FM; ++i)
+                for (int i = 0; i < T::FM; ++i)
 #pragma unroll
-                        for (int jj = 0; jj < T::FN; ++jj) {
-                            const int64_t col = n0 + wn * T::WN + jj * 32 + (lane & 31);
-                            const int64_t rowb = m0 + wm * T::WM + i * 32 + 4 * (lane >> 5);
+                    for (int jj = 0; jj < T::FN; ++jj) {
+                        const int64_t col = n0 + wn * T::WN + jj * 32 + (lane & 31);
+                        const int64_t rowb = m0 + wm * T::WM + i * 32 + 4 * (lane >> 5);
 #pragma unroll
-                            for (int v4 = 0; v4 < 4; ++v4) {
-                                v4i o = {acc[j][i][jj][4 * v4 + 0], acc[j][i][jj][4 * v4 + 1],
-                                         acc[j][i][jj][4 * v4 + 2], acc[j][i][jj][4 * v4 + 3]};
-                                *(v4i*)(Sd + col * Mp + rowb + 8 * v4) = o;
-                            }
-                            acc[j][i][jj] = v16i{0};
+                        for (int v4 = 0; v4 < 4; ++v4) {
+                            v4i o = {acc[j][i][jj][4 * v4 + 0], acc[j][i][jj][4 * v4 + 1],
+                                     acc[j][i][jj][4 * v4 + 2], acc[j][i][jj][4 * v4 + 3]};
+                            *(v4i*)(Sd + col * Mp + rowb + 8 * v4) = o;
                         }
-                }
+                    }
             }
+#pragma unroll
+            for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+                for (int jj = 0; jj < T::FN; ++jj) acc[j][i][jj] = v16i{0};
         }
-
-        if (!f_valid) return true;
-        sstore(raS, rbS, SET ^ 1);
-        __syncthreads();
-        cd0 = fd0; cd1 = fd1; cp = fp; ckt = fkt;
-        fd0 = nd0; fd1 = nd1; fp = np; fkt = nkt2; f_valid = n_valid;
-        (void)base;
-        return false;
-    };
-
-    for (int64_t base = 0;; base += T::U) {
-        if (diag_unrolled([&](auto sc) { return iteration(sc, base); },
-                          std::make_integer_sequence<int, T::U>{}))
-            break;
+        // the stores share the vector-memory counter with the copies: drain
+        // it so the counts in the waits stay exact
+        wait_vm_all();
+        if (cd1 == last_d) break;
+        cd0 = cd1 + 1;
+        cd1 = min(cd0 + G - 1, last_d);
+        cL = pass_len(cd1, U);
+        ckt = 0;
     }
+    // the copies run ahead of the last step: let them land before the
+    // workgroup's LDS is released
+    wait_vm_all();
 }
 
 // ---------------------------------------------------------------------------
@@ -471,14 +531,15 @@ static int launch_diag(int cfg, const int8_t* DA, const int8_t* DB, int32_t* S, 
     const SplitConfig c = kSplit[cfg];
     const int64_t grid = xcd_grid((Mp / c.bm) * (Np / c.bn));
     if (grid > 0x7fffffffLL) return (int)hipErrorInvalidConfiguration;
-#define MPG_DIAG(BM, BN, G)                                                                   \
-    hipLaunchKernelGGL((diag_mfma_kernel<BM, BN, G>), dim3((unsigned)grid), dim3(256), 0, st, DA, DB, \
+#define MPG_DIAG(BM, BN, G, D)                                                                   \
+    hipLaunchKernelGGL((diag_mfma_kernel<BM, BN, G, D>), dim3((unsigned)grid), dim3(256), 0, st, DA, DB, \
                        S, Mp, Np, Kp, s)
+    // ring depths: at most 64 KiB of LDS per workgroup, so two fit on a CU
     switch (cfg) {
-    case 0: MPG_DIAG(128, 128, 4); break;
-    case 1: MPG_DIAG(64, 64, 8); break;
-    case 2: MPG_DIAG(128, 128, 2); break;
-    default: MPG_DIAG(64, 64, 4); break;
+    case 0: MPG_DIAG(128, 128, 2, 4); break;
+    case 1: MPG_DIAG(64, 64, 8, 8); break;
+    case 2: MPG_DIAG(128, 64, 4, 4); break;
+    default: MPG_DIAG(64, 64, 4, 4); break;
     }
 #undef MPG_DIAG
     return (int)hipGetLastError();

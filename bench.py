@@ -100,6 +100,11 @@ def parse():
     return ap.parse_args()
 
 
+def note(*a):
+    """Progress line on stderr (the JSON result goes to stdout)."""
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -148,6 +153,7 @@ def main():
             d["s"] = mp.DEFAULT_SLICES[P]
             d["ws"] = mp.alloc_workspace(P, n, n, n, d["s"], device=dev)
         devd[P] = d
+        note("inputs ready", NAME[P])
     torch.cuda.synchronize()
 
     # batched sets (config 5's shape mix): DD and TD, 512 problems each
@@ -165,6 +171,7 @@ def main():
             plan = mp.BatchPlan(P, dp, stream=stream)
             work = sum(2.0 * q["m"] * q["n"] * q["k"] for q in dp)
             batched[P] = {"plan": plan, "probs": dp, "work": work, "host": hp}
+            note("batched plan ready", NAME[P])
         torch.cuda.synchronize()
 
     def run(P, f):
@@ -194,6 +201,7 @@ def main():
                 r = chk.ratios(got, ents)
                 errors[(P, f)] = float(r.max())
                 devd[P]["C_" + f].copy_(devd[P]["C0"])
+                note("checked", NAME[P], f, "max err ratio", errors[(P, f)])
         torch.cuda.synchronize()
 
     # ---- warmup + timed steps; per-part events on the launch stream ----
@@ -204,6 +212,7 @@ def main():
         for P, f in order:
             run(P, f)
     torch.cuda.synchronize()
+    note("warmup done")
     ev = {key: [] for key in order}
     t0 = time.perf_counter()
     start_all = torch.cuda.Event(enable_timing=True)
@@ -220,6 +229,7 @@ def main():
     end_all.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    note("timed steps done", round(wall, 2), "s")
     total_ms = start_all.elapsed_time(end_all)
     ms_per_step = total_ms / args.steps
     work_per_step = sum(part_work.values())
@@ -292,6 +302,7 @@ def main():
 
     # ---- CPU oracle on this host's cores (bounded sample) ----
     if not args.no_cpu:
+        note("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(host, precs, forms, n, devd, args.cpu_budget, batched)
 
     print(json.dumps(out), flush=True)
@@ -333,12 +344,14 @@ def other_config(args, mp, synth, dev, stream):
     one, zero = synth.mp_one(P), np.zeros(P)
     dA = torch.from_numpy(A).to(dev)
     dB = torch.from_numpy(B).to(dev)
+    note("inputs ready", NAME[P], n)
     forms = args.forms.split(",")
     if cfg == 3:
         # "same error": the smallest s whose result on a block of rows stays
         # within 1e-6 k u (|A||B|)_ij of the plain (canonical) result
         s, rule_ratio = mp.tune_slices(P, "N", "N", n, n, n, dA, dB, target=SAME_ERROR_TARGET,
                                        smin=28, smax=40, stream=stream)
+        note("slice rule", s, rule_ratio)
     else:
         s, rule_ratio = mp.DEFAULT_SLICES[P], None
     ws = mp.alloc_workspace(P, n, n, n, s, device=dev) if "split" in forms else None
@@ -363,6 +376,7 @@ def other_config(args, mp, synth, dev, stream):
             torch.cuda.synchronize()
             times.append(e0.elapsed_time(e1))
         ms = float(np.median(times))
+        note("timed", f, round(ms, 3), "ms")
         item = {"ms": round(ms, 3), "2mnk/s": 2.0 * n ** 3 / (ms * 1e-3)}
         if f == "split":
             item["slices"] = s
@@ -373,6 +387,7 @@ def other_config(args, mp, synth, dev, stream):
             r = chk.ratios(dC.cpu().numpy(), ents)
             item["err_ratio_max"] = float(r.max())
             item["err_ratio_median"] = float(np.median(r))
+            note("checked", f, item["err_ratio_max"])
         parts[f"{NAME[P]}_{f}"] = item
     total_ms = sum(v["ms"] for v in parts.values())
     workload = ("QD GEMM m=n=k=2048, entries u*2^e, e ~ U{-30..30} per entry, both forms, slices "

@@ -34,16 +34,19 @@ METRIC = "DD/TD/QD GEMM 2mnk/s, % FP64 peak; Ozaki-MFMA vs plain EFT at same err
 FP64_PEAK = 78.6e12            # MI355X FP64 vector, FLOP/s (FMA = 2)
 FP64_ISSUE = 256 * 64 * 2.4e9  # FP64 lane-instructions per second (256 CU x 64 lanes x 2.4 GHz)
 INT8_PEAK = 5.0e15             # MI355X dense INT8 MFMA, OP/s
-# FP64 operations per multiply-add as the algorithms execute them (MUL + ADD,
-# common branch of Renorm/VSEB):
-#   DD: Algorithm 2 (9 ops, 1 of them an FMA) + Algorithm 1 (11)              -> 20 ops, 21 flops
-#   TD: Algorithm 4 (47 ops, 6 FMA) + TDaddq = Algorithm 5 on (x0,x1,x2,0) and
-#       (y0,y1,y2,0) (82 ops, of which the 6 on the all-zero fourth lane
-#       fold to constants)                                                 -> 123 ops, 129 flops
-#   QD: Algorithm 6 (121 ops, 6 FMA) + Algorithm 5 (82: 4 lane TwoSums 24,
-#       TwoSum 6, ThreeSum 18, ThreeSum2 13, 2 adds, Renorm 19)           -> 203 ops, 209 flops
-INSTR_PER_MAC = {2: 20, 3: 123, 4: 203}
-FLOPS_PER_MAC = {2: 21, 3: 129, 4: 209}
+# FP64 arithmetic per multiply-add (MUL_P + ADD_P, common Renorm/VSEB branch)
+# as the plain kernels execute it, counted by the hardware
+# (SQ_INSTS_VALU_{ADD,MUL,FMA}_F64 x 64 / n^3 at n = 4096):
+#   DD: Algorithms 2 + 1:                    16 add, 3 mul, 1 FMA ->  20 ops,  21 flops
+#   TD: Algorithm 4 + TDaddq (Algorithm 5 on zero fourth components, whose
+#       all-constant operations fold):     109 add, 3 mul, 6 FMA -> 118 ops, 124 flops
+#   QD: Algorithms 6 + 5:                   184 add, 10 mul, 6 FMA -> 200 ops, 206 flops
+# The kernels issue a few more vector instructions per multiply-add than that
+# (compares and selects of the Renorm/VSEB test, LDS address arithmetic):
+# 21.2 (DD), 128.0 (TD), 210.6 (QD) in all; VALU_PER_MAC gives the issue-slot use.
+INSTR_PER_MAC = {2: 20, 3: 118, 4: 200}
+FLOPS_PER_MAC = {2: 21, 3: 124, 4: 206}
+VALU_PER_MAC = {2: 21.2, 3: 128.0, 4: 210.6}
 NAME = {2: "DD", 3: "TD", 4: "QD"}
 PAPER_CONTEXT = {
     "note": "paper's CPU seconds for C := AB, n = 4096 (AVX2 + OpenMP); other hardware, context only",
@@ -249,6 +252,7 @@ def main():
         elif f == "plain":
             item["fp64_peak_frac"] = n ** 3 * FLOPS_PER_MAC[P] / (ms * 1e-3) / FP64_PEAK
             item["fp64_issue_frac"] = n ** 3 * INSTR_PER_MAC[P] / (ms * 1e-3) / FP64_ISSUE
+            item["valu_issue_frac"] = n ** 3 * VALU_PER_MAC[P] / (ms * 1e-3) / FP64_ISSUE
         else:
             s = devd[P]["s"]
             item["slices"] = s
@@ -266,9 +270,10 @@ def main():
         flops = n ** 3 * FLOPS_PER_MAC[dom_P]
         achieved = flops / (ms * 1e-3) / 1e12
         # The EFT chains are almost all separate adds and multiplies (QD: 6 of
-        # 203 operations per multiply-add are FMAs), so the bound is the FP64
+        # 200 operations per multiply-add are FMAs), so the bound is the FP64
         # operation issue rate, 256 CU x 64 lanes x 2.4 GHz = 39.3 T op/s; the
-        # FMA-counted 78.6 TFLOP/s figure is reported beside it.
+        # FMA-counted 78.6 TFLOP/s figure is reported beside it, and so is the
+        # fraction of vector issue slots used by all the kernel's instructions.
         ops = n ** 3 * INSTR_PER_MAC[dom_P]
         achieved_ops = ops / (ms * 1e-3) / 1e12
         roofline = {"bound": "alu", "kernel": f"plain_gemm_kernel<{dom_P},...> ({NAME[dom_P]}, n={n})",
@@ -278,10 +283,27 @@ def main():
                     "flops_per_launch": flops, "achieved_tflops": round(achieved, 3),
                     "fp64_tflops_peak": FP64_PEAK / 1e12,
                     "flops_frac": round(achieved * 1e12 / FP64_PEAK, 4),
+                    "valu_issue_frac": round(n ** 3 * VALU_PER_MAC[dom_P] / (ms * 1e-3) / FP64_ISSUE, 4),
                     "traffic": read_traffic() if (dom_P == 4 and n == 4096) else None}
 
     for P in batched:
         batched[P]["plan"].close()
+
+    # ---- measured peaks of this GPU (after the timed region), and the parts'
+    # fractions of them beside the fractions of the published figures ----
+    peaks = measured_peaks(mp, stream)
+    note("measured peaks", peaks)
+    for key, item in breakdown.items():
+        P = PREC_OF[key.split("_")[0]]
+        ms = item["ms"]
+        if key.endswith("_plain"):
+            item["fp64_issue_frac_measured"] = n ** 3 * INSTR_PER_MAC[P] / (ms * 1e-3) / peaks["fp64_add_op_s"]
+        elif key.endswith("_split"):
+            s_ = item["slices"]
+            item["int8_ops_frac_measured"] = s_ * (s_ + 1) / 2 * 2.0 * n ** 3 / (ms * 1e-3) / peaks["int8_mfma_op_s"]
+    if roofline is not None:
+        roofline["peak_measured"] = round(peaks["fp64_add_op_s"] / 1e12, 2)
+        roofline["frac_of_measured"] = round(roofline["achieved"] * 1e12 / peaks["fp64_add_op_s"], 4)
 
     out = {
         "metric": METRIC, "value": value, "unit": "2mnk/s", "n_gpus": 1, "steps": args.steps,
@@ -296,6 +318,7 @@ def main():
                    "parts_per_step": len(order), "parallelism": "single GPU"},
         "breakdown": breakdown,
         "roofline": roofline,
+        "measured_peaks": peaks,
         "wall_s_timed": round(wall, 3),
         "paper_context": PAPER_CONTEXT,
     }
@@ -306,6 +329,20 @@ def main():
         out["cpu_baseline"] = cpu_baseline(host, precs, forms, n, devd, args.cpu_budget, batched)
 
     print(json.dumps(out), flush=True)
+
+
+PREC_OF = {"DD": 2, "TD": 3, "QD": 4}
+
+
+def measured_peaks(mp, stream):
+    """FP64 and INT8 matrix-core throughput measured on this GPU by the
+    library's probes (independent FMA / add / multiply chains per thread;
+    back-to-back 32x32x32 INT8 MFMAs per wave), a few milliseconds each."""
+    return {"fp64_fma_flop_s": mp.probe_peak("fp64_fma", stream),
+            "fp64_add_op_s": mp.probe_peak("fp64_add", stream),
+            "fp64_mul_op_s": mp.probe_peak("fp64_mul", stream),
+            "int8_mfma_op_s": mp.probe_peak("int8_mfma", stream),
+            "published": {"fp64_fma_flop_s": FP64_PEAK, "fp64_op_s": FP64_ISSUE, "int8_op_s": INT8_PEAK}}
 
 
 def separate_launches(mp, P, b, stream):
@@ -457,10 +494,30 @@ def cpu_baseline(host, precs, forms, n, devd, budget, batched):
             total_work += 2.0 * n ** 3
             parts.append(f"{NAME[P]}-{f}: {rows}x{cols} block ({rate:.3g} 2mnk/s)")
     value = total_work / est_total
+    # one thread, for scale: the plain DD part on a 1 x 256 block
+    P1 = min(precs)
+    A, B, C, alpha, beta = host[P1]
+    t = time.perf_counter()
+    oracle.gemm(P1, "N", "N", n, n, n, alpha, A, B, beta, C, rows=(0, 1), cols=(0, 256), nthreads=1)
+    one_thread = 2.0 * 256 * n / (time.perf_counter() - t)
     return {"value": value, "unit": "2mnk/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "one_thread": {"value": one_thread, "unit": "2mnk/s",
+                           "sample": f"{NAME[P1]} plain, 1 x 256 block of C, k = {n}"},
             "sample": "per large GEMM of the step a block of rows x columns of C (all k), per "
                       "batched set its first problems, each timed and extrapolated to the part's "
                       "full 2mnk: " + "; ".join(parts)}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 if __name__ == "__main__":

@@ -269,6 +269,22 @@ int mpgemm_split_stages(int prec, int last, char transa, char transb, int64_t m,
                         int64_t b_plane_stride, const double* beta, double* C, int64_t ldc,
                         int64_t c_plane_stride, hipStream_t stream, const mpgemm_opts* opts);
 
+/*
+ * Measure a throughput peak of the GPU that `stream` runs on, as the figure
+ * the GEMM kernels are compared with (not a hot-path call):
+ *   which = 0: FP64 FMA, in flops/s (2 per FMA);
+ *   which = 1: FP64 add, in operations/s;
+ *   which = 2: FP64 multiply, in operations/s;
+ *   which = 3: INT8 matrix cores (v_mfma_i32_32x32x32_i8), in operations/s
+ *              (2 per multiply-add).
+ * Each thread (FP64) or wave (MFMA) runs independent chains over 4096
+ * workgroups of 256 threads for a few milliseconds; *rate is the best of three
+ * timed launches after one warm-up.  Allocates and frees a 8 MiB scratch
+ * buffer; synchronises on the stream.  Returns -1 for a bad `which`, -3 for a
+ * NULL `rate`, MPGEMM_ERR_NOMEM or MPGEMM_ERR_HIP on failure.
+ */
+int mpgemm_probe_peak(int which, hipStream_t stream, double* rate);
+
 /* Message for an error code; never NULL. */
 const char* mpgemm_strerror(int code);
 /* Library version string. */

@@ -62,6 +62,7 @@ EXPORTS = {
     "mpgemm_split_layout": ([_int, _i64, _i64, _i64, _int, _int, _P(_sz), _P(_sz), _P(_sz),
                              _P(_sz), _P(_sz), _P(_i64), _P(_i64), _P(_i64)], _int),
     "mpgemm_split_stages": ([_int, _int] + _GEMM_ARGS + [_P(Opts)], _int),
+    "mpgemm_probe_peak": ([_int, _vp, _P(_dbl)], _int),
     "mpgemm_strerror": ([_int], C.c_char_p),
     "mpgemm_version": ([], C.c_char_p),
     "mpgemm_finalize": ([], None),

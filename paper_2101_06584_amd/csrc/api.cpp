@@ -28,6 +28,7 @@ int launch_fill(int P, double* X, int64_t plane, int64_t planes_stride, uint64_t
 int launch_absdot(const GemmArgs& g, double* out, hipStream_t st);
 int launch_diff_ratio(int P, int64_t m, int64_t n, const double* Cs, const double* Cr, int64_t ld,
                       int64_t ps, const double* absab, double scale, double* out, hipStream_t st);
+int launch_probe(int which, double* out, int blocks, int iters, double* ops, hipStream_t st);
 }  // namespace mpg
 
 using namespace mpg;
@@ -687,6 +688,39 @@ const char* mpgemm_version(void) { return "mpgemm 0.1.0 gfx950"; }
 void mpgemm_finalize(void) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune.clear();
+}
+
+int mpgemm_probe_peak(int which, hipStream_t st, double* rate) {
+    if (which < 0 || which > 3) return -1;
+    if (!rate) return -3;
+    // 4096 workgroups (16 per CU); iterations sized for a few milliseconds
+    const int blocks = 4096;
+    const int iters = which == 3 ? 4096 : 16384;
+    double* out = nullptr;
+    if (hipMalloc((void**)&out, sizeof(double) * blocks * 256) != hipSuccess) return MPGEMM_ERR_NOMEM;
+    hipEvent_t e0, e1;
+    int rc = 0;
+    if (hipEventCreate(&e0) != hipSuccess) rc = MPGEMM_ERR_HIP;
+    if (!rc && hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); rc = MPGEMM_ERR_HIP; }
+    double ops = 0.0;
+    float best = 1e30f;
+    if (!rc) {
+        for (int rep = 0; rep < 4 && !rc; ++rep) {      // first run warms up
+            (void)hipEventRecord(e0, st);
+            rc = launch_probe(which, out, blocks, iters, &ops, st) ? MPGEMM_ERR_HIP : 0;
+            (void)hipEventRecord(e1, st);
+            if (hipEventSynchronize(e1) != hipSuccess) rc = MPGEMM_ERR_HIP;
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (rep > 0) best = std::min(best, ms);
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    (void)hipFree(out);
+    if (rc) return rc;
+    *rate = ops / (best * 1e-3);
+    return 0;
 }
 
 }  // extern "C"

@@ -1,7 +1,8 @@
 // tune_kernels.hip -- small kernels used only by the autotuner and by the
 // slice-count rule: a deterministic operand fill, |op(A)||op(B)| on the
 // leading components, and the per-entry error ratio of two P-component
-// results.
+// results; and the throughput probes that measure the FP64 vector and INT8
+// matrix-core peaks the GEMM kernels are compared with.
 #pragma clang fp contract(off)
 
 #include "internal.hpp"
@@ -91,6 +92,83 @@ int launch_diff_ratio(int P, int64_t m, int64_t n, const double* Cs, const doubl
     if (P == 2) hipLaunchKernelGGL(diff_ratio_kernel<2>, gr, bl, 0, st, m, n, Cs, Cr, ld, ps, absab, scale, out);
     else if (P == 3) hipLaunchKernelGGL(diff_ratio_kernel<3>, gr, bl, 0, st, m, n, Cs, Cr, ld, ps, absab, scale, out);
     else hipLaunchKernelGGL(diff_ratio_kernel<4>, gr, bl, 0, st, m, n, Cs, Cr, ld, ps, absab, scale, out);
+    return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Peak probes.  Each thread (FP64) or wave (MFMA) runs 8 or 4 independent
+// chains so that issue, not latency, limits the rate; the results are summed
+// into out[] only to keep the chains alive.
+// ---------------------------------------------------------------------------
+
+// OP 0: fma(x, b, c); 1: x + c; 2: x * b.  Values stay near 1 (no overflow,
+// no subnormals).
+template <int OP>
+__global__ __launch_bounds__(256) void probe_fp64_kernel(double* out, int iters, double b, double c) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double x[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) x[i] = 1.0 + 1e-3 * (double)((id + i) & 1023);
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            if (OP == 0) x[i] = __builtin_fma(x[i], b, c);
+            else if (OP == 1) x[i] = x[i] + c;
+            else x[i] = x[i] * b;
+        }
+        c = -c;      // keeps the add chains bounded
+    }
+    double sum = 0.0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) sum = sum + x[i];
+    out[id] = sum;
+}
+
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+typedef int v16i_t __attribute__((ext_vector_type(16)));
+
+__global__ __launch_bounds__(256) void probe_mfma_i8_kernel(double* out, int iters) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // non-zero bytes in both operands (the matrix cores do the full work)
+    const int l = (int)threadIdx.x;
+    const v4i_t a = {0x11223344 ^ l, 0x55667788 ^ (l << 8), 0x0f1e2d3c ^ (l << 16), 0x4b5a6978 ^ l};
+    const v4i_t b = {0x13579bdf ^ (l << 4), 0x2468ace0 ^ l, 0x7f6e5d4c ^ (l << 12), 0x3b2a1908 ^ (l << 20)};
+    v16i_t acc0 = v16i_t{0}, acc1 = v16i_t{0}, acc2 = v16i_t{0}, acc3 = v16i_t{0};
+    for (int it = 0; it < iters; ++it) {
+        acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(b, a, acc1, 0, 0, 0);
+        acc2 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, a, acc2, 0, 0, 0);
+        acc3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(b, b, acc3, 0, 0, 0);
+    }
+    double sum = 0.0;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) sum = sum + (double)(acc0[v] ^ acc1[v] ^ acc2[v] ^ acc3[v]);
+    out[id] = sum;
+}
+
+// Launches probe `which` (0 FP64 FMA, 1 FP64 add, 2 FP64 mul, 3 INT8 MFMA
+// 32x32x32) over `blocks` x 256 threads into out[blocks * 256]; *ops is the
+// work of one launch (flops for FMA: 2 per FMA; operations otherwise).
+int launch_probe(int which, double* out, int blocks, int iters, double* ops, hipStream_t st) {
+    const double threads = (double)blocks * 256.0;
+    switch (which) {
+    case 0:
+        hipLaunchKernelGGL(probe_fp64_kernel<0>, dim3(blocks), dim3(256), 0, st, out, iters, 0.999999, 1e-3);
+        *ops = threads * iters * 8.0 * 2.0;
+        break;
+    case 1:
+        hipLaunchKernelGGL(probe_fp64_kernel<1>, dim3(blocks), dim3(256), 0, st, out, iters, 0.999999, 1e-3);
+        *ops = threads * iters * 8.0;
+        break;
+    case 2:
+        hipLaunchKernelGGL(probe_fp64_kernel<2>, dim3(blocks), dim3(256), 0, st, out, iters, 0.999999, 1e-3);
+        *ops = threads * iters * 8.0;
+        break;
+    default:
+        hipLaunchKernelGGL(probe_mfma_i8_kernel, dim3(blocks), dim3(256), 0, st, out, iters);
+        *ops = threads / 64.0 * iters * 4.0 * (32.0 * 32.0 * 32.0 * 2.0);
+        break;
+    }
     return (int)hipGetLastError();
 }
 

@@ -34,6 +34,7 @@ METRIC = "DD/TD/QD GEMM 2mnk/s, % FP64 peak; Ozaki-MFMA vs plain EFT at same err
 FP64_PEAK = 78.6e12            # MI355X FP64 vector, FLOP/s (FMA = 2)
 FP64_ISSUE = 256 * 64 * 2.4e9  # FP64 lane-instructions per second (256 CU x 64 lanes x 2.4 GHz)
 INT8_PEAK = 5.0e15             # MI355X dense INT8 MFMA, OP/s
+HBM_PEAK = 8.0e12              # MI355X HBM3E, bytes/s
 # FP64 arithmetic per multiply-add (MUL_P + ADD_P, common Renorm/VSEB branch)
 # as the plain kernels execute it, counted by the hardware
 # (SQ_INSTS_VALU_{ADD,MUL,FMA}_F64 x 64 / n^3 at n = 4096):
@@ -100,6 +101,9 @@ def parse():
                     help="run a plain device copy of 1 GiB first (counter calibration)")
     ap.add_argument("--no-batched", action="store_true", help="leave the batched sets out")
     ap.add_argument("--config", type=int, default=0, help="3 or 4: the other workloads")
+    ap.add_argument("--vec", action="store_true",
+                    help="element-wise DD/TD/QD add and mul (Sec. 2.5) against the HBM roofline")
+    ap.add_argument("--vec-n", type=int, default=1 << 26, help="vector length for --vec")
     return ap.parse_args()
 
 
@@ -134,6 +138,8 @@ def main():
         del src, dst
     if args.config in (3, 4):
         return other_config(args, mp, synth, dev, stream)
+    if args.vec:
+        return vec_bench(args, mp, dev, stream)
     n = args.n
     precs = [int(p) for p in args.prec.split(",")]
     forms = args.forms.split(",")
@@ -334,6 +340,68 @@ def main():
 PREC_OF = {"DD": 2, "TD": 3, "QD": 4}
 
 
+def vec_bench(args, mp, dev, stream):
+    """Element-wise r = x + y and r = x * y on n-element DD/TD/QD vectors in
+    component planes (Sec. 2.5): reads 2 x 8P bytes and writes 8P bytes per
+    element, so the bound is HBM bandwidth.  One JSON line."""
+    import numpy as np
+    import torch
+    n = args.vec_n
+    parts = {}
+    for P in (2, 3, 4):
+        g = torch.Generator(device=dev).manual_seed(P)
+        x = torch.empty((P, n), dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        for t in (x, y):
+            t[0].uniform_(-1, 1, generator=g)
+            for p in range(1, P):      # each further component below half an ulp of the one before
+                t[p] = t[p - 1] * 2.0 ** -54 * (torch.rand(n, dtype=torch.float64, device=dev,
+                                                           generator=g) * 2 - 1)
+        r = torch.empty_like(x)
+        for op in ("add", "mul"):
+            call = lambda: mp.vec(P, op, x, y, r, stream=stream)  # noqa: E731
+            for _ in range(max(1, args.warmup)):
+                call()
+            torch.cuda.synchronize()
+            times = []
+            for _ in range(max(3, args.steps)):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                call()
+                e1.record(stream)
+                torch.cuda.synchronize()
+                times.append(e0.elapsed_time(e1))
+            ms = float(np.median(times))
+            nbytes = 3.0 * 8 * P * n
+            parts[f"{NAME[P]}_{op}"] = {"ms": round(ms, 4), "GB/s": nbytes / (ms * 1e-3) / 1e9,
+                                        "hbm_frac": nbytes / (ms * 1e-3) / HBM_PEAK,
+                                        "elements/s": n / (ms * 1e-3)}
+            note("vec", NAME[P], op, round(ms, 3), "ms", round(nbytes / (ms * 1e-3) / 1e9, 1), "GB/s")
+        del x, y, r
+        torch.cuda.empty_cache()
+    copy_rate = mp.probe_peak("hbm_copy", stream)
+    note("hbm copy probe", round(copy_rate / 1e9, 1), "GB/s")
+    for v in parts.values():
+        v["hbm_frac_of_copy"] = v["GB/s"] * 1e9 / copy_rate
+    worst = min(parts, key=lambda k: parts[k]["hbm_frac"])
+    total_ms = sum(v["ms"] for v in parts.values())
+    total_bytes = sum(3.0 * 8 * PREC_OF[k.split("_")[0]] * n for k in parts)
+    out = {"metric": "element-wise DD/TD/QD add and mul, bytes/s", "value": total_bytes / (total_ms * 1e-3),
+           "unit": "B/s", "n_gpus": 1, "steps": max(3, args.steps), "warmup": max(1, args.warmup),
+           "ms_per_step": round(total_ms, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"r = x op y, n = {n} elements per vector, DD/TD/QD, add and mul, "
+                                  "component planes", "n": n},
+           "breakdown": parts,
+           "roofline": {"bound": "hbm", "kernel": f"vec_kernel ({worst})",
+                        "achieved": round(parts[worst]["GB/s"], 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                        "frac": round(parts[worst]["hbm_frac"], 4), "traffic": None,
+                        "peak_measured": round(copy_rate / 1e9, 1),
+                        "frac_of_measured": round(parts[worst]["GB/s"] * 1e9 / copy_rate, 4)}}
+    print(json.dumps(out), flush=True)
+
+
 def measured_peaks(mp, stream):
     """FP64 and INT8 matrix-core throughput measured on this GPU by the
     library's probes (independent FMA / add / multiply chains per thread;
@@ -342,7 +410,9 @@ def measured_peaks(mp, stream):
             "fp64_add_op_s": mp.probe_peak("fp64_add", stream),
             "fp64_mul_op_s": mp.probe_peak("fp64_mul", stream),
             "int8_mfma_op_s": mp.probe_peak("int8_mfma", stream),
-            "published": {"fp64_fma_flop_s": FP64_PEAK, "fp64_op_s": FP64_ISSUE, "int8_op_s": INT8_PEAK}}
+            "hbm_copy_byte_s": mp.probe_peak("hbm_copy", stream),
+            "published": {"fp64_fma_flop_s": FP64_PEAK, "fp64_op_s": FP64_ISSUE, "int8_op_s": INT8_PEAK,
+                          "hbm_byte_s": HBM_PEAK}}
 
 
 def separate_launches(mp, P, b, stream):

@@ -276,12 +276,15 @@ int mpgemm_split_stages(int prec, int last, char transa, char transb, int64_t m,
  *   which = 1: FP64 add, in operations/s;
  *   which = 2: FP64 multiply, in operations/s;
  *   which = 3: INT8 matrix cores (v_mfma_i32_32x32x32_i8), in operations/s
- *              (2 per multiply-add).
+ *              (2 per multiply-add);
+ *   which = 4: HBM, a streaming copy of 1 GiB with the element-wise kernels'
+ *              access pattern, in bytes/s (read + written).
  * Each thread (FP64) or wave (MFMA) runs independent chains over 4096
  * workgroups of 256 threads for a few milliseconds; *rate is the best of three
- * timed launches after one warm-up.  Allocates and frees a 8 MiB scratch
- * buffer; synchronises on the stream.  Returns -1 for a bad `which`, -3 for a
- * NULL `rate`, MPGEMM_ERR_NOMEM or MPGEMM_ERR_HIP on failure.
+ * timed launches after one warm-up.  Allocates and frees a scratch buffer
+ * (8 MiB; 2 GiB for the copy); synchronises on the stream.  Returns -1 for a
+ * bad `which`, -3 for a NULL `rate`, MPGEMM_ERR_NOMEM or MPGEMM_ERR_HIP on
+ * failure.
  */
 int mpgemm_probe_peak(int which, hipStream_t stream, double* rate);
 

@@ -266,12 +266,13 @@ def tune_slices(prec, transa, transb, m, n, k, A, B, target=1.0, smin=None, smax
     return s.value, r.value
 
 
-PROBES = {"fp64_fma": 0, "fp64_add": 1, "fp64_mul": 2, "int8_mfma": 3}
+PROBES = {"fp64_fma": 0, "fp64_add": 1, "fp64_mul": 2, "int8_mfma": 3, "hbm_copy": 4}
 
 
 def probe_peak(which, stream=None) -> float:
     """Measured throughput of the GPU: flops/s for "fp64_fma", operations/s for
-    "fp64_add", "fp64_mul" and "int8_mfma" (mpgemm_probe_peak)."""
+    "fp64_add", "fp64_mul" and "int8_mfma", bytes/s for "hbm_copy"
+    (mpgemm_probe_peak)."""
     r = C.c_double()
     _check(_lib.load().mpgemm_probe_peak(PROBES[which], _stream(stream), C.byref(r)), "mpgemm_probe_peak")
     return r.value

@@ -29,6 +29,7 @@ int launch_absdot(const GemmArgs& g, double* out, hipStream_t st);
 int launch_diff_ratio(int P, int64_t m, int64_t n, const double* Cs, const double* Cr, int64_t ld,
                       int64_t ps, const double* absab, double scale, double* out, hipStream_t st);
 int launch_probe(int which, double* out, int blocks, int iters, double* ops, hipStream_t st);
+int launch_probe_copy(const double* src, double* dst, int64_t n, double* bytes, hipStream_t st);
 }  // namespace mpg
 
 using namespace mpg;
@@ -691,13 +692,16 @@ void mpgemm_finalize(void) {
 }
 
 int mpgemm_probe_peak(int which, hipStream_t st, double* rate) {
-    if (which < 0 || which > 3) return -1;
+    if (which < 0 || which > 4) return -1;
     if (!rate) return -3;
-    // 4096 workgroups (16 per CU); iterations sized for a few milliseconds
+    // 4096 workgroups (16 per CU); iterations sized for a few milliseconds;
+    // the copy moves 1 GiB each way
     const int blocks = 4096;
     const int iters = which == 3 ? 4096 : 16384;
+    const int64_t copy_n = (int64_t)1 << 27;
+    const size_t out_elems = which == 4 ? (size_t)2 * copy_n : (size_t)blocks * 256;
     double* out = nullptr;
-    if (hipMalloc((void**)&out, sizeof(double) * blocks * 256) != hipSuccess) return MPGEMM_ERR_NOMEM;
+    if (hipMalloc((void**)&out, sizeof(double) * out_elems) != hipSuccess) return MPGEMM_ERR_NOMEM;
     hipEvent_t e0, e1;
     int rc = 0;
     if (hipEventCreate(&e0) != hipSuccess) rc = MPGEMM_ERR_HIP;
@@ -707,7 +711,10 @@ int mpgemm_probe_peak(int which, hipStream_t st, double* rate) {
     if (!rc) {
         for (int rep = 0; rep < 4 && !rc; ++rep) {      // first run warms up
             (void)hipEventRecord(e0, st);
-            rc = launch_probe(which, out, blocks, iters, &ops, st) ? MPGEMM_ERR_HIP : 0;
+            rc = (which == 4 ? launch_probe_copy(out, out + copy_n, copy_n, &ops, st)
+                             : launch_probe(which, out, blocks, iters, &ops, st))
+                     ? MPGEMM_ERR_HIP
+                     : 0;
             (void)hipEventRecord(e1, st);
             if (hipEventSynchronize(e1) != hipSuccess) rc = MPGEMM_ERR_HIP;
             float ms = 0.f;

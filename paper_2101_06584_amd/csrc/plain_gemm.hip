@@ -232,17 +232,20 @@ template <int P, int OP>
 __global__ void vec_kernel(int64_t n, const double* __restrict__ x, int64_t sx,
                            const double* __restrict__ y, int64_t sy, double* __restrict__ r,
                            int64_t sr) {
+    // a pure stream: every byte is used once, so loads and stores carry the
+    // non-temporal hint (keeps the caches for other work, and measured a few
+    // percent faster than plain accesses)
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         mp<P> a, b;
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            a.c[p] = x[p * sx + i];
-            b.c[p] = y[p * sy + i];
+            a.c[p] = __builtin_nontemporal_load(x + p * sx + i);
+            b.c[p] = __builtin_nontemporal_load(y + p * sy + i);
         }
         const mp<P> o = OP == 0 ? add(a, b) : mul(a, b);
 #pragma unroll
-        for (int p = 0; p < P; ++p) r[p * sr + i] = o.c[p];
+        for (int p = 0; p < P; ++p) __builtin_nontemporal_store(o.c[p], r + p * sr + i);
     }
 }
 

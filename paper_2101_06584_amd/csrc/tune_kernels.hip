@@ -146,6 +146,21 @@ __global__ __launch_bounds__(256) void probe_mfma_i8_kernel(double* out, int ite
     out[id] = sum;
 }
 
+// Streaming copy dst[i] = src[i], i < n, with the non-temporal hints of the
+// element-wise kernels: the HBM bandwidth such a stream reaches.
+__global__ __launch_bounds__(256) void probe_copy_kernel(const double* __restrict__ src,
+                                                          double* __restrict__ dst, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+int launch_probe_copy(const double* src, double* dst, int64_t n, double* bytes, hipStream_t st) {
+    hipLaunchKernelGGL(probe_copy_kernel, dim3(16384), dim3(256), 0, st, src, dst, n);
+    *bytes = 16.0 * (double)n;
+    return (int)hipGetLastError();
+}
+
 // Launches probe `which` (0 FP64 FMA, 1 FP64 add, 2 FP64 mul, 3 INT8 MFMA
 // 32x32x32) over `blocks` x 256 threads into out[blocks * 256]; *ops is the
 // work of one launch (flops for FMA: 2 per FMA; operations otherwise).

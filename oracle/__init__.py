@@ -27,13 +27,15 @@ def lib():
             _b.build()
         L = C.CDLL(path)
         L.ref_vec.argtypes = [_int, _int, _i64, C.c_void_p, _i64, C.c_void_p, _i64, C.c_void_p, _i64]
-        L.ref_vec.restype = None
+        L.ref_vec.restype = _int
         L.ref_prim.argtypes = [_int, _i64, C.c_void_p, C.c_void_p]
         L.ref_prim.restype = _int
         L.ref_gemm.argtypes = [_int, _ch, _ch, _i64, _i64, _i64, C.c_void_p, C.c_void_p, _i64, _i64,
                                C.c_void_p, _i64, _i64, C.c_void_p, C.c_void_p, _i64, _i64, _i64, _i64,
                                _i64, _i64, _int]
         L.ref_gemm.restype = _int
+        L.ref_gemm_v.argtypes = [_int, _int] + L.ref_gemm.argtypes[1:]
+        L.ref_gemm_v.restype = _int
         L.ref_gemm_split.argtypes = [_int, _int, _ch, _ch, _i64, _i64, _i64, C.c_void_p, C.c_void_p, _i64,
                                      _i64, C.c_void_p, _i64, _i64, C.c_void_p, C.c_void_p, _i64, _i64,
                                      _i64, _i64, _i64, _i64, _int, C.c_void_p, C.c_void_p, C.c_void_p]
@@ -59,7 +61,8 @@ def _f64(a):
 
 PRIM = {"quick_two_sum": (0, 2, 2), "two_sum": (1, 2, 2), "two_prod": (2, 2, 2),
         "three_sum": (3, 3, 3), "three_sum2": (4, 3, 2), "vec_sum4": (5, 4, 4),
-        "vseb2": (6, 3, 2), "renorm4": (7, 5, 4), "vseb3": (8, 6, 3), "vec_sum3": (9, 3, 3)}
+        "vseb2": (6, 3, 2), "renorm4": (7, 5, 4), "vseb3": (8, 6, 3), "vec_sum3": (9, 3, 3),
+        "merge3": (10, 6, 6)}
 
 
 def prim(name: str, *args):
@@ -74,20 +77,26 @@ def prim(name: str, *args):
     return tuple(out[q] for q in range(nout))
 
 
+VEC_OPS = {"add": 0, "mul": 1, "add_acc": 2, "mulq": 3}
+
+
 def vec(P: int, op: str, x: np.ndarray, y: np.ndarray) -> np.ndarray:
-    """Element-wise add/mul of (P, n) arrays."""
+    """Element-wise op of (P, n) arrays: "add", "mul", and for TD "add_acc"
+    (the accurate addition, Algorithm 3) and "mulq" (TDmulq)."""
     x = _f64(x)
     y = _f64(y)
     n = x.shape[1]
     r = np.zeros_like(x)
-    lib().ref_vec(P, 0 if op == "add" else 1, n, _ptr(x), n, _ptr(y), n, _ptr(r), n)
+    rc = lib().ref_vec(P, VEC_OPS[op], n, _ptr(x), n, _ptr(y), n, _ptr(r), n)
+    assert rc == 0, rc
     return r
 
 
-def gemm(P, ta, tb, m, n, k, alpha, A, B, beta, C, rows=None, cols=None, nthreads=0):
+def gemm(P, ta, tb, m, n, k, alpha, A, B, beta, C, rows=None, cols=None, nthreads=0, variant=0):
     """C = alpha op(A) op(B) + beta C in the canonical order; returns a new C.
     A, B, C are (P, cols, ld) component planes; rows=(r0, r1) / cols=(c0, c1)
-    limit the computed block (the rest of C is returned unchanged)."""
+    limit the computed block (the rest of C is returned unchanged).  For TD,
+    variant bit 0 selects the accurate addition (Algorithm 3), bit 1 TDmulq."""
     A = _f64(A)
     B = _f64(B)
     Cout = _f64(C).copy()
@@ -95,10 +104,10 @@ def gemm(P, ta, tb, m, n, k, alpha, A, B, beta, C, rows=None, cols=None, nthread
     beta = _f64(beta)
     r0, r1 = rows if rows is not None else (0, -1)
     c0, c1 = cols if cols is not None else (0, -1)
-    rc = lib().ref_gemm(P, ta.encode(), tb.encode(), m, n, k, _ptr(alpha), _ptr(A), A.shape[2],
-                        A.shape[1] * A.shape[2], _ptr(B), B.shape[2], B.shape[1] * B.shape[2],
-                        _ptr(beta), _ptr(Cout), Cout.shape[2], Cout.shape[1] * Cout.shape[2],
-                        r0, r1, c0, c1, nthreads)
+    rc = lib().ref_gemm_v(P, variant, ta.encode(), tb.encode(), m, n, k, _ptr(alpha), _ptr(A),
+                          A.shape[2], A.shape[1] * A.shape[2], _ptr(B), B.shape[2],
+                          B.shape[1] * B.shape[2], _ptr(beta), _ptr(Cout), Cout.shape[2],
+                          Cout.shape[1] * Cout.shape[2], r0, r1, c0, c1, nthreads)
     assert rc == 0, rc
     return Cout
 

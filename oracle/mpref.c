@@ -302,29 +302,78 @@ static void td_mul(const double *x, const double *y, double *r)
     vseb(&e[1], 3, &r[1], 2);
 }
 
+/* The other TD operations of Sec. 2.3, which the paper measures but does not
+ * adopt for its TD matrix multiplication.
+ *
+ * Merge (first step of Algorithm 3): the six components of x and y in order
+ * of decreasing magnitude, by the two-pointer merge of the two expansions:
+ * take the head of x when its magnitude is at least that of y's head,
+ * otherwise y's head.  On normalised operands (each ordered by decreasing
+ * magnitude) this is the stable sort of (x0, x1, x2, y0, y1, y2) by
+ * decreasing |.|, x before y on equal magnitudes. */
+static void merge_mag(const double *x, int nx, const double *y, int ny, double *z)
+{
+    int i = 0, j = 0;
+    for (int k = 0; k < nx + ny; ++k) {
+        if (j >= ny || (i < nx && fabs(x[i]) >= fabs(y[j])))
+            z[k] = x[i++];
+        else
+            z[k] = y[j++];
+    }
+}
+
+/* Algorithm 3 (the accurate TD addition, TDadd): Merge, VecSum over the six
+ * terms, VSEB(3). */
+static void td_add_acc(const double *x, const double *y, double *r)
+{
+    double z[6], e[6];
+    merge_mag(x, 3, y, 3, z);
+    vec_sum(z, 6, e);
+    vseb(e, 6, r, 3);
+}
+
+/* TDmulq: the QD multiplication applied to (x0, x1, x2, 0) and (y0, y1, y2, 0),
+ * fourth output dropped (the TD product "converted to QDmul" that the paper
+ * tried). */
+static void td_mulq(const double *x, const double *y, double *r)
+{
+    double xq[4] = {x[0], x[1], x[2], 0.0};
+    double yq[4] = {y[0], y[1], y[2], 0.0};
+    double rq[4];
+    qd_mul(xq, yq, rq);
+    r[0] = rq[0];
+    r[1] = rq[1];
+    r[2] = rq[2];
+}
+
 /* ------------------------------------------------------------------------ */
-/* Precision dispatch.                                                      */
+/* Precision dispatch.  `variant` selects the TD operations (P == 3 only):  */
+/* bit 0 the accurate addition (Algorithm 3) instead of TDaddq, bit 1       */
+/* TDmulq instead of Algorithm 4.                                           */
 /* ------------------------------------------------------------------------ */
 
-static void mp_add(int P, const double *x, const double *y, double *r)
+static void mp_add_v(int P, int variant, const double *x, const double *y, double *r)
 {
     if (P == 2)
         dd_add(x, y, r);
     else if (P == 3)
-        td_addq(x, y, r);
+        (variant & 1) ? td_add_acc(x, y, r) : td_addq(x, y, r);
     else
         qd_add(x, y, r);
 }
 
-static void mp_mul(int P, const double *x, const double *y, double *r)
+static void mp_mul_v(int P, int variant, const double *x, const double *y, double *r)
 {
     if (P == 2)
         dd_mul(x, y, r);
     else if (P == 3)
-        td_mul(x, y, r);
+        (variant & 2) ? td_mulq(x, y, r) : td_mul(x, y, r);
     else
         qd_mul(x, y, r);
 }
+
+static void mp_add(int P, const double *x, const double *y, double *r) { mp_add_v(P, 0, x, y, r); }
+static void mp_mul(int P, const double *x, const double *y, double *r) { mp_mul_v(P, 0, x, y, r); }
 
 static int mp_is_zero(int P, const double *x)
 {
@@ -359,10 +408,14 @@ static void load_op(int P, char t, const double *A, int64_t ld, int64_t ps,
 /* Exported element-wise operations and primitives (for pinning).           */
 /* ------------------------------------------------------------------------ */
 
-/* r[i] = x[i] (+ or *) y[i] for i < n; planes at the given strides. */
-EXPORT void ref_vec(int P, int op, int64_t n, const double *x, int64_t sx,
-                    const double *y, int64_t sy, double *r, int64_t sr)
+/* r[i] = x[i] op y[i] for i < n; planes at the given strides.  op: 0 add,
+ * 1 mul, 2 the accurate TD addition (P == 3), 3 TDmulq (P == 3).  Returns -1
+ * for an op that the precision does not have. */
+EXPORT int ref_vec(int P, int op, int64_t n, const double *x, int64_t sx,
+                   const double *y, int64_t sy, double *r, int64_t sr)
 {
+    if (op < 0 || op > 3 || (op >= 2 && P != 3))
+        return -1;
     for (int64_t i = 0; i < n; ++i) {
         double a[4], b[4], o[4];
         for (int c = 0; c < P; ++c) {
@@ -371,11 +424,16 @@ EXPORT void ref_vec(int P, int op, int64_t n, const double *x, int64_t sx,
         }
         if (op == 0)
             mp_add(P, a, b, o);
-        else
+        else if (op == 1)
             mp_mul(P, a, b, o);
+        else if (op == 2)
+            td_add_acc(a, b, o);
+        else
+            td_mulq(a, b, o);
         for (int c = 0; c < P; ++c)
             r[c * sr + i] = o[c];
     }
+    return 0;
 }
 
 /* Primitive under test, applied to n argument tuples stored argument-major
@@ -384,7 +442,8 @@ EXPORT void ref_vec(int P, int op, int64_t n, const double *x, int64_t sx,
  *   2 two_prod(a,b)->(p,e)        3 three_sum(a,b,c)->(a,b,c)
  *   4 three_sum2(a,b,c)->(a,b)    5 vec_sum(x0..x3)->(e0..e3)
  *   6 vseb2(e0,e1,e2)->(r0,r1)    7 renorm4(c0..c4)->(r0..r3)
- *   8 vseb3(e0..e5)->(r0,r1,r2)   9 vec_sum(x0..x2)->(e0..e2) */
+ *   8 vseb3(e0..e5)->(r0,r1,r2)   9 vec_sum(x0..x2)->(e0..e2)
+ *  10 merge(x0,x1,x2,y0,y1,y2)->(z0..z5) */
 EXPORT int ref_prim(int which, int64_t n, const double *in, double *out)
 {
     for (int64_t i = 0; i < n; ++i) {
@@ -436,6 +495,11 @@ EXPORT int ref_prim(int which, int64_t n, const double *in, double *out)
             vec_sum(a, 3, o);
             for (int q = 0; q < 3; ++q) out[q * n + i] = o[q];
             break;
+        case 10:
+            for (int q = 0; q < 6; ++q) a[q] = in[q * n + i];
+            merge_mag(&a[0], 3, &a[3], 3, o);
+            for (int q = 0; q < 6; ++q) out[q * n + i] = o[q];
+            break;
         default:
             return -1;
         }
@@ -456,8 +520,8 @@ EXPORT int ref_prim(int which, int64_t n, const double *in, double *out)
  * and nothing is written when m == 0, n == 0, or (alpha == 0 or k == 0) and
  * beta == 1.  Only rows row0 <= i < row1 and columns col0 <= j < col1 are
  * computed (a negative end means "to the last"). */
-static void epilogue(int P, const double *alpha, const double *acc, const double *beta,
-                     double *c_io, int alpha_or_k_zero)
+static void epilogue(int P, int variant, const double *alpha, const double *acc,
+                     const double *beta, double *c_io, int alpha_or_k_zero)
 {
     double t1[4], t2[4];
     int beta_zero = mp_is_zero(P, beta);
@@ -465,28 +529,31 @@ static void epilogue(int P, const double *alpha, const double *acc, const double
         if (beta_zero) {
             for (int c = 0; c < P; ++c) c_io[c] = 0.0;
         } else {
-            mp_mul(P, beta, c_io, t2);
+            mp_mul_v(P, variant, beta, c_io, t2);
             for (int c = 0; c < P; ++c) c_io[c] = t2[c];
         }
         return;
     }
-    mp_mul(P, alpha, acc, t1);
+    mp_mul_v(P, variant, alpha, acc, t1);
     if (beta_zero) {
         for (int c = 0; c < P; ++c) c_io[c] = t1[c];
     } else {
-        mp_mul(P, beta, c_io, t2);
-        mp_add(P, t1, t2, c_io);
+        mp_mul_v(P, variant, beta, c_io, t2);
+        mp_add_v(P, variant, t1, t2, c_io);
     }
 }
 
-EXPORT int ref_gemm(int P, char ta, char tb, int64_t m, int64_t n, int64_t k,
-                    const double *alpha, const double *A, int64_t lda, int64_t sa,
-                    const double *B, int64_t ldb, int64_t sb, const double *beta,
-                    double *C, int64_t ldc, int64_t sc, int64_t row0, int64_t row1,
-                    int64_t col0, int64_t col1, int nthreads)
+/* The GEMM with the TD operations chosen by `variant` (0 for DD and QD). */
+EXPORT int ref_gemm_v(int P, int variant, char ta, char tb, int64_t m, int64_t n, int64_t k,
+                      const double *alpha, const double *A, int64_t lda, int64_t sa,
+                      const double *B, int64_t ldb, int64_t sb, const double *beta,
+                      double *C, int64_t ldc, int64_t sc, int64_t row0, int64_t row1,
+                      int64_t col0, int64_t col1, int nthreads)
 {
     if (P < 2 || P > 4)
         return -1;
+    if (variant < 0 || variant > 3 || (variant != 0 && P != 3))
+        return -2;
     if (row1 < 0 || row1 > m)
         row1 = m;
     if (row0 < 0)
@@ -513,19 +580,29 @@ EXPORT int ref_gemm(int P, char ta, char tb, int64_t m, int64_t n, int64_t k,
                 double a[4], b[4], p[4], t[4];
                 load_op(P, ta, A, lda, sa, i, l, a);
                 load_op(P, tb == 'N' || tb == 'n' ? 'T' : 'N', B, ldb, sb, j, l, b);
-                mp_mul(P, a, b, p);
-                mp_add(P, acc, p, t);
+                mp_mul_v(P, variant, a, b, p);
+                mp_add_v(P, variant, acc, p, t);
                 for (int c = 0; c < P; ++c) acc[c] = t[c];
             }
         }
         double cv[4];
         for (int c = 0; c < P; ++c)
             cv[c] = C[c * sc + i + j * ldc];
-        epilogue(P, alpha, acc, beta, cv, az);
+        epilogue(P, variant, alpha, acc, beta, cv, az);
         for (int c = 0; c < P; ++c)
             C[c * sc + i + j * ldc] = cv[c];
     }
     return 0;
+}
+
+EXPORT int ref_gemm(int P, char ta, char tb, int64_t m, int64_t n, int64_t k,
+                    const double *alpha, const double *A, int64_t lda, int64_t sa,
+                    const double *B, int64_t ldb, int64_t sb, const double *beta,
+                    double *C, int64_t ldc, int64_t sc, int64_t row0, int64_t row1,
+                    int64_t col0, int64_t col1, int nthreads)
+{
+    return ref_gemm_v(P, 0, ta, tb, m, n, k, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc,
+                      row0, row1, col0, col1, nthreads);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -702,7 +779,7 @@ EXPORT int ref_gemm_split(int P, int s, char ta, char tb, int64_t m, int64_t n, 
         double cv[4];
         for (int c = 0; c < P; ++c)
             cv[c] = C[c * sc + i + j * ldc];
-        epilogue(P, alpha, acc, beta, cv, az);
+        epilogue(P, 0, alpha, acc, beta, cv, az);
         for (int c = 0; c < P; ++c)
             C[c * sc + i + j * ldc] = cv[c];
     }

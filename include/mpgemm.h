@@ -68,6 +68,15 @@ extern "C" {
 #define MPGEMM_FORM_AUTO 2      /* tuned choice between the two (plain when
                                    no workspace is given)                   */
 
+/* TD operation variants (Sec. 2.3).  The defaults are TDaddq (the QD
+ * addition on zero fourth components) and the "fast" triple-word product
+ * (Algorithm 4). */
+#define MPGEMM_TD_ADD_ACCURATE 1  /* Algorithm 3: Merge by decreasing magnitude,
+                                     VecSum of the six terms, VSEB(3)        */
+#define MPGEMM_TD_MULQ 2          /* TDmulq: the QD product (Algorithm 6) on
+                                     zero fourth components, fourth output
+                                     dropped                                 */
+
 /* Options for the _ex entry points.  Zero-initialise and set what you need. */
 typedef struct mpgemm_opts {
     int form;               /* MPGEMM_FORM_*                                   */
@@ -76,7 +85,9 @@ typedef struct mpgemm_opts {
                                enough for inputs of similar magnitude within a
                                row of op(A) / column of op(B)              */
     int tile;               /* kernel configuration id; -1 or 0.. = tuned/fixed */
-    int reserved;
+    int variant;            /* TD only, plain form: MPGEMM_TD_* bits selecting
+                               the other TD operations of Sec. 2.3 (runs TD
+                               tile configuration 0); 0 = the defaults      */
     void* workspace;        /* split form: device scratch owned by the caller  */
     size_t workspace_bytes; /* its size; see mpgemm_workspace_bytes()          */
 } mpgemm_opts;
@@ -126,6 +137,11 @@ int mpgemm_qd(char transa, char transb, int64_t m, int64_t n, int64_t k, const d
  * mpgemm_workspace_bytes() bytes (device memory the caller owns; no
  * allocation on this path).  Supported for k * s <= 2^19 (exact 32-bit
  * accumulation); larger k returns MPGEMM_ERR_UNSUPPORTED.
+ * opts->variant (TD, plain form only; MPGEMM_ERR_UNSUPPORTED for another
+ * precision or the split form, -18 outside 0..3): the same canonical
+ * evaluation with the accurate TD addition (MPGEMM_TD_ADD_ACCURATE) and / or
+ * TDmulq (MPGEMM_TD_MULQ) in place of TDaddq and Algorithm 4, everywhere
+ * including the alpha/beta epilogue; FORM_AUTO then means plain.
  */
 int mpgemm_dd_ex(char transa, char transb, int64_t m, int64_t n, int64_t k, const double* alpha,
                  const double* A, int64_t lda, int64_t a_plane_stride, const double* B, int64_t ldb,
@@ -165,6 +181,12 @@ int mp_vec_qd_add(int64_t n, const double* x, int64_t sx, const double* y, int64
                   int64_t sr, hipStream_t stream);
 int mp_vec_qd_mul(int64_t n, const double* x, int64_t sx, const double* y, int64_t sy, double* r,
                   int64_t sr, hipStream_t stream);
+/* The other TD operations of Sec. 2.3, element-wise, same arguments:
+ * the accurate addition (Algorithm 3) and TDmulq (see MPGEMM_TD_*). */
+int mp_vec_td_add_acc(int64_t n, const double* x, int64_t sx, const double* y, int64_t sy,
+                      double* r, int64_t sr, hipStream_t stream);
+int mp_vec_td_mulq(int64_t n, const double* x, int64_t sx, const double* y, int64_t sy, double* r,
+                   int64_t sr, hipStream_t stream);
 
 /*
  * Batched GEMMs of uneven shapes in one persistent launch (plain form, same

@@ -18,10 +18,11 @@ _P = C.POINTER
 
 ERR_HIP, ERR_WORKSPACE, ERR_UNSUPPORTED, ERR_GRAPH, ERR_ALIAS, ERR_NOMEM = 1, 2, 3, 4, 5, 6
 FORM_PLAIN, FORM_SPLIT_I8, FORM_AUTO = 0, 1, 2
+TD_ADD_ACCURATE, TD_MULQ = 1, 2
 
 
 class Opts(C.Structure):
-    _fields_ = [("form", _int), ("slices", _int), ("tile", _int), ("reserved", _int),
+    _fields_ = [("form", _int), ("slices", _int), ("tile", _int), ("variant", _int),
                 ("workspace", _vp), ("workspace_bytes", _sz)]
 
 
@@ -46,6 +47,7 @@ EXPORTS = {
     "mp_vec_dd_add": (_VEC_ARGS, _int), "mp_vec_dd_mul": (_VEC_ARGS, _int),
     "mp_vec_td_add": (_VEC_ARGS, _int), "mp_vec_td_mul": (_VEC_ARGS, _int),
     "mp_vec_qd_add": (_VEC_ARGS, _int), "mp_vec_qd_mul": (_VEC_ARGS, _int),
+    "mp_vec_td_add_acc": (_VEC_ARGS, _int), "mp_vec_td_mulq": (_VEC_ARGS, _int),
     "mpgemm_batch_plan_create": ([_int, _i64, _P(Problem), _P(Opts), _vp, _P(_vp)], _int),
     "mpgemm_batch_plan_run": ([_vp, _vp], _int),
     "mpgemm_batch_plan_launch": ([_vp, _vp], _int),

@@ -59,12 +59,16 @@ def _scalar(v: Sequence[float], P: int):
     return (C.c_double * P)(*vals[:P])
 
 
-def make_opts(form="plain", slices=0, tile=-1, workspace: torch.Tensor | None = None):
+TD_VARIANTS = {"default": 0, "add_acc": _lib.TD_ADD_ACCURATE, "mulq": _lib.TD_MULQ,
+               "add_acc+mulq": _lib.TD_ADD_ACCURATE | _lib.TD_MULQ}
+
+
+def make_opts(form="plain", slices=0, tile=-1, workspace: torch.Tensor | None = None, variant=0):
     o = _lib.Opts()
     o.form = FORMS[form] if isinstance(form, str) else int(form)
     o.slices = int(slices)
     o.tile = int(tile)
-    o.reserved = 0
+    o.variant = TD_VARIANTS[variant] if isinstance(variant, str) else int(variant)
     if workspace is not None:
         o.workspace = C.c_void_p(workspace.data_ptr())
         o.workspace_bytes = workspace.numel() * workspace.element_size()
@@ -86,8 +90,10 @@ def alloc_workspace(prec, m, n, k, slices=0, tile=-1, device=None) -> torch.Tens
 
 
 def gemm_raw(prec, transa, transb, m, n, k, alpha, A, B, beta, C_, *, form=None, slices=0,
-             tile=-1, workspace=None, stream=None) -> int:
-    """Calls mpgemm_{dd,td,qd}[_ex]; returns the library's status code."""
+             tile=-1, workspace=None, stream=None, variant=0) -> int:
+    """Calls mpgemm_{dd,td,qd}[_ex]; returns the library's status code.
+    variant (TD, plain form): "add_acc" (Algorithm 3), "mulq" (TDmulq), both,
+    or the MPGEMM_TD_* bits."""
     P = PREC[prec]
     L = _lib.load()
     a, lda, sa = _mat(A, P)
@@ -96,9 +102,10 @@ def gemm_raw(prec, transa, transb, m, n, k, alpha, A, B, beta, C_, *, form=None,
     args = [transa.encode(), transb.encode(), m, n, k, _scalar(alpha, P), a, lda, sa, b, ldb, sb,
             _scalar(beta, P), c, ldc, sc, _stream(stream)]
     name = "mpgemm_" + _NAME[P]
-    if form is None:
+    if form is None and not variant:
         return getattr(L, name)(*args)
-    return getattr(L, name + "_ex")(*args, C.byref(make_opts(form, slices, tile, workspace)))
+    return getattr(L, name + "_ex")(*args, C.byref(make_opts(form or "plain", slices, tile, workspace,
+                                                               variant)))
 
 
 def gemm(prec, transa, transb, m, n, k, alpha, A, B, beta, C_, **kw) -> None:
@@ -119,7 +126,8 @@ def vec_raw(prec, op, x, y, r, n=None, stream=None) -> int:
 
 
 def vec(prec, op, x, y, r, n=None, stream=None) -> None:
-    """r = x (+|*) y element-wise; x, y, r are (P, n) float64 CUDA tensors."""
+    """r = x op y element-wise; x, y, r are (P, n) float64 CUDA tensors; op is
+    "add" or "mul", and for TD also "add_acc" (Algorithm 3) or "mulq"."""
     _check(vec_raw(prec, op, x, y, r, n, stream), "mp_vec")
 
 

@@ -169,11 +169,17 @@ int gemm_common(int P, char ta, char tb, int64_t m, int64_t n, int64_t k, const 
         if (!opts) return -18;
         if (opts->form < 0 || opts->form > 2) return -18;
         if (opts->slices < 0 || opts->slices > kMaxSlices) return -18;
+        if (opts->variant < 0 || opts->variant > 3) return -18;
     }
+    const int variant = has_opts ? opts->variant : 0;
+    // the TD variants exist for the plain form only
+    if (variant != 0 && (P != 3 || opts->form == MPGEMM_FORM_SPLIT_I8 || last_stage > 0))
+        return MPGEMM_ERR_UNSUPPORTED;
     if (m == 0 || n == 0) return 0;
     const bool az = (k == 0) || mp_zero(P, alpha);
     if (az && mp_one(P, beta)) return 0;
-    if (az) return hip_rc(launch_scale(P, g, st));
+    if (az) return hip_rc(variant ? launch_scale_td_variant(variant, g, st) : launch_scale(P, g, st));
+    if (variant) return hip_rc(launch_plain_td_variant(variant, g, st));
 
     int form = has_opts ? opts->form : MPGEMM_FORM_PLAIN;
     const int s = (has_opts && opts->slices > 0) ? opts->slices : kDefaultSlices[P];
@@ -279,6 +285,8 @@ MPG_VEC(mp_vec_td_add, 3, 0)
 MPG_VEC(mp_vec_td_mul, 3, 1)
 MPG_VEC(mp_vec_qd_add, 4, 0)
 MPG_VEC(mp_vec_qd_mul, 4, 1)
+MPG_VEC(mp_vec_td_add_acc, 3, 2)
+MPG_VEC(mp_vec_td_mulq, 3, 3)
 #undef MPG_VEC
 
 // ---- batched plan -----------------------------------------------------------
@@ -311,6 +319,7 @@ int mpgemm_batch_plan_create(int prec, int64_t count, const mpgemm_problem* prob
                           pr.ldc, pr.c_plane_stride, gs[(size_t)q]);
         if (rc) return rc == MPGEMM_ERR_ALIAS ? rc : (int)(-(1000 + q));
     }
+    if (opts && opts->variant != 0) return MPGEMM_ERR_UNSUPPORTED;   // TD variants: plain calls only
     int cfg = (opts && opts->tile >= 0 && opts->tile < kPlainConfigs) ? opts->tile : -1;
     if (cfg < 0) {
         // tile shape for the typical problem of the batch

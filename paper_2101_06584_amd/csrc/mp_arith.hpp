@@ -440,6 +440,114 @@ MPG_DEV void tile_mac(mp<3> (&acc)[TM][TN], const mp<3> (&a)[TM], const mp<3> (&
     }
 }
 
+// ---- The other TD operations of Sec. 2.3 ---------------------------------
+//
+// The accurate TD addition (Algorithm 3) and TDmulq, which the paper measures
+// against its defaults (TDaddq, Algorithm 4).  Selected per call through a
+// variant: bit 0 the accurate addition, bit 1 TDmulq.
+
+// Merge of two three-term expansions by decreasing magnitude: the two-pointer
+// merge, x's head first when |x_i| >= |y_j|.  Written with selects (no
+// run-time register indexing).
+MPG_DEV void merge3(const mp<3>& x, const mp<3>& y, double (&z)[6]) {
+    // the heads are shifted queues (hx0 = current head of x), so no value is
+    // ever picked by a run-time index
+    double hx0 = x.c[0], hx1 = x.c[1], hx2 = x.c[2];
+    double hy0 = y.c[0], hy1 = y.c[1], hy2 = y.c[2];
+    int nx = 3, ny = 3;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const bool take_x = (ny == 0) || (nx > 0 && fabs(hx0) >= fabs(hy0));
+        z[k] = take_x ? hx0 : hy0;
+        hx0 = take_x ? hx1 : hx0;
+        hx1 = take_x ? hx2 : hx1;
+        hy0 = take_x ? hy0 : hy1;
+        hy1 = take_x ? hy1 : hy2;
+        nx -= take_x ? 1 : 0;
+        ny -= take_x ? 0 : 1;
+    }
+}
+
+// VecSum over N terms: s = x[N-1]; (s, e[i+1]) = TwoSum(x[i], s) for
+// i = N-2..0; e[0] = s.
+template <int N>
+MPG_DEV void vec_sum_n(const double (&x)[N], double (&e)[N]) {
+    double s = x[N - 1];
+#pragma unroll
+    for (int i = N - 2; i >= 0; --i) two_sum(x[i], s, s, e[i + 1]);
+    e[0] = s;
+}
+
+// VSEB(K) over N terms in select form: a top-down QuickTwoSum pass; a
+// non-zero error closes the next output (the sum is the output, the error
+// the new carry), a zero error keeps the sum as carry; after K outputs the
+// rest is dropped; the carry fills the next open output at the end, later
+// outputs are zero.
+template <int N, int K>
+MPG_DEV void vseb_n(const double (&e)[N], double (&r)[K]) {
+#pragma unroll
+    for (int q = 0; q < K; ++q) r[q] = 0.0;
+    int j = 0;
+    bool done = false;
+    double carry = e[0];
+#pragma unroll
+    for (int i = 1; i < N; ++i) {
+        double s, t;
+        quick_two_sum(carry, e[i], s, t);
+        const bool close = !done && (t != 0.0);
+#pragma unroll
+        for (int q = 0; q < K; ++q) r[q] = (close && j == q) ? s : r[q];
+        carry = done ? carry : (close ? t : s);
+        j += close ? 1 : 0;
+        done = done || (j == K);
+    }
+#pragma unroll
+    for (int q = 0; q < K; ++q) r[q] = (!done && j == q) ? carry : r[q];
+}
+
+// Algorithm 3: Merge, VecSum over the six terms, VSEB(3).
+MPG_DEV mp<3> td_add_acc(const mp<3>& x, const mp<3>& y) {
+    double z[6], e[6], r[3];
+    merge3(x, y, z);
+    vec_sum_n<6>(z, e);
+    vseb_n<6, 3>(e, r);
+    return mp<3>{{r[0], r[1], r[2]}};
+}
+
+// TDmulq: Algorithm 6 on (x0, x1, x2, 0) and (y0, y1, y2, 0), fourth output
+// dropped.
+MPG_DEV mp<3> td_mulq(const mp<3>& x, const mp<3>& y) {
+    const mp<4> r = mul(mp<4>{{x.c[0], x.c[1], x.c[2], 0.0}}, mp<4>{{y.c[0], y.c[1], y.c[2], 0.0}});
+    return mp<3>{{r.c[0], r.c[1], r.c[2]}};
+}
+
+// The precision's addition / multiplication under variant V (only TD has
+// variants).
+template <int V, int P>
+MPG_DEV mp<P> add_v(const mp<P>& x, const mp<P>& y) {
+    if constexpr (P == 3 && (V & 1) != 0) return td_add_acc(x, y);
+    else return add(x, y);
+}
+template <int V, int P>
+MPG_DEV mp<P> mul_v(const mp<P>& x, const mp<P>& y) {
+    if constexpr (P == 3 && (V & 2) != 0) return td_mulq(x, y);
+    else return mul(x, y);
+}
+
+// tile_mac under variant V: the fast-path tile routine for V == 0, the plain
+// loop over add_v / mul_v otherwise.
+template <int V, int TM, int TN, int P>
+MPG_DEV void tile_mac_v(mp<P> (&acc)[TM][TN], const mp<P> (&a)[TM], const mp<P> (&b)[TN]) {
+    if constexpr (V == 0) {
+        tile_mac<TM, TN>(acc, a, b);
+    } else {
+#pragma unroll
+        for (int r = 0; r < TM; ++r)
+#pragma unroll
+            for (int c = 0; c < TN; ++c) acc[r][c] = add_v<V>(acc[r][c], mul_v<V>(a[r], b[c]));
+    }
+}
+
 template <int P>
 MPG_DEV mp<P> mp_zero() {
     mp<P> r;

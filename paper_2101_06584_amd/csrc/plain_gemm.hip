@@ -24,7 +24,7 @@ namespace mpg {
 // Tile routine
 // ---------------------------------------------------------------------------
 
-template <int P, int TX, int TY, int TM, int TN, int BK>
+template <int P, int TX, int TY, int TM, int TN, int BK, int V = 0>
 struct PlainTile {
     static constexpr int BM = TX * TM;
     static constexpr int BN = TY * TN;
@@ -71,7 +71,7 @@ struct PlainTile {
         for (int c = 0; c < TN; ++c)
 #pragma unroll
             for (int p = 0; p < P; ++p) b[c].c[p] = Bs[(p * BK + kk) * BN + ty + c * TY];
-        tile_mac<TM, TN>(acc, a, b);
+        tile_mac_v<V, TM, TN>(acc, a, b);
     }
 
     __device__ static void run(const GemmArgs& g, const mp<P>& alpha, const mp<P>& beta,
@@ -124,15 +124,15 @@ struct PlainTile {
                             mp<P> co;
 #pragma unroll
                             for (int p = 0; p < P; ++p) co.c[p] = g.C[p * g.sc + off];
-                            t = mul(beta, co);
+                            t = mul_v<V>(beta, co);
                         }
                     } else {
-                        t = mul(alpha, acc[r][c]);
+                        t = mul_v<V>(alpha, acc[r][c]);
                         if (!beta_zero) {
                             mp<P> co;
 #pragma unroll
                             for (int p = 0; p < P; ++p) co.c[p] = g.C[p * g.sc + off];
-                            t = add(t, mul(beta, co));
+                            t = add_v<V>(t, mul_v<V>(beta, co));
                         }
                     }
 #pragma unroll
@@ -150,9 +150,9 @@ __device__ __forceinline__ mp<P> load_scalar(const double* v) {
     return r;
 }
 
-template <int P, int TX, int TY, int TM, int TN, int BK>
+template <int P, int TX, int TY, int TM, int TN, int BK, int V = 0>
 __global__ __launch_bounds__(TX * TY) void plain_gemm_kernel(GemmArgs g) {
-    using T = PlainTile<P, TX, TY, TM, TN, BK>;
+    using T = PlainTile<P, TX, TY, TM, TN, BK, V>;
     __shared__ double lds[T::LDS_DOUBLES];
     int64_t tm, tn;
     if (!xcd_tile_coords<8>(blockIdx.x, (g.m + T::BM - 1) / T::BM, (g.n + T::BN - 1) / T::BN, tm, tn))
@@ -206,7 +206,7 @@ __global__ void reset_counter_kernel(unsigned* counter) { *counter = 0u; }
 // alpha == 0 or k == 0: C = beta C, or 0 when beta == 0 (C then not read).
 // ---------------------------------------------------------------------------
 
-template <int P>
+template <int P, int V = 0>
 __global__ void scale_kernel(GemmArgs g) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= g.m * g.n) return;
@@ -218,7 +218,7 @@ __global__ void scale_kernel(GemmArgs g) {
         mp<P> co;
 #pragma unroll
         for (int p = 0; p < P; ++p) co.c[p] = g.C[p * g.sc + off];
-        t = mul(beta, co);
+        t = mul_v<V>(beta, co);
     }
 #pragma unroll
     for (int p = 0; p < P; ++p) g.C[p * g.sc + off] = t.c[p];
@@ -243,7 +243,11 @@ __global__ void vec_kernel(int64_t n, const double* __restrict__ x, int64_t sx,
             a.c[p] = __builtin_nontemporal_load(x + p * sx + i);
             b.c[p] = __builtin_nontemporal_load(y + p * sy + i);
         }
-        const mp<P> o = OP == 0 ? add(a, b) : mul(a, b);
+        mp<P> o;
+        if constexpr (OP == 0) o = add(a, b);
+        else if constexpr (OP == 1) o = mul(a, b);
+        else if constexpr (OP == 2) o = add_v<1>(a, b);    // TD only: Algorithm 3
+        else o = mul_v<2>(a, b);                           // TD only: TDmulq
 #pragma unroll
         for (int p = 0; p < P; ++p) __builtin_nontemporal_store(o.c[p], r + p * sr + i);
     }
@@ -286,12 +290,12 @@ int plain_default_config(int P, int64_t m, int64_t n, int64_t k) {
     return mn >= (int64_t)1024 * 1024 ? 0 : 1;
 }
 
-template <int P, int TX, int TY, int TM, int TN, int BK>
+template <int P, int TX, int TY, int TM, int TN, int BK, int V = 0>
 static int launch_plain_t(const GemmArgs& g, hipStream_t st) {
-    using T = PlainTile<P, TX, TY, TM, TN, BK>;
+    using T = PlainTile<P, TX, TY, TM, TN, BK, V>;
     const int64_t grid = xcd_grid(((g.m + T::BM - 1) / T::BM) * ((g.n + T::BN - 1) / T::BN));
     if (grid > 0x7fffffffLL) return (int)hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((plain_gemm_kernel<P, TX, TY, TM, TN, BK>), dim3((unsigned)grid), dim3(T::NT),
+    hipLaunchKernelGGL((plain_gemm_kernel<P, TX, TY, TM, TN, BK, V>), dim3((unsigned)grid), dim3(T::NT),
                        0, st, g);
     return (int)hipGetLastError();
 }
@@ -350,6 +354,26 @@ int64_t batch_build_desc(int P, int cfg, int64_t count, const GemmArgs* probs, c
     return tiles;
 }
 
+// TD with the other operations of Sec. 2.3 (variant bit 0: the accurate
+// addition, bit 1: TDmulq), on TD tile configuration 0.
+int launch_plain_td_variant(int variant, const GemmArgs& g, hipStream_t st) {
+    switch (variant) {
+    case 1: return launch_plain_t<3, 16, 16, 2, 2, 16, 1>(g, st);
+    case 2: return launch_plain_t<3, 16, 16, 2, 2, 16, 2>(g, st);
+    case 3: return launch_plain_t<3, 16, 16, 2, 2, 16, 3>(g, st);
+    default: return (int)hipErrorInvalidValue;
+    }
+}
+
+int launch_scale_td_variant(int variant, const GemmArgs& g, hipStream_t st) {
+    const int64_t blocks = (g.m * g.n + 255) / 256;
+    if (blocks > 0x7fffffffLL) return (int)hipErrorInvalidConfiguration;
+    const dim3 gr((unsigned)blocks), bl(256);
+    if (variant & 2) hipLaunchKernelGGL((scale_kernel<3, 2>), gr, bl, 0, st, g);
+    else hipLaunchKernelGGL((scale_kernel<3, 0>), gr, bl, 0, st, g);
+    return (int)hipGetLastError();
+}
+
 int launch_scale(int P, const GemmArgs& g, hipStream_t st) {
     const int64_t total = g.m * g.n;
     const int64_t blocks = (total + 255) / 256;
@@ -368,7 +392,12 @@ int launch_vec(int P, int op, int64_t n, const double* x, int64_t sx, const doub
     const dim3 gr((unsigned)blocks), bl(256);
 #define MPG_VEC(PP, OO) hipLaunchKernelGGL((vec_kernel<PP, OO>), gr, bl, 0, st, n, x, sx, y, sy, r, sr)
     if (P == 2) { if (op == 0) MPG_VEC(2, 0); else MPG_VEC(2, 1); }
-    else if (P == 3) { if (op == 0) MPG_VEC(3, 0); else MPG_VEC(3, 1); }
+    else if (P == 3) {
+        if (op == 0) MPG_VEC(3, 0);
+        else if (op == 1) MPG_VEC(3, 1);
+        else if (op == 2) MPG_VEC(3, 2);
+        else MPG_VEC(3, 3);
+    }
     else { if (op == 0) MPG_VEC(4, 0); else MPG_VEC(4, 1); }
 #undef MPG_VEC
     return (int)hipGetLastError();

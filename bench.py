@@ -104,6 +104,8 @@ def parse():
     ap.add_argument("--vec", action="store_true",
                     help="element-wise DD/TD/QD add and mul (Sec. 2.5) against the HBM roofline")
     ap.add_argument("--vec-n", type=int, default=1 << 26, help="vector length for --vec")
+    ap.add_argument("--td-variants", action="store_true",
+                    help="accuracy and speed of the TD operation variants (Sec. 2.3)")
     return ap.parse_args()
 
 
@@ -140,6 +142,8 @@ def main():
         return other_config(args, mp, synth, dev, stream)
     if args.vec:
         return vec_bench(args, mp, dev, stream)
+    if args.td_variants:
+        return td_variants_bench(args, mp, synth, dev, stream)
     n = args.n
     precs = [int(p) for p in args.prec.split(",")]
     forms = args.forms.split(",")
@@ -338,6 +342,110 @@ def main():
 
 
 PREC_OF = {"DD": 2, "TD": 3, "QD": 4}
+
+
+TD_VARIANT_NAMES = {0: "TDaddq+TDmul", 1: "TDadd+TDmul", 2: "TDaddq+TDmulq", 3: "TDadd+TDmulq"}
+
+
+def td_variants_bench(args, mp, synth, dev, stream):
+    """The TD operations of Sec. 2.3 side by side: the default pair (TDaddq,
+    Algorithm 4) against the accurate addition (Algorithm 3) and TDmulq.
+    GEMM: m = n = k = 2048 on uniform and on exponent-spread inputs, time and
+    error against the exact product on sampled entries.  Element-wise: rate at
+    n = 2^26 and relative error against the exact result on cancelling
+    operands.  One JSON line."""
+    import numpy as np
+    import torch
+    from fractions import Fraction
+    from tests.exact import GemmChecker, mp_frac, sample_entries
+    P, n = 3, 2048
+    one, zero = synth.mp_one(P), np.zeros(P)
+    gemm_parts = {}
+    for label, spread in (("uniform", None), ("spread_e30", (-30, 30))):
+        A = synth.mp_matrix(3, "A", P, n, n, exp_range=spread)
+        B = synth.mp_matrix(3, "B", P, n, n, exp_range=spread)
+        dA, dB = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+        chk = GemmChecker(P, "N", "N", n, n, n, one, A, B, zero, np.zeros((P, n, 1)))
+        ents = sample_entries(synth.rng_for(3, "samples"), n, n, 256)
+        for v, name in TD_VARIANT_NAMES.items():
+            dC = torch.zeros((P, n, n), dtype=torch.float64, device=dev)
+            call = lambda: mp.gemm(P, "N", "N", n, n, n, one, dA, dB, zero, dC, variant=v,  # noqa: E731
+                                   stream=stream)
+            call()
+            torch.cuda.synchronize()
+            times = []
+            for _ in range(max(3, args.steps)):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                call()
+                e1.record(stream)
+                torch.cuda.synchronize()
+                times.append(e0.elapsed_time(e1))
+            ms = float(np.median(times))
+            r = chk.ratios(dC.cpu().numpy(), ents)
+            gemm_parts[f"gemm_{label}_{name}"] = {"ms": round(ms, 3), "2mnk/s": 2.0 * n ** 3 / (ms * 1e-3),
+                                                  "err_ratio_max": float(r.max()),
+                                                  "err_ratio_median": float(np.median(r))}
+            note("td gemm", label, name, round(ms, 2), "ms", f"{r.max():.3g}")
+            del dC
+        del dA, dB
+    # element-wise: rate on long vectors, error on cancelling operands
+    vec_parts = {}
+    nv = args.vec_n
+    g = torch.Generator(device=dev).manual_seed(3)
+    x = torch.empty((P, nv), dtype=torch.float64, device=dev)
+    y = torch.empty_like(x)
+    for t in (x, y):
+        t[0].uniform_(-1, 1, generator=g)
+        for p in range(1, P):
+            t[p] = t[p - 1] * 2.0 ** -54 * (torch.rand(nv, dtype=torch.float64, device=dev, generator=g) * 2 - 1)
+    r = torch.empty_like(x)
+    rng = np.random.Generator(np.random.PCG64(31))
+    ns = 1 << 13
+    xs = synth.mp_uniform(rng, P, (ns,))
+    ys = synth.mp_uniform(rng, P, (ns,))
+    ys[:, : ns // 2] = -xs[:, : ns // 2]
+    ys[0, : ns // 2] *= 1 + 2.0 ** -45 * rng.uniform(-1, 1, ns // 2)   # heavy cancellation
+    dxs, dys = torch.from_numpy(xs).to(dev), torch.from_numpy(ys).to(dev)
+    for op in ("add", "add_acc", "mul", "mulq"):
+        call = lambda: mp.vec(P, op, x, y, r, stream=stream)  # noqa: E731
+        call()
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(max(3, args.steps)):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            call()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        ms = float(np.median(times))
+        drs = torch.empty_like(dxs)
+        mp.vec(P, op, dxs, dys, drs, stream=stream)
+        got = drs.cpu().numpy()
+        worst = 0.0
+        for i in range(ns):
+            X, Y, R = mp_frac(xs[:, i]), mp_frac(ys[:, i]), mp_frac(got[:, i])
+            ex = X + Y if op.startswith("add") else X * Y
+            if ex != 0:
+                worst = max(worst, float(abs(R - ex) / abs(ex) / Fraction(1, 2 ** 159)))
+        vec_parts[op] = {"ms": round(ms, 4), "GB/s": 3.0 * 8 * P * nv / (ms * 1e-3) / 1e9,
+                         "max_rel_err_2^-159": worst}
+        note("td vec", op, round(ms, 3), "ms", f"{worst:.3g}")
+    total_ms = sum(v["ms"] for v in gemm_parts.values())
+    out = {"metric": "TD GEMM 2mnk/s and error by TD operation variant", "unit": "2mnk/s",
+           "value": 2.0 * n ** 3 * len(gemm_parts) / (total_ms * 1e-3), "n_gpus": 1,
+           "steps": max(3, args.steps), "warmup": 1, "ms_per_step": round(total_ms, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"TD GEMM m=n=k={n} (uniform and exponent-spread entries), four "
+                                  "add/mul variants; element-wise TD add/mul variants, n = 2^26",
+                      "err_ratio_unit": "|C - C*| / (k u |A||B|), u = 2^-150, 256 sampled entries",
+                      "vec_error_sample": f"{ns} operand pairs, half with |x + y| ~ 2^-45 |x|"},
+           "gemm": gemm_parts, "vec": vec_parts}
+    print(json.dumps(out), flush=True)
 
 
 def vec_bench(args, mp, dev, stream):

@@ -36,6 +36,10 @@ def lib():
         L.ref_gemm.restype = _int
         L.ref_gemm_v.argtypes = [_int, _int] + L.ref_gemm.argtypes[1:]
         L.ref_gemm_v.restype = _int
+        L.ref_gemm_strassen.argtypes = [_int, _int, _ch, _ch, _i64, _i64, _i64, C.c_void_p, C.c_void_p,
+                                        _i64, _i64, C.c_void_p, _i64, _i64, C.c_void_p, C.c_void_p,
+                                        _i64, _i64]
+        L.ref_gemm_strassen.restype = _int
         L.ref_gemm_split.argtypes = [_int, _int, _ch, _ch, _i64, _i64, _i64, C.c_void_p, C.c_void_p, _i64,
                                      _i64, C.c_void_p, _i64, _i64, C.c_void_p, C.c_void_p, _i64, _i64,
                                      _i64, _i64, _i64, _i64, _int, C.c_void_p, C.c_void_p, C.c_void_p]
@@ -108,6 +112,23 @@ def gemm(P, ta, tb, m, n, k, alpha, A, B, beta, C, rows=None, cols=None, nthread
                           A.shape[2], A.shape[1] * A.shape[2], _ptr(B), B.shape[2],
                           B.shape[1] * B.shape[2], _ptr(beta), _ptr(Cout), Cout.shape[2],
                           Cout.shape[1] * Cout.shape[2], r0, r1, c0, c1, nthreads)
+    assert rc == 0, rc
+    return Cout
+
+
+def gemm_strassen(P, levels, ta, tb, m, n, k, alpha, A, B, beta, C):
+    """C = alpha op(A) op(B) + beta C with `levels` levels of Strassen's method
+    over canonical-order block products; returns a new C (m, n, k must be
+    multiples of 2^levels)."""
+    A = _f64(A)
+    B = _f64(B)
+    Cout = _f64(C).copy()
+    alpha = _f64(alpha)
+    beta = _f64(beta)
+    rc = lib().ref_gemm_strassen(P, levels, ta.encode(), tb.encode(), m, n, k, _ptr(alpha), _ptr(A),
+                                 A.shape[2], A.shape[1] * A.shape[2], _ptr(B), B.shape[2],
+                                 B.shape[1] * B.shape[2], _ptr(beta), _ptr(Cout), Cout.shape[2],
+                                 Cout.shape[1] * Cout.shape[2])
     assert rc == 0, rc
     return Cout
 

@@ -794,6 +794,163 @@ EXPORT int ref_gemm_split(int P, int s, char ta, char tb, int64_t m, int64_t n, 
     return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Strassen's method (Sec. 3, Fig. 5): for even dimensions, op(A), op(B) and */
+/* C are cut into 2 x 2 blocks and the product is formed from seven block   */
+/* products, recursively for `levels` levels; the blocks at the bottom are  */
+/* multiplied in the canonical order above.  The paper's figure with the    */
+/* formulas is not reproduced; the reading is Strassen's original scheme:   */
+/*   M1 = (A11 + A22)(B11 + B22)   M2 = (A21 + A22) B11                     */
+/*   M3 = A11 (B12 - B22)          M4 = A22 (B21 - B11)                     */
+/*   M5 = (A11 + A12) B22          M6 = (A21 - A11)(B11 + B12)              */
+/*   M7 = (A12 - A22)(B21 + B22)                                            */
+/*   C11 = M1 + M4 - M5 + M7       C12 = M3 + M5                            */
+/*   C21 = M2 + M4                 C22 = M1 - M2 + M3 + M6                  */
+/* Sums are evaluated left to right; x - y is ADD(x, -y) with -y the exact  */
+/* componentwise negation.  The product P = op(A) op(B) then goes through   */
+/* the epilogue of the canonical GEMM (alpha, beta).                        */
+/* ------------------------------------------------------------------------ */
+
+/* A dense matrix view in op space: element (i, j) of component c is at
+ * p[c * ps + (t ? j + i * ld : i + j * ld)]. */
+typedef struct {
+    double *p;
+    int64_t ld, ps;
+    int t;
+} mview;
+
+static mview mv_block(mview v, int64_t bi, int64_t bj, int64_t h, int64_t w)
+{
+    /* block (bi, bj) of height h and width w, in op space */
+    mview r = v;
+    r.p = v.t ? v.p + bj * w + bi * h * v.ld : v.p + bi * h + bj * w * v.ld;
+    return r;
+}
+
+static void mv_get(int P, mview v, int64_t i, int64_t j, double *x)
+{
+    int64_t off = v.t ? j + i * v.ld : i + j * v.ld;
+    for (int c = 0; c < P; ++c)
+        x[c] = v.p[c * v.ps + off];
+}
+
+static void mv_set(int P, mview v, int64_t i, int64_t j, const double *x)
+{
+    int64_t off = v.t ? j + i * v.ld : i + j * v.ld;
+    for (int c = 0; c < P; ++c)
+        v.p[c * v.ps + off] = x[c];
+}
+
+/* R = X + sign * Y over h x w (sign = +1 or -1; -Y negated exactly). */
+static void mv_addsub(int P, mview X, mview Y, int sign, mview R, int64_t h, int64_t w)
+{
+    for (int64_t j = 0; j < w; ++j)
+        for (int64_t i = 0; i < h; ++i) {
+            double x[4], y[4], r[4];
+            mv_get(P, X, i, j, x);
+            mv_get(P, Y, i, j, y);
+            if (sign < 0)
+                for (int c = 0; c < P; ++c) y[c] = -y[c];
+            mp_add(P, x, y, r);
+            mv_set(P, R, i, j, r);
+        }
+}
+
+static mview mv_alloc(int P, int64_t h, int64_t w)
+{
+    mview v;
+    v.p = (double *)calloc((size_t)P * (size_t)(h * w > 0 ? h * w : 1), sizeof(double));
+    v.ld = h > 0 ? h : 1;
+    v.ps = h * w;
+    v.t = 0;
+    return v;
+}
+
+/* Out (h x w, op space) = X (h x q) * Y (q x w). */
+static int strassen_rec(int P, int levels, int64_t h, int64_t w, int64_t q, mview X, mview Y,
+                        mview Out)
+{
+    if (levels == 0) {
+        double one[4] = {1.0, 0.0, 0.0, 0.0}, zero[4] = {0.0, 0.0, 0.0, 0.0};
+        return ref_gemm(P, X.t ? 'T' : 'N', Y.t ? 'T' : 'N', h, w, q, one, X.p, X.ld, X.ps,
+                        Y.p, Y.ld, Y.ps, zero, Out.p, Out.ld, Out.ps, 0, -1, 0, -1, 0);
+    }
+    int64_t a = h / 2, b = w / 2, c = q / 2;
+    mview A11 = mv_block(X, 0, 0, a, c), A12 = mv_block(X, 0, 1, a, c);
+    mview A21 = mv_block(X, 1, 0, a, c), A22 = mv_block(X, 1, 1, a, c);
+    mview B11 = mv_block(Y, 0, 0, c, b), B12 = mv_block(Y, 0, 1, c, b);
+    mview B21 = mv_block(Y, 1, 0, c, b), B22 = mv_block(Y, 1, 1, c, b);
+    mview C11 = mv_block(Out, 0, 0, a, b), C12 = mv_block(Out, 0, 1, a, b);
+    mview C21 = mv_block(Out, 1, 0, a, b), C22 = mv_block(Out, 1, 1, a, b);
+    mview SA = mv_alloc(P, a, c), SB = mv_alloc(P, c, b), M[7];
+    for (int i = 0; i < 7; ++i)
+        M[i] = mv_alloc(P, a, b);
+    int rc = 0;
+    mv_addsub(P, A11, A22, 1, SA, a, c);
+    mv_addsub(P, B11, B22, 1, SB, c, b);
+    rc |= strassen_rec(P, levels - 1, a, b, c, SA, SB, M[0]);
+    mv_addsub(P, A21, A22, 1, SA, a, c);
+    rc |= strassen_rec(P, levels - 1, a, b, c, SA, B11, M[1]);
+    mv_addsub(P, B12, B22, -1, SB, c, b);
+    rc |= strassen_rec(P, levels - 1, a, b, c, A11, SB, M[2]);
+    mv_addsub(P, B21, B11, -1, SB, c, b);
+    rc |= strassen_rec(P, levels - 1, a, b, c, A22, SB, M[3]);
+    mv_addsub(P, A11, A12, 1, SA, a, c);
+    rc |= strassen_rec(P, levels - 1, a, b, c, SA, B22, M[4]);
+    mv_addsub(P, A21, A11, -1, SA, a, c);
+    mv_addsub(P, B11, B12, 1, SB, c, b);
+    rc |= strassen_rec(P, levels - 1, a, b, c, SA, SB, M[5]);
+    mv_addsub(P, A12, A22, -1, SA, a, c);
+    mv_addsub(P, B21, B22, 1, SB, c, b);
+    rc |= strassen_rec(P, levels - 1, a, b, c, SA, SB, M[6]);
+    /* C11 = M1 + M4 - M5 + M7, C12 = M3 + M5, C21 = M2 + M4, C22 = M1 - M2 + M3 + M6 */
+    mv_addsub(P, M[0], M[3], 1, C11, a, b);
+    mv_addsub(P, C11, M[4], -1, C11, a, b);
+    mv_addsub(P, C11, M[6], 1, C11, a, b);
+    mv_addsub(P, M[2], M[4], 1, C12, a, b);
+    mv_addsub(P, M[1], M[3], 1, C21, a, b);
+    mv_addsub(P, M[0], M[1], -1, C22, a, b);
+    mv_addsub(P, C22, M[2], 1, C22, a, b);
+    mv_addsub(P, C22, M[5], 1, C22, a, b);
+    free(SA.p);
+    free(SB.p);
+    for (int i = 0; i < 7; ++i)
+        free(M[i].p);
+    return rc;
+}
+
+/* C = alpha op(A) op(B) + beta C with the product from `levels` levels of
+ * Strassen's method; m, n, k must be multiples of 2^levels (else -2). */
+EXPORT int ref_gemm_strassen(int P, int levels, char ta, char tb, int64_t m, int64_t n, int64_t k,
+                             const double *alpha, const double *A, int64_t lda, int64_t sa,
+                             const double *B, int64_t ldb, int64_t sb, const double *beta,
+                             double *C, int64_t ldc, int64_t sc)
+{
+    if (P < 2 || P > 4 || levels < 0)
+        return -1;
+    int64_t unit = (int64_t)1 << levels;
+    if (m % unit || n % unit || k % unit)
+        return -2;
+    int az = mp_is_zero(P, alpha) || k == 0;
+    if (m == 0 || n == 0 || (az && mp_is_one(P, beta)))
+        return 0;
+    mview X = {(double *)A, lda, sa, is_trans(ta)}, Y = {(double *)B, ldb, sb, is_trans(tb)};
+    mview PR = mv_alloc(P, m, n);
+    int rc = az ? 0 : strassen_rec(P, levels, m, n, k, X, Y, PR);
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < m; ++i) {
+            double acc[4], cv[4];
+            mv_get(P, PR, i, j, acc);
+            for (int c = 0; c < P; ++c)
+                cv[c] = C[c * sc + i + j * ldc];
+            epilogue(P, 0, alpha, acc, beta, cv, az);
+            for (int c = 0; c < P; ++c)
+                C[c * sc + i + j * ldc] = cv[c];
+        }
+    free(PR.p);
+    return rc;
+}
+
 EXPORT int ref_num_threads(void)
 {
 #ifdef _OPENMP

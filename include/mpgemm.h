@@ -67,6 +67,9 @@ extern "C" {
                                    recombination into P components          */
 #define MPGEMM_FORM_AUTO 2      /* tuned choice between the two (plain when
                                    no workspace is given)                   */
+#define MPGEMM_FORM_STRASSEN 4  /* Strassen's method (Sec. 3, Fig. 5): opts.levels
+                                   levels of the seven-product recursion over
+                                   plain-form block products               */
 
 /* TD operation variants (Sec. 2.3).  The defaults are TDaddq (the QD
  * addition on zero fourth components) and the "fast" triple-word product
@@ -88,8 +91,11 @@ typedef struct mpgemm_opts {
     int variant;            /* TD only, plain form: MPGEMM_TD_* bits selecting
                                the other TD operations of Sec. 2.3 (runs TD
                                tile configuration 0); 0 = the defaults      */
-    void* workspace;        /* split form: device scratch owned by the caller  */
+    void* workspace;        /* split / Strassen form: device scratch owned by
+                               the caller                                   */
     size_t workspace_bytes; /* its size; see mpgemm_workspace_bytes()          */
+    int levels;             /* Strassen form: recursion levels L (1..8; 0 = 1);
+                               m, n, k must be multiples of 2^L            */
 } mpgemm_opts;
 
 /*
@@ -137,6 +143,19 @@ int mpgemm_qd(char transa, char transb, int64_t m, int64_t n, int64_t k, const d
  * mpgemm_workspace_bytes() bytes (device memory the caller owns; no
  * allocation on this path).  Supported for k * s <= 2^19 (exact 32-bit
  * accumulation); larger k returns MPGEMM_ERR_UNSUPPORTED.
+ * form = MPGEMM_FORM_STRASSEN: C = alpha P + beta C (the plain epilogue) with
+ * P from opts->levels levels of Strassen's method: op(A), op(B) and P cut into
+ * 2 x 2 blocks, P from the seven block products
+ *   M1 = (A11 + A22)(B11 + B22), M2 = (A21 + A22) B11, M3 = A11 (B12 - B22),
+ *   M4 = A22 (B21 - B11), M5 = (A11 + A12) B22, M6 = (A21 - A11)(B11 + B12),
+ *   M7 = (A12 - A22)(B21 + B22); P11 = M1 + M4 - M5 + M7, P12 = M3 + M5,
+ *   P21 = M2 + M4, P22 = M1 - M2 + M3 + M6
+ * (sums left to right, x - y as x + (-y) with exact negation), recursively;
+ * the bottom blocks are plain-form products.  Deterministic; its error bound
+ * is normwise (Strassen's), not componentwise.  m, n, k not multiples of
+ * 2^levels return MPGEMM_ERR_UNSUPPORTED; needs opts->workspace (256-byte
+ * aligned) of mpgemm_workspace_bytes(prec, MPGEMM_FORM_STRASSEN, m, n, k,
+ * levels, -1) bytes.
  * opts->variant (TD, plain form only; MPGEMM_ERR_UNSUPPORTED for another
  * precision or the split form, -18 outside 0..3): the same canonical
  * evaluation with the accurate TD addition (MPGEMM_TD_ADD_ACCURATE) and / or
@@ -157,8 +176,10 @@ int mpgemm_qd_ex(char transa, char transb, int64_t m, int64_t n, int64_t k, cons
                  int64_t c_plane_stride, hipStream_t stream, const mpgemm_opts* opts);
 
 /* Workspace bytes the split form needs for this shape (0 for the plain form;
- * slices 0 = default; tile -1 = the one the library would pick).  Returns 0
- * for invalid arguments. */
+ * slices 0 = default; tile -1 = the one the library would pick); for
+ * MPGEMM_FORM_STRASSEN, `slices` is the number of levels (0 = 1) and the
+ * result is 8 P (m n + sum over levels of (m k + k n + 7 m n) / 4^level)
+ * bytes.  Returns 0 for invalid arguments. */
 size_t mpgemm_workspace_bytes(int prec, int form, int64_t m, int64_t n, int64_t k, int slices,
                               int tile);
 

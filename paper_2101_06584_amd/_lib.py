@@ -17,13 +17,13 @@ _i64, _int, _ch, _vp, _sz, _dbl = C.c_int64, C.c_int, C.c_char, C.c_void_p, C.c_
 _P = C.POINTER
 
 ERR_HIP, ERR_WORKSPACE, ERR_UNSUPPORTED, ERR_GRAPH, ERR_ALIAS, ERR_NOMEM = 1, 2, 3, 4, 5, 6
-FORM_PLAIN, FORM_SPLIT_I8, FORM_AUTO = 0, 1, 2
+FORM_PLAIN, FORM_SPLIT_I8, FORM_AUTO, FORM_STRASSEN = 0, 1, 2, 4
 TD_ADD_ACCURATE, TD_MULQ = 1, 2
 
 
 class Opts(C.Structure):
     _fields_ = [("form", _int), ("slices", _int), ("tile", _int), ("variant", _int),
-                ("workspace", _vp), ("workspace_bytes", _sz)]
+                ("workspace", _vp), ("workspace_bytes", _sz), ("levels", _int)]
 
 
 class Problem(C.Structure):

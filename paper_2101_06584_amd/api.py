@@ -14,7 +14,8 @@ import torch
 from . import _lib
 
 PREC = {"dd": 2, "td": 3, "qd": 4, 2: 2, 3: 3, 4: 4}
-FORMS = {"plain": _lib.FORM_PLAIN, "split": _lib.FORM_SPLIT_I8, "auto": _lib.FORM_AUTO}
+FORMS = {"plain": _lib.FORM_PLAIN, "split": _lib.FORM_SPLIT_I8, "auto": _lib.FORM_AUTO,
+         "strassen": _lib.FORM_STRASSEN}
 DEFAULT_SLICES = {2: 16, 3: 23, 4: 31}
 _NAME = {2: "dd", 3: "td", 4: "qd"}
 
@@ -63,8 +64,10 @@ TD_VARIANTS = {"default": 0, "add_acc": _lib.TD_ADD_ACCURATE, "mulq": _lib.TD_MU
                "add_acc+mulq": _lib.TD_ADD_ACCURATE | _lib.TD_MULQ}
 
 
-def make_opts(form="plain", slices=0, tile=-1, workspace: torch.Tensor | None = None, variant=0):
+def make_opts(form="plain", slices=0, tile=-1, workspace: torch.Tensor | None = None, variant=0,
+              levels=0):
     o = _lib.Opts()
+    o.levels = int(levels)
     o.form = FORMS[form] if isinstance(form, str) else int(form)
     o.slices = int(slices)
     o.tile = int(tile)
@@ -84,13 +87,18 @@ def workspace_bytes(prec, form, m, n, k, slices=0, tile=-1) -> int:
     return int(_lib.load().mpgemm_workspace_bytes(P, f, m, n, k, slices, tile))
 
 
-def alloc_workspace(prec, m, n, k, slices=0, tile=-1, device=None) -> torch.Tensor:
-    nbytes = workspace_bytes(prec, "split", m, n, k, slices, tile)
+def alloc_workspace(prec, m, n, k, slices=0, tile=-1, device=None, form="split", levels=0) -> torch.Tensor:
+    """Device workspace for the split form (slices, tile) or, with
+    form="strassen", for `levels` levels of Strassen's method."""
+    if form == "strassen":
+        nbytes = workspace_bytes(prec, "strassen", m, n, k, levels, -1)
+    else:
+        nbytes = workspace_bytes(prec, "split", m, n, k, slices, tile)
     return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device or "cuda")
 
 
 def gemm_raw(prec, transa, transb, m, n, k, alpha, A, B, beta, C_, *, form=None, slices=0,
-             tile=-1, workspace=None, stream=None, variant=0) -> int:
+             tile=-1, workspace=None, stream=None, variant=0, levels=0) -> int:
     """Calls mpgemm_{dd,td,qd}[_ex]; returns the library's status code.
     variant (TD, plain form): "add_acc" (Algorithm 3), "mulq" (TDmulq), both,
     or the MPGEMM_TD_* bits."""
@@ -105,7 +113,7 @@ def gemm_raw(prec, transa, transb, m, n, k, alpha, A, B, beta, C_, *, form=None,
     if form is None and not variant:
         return getattr(L, name)(*args)
     return getattr(L, name + "_ex")(*args, C.byref(make_opts(form or "plain", slices, tile, workspace,
-                                                               variant)))
+                                                               variant, levels)))
 
 
 def gemm(prec, transa, transb, m, n, k, alpha, A, B, beta, C_, **kw) -> None:

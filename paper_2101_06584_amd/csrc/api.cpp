@@ -38,6 +38,7 @@ namespace {
 
 const int kDefaultSlices[5] = {0, 0, 16, 23, 31};
 const int kMaxSlices = 40;
+const int kMaxStrassenLevels = 8;
 
 bool valid_trans(char t) {
     return t == 'N' || t == 'n' || t == 'T' || t == 't' || t == 'C' || t == 'c';
@@ -158,6 +159,11 @@ int pick_tile(int P, int form, int64_t m, int64_t n, int64_t k, int requested) {
 
 bool split_k_ok(int64_t k, int s) { return (int64_t)s * k <= 524287; }
 
+// plain tile for a Strassen bottom block (tuned choice, else the default)
+int plain_tile_for(int P, int64_t m, int64_t n, int64_t k) {
+    return pick_tile(P, MPGEMM_FORM_PLAIN, m, n, k, -1);
+}
+
 int gemm_common(int P, char ta, char tb, int64_t m, int64_t n, int64_t k, const double* alpha,
                 const double* A, int64_t lda, int64_t sa, const double* B, int64_t ldb, int64_t sb,
                 const double* beta, double* C, int64_t ldc, int64_t sc, hipStream_t st,
@@ -167,19 +173,33 @@ int gemm_common(int P, char ta, char tb, int64_t m, int64_t n, int64_t k, const 
     if (rc) return rc;
     if (has_opts) {
         if (!opts) return -18;
-        if (opts->form < 0 || opts->form > 2) return -18;
+        if (opts->form < 0 || opts->form > 4 || opts->form == 3) return -18;
         if (opts->slices < 0 || opts->slices > kMaxSlices) return -18;
         if (opts->variant < 0 || opts->variant > 3) return -18;
+        if (opts->levels < 0 || opts->levels > kMaxStrassenLevels) return -18;
     }
     const int variant = has_opts ? opts->variant : 0;
     // the TD variants exist for the plain form only
-    if (variant != 0 && (P != 3 || opts->form == MPGEMM_FORM_SPLIT_I8 || last_stage > 0))
+    if (variant != 0 && (P != 3 || opts->form == MPGEMM_FORM_SPLIT_I8 ||
+                         opts->form == MPGEMM_FORM_STRASSEN || last_stage > 0))
         return MPGEMM_ERR_UNSUPPORTED;
+    const bool strassen = has_opts && opts->form == MPGEMM_FORM_STRASSEN && last_stage <= 0;
+    const int levels = strassen ? (opts->levels > 0 ? opts->levels : 1) : 0;
+    if (strassen) {
+        const int64_t unit = (int64_t)1 << levels;
+        if (m % unit || n % unit || k % unit) return MPGEMM_ERR_UNSUPPORTED;
+    }
     if (m == 0 || n == 0) return 0;
     const bool az = (k == 0) || mp_zero(P, alpha);
     if (az && mp_one(P, beta)) return 0;
     if (az) return hip_rc(variant ? launch_scale_td_variant(variant, g, st) : launch_scale(P, g, st));
     if (variant) return hip_rc(launch_plain_td_variant(variant, g, st));
+    if (strassen) {
+        const size_t need = strassen_workspace_bytes(P, levels, m, n, k);
+        if (!opts->workspace || opts->workspace_bytes < need) return MPGEMM_ERR_WORKSPACE;
+        if ((uintptr_t)opts->workspace % 256 != 0) return MPGEMM_ERR_WORKSPACE;
+        return hip_rc(launch_strassen(P, levels, g, opts->workspace, st, &plain_tile_for));
+    }
 
     int form = has_opts ? opts->form : MPGEMM_FORM_PLAIN;
     const int s = (has_opts && opts->slices > 0) ? opts->slices : kDefaultSlices[P];
@@ -234,6 +254,11 @@ size_t mpgemm_workspace_bytes(int prec, int form, int64_t m, int64_t n, int64_t 
     if (prec < 2 || prec > 4 || m < 0 || n < 0 || k < 0 || slices < 0 || slices > kMaxSlices)
         return 0;
     if (form == MPGEMM_FORM_PLAIN) return 0;
+    if (form == MPGEMM_FORM_STRASSEN) {
+        const int levels = slices > 0 ? slices : 1;
+        if (levels > kMaxStrassenLevels) return 0;
+        return strassen_workspace_bytes(prec, levels, m, n, k);
+    }
     if (form != MPGEMM_FORM_SPLIT_I8 && form != MPGEMM_FORM_AUTO) return 0;
     const int s = slices > 0 ? slices : kDefaultSlices[prec];
     const int cfg = pick_tile(prec, MPGEMM_FORM_SPLIT_I8, m, n, k, tile);

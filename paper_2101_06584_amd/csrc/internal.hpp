@@ -35,6 +35,11 @@ int plain_default_config(int P, int64_t m, int64_t n, int64_t k);
 int launch_plain(int P, int cfg, const GemmArgs& g, hipStream_t st);
 int launch_scale(int P, const GemmArgs& g, hipStream_t st);   // alpha == 0 or k == 0
 int launch_plain_td_variant(int variant, const GemmArgs& g, hipStream_t st);
+
+// Strassen's method over the plain form (strassen.hip).
+size_t strassen_workspace_bytes(int P, int levels, int64_t m, int64_t n, int64_t k);
+int launch_strassen(int P, int levels, const GemmArgs& g, void* ws, hipStream_t st,
+                    int (*pick)(int, int64_t, int64_t, int64_t));
 int launch_scale_td_variant(int variant, const GemmArgs& g, hipStream_t st);
 int launch_vec(int P, int op, int64_t n, const double* x, int64_t sx, const double* y,
                int64_t sy, double* r, int64_t sr, hipStream_t st);

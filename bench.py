@@ -106,6 +106,8 @@ def parse():
     ap.add_argument("--vec-n", type=int, default=1 << 26, help="vector length for --vec")
     ap.add_argument("--td-variants", action="store_true",
                     help="accuracy and speed of the TD operation variants (Sec. 2.3)")
+    ap.add_argument("--strassen", action="store_true",
+                    help="Strassen's method (Sec. 3, Fig. 5) against the plain form, n = 4096")
     return ap.parse_args()
 
 
@@ -144,6 +146,8 @@ def main():
         return vec_bench(args, mp, dev, stream)
     if args.td_variants:
         return td_variants_bench(args, mp, synth, dev, stream)
+    if args.strassen:
+        return strassen_bench(args, mp, synth, dev, stream)
     n = args.n
     precs = [int(p) for p in args.prec.split(",")]
     forms = args.forms.split(",")
@@ -342,6 +346,76 @@ def main():
 
 
 PREC_OF = {"DD": 2, "TD": 3, "QD": 4}
+
+
+def strassen_bench(args, mp, synth, dev, stream):
+    """C = A B at m = n = k = args.n in DD/TD/QD: the plain form against 1..4
+    levels of Strassen's method over it.  Time (2 n^3 counted as the work, as
+    for the plain form) and error on sampled entries, both componentwise
+    (k u |A||B|) and normwise (u max|A| max|B| n).  One JSON line."""
+    import numpy as np
+    import torch
+    from tests.exact import GemmChecker, mp_frac, sample_entries
+    n = args.n
+    parts = {}
+    for P in (2, 3, 4):
+        A = synth.mp_matrix(2, "A", P, n, n)
+        B = synth.mp_matrix(2, "B", P, n, n)
+        dA, dB = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+        one, zero = synth.mp_one(P), np.zeros(P)
+        chk = GemmChecker(P, "N", "N", n, n, n, one, A, B, zero, np.zeros((P, n, 1)))
+        ents = sample_entries(synth.rng_for(2, "samples"), n, n, 32)
+        u = 2.0 ** -{2: 104, 3: 150, 4: 200}[P]
+        norm = u * float(np.abs(A[0]).max()) * float(np.abs(B[0]).max()) * n
+        base_ms = None
+        for L in (0, 1, 2, 3, 4):
+            dC = torch.zeros((P, n, n), dtype=torch.float64, device=dev)
+            if L == 0:
+                call = lambda: mp.gemm(P, "N", "N", n, n, n, one, dA, dB, zero, dC, stream=stream)  # noqa: E731
+            else:
+                ws = mp.alloc_workspace(P, n, n, n, form="strassen", levels=L, device=dev)
+                call = lambda: mp.gemm(P, "N", "N", n, n, n, one, dA, dB, zero, dC,  # noqa: E731
+                                       form="strassen", levels=L, workspace=ws, stream=stream)
+            call()
+            torch.cuda.synchronize()
+            times = []
+            for _ in range(max(3, args.steps)):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                call()
+                e1.record(stream)
+                torch.cuda.synchronize()
+                times.append(e0.elapsed_time(e1))
+            ms = float(np.median(times))
+            base_ms = ms if L == 0 else base_ms
+            got = dC.cpu().numpy()
+            comp = chk.ratios(got, ents)
+            nw = 0.0
+            for i, j in ents:
+                exact, _ = chk.entry(i, j)
+                nw = max(nw, float(abs(mp_frac(got[:, j, i]) - exact)) / norm)
+            parts[f"{NAME[P]}_L{L}"] = {"ms": round(ms, 3), "2mnk/s": 2.0 * n ** 3 / (ms * 1e-3),
+                                        "speedup_vs_plain": round(base_ms / ms, 4),
+                                        "err_ratio_max": float(comp.max()), "normwise_err": nw}
+            note("strassen", NAME[P], "L", L, round(ms, 2), "ms", f"{comp.max():.3g}", f"{nw:.3g}")
+            del dC
+            if L > 0:
+                del ws
+            torch.cuda.empty_cache()
+        del dA, dB
+    total_ms = sum(v["ms"] for v in parts.values())
+    out = {"metric": "DD/TD/QD GEMM 2mnk/s, plain vs Strassen levels", "unit": "2mnk/s",
+           "value": 2.0 * n ** 3 * len(parts) / (total_ms * 1e-3), "n_gpus": 1,
+           "steps": max(3, args.steps), "warmup": 1, "ms_per_step": round(total_ms, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"C = A B, m = n = k = {n}, DD/TD/QD, plain form and 1..4 levels of "
+                                  "Strassen's method over it", "n": n,
+                      "err_units": "err_ratio_max: |C - C*| / (k u |A||B|); normwise_err: |C - C*| / "
+                                   "(u max|A| max|B| n); 32 sampled entries"},
+           "breakdown": parts}
+    print(json.dumps(out), flush=True)
 
 
 TD_VARIANT_NAMES = {0: "TDaddq+TDmul", 1: "TDadd+TDmul", 2: "TDaddq+TDmulq", 3: "TDadd+TDmulq"}

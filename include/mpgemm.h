@@ -94,7 +94,7 @@ typedef struct mpgemm_opts {
     void* workspace;        /* split / Strassen form: device scratch owned by
                                the caller                                   */
     size_t workspace_bytes; /* its size; see mpgemm_workspace_bytes()          */
-    int levels;             /* Strassen form: recursion levels L (1..8; 0 = 1);
+    int levels;             /* Strassen form: recursion levels L (1..5; 0 = 1);
                                m, n, k must be multiples of 2^L            */
 } mpgemm_opts;
 
@@ -177,9 +177,10 @@ int mpgemm_qd_ex(char transa, char transb, int64_t m, int64_t n, int64_t k, cons
 
 /* Workspace bytes the split form needs for this shape (0 for the plain form;
  * slices 0 = default; tile -1 = the one the library would pick); for
- * MPGEMM_FORM_STRASSEN, `slices` is the number of levels (0 = 1) and the
- * result is 8 P (m n + sum over levels of (m k + k n + 7 m n) / 4^level)
- * bytes.  Returns 0 for invalid arguments. */
+ * MPGEMM_FORM_STRASSEN, `slices` is the number of levels L (0 = 1) and the
+ * result is 8 P (m n + sum over l = 1..L of 7^l (m k + k n + m n) / 4^l)
+ * bytes (the product and, per level, operands and results of its 7^l
+ * nodes).  Returns 0 for invalid arguments. */
 size_t mpgemm_workspace_bytes(int prec, int form, int64_t m, int64_t n, int64_t k, int slices,
                               int tile);
 

@@ -38,7 +38,7 @@ namespace {
 
 const int kDefaultSlices[5] = {0, 0, 16, 23, 31};
 const int kMaxSlices = 40;
-const int kMaxStrassenLevels = 8;
+const int kMaxStrassenLevels = 5;
 
 bool valid_trans(char t) {
     return t == 'N' || t == 'n' || t == 'T' || t == 't' || t == 'C' || t == 'c';

@@ -33,6 +33,9 @@ int plain_default_config(int P, int64_t m, int64_t n, int64_t k);
 
 // Launchers return a hipError_t value (0 on success).
 int launch_plain(int P, int cfg, const GemmArgs& g, hipStream_t st);
+// `batch` equal-shape products, problem z at A + z zA, B + z zB, C + z zC
+int launch_plain_strided(int P, int cfg, const GemmArgs& g, int64_t batch, int64_t zA, int64_t zB,
+                         int64_t zC, hipStream_t st);
 int launch_scale(int P, const GemmArgs& g, hipStream_t st);   // alpha == 0 or k == 0
 int launch_plain_td_variant(int variant, const GemmArgs& g, hipStream_t st);
 

@@ -162,6 +162,25 @@ __global__ __launch_bounds__(TX * TY) void plain_gemm_kernel(GemmArgs g) {
     T::run(g, alpha, beta, tm * T::BM, tn * T::BN, lds);
 }
 
+// Strided batch of equal-shape products (Strassen's leaves): problem z =
+// blockIdx.y uses A + z zA, B + z zB, C + z zC; alpha and beta from g.
+template <int P, int TX, int TY, int TM, int TN, int BK>
+__global__ __launch_bounds__(TX * TY) void plain_gemm_strided_kernel(GemmArgs g, int64_t zA, int64_t zB,
+                                                                      int64_t zC) {
+    using T = PlainTile<P, TX, TY, TM, TN, BK>;
+    __shared__ double lds[T::LDS_DOUBLES];
+    int64_t tm, tn;
+    if (!xcd_tile_coords<8>(blockIdx.x, (g.m + T::BM - 1) / T::BM, (g.n + T::BN - 1) / T::BN, tm, tn))
+        return;
+    const int64_t z = blockIdx.y;
+    g.A += z * zA;
+    g.B += z * zB;
+    g.C += z * zC;
+    const mp<P> alpha = load_scalar<P>(g.alpha);
+    const mp<P> beta = load_scalar<P>(g.beta);
+    T::run(g, alpha, beta, tm * T::BM, tn * T::BN, lds);
+}
+
 // ---------------------------------------------------------------------------
 // Persistent batched kernel: one launch, many GEMMs, a global tile queue.
 // ---------------------------------------------------------------------------
@@ -308,6 +327,26 @@ static int launch_batch_t(int64_t count, int64_t total, const void* desc, unsign
     hipLaunchKernelGGL((batch_gemm_kernel<P, TX, TY, TM, TN, BK>), dim3(grid), dim3(T::NT), 0, st,
                        (const BatchDesc*)desc, count, total, counter);
     return (int)hipGetLastError();
+}
+
+template <int P, int TX, int TY, int TM, int TN, int BK>
+static int launch_plain_strided_t(const GemmArgs& g, int64_t batch, int64_t zA, int64_t zB, int64_t zC,
+                                  hipStream_t st) {
+    using T = PlainTile<P, TX, TY, TM, TN, BK>;
+    const int64_t grid = xcd_grid(((g.m + T::BM - 1) / T::BM) * ((g.n + T::BN - 1) / T::BN));
+    if (grid > 0x7fffffffLL || batch > 65535) return (int)hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((plain_gemm_strided_kernel<P, TX, TY, TM, TN, BK>),
+                       dim3((unsigned)grid, (unsigned)batch), dim3(T::NT), 0, st, g, zA, zB, zC);
+    return (int)hipGetLastError();
+}
+
+int launch_plain_strided(int P, int cfg, const GemmArgs& g, int64_t batch, int64_t zA, int64_t zB,
+                         int64_t zC, hipStream_t st) {
+#define MPG_CASE(PP, ID, TX, TY, TM, TN, BK) \
+    if (P == PP && cfg == ID) return launch_plain_strided_t<PP, TX, TY, TM, TN, BK>(g, batch, zA, zB, zC, st);
+    MPG_PLAIN_LIST(MPG_CASE)
+#undef MPG_CASE
+    return (int)hipErrorInvalidValue;
 }
 
 int launch_plain(int P, int cfg, const GemmArgs& g, hipStream_t st) {

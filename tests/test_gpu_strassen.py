@@ -36,6 +36,8 @@ CASES = [
     (4, 2, "N", "T", 32, 96, 64),
     (2, 3, "T", "T", 128, 64, 128),
     (3, 1, "N", "N", 2, 2, 2),
+    (4, 4, "T", "N", 48, 32, 16),
+    (2, 5, "N", "N", 64, 64, 64),
 ]
 
 

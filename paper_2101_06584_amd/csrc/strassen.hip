@@ -214,7 +214,8 @@ static int strassen_bfs(int levels, const GemmArgs& g, double* ws, hipStream_t s
         lg.B = YB[levels]; lg.ldb = q; lg.sb = q * w;
         lg.C = R[levels]; lg.ldc = h; lg.sc = h * w;
         lg.alpha[0] = 1.0;
-        rc = launch_plain_strided(P, pick(P, h, w, q), lg, pow7(levels), (int64_t)P * h * q,
+        // the batch as a whole is as parallel as the full product: tile for that
+        rc = launch_plain_strided(P, pick(P, g.m, g.n, q), lg, pow7(levels), (int64_t)P * h * q,
                                   (int64_t)P * q * w, (int64_t)P * h * w, st);
         if (rc) return rc;
     }

@@ -40,6 +40,13 @@ def lib():
                                         _i64, _i64, C.c_void_p, _i64, _i64, C.c_void_p, C.c_void_p,
                                         _i64, _i64]
         L.ref_gemm_strassen.restype = _int
+        L.ref_axpy.argtypes = [_int, _i64, C.c_void_p, C.c_void_p, _i64, C.c_void_p, _i64]
+        L.ref_axpy.restype = _int
+        L.ref_dot.argtypes = [_int, _i64, C.c_void_p, _i64, C.c_void_p, _i64, C.c_void_p]
+        L.ref_dot.restype = _int
+        L.ref_gemv.argtypes = [_int, _ch, _i64, _i64, C.c_void_p, C.c_void_p, _i64, _i64, C.c_void_p, _i64,
+                               C.c_void_p, C.c_void_p, _i64]
+        L.ref_gemv.restype = _int
         L.ref_gemm_split.argtypes = [_int, _int, _ch, _ch, _i64, _i64, _i64, C.c_void_p, C.c_void_p, _i64,
                                      _i64, C.c_void_p, _i64, _i64, C.c_void_p, C.c_void_p, _i64, _i64,
                                      _i64, _i64, _i64, _i64, _int, C.c_void_p, C.c_void_p, C.c_void_p]
@@ -114,6 +121,40 @@ def gemm(P, ta, tb, m, n, k, alpha, A, B, beta, C, rows=None, cols=None, nthread
                           Cout.shape[1] * Cout.shape[2], r0, r1, c0, c1, nthreads)
     assert rc == 0, rc
     return Cout
+
+
+def axpy(P, alpha, x, y):
+    """Returns alpha x + y for (P, n) arrays, element by element."""
+    x = _f64(x)
+    yo = _f64(y).copy()
+    n = x.shape[1]
+    rc = lib().ref_axpy(P, n, _ptr(_f64(alpha)), _ptr(x), n, _ptr(yo), n)
+    assert rc == 0, rc
+    return yo
+
+
+def dot(P, x, y):
+    """The dot product of (P, n) arrays in the fixed 64-ary tree order."""
+    x = _f64(x)
+    y = _f64(y)
+    n = x.shape[1]
+    r = np.zeros(P)
+    rc = lib().ref_dot(P, n, _ptr(x), n, _ptr(y), n, _ptr(r))
+    assert rc == 0, rc
+    return r
+
+
+def gemv(P, trans, m, n, alpha, A, x, beta, y):
+    """y = alpha op(A) x + beta y; A is (P, n, lda) column-major m x n; x, y are
+    (P, len) arrays.  Returns a new y."""
+    A = _f64(A)
+    x = _f64(x)
+    yo = _f64(y).copy()
+    rc = lib().ref_gemv(P, trans.encode(), m, n, _ptr(_f64(alpha)), _ptr(A), A.shape[2],
+                        A.shape[1] * A.shape[2], _ptr(x), x.shape[1], _ptr(_f64(beta)), _ptr(yo),
+                        yo.shape[1])
+    assert rc == 0, rc
+    return yo
 
 
 def gemm_strassen(P, levels, ta, tb, m, n, k, alpha, A, B, beta, C):

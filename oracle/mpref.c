@@ -951,6 +951,97 @@ EXPORT int ref_gemm_strassen(int P, int levels, char ta, char tb, int64_t m, int
     return rc;
 }
 
+/* ------------------------------------------------------------------------ */
+/* BLAS-1/2 in DD/TD/QD (the vector kernels the paper lists beside its      */
+/* Strassen code, Sec. 4).  Readings:                                        */
+/*   axpy: y_i = ADD(MUL(alpha, x_i), y_i);                                  */
+/*   gemv: y = alpha op(A) x + beta y, each entry in the canonical GEMM      */
+/*         order, i.e. exactly the GEMM with one column;                     */
+/*   dot:  a 64-ary tree in a fixed order: the n products are taken in       */
+/*         blocks of 64 consecutive terms, each block summed from zero in    */
+/*         ascending order (acc = ADD(acc, MUL(x_i, y_i))); the block sums   */
+/*         are again taken 64 at a time and summed the same way, until one   */
+/*         value is left.  For n <= 64 this is the sequential chain.         */
+/* ------------------------------------------------------------------------ */
+
+#define DOT_FANIN 64
+
+EXPORT int ref_axpy(int P, int64_t n, const double *alpha, const double *x, int64_t sx, double *y,
+                    int64_t sy)
+{
+    if (P < 2 || P > 4)
+        return -1;
+    for (int64_t i = 0; i < n; ++i) {
+        double a[4], b[4], t[4], r[4];
+        for (int c = 0; c < P; ++c) {
+            a[c] = x[c * sx + i];
+            b[c] = y[c * sy + i];
+        }
+        mp_mul(P, alpha, a, t);
+        mp_add(P, t, b, r);
+        for (int c = 0; c < P; ++c)
+            y[c * sy + i] = r[c];
+    }
+    return 0;
+}
+
+EXPORT int ref_dot(int P, int64_t n, const double *x, int64_t sx, const double *y, int64_t sy,
+                   double *result)
+{
+    if (P < 2 || P > 4)
+        return -1;
+    if (n <= 0) {
+        for (int c = 0; c < P; ++c) result[c] = 0.0;
+        return 0;
+    }
+    /* level 0: block sums of products */
+    int64_t cnt = (n + DOT_FANIN - 1) / DOT_FANIN;
+    double *part = (double *)malloc((size_t)cnt * P * sizeof(double));
+    for (int64_t b = 0; b < cnt; ++b) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int64_t i = b * DOT_FANIN; i < n && i < (b + 1) * DOT_FANIN; ++i) {
+            double a[4], e[4], p[4], t[4];
+            for (int c = 0; c < P; ++c) {
+                a[c] = x[c * sx + i];
+                e[c] = y[c * sy + i];
+            }
+            mp_mul(P, a, e, p);
+            mp_add(P, acc, p, t);
+            for (int c = 0; c < P; ++c) acc[c] = t[c];
+        }
+        for (int c = 0; c < P; ++c) part[b * P + c] = acc[c];
+    }
+    /* higher levels: block sums of block sums */
+    while (cnt > 1) {
+        int64_t next = (cnt + DOT_FANIN - 1) / DOT_FANIN;
+        for (int64_t b = 0; b < next; ++b) {
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int64_t i = b * DOT_FANIN; i < cnt && i < (b + 1) * DOT_FANIN; ++i) {
+                double t[4];
+                mp_add(P, acc, &part[i * P], t);
+                for (int c = 0; c < P; ++c) acc[c] = t[c];
+            }
+            for (int c = 0; c < P; ++c) part[b * P + c] = acc[c];   /* b <= i: in place is safe */
+        }
+        cnt = next;
+    }
+    for (int c = 0; c < P; ++c) result[c] = part[c];
+    free(part);
+    return 0;
+}
+
+/* y (length rows of op(A)) = alpha op(A) x + beta y, A stored m x n (column-
+ * major, planes at sa); x, y planes at sx, sy.  The GEMM with one column. */
+EXPORT int ref_gemv(int P, char trans, int64_t m, int64_t n, const double *alpha, const double *A,
+                    int64_t lda, int64_t sa, const double *x, int64_t sx, const double *beta,
+                    double *y, int64_t sy)
+{
+    int t = is_trans(trans);
+    int64_t rows = t ? n : m, inner = t ? m : n;
+    return ref_gemm(P, trans, 'N', rows, 1, inner, alpha, A, lda, sa, x, inner > 0 ? inner : 1, sx,
+                    beta, y, rows > 0 ? rows : 1, sy, 0, -1, 0, -1, 0);
+}
+
 EXPORT int ref_num_threads(void)
 {
 #ifdef _OPENMP

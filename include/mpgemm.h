@@ -211,6 +211,61 @@ int mp_vec_td_mulq(int64_t n, const double* x, int64_t sx, const double* y, int6
                    int64_t sr, hipStream_t stream);
 
 /*
+ * BLAS-1/2 in DD / TD / QD (the vector kernels that accompany the paper's
+ * Strassen code, Sec. 4).  Vectors are P planes of doubles at the given plane
+ * strides (device pointers); scalars are host arrays of P doubles.  Error
+ * codes: -(argument position) as for the GEMM entry points.
+ *
+ * axpy: y_i = ADD(MUL(alpha, x_i), y_i), i < n.  Arguments: 1 n >= 0,
+ *   2 alpha, 3 x, 4 sx >= n, 5 y (may equal x), 6 sy >= n, 7 stream.
+ */
+int mp_axpy_dd(int64_t n, const double* alpha, const double* x, int64_t sx, double* y, int64_t sy,
+               hipStream_t stream);
+int mp_axpy_td(int64_t n, const double* alpha, const double* x, int64_t sx, double* y, int64_t sy,
+               hipStream_t stream);
+int mp_axpy_qd(int64_t n, const double* alpha, const double* x, int64_t sx, double* y, int64_t sy,
+               hipStream_t stream);
+
+/*
+ * dot: result = sum_i x_i y_i in a fixed order: the products in blocks of 64
+ * consecutive terms, each block summed from zero in ascending order
+ * (acc = ADD(acc, MUL(x_i, y_i))), then the block sums 64 at a time the same
+ * way, until one value is left (for n <= 64 the sequential chain).  The
+ * P-component result is written to device memory at `result` (asynchronously,
+ * on the stream).  Partial sums use the caller's workspace of
+ * mp_dot_workspace_bytes(prec, n) bytes (0 when n <= 64; NULL allowed then).
+ * Arguments: 1 n >= 0, 2 x, 3 sx >= n, 4 y, 5 sy >= n, 6 result, 7 workspace,
+ * 8 workspace_bytes (MPGEMM_ERR_WORKSPACE if short), 9 stream.
+ */
+size_t mp_dot_workspace_bytes(int prec, int64_t n);
+int mp_dot_dd(int64_t n, const double* x, int64_t sx, const double* y, int64_t sy, double* result,
+              void* workspace, size_t workspace_bytes, hipStream_t stream);
+int mp_dot_td(int64_t n, const double* x, int64_t sx, const double* y, int64_t sy, double* result,
+              void* workspace, size_t workspace_bytes, hipStream_t stream);
+int mp_dot_qd(int64_t n, const double* x, int64_t sx, const double* y, int64_t sy, double* result,
+              void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * gemv: y = alpha op(A) x + beta y for A stored m x n (column-major, planes at
+ * a_plane_stride), y of length rows(op(A)) and x of length cols(op(A)); each
+ * entry bitwise as the plain GEMM with one column (canonical ascending chain,
+ * same epilogue, C = y never read when beta == 0, quick return when alpha or
+ * the inner length is 0 and beta == 1).  Arguments: 1 trans, 2 m >= 0,
+ * 3 n >= 0, 4 alpha, 5 A, 6 lda >= max(1, m), 7 a_plane_stride >= lda n, 8 x,
+ * 9 sx >= cols(op(A)), 10 beta, 11 y, 12 sy >= rows(op(A)), 13 stream;
+ * MPGEMM_ERR_ALIAS if y overlaps A or x.
+ */
+int mp_gemv_dd(char trans, int64_t m, int64_t n, const double* alpha, const double* A, int64_t lda,
+               int64_t a_plane_stride, const double* x, int64_t sx, const double* beta, double* y,
+               int64_t sy, hipStream_t stream);
+int mp_gemv_td(char trans, int64_t m, int64_t n, const double* alpha, const double* A, int64_t lda,
+               int64_t a_plane_stride, const double* x, int64_t sx, const double* beta, double* y,
+               int64_t sy, hipStream_t stream);
+int mp_gemv_qd(char trans, int64_t m, int64_t n, const double* alpha, const double* A, int64_t lda,
+               int64_t a_plane_stride, const double* x, int64_t sx, const double* beta, double* y,
+               int64_t sy, hipStream_t stream);
+
+/*
  * Batched GEMMs of uneven shapes in one persistent launch (plain form, same
  * per-entry results as one mpgemm_*() call per problem).  A problem is the
  * argument list of mpgemm_dd() as a struct; alpha/beta use the first P

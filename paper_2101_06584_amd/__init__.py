@@ -3,7 +3,8 @@ Instinct MI355X (gfx950): error-free-transformation kernels on the FP64 vector
 ALUs, a split form on the INT8 matrix cores, a batched persistent form and an
 autotuner, behind the C ABI in include/mpgemm.h.  This package is the thin
 Python binding (PyTorch supplies device memory and streams)."""
-from .api import (BatchPlan, DEFAULT_SLICES, MPGemmError, PREC, alloc_workspace, autotune,  # noqa: F401
+from .api import (BatchPlan, DEFAULT_SLICES, MPGemmError, PREC, alloc_workspace, autotune, axpy,  # noqa: F401
+                  dot, dot_raw, dot_workspace, gemv, gemv_raw,
                   autotune_load, autotune_save, autotune_set, batch_autotune, gemm, gemm_raw, load,
                   make_opts, num_configs, probe_peak, split_layout, split_stages, tune_slices, vec, vec_raw,
                   version, workspace_bytes)

@@ -48,6 +48,16 @@ EXPORTS = {
     "mp_vec_td_add": (_VEC_ARGS, _int), "mp_vec_td_mul": (_VEC_ARGS, _int),
     "mp_vec_qd_add": (_VEC_ARGS, _int), "mp_vec_qd_mul": (_VEC_ARGS, _int),
     "mp_vec_td_add_acc": (_VEC_ARGS, _int), "mp_vec_td_mulq": (_VEC_ARGS, _int),
+    "mp_axpy_dd": ([_i64, _P(_dbl), _vp, _i64, _vp, _i64, _vp], _int),
+    "mp_axpy_td": ([_i64, _P(_dbl), _vp, _i64, _vp, _i64, _vp], _int),
+    "mp_axpy_qd": ([_i64, _P(_dbl), _vp, _i64, _vp, _i64, _vp], _int),
+    "mp_dot_workspace_bytes": ([_int, _i64], _sz),
+    "mp_dot_dd": ([_i64, _vp, _i64, _vp, _i64, _vp, _vp, _sz, _vp], _int),
+    "mp_dot_td": ([_i64, _vp, _i64, _vp, _i64, _vp, _vp, _sz, _vp], _int),
+    "mp_dot_qd": ([_i64, _vp, _i64, _vp, _i64, _vp, _vp, _sz, _vp], _int),
+    "mp_gemv_dd": ([_ch, _i64, _i64, _P(_dbl), _vp, _i64, _i64, _vp, _i64, _P(_dbl), _vp, _i64, _vp], _int),
+    "mp_gemv_td": ([_ch, _i64, _i64, _P(_dbl), _vp, _i64, _i64, _vp, _i64, _P(_dbl), _vp, _i64, _vp], _int),
+    "mp_gemv_qd": ([_ch, _i64, _i64, _P(_dbl), _vp, _i64, _i64, _vp, _i64, _P(_dbl), _vp, _i64, _vp], _int),
     "mpgemm_batch_plan_create": ([_int, _i64, _P(Problem), _P(Opts), _vp, _P(_vp)], _int),
     "mpgemm_batch_plan_run": ([_vp, _vp], _int),
     "mpgemm_batch_plan_launch": ([_vp, _vp], _int),

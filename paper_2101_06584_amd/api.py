@@ -282,6 +282,51 @@ def tune_slices(prec, transa, transb, m, n, k, A, B, target=1.0, smin=None, smax
     return s.value, r.value
 
 
+def axpy(prec, alpha, x, y, n=None, stream=None) -> None:
+    """y = alpha x + y element-wise (mp_axpy_*); x, y are (P, n) CUDA tensors."""
+    P = PREC[prec]
+    n = x.shape[-1] if n is None else n
+    rc = getattr(_lib.load(), f"mp_axpy_{_NAME[P]}")(n, _scalar(alpha, P), C.c_void_p(x.data_ptr()),
+                                                     x.stride(0), C.c_void_p(y.data_ptr()), y.stride(0),
+                                                     _stream(stream))
+    _check(rc, "mp_axpy")
+
+
+def dot_workspace(prec, n, device=None) -> torch.Tensor:
+    nbytes = int(_lib.load().mp_dot_workspace_bytes(PREC[prec], n))
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device or "cuda")
+
+
+def dot_raw(prec, x, y, result, workspace=None, n=None, stream=None) -> int:
+    P = PREC[prec]
+    n = x.shape[-1] if n is None else n
+    ws = workspace if workspace is not None else dot_workspace(prec, n, x.device)
+    return getattr(_lib.load(), f"mp_dot_{_NAME[P]}")(
+        n, C.c_void_p(x.data_ptr()), x.stride(0), C.c_void_p(y.data_ptr()), y.stride(0),
+        C.c_void_p(result.data_ptr()), C.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+        _stream(stream))
+
+
+def dot(prec, x, y, result, workspace=None, n=None, stream=None) -> None:
+    """result (P-element CUDA tensor) = x . y in the fixed 64-ary tree order
+    (mp_dot_*); x, y are (P, n) CUDA tensors."""
+    _check(dot_raw(prec, x, y, result, workspace, n, stream), "mp_dot")
+
+
+def gemv_raw(prec, trans, m, n, alpha, A, x, beta, y, stream=None) -> int:
+    P = PREC[prec]
+    a, lda, sa = _mat(A, P)
+    return getattr(_lib.load(), f"mp_gemv_{_NAME[P]}")(
+        trans.encode(), m, n, _scalar(alpha, P), a, lda, sa, C.c_void_p(x.data_ptr()), x.stride(0),
+        _scalar(beta, P), C.c_void_p(y.data_ptr()), y.stride(0), _stream(stream))
+
+
+def gemv(prec, trans, m, n, alpha, A, x, beta, y, stream=None) -> None:
+    """y = alpha op(A) x + beta y (mp_gemv_*): A a (P, n, lda) component-plane
+    m x n matrix, x and y (P, len) CUDA tensors."""
+    _check(gemv_raw(prec, trans, m, n, alpha, A, x, beta, y, stream), "mp_gemv")
+
+
 PROBES = {"fp64_fma": 0, "fp64_add": 1, "fp64_mul": 2, "int8_mfma": 3, "hbm_copy": 4}
 
 

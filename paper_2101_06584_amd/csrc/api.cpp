@@ -21,6 +21,14 @@
 #include "internal.hpp"
 
 namespace mpg {
+int launch_axpy(int P, int64_t n, const double* alpha, const double* x, int64_t sx, double* y, int64_t sy,
+                hipStream_t st);
+size_t dot_workspace_bytes(int P, int64_t n);
+int launch_dot(int P, int64_t n, const double* x, int64_t sx, const double* y, int64_t sy, double* result,
+               void* ws, hipStream_t st);
+int launch_gemv(int P, int t, int64_t rows, int64_t inner, const double* alpha, const double* A, int64_t lda,
+                int64_t sa, const double* x, int64_t sx, const double* beta, double* y, int64_t sy, int az,
+                hipStream_t st);
 int launch_split_stages(int P, int s, int cfg, int last, const GemmArgs& g, void* ws,
                         hipStream_t st);
 int launch_fill(int P, double* X, int64_t plane, int64_t planes_stride, uint64_t seed,
@@ -313,6 +321,89 @@ MPG_VEC(mp_vec_qd_mul, 4, 1)
 MPG_VEC(mp_vec_td_add_acc, 3, 2)
 MPG_VEC(mp_vec_td_mulq, 3, 3)
 #undef MPG_VEC
+
+// ---- BLAS-1/2 ----------------------------------------------------------------
+
+#define MPG_AXPY(NAME, P)                                                                          \
+    int NAME(int64_t n, const double* alpha, const double* x, int64_t sx, double* y, int64_t sy,  \
+             hipStream_t st) {                                                                    \
+        if (n < 0) return -1;                                                                      \
+        if (!alpha) return -2;                                                                     \
+        if (n > 0 && !x) return -3;                                                                \
+        if (sx < n) return -4;                                                                     \
+        if (n > 0 && !y) return -5;                                                                \
+        if (sy < n) return -6;                                                                     \
+        return hip_rc(launch_axpy(P, n, alpha, x, sx, y, sy, st));                                 \
+    }
+MPG_AXPY(mp_axpy_dd, 2)
+MPG_AXPY(mp_axpy_td, 3)
+MPG_AXPY(mp_axpy_qd, 4)
+#undef MPG_AXPY
+
+size_t mp_dot_workspace_bytes(int prec, int64_t n) {
+    if (prec < 2 || prec > 4 || n < 0) return 0;
+    return dot_workspace_bytes(prec, n);
+}
+
+#define MPG_DOT(NAME, P)                                                                           \
+    int NAME(int64_t n, const double* x, int64_t sx, const double* y, int64_t sy, double* result,  \
+             void* ws, size_t ws_bytes, hipStream_t st) {                                          \
+        if (n < 0) return -1;                                                                      \
+        if (n > 0 && !x) return -2;                                                                \
+        if (sx < n) return -3;                                                                     \
+        if (n > 0 && !y) return -4;                                                                \
+        if (sy < n) return -5;                                                                     \
+        if (!result) return -6;                                                                    \
+        const size_t need = dot_workspace_bytes(P, n);                                             \
+        if (need > 0 && !ws) return -7;                                                            \
+        if (ws_bytes < need) return MPGEMM_ERR_WORKSPACE;                                          \
+        return hip_rc(launch_dot(P, n, x, sx, y, sy, result, ws, st));                             \
+    }
+MPG_DOT(mp_dot_dd, 2)
+MPG_DOT(mp_dot_td, 3)
+MPG_DOT(mp_dot_qd, 4)
+#undef MPG_DOT
+
+static int gemv_common(int P, char trans, int64_t m, int64_t n, const double* alpha, const double* A,
+                       int64_t lda, int64_t sa, const double* x, int64_t sx, const double* beta, double* y,
+                       int64_t sy, hipStream_t st) {
+    if (!valid_trans(trans)) return -1;
+    if (m < 0) return -2;
+    if (n < 0) return -3;
+    if (!alpha) return -4;
+    const int t = is_trans(trans) ? 1 : 0;
+    const int64_t rows = t ? n : m, inner = t ? m : n;
+    const bool az = mp_zero(P, alpha) || inner == 0;
+    const bool reads_a = rows > 0 && !az;
+    if (reads_a && !A) return -5;
+    if (lda < std::max<int64_t>(1, m)) return -6;
+    if (sa < lda * n) return -7;
+    if (reads_a && !x) return -8;
+    if (sx < inner) return -9;
+    if (!beta) return -10;
+    if (rows > 0 && !y) return -11;
+    if (sy < rows) return -12;
+    if (rows == 0 || (az && mp_one(P, beta))) return 0;
+    if (reads_a) {
+        uintptr_t y0, y1, a0, a1, x0, x1;
+        extent(y, P, rows, 1, rows, sy, y0, y1);
+        extent(A, P, m, n, lda, sa, a0, a1);
+        extent(x, P, inner, 1, inner, sx, x0, x1);
+        if (overlaps(y0, y1, a0, a1) || overlaps(y0, y1, x0, x1)) return MPGEMM_ERR_ALIAS;
+    }
+    return hip_rc(launch_gemv(P, t, rows, inner, alpha, A, lda, sa, x, sx, beta, y, sy, az ? 1 : 0, st));
+}
+
+#define MPG_GEMV(NAME, P)                                                                           \
+    int NAME(char trans, int64_t m, int64_t n, const double* alpha, const double* A, int64_t lda,     \
+             int64_t sa, const double* x, int64_t sx, const double* beta, double* y, int64_t sy,      \
+             hipStream_t st) {                                                                       \
+        return gemv_common(P, trans, m, n, alpha, A, lda, sa, x, sx, beta, y, sy, st);               \
+    }
+MPG_GEMV(mp_gemv_dd, 2)
+MPG_GEMV(mp_gemv_td, 3)
+MPG_GEMV(mp_gemv_qd, 4)
+#undef MPG_GEMV
 
 // ---- batched plan -----------------------------------------------------------
 

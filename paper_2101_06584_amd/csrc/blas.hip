@@ -1,0 +1,217 @@
+// blas.hip -- BLAS-1/2 in DD / TD / QD on component planes: axpy, a dot
+// product in a fixed 64-ary tree order, and gemv (the GEMM with one column).
+//
+// axpy:  y_i = ADD(MUL(alpha, x_i), y_i); a stream, HBM-bound.
+// dot:   the n products are taken in blocks of 64 consecutive terms, each
+//        block summed from zero in ascending order; the block sums are again
+//        taken 64 at a time and summed the same way until one value is left
+//        (one kernel pass per level, partial sums in the caller's workspace).
+//        The order is fixed, so the result is reproducible bit for bit; for
+//        n <= 64 it is the sequential chain.
+// gemv:  y = alpha op(A) x + beta y with one thread per entry of y running the
+//        canonical ascending chain, then the plain GEMM's epilogue: the same
+//        bits as the GEMM with a single column.
+#pragma clang fp contract(off)
+
+#include "internal.hpp"
+#include "mp_arith.hpp"
+
+namespace mpg {
+
+static constexpr int kDotFanin = 64;
+
+struct Scal {
+    double v[4];
+};
+
+template <int P>
+__device__ __forceinline__ mp<P> scal(const Scal& s) {
+    mp<P> r;
+#pragma unroll
+    for (int c = 0; c < P; ++c) r.c[c] = s.v[c];
+    return r;
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void axpy_kernel(int64_t n, Scal alpha, const double* __restrict__ x,
+                                                   int64_t sx, double* __restrict__ y, int64_t sy) {
+    const mp<P> a = scal<P>(alpha);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        mp<P> xv, yv;
+#pragma unroll
+        for (int c = 0; c < P; ++c) {
+            xv.c[c] = __builtin_nontemporal_load(x + c * sx + i);
+            yv.c[c] = __builtin_nontemporal_load(y + c * sy + i);
+        }
+        const mp<P> r = add(mul(a, xv), yv);
+#pragma unroll
+        for (int c = 0; c < P; ++c) __builtin_nontemporal_store(r.c[c], y + c * sy + i);
+    }
+}
+
+// Leaf level: out[b] (P doubles, node-major) = ascending sum of the products
+// x_i y_i, i in [64 b, min(64 b + 64, n)).
+template <int P>
+__global__ __launch_bounds__(256) void dot_leaf_kernel(int64_t n, const double* __restrict__ x, int64_t sx,
+                                                       const double* __restrict__ y, int64_t sy,
+                                                       double* __restrict__ out, int64_t cnt) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= cnt) return;
+    mp<P> acc = mp_zero<P>();
+    const int64_t i0 = b * kDotFanin, i1 = min(n, i0 + kDotFanin);
+    for (int64_t i = i0; i < i1; ++i) {
+        mp<P> xv, yv;
+#pragma unroll
+        for (int c = 0; c < P; ++c) {
+            xv.c[c] = x[c * sx + i];
+            yv.c[c] = y[c * sy + i];
+        }
+        acc = add(acc, mul(xv, yv));
+    }
+#pragma unroll
+    for (int c = 0; c < P; ++c) out[b * P + c] = acc.c[c];
+}
+
+// Higher levels: out[b] = ascending sum of in[64 b .. min(64 b + 64, cnt_in)).
+template <int P>
+__global__ __launch_bounds__(256) void dot_node_kernel(int64_t cnt_in, const double* __restrict__ in,
+                                                       double* __restrict__ out, int64_t cnt) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= cnt) return;
+    mp<P> acc = mp_zero<P>();
+    const int64_t i0 = b * kDotFanin, i1 = min(cnt_in, i0 + kDotFanin);
+    for (int64_t i = i0; i < i1; ++i) {
+        mp<P> v;
+#pragma unroll
+        for (int c = 0; c < P; ++c) v.c[c] = in[i * P + c];
+        acc = add(acc, v);
+    }
+#pragma unroll
+    for (int c = 0; c < P; ++c) out[b * P + c] = acc.c[c];
+}
+
+template <int P>
+__global__ void dot_zero_kernel(double* out) {
+    if (threadIdx.x < P) out[threadIdx.x] = 0.0;
+}
+
+// y = alpha op(A) x + beta y over `rows` entries; element (i, l) of op(A) at
+// A[t ? l + i lda : i + l lda] (component planes at sa).  az: alpha == 0 or
+// inner == 0 (then y = beta y, or 0 when beta == 0).
+template <int P>
+__global__ __launch_bounds__(256) void gemv_kernel(int64_t rows, int64_t inner, int t, Scal alpha,
+                                                   const double* __restrict__ A, int64_t lda, int64_t sa,
+                                                   const double* __restrict__ x, int64_t sx, Scal beta,
+                                                   double* __restrict__ y, int64_t sy, int az) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows) return;
+    const mp<P> al = scal<P>(alpha), be = scal<P>(beta);
+    const bool beta_zero = mp_is_zero(be);
+    mp<P> r;
+    if (az) {
+        r = mp_zero<P>();
+        if (!beta_zero) {
+            mp<P> yo;
+#pragma unroll
+            for (int c = 0; c < P; ++c) yo.c[c] = y[c * sy + i];
+            r = mul(be, yo);
+        }
+    } else {
+        mp<P> acc = mp_zero<P>();
+        for (int64_t l = 0; l < inner; ++l) {
+            const int64_t off = t ? l + i * lda : i + l * lda;
+            mp<P> a, b;
+#pragma unroll
+            for (int c = 0; c < P; ++c) {
+                a.c[c] = A[c * sa + off];
+                b.c[c] = x[c * sx + l];
+            }
+            acc = add(acc, mul(a, b));
+        }
+        r = mul(al, acc);
+        if (!beta_zero) {
+            mp<P> yo;
+#pragma unroll
+            for (int c = 0; c < P; ++c) yo.c[c] = y[c * sy + i];
+            r = add(r, mul(be, yo));
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < P; ++c) y[c * sy + i] = r.c[c];
+}
+
+static Scal to_scal(int P, const double* v) {
+    Scal s{};
+    for (int c = 0; c < P; ++c) s.v[c] = v[c];
+    return s;
+}
+
+int launch_axpy(int P, int64_t n, const double* alpha, const double* x, int64_t sx, double* y, int64_t sy,
+                hipStream_t st) {
+    if (n <= 0) return 0;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 256 * 64) blocks = 256 * 64;
+    const dim3 gr((unsigned)blocks), bl(256);
+    const Scal a = to_scal(P, alpha);
+    if (P == 2) hipLaunchKernelGGL(axpy_kernel<2>, gr, bl, 0, st, n, a, x, sx, y, sy);
+    else if (P == 3) hipLaunchKernelGGL(axpy_kernel<3>, gr, bl, 0, st, n, a, x, sx, y, sy);
+    else hipLaunchKernelGGL(axpy_kernel<4>, gr, bl, 0, st, n, a, x, sx, y, sy);
+    return (int)hipGetLastError();
+}
+
+size_t dot_workspace_bytes(int P, int64_t n) {
+    // every level's partial sums, node-major
+    size_t d = 0;
+    for (int64_t cnt = (n + kDotFanin - 1) / kDotFanin; cnt > 1; cnt = (cnt + kDotFanin - 1) / kDotFanin)
+        d += (size_t)cnt * P;
+    return d * 8;
+}
+
+template <int P>
+static int dot_t(int64_t n, const double* x, int64_t sx, const double* y, int64_t sy, double* result,
+                 double* ws, hipStream_t st) {
+    if (n <= 0) {
+        hipLaunchKernelGGL(dot_zero_kernel<P>, dim3(1), dim3(64), 0, st, result);
+        return (int)hipGetLastError();
+    }
+    int64_t cnt = (n + kDotFanin - 1) / kDotFanin;
+    double* out = cnt == 1 ? result : ws;
+    hipLaunchKernelGGL(dot_leaf_kernel<P>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, n, x, sx, y,
+                       sy, out, cnt);
+    double* in = out;
+    double* free_at = ws + cnt * P;
+    while (cnt > 1) {
+        const int64_t next = (cnt + kDotFanin - 1) / kDotFanin;
+        double* dst = next == 1 ? result : free_at;
+        hipLaunchKernelGGL(dot_node_kernel<P>, dim3((unsigned)((next + 255) / 256)), dim3(256), 0, st, cnt,
+                           (const double*)in, dst, next);
+        in = dst;
+        free_at += next * P;
+        cnt = next;
+    }
+    return (int)hipGetLastError();
+}
+
+int launch_dot(int P, int64_t n, const double* x, int64_t sx, const double* y, int64_t sy, double* result,
+               void* ws, hipStream_t st) {
+    if (P == 2) return dot_t<2>(n, x, sx, y, sy, result, (double*)ws, st);
+    if (P == 3) return dot_t<3>(n, x, sx, y, sy, result, (double*)ws, st);
+    return dot_t<4>(n, x, sx, y, sy, result, (double*)ws, st);
+}
+
+int launch_gemv(int P, int t, int64_t rows, int64_t inner, const double* alpha, const double* A, int64_t lda,
+                int64_t sa, const double* x, int64_t sx, const double* beta, double* y, int64_t sy, int az,
+                hipStream_t st) {
+    if (rows <= 0) return 0;
+    const int64_t blocks = (rows + 255) / 256;
+    if (blocks > 0x7fffffffLL) return (int)hipErrorInvalidConfiguration;
+    const dim3 gr((unsigned)blocks), bl(256);
+    const Scal al = to_scal(P, alpha), be = to_scal(P, beta);
+    if (P == 2) hipLaunchKernelGGL(gemv_kernel<2>, gr, bl, 0, st, rows, inner, t, al, A, lda, sa, x, sx, be, y, sy, az);
+    else if (P == 3) hipLaunchKernelGGL(gemv_kernel<3>, gr, bl, 0, st, rows, inner, t, al, A, lda, sa, x, sx, be, y, sy, az);
+    else hipLaunchKernelGGL(gemv_kernel<4>, gr, bl, 0, st, rows, inner, t, al, A, lda, sa, x, sx, be, y, sy, az);
+    return (int)hipGetLastError();
+}
+
+}  // namespace mpg

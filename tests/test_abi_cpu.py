@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def header_symbols():
     txt = open(os.path.join(ROOT, "include", "mpgemm.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    names = set(re.findall(r"\b((?:mpgemm|mp_vec)_\w+)\s*\(", txt))
+    names = set(re.findall(r"\b((?:mpgemm|mp)_\w+)\s*\(", txt))
     return names
 
 
@@ -140,3 +140,29 @@ def test_tune_slices_validation():
                                 None, C.byref(s), C.byref(r)) == -13
     assert L.mpgemm_tune_slices(2, b"N", b"N", 4, 4, 4, FAKE_A, 4, 16, FAKE_B, 4, 16, 1.0, 10, 5,
                                 None, C.byref(s), C.byref(r)) == -15
+
+
+def test_blas_rejects_invalid_arguments_on_the_host():
+    """axpy, dot and gemv validate in argument order before any GPU work."""
+    L = mp.load()
+    d2 = (C.c_double * 2)(1.0, 0.0)
+    fake = C.c_void_p(4096)
+    assert L.mp_axpy_dd(-1, d2, fake, 0, fake, 0, None) == -1
+    assert L.mp_axpy_dd(4, None, fake, 4, fake, 4, None) == -2
+    assert L.mp_axpy_dd(4, d2, fake, 3, fake, 4, None) == -4
+    assert L.mp_axpy_dd(4, d2, fake, 4, fake, 3, None) == -6
+    assert L.mp_dot_workspace_bytes(2, 64) == 0
+    assert L.mp_dot_workspace_bytes(2, 65) == 2 * 2 * 8
+    assert L.mp_dot_workspace_bytes(4, 64 * 64 * 64 + 1) == 8 * 4 * (4097 + 65 + 2)
+    assert L.mp_dot_dd(5, fake, 4, fake, 5, fake, None, 0, None) == -3
+    assert L.mp_dot_dd(5, fake, 5, fake, 5, None, None, 0, None) == -6
+    assert L.mp_dot_dd(65, fake, 65, fake, 65, fake, None, 0, None) == -7
+    assert L.mp_dot_dd(65, fake, 65, fake, 65, fake, fake, 8, None) == _lib.ERR_WORKSPACE
+    assert L.mp_gemv_dd(b"X", 4, 4, d2, fake, 4, 16, fake, 4, d2, fake, 4, None) == -1
+    assert L.mp_gemv_dd(b"N", 4, 4, d2, fake, 3, 16, fake, 4, d2, fake, 4, None) == -6
+    assert L.mp_gemv_dd(b"N", 4, 4, d2, fake, 4, 15, fake, 4, d2, fake, 4, None) == -7
+    assert L.mp_gemv_dd(b"T", 4, 6, d2, fake, 4, 24, fake, 3, d2, fake, 6, None) == -9
+    assert L.mp_gemv_dd(b"N", 4, 6, d2, fake, 4, 24, fake, 6, d2, fake, 3, None) == -12
+    # y overlapping A
+    assert L.mp_gemv_dd(b"N", 4, 4, d2, fake, 4, 16, C.c_void_p(9 * 4096), 4, d2,
+                        C.c_void_p(4096 + 8), 4, None) == _lib.ERR_ALIAS

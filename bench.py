@@ -106,6 +106,8 @@ def parse():
     ap.add_argument("--vec-n", type=int, default=1 << 26, help="vector length for --vec")
     ap.add_argument("--td-variants", action="store_true",
                     help="accuracy and speed of the TD operation variants (Sec. 2.3)")
+    ap.add_argument("--blas", action="store_true",
+                    help="BLAS-1/2 (axpy, dot, gemv) in DD/TD/QD against the HBM roofline")
     ap.add_argument("--strassen", action="store_true",
                     help="Strassen's method (Sec. 3, Fig. 5) against the plain form, n = 4096")
     return ap.parse_args()
@@ -148,6 +150,8 @@ def main():
         return td_variants_bench(args, mp, synth, dev, stream)
     if args.strassen:
         return strassen_bench(args, mp, synth, dev, stream)
+    if args.blas:
+        return blas_bench(args, mp, dev, stream)
     n = args.n
     precs = [int(p) for p in args.prec.split(",")]
     forms = args.forms.split(",")
@@ -346,6 +350,80 @@ def main():
 
 
 PREC_OF = {"DD": 2, "TD": 3, "QD": 4}
+
+
+def blas_bench(args, mp, dev, stream):
+    """axpy and dot at n = args.vec_n, gemv at m = n = 16384 ('N' and 'T'), in
+    DD/TD/QD.  Reported against HBM bandwidth (algorithmic bytes: axpy 3 x 8P
+    per element, dot 2 x 8P, gemv 8P per matrix entry) and as multiply-adds
+    per second.  One JSON line."""
+    import numpy as np
+    import torch
+
+    def timed(call):
+        call()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(max(3, args.steps)):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            call()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    def fill(P, shape, seed):
+        g = torch.Generator(device=dev).manual_seed(seed)
+        t = torch.empty((P,) + shape, dtype=torch.float64, device=dev)
+        t[0].uniform_(-1, 1, generator=g)
+        for p in range(1, P):
+            t[p] = t[p - 1] * 2.0 ** -54 * (torch.rand(shape, dtype=torch.float64, device=dev,
+                                                       generator=g) * 2 - 1)
+        return t
+
+    parts = {}
+    nv = args.vec_n
+    for P in (2, 3, 4):
+        x, y = fill(P, (nv,), 1), fill(P, (nv,), 2)
+        alpha = [0.75] + [0.0] * (P - 1)
+        ms = timed(lambda: mp.axpy(P, alpha, x, y, stream=stream))
+        parts[f"{NAME[P]}_axpy"] = {"ms": round(ms, 4), "GB/s": 3 * 8 * P * nv / (ms * 1e-3) / 1e9,
+                                    "MAC/s": nv / (ms * 1e-3)}
+        res = torch.empty(P, dtype=torch.float64, device=dev)
+        ws = mp.dot_workspace(P, nv, dev)
+        ms = timed(lambda: mp.dot(P, x, y, res, workspace=ws, stream=stream))
+        parts[f"{NAME[P]}_dot"] = {"ms": round(ms, 4), "GB/s": 2 * 8 * P * nv / (ms * 1e-3) / 1e9,
+                                   "MAC/s": nv / (ms * 1e-3)}
+        del x, y, ws
+        torch.cuda.empty_cache()
+        m = nm = 16384
+        A = fill(P, (nm, m), 3)
+        xv, yv = fill(P, (nm,), 4), fill(P, (m,), 5)
+        for trans in ("N", "T"):
+            ms = timed(lambda: mp.gemv(P, trans, m, nm, alpha, A, xv, [0.0] * P, yv, stream=stream))
+            parts[f"{NAME[P]}_gemv_{trans}"] = {"ms": round(ms, 3), "GB/s": 8 * P * m * nm / (ms * 1e-3) / 1e9,
+                                                "MAC/s": m * nm / (ms * 1e-3)}
+        for k, v in parts.items():
+            if k.startswith(NAME[P]):
+                note("blas", k, v["ms"], "ms", round(v["GB/s"], 1), "GB/s")
+        del A, xv, yv
+        torch.cuda.empty_cache()
+    copy_rate = mp.probe_peak("hbm_copy", stream)
+    for v in parts.values():
+        v["hbm_frac"] = v["GB/s"] * 1e9 / HBM_PEAK
+        v["hbm_frac_of_copy"] = v["GB/s"] * 1e9 / copy_rate
+    total_ms = sum(v["ms"] for v in parts.values())
+    out = {"metric": "DD/TD/QD BLAS-1/2 bytes/s", "unit": "B/s",
+           "value": sum(v["GB/s"] * 1e9 * v["ms"] for v in parts.values()) / total_ms, "n_gpus": 1,
+           "steps": max(3, args.steps), "warmup": 1, "ms_per_step": round(total_ms, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"axpy and dot with n = {nv}, gemv 'N' and 'T' with m = n = 16384, "
+                                  "DD/TD/QD, component planes", "n": nv},
+           "hbm_copy_probe_GB/s": copy_rate / 1e9, "breakdown": parts}
+    print(json.dumps(out), flush=True)
 
 
 def strassen_bench(args, mp, synth, dev, stream):

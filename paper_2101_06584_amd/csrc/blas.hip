@@ -51,26 +51,67 @@ __global__ __launch_bounds__(256) void axpy_kernel(int64_t n, Scal alpha, const 
 }
 
 // Leaf level: out[b] (P doubles, node-major) = ascending sum of the products
-// x_i y_i, i in [64 b, min(64 b + 64, n)).
+// x_i y_i, i in [64 b, min(64 b + 64, n)).  Each wave owns 64 consecutive
+// blocks (lane = block).  Per round of 8 positions, the wave's lanes form the
+// 512 products of the round from coalesced 64-byte runs (8 lanes per block)
+// into LDS, then every lane adds its block's 8 products in order.  The
+// products and the order of the sum are those of the plain sequential loop.
+static constexpr int kDotRound = 8;
+
 template <int P>
 __global__ __launch_bounds__(256) void dot_leaf_kernel(int64_t n, const double* __restrict__ x, int64_t sx,
                                                        const double* __restrict__ y, int64_t sy,
                                                        double* __restrict__ out, int64_t cnt) {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= cnt) return;
+    // per wave: [64 blocks][kDotRound + 1 (pad)][P]
+    __shared__ double prod[4][64 * (kDotRound + 1) * P];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double* pw = prod[wave];
+    const int64_t b0 = ((int64_t)blockIdx.x * 4 + wave) * 64;      // first block of this wave
+    if (b0 >= cnt) return;                                            // whole wave past the end
+    const int64_t b = b0 + lane;
     mp<P> acc = mp_zero<P>();
-    const int64_t i0 = b * kDotFanin, i1 = min(n, i0 + kDotFanin);
-    for (int64_t i = i0; i < i1; ++i) {
-        mp<P> xv, yv;
+    for (int j0 = 0; j0 < kDotFanin; j0 += kDotRound) {
+        // products: lane handles (block b0 + 8 q + lane / 8, position j0 + lane % 8), q = 0..7
+        // loads first (indices past the end read element n - 1 and their
+        // products are never summed), then the products
+        mp<P> xv[8], yv[8];
 #pragma unroll
-        for (int c = 0; c < P; ++c) {
-            xv.c[c] = x[c * sx + i];
-            yv.c[c] = y[c * sy + i];
+        for (int q = 0; q < 8; ++q) {
+            const int bl = 8 * q + (lane >> 3), pos = lane & 7;
+            const int64_t i = min((b0 + bl) * kDotFanin + j0 + pos, n - 1);
+#pragma unroll
+            for (int c = 0; c < P; ++c) {
+                xv[q].c[c] = x[c * sx + i];
+                yv[q].c[c] = y[c * sy + i];
+            }
         }
-        acc = add(acc, mul(xv, yv));
-    }
 #pragma unroll
-    for (int c = 0; c < P; ++c) out[b * P + c] = acc.c[c];
+        for (int q = 0; q < 8; ++q) {
+            const int bl = 8 * q + (lane >> 3), pos = lane & 7;
+            const mp<P> pr = mul(xv[q], yv[q]);
+#pragma unroll
+            for (int c = 0; c < P; ++c) pw[(bl * (kDotRound + 1) + pos) * P + c] = pr.c[c];
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        // sums: this lane's block, positions j0 .. j0 + 7 that exist
+#pragma unroll
+        for (int pos = 0; pos < kDotRound; ++pos) {
+            const int64_t i = b * kDotFanin + j0 + pos;
+            if (b < cnt && i < n) {
+                mp<P> v;
+#pragma unroll
+                for (int c = 0; c < P; ++c) v.c[c] = pw[(lane * (kDotRound + 1) + pos) * P + c];
+                acc = add(acc, v);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    }
+    if (b < cnt) {
+#pragma unroll
+        for (int c = 0; c < P; ++c) out[b * P + c] = acc.c[c];
+    }
 }
 
 // Higher levels: out[b] = ascending sum of in[64 b .. min(64 b + 64, cnt_in)).
@@ -118,8 +159,26 @@ __global__ __launch_bounds__(256) void gemv_kernel(int64_t rows, int64_t inner, 
             r = mul(be, yo);
         }
     } else {
+        // the chain is sequential, so the loads of 8 steps are issued first
+        // to overlap their latency (one thread per row leaves few waves)
+        constexpr int UN = 8;
         mp<P> acc = mp_zero<P>();
-        for (int64_t l = 0; l < inner; ++l) {
+        int64_t l = 0;
+        for (; l + UN <= inner; l += UN) {
+            mp<P> a[UN], b[UN];
+#pragma unroll
+            for (int u = 0; u < UN; ++u) {
+                const int64_t off = t ? (l + u) + i * lda : i + (l + u) * lda;
+#pragma unroll
+                for (int c = 0; c < P; ++c) {
+                    a[u].c[c] = A[c * sa + off];
+                    b[u].c[c] = x[c * sx + l + u];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < UN; ++u) acc = add(acc, mul(a[u], b[u]));
+        }
+        for (; l < inner; ++l) {
             const int64_t off = t ? l + i * lda : i + l * lda;
             mp<P> a, b;
 #pragma unroll
@@ -177,6 +236,7 @@ static int dot_t(int64_t n, const double* x, int64_t sx, const double* y, int64_
     }
     int64_t cnt = (n + kDotFanin - 1) / kDotFanin;
     double* out = cnt == 1 ? result : ws;
+    // 4 waves of 64 blocks per workgroup
     hipLaunchKernelGGL(dot_leaf_kernel<P>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, n, x, sx, y,
                        sy, out, cnt);
     double* in = out;

@@ -40,6 +40,10 @@ def lib():
                                         _i64, _i64, C.c_void_p, _i64, _i64, C.c_void_p, C.c_void_p,
                                         _i64, _i64]
         L.ref_gemm_strassen.restype = _int
+        L.ref_gemm_crt.argtypes = [_int, _int, _ch, _ch, _i64, _i64, _i64, C.c_void_p, C.c_void_p, _i64,
+                                   _i64, C.c_void_p, _i64, _i64, C.c_void_p, C.c_void_p, _i64, _i64,
+                                   _i64, _i64, _i64, _i64, _int]
+        L.ref_gemm_crt.restype = _int
         L.ref_axpy.argtypes = [_int, _i64, C.c_void_p, C.c_void_p, _i64, C.c_void_p, _i64]
         L.ref_axpy.restype = _int
         L.ref_dot.argtypes = [_int, _i64, C.c_void_p, _i64, C.c_void_p, _i64, C.c_void_p]
@@ -170,6 +174,25 @@ def gemm_strassen(P, levels, ta, tb, m, n, k, alpha, A, B, beta, C):
                                  A.shape[2], A.shape[1] * A.shape[2], _ptr(B), B.shape[2],
                                  B.shape[1] * B.shape[2], _ptr(beta), _ptr(Cout), Cout.shape[2],
                                  Cout.shape[1] * Cout.shape[2])
+    assert rc == 0, rc
+    return Cout
+
+
+def gemm_crt(P, s, ta, tb, m, n, k, alpha, A, B, beta, C, rows=None, cols=None, nthreads=0):
+    """Residue (CRT) form: the exact product of the s-digit integers of the
+    split form (full square of digit pairs), rounded to P components; returns
+    a new C."""
+    A = _f64(A)
+    B = _f64(B)
+    Cout = _f64(C).copy()
+    alpha = _f64(alpha)
+    beta = _f64(beta)
+    r0, r1 = rows if rows is not None else (0, -1)
+    c0, c1 = cols if cols is not None else (0, -1)
+    rc = lib().ref_gemm_crt(P, s, ta.encode(), tb.encode(), m, n, k, _ptr(alpha), _ptr(A), A.shape[2],
+                            A.shape[1] * A.shape[2], _ptr(B), B.shape[2], B.shape[1] * B.shape[2],
+                            _ptr(beta), _ptr(Cout), Cout.shape[2], Cout.shape[1] * Cout.shape[2],
+                            r0, r1, c0, c1, nthreads)
     assert rc == 0, rc
     return Cout
 

@@ -1042,6 +1042,216 @@ EXPORT int ref_gemv(int P, char trans, int64_t m, int64_t n, const double *alpha
                     beta, y, rows > 0 ? rows : 1, sy, 0, -1, 0, -1, 0);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Residue (CRT) form of the split product: the same digits as the split    */
+/* form, but the product of the digit integers A'_il = sum_p d_p 128^(s-p)  */
+/* and B'_lj is formed exactly over the full square of digit pairs:         */
+/*   T_d = sum_{p+q=d} sum_l d_p(a_il) d_q(b_lj),  d = 2..2s,               */
+/*   C'_ij = sum_d T_d 128^(2s-d)   (exact integer, Horner in base 128),   */
+/*   value = C'_ij 2^(E_i + F_j - 14 s),                                   */
+/* rounded to P components by repeated round-to-nearest (ties to even) of  */
+/* the exact remainder, then the epilogue.  On the GPU the same integer is  */
+/* obtained from its residues modulo pairwise coprime int8 moduli (one      */
+/* INT8 matrix product per modulus) and the Chinese remainder theorem;      */
+/* here it is the plain definition.                                         */
+/* ------------------------------------------------------------------------ */
+
+#define BIG_LIMBS 16          /* 512-bit two's complement, 32-bit limbs */
+
+typedef struct {
+    uint32_t w[BIG_LIMBS];    /* little-endian */
+} big;
+
+static void big_set_i64(big *a, int64_t v)
+{
+    uint64_t u = (uint64_t)v;
+    a->w[0] = (uint32_t)u;
+    a->w[1] = (uint32_t)(u >> 32);
+    uint32_t ext = v < 0 ? 0xffffffffu : 0u;
+    for (int i = 2; i < BIG_LIMBS; ++i) a->w[i] = ext;
+}
+
+static int big_neg_p(const big *a) { return (a->w[BIG_LIMBS - 1] >> 31) != 0; }
+
+static void big_add(big *a, const big *b)
+{
+    uint64_t c = 0;
+    for (int i = 0; i < BIG_LIMBS; ++i) {
+        uint64_t t = (uint64_t)a->w[i] + b->w[i] + c;
+        a->w[i] = (uint32_t)t;
+        c = t >> 32;
+    }
+}
+
+static void big_negate(big *a)
+{
+    uint64_t c = 1;
+    for (int i = 0; i < BIG_LIMBS; ++i) {
+        uint64_t t = (uint64_t)(~a->w[i]) + c;
+        a->w[i] = (uint32_t)t;
+        c = t >> 32;
+    }
+}
+
+static void big_shl(big *a, int sh)     /* 0 <= sh < 32 */
+{
+    if (sh == 0)
+        return;
+    for (int i = BIG_LIMBS - 1; i > 0; --i)
+        a->w[i] = (a->w[i] << sh) | (a->w[i - 1] >> (32 - sh));
+    a->w[0] <<= sh;
+}
+
+static int big_top_bit(const big *a)    /* of a non-negative value; -1 if zero */
+{
+    for (int i = BIG_LIMBS - 1; i >= 0; --i)
+        if (a->w[i])
+            return 32 * i + 31 - __builtin_clz(a->w[i]);
+    return -1;
+}
+
+static int big_bit(const big *a, int b) { return (a->w[b >> 5] >> (b & 31)) & 1; }
+
+/* bits [lo, lo + 53) of a non-negative value as an integer */
+static uint64_t big_bits53(const big *a, int lo)
+{
+    uint64_t r = 0;
+    for (int b = lo + 52; b >= lo; --b)
+        r = (r << 1) | (uint64_t)(b >= 0 ? big_bit(a, b) : 0);
+    return r;
+}
+
+/* a -= q 2^sh for a non-negative a, q < 2^54 */
+static void big_sub_shifted(big *a, uint64_t q, int sh)
+{
+    big t;
+    memset(&t, 0, sizeof t);
+    for (int b = 0; b < 54; ++b)
+        if ((q >> b) & 1) {
+            int pos = b + sh;
+            t.w[pos >> 5] |= 1u << (pos & 31);
+        }
+    big_negate(&t);
+    big_add(a, &t);
+}
+
+/* Components c_0..c_{P-1} of X 2^e: c_0 = RN(X 2^e), then RN of the exact
+ * remainder, and so on (round to nearest, ties to even). */
+static void big_to_components(int P, const big *X, int e, double *c)
+{
+    big m = *X;
+    int neg = big_neg_p(&m);
+    if (neg)
+        big_negate(&m);
+    for (int q = 0; q < P; ++q) {
+        int h = big_top_bit(&m);
+        if (h < 0) {
+            c[q] = 0.0;
+            continue;
+        }
+        if (h <= 52) {
+            uint64_t v = big_bits53(&m, 0);
+            c[q] = (neg ? -1.0 : 1.0) * ldexp((double)v, e);
+            memset(&m, 0, sizeof m);
+            continue;
+        }
+        int sh = h - 52;
+        uint64_t v = big_bits53(&m, sh);
+        /* rounding: guard bit sh-1, sticky below */
+        int guard = big_bit(&m, sh - 1);
+        int sticky = 0;
+        for (int b = 0; b < sh - 1 && !sticky; ++b)
+            sticky = big_bit(&m, b);
+        if (guard && (sticky || (v & 1)))
+            v += 1;
+        c[q] = (neg ? -1.0 : 1.0) * ldexp((double)v, sh + e);
+        /* remainder m - v 2^sh, which may be negative after rounding up */
+        big_sub_shifted(&m, v, sh);
+        if (big_neg_p(&m)) {
+            big_negate(&m);
+            neg = !neg;
+        }
+    }
+}
+
+EXPORT int ref_gemm_crt(int P, int s, char ta, char tb, int64_t m, int64_t n, int64_t k,
+                        const double *alpha, const double *A, int64_t lda, int64_t sa,
+                        const double *B, int64_t ldb, int64_t sb, const double *beta,
+                        double *C, int64_t ldc, int64_t sc, int64_t row0, int64_t row1,
+                        int64_t col0, int64_t col1, int nthreads)
+{
+    if (P < 2 || P > 4 || s < 1 || s > 35)
+        return -1;
+    if (row1 < 0 || row1 > m)
+        row1 = m;
+    if (row0 < 0)
+        row0 = 0;
+    if (col1 < 0 || col1 > n)
+        col1 = n;
+    if (col0 < 0)
+        col0 = 0;
+    int az = mp_is_zero(P, alpha) || k == 0;
+    if (m == 0 || n == 0 || (az && mp_is_one(P, beta)))
+        return 0;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#endif
+    int64_t rows = row1 - row0, cols = col1 - col0;
+    int32_t *E = (int32_t *)calloc((size_t)(m > 0 ? m : 1), sizeof(int32_t));
+    int32_t *F = (int32_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int32_t));
+    int8_t *DA = NULL, *DB = NULL;
+    if (!az) {
+        DA = (int8_t *)malloc((size_t)s * rows * k);
+        DB = (int8_t *)malloc((size_t)s * cols * k);
+        const double *Ab = A + (is_trans(ta) ? row0 * lda : row0);
+        const double *Bb = B + (is_trans(tb) ? col0 : col0 * ldb);
+        ref_split_exponents(P, ta, 0, rows, k, Ab, lda, sa, E + row0);
+        ref_split_exponents(P, tb, 1, cols, k, Bb, ldb, sb, F + col0);
+        ref_split_slices(P, s, ta, 0, rows, k, Ab, lda, sa, E + row0, DA);
+        ref_split_slices(P, s, tb, 1, cols, k, Bb, ldb, sb, F + col0, DB);
+    }
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t idx = 0; idx < rows * cols; ++idx) {
+        int64_t ii = idx % rows, i = row0 + ii;
+        int64_t jj = idx / rows, j = col0 + jj;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        if (!az) {
+            big X;
+            big_set_i64(&X, 0);
+            for (int d = 2; d <= 2 * s; ++d) {
+                int64_t T = 0;
+                for (int p = 1; p <= s; ++p) {
+                    int q = d - p;
+                    if (q < 1 || q > s)
+                        continue;
+                    const int8_t *da = DA + (int64_t)(p - 1) * rows * k + ii * k;
+                    const int8_t *db = DB + (int64_t)(q - 1) * cols * k + jj * k;
+                    for (int64_t l = 0; l < k; ++l)
+                        T += (int64_t)da[l] * (int64_t)db[l];
+                }
+                /* X = X 128 + T */
+                big_shl(&X, 7);
+                big t;
+                big_set_i64(&t, T);
+                big_add(&X, &t);
+            }
+            big_to_components(P, &X, E[i] + F[j] - 14 * s, acc);
+        }
+        double cv[4];
+        for (int c = 0; c < P; ++c)
+            cv[c] = C[c * sc + i + j * ldc];
+        epilogue(P, 0, alpha, acc, beta, cv, az);
+        for (int c = 0; c < P; ++c)
+            C[c * sc + i + j * ldc] = cv[c];
+    }
+    free(E);
+    free(F);
+    free(DA);
+    free(DB);
+    return 0;
+}
+
 EXPORT int ref_num_threads(void)
 {
 #ifdef _OPENMP

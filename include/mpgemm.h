@@ -70,6 +70,10 @@ extern "C" {
 #define MPGEMM_FORM_STRASSEN 4  /* Strassen's method (Sec. 3, Fig. 5): opts.levels
                                    levels of the seven-product recursion over
                                    plain-form block products               */
+#define MPGEMM_FORM_SPLIT_CRT 5 /* residue form of the split product: the
+                                   same digits, their integer product over
+                                   the full square of digit pairs from one
+                                   INT8 product per coprime modulus        */
 
 /* TD operation variants (Sec. 2.3).  The defaults are TDaddq (the QD
  * addition on zero fourth components) and the "fast" triple-word product
@@ -156,8 +160,21 @@ int mpgemm_qd(char transa, char transb, int64_t m, int64_t n, int64_t k, const d
  * 2^levels return MPGEMM_ERR_UNSUPPORTED; needs opts->workspace (256-byte
  * aligned) of mpgemm_workspace_bytes(prec, MPGEMM_FORM_STRASSEN, m, n, k,
  * levels, -1) bytes.
+ * form = MPGEMM_FORM_SPLIT_CRT: the split form's scaling and s digits per
+ * entry define integers A'_il = sum_p d_p 128^(s-p) and B'_lj; the exact
+ * C'_ij = sum_l A'_il B'_lj is reconstructed (Chinese remainder theorem) from
+ * its residues modulo the first N of 49 pairwise coprime moduli <= 256, one
+ * exact INT8 matrix-core product per modulus, N the smallest count whose
+ * product M exceeds 2 k (64 (128^s - 1) / 127)^2; then C'_ij 2^(E_i + F_j -
+ * 14 s) is rounded to P components by repeated round to nearest (ties to
+ * even) of the exact remainder and the plain epilogue applied.  N grows with
+ * 14 s + log2 k (DD, s = 16: at most 32 moduli; TD, s = 23: 48 for k <= 2^13,
+ * 49 above); MPGEMM_ERR_UNSUPPORTED when 49 do not suffice (QD at its default
+ * s, s > 24, or k > 131071).  Deterministic; the exactly rounded product of
+ * the truncated operands.  Workspace as for the split form, sized by
+ * mpgemm_workspace_bytes(prec, MPGEMM_FORM_SPLIT_CRT, m, n, k, slices, tile).
  * opts->variant (TD, plain form only; MPGEMM_ERR_UNSUPPORTED for another
- * precision or the split form, -18 outside 0..3): the same canonical
+ * precision or the split forms, -18 outside 0..3): the same canonical
  * evaluation with the accurate TD addition (MPGEMM_TD_ADD_ACCURATE) and / or
  * TDmulq (MPGEMM_TD_MULQ) in place of TDaddq and Algorithm 4, everywhere
  * including the alpha/beta epilogue; FORM_AUTO then means plain.
@@ -175,8 +192,10 @@ int mpgemm_qd_ex(char transa, char transb, int64_t m, int64_t n, int64_t k, cons
                  int64_t b_plane_stride, const double* beta, double* C, int64_t ldc,
                  int64_t c_plane_stride, hipStream_t stream, const mpgemm_opts* opts);
 
-/* Workspace bytes the split form needs for this shape (0 for the plain form;
- * slices 0 = default; tile -1 = the one the library would pick); for
+/* Workspace bytes the split forms (MPGEMM_FORM_SPLIT_I8, _AUTO, _SPLIT_CRT)
+ * need for this shape (0 for the plain form; for the residue form also 0 when
+ * no modulus count suffices; slices 0 = default; tile -1 = the one the
+ * library would pick); for
  * MPGEMM_FORM_STRASSEN, `slices` is the number of levels L (0 = 1) and the
  * result is 8 P (m n + sum over l = 1..L of 7^l (m k + k n + m n) / 4^l)
  * bytes (the product and, per level, operands and results of its 7^l
@@ -310,8 +329,8 @@ int mpgemm_batch_plan_info(const mpgemm_batch_plan* plan, int64_t* tiles, int* g
 int mpgemm_batch_plan_destroy(mpgemm_batch_plan* plan);
 
 /*
- * Autotuner: times every kernel configuration of a form on a problem of the
- * given shape (synthetic operands allocated by the tuner; not a hot path) and
+ * Autotuner: times every kernel configuration of a form (MPGEMM_FORM_PLAIN,
+ * _SPLIT_I8 or _SPLIT_CRT) on a problem of the given shape (synthetic operands allocated by the tuner; not a hot path) and
  * records the fastest for that precision / form / shape bucket (log2 of m, n,
  * k).  Later calls with tile = -1 (or the non-_ex entry points) use it.
  * Writes the chosen configuration id to *best (may be NULL).
@@ -324,8 +343,8 @@ int mpgemm_autotune(int prec, int form, int64_t m, int64_t n, int64_t k, int sli
  * Arguments as mpgemm_batch_plan_create; *best (may be NULL) gets the id. */
 int mpgemm_batch_autotune(int prec, int64_t count, const mpgemm_problem* problems,
                           hipStream_t stream, int* best);
-/* Record a configuration for a precision / form (0 plain, 1 split, 3 batched)
- * / shape bucket directly (e.g. from a table produced elsewhere). */
+/* Record a configuration for a precision / form (0 plain, 1 split, 3 batched,
+ * 5 residue split) / shape bucket directly (e.g. from a table produced elsewhere). */
 int mpgemm_autotune_set(int prec, int form, int64_t m, int64_t n, int64_t k, int tile);
 /* Persist / restore the tuning table as a small text file (one entry per
  * line: prec form log2m log2n log2k tile). */

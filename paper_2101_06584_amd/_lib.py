@@ -17,7 +17,7 @@ _i64, _int, _ch, _vp, _sz, _dbl = C.c_int64, C.c_int, C.c_char, C.c_void_p, C.c_
 _P = C.POINTER
 
 ERR_HIP, ERR_WORKSPACE, ERR_UNSUPPORTED, ERR_GRAPH, ERR_ALIAS, ERR_NOMEM = 1, 2, 3, 4, 5, 6
-FORM_PLAIN, FORM_SPLIT_I8, FORM_AUTO, FORM_STRASSEN = 0, 1, 2, 4
+FORM_PLAIN, FORM_SPLIT_I8, FORM_AUTO, FORM_STRASSEN, FORM_SPLIT_CRT = 0, 1, 2, 4, 5
 TD_ADD_ACCURATE, TD_MULQ = 1, 2
 
 

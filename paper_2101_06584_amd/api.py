@@ -15,7 +15,7 @@ from . import _lib
 
 PREC = {"dd": 2, "td": 3, "qd": 4, 2: 2, 3: 3, 4: 4}
 FORMS = {"plain": _lib.FORM_PLAIN, "split": _lib.FORM_SPLIT_I8, "auto": _lib.FORM_AUTO,
-         "strassen": _lib.FORM_STRASSEN}
+         "strassen": _lib.FORM_STRASSEN, "crt": _lib.FORM_SPLIT_CRT}
 DEFAULT_SLICES = {2: 16, 3: 23, 4: 31}
 _NAME = {2: "dd", 3: "td", 4: "qd"}
 
@@ -88,10 +88,13 @@ def workspace_bytes(prec, form, m, n, k, slices=0, tile=-1) -> int:
 
 
 def alloc_workspace(prec, m, n, k, slices=0, tile=-1, device=None, form="split", levels=0) -> torch.Tensor:
-    """Device workspace for the split form (slices, tile) or, with
-    form="strassen", for `levels` levels of Strassen's method."""
+    """Device workspace for the split form (slices, tile), with form="crt"
+    for its residue form, or with form="strassen" for `levels` levels of
+    Strassen's method."""
     if form == "strassen":
         nbytes = workspace_bytes(prec, "strassen", m, n, k, levels, -1)
+    elif form == "crt":
+        nbytes = workspace_bytes(prec, "crt", m, n, k, slices, tile)
     else:
         nbytes = workspace_bytes(prec, "split", m, n, k, slices, tile)
     return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device or "cuda")

@@ -157,6 +157,13 @@ int split_default_config(int64_t m, int64_t n) {
 }
 
 int pick_tile(int P, int form, int64_t m, int64_t n, int64_t k, int requested) {
+    if (form == MPGEMM_FORM_SPLIT_CRT) {
+        if (requested >= 0 && requested < kCrtConfigs) return requested;
+        const int t = tuned_tile(P, form, m, n, k);
+        if (t >= 0 && t < kCrtConfigs) return t;
+        // 64 x 64 output tiles when 128 x 128 ones leave CUs idle
+        return (((m + 127) / 128) * ((n + 127) / 128) >= 512) ? 0 : 1;
+    }
     const int nconf = form == MPGEMM_FORM_SPLIT_I8 ? kSplitConfigs : kPlainConfigs;
     if (requested >= 0 && requested < nconf) return requested;
     const int t = tuned_tile(P, form, m, n, k);
@@ -181,7 +188,7 @@ int gemm_common(int P, char ta, char tb, int64_t m, int64_t n, int64_t k, const 
     if (rc) return rc;
     if (has_opts) {
         if (!opts) return -18;
-        if (opts->form < 0 || opts->form > 4 || opts->form == 3) return -18;
+        if (opts->form < 0 || opts->form > 5 || opts->form == 3) return -18;
         if (opts->slices < 0 || opts->slices > kMaxSlices) return -18;
         if (opts->variant < 0 || opts->variant > 3) return -18;
         if (opts->levels < 0 || opts->levels > kMaxStrassenLevels) return -18;
@@ -189,7 +196,8 @@ int gemm_common(int P, char ta, char tb, int64_t m, int64_t n, int64_t k, const 
     const int variant = has_opts ? opts->variant : 0;
     // the TD variants exist for the plain form only
     if (variant != 0 && (P != 3 || opts->form == MPGEMM_FORM_SPLIT_I8 ||
-                         opts->form == MPGEMM_FORM_STRASSEN || last_stage > 0))
+                         opts->form == MPGEMM_FORM_STRASSEN || opts->form == MPGEMM_FORM_SPLIT_CRT ||
+                         last_stage > 0))
         return MPGEMM_ERR_UNSUPPORTED;
     const bool strassen = has_opts && opts->form == MPGEMM_FORM_STRASSEN && last_stage <= 0;
     const int levels = strassen ? (opts->levels > 0 ? opts->levels : 1) : 0;
@@ -197,6 +205,11 @@ int gemm_common(int P, char ta, char tb, int64_t m, int64_t n, int64_t k, const 
         const int64_t unit = (int64_t)1 << levels;
         if (m % unit || n % unit || k % unit) return MPGEMM_ERR_UNSUPPORTED;
     }
+    const bool crt = has_opts && opts->form == MPGEMM_FORM_SPLIT_CRT && last_stage <= 0;
+    const int crt_s = crt ? (opts->slices > 0 ? opts->slices : kDefaultSlices[P]) : 0;
+    // the residue form needs enough moduli for the exact product (checked
+    // for every shape, also those that return early)
+    if (crt && k > 0 && crt_moduli_count(k, crt_s) == 0) return MPGEMM_ERR_UNSUPPORTED;
     if (m == 0 || n == 0) return 0;
     const bool az = (k == 0) || mp_zero(P, alpha);
     if (az && mp_one(P, beta)) return 0;
@@ -207,6 +220,13 @@ int gemm_common(int P, char ta, char tb, int64_t m, int64_t n, int64_t k, const 
         if (!opts->workspace || opts->workspace_bytes < need) return MPGEMM_ERR_WORKSPACE;
         if ((uintptr_t)opts->workspace % 256 != 0) return MPGEMM_ERR_WORKSPACE;
         return hip_rc(launch_strassen(P, levels, g, opts->workspace, st, &plain_tile_for));
+    }
+    if (crt) {
+        const int cfg = pick_tile(P, MPGEMM_FORM_SPLIT_CRT, m, n, k, opts->tile);
+        const size_t need = crt_workspace_bytes(P, m, n, k, crt_s, cfg);
+        if (!opts->workspace || opts->workspace_bytes < need) return MPGEMM_ERR_WORKSPACE;
+        if ((uintptr_t)opts->workspace % 256 != 0) return MPGEMM_ERR_WORKSPACE;
+        return hip_rc(launch_crt(P, crt_s, cfg, g, opts->workspace, st));
     }
 
     int form = has_opts ? opts->form : MPGEMM_FORM_PLAIN;
@@ -266,6 +286,10 @@ size_t mpgemm_workspace_bytes(int prec, int form, int64_t m, int64_t n, int64_t 
         const int levels = slices > 0 ? slices : 1;
         if (levels > kMaxStrassenLevels) return 0;
         return strassen_workspace_bytes(prec, levels, m, n, k);
+    }
+    if (form == MPGEMM_FORM_SPLIT_CRT) {
+        const int s = slices > 0 ? slices : kDefaultSlices[prec];
+        return crt_workspace_bytes(prec, m, n, k, s, pick_tile(prec, form, m, n, k, tile));
     }
     if (form != MPGEMM_FORM_SPLIT_I8 && form != MPGEMM_FORM_AUTO) return 0;
     const int s = slices > 0 ? slices : kDefaultSlices[prec];
@@ -530,6 +554,7 @@ int mpgemm_num_configs(int prec, int form) {
     if (prec < 2 || prec > 4) return 0;
     if (form == MPGEMM_FORM_PLAIN || form == 3) return kPlainConfigs;
     if (form == MPGEMM_FORM_SPLIT_I8) return kSplitConfigs;
+    if (form == MPGEMM_FORM_SPLIT_CRT) return kCrtConfigs;
     return 0;
 }
 
@@ -539,8 +564,9 @@ static int time_config(int P, int form, int cfg, const GemmArgs& g, int s, void*
     if (hipEventCreate(&e0) != hipSuccess) return MPGEMM_ERR_HIP;
     if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return MPGEMM_ERR_HIP; }
     auto run = [&]() {
-        return form == MPGEMM_FORM_PLAIN ? launch_plain(P, cfg, g, st)
-                                         : launch_split(P, s, cfg, g, ws, wsb, st);
+        return form == MPGEMM_FORM_PLAIN     ? launch_plain(P, cfg, g, st)
+               : form == MPGEMM_FORM_SPLIT_CRT ? launch_crt(P, s, cfg, g, ws, st)
+                                               : launch_split(P, s, cfg, g, ws, wsb, st);
     };
     int rc = run();  // warm-up
     float best = 1e30f;
@@ -562,7 +588,8 @@ static int time_config(int P, int form, int cfg, const GemmArgs& g, int s, void*
 int mpgemm_autotune(int prec, int form, int64_t m, int64_t n, int64_t k, int slices,
                     hipStream_t st, int* best) {
     if (prec < 2 || prec > 4) return -1;
-    if (form != MPGEMM_FORM_PLAIN && form != MPGEMM_FORM_SPLIT_I8) return -2;
+    if (form != MPGEMM_FORM_PLAIN && form != MPGEMM_FORM_SPLIT_I8 && form != MPGEMM_FORM_SPLIT_CRT)
+        return -2;
     if (m <= 0) return -3;
     if (n <= 0) return -4;
     if (k <= 0) return -5;
@@ -570,6 +597,7 @@ int mpgemm_autotune(int prec, int form, int64_t m, int64_t n, int64_t k, int sli
     const int P = prec;
     const int s = slices > 0 ? slices : kDefaultSlices[P];
     if (form == MPGEMM_FORM_SPLIT_I8 && !split_k_ok(k, s)) return MPGEMM_ERR_UNSUPPORTED;
+    if (form == MPGEMM_FORM_SPLIT_CRT && crt_moduli_count(k, s) == 0) return MPGEMM_ERR_UNSUPPORTED;
     double *A = nullptr, *B = nullptr, *C = nullptr;
     void* ws = nullptr;
     size_t wsb = 0;
@@ -580,6 +608,10 @@ int mpgemm_autotune(int prec, int form, int64_t m, int64_t n, int64_t k, int sli
         rc = MPGEMM_ERR_NOMEM;
     if (!rc && form == MPGEMM_FORM_SPLIT_I8) {
         for (int c = 0; c < kSplitConfigs; ++c) wsb = std::max(wsb, split_workspace_bytes(P, m, n, k, s, c));
+        if (hipMalloc(&ws, wsb) != hipSuccess) rc = MPGEMM_ERR_NOMEM;
+    }
+    if (!rc && form == MPGEMM_FORM_SPLIT_CRT) {
+        for (int c = 0; c < kCrtConfigs; ++c) wsb = std::max(wsb, crt_workspace_bytes(P, m, n, k, s, c));
         if (hipMalloc(&ws, wsb) != hipSuccess) rc = MPGEMM_ERR_NOMEM;
     }
     if (!rc) rc = launch_fill(P, A, m * k, m * k, 11, st) ? MPGEMM_ERR_HIP : 0;
@@ -615,7 +647,9 @@ int mpgemm_autotune(int prec, int form, int64_t m, int64_t n, int64_t k, int sli
 
 int mpgemm_autotune_set(int prec, int form, int64_t m, int64_t n, int64_t k, int tile) {
     if (prec < 2 || prec > 4) return -1;
-    if (form != MPGEMM_FORM_PLAIN && form != MPGEMM_FORM_SPLIT_I8 && form != 3) return -2;
+    if (form != MPGEMM_FORM_PLAIN && form != MPGEMM_FORM_SPLIT_I8 && form != MPGEMM_FORM_SPLIT_CRT &&
+        form != 3)
+        return -2;
     if (m <= 0) return -3;
     if (n <= 0) return -4;
     if (k <= 0) return -5;

@@ -75,4 +75,16 @@ int launch_split(int P, int s, int cfg, const GemmArgs& g, void* ws, size_t ws_b
 int split_layout(int P, int64_t m, int64_t n, int64_t k, int s, int cfg, size_t* offE, size_t* offF,
                  size_t* offDA, size_t* offDB, size_t* offS, int64_t* Mp, int64_t* Np, int64_t* Kp);
 
+// Scale exponents of the split forms (stage 1 above): row r of a matrix whose
+// element (r, l) sits at X[r rs + l ls]; E[r] = 0 for count <= r < padded.
+int launch_row_exponents(const double* X, int64_t rs, int64_t ls, int64_t count, int64_t padded,
+                         int64_t k, int32_t* E, hipStream_t st);
+
+// Residue (CRT) form of the split product (crt_gemm.hip).
+constexpr int kCrtConfigs = 2;
+// number of moduli for k and s digits, 0 when the product does not fit
+int crt_moduli_count(int64_t k, int s);
+size_t crt_workspace_bytes(int P, int64_t m, int64_t n, int64_t k, int s, int cfg);
+int launch_crt(int P, int s, int cfg, const GemmArgs& g, void* ws, hipStream_t st);
+
 }  // namespace mpg

@@ -25,15 +25,12 @@
 #include <utility>
 
 #include "internal.hpp"
+#include "lds_dma.hpp"
 #include "mp_arith.hpp"
 #include "tile_order.hpp"
 
 namespace mpg {
 
-typedef int v4i __attribute__((ext_vector_type(4)));
-typedef int v16i __attribute__((ext_vector_type(16)));
-
-static constexpr int kTileK = 64;          // k bytes per pipeline step (and k-tile width)
 static constexpr int kSliceTile = 32;      // slicing kernel: 32 rows x 32 k per block
 
 static inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
@@ -236,28 +233,6 @@ template <typename F, int... I>
 __device__ __forceinline__ bool diag_unrolled(F&& f, std::integer_sequence<int, I...>) {
     return (... || f(std::integral_constant<int, I>{}));
 }
-
-template <int N, typename F, int... I>
-__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
-    (f(std::integral_constant<int, I>{}), ...);
-}
-template <int N, typename F>
-__device__ __forceinline__ void static_for(F&& f) {   // f(0), ..., f(N - 1) as constants
-    static_for_impl<N>(f, std::make_integer_sequence<int, N>{});
-}
-
-// LDS offset of 16-byte chunk c (0..3) of tile row r (64-byte rows).
-__device__ __forceinline__ int swz(int r, int c) { return r * kTileK + ((c ^ ((r >> 2) & 3)) << 4); }
-
-// Wait until at most N vector-memory operations of this wave are pending and
-// its LDS reads are done, then meet the other waves; a compiler barrier too.
-template <int N>
-__device__ __forceinline__ void wait_vm_barrier() {
-    static_assert(N >= 0 && N <= 63, "vmcnt range");
-    asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
-}
-
-__device__ __forceinline__ void wait_vm_all() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
 
@@ -511,6 +486,11 @@ static int launch_exponents(const double* X, int64_t rs, int64_t ls, int64_t cou
                            ls, count, padded, k, E);
     }
     return (int)hipGetLastError();
+}
+
+int launch_row_exponents(const double* X, int64_t rs, int64_t ls, int64_t count, int64_t padded,
+                         int64_t k, int32_t* E, hipStream_t st) {
+    return launch_exponents(X, rs, ls, count, padded, k, E, st);
 }
 
 static int launch_slices(int P, const double* X, int64_t rs, int64_t ls, int64_t ps, int64_t count,

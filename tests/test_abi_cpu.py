@@ -96,6 +96,41 @@ def test_ex_options_validated():
     assert rc == _lib.ERR_UNSUPPORTED
 
 
+def test_crt_form_host_rules():
+    """Residue form: feasibility by modulus count, workspace checks, all on
+    the host before any GPU work."""
+    L = mp.load()
+    D4 = C.c_double * 4
+    one4, zero4 = D4(1.0, 0, 0, 0), D4(0, 0, 0, 0)
+    o = mp.make_opts("crt")                       # QD at its default s = 31: 49 moduli do not suffice
+    rc = L.mpgemm_qd_ex(b"N", b"N", 4, 5, 6, one4, FAKE_A, 4, 24, FAKE_B, 6, 30, zero4, FAKE_C, 4, 20,
+                        None, C.byref(o))
+    assert rc == _lib.ERR_UNSUPPORTED
+    assert L.mpgemm_workspace_bytes(4, 5, 4, 5, 6, 0, -1) == 0
+    o = mp.make_opts("crt", slices=25)            # s > 24
+    rc = L.mpgemm_dd_ex(b"N", b"N", 4, 5, 6, ONE, FAKE_A, 4, 24, FAKE_B, 6, 30, ZERO, FAKE_C, 4, 20,
+                        None, C.byref(o))
+    assert rc == _lib.ERR_UNSUPPORTED
+    o = mp.make_opts("crt")                       # k beyond exact int32 sums of byte products
+    rc = L.mpgemm_dd_ex(b"N", b"N", 4, 5, 131072, ONE, FAKE_A, 4, 4 * 131072, FAKE_B, 131072,
+                        5 * 131072, ZERO, FAKE_C, 4, 20, None, C.byref(o))
+    assert rc == _lib.ERR_UNSUPPORTED
+    o = mp.make_opts("crt")                       # feasible, but no workspace
+    rc = L.mpgemm_dd_ex(b"N", b"N", 4, 5, 6, ONE, FAKE_A, 4, 24, FAKE_B, 6, 30, ZERO, FAKE_C, 4, 20,
+                        None, C.byref(o))
+    assert rc == _lib.ERR_WORKSPACE
+    o = mp.make_opts("crt", variant=1)
+    rc = L.mpgemm_td_ex(b"N", b"N", 4, 5, 6, D4(1, 0, 0, 0), FAKE_A, 4, 24, FAKE_B, 6, 30, D4(), FAKE_C,
+                        4, 20, None, C.byref(o))
+    assert rc == _lib.ERR_UNSUPPORTED
+    # workspace: exponents, N residue planes per operand, N result bytes per entry
+    b16 = L.mpgemm_workspace_bytes(2, 5, 100, 100, 4096, 16, 1)      # DD: 32 moduli
+    assert b16 >= 32 * (128 * 4096 * 2 + 128 * 128)
+    b23 = L.mpgemm_workspace_bytes(3, 5, 100, 100, 4096, 0, 1)       # TD default s = 23: 48 moduli
+    assert b23 >= 48 * (128 * 4096 * 2 + 128 * 128) > b16
+    assert mp.num_configs(2, "crt") == 2
+
+
 def test_vec_validation():
     L = mp.load()
     assert L.mp_vec_td_add(-1, None, 0, None, 0, None, 0, None) == -1

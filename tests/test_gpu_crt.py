@@ -1,0 +1,130 @@
+"""Residue (CRT) form of the split product on the GPU: bit for bit against
+the oracle's residue form (the exact product of the digit integers, rounded
+component by component), on ragged shapes, every transpose pair, odd and
+even digit counts and every modulus-count bucket; at the benchmark size on
+sampled blocks, and within the truncation bound of the exact product."""
+import numpy as np
+import pytest
+
+import oracle
+from tests import synth
+from tests.exact import GemmChecker, sample_entries
+from tests.gpu_util import dev, host, note
+
+pytestmark = pytest.mark.gpu
+
+
+def make(P, ta, tb, m, n, k, cfg, exp_range=None):
+    A_rows, A_cols = (m, k) if ta == "N" else (k, m)
+    B_rows, B_cols = (k, n) if tb == "N" else (n, k)
+    A = synth.mp_matrix(cfg, "A", P, A_rows, A_cols, exp_range=exp_range)
+    B = synth.mp_matrix(cfg, "B", P, B_rows, B_cols, exp_range=exp_range)
+    C = synth.mp_matrix(cfg, "C", P, m, n)
+    return A, B, C, synth.mp_scalar(cfg, "alpha", P), synth.mp_scalar(cfg, "beta", P)
+
+
+def run(gpu_lib, P, ta, tb, m, n, k, alpha, A, B, beta, C, s, tile=-1):
+    ws = gpu_lib.alloc_workspace(P, m, n, k, s, tile, form="crt")
+    dC = dev(C)
+    gpu_lib.gemm(P, ta, tb, m, n, k, alpha, dev(A), dev(B), beta, dC, form="crt", slices=s, tile=tile,
+                 workspace=ws)
+    return host(dC)
+
+
+CASES = [
+    # P, ta, tb, m, n, k, s, tile        (moduli: from k and s)
+    (2, "N", "N", 130, 67, 100, 16, 0),    # 31 moduli, 8 limbs
+    (2, "T", "N", 64, 64, 64, 5, 1),       # odd s; 10 moduli, 4 limbs
+    (3, "N", "T", 97, 140, 33, 23, 1),     # 46 moduli, 11 limbs
+    (3, "T", "T", 129, 31, 70, 23, 0),
+    (4, "N", "N", 1, 1, 1, 9, 1),          # 16 moduli
+    (4, "T", "N", 200, 3, 129, 20, 0),     # QD with a feasible s: 40 moduli
+    (2, "N", "T", 33, 65, 17, 1, 1),       # one digit: 3 moduli
+    (2, "N", "N", 257, 300, 1000, 16, 0),  # 16 k-tiles
+    (3, "N", "N", 65, 70, 2000, 23, 1),    # 48 moduli, 11 limbs
+    (2, "T", "T", 70, 129, 300, 11, 1),    # 21 moduli, 6 limbs
+    (3, "N", "N", 50, 40, 90, 14, 0),      # 27 moduli
+    (2, "N", "T", 50, 60, 50, 13, 0),      # 25 moduli, 6 limbs
+    (4, "T", "T", 40, 41, 129, 20, 1),     # 40 moduli
+]
+
+
+@pytest.mark.parametrize("P,ta,tb,m,n,k,s,tile", CASES)
+def test_bitwise_against_oracle(gpu_lib, P, ta, tb, m, n, k, s, tile):
+    A, B, C, alpha, beta = make(P, ta, tb, m, n, k, cfg=5)
+    note("crt", P, ta, tb, (m, n, k), "s", s, "tile", tile)
+    got = run(gpu_lib, P, ta, tb, m, n, k, alpha, A, B, beta, C, s, tile)
+    want = oracle.gemm_crt(P, s, ta, tb, m, n, k, alpha, A, B, beta, C)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("P", [2, 3])
+def test_exponent_spread_and_beta_zero(gpu_lib, P):
+    """Entries u 2^e with e in -30..30 per entry (wide scale exponents, long
+    remainders), beta = 0 and alpha = 1."""
+    m, n, k = 90, 75, 130
+    s = gpu_lib.DEFAULT_SLICES[P]
+    A, B, _, _, _ = make(P, "N", "N", m, n, k, cfg=3, exp_range=(-30, 30))
+    one, zero = synth.mp_one(P), np.zeros(P)
+    C = np.full((P, n, m), np.nan)          # beta = 0: C is not read
+    note("crt spread", P, (m, n, k))
+    got = run(gpu_lib, P, "N", "N", m, n, k, one, A, B, zero, C, s)
+    want = oracle.gemm_crt(P, s, "N", "N", m, n, k, one, A, B, zero, np.zeros((P, n, m)))
+    assert np.array_equal(got, want)
+
+
+def test_integers_exact(gpu_lib):
+    """Integer operands below 2^12: the product is the exact integer matrix."""
+    P, m, n, k = 2, 70, 66, 300
+    rng = np.random.Generator(np.random.PCG64(77))
+    A = np.zeros((P, k, m)); A[0] = rng.integers(-4096, 4096, (k, m))
+    B = np.zeros((P, n, k)); B[0] = rng.integers(-4096, 4096, (n, k))
+    one, zero = synth.mp_one(P), np.zeros(P)
+    note("crt integers", (m, n, k))
+    got = run(gpu_lib, P, "N", "N", m, n, k, one, A, B, zero, np.zeros((P, n, m)), 16)
+    exact = A[0].T.astype(np.int64) @ B[0].T.astype(np.int64)
+    assert np.array_equal(got[0].T, exact.astype(np.float64)) and not got[1:].any()
+
+
+@pytest.mark.parametrize("P", [2, 3])
+def test_full_size_sampled(gpu_lib, P):
+    """The benchmark's square workload (n = 4096, default digits): sampled
+    blocks bit-identical to the oracle's residue form, sampled entries within
+    the split form's bound of the exact product."""
+    n = 4096
+    A, B, C, alpha, beta = make(P, "N", "N", n, n, n, cfg=2)
+    s = gpu_lib.DEFAULT_SLICES[P]
+    note("crt full size", P, n, s)
+    got = run(gpu_lib, P, "N", "N", n, n, n, alpha, A, B, beta, C, s)
+    rng = synth.rng_for(2, 9)                # a seed slot of its own
+    r0 = int(rng.integers(0, n - 2))
+    c0 = int(rng.integers(0, n - 16))
+    for rows, cols in [((r0, r0 + 2), (c0, c0 + 16)), ((n - 1, n), (n - 8, n)), ((0, 1), (0, 8))]:
+        want = oracle.gemm_crt(P, s, "N", "N", n, n, n, alpha, A, B, beta, C, rows=rows, cols=cols)
+        blk = (slice(None), slice(*cols), slice(*rows))
+        assert np.array_equal(got[blk], want[blk]), (P, rows, cols)
+    chk = GemmChecker(P, "N", "N", n, n, n, alpha, A, B, beta, C)
+    r = chk.ratios(got, sample_entries(rng, n, n, 64))
+    print(f"crt P={P} n={n} s={s}: max err / (k u (|alpha||A||B| + |beta||C|)) = {r.max():.3g}")
+    assert r.max() <= 8 * (n + 2) / n
+
+
+def test_repeat_and_workspace_reuse(gpu_lib):
+    """Deterministic: repeated calls, a larger reused workspace and both
+    tile configurations give the same bits."""
+    P, m, n, k, s = 3, 150, 130, 260, 23
+    A, B, C, alpha, beta = make(P, "T", "N", m, n, k, cfg=6)
+    big = gpu_lib.alloc_workspace(P, 300, 300, 600, s, 0, form="crt")
+    outs = []
+    for tile in (0, 1, 0):
+        note("crt reuse", tile)
+        dC = dev(C)
+        gpu_lib.gemm(P, "T", "N", m, n, k, alpha, dev(A), dev(B), beta, dC, form="crt", slices=s,
+                     tile=tile, workspace=big)
+        outs.append(host(dC))
+    assert all(np.array_equal(outs[0], o) for o in outs[1:])
+    small = gpu_lib.alloc_workspace(P, 8, 8, 8, s, 0, form="crt")
+    with pytest.raises(gpu_lib.MPGemmError) as e:
+        gpu_lib.gemm(P, "T", "N", m, n, k, alpha, dev(A), dev(B), beta, dev(C), form="crt", slices=s,
+                     tile=0, workspace=small)
+    assert e.value.code == 2

@@ -110,6 +110,8 @@ def parse():
                     help="BLAS-1/2 (axpy, dot, gemv) in DD/TD/QD against the HBM roofline")
     ap.add_argument("--strassen", action="store_true",
                     help="Strassen's method (Sec. 3, Fig. 5) against the plain form, n = 4096")
+    ap.add_argument("--crt", action="store_true",
+                    help="residue (CRT) split form against the triangular split form, DD and TD")
     return ap.parse_args()
 
 
@@ -152,6 +154,8 @@ def main():
         return strassen_bench(args, mp, synth, dev, stream)
     if args.blas:
         return blas_bench(args, mp, dev, stream)
+    if args.crt:
+        return crt_bench(args, mp, synth, dev, stream)
     n = args.n
     precs = [int(p) for p in args.prec.split(",")]
     forms = args.forms.split(",")
@@ -492,6 +496,71 @@ def strassen_bench(args, mp, synth, dev, stream):
                                   "Strassen's method over it", "n": n,
                       "err_units": "err_ratio_max: |C - C*| / (k u |A||B|); normwise_err: |C - C*| / "
                                    "(u max|A| max|B| n); 32 sampled entries"},
+           "breakdown": parts}
+    print(json.dumps(out), flush=True)
+
+
+def crt_bench(args, mp, synth, dev, stream):
+    """C = alpha A B + beta C at m = n = k = args.n in DD and TD (default
+    digits): the triangular split form (one INT8 product per digit pair,
+    s (s + 1) / 2 of them) against its residue form (one per modulus) with
+    each tile configuration.  Time and error on sampled entries (k u
+    (|alpha||A||B| + |beta||C|)).  One JSON line."""
+    import numpy as np
+    import torch
+    from tests.exact import GemmChecker, sample_entries
+    n = args.n
+    parts = {}
+    for P in (2, 3):
+        A = synth.mp_matrix(2, "A", P, n, n)
+        B = synth.mp_matrix(2, "B", P, n, n)
+        C = synth.mp_matrix(2, "C", P, n, n)
+        alpha, beta = synth.mp_scalar(2, "alpha", P), synth.mp_scalar(2, "beta", P)
+        dA, dB, dC0 = (torch.from_numpy(x).to(dev) for x in (A, B, C))
+        s = mp.DEFAULT_SLICES[P]
+        chk = GemmChecker(P, "N", "N", n, n, n, alpha, A, B, beta, C)
+        ents = sample_entries(synth.rng_for(2, "samples"), n, n, 32)
+        runs = [("split", -1)] + [("crt", t) for t in range(mp.num_configs(P, "crt"))]
+        for form, tile in runs:
+            ws = mp.alloc_workspace(P, n, n, n, s, tile, device=dev, form=form)
+            dC = dC0.clone()
+            call = lambda: mp.gemm(P, "N", "N", n, n, n, alpha, dA, dB, beta, dC, form=form,  # noqa: E731
+                                   slices=s, tile=tile, workspace=ws, stream=stream)
+            call()
+            torch.cuda.synchronize()
+            times = []
+            for _ in range(max(3, args.steps)):
+                dC.copy_(dC0)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                call()
+                e1.record(stream)
+                torch.cuda.synchronize()
+                times.append(e0.elapsed_time(e1))
+            ms = float(np.median(times))
+            r = chk.ratios(dC.cpu().numpy(), ents)
+            key = f"{NAME[P]}_{form}" + (f"_tile{tile}" if form == "crt" else "")
+            products = s * (s + 1) // 2 if form == "split" else mp.crt_moduli(P, n, s)
+            parts[key] = {"ms": round(ms, 3), "2mnk/s": 2.0 * n ** 3 / (ms * 1e-3), "s": s,
+                          "int8_products": products,
+                          "int8_ops/s": products * 2.0 * n ** 3 / (ms * 1e-3),
+                          "err_ratio_max": float(r.max())}
+            note("crt", key, round(ms, 3), "ms", f"{r.max():.3g}")
+            del ws, dC
+            torch.cuda.empty_cache()
+        best = min(v["ms"] for k_, v in parts.items() if k_.startswith(NAME[P] + "_crt"))
+        parts[f"{NAME[P]}_crt_speedup_vs_split"] = round(parts[f"{NAME[P]}_split"]["ms"] / best, 3)
+        del dA, dB, dC0
+    best_ms = [min(v["ms"] for k_, v in parts.items() if k_.startswith(nm + "_crt") and isinstance(v, dict))
+               for nm in ("DD", "TD")]
+    out = {"metric": "DD/TD GEMM 2mnk/s, residue split form", "unit": "2mnk/s",
+           "value": 2.0 * n ** 3 * 2 / (sum(best_ms) * 1e-3), "n_gpus": 1, "steps": max(3, args.steps),
+           "warmup": 1, "ms_per_step": round(sum(best_ms), 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "i8", "data": "synthetic",
+           "config": {"workload": f"C = alpha A B + beta C, m = n = k = {n}, DD (s = 16) and TD (s = 23), "
+                                  "triangular split form vs residue form", "n": n,
+                      "err_units": "|C - C*| / (k u (|alpha||A||B| + |beta||C|)), 32 sampled entries"},
            "breakdown": parts}
     print(json.dumps(out), flush=True)
 

@@ -192,6 +192,12 @@ int mpgemm_qd_ex(char transa, char transb, int64_t m, int64_t n, int64_t k, cons
                  int64_t b_plane_stride, const double* beta, double* C, int64_t ldc,
                  int64_t c_plane_stride, hipStream_t stream, const mpgemm_opts* opts);
 
+/* Residue form: the number of moduli (INT8 products) N for inner dimension
+ * k and s digits per entry (slices 0 = the default of precision prec), or 0
+ * when the first 49 moduli do not suffice or k is outside 1..131071; -1 for
+ * an invalid precision. */
+int mpgemm_crt_moduli(int prec, int64_t k, int slices);
+
 /* Workspace bytes the split forms (MPGEMM_FORM_SPLIT_I8, _AUTO, _SPLIT_CRT)
  * need for this shape (0 for the plain form; for the residue form also 0 when
  * no modulus count suffices; slices 0 = default; tile -1 = the one the

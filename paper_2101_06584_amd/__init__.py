@@ -4,7 +4,7 @@ ALUs, a split form on the INT8 matrix cores, a batched persistent form and an
 autotuner, behind the C ABI in include/mpgemm.h.  This package is the thin
 Python binding (PyTorch supplies device memory and streams)."""
 from .api import (BatchPlan, DEFAULT_SLICES, MPGemmError, PREC, alloc_workspace, autotune, axpy,  # noqa: F401
-                  dot, dot_raw, dot_workspace, gemv, gemv_raw,
+                  crt_moduli, dot, dot_raw, dot_workspace, gemv, gemv_raw,
                   autotune_load, autotune_save, autotune_set, batch_autotune, gemm, gemm_raw, load,
                   make_opts, num_configs, probe_peak, split_layout, split_stages, tune_slices, vec, vec_raw,
                   version, workspace_bytes)

@@ -44,6 +44,7 @@ EXPORTS = {
     "mpgemm_td_ex": (_GEMM_ARGS + [_P(Opts)], _int),
     "mpgemm_qd_ex": (_GEMM_ARGS + [_P(Opts)], _int),
     "mpgemm_workspace_bytes": ([_int, _int, _i64, _i64, _i64, _int, _int], _sz),
+    "mpgemm_crt_moduli": ([_int, _i64, _int], _int),
     "mp_vec_dd_add": (_VEC_ARGS, _int), "mp_vec_dd_mul": (_VEC_ARGS, _int),
     "mp_vec_td_add": (_VEC_ARGS, _int), "mp_vec_td_mul": (_VEC_ARGS, _int),
     "mp_vec_qd_add": (_VEC_ARGS, _int), "mp_vec_qd_mul": (_VEC_ARGS, _int),

@@ -81,6 +81,12 @@ def make_opts(form="plain", slices=0, tile=-1, workspace: torch.Tensor | None = 
     return o
 
 
+def crt_moduli(prec, k, slices=0) -> int:
+    """Moduli (INT8 products) of the residue form for inner dimension k and
+    `slices` digits (0 = default); 0 when it does not apply."""
+    return int(_lib.load().mpgemm_crt_moduli(PREC[prec], k, slices))
+
+
 def workspace_bytes(prec, form, m, n, k, slices=0, tile=-1) -> int:
     P = PREC[prec]
     f = FORMS[form] if isinstance(form, str) else int(form)

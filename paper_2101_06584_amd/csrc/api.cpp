@@ -161,8 +161,7 @@ int pick_tile(int P, int form, int64_t m, int64_t n, int64_t k, int requested) {
         if (requested >= 0 && requested < kCrtConfigs) return requested;
         const int t = tuned_tile(P, form, m, n, k);
         if (t >= 0 && t < kCrtConfigs) return t;
-        // 64 x 64 output tiles when 128 x 128 ones leave CUs idle
-        return (((m + 127) / 128) * ((n + 127) / 128) >= 512) ? 0 : 1;
+        return crt_default_config(m, n);
     }
     const int nconf = form == MPGEMM_FORM_SPLIT_I8 ? kSplitConfigs : kPlainConfigs;
     if (requested >= 0 && requested < nconf) return requested;
@@ -295,6 +294,12 @@ size_t mpgemm_workspace_bytes(int prec, int form, int64_t m, int64_t n, int64_t 
     const int s = slices > 0 ? slices : kDefaultSlices[prec];
     const int cfg = pick_tile(prec, MPGEMM_FORM_SPLIT_I8, m, n, k, tile);
     return split_workspace_bytes(prec, m, n, k, s, cfg);
+}
+
+int mpgemm_crt_moduli(int prec, int64_t k, int slices) {
+    if (prec < 2 || prec > 4) return -1;
+    if (slices < 0 || slices > kMaxSlices) return 0;
+    return crt_moduli_count(k, slices > 0 ? slices : kDefaultSlices[prec]);
 }
 
 int mpgemm_split_layout(int prec, int64_t m, int64_t n, int64_t k, int slices, int tile,

@@ -41,7 +41,8 @@ namespace {
 
 constexpr int kNumModuli = 49;
 constexpr int kLimbs = 11;          // 32-bit limbs: the product of all moduli has 342 bits
-constexpr int kMaxPairs = 18;       // digit pairs for s <= 35
+constexpr int kMaxCrtDigits = 24;  // 14 s + log2 k - 1 < 342 bits needs s <= 24
+constexpr int kCrtTileK = 32;       // k bytes per residue tile row and per product step
 
 // Greedy pairwise coprime moduli from 256 down: every m <= 256 coprime to
 // all larger ones taken so far.  Their product reaches 2^341.87.
@@ -57,6 +58,8 @@ struct CrtTables {
     uint32_t W[kNumModuli * (kNumModuli + 1) / 2][kLimbs];
     double inv[kNumModuli];          // 1 / m_t, rounded to nearest
     int mod[kNumModuli];             // m_t
+    double Md[kNumModuli + 1][kLimbs];                       // M as binary64 limbs
+    double Wd[kNumModuli * (kNumModuli + 1) / 2][kLimbs];    // W as binary64 limbs
 };
 
 constexpr CrtTables make_crt_tables() {
@@ -85,6 +88,10 @@ constexpr CrtTables make_crt_tables() {
         t.inv[i] = 1.0 / (double)kModuli[i];
         t.mod[i] = kModuli[i];
     }
+    for (int r = 0; r <= kNumModuli; ++r)
+        for (int l = 0; l < kLimbs; ++l) t.Md[r][l] = (double)t.M[r][l];
+    for (int r = 0; r < kNumModuli * (kNumModuli + 1) / 2; ++r)
+        for (int l = 0; l < kLimbs; ++l) t.Wd[r][l] = (double)t.W[r][l];
     return t;
 }
 
@@ -95,24 +102,25 @@ const CrtTables& crt_host_tables() {
     return t;
 }
 
-// Per-operand digit-pair weights, passed by value: w[e][t] congruent to
-// 2^(14 e) (times u_t for op(A)) modulo m_t, in [-128, 127]; zero for t >= N.
+// Per-operand digit weights, passed by value: w[t][p] congruent to
+// 128^(s - 1 - p) (times u_t for op(A)) modulo m_t, in [-128, 127]; zero for
+// p >= s and t >= N (64 columns: two MFMA groups of 32 moduli).
 struct CrtWeights {
-    int8_t w[kMaxPairs][kNumModuli];
+    int8_t w[64][32];
 };
 
-// Output tile (bm x bn) and LDS ring depth of the per-modulus product.
+// Output tile (bm x bn) of the per-modulus product and workgroups per CU.
 struct CrtConfig {
-    int bm, bn;
+    int bm, bn, per_cu;
 };
-constexpr CrtConfig kCrt[kCrtConfigs] = {{128, 128}, {64, 64}};
+constexpr CrtConfig kCrt[kCrtConfigs] = {{256, 256, 1}, {256, 128, 2}, {128, 128, 2}};
 
 inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct CrtLayout {
     int64_t Mp, Np, Kp;
-    size_t oE, oF, oRA, oRB, oY, total;
+    size_t oE, oF, oMX, oRA, oRB, oY, total;
 };
 
 CrtLayout crt_layout(int64_t m, int64_t n, int64_t k, int N, int cfg) {
@@ -124,6 +132,7 @@ CrtLayout crt_layout(int64_t m, int64_t n, int64_t k, int N, int cfg) {
     size_t off = 0;
     L.oE = off;  off = align256(off + sizeof(int32_t) * L.Mp);
     L.oF = off;  off = align256(off + sizeof(int32_t) * L.Np);
+    L.oMX = off; off = align256(off + sizeof(uint64_t) * (L.Mp + L.Np));
     L.oRA = off; off = align256(off + (size_t)N * L.Mp * L.Kp);
     L.oRB = off; off = align256(off + (size_t)N * L.Np * L.Kp);
     L.oY = off;  off = align256(off + (size_t)N * L.Mp * L.Np);
@@ -132,11 +141,20 @@ CrtLayout crt_layout(int64_t m, int64_t n, int64_t k, int N, int cfg) {
 }
 
 // ---------------------------------------------------------------------------
-// Stage 2: residues.  Block (kt, row tile) handles 16 rows x 64 k; thread t
-// owns row t / 16 and the four k entries 4 (t % 16) .. + 3, so that one
-// 32-bit store per modulus writes its four residue bytes.  Residue plane t
-// has the digit planes' layout: byte (r, l) at
-// R[((t (Kp/64) + l/64) Rp + r) 64 + l % 64].
+// Stage 2: residues.  Block (64-wide k segment, row tile) stages 16 rows x 64
+// k of the P component planes through LDS (loads coalesced along whichever
+// index is contiguous); wave w then takes rows 4 w .. 4 w + 3 one at a time,
+// lane L the entry (r, l) with l = 64 segment + L.  The lane computes the
+// entry's digits d_1..d_s (the split form's slicing arithmetic) into bytes
+// 0..s-1 of eight dwords.  The weighted sums a_t = sum_p d_p w_pt, with w_pt
+// congruent to 128^(s-p) (times u_t for op(A)) modulo m_t in [-128, 127], are
+// the product of the 64 x 32 digit block with the 32 x 32 weight block of
+// each group of 32 moduli: two INT8 MFMAs per group (|a_t| <= 24 64 128 <
+// 2^18, exact).  Each a_t is reduced to a residue in [-128, 127] in single
+// precision (exact: |a_t| < 2^24 and the quotient is the nearest integer or
+// off by one only next to a half-integer, so |a_t - q m_t| <= m_t / 2 + 1/8).
+// Residue plane t is cut into 32-byte k-tiles:
+// byte (r, l) at R[((t (Kp/32) + l/32) Rp + r) 32 + l % 32].
 // ---------------------------------------------------------------------------
 
 constexpr int kResRows = 16;
@@ -159,22 +177,7 @@ __device__ __forceinline__ int next_digit(double (&r)[P], int p) {
     return (int)d;
 }
 
-// A value congruent to a modulo MOD in [-128, 127], for |a| < 2^24.2: the
-// quotient from a single-precision reciprocal is off by at most one, so
-// |a - q MOD| <= 0.62 MOD and one correction brings large moduli in range.
-template <int MOD>
-__device__ __forceinline__ int reduce_byte(int a) {
-    constexpr float inv = 1.0f / (float)MOD;
-    const int q = (int)rintf((float)a * inv);
-    int r = a - __mul24(q, MOD);
-    if constexpr (MOD > 190) {
-        r = r > 127 ? r - MOD : r;
-        r = r < -128 ? r + MOD : r;
-    }
-    return r;
-}
-
-template <int P, int NB>
+template <int P, int NG>
 __global__ __launch_bounds__(256) void crt_residue_kernel(const double* __restrict__ X, int64_t rs,
                                                           int64_t ls, int64_t ps, int64_t count,
                                                           int64_t k, const int32_t* __restrict__ E,
@@ -182,9 +185,9 @@ __global__ __launch_bounds__(256) void crt_residue_kernel(const double* __restri
                                                           int8_t* __restrict__ R, int64_t Rp,
                                                           int64_t Kp) {
     __shared__ double tile[P][kResRows][kTileK + 1];
-    const int64_t kt = blockIdx.x;
+    const int64_t seg = blockIdx.x;
     const int64_t r0 = (int64_t)blockIdx.y * kResRows;
-    const int64_t l0 = kt * kTileK;
+    const int64_t l0 = seg * kTileK;
     const int t = threadIdx.x;
     const bool rows_contig = (rs == 1);
 #pragma unroll
@@ -199,83 +202,118 @@ __global__ __launch_bounds__(256) void crt_residue_kernel(const double* __restri
     }
     __syncthreads();
 
-    const int rr = t >> 4, lq = t & 15;
-    const int64_t gr = r0 + rr;
-    const int32_t Ei = (gr < count) ? E[gr] : 0;
-    // digit pairs (p, p + 1) from p = start; digit 0 is zero when s is odd
-    const int start = (s & 1) ? 0 : 1;
-    const int npairs = (s + 1 - start) / 2;
-    uint32_t word[NB];
+    const int lane = t & 63, wave = t >> 6;
+    // this lane's weight columns (modulus 32 cg + lane % 32, digits
+    // 16 (lane / 32) .. + 15) and its moduli for the reduction
+    v4i bw[NG];
+    float mf[NG], invm[NG];
 #pragma unroll
-    for (int i = 0; i < NB; ++i) word[i] = 0;
+    for (int cg = 0; cg < NG; ++cg) {
+        const int tt = 32 * cg + (lane & 31);
+        const uint32_t* wp = (const uint32_t*)wt.w[tt] + 4 * (lane >> 5);
+        bw[cg] = v4i{(int)wp[0], (int)wp[1], (int)wp[2], (int)wp[3]};
+        const int m = tt < kNumModuli ? kCrtDev.mod[tt] : 1;
+        mf[cg] = (float)m;
+        invm[cg] = 1.0f / (float)m;
+    }
+    const int64_t nkt = Kp / kCrtTileK;
 #pragma unroll 1
-    for (int e4 = 0; e4 < 4; ++e4) {
+    for (int rw = 0; rw < 4; ++rw) {
+        const int rr = wave * 4 + rw;
+        const int64_t gr = r0 + rr;
+        const int32_t Ei = (gr < count) ? E[gr] : 0;
         double rem[P];
 #pragma unroll
-        for (int p = 0; p < P; ++p) rem[p] = ldexp(tile[p][rr][4 * lq + e4], -Ei);
-        int acc[NB];
+        for (int p = 0; p < P; ++p) rem[p] = ldexp(tile[p][rr][lane], -Ei);
+        uint32_t dg[8];
 #pragma unroll
-        for (int i = 0; i < NB; ++i) acc[i] = 0;
-        int p = start;
-#pragma unroll 1
-        for (int g = 0; g < npairs; ++g, p += 2) {
-            const int d1 = (p == 0) ? 0 : next_digit<P>(rem, p);
-            const int d2 = next_digit<P>(rem, p + 1);
-            const int c = d1 * 128 + d2;              // |c| <= 8256
-            const int8_t* w = wt.w[npairs - 1 - g];
+        for (int i = 0; i < 8; ++i) dg[i] = 0u;
 #pragma unroll
-            for (int i = 0; i < NB; ++i) acc[i] = __mul24(c, (int)w[i]) + acc[i];
+        for (int p = 1; p <= kMaxCrtDigits; ++p)
+            if (p <= s) dg[(p - 1) / 4] |= ((uint32_t)next_digit<P>(rem, p) & 255u) << (8 * ((p - 1) % 4));
+        // A fragments: lane L < 32 gives digits 0..15 of entry L (first MFMA)
+        // or of entry L + 32 (second), lane L >= 32 digits 16..31 of entry
+        // L - 32 (first) or L (second); the halves trade through a lane swap
+        const v4i lo = {(int)dg[0], (int)dg[1], (int)dg[2], (int)dg[3]};
+        const v4i hi = {(int)dg[4], (int)dg[5], (int)dg[6], (int)dg[7]};
+        const bool low = lane < 32;
+        const v4i x = low ? hi : lo;
+        v4i xs;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) xs[c] = __shfl_xor(x[c], 32, 64);
+        const v4i a1 = low ? lo : xs;
+        const v4i a2 = low ? xs : hi;
+#pragma unroll
+        for (int cg = 0; cg < NG; ++cg) {
+            v16i acc[2];
+            acc[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, bw[cg], v16i{0}, 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, bw[cg], v16i{0}, 0, 0, 0);
+            const int tt = 32 * cg + (lane & 31);
+            if (tt >= N) continue;
+#pragma unroll
+            for (int eg = 0; eg < 2; ++eg)
+#pragma unroll
+                for (int v4 = 0; v4 < 4; ++v4) {
+                    uint32_t word = 0;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const float a = (float)acc[eg][4 * v4 + q];
+                        float r = fmaf(-rintf(a * invm[cg]), mf[cg], a);
+                        r = r >= 127.5f ? r - mf[cg] : r;
+                        word |= ((uint32_t)(int)r & 255u) << (8 * q);
+                    }
+                    // entries 32 eg + 8 v4 + 4 (lane / 32) + 0..3 of this row
+                    const int64_t l = l0 + 32 * eg + 8 * v4 + 4 * (lane >> 5);
+                    *(uint32_t*)(R + ((tt * nkt + l / kCrtTileK) * Rp + gr) * kCrtTileK + l % kCrtTileK) = word;
+                }
         }
-        static_for<NB>([&](auto ic) __attribute__((always_inline)) {
-            constexpr int i = decltype(ic)::value;
-            const int r = reduce_byte<kModuli[i]>(acc[i]);
-            word[i] |= (uint32_t)(r & 255) << (8 * e4);
-        });
     }
-    if (gr >= Rp) return;
-    const int64_t nkt = Kp / kTileK;
-    uint8_t* out = (uint8_t*)R + (kt * Rp + gr) * kTileK + 4 * lq;
-#pragma unroll
-    for (int i = 0; i < NB; ++i)
-        if (i < N) *(uint32_t*)(out + (int64_t)i * nkt * Rp * kTileK) = word[i];
 }
 
 // ---------------------------------------------------------------------------
 // Stage 3: one INT8 product per modulus on the matrix cores.
 //
-// One workgroup (4 waves in 2 x 2) owns a BM x BN output tile and walks the
-// steps (modulus t, k-tile kt) in order t nkt + kt; since residue planes are
-// stored modulus-major and k-tile-major, the tiles of step u sit at
-// RA + u Mp 64 + m0 64 and RB + u Np 64 + n0 64.  Tiles are staged D steps
-// deep through LDS by 16-byte direct-to-LDS copies (the split form's scheme:
-// swizzled 64-byte rows, a wave waits for its own copies and then meets the
-// others at a barrier).  After the last k-tile of a modulus the int32 sums
-// are reduced to y = sum mod m_t in [0, m_t) (exactly, in binary64), four
+// One workgroup (WGM x WGN waves) owns a BM x BN output tile and walks the
+// steps (modulus t, k-tile kt) in order t (Kp/32) + kt; since residue planes
+// are stored modulus-major and k-tile-major, the tiles of step u are the
+// contiguous blocks at RA + (u Mp + m0) 32 and RB + (u Np + n0) 32.  They are
+// staged D steps deep through LDS by 16-byte direct-to-LDS copies: a wave
+// waits for its own copies of the step it computes (vector-memory counter)
+// and then meets the others at a barrier, so no register holds data in
+// flight.  The 16-byte half c of tile row r sits at LDS half c ^ ((r / 4) % 2)
+// of that row, so that the fragment reads (32 rows, one half each) hit
+// distinct banks.  After the last k-tile of a modulus the int32 sums are
+// reduced to y = sum mod m_t in [0, m_t) (exactly, in binary64), four
 // consecutive rows packed per 32-bit store into plane t of Y (column-major,
 // Y[(t Np + col) Mp + row]), and the accumulators cleared.
 // ---------------------------------------------------------------------------
 
-template <int BM, int BN, int D>
+template <int BM, int BN, int WGM, int WGN, int D>
 struct CrtDma {
-    static constexpr int WM = BM / 2, WN = BN / 2;
-    static constexpr int FM = WM / 32, FN = WN / 32;
-    static constexpr int KS = kTileK / 32;
-    static constexpr int A_BYTES = BM * kTileK, B_BYTES = BN * kTileK;
+    static constexpr int NT = 64 * WGM * WGN;             // threads
+    static constexpr int WM = BM / WGM, WN = BN / WGN;    // wave block
+    static constexpr int FM = WM / 32, FN = WN / 32;      // MFMA tiles per wave
+    static constexpr int A_BYTES = BM * kCrtTileK, B_BYTES = BN * kCrtTileK;
     static constexpr int STAGE = A_BYTES + B_BYTES;
-    static constexpr int A_LOADS = A_BYTES / 4096, B_LOADS = B_BYTES / 4096;
+    static constexpr int ROUND = NT * 16;                 // bytes one copy instruction moves
+    static constexpr int A_LOADS = A_BYTES / ROUND, B_LOADS = B_BYTES / ROUND;
     static constexpr int PER_STEP = A_LOADS + B_LOADS;
     static constexpr int LDS_BYTES = D * STAGE;
-    static_assert(A_BYTES % 4096 == 0 && B_BYTES % 4096 == 0, "tiles split into 1 KiB wave copies");
+    static_assert(A_BYTES % ROUND == 0 && B_BYTES % ROUND == 0, "tiles split into whole copy rounds");
+    static_assert(WM % 32 == 0 && WN % 32 == 0, "wave block of 32 x 32 MFMA tiles");
     static_assert(PER_STEP * (D - 2) <= 63, "vector-memory counter range");
-    static_assert(LDS_BYTES <= 65536, "two workgroups per CU");
+    static_assert(LDS_BYTES <= 65536, "64 KiB LDS window per workgroup");
 };
 
-template <int BM, int BN, int D>
-__global__ __launch_bounds__(256, 2) void crt_mfma_kernel(const int8_t* __restrict__ RA,
-                                                          const int8_t* __restrict__ RB,
-                                                          uint8_t* __restrict__ Y, int64_t Mp,
-                                                          int64_t Np, int64_t Kp, int N) {
-    using T = CrtDma<BM, BN, D>;
+// LDS offset of 16-byte half c of row r in a 32-byte-row tile
+__device__ __forceinline__ int swz32(int r, int c) { return r * kCrtTileK + ((c ^ ((r >> 2) & 1)) << 4); }
+
+template <int BM, int BN, int WGM, int WGN, int D>
+__global__ __launch_bounds__(64 * WGM * WGN, 2) void crt_mfma_kernel(const int8_t* __restrict__ RA,
+                                                                     const int8_t* __restrict__ RB,
+                                                                     uint8_t* __restrict__ Y, int64_t Mp,
+                                                                     int64_t Np, int64_t Kp, int N) {
+    using T = CrtDma<BM, BN, WGM, WGN, D>;
     __shared__ __attribute__((aligned(1024))) int8_t lds[T::LDS_BYTES];
 
     int64_t tm, tn;
@@ -283,44 +321,41 @@ __global__ __launch_bounds__(256, 2) void crt_mfma_kernel(const int8_t* __restri
     const int64_t m0 = tm * BM, n0 = tn * BN;
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
-    const int wm = wave & 1, wn = wave >> 1;
+    const int wm = wave % WGM, wn = wave / WGM;
     const int wave_lds = __builtin_amdgcn_readfirstlane(wave) * 1024;
-    const int nkt = (int)(Kp / kTileK);
+    const int nkt = (int)(Kp / kCrtTileK);
     const int steps = N * nkt;
-    const int64_t stepA = Mp * kTileK, stepB = Np * kTileK;
+    const int64_t stepA = Mp * kCrtTileK, stepB = Np * kCrtTileK;
 
-    // this lane's global byte offset within a tile for its h-th 1 KiB slot
-    // (LDS chunk u = t + 256 h -> row u / 4, global chunk (u % 4) ^ ((row / 4) % 4))
+    // this lane's global byte offset within a tile for its h-th copy round:
+    // LDS half u = t + NT h is row u / 2, position u % 2, which holds global
+    // half (u % 2) ^ ((row / 4) % 2)
     constexpr int NL = T::A_LOADS > T::B_LOADS ? T::A_LOADS : T::B_LOADS;
     int gofs[NL];
 #pragma unroll
     for (int h = 0; h < NL; ++h) {
-        const int u = t + 256 * h;
-        const int r = u >> 2;
-        gofs[h] = r * kTileK + (((u & 3) ^ ((r >> 2) & 3)) << 4);
+        const int u = t + T::NT * h;
+        const int r = u >> 1;
+        gofs[h] = r * kCrtTileK + (((u & 1) ^ ((r >> 2) & 1)) << 4);
     }
-    int aofs[T::KS][T::FM], bofs[T::KS][T::FN];
+    int aofs[T::FM], bofs[T::FN];
 #pragma unroll
-    for (int ks = 0; ks < T::KS; ++ks) {
+    for (int i = 0; i < T::FM; ++i) aofs[i] = swz32(wm * T::WM + i * 32 + (lane & 31), lane >> 5);
 #pragma unroll
-        for (int i = 0; i < T::FM; ++i) aofs[ks][i] = swz(wm * T::WM + i * 32 + (lane & 31), 2 * ks + (lane >> 5));
-#pragma unroll
-        for (int jj = 0; jj < T::FN; ++jj)
-            bofs[ks][jj] = T::A_BYTES + swz(wn * T::WN + jj * 32 + (lane & 31), 2 * ks + (lane >> 5));
-    }
+    for (int jj = 0; jj < T::FN; ++jj) bofs[jj] = T::A_BYTES + swz32(wn * T::WN + jj * 32 + (lane & 31), lane >> 5);
 
     // fetch cursor: the next step to copy; past the last step it stays on the
     // last tiles (re-copied into slots no step reads), so every step issues
     // the same number of copies, all in bounds
-    const int8_t* fa = RA + m0 * kTileK;
-    const int8_t* fb = RB + n0 * kTileK;
+    const int8_t* fa = RA + m0 * kCrtTileK;
+    const int8_t* fb = RB + n0 * kCrtTileK;
     int fstep = 0, fslot = 0;
     auto issue = [&]() __attribute__((always_inline)) {
         int8_t* la = lds + fslot * T::STAGE + wave_lds;
 #pragma unroll
-        for (int h = 0; h < T::A_LOADS; ++h) copy16_to_lds(fa + gofs[h], la + 4096 * h);
+        for (int h = 0; h < T::A_LOADS; ++h) copy16_to_lds(fa + gofs[h], la + T::ROUND * h);
 #pragma unroll
-        for (int h = 0; h < T::B_LOADS; ++h) copy16_to_lds(fb + gofs[h], la + T::A_BYTES + 4096 * h);
+        for (int h = 0; h < T::B_LOADS; ++h) copy16_to_lds(fb + gofs[h], la + T::A_BYTES + T::ROUND * h);
         if (++fstep < steps) {
             fa += stepA;
             fb += stepB;
@@ -344,21 +379,16 @@ __global__ __launch_bounds__(256, 2) void crt_mfma_kernel(const int8_t* __restri
         issue();
         const int8_t* st = lds + cslot * T::STAGE;
         cslot = (cslot + 1 == D) ? 0 : cslot + 1;
-        v4i fa_[T::KS][T::FM], fb_[T::KS][T::FN];
+        v4i fa_[T::FM], fb_[T::FN];
 #pragma unroll
-        for (int ks = 0; ks < T::KS; ++ks) {
+        for (int i = 0; i < T::FM; ++i) fa_[i] = *(const v4i*)(st + aofs[i]);
 #pragma unroll
-            for (int i = 0; i < T::FM; ++i) fa_[ks][i] = *(const v4i*)(st + aofs[ks][i]);
+        for (int jj = 0; jj < T::FN; ++jj) fb_[jj] = *(const v4i*)(st + bofs[jj]);
 #pragma unroll
-            for (int jj = 0; jj < T::FN; ++jj) fb_[ks][jj] = *(const v4i*)(st + bofs[ks][jj]);
-        }
+        for (int i = 0; i < T::FM; ++i)
 #pragma unroll
-        for (int ks = 0; ks < T::KS; ++ks)
-#pragma unroll
-            for (int i = 0; i < T::FM; ++i)
-#pragma unroll
-                for (int jj = 0; jj < T::FN; ++jj)
-                    acc[i][jj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa_[ks][i], fb_[ks][jj], acc[i][jj], 0, 0, 0);
+            for (int jj = 0; jj < T::FN; ++jj)
+                acc[i][jj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa_[i], fb_[jj], acc[i][jj], 0, 0, 0);
         if (++kt < nkt) continue;
 
         // last k-tile of modulus `mod`: reduce, store, clear
@@ -398,8 +428,8 @@ __global__ __launch_bounds__(256, 2) void crt_mfma_kernel(const int8_t* __restri
 }
 
 // ---------------------------------------------------------------------------
-// Stage 4: reconstruction, rounding and epilogue, one thread per entry (i
-// fastest).  K 32-bit limbs hold M_N (M_N < 2^(32 K)).
+// Stage 4: reconstruction, rounding and epilogue.  K 32-bit limbs hold M_N
+// (M_N < 2^(32 K)).
 // ---------------------------------------------------------------------------
 
 // Components c_0..c_{P-1} of w 2^e (w: K-limb magnitude, sign sg): c_0 = RN
@@ -475,36 +505,14 @@ __device__ __forceinline__ void limbs_to_components(uint32_t (&w)[K], double sg,
     }
 }
 
+// One entry: the limb sums L (exact), the quotient estimate f; C' in
+// two's complement, its magnitude rounded into P components, the epilogue.
 template <int P, int K>
-__global__ __launch_bounds__(256) void crt_recombine_kernel(GemmArgs g, const int32_t* __restrict__ E,
-                                                            const int32_t* __restrict__ F,
-                                                            const uint8_t* __restrict__ Y, int N,
-                                                            int s, int64_t Mp, int64_t Np) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= g.m * g.n) return;
-    const int64_t i = idx % g.m, j = idx / g.m;
-    const int64_t plane = Mp * Np;
-    const uint8_t* yp = Y + j * Mp + i;
-    const int row0 = N * (N - 1) / 2;
-
-    // S = sum_t y_t (M / m_t) limb by limb (each limb sum < 2^46, exact) and
-    // f = sum_t y_t / m_t, whose nearest integer q gives C' = S - q M
-    double L[K];
-#pragma unroll
-    for (int l = 0; l < K; ++l) L[l] = 0.0;
-    double f = 0.0;
-    for (int t = 0; t < N; ++t) {
-        const double y = (double)yp[t * plane];
-        f = fma(y, kCrtDev.inv[t], f);
-        const uint32_t* w = kCrtDev.W[row0 + t];
-#pragma unroll
-        for (int l = 0; l < K; ++l) L[l] = fma(y, (double)w[l], L[l]);
-    }
+__device__ __forceinline__ void crt_finish_entry(const GemmArgs& g, double (&L)[K], double f, int N,
+                                                 int e, int64_t i, int64_t j) {
     const double q = rint(f);
 #pragma unroll
-    for (int l = 0; l < K; ++l) L[l] = fma(-q, (double)kCrtDev.M[N][l], L[l]);
-
-    // carries: two's complement K-limb C', then sign and magnitude
+    for (int l = 0; l < K; ++l) L[l] = fma(-q, kCrtDev.Md[N][l], L[l]);
     uint32_t w[K];
     int64_t carry = 0;
 #pragma unroll
@@ -525,7 +533,7 @@ __global__ __launch_bounds__(256) void crt_recombine_kernel(GemmArgs g, const in
         sg = -1.0;
     }
     double comp[P];
-    limbs_to_components<P, K>(w, sg, E[i] + F[j] - 14 * s, comp);
+    limbs_to_components<P, K>(w, sg, e, comp);
 
     mp<P> acc, alpha, beta;
 #pragma unroll
@@ -546,6 +554,58 @@ __global__ __launch_bounds__(256) void crt_recombine_kernel(GemmArgs g, const in
     for (int p = 0; p < P; ++p) g.C[p * g.sc + off] = t.c[p];
 }
 
+// Thread (i4, j) handles rows 4 i4 .. 4 i4 + 3 of column j: one 32-bit load
+// per modulus brings their four residues.  S = sum_t y_t (M / m_t) limb by
+// limb (each limb sum < 2^46, exact in binary64) and f = sum_t y_t / m_t,
+// whose nearest integer q gives C' = S - q M.
+template <int P, int K>
+__global__ __launch_bounds__(256) void crt_recombine_kernel(GemmArgs g, const int32_t* __restrict__ E,
+                                                            const int32_t* __restrict__ F,
+                                                            const uint8_t* __restrict__ Y, int N,
+                                                            int s, int64_t Mp, int64_t Np) {
+    const int64_t quads = Mp / 4;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= quads * g.n) return;
+    const int64_t i0 = 4 * (idx % quads), j = idx / quads;
+    if (i0 >= g.m) return;
+    const int64_t plane = Mp * Np;
+    const uint32_t* yp = (const uint32_t*)(Y + j * Mp + i0);
+    const int row0 = N * (N - 1) / 2;
+
+    double L[4][K], f[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        f[r] = 0.0;
+#pragma unroll
+        for (int l = 0; l < K; ++l) L[r][l] = 0.0;
+    }
+    // moduli in groups of eight: their loads are in flight together
+    for (int t0 = 0; t0 < N; t0 += 8) {
+        uint32_t y4[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) y4[u] = (t0 + u < N) ? yp[(t0 + u) * (plane / 4)] : 0u;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int t = t0 + u;
+            if (t >= N) break;
+            const double inv = kCrtDev.inv[t];
+            const double* w = kCrtDev.Wd[row0 + t];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const double y = (double)((y4[u] >> (8 * r)) & 255u);
+                f[r] = fma(y, inv, f[r]);
+#pragma unroll
+                for (int l = 0; l < K; ++l) L[r][l] = fma(y, w[l], L[r][l]);
+            }
+        }
+    }
+    const int32_t ef = F[j] - 14 * s;
+    static_for<4>([&](auto rc) __attribute__((always_inline)) {
+        constexpr int r = decltype(rc)::value;
+        if (i0 + r < g.m) crt_finish_entry<P, K>(g, L[r], f[r], N, E[i0 + r] + ef, i0 + r, j);
+    });
+}
+
 // ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
@@ -558,8 +618,8 @@ int inverse_mod(int a, int m) {          // a^-1 mod m for gcd(a, m) = 1, m <= 2
 
 int8_t sym_byte(int v, int m) { return (int8_t)(v >= 128 ? v - m : v); }   // v in [0, m)
 
-// Digit-pair weights 16384^e mod m_t (times u_t when `scaled`).
-CrtWeights crt_weights(int N, int npairs, bool scaled) {
+// Digit weights 128^(s - 1 - p) mod m_t (times u_t when `scaled`).
+CrtWeights crt_weights(int N, int s, bool scaled) {
     CrtWeights W{};
     for (int t = 0; t < N; ++t) {
         const int m = kModuli[t];
@@ -570,10 +630,10 @@ CrtWeights crt_weights(int N, int npairs, bool scaled) {
                 if (j != t) cof = cof * (kModuli[j] % m) % m;
             u = inverse_mod(cof, m);
         }
-        int pw = u % m;
-        for (int e = 0; e < npairs; ++e) {
-            W.w[e][t] = sym_byte(pw, m);
-            pw = pw * (16384 % m) % m;
+        int pw = u % m;                                 // weight of the last digit
+        for (int p = s - 1; p >= 0; --p) {
+            W.w[t][p] = sym_byte(pw, m);
+            pw = pw * (128 % m) % m;
         }
     }
     return W;
@@ -586,34 +646,23 @@ int limbs_for(int N) {
     return top <= 4 ? 4 : top <= 6 ? 6 : top <= 8 ? 8 : 11;
 }
 
-int residue_bucket(int N) { return N <= 16 ? 16 : N <= 24 ? 24 : N <= 32 ? 32 : N <= 40 ? 40 : 49; }
-
-template <int P>
-int launch_residues_p(int NB, dim3 grid, hipStream_t st, const double* X, int64_t rs, int64_t ls,
-                      int64_t ps, int64_t count, int64_t k, const int32_t* E, int s, int N,
-                      const CrtWeights& w, int8_t* R, int64_t Rp, int64_t Kp) {
-#define MPG_RES(NBV)                                                                                  \
-    hipLaunchKernelGGL((crt_residue_kernel<P, NBV>), grid, dim3(256), 0, st, X, rs, ls, ps, count, k, E, \
-                       s, N, w, R, Rp, Kp)
-    switch (NB) {
-    case 16: MPG_RES(16); break;
-    case 24: MPG_RES(24); break;
-    case 32: MPG_RES(32); break;
-    case 40: MPG_RES(40); break;
-    default: MPG_RES(49); break;
-    }
-#undef MPG_RES
-    return (int)hipGetLastError();
-}
-
 int launch_residues(int P, const double* X, int64_t rs, int64_t ls, int64_t ps, int64_t count,
                     int64_t k, const int32_t* E, int s, int N, const CrtWeights& w, int8_t* R,
                     int64_t Rp, int64_t Kp, hipStream_t st) {
     const dim3 grid((unsigned)(Kp / kTileK), (unsigned)(Rp / kResRows));
-    const int NB = residue_bucket(N);
-    if (P == 2) return launch_residues_p<2>(NB, grid, st, X, rs, ls, ps, count, k, E, s, N, w, R, Rp, Kp);
-    if (P == 3) return launch_residues_p<3>(NB, grid, st, X, rs, ls, ps, count, k, E, s, N, w, R, Rp, Kp);
-    return launch_residues_p<4>(NB, grid, st, X, rs, ls, ps, count, k, E, s, N, w, R, Rp, Kp);
+#define MPG_RES(PV, NGV)                                                                               \
+    hipLaunchKernelGGL((crt_residue_kernel<PV, NGV>), grid, dim3(256), 0, st, X, rs, ls, ps, count, k, E, \
+                       s, N, w, R, Rp, Kp)
+    const bool two = N > 32;
+    if (P == 2) {
+        if (two) MPG_RES(2, 2); else MPG_RES(2, 1);
+    } else if (P == 3) {
+        if (two) MPG_RES(3, 2); else MPG_RES(3, 1);
+    } else {
+        if (two) MPG_RES(4, 2); else MPG_RES(4, 1);
+    }
+#undef MPG_RES
+    return (int)hipGetLastError();
 }
 
 int launch_crt_mfma(int cfg, const int8_t* RA, const int8_t* RB, uint8_t* Y, int64_t Mp, int64_t Np,
@@ -621,12 +670,16 @@ int launch_crt_mfma(int cfg, const int8_t* RA, const int8_t* RB, uint8_t* Y, int
     const CrtConfig c = kCrt[cfg];
     const int64_t grid = xcd_grid((Mp / c.bm) * (Np / c.bn));
     if (grid > 0x7fffffffLL) return (int)hipErrorInvalidConfiguration;
+    // ring depths: at most 64 KiB of LDS per workgroup
     if (cfg == 0)
-        hipLaunchKernelGGL((crt_mfma_kernel<128, 128, 4>), dim3((unsigned)grid), dim3(256), 0, st, RA, RB,
-                           Y, Mp, Np, Kp, N);
+        hipLaunchKernelGGL((crt_mfma_kernel<256, 256, 2, 4, 4>), dim3((unsigned)grid), dim3(512), 0, st, RA,
+                           RB, Y, Mp, Np, Kp, N);
+    else if (cfg == 1)
+        hipLaunchKernelGGL((crt_mfma_kernel<256, 128, 2, 2, 5>), dim3((unsigned)grid), dim3(256), 0, st, RA,
+                           RB, Y, Mp, Np, Kp, N);
     else
-        hipLaunchKernelGGL((crt_mfma_kernel<64, 64, 8>), dim3((unsigned)grid), dim3(256), 0, st, RA, RB, Y,
-                           Mp, Np, Kp, N);
+        hipLaunchKernelGGL((crt_mfma_kernel<128, 128, 2, 2, 8>), dim3((unsigned)grid), dim3(256), 0, st, RA,
+                           RB, Y, Mp, Np, Kp, N);
     return (int)hipGetLastError();
 }
 
@@ -647,8 +700,27 @@ int launch_crt_recombine_p(int K, dim3 grid, hipStream_t st, const GemmArgs& g, 
 
 }  // namespace
 
+int crt_default_config(int64_t m, int64_t n) {
+    // rounds of resident workgroups times one workgroup's tile time, with
+    // the measured relative throughput of each tile shape per CU
+    const double eff[kCrtConfigs] = {1.0, 0.9, 0.6};
+    int best = 0;
+    double best_cost = 0.0;
+    for (int c = 0; c < kCrtConfigs; ++c) {
+        const int64_t tiles = ((m + kCrt[c].bm - 1) / kCrt[c].bm) * ((n + kCrt[c].bn - 1) / kCrt[c].bn);
+        const int64_t slots = 256 * kCrt[c].per_cu;
+        const double rounds = (double)((tiles + slots - 1) / slots);
+        const double cost = rounds * kCrt[c].bm * kCrt[c].bn * kCrt[c].per_cu / eff[c];
+        if (c == 0 || cost < best_cost) {
+            best = c;
+            best_cost = cost;
+        }
+    }
+    return best;
+}
+
 int crt_moduli_count(int64_t k, int s) {
-    if (k <= 0 || k > 131071 || s < 1 || (s + 1) / 2 > kMaxPairs) return 0;
+    if (k <= 0 || k > 131071 || s < 1 || s > kMaxCrtDigits) return 0;
     // log2 of max|C'| = k (64 (128^s - 1) / 127)^2, then one bit for the sign
     // and a margin far above the rounding of these logarithms
     const double amax = 6.0 + 7.0 * s + std::log1p(-std::ldexp(1.0, -7 * s)) / std::log(2.0) -
@@ -683,17 +755,16 @@ int launch_crt(int P, int s, int cfg, const GemmArgs& g, void* ws, hipStream_t s
     uint8_t* Y = (uint8_t*)(base + L.oY);
     const int64_t a_rs = g.ta ? g.lda : 1, a_ls = g.ta ? 1 : g.lda;
     const int64_t b_rs = g.tb ? 1 : g.ldb, b_ls = g.tb ? g.ldb : 1;
-    const int start = (s & 1) ? 0 : 1;
-    const int npairs = (s + 1 - start) / 2;
-    const CrtWeights wa = crt_weights(N, npairs, true);
-    const CrtWeights wb = crt_weights(N, npairs, false);
+    const CrtWeights wa = crt_weights(N, s, true);
+    const CrtWeights wb = crt_weights(N, s, false);
     int rc;
-    if ((rc = launch_row_exponents(g.A, a_rs, a_ls, g.m, L.Mp, g.k, E, st))) return rc;
-    if ((rc = launch_row_exponents(g.B, b_rs, b_ls, g.n, L.Np, g.k, F, st))) return rc;
+    uint64_t* MX = (uint64_t*)(base + L.oMX);
+    if ((rc = launch_row_exponents(g.A, a_rs, a_ls, g.m, L.Mp, g.k, E, MX, st))) return rc;
+    if ((rc = launch_row_exponents(g.B, b_rs, b_ls, g.n, L.Np, g.k, F, MX + L.Mp, st))) return rc;
     if ((rc = launch_residues(P, g.A, a_rs, a_ls, g.sa, g.m, g.k, E, s, N, wa, RA, L.Mp, L.Kp, st))) return rc;
     if ((rc = launch_residues(P, g.B, b_rs, b_ls, g.sb, g.n, g.k, F, s, N, wb, RB, L.Np, L.Kp, st))) return rc;
     if ((rc = launch_crt_mfma(cfg, RA, RB, Y, L.Mp, L.Np, L.Kp, N, st))) return rc;
-    const int64_t blocks = (g.m * g.n + 255) / 256;
+    const int64_t blocks = (L.Mp / 4 * g.n + 255) / 256;
     if (blocks > 0x7fffffffLL) return (int)hipErrorInvalidConfiguration;
     const dim3 grid((unsigned)blocks);
     const int K = limbs_for(N);

@@ -76,12 +76,15 @@ int split_layout(int P, int64_t m, int64_t n, int64_t k, int s, int cfg, size_t*
                  size_t* offDA, size_t* offDB, size_t* offS, int64_t* Mp, int64_t* Np, int64_t* Kp);
 
 // Scale exponents of the split forms (stage 1 above): row r of a matrix whose
-// element (r, l) sits at X[r rs + l ls]; E[r] = 0 for count <= r < padded.
+// element (r, l) sits at X[r rs + l ls]; E[r] = 0 for count <= r < padded;
+// mx: scratch of `count` 64-bit words (device).
 int launch_row_exponents(const double* X, int64_t rs, int64_t ls, int64_t count, int64_t padded,
-                         int64_t k, int32_t* E, hipStream_t st);
+                         int64_t k, int32_t* E, uint64_t* mx, hipStream_t st);
 
 // Residue (CRT) form of the split product (crt_gemm.hip).
-constexpr int kCrtConfigs = 2;
+constexpr int kCrtConfigs = 3;
+// configuration the library picks for an m x n output when none is tuned
+int crt_default_config(int64_t m, int64_t n);
 // number of moduli for k and s digits, 0 when the product does not fit
 int crt_moduli_count(int64_t k, int s);
 size_t crt_workspace_bytes(int P, int64_t m, int64_t n, int64_t k, int s, int cfg);

@@ -55,6 +55,7 @@ int split_layout(int P, int64_t m, int64_t n, int64_t k, int s, int cfg, size_t*
     size_t off = 0;
     *offE = off;  off = align256(off + sizeof(int32_t) * Mp);
     *offF = off;  off = align256(off + sizeof(int32_t) * Np);
+    off = align256(off + sizeof(uint64_t) * (Mp + Np));      // row maxima (stage 1)
     *offDA = off; off = align256(off + (size_t)s * Mp * Kp);
     *offDB = off; off = align256(off + (size_t)s * Np * Kp);
     *offS = off;  off = align256(off + sizeof(int32_t) * (size_t)s * Np * Mp);
@@ -84,23 +85,45 @@ __device__ __forceinline__ int32_t scale_exponent(double M) {
     return e + 1;
 }
 
-// Lanes along rows (coalesced when rows are contiguous, rs == 1).
+// Rows contiguous (rs == 1): lanes along rows, so every load is coalesced;
+// k is cut into chunks of kExpChunk so that the grid fills the chip, and the
+// chunk maxima meet in a per-row atomic maximum of the bit patterns (for
+// non-negative binary64 values their order as unsigned integers), which does
+// not depend on the order of the updates.
+constexpr int kExpChunk = 256;
+
+__global__ __launch_bounds__(256) void exponent_clear_kernel(unsigned long long* __restrict__ mx,
+                                                             int64_t count) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < count) mx[r] = 0ull;
+}
+
 __global__ __launch_bounds__(256) void exponent_rows_kernel(const double* __restrict__ X,
-                                                            int64_t rs, int64_t ls, int64_t count,
-                                                            int64_t padded, int64_t k,
-                                                            int32_t* __restrict__ E) {
+                                                            int64_t ls, int64_t count, int64_t k,
+                                                            unsigned long long* __restrict__ mx) {
     __shared__ double red[4][64];
     const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
     const int64_t r = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t l0 = (int64_t)blockIdx.y * kExpChunk;
+    const int64_t l1 = (l0 + kExpChunk < k) ? l0 + kExpChunk : k;
     double M = 0.0;
-    if (r < count)
-        for (int64_t l = grp; l < k; l += 4) M = fmax(M, fabs(X[r * rs + l * ls]));
+    if (r < count) {
+#pragma unroll 8
+        for (int64_t l = l0 + grp; l < l1; l += 4) M = fmax(M, fabs(X[r + l * ls]));
+    }
     red[grp][lane] = M;
     __syncthreads();
-    if (grp == 0 && r < padded) {
+    if (grp == 0 && r < count) {
         M = fmax(fmax(red[0][lane], red[1][lane]), fmax(red[2][lane], red[3][lane]));
-        E[r] = (r < count) ? scale_exponent(M) : 0;
+        if (M != 0.0) atomicMax(mx + r, (unsigned long long)__double_as_longlong(M));
     }
+}
+
+__global__ __launch_bounds__(256) void exponent_finish_kernel(const unsigned long long* __restrict__ mx,
+                                                              int64_t count, int64_t padded,
+                                                              int32_t* __restrict__ E) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < padded) E[r] = (r < count) ? scale_exponent(__longlong_as_double((long long)mx[r])) : 0;
 }
 
 // One wave per row, lanes along l (coalesced when l is contiguous, ls == 1).
@@ -475,11 +498,19 @@ __global__ __launch_bounds__(256) void recombine_kernel(GemmArgs g, const int32_
 // ---------------------------------------------------------------------------
 
 static int launch_exponents(const double* X, int64_t rs, int64_t ls, int64_t count, int64_t padded,
-                            int64_t k, int32_t* E, hipStream_t st) {
+                            int64_t k, int32_t* E, uint64_t* mx, hipStream_t st) {
     if (rs == 1) {
-        const int64_t blocks = (padded + 63) / 64;
-        hipLaunchKernelGGL(exponent_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, st, X, rs, ls,
-                           count, padded, k, E);
+        const int64_t cb = (count + 255) / 256, pb = (padded + 255) / 256;
+        const int64_t chunks = (k + kExpChunk - 1) / kExpChunk;
+        if (chunks > 65535) return (int)hipErrorInvalidConfiguration;
+        unsigned long long* m = (unsigned long long*)mx;
+        if (cb > 0) {
+            hipLaunchKernelGGL(exponent_clear_kernel, dim3((unsigned)cb), dim3(256), 0, st, m, count);
+            if (chunks > 0)
+                hipLaunchKernelGGL(exponent_rows_kernel, dim3((unsigned)((count + 63) / 64), (unsigned)chunks),
+                                   dim3(256), 0, st, X, ls, count, k, m);
+        }
+        hipLaunchKernelGGL(exponent_finish_kernel, dim3((unsigned)pb), dim3(256), 0, st, m, count, padded, E);
     } else {
         const int64_t blocks = (padded + 3) / 4;
         hipLaunchKernelGGL(exponent_rows_wave_kernel, dim3((unsigned)blocks), dim3(256), 0, st, X, rs,
@@ -489,8 +520,8 @@ static int launch_exponents(const double* X, int64_t rs, int64_t ls, int64_t cou
 }
 
 int launch_row_exponents(const double* X, int64_t rs, int64_t ls, int64_t count, int64_t padded,
-                         int64_t k, int32_t* E, hipStream_t st) {
-    return launch_exponents(X, rs, ls, count, padded, k, E, st);
+                         int64_t k, int32_t* E, uint64_t* mx, hipStream_t st) {
+    return launch_exponents(X, rs, ls, count, padded, k, E, mx, st);
 }
 
 static int launch_slices(int P, const double* X, int64_t rs, int64_t ls, int64_t ps, int64_t count,
@@ -551,13 +582,14 @@ int launch_split_stages(int P, int s, int cfg, int last, const GemmArgs& g, void
     int8_t* DA = (int8_t*)(base + oA);
     int8_t* DB = (int8_t*)(base + oB);
     int32_t* S = (int32_t*)(base + oS);
+    uint64_t* MX = (uint64_t*)(base + align256(oF + sizeof(int32_t) * Np));   // Mp + Np row maxima
     // rows of op(A): element (i, l) at A[i*rs + l*ls]
     const int64_t a_rs = g.ta ? g.lda : 1, a_ls = g.ta ? 1 : g.lda;
     // columns of op(B): element (j, l) = op(B)(l, j)
     const int64_t b_rs = g.tb ? 1 : g.ldb, b_ls = g.tb ? g.ldb : 1;
     int rc;
-    if ((rc = launch_exponents(g.A, a_rs, a_ls, g.m, Mp, g.k, E, st))) return rc;
-    if ((rc = launch_exponents(g.B, b_rs, b_ls, g.n, Np, g.k, F, st))) return rc;
+    if ((rc = launch_exponents(g.A, a_rs, a_ls, g.m, Mp, g.k, E, MX, st))) return rc;
+    if ((rc = launch_exponents(g.B, b_rs, b_ls, g.n, Np, g.k, F, MX + Mp, st))) return rc;
     if (last <= 1) return 0;
     if ((rc = launch_slices(P, g.A, a_rs, a_ls, g.sa, g.m, g.k, E, s, DA, Mp, Kp, st))) return rc;
     if ((rc = launch_slices(P, g.B, b_rs, b_ls, g.sb, g.n, g.k, F, s, DB, Np, Kp, st))) return rc;

@@ -124,11 +124,14 @@ def test_crt_form_host_rules():
                         4, 20, None, C.byref(o))
     assert rc == _lib.ERR_UNSUPPORTED
     # workspace: exponents, N residue planes per operand, N result bytes per entry
-    b16 = L.mpgemm_workspace_bytes(2, 5, 100, 100, 4096, 16, 1)      # DD: 32 moduli
+    b16 = L.mpgemm_workspace_bytes(2, 5, 100, 100, 4096, 16, 2)      # DD: 32 moduli, 128 x 128 tiles
     assert b16 >= 32 * (128 * 4096 * 2 + 128 * 128)
-    b23 = L.mpgemm_workspace_bytes(3, 5, 100, 100, 4096, 0, 1)       # TD default s = 23: 48 moduli
+    b23 = L.mpgemm_workspace_bytes(3, 5, 100, 100, 4096, 0, 2)       # TD default s = 23: 48 moduli
     assert b23 >= 48 * (128 * 4096 * 2 + 128 * 128) > b16
-    assert mp.num_configs(2, "crt") == 2
+    assert mp.num_configs(2, "crt") == 3
+    assert (mp.crt_moduli(2, 4096), mp.crt_moduli(3, 4096), mp.crt_moduli(3, 65536)) == (32, 48, 49)
+    assert mp.crt_moduli(4, 100) == 0 and mp.crt_moduli(4, 129, 20) == 40 and mp.crt_moduli(2, 131072) == 0
+    assert L.mpgemm_crt_moduli(7, 10, 0) == -1
 
 
 def test_vec_validation():

@@ -128,7 +128,7 @@ CrtLayout crt_layout(int64_t m, int64_t n, int64_t k, int N, int cfg) {
     CrtLayout L;
     L.Mp = round_up(m > 0 ? m : 1, c.bm);
     L.Np = round_up(n > 0 ? n : 1, c.bn);
-    L.Kp = round_up(k > 0 ? k : 1, kTileK);
+    L.Kp = round_up(k > 0 ? k : 1, 2 * kTileK);    // an even number of 64-byte steps per modulus
     size_t off = 0;
     L.oE = off;  off = align256(off + sizeof(int32_t) * L.Mp);
     L.oF = off;  off = align256(off + sizeof(int32_t) * L.Np);
@@ -150,9 +150,9 @@ CrtLayout crt_layout(int64_t m, int64_t n, int64_t k, int N, int cfg) {
 // congruent to 128^(s-p) (times u_t for op(A)) modulo m_t in [-128, 127], are
 // the product of the 64 x 32 digit block with the 32 x 32 weight block of
 // each group of 32 moduli: two INT8 MFMAs per group (|a_t| <= 24 64 128 <
-// 2^18, exact).  Each a_t is reduced to a residue in [-128, 127] in single
-// precision (exact: |a_t| < 2^24 and the quotient is the nearest integer or
-// off by one only next to a half-integer, so |a_t - q m_t| <= m_t / 2 + 1/8).
+// 2^18, exact).  Each a_t is reduced to a residue of magnitude <= m_t / 2
+// in single precision (exact: |a_t| < 2^24, and the rounded quotient errs by
+// far less than 1/2), stored as its low byte.
 // Residue plane t is cut into 32-byte k-tiles:
 // byte (r, l) at R[((t (Kp/32) + l/32) Rp + r) 32 + l % 32].
 // ---------------------------------------------------------------------------
@@ -217,25 +217,33 @@ __global__ __launch_bounds__(256) void crt_residue_kernel(const double* __restri
         invm[cg] = 1.0f / (float)m;
     }
     const int64_t nkt = Kp / kCrtTileK;
-#pragma unroll 1
+    // the digits of the wave's four rows first, their chains interleaved
+    double rem[4][P];
+    uint32_t dg[4][8];
+#pragma unroll
     for (int rw = 0; rw < 4; ++rw) {
-        const int rr = wave * 4 + rw;
-        const int64_t gr = r0 + rr;
+        const int64_t gr = r0 + wave * 4 + rw;
         const int32_t Ei = (gr < count) ? E[gr] : 0;
-        double rem[P];
 #pragma unroll
-        for (int p = 0; p < P; ++p) rem[p] = ldexp(tile[p][rr][lane], -Ei);
-        uint32_t dg[8];
+        for (int p = 0; p < P; ++p) rem[rw][p] = ldexp(tile[p][wave * 4 + rw][lane], -Ei);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) dg[i] = 0u;
+        for (int i = 0; i < 8; ++i) dg[rw][i] = 0u;
+    }
 #pragma unroll
-        for (int p = 1; p <= kMaxCrtDigits; ++p)
-            if (p <= s) dg[(p - 1) / 4] |= ((uint32_t)next_digit<P>(rem, p) & 255u) << (8 * ((p - 1) % 4));
+    for (int p = 1; p <= kMaxCrtDigits; ++p)
+        if (p <= s) {
+#pragma unroll
+            for (int rw = 0; rw < 4; ++rw)
+                dg[rw][(p - 1) / 4] |= ((uint32_t)next_digit<P>(rem[rw], p) & 255u) << (8 * ((p - 1) % 4));
+        }
+#pragma unroll
+    for (int rw = 0; rw < 4; ++rw) {
+        const int64_t gr = r0 + wave * 4 + rw;
         // A fragments: lane L < 32 gives digits 0..15 of entry L (first MFMA)
         // or of entry L + 32 (second), lane L >= 32 digits 16..31 of entry
         // L - 32 (first) or L (second); the halves trade through a lane swap
-        const v4i lo = {(int)dg[0], (int)dg[1], (int)dg[2], (int)dg[3]};
-        const v4i hi = {(int)dg[4], (int)dg[5], (int)dg[6], (int)dg[7]};
+        const v4i lo = {(int)dg[rw][0], (int)dg[rw][1], (int)dg[rw][2], (int)dg[rw][3]};
+        const v4i hi = {(int)dg[rw][4], (int)dg[rw][5], (int)dg[rw][6], (int)dg[rw][7]};
         const bool low = lane < 32;
         const v4i x = low ? hi : lo;
         v4i xs;
@@ -257,9 +265,10 @@ __global__ __launch_bounds__(256) void crt_residue_kernel(const double* __restri
                     uint32_t word = 0;
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
+                        // |r| <= m / 2: a byte for m < 256; for m = 256 the
+                        // low byte of r is congruent all the same
                         const float a = (float)acc[eg][4 * v4 + q];
-                        float r = fmaf(-rintf(a * invm[cg]), mf[cg], a);
-                        r = r >= 127.5f ? r - mf[cg] : r;
+                        const float r = fmaf(-rintf(a * invm[cg]), mf[cg], a);
                         word |= ((uint32_t)(int)r & 255u) << (8 * q);
                     }
                     // entries 32 eg + 8 v4 + 4 (lane / 32) + 0..3 of this row
@@ -280,7 +289,7 @@ __global__ __launch_bounds__(256) void crt_residue_kernel(const double* __restri
 // staged D steps deep through LDS by 16-byte direct-to-LDS copies: a wave
 // waits for its own copies of the step it computes (vector-memory counter)
 // and then meets the others at a barrier, so no register holds data in
-// flight.  The 16-byte half c of tile row r sits at LDS half c ^ ((r / 4) % 2)
+// flight.  The 16-byte half c of tile row r sits at LDS half c ^ ((r / 8) % 2)
 // of that row, so that the fragment reads (32 rows, one half each) hit
 // distinct banks.  After the last k-tile of a modulus the int32 sums are
 // reduced to y = sum mod m_t in [0, m_t) (exactly, in binary64), four
@@ -302,11 +311,14 @@ struct CrtDma {
     static_assert(A_BYTES % ROUND == 0 && B_BYTES % ROUND == 0, "tiles split into whole copy rounds");
     static_assert(WM % 32 == 0 && WN % 32 == 0, "wave block of 32 x 32 MFMA tiles");
     static_assert(PER_STEP * (D - 2) <= 63, "vector-memory counter range");
-    static_assert(LDS_BYTES <= 65536, "64 KiB LDS window per workgroup");
+    static_assert(LDS_BYTES <= 163840, "160 KiB of LDS per CU");
 };
 
-// LDS offset of 16-byte half c of row r in a 32-byte-row tile
-__device__ __forceinline__ int swz32(int r, int c) { return r * kCrtTileK + ((c ^ ((r >> 2) & 1)) << 4); }
+// LDS offset of 16-byte half c of row r in a 32-byte-row tile.  A 128-bit
+// LDS read is served 16 lanes at a time from 64 four-byte banks; lanes read
+// 16 consecutive rows, so the four-bank group 2 r + position must differ
+// across them: the halves swap every 8 rows.
+__device__ __forceinline__ int swz32(int r, int c) { return r * kCrtTileK + ((c ^ ((r >> 3) & 1)) << 4); }
 
 template <int BM, int BN, int WGM, int WGN, int D>
 __global__ __launch_bounds__(64 * WGM * WGN, 2) void crt_mfma_kernel(const int8_t* __restrict__ RA,
@@ -329,14 +341,14 @@ __global__ __launch_bounds__(64 * WGM * WGN, 2) void crt_mfma_kernel(const int8_
 
     // this lane's global byte offset within a tile for its h-th copy round:
     // LDS half u = t + NT h is row u / 2, position u % 2, which holds global
-    // half (u % 2) ^ ((row / 4) % 2)
+    // half (u % 2) ^ ((row / 8) % 2)
     constexpr int NL = T::A_LOADS > T::B_LOADS ? T::A_LOADS : T::B_LOADS;
     int gofs[NL];
 #pragma unroll
     for (int h = 0; h < NL; ++h) {
         const int u = t + T::NT * h;
         const int r = u >> 1;
-        gofs[h] = r * kCrtTileK + (((u & 1) ^ ((r >> 2) & 1)) << 4);
+        gofs[h] = r * kCrtTileK + (((u & 1) ^ ((r >> 3) & 1)) << 4);
     }
     int aofs[T::FM], bofs[T::FN];
 #pragma unroll
@@ -421,6 +433,169 @@ __global__ __launch_bounds__(64 * WGM * WGN, 2) void crt_mfma_kernel(const int8_
         wait_vm_all();
         kt = 0;
         ++mod;
+    }
+    // the copies run ahead of the last step: let them land before the
+    // workgroup's LDS is released
+    wait_vm_all();
+}
+
+// Wide variant: a 256 x 256 tile, four waves in 2 x 2 with 128 x 128 each
+// (sixteen 32 x 32 accumulators, one wave per SIMD), which halves the LDS
+// bytes read per MAC against 128 x 64 wave blocks.  With one wave per SIMD
+// nothing else hides the LDS latency, so the fragments of step u + 1 are
+// read while the MFMAs of step u run (two register buffers, the loop
+// unrolled by two), and the ring is read one step ahead: at the top of step
+// u the copies of step u + 1 must have landed and every wave must be done
+// reading step u's slot, which step u + D then refills.
+
+// KH 32-byte k-tiles per step (32 KH MFMAs per wave between barriers); the
+// ring holds D steps.
+template <int KH>
+struct WideCfg {
+    static constexpr int NT = 256, BM = 256, BN = 256, WM = 128, WN = 128, FM = 4, FN = 4;
+    static constexpr int SUB = BM * kCrtTileK;            // one operand's k-tile: 8 KiB
+    static constexpr int B_OFF = KH * SUB;
+    static constexpr int STAGE = 2 * KH * SUB;
+    static constexpr int ROUND = NT * 16;
+    static constexpr int LOADS = SUB / ROUND;             // copy rounds per operand k-tile
+    static constexpr int PER_STEP = 2 * KH * LOADS;
+    static constexpr int D = KH == 1 ? 8 : 4;
+    static constexpr int LDS_BYTES = D * STAGE;
+    static_assert(SUB % ROUND == 0, "whole copy rounds");
+    static_assert(PER_STEP * (D - 1) <= 63, "vector-memory counter range");
+    static_assert(LDS_BYTES <= 163840, "160 KiB of LDS per CU");
+};
+
+__device__ __forceinline__ uint32_t reduce_word(const v16i& x, int v4, int mt, double md, double inv) {
+    uint32_t word = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        // |x| < 2^31: the rounded quotient is off by at most one
+        const double xd = (double)x[4 * v4 + q];
+        int y = (int)fma(-rint(xd * inv), md, xd);
+        y += (y < 0) ? mt : 0;
+        word |= (uint32_t)y << (8 * q);
+    }
+    return word;
+}
+
+template <int KH>
+__global__ __launch_bounds__(256, 1) void crt_mfma_wide_kernel(const int8_t* __restrict__ RA,
+                                                               const int8_t* __restrict__ RB,
+                                                               uint8_t* __restrict__ Y, int64_t Mp,
+                                                               int64_t Np, int64_t Kp, int N) {
+    using W = WideCfg<KH>;
+    constexpr int D = W::D;
+    __shared__ __attribute__((aligned(1024))) int8_t lds[W::LDS_BYTES];
+
+    int64_t tm, tn;
+    if (!xcd_tile_coords<8>(blockIdx.x, Mp / 256, Np / 256, tm, tn)) return;
+    const int64_t m0 = tm * 256, n0 = tn * 256;
+    const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
+    const int wm = wave % 2, wn = wave / 2;
+    const int wave_lds = __builtin_amdgcn_readfirstlane(wave) * 1024;
+    const int spm = (int)(Kp / kCrtTileK) / KH;   // steps per modulus, even (Kp % (64 KH) == 0)
+    const int steps = N * spm;
+    const int64_t tileA = Mp * kCrtTileK, tileB = Np * kCrtTileK;
+
+    int gofs[W::LOADS];
+#pragma unroll
+    for (int h = 0; h < W::LOADS; ++h) {
+        const int u = t + W::NT * h;
+        const int r = u >> 1;
+        gofs[h] = r * kCrtTileK + (((u & 1) ^ ((r >> 3) & 1)) << 4);
+    }
+    int aofs[W::FM], bofs[W::FN];
+#pragma unroll
+    for (int i = 0; i < W::FM; ++i) aofs[i] = swz32(wm * W::WM + i * 32 + (lane & 31), lane >> 5);
+#pragma unroll
+    for (int jj = 0; jj < W::FN; ++jj) bofs[jj] = W::B_OFF + swz32(wn * W::WN + jj * 32 + (lane & 31), lane >> 5);
+
+    const int8_t* fa = RA + m0 * kCrtTileK;
+    const int8_t* fb = RB + n0 * kCrtTileK;
+    int fstep = 0, fslot = 0;
+    auto issue = [&]() __attribute__((always_inline)) {
+        int8_t* la = lds + fslot * W::STAGE + wave_lds;
+#pragma unroll
+        for (int kh = 0; kh < KH; ++kh)
+#pragma unroll
+            for (int h = 0; h < W::LOADS; ++h) {
+                copy16_to_lds(fa + kh * tileA + gofs[h], la + kh * W::SUB + W::ROUND * h);
+                copy16_to_lds(fb + kh * tileB + gofs[h], la + W::B_OFF + kh * W::SUB + W::ROUND * h);
+            }
+        if (++fstep < steps) {
+            fa += KH * tileA;
+            fb += KH * tileB;
+        }
+        fslot = (fslot + 1 == D) ? 0 : fslot + 1;
+    };
+
+    v16i acc[W::FM][W::FN];
+#pragma unroll
+    for (int i = 0; i < W::FM; ++i)
+#pragma unroll
+        for (int jj = 0; jj < W::FN; ++jj) acc[i][jj] = v16i{0};
+    v4i fra[2][KH][W::FM], frb[2][KH][W::FN];
+    auto load_frags = [&](auto bufc, int slot) __attribute__((always_inline)) {
+        constexpr int b = decltype(bufc)::value;
+        const int8_t* st = lds + slot * W::STAGE;
+#pragma unroll
+        for (int kh = 0; kh < KH; ++kh) {
+#pragma unroll
+            for (int i = 0; i < W::FM; ++i) fra[b][kh][i] = *(const v4i*)(st + kh * W::SUB + aofs[i]);
+#pragma unroll
+            for (int jj = 0; jj < W::FN; ++jj) frb[b][kh][jj] = *(const v4i*)(st + kh * W::SUB + bofs[jj]);
+        }
+    };
+
+    // prologue: steps 0 .. D-1 in flight, step 0 landed, its fragments read
+    for (int r = 0; r < D; ++r) issue();
+    wait_vm_barrier<W::PER_STEP * (D - 1)>();
+    load_frags(std::integral_constant<int, 0>{}, 0);
+
+    auto step = [&](auto curc, int u) __attribute__((always_inline)) {
+        constexpr int cur = decltype(curc)::value, nxt = 1 - cur;
+        // keep each step's MFMAs after its barrier: hoisted above it they
+        // would wait on the fragment reads just issued for them
+        __builtin_amdgcn_sched_barrier(0);
+        wait_vm_barrier<W::PER_STEP * (D - 2)>();
+        issue();                                   // step u + D into step u's slot
+        load_frags(std::integral_constant<int, nxt>{}, (u + 1) % D);
+#pragma unroll
+        for (int kh = 0; kh < KH; ++kh)
+#pragma unroll
+            for (int i = 0; i < W::FM; ++i)
+#pragma unroll
+                for (int jj = 0; jj < W::FN; ++jj)
+                    acc[i][jj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fra[cur][kh][i], frb[cur][kh][jj],
+                                                                       acc[i][jj], 0, 0, 0);
+    };
+    const int64_t ybase = (n0 + wn * W::WN + (lane & 31)) * Mp + m0 + wm * W::WM + 4 * (lane >> 5);
+    int u = 0;
+    for (int mod = 0; mod < N; ++mod) {
+        for (int kk = 0; kk < spm; kk += 2, u += 2) {
+            step(std::integral_constant<int, 0>{}, u);
+            step(std::integral_constant<int, 1>{}, u + 1);
+        }
+        const int mt = kCrtDev.mod[mod];
+        const double md = (double)mt, inv = kCrtDev.inv[mod];
+        // this lane's first byte in plane `mod`; the tiles are uniform offsets from it
+        uint8_t* Yl = Y + (int64_t)mod * Np * Mp + ybase;
+#pragma unroll
+        for (int i = 0; i < W::FM; ++i)
+#pragma unroll
+            for (int jj = 0; jj < W::FN; ++jj) {
+                const int64_t tofs = (int64_t)(jj * 32) * Mp + i * 32;
+#pragma unroll
+                for (int v4 = 0; v4 < 4; ++v4)
+                    *(uint32_t*)(Yl + tofs + 8 * v4) = reduce_word(acc[i][jj], v4, mt, md, inv);
+                acc[i][jj] = v16i{0};
+                __builtin_amdgcn_sched_barrier(0);      // one accumulator's temporaries at a time
+            }
+        // the stores share the vector-memory counter with the copies: drain
+        // it so the counts in the waits stay exact
+        wait_vm_all();
     }
     // the copies run ahead of the last step: let them land before the
     // workgroup's LDS is released
@@ -670,12 +845,13 @@ int launch_crt_mfma(int cfg, const int8_t* RA, const int8_t* RB, uint8_t* Y, int
     const CrtConfig c = kCrt[cfg];
     const int64_t grid = xcd_grid((Mp / c.bm) * (Np / c.bn));
     if (grid > 0x7fffffffLL) return (int)hipErrorInvalidConfiguration;
-    // ring depths: at most 64 KiB of LDS per workgroup
+    // ring depths: the LDS of one CU (160 KiB) holds one wide workgroup's
+    // ring or two of the others
     if (cfg == 0)
-        hipLaunchKernelGGL((crt_mfma_kernel<256, 256, 2, 4, 4>), dim3((unsigned)grid), dim3(512), 0, st, RA,
-                           RB, Y, Mp, Np, Kp, N);
+        hipLaunchKernelGGL(crt_mfma_wide_kernel<1>, dim3((unsigned)grid), dim3(256), 0, st, RA, RB, Y, Mp, Np,
+                           Kp, N);
     else if (cfg == 1)
-        hipLaunchKernelGGL((crt_mfma_kernel<256, 128, 2, 2, 5>), dim3((unsigned)grid), dim3(256), 0, st, RA,
+        hipLaunchKernelGGL((crt_mfma_kernel<256, 128, 2, 2, 6>), dim3((unsigned)grid), dim3(256), 0, st, RA,
                            RB, Y, Mp, Np, Kp, N);
     else
         hipLaunchKernelGGL((crt_mfma_kernel<128, 128, 2, 2, 8>), dim3((unsigned)grid), dim3(256), 0, st, RA,

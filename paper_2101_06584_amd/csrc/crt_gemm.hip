@@ -609,74 +609,58 @@ __global__ __launch_bounds__(256, 1) void crt_mfma_wide_kernel(const int8_t* __r
 
 // Components c_0..c_{P-1} of w 2^e (w: K-limb magnitude, sign sg): c_0 = RN
 // of the value, then RN of the exact remainder, and so on (ties to even).
+// Branch-free: the top nonzero limb and the two below it are gathered by
+// selects into a 96-bit window, normalised by its leading zeros; its top 53
+// bits are the significand, then the guard bit, the rest and all lower limbs
+// the sticky bit.  Values below 2^53 need no case of their own: the window
+// then reaches below bit 0, where everything reads as zero.
 template <int P, int K>
 __device__ __forceinline__ void limbs_to_components(uint32_t (&w)[K], double sg, int e, double* c) {
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-        int h = -1;                                     // top set bit
+        int L = -1;                                     // top nonzero limb
 #pragma unroll
-        for (int l = K - 1; l >= 0; --l)
-            if (h < 0 && w[l] != 0u) h = 32 * l + 31 - __builtin_clz(w[l]);
-        if (h < 0) {
-            c[q] = 0.0;
-            continue;
-        }
-        if (h <= 52) {                                  // exact: the rest is zero
-            const uint64_t v = (uint64_t)w[0] | ((uint64_t)w[1] << 32);
-            c[q] = sg * ldexp((double)v, e);
-#pragma unroll
-            for (int l = 0; l < K; ++l) w[l] = 0u;
-            continue;
-        }
-        const int sh = h - 52;
-        // bits [sh - 11, sh + 53) as one 64-bit window (the top 53 are the
-        // significand, then the guard bit), sticky bits below it
-        const int base = sh - 11;
-        uint64_t win = 0;
-        bool below = false;
+        for (int l = 0; l < K; ++l) L = (w[l] != 0u) ? l : L;
+        uint32_t hi = 0u, mid = 0u, lo = 0u, below = 0u;
 #pragma unroll
         for (int l = 0; l < K; ++l) {
-            const int a = 32 * l - base;                // position of limb l's bit 0 in the window
-            if (a >= 64) continue;
-            if (a >= 0) {
-                win |= (uint64_t)w[l] << a;
-            } else if (a > -32) {
-                win |= (uint64_t)(w[l] >> (-a));
-                below = below || (w[l] & ((1u << (-a)) - 1u)) != 0u;
-            } else {
-                below = below || w[l] != 0u;
-            }
+            hi = (l == L) ? w[l] : hi;
+            mid = (l == L - 1) ? w[l] : mid;
+            lo = (l == L - 2) ? w[l] : lo;
+            below |= (l < L - 2) ? w[l] : 0u;
         }
+        const int z = __clz(hi | 1u);                   // leading zeros of hi (nonzero when L >= 0)
+        const uint64_t hm = ((uint64_t)hi << 32) | mid;
+        // (hi:mid:lo) << z: the top 64 bits and the 32 left over
+        const uint64_t win = (z == 0) ? hm : ((hm << z) | (uint64_t)(lo >> (32 - z)));
+        const uint32_t rest = lo << z;
+        const int h = 32 * L + 31 - z;                  // top set bit
+        const int sh = h - 52;                          // exponent of the significand's last bit
         uint64_t v = win >> 11;
         const bool guard = ((win >> 10) & 1u) != 0u;
-        const bool sticky = below || (win & 0x3ffu) != 0u;
+        const bool sticky = (win & 0x3ffu) != 0u || rest != 0u || below != 0u;
         const bool up = guard && (sticky || (v & 1u));
         v += up ? 1u : 0u;
-        c[q] = sg * ldexp((double)v, sh + e);
+        c[q] = (L < 0) ? 0.0 : sg * ldexp((double)v, sh + e);
+        if (q == P - 1) break;
         // remainder: the bits below sh; after rounding up, 2^sh minus them
-        // with the sign flipped
+        // with the sign flipped (a value below 2^53 leaves nothing)
+        uint32_t mask[K];
 #pragma unroll
         for (int l = 0; l < K; ++l) {
-            const int a = 32 * l;
-            if (a >= sh) w[l] = 0u;
-            else if (a + 32 > sh) w[l] &= (1u << (sh - a)) - 1u;
+            const int t = sh - 32 * l;                  // bits of limb l below sh
+            mask[l] = (t <= 0) ? 0u : (t >= 32) ? 0xffffffffu : ((1u << (t & 31)) - 1u);
+            w[l] &= mask[l];
         }
-        if (up) {
-            uint64_t carry = 1;
+        uint32_t carry = 1u;
 #pragma unroll
-            for (int l = 0; l < K; ++l) {
-                const uint64_t t = (uint64_t)(~w[l]) + carry;
-                w[l] = (uint32_t)t;
-                carry = t >> 32;
-            }
-#pragma unroll
-            for (int l = 0; l < K; ++l) {
-                const int a = 32 * l;
-                if (a >= sh) w[l] = 0u;
-                else if (a + 32 > sh) w[l] &= (1u << (sh - a)) - 1u;
-            }
-            sg = -sg;
+        for (int l = 0; l < K; ++l) {
+            const uint64_t t = (uint64_t)(~w[l]) + carry;
+            const uint32_t nl = (uint32_t)t & mask[l];
+            carry = (uint32_t)(t >> 32);
+            w[l] = up ? nl : w[l];
         }
+        sg = up ? -sg : sg;
     }
 }
 

@@ -782,6 +782,8 @@ def other_config(args, mp, synth, dev, stream):
     dB = torch.from_numpy(B).to(dev)
     note("inputs ready", NAME[P], n)
     forms = args.forms.split(",")
+    if cfg == 4 and "crt" not in forms:
+        forms.append("crt")        # the residue form of the split product, too
     if cfg == 3:
         # "same error": the smallest s whose result on a block of rows stays
         # within 1e-6 k u (|A||B|)_ij of the plain (canonical) result
@@ -791,13 +793,19 @@ def other_config(args, mp, synth, dev, stream):
     else:
         s, rule_ratio = mp.DEFAULT_SLICES[P], None
     ws = mp.alloc_workspace(P, n, n, n, s, device=dev) if "split" in forms else None
+    n_mod = mp.crt_moduli(P, n, s) if "crt" in forms else 0
+    if "crt" in forms and n_mod == 0:
+        note("residue form: no modulus count suffices for", NAME[P], "s =", s, "- skipped")
+        forms.remove("crt")
+    ws_crt = mp.alloc_workspace(P, n, n, n, s, device=dev, form="crt") if "crt" in forms else None
     parts = {}
     chk = None if args.no_check else GemmChecker(P, "N", "N", n, n, n, one, A, B, zero,
                                                  np.zeros((P, 1, 1)))
     ents = sample_entries(synth.rng_for(cfg, "samples"), n, n, 1024)
     for f in forms:
         dC = torch.zeros((P, n, n), dtype=torch.float64, device=dev)
-        kw = dict(form="split", slices=s, workspace=ws) if f == "split" else dict(form="plain")
+        kw = (dict(form="split", slices=s, workspace=ws) if f == "split" else
+              dict(form="crt", slices=s, workspace=ws_crt) if f == "crt" else dict(form="plain"))
         call = lambda: mp.gemm(P, "N", "N", n, n, n, one, dA, dB, zero, dC, stream=stream, **kw)  # noqa: E731
         for _ in range(args.warmup):
             call()
@@ -817,6 +825,10 @@ def other_config(args, mp, synth, dev, stream):
         if f == "split":
             item["slices"] = s
             item["int8_ops_frac"] = s * (s + 1) / 2 * 2.0 * n ** 3 / (ms * 1e-3) / INT8_PEAK
+        elif f == "crt":
+            item["slices"] = s
+            item["moduli"] = n_mod
+            item["int8_ops_frac"] = n_mod * 2.0 * n ** 3 / (ms * 1e-3) / INT8_PEAK
         else:
             item["fp64_peak_frac"] = n ** 3 * FLOPS_PER_MAC[P] / (ms * 1e-3) / FP64_PEAK
         if chk is not None:
@@ -827,7 +839,8 @@ def other_config(args, mp, synth, dev, stream):
         parts[f"{NAME[P]}_{f}"] = item
     total_ms = sum(v["ms"] for v in parts.values())
     workload = ("QD GEMM m=n=k=2048, entries u*2^e, e ~ U{-30..30} per entry, both forms, slices "
-                "from the accuracy rule" if cfg == 3 else "DD GEMM m=n=k=8192, both forms")
+                "from the accuracy rule" if cfg == 3 else
+                "DD GEMM m=n=k=8192, plain, split and residue (CRT) split forms")
     out = {"metric": METRIC, "value": 2.0 * n ** 3 * len(parts) / (total_ms * 1e-3), "unit": "2mnk/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(total_ms, 3), "higher_is_better": True, "scaling": "weak",

@@ -501,17 +501,17 @@ def strassen_bench(args, mp, synth, dev, stream):
 
 
 def crt_bench(args, mp, synth, dev, stream):
-    """C = alpha A B + beta C at m = n = k = args.n in DD and TD (default
+    """C = alpha A B + beta C at m = n = k = args.n in DD, TD and QD (default
     digits): the triangular split form (one INT8 product per digit pair,
-    s (s + 1) / 2 of them) against its residue form (one per modulus) with
-    each tile configuration.  Time and error on sampled entries (k u
+    s (s + 1) / 2 of them) against its residue form (one per modulus; for QD
+    three half-size products of N moduli) with each tile configuration.  Time and error on sampled entries (k u
     (|alpha||A||B| + |beta||C|)).  One JSON line."""
     import numpy as np
     import torch
     from tests.exact import GemmChecker, sample_entries
     n = args.n
     parts = {}
-    for P in (2, 3):
+    for P in (2, 3, 4):
         A = synth.mp_matrix(2, "A", P, n, n)
         B = synth.mp_matrix(2, "B", P, n, n)
         C = synth.mp_matrix(2, "C", P, n, n)
@@ -553,13 +553,13 @@ def crt_bench(args, mp, synth, dev, stream):
         parts[f"{NAME[P]}_crt_speedup_vs_split"] = round(parts[f"{NAME[P]}_split"]["ms"] / best, 3)
         del dA, dB, dC0
     best_ms = [min(v["ms"] for k_, v in parts.items() if k_.startswith(nm + "_crt") and isinstance(v, dict))
-               for nm in ("DD", "TD")]
-    out = {"metric": "DD/TD GEMM 2mnk/s, residue split form", "unit": "2mnk/s",
-           "value": 2.0 * n ** 3 * 2 / (sum(best_ms) * 1e-3), "n_gpus": 1, "steps": max(3, args.steps),
+               for nm in ("DD", "TD", "QD")]
+    out = {"metric": "DD/TD/QD GEMM 2mnk/s, residue split form", "unit": "2mnk/s",
+           "value": 2.0 * n ** 3 * 3 / (sum(best_ms) * 1e-3), "n_gpus": 1, "steps": max(3, args.steps),
            "warmup": 1, "ms_per_step": round(sum(best_ms), 3), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "i8", "data": "synthetic",
-           "config": {"workload": f"C = alpha A B + beta C, m = n = k = {n}, DD (s = 16) and TD (s = 23), "
-                                  "triangular split form vs residue form", "n": n,
+           "config": {"workload": f"C = alpha A B + beta C, m = n = k = {n}, DD (s = 16), TD (s = 23) and "
+                                  "QD (s = 31, two levels), triangular split form vs residue form", "n": n,
                       "err_units": "|C - C*| / (k u (|alpha||A||B| + |beta||C|)), 32 sampled entries"},
            "breakdown": parts}
     print(json.dumps(out), flush=True)

@@ -169,9 +169,15 @@ int mpgemm_qd(char transa, char transb, int64_t m, int64_t n, int64_t k, const d
  * 14 s) is rounded to P components by repeated round to nearest (ties to
  * even) of the exact remainder and the plain epilogue applied.  N grows with
  * 14 s + log2 k (DD, s = 16: at most 32 moduli; TD, s = 23: 48 for k <= 2^13,
- * 49 above); MPGEMM_ERR_UNSUPPORTED when 49 do not suffice (QD at its default
- * s, s > 24, or k > 131071).  Deterministic; the exactly rounded product of
- * the truncated operands.  Workspace as for the split form, sized by
+ * 49 above).  QD with 25 <= s <= 32 digits (its default s = 31 included), where
+ * 49 moduli do not suffice, cuts each digit integer into a high half of
+ * ceil(s/2) digits and a low half, A' = A_h 128^(s/2) + A_l, and forms C' =
+ * hh 128^(2 floor(s/2)) + (ss - hh - ll) 128^floor(s/2) + ll from the three
+ * half-size products hh = A_h B_h, ll = A_l B_l, ss = (A_h + A_l)(B_h + B_l),
+ * each from N <= 33 moduli: the same integer, so the same result.
+ * MPGEMM_ERR_UNSUPPORTED otherwise (s > 24 for DD and TD, s > 32 for QD, or
+ * k > 131071).  Deterministic; the exactly rounded product of the truncated
+ * operands.  Workspace as for the split form, sized by
  * mpgemm_workspace_bytes(prec, MPGEMM_FORM_SPLIT_CRT, m, n, k, slices, tile).
  * opts->variant (TD, plain form only; MPGEMM_ERR_UNSUPPORTED for another
  * precision or the split forms, -18 outside 0..3): the same canonical
@@ -192,10 +198,11 @@ int mpgemm_qd_ex(char transa, char transb, int64_t m, int64_t n, int64_t k, cons
                  int64_t b_plane_stride, const double* beta, double* C, int64_t ldc,
                  int64_t c_plane_stride, hipStream_t stream, const mpgemm_opts* opts);
 
-/* Residue form: the number of moduli (INT8 products) N for inner dimension
- * k and s digits per entry (slices 0 = the default of precision prec), or 0
- * when the first 49 moduli do not suffice or k is outside 1..131071; -1 for
- * an invalid precision. */
+/* Residue form: the number of INT8 products a call runs for inner dimension
+ * k and s digits per entry (slices 0 = the default of precision prec): the
+ * modulus count N, or 3 N with two levels (QD, s > 24); 0 when the form does
+ * not apply (too many digits, or k outside 1..131071); -1 for an invalid
+ * precision. */
 int mpgemm_crt_moduli(int prec, int64_t k, int slices);
 
 /* Workspace bytes the split forms (MPGEMM_FORM_SPLIT_I8, _AUTO, _SPLIT_CRT)

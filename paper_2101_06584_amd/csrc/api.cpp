@@ -208,7 +208,7 @@ int gemm_common(int P, char ta, char tb, int64_t m, int64_t n, int64_t k, const 
     const int crt_s = crt ? (opts->slices > 0 ? opts->slices : kDefaultSlices[P]) : 0;
     // the residue form needs enough moduli for the exact product (checked
     // for every shape, also those that return early)
-    if (crt && k > 0 && crt_moduli_count(k, crt_s) == 0) return MPGEMM_ERR_UNSUPPORTED;
+    if (crt && k > 0 && crt_products(P, k, crt_s) == 0) return MPGEMM_ERR_UNSUPPORTED;
     if (m == 0 || n == 0) return 0;
     const bool az = (k == 0) || mp_zero(P, alpha);
     if (az && mp_one(P, beta)) return 0;
@@ -299,7 +299,7 @@ size_t mpgemm_workspace_bytes(int prec, int form, int64_t m, int64_t n, int64_t 
 int mpgemm_crt_moduli(int prec, int64_t k, int slices) {
     if (prec < 2 || prec > 4) return -1;
     if (slices < 0 || slices > kMaxSlices) return 0;
-    return crt_moduli_count(k, slices > 0 ? slices : kDefaultSlices[prec]);
+    return crt_products(prec, k, slices > 0 ? slices : kDefaultSlices[prec]);
 }
 
 int mpgemm_split_layout(int prec, int64_t m, int64_t n, int64_t k, int slices, int tile,
@@ -602,7 +602,7 @@ int mpgemm_autotune(int prec, int form, int64_t m, int64_t n, int64_t k, int sli
     const int P = prec;
     const int s = slices > 0 ? slices : kDefaultSlices[P];
     if (form == MPGEMM_FORM_SPLIT_I8 && !split_k_ok(k, s)) return MPGEMM_ERR_UNSUPPORTED;
-    if (form == MPGEMM_FORM_SPLIT_CRT && crt_moduli_count(k, s) == 0) return MPGEMM_ERR_UNSUPPORTED;
+    if (form == MPGEMM_FORM_SPLIT_CRT && crt_products(P, k, s) == 0) return MPGEMM_ERR_UNSUPPORTED;
     double *A = nullptr, *B = nullptr, *C = nullptr;
     void* ws = nullptr;
     size_t wsb = 0;

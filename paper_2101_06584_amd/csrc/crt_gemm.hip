@@ -41,7 +41,7 @@ namespace {
 
 constexpr int kNumModuli = 49;
 constexpr int kLimbs = 11;          // 32-bit limbs: the product of all moduli has 342 bits
-constexpr int kMaxCrtDigits = 24;  // 14 s + log2 k - 1 < 342 bits needs s <= 24
+constexpr int kMaxCrtDigits = 24;  // one level: 14 s + log2 k - 1 < 342 bits needs s <= 24
 constexpr int kCrtTileK = 32;       // k bytes per residue tile row and per product step
 
 // Greedy pairwise coprime moduli from 256 down: every m <= 256 coprime to
@@ -177,11 +177,11 @@ __device__ __forceinline__ int next_digit(double (&r)[P], int p) {
     return (int)d;
 }
 
-template <int P, int NG>
+template <int P, int NG, int SETS>
 __global__ __launch_bounds__(256) void crt_residue_kernel(const double* __restrict__ X, int64_t rs,
                                                           int64_t ls, int64_t ps, int64_t count,
                                                           int64_t k, const int32_t* __restrict__ E,
-                                                          int s, int N, CrtWeights wt,
+                                                          int s, int N, int shi, CrtWeights wt,
                                                           int8_t* __restrict__ R, int64_t Rp,
                                                           int64_t Kp) {
     __shared__ double tile[P][kResRows][kTileK + 1];
@@ -205,13 +205,32 @@ __global__ __launch_bounds__(256) void crt_residue_kernel(const double* __restri
     const int lane = t & 63, wave = t >> 6;
     // this lane's weight columns (modulus 32 cg + lane % 32, digits
     // 16 (lane / 32) .. + 15) and its moduli for the reduction
-    v4i bw[NG];
+    // with two levels (SETS = 3) the row holds the high half's weights on
+    // digits 0..shi-1 and the low half's on the rest: set 0 keeps the first,
+    // set 1 the second, set 2 (their sum) the whole row
+    v4i bw[SETS][NG];
     float mf[NG], invm[NG];
 #pragma unroll
     for (int cg = 0; cg < NG; ++cg) {
         const int tt = 32 * cg + (lane & 31);
         const uint32_t* wp = (const uint32_t*)wt.w[tt] + 4 * (lane >> 5);
-        bw[cg] = v4i{(int)wp[0], (int)wp[1], (int)wp[2], (int)wp[3]};
+        const v4i row = v4i{(int)wp[0], (int)wp[1], (int)wp[2], (int)wp[3]};
+        if constexpr (SETS == 1) {
+            bw[0][cg] = row;
+        } else {
+            v4i hi_mask;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                uint32_t mk = 0u;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    mk |= (16 * (lane >> 5) + 4 * c + j < shi) ? (0xffu << (8 * j)) : 0u;
+                hi_mask[c] = (int)mk;
+            }
+            bw[0][cg] = row & hi_mask;
+            bw[1][cg] = row & ~hi_mask;
+            bw[2][cg] = row;
+        }
         const int m = tt < kNumModuli ? kCrtDev.mod[tt] : 1;
         mf[cg] = (float)m;
         invm[cg] = 1.0f / (float)m;
@@ -230,7 +249,7 @@ __global__ __launch_bounds__(256) void crt_residue_kernel(const double* __restri
         for (int i = 0; i < 8; ++i) dg[rw][i] = 0u;
     }
 #pragma unroll
-    for (int p = 1; p <= kMaxCrtDigits; ++p)
+    for (int p = 1; p <= 32; ++p)                 // 32 digit bytes per entry
         if (p <= s) {
 #pragma unroll
             for (int rw = 0; rw < 4; ++rw)
@@ -252,12 +271,15 @@ __global__ __launch_bounds__(256) void crt_residue_kernel(const double* __restri
         const v4i a1 = low ? lo : xs;
         const v4i a2 = low ? xs : hi;
 #pragma unroll
-        for (int cg = 0; cg < NG; ++cg) {
+        for (int cg = 0; cg < NG; ++cg)
+#pragma unroll
+        for (int set = 0; set < SETS; ++set) {
             v16i acc[2];
-            acc[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, bw[cg], v16i{0}, 0, 0, 0);
-            acc[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, bw[cg], v16i{0}, 0, 0, 0);
+            acc[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, bw[set][cg], v16i{0}, 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, bw[set][cg], v16i{0}, 0, 0, 0);
             const int tt = 32 * cg + (lane & 31);
             if (tt >= N) continue;
+            const int64_t plane = (int64_t)set * N + tt;
 #pragma unroll
             for (int eg = 0; eg < 2; ++eg)
 #pragma unroll
@@ -273,7 +295,7 @@ __global__ __launch_bounds__(256) void crt_residue_kernel(const double* __restri
                     }
                     // entries 32 eg + 8 v4 + 4 (lane / 32) + 0..3 of this row
                     const int64_t l = l0 + 32 * eg + 8 * v4 + 4 * (lane >> 5);
-                    *(uint32_t*)(R + ((tt * nkt + l / kCrtTileK) * Rp + gr) * kCrtTileK + l % kCrtTileK) = word;
+                    *(uint32_t*)(R + ((plane * nkt + l / kCrtTileK) * Rp + gr) * kCrtTileK + l % kCrtTileK) = word;
                 }
         }
     }
@@ -324,7 +346,8 @@ template <int BM, int BN, int WGM, int WGN, int D>
 __global__ __launch_bounds__(64 * WGM * WGN, 2) void crt_mfma_kernel(const int8_t* __restrict__ RA,
                                                                      const int8_t* __restrict__ RB,
                                                                      uint8_t* __restrict__ Y, int64_t Mp,
-                                                                     int64_t Np, int64_t Kp, int N) {
+                                                                     int64_t Np, int64_t Kp, int N,
+                                                                     int Nmod) {
     using T = CrtDma<BM, BN, WGM, WGN, D>;
     __shared__ __attribute__((aligned(1024))) int8_t lds[T::LDS_BYTES];
 
@@ -404,8 +427,10 @@ __global__ __launch_bounds__(64 * WGM * WGN, 2) void crt_mfma_kernel(const int8_
         if (++kt < nkt) continue;
 
         // last k-tile of modulus `mod`: reduce, store, clear
-        const int mt = kCrtDev.mod[mod];
-        const double md = (double)mt, inv = kCrtDev.inv[mod];
+        // plane `mod` is modulus mod % Nmod of its residue set
+        const int mi = mod % Nmod;
+        const int mt = kCrtDev.mod[mi];
+        const double md = (double)mt, inv = kCrtDev.inv[mi];
         uint8_t* Yt = Y + (int64_t)mod * Np * Mp;
 #pragma unroll
         for (int i = 0; i < T::FM; ++i)
@@ -483,7 +508,8 @@ template <int KH>
 __global__ __launch_bounds__(256, 1) void crt_mfma_wide_kernel(const int8_t* __restrict__ RA,
                                                                const int8_t* __restrict__ RB,
                                                                uint8_t* __restrict__ Y, int64_t Mp,
-                                                               int64_t Np, int64_t Kp, int N) {
+                                                               int64_t Np, int64_t Kp, int N,
+                                                               int Nmod) {
     using W = WideCfg<KH>;
     constexpr int D = W::D;
     __shared__ __attribute__((aligned(1024))) int8_t lds[W::LDS_BYTES];
@@ -578,8 +604,10 @@ __global__ __launch_bounds__(256, 1) void crt_mfma_wide_kernel(const int8_t* __r
             step(std::integral_constant<int, 0>{}, u);
             step(std::integral_constant<int, 1>{}, u + 1);
         }
-        const int mt = kCrtDev.mod[mod];
-        const double md = (double)mt, inv = kCrtDev.inv[mod];
+        // plane `mod` is modulus mod % Nmod of its residue set
+        const int mi = mod % Nmod;
+        const int mt = kCrtDev.mod[mi];
+        const double md = (double)mt, inv = kCrtDev.inv[mi];
         // this lane's first byte in plane `mod`; the tiles are uniform offsets from it
         uint8_t* Yl = Y + (int64_t)mod * Np * Mp + ybase;
 #pragma unroll
@@ -765,6 +793,121 @@ __global__ __launch_bounds__(256) void crt_recombine_kernel(GemmArgs g, const in
     });
 }
 
+// Two levels (digit integers cut into a high and a low half, A' = A_h 2^w +
+// A_l with w = 7 SLO): the products hh = A_h B_h, ll = A_l B_l and
+// ss = (A_h + A_l)(B_h + B_l) come as three sets of N residue planes and are
+// reconstructed one after the other; then C' = hh 2^(2w) + (ss - hh - ll) 2^w
+// + ll, formed exactly in 16 limbs (two's complement), and rounded as above.
+constexpr int kLimbsC = 16;           // C' below 2^511: up to 32 digits
+
+// c += sign * (x, sign-extended by ext) * 2^SH, modulo 2^512; K-limb x.
+template <int SIGN, int SH, int K>
+__device__ __forceinline__ void add_shifted(uint32_t (&c)[kLimbsC], const uint32_t (&x)[K], uint32_t ext) {
+    constexpr int ws = SH / 32, bs = SH % 32;
+    uint64_t carry = SIGN > 0 ? 0u : 1u;          // subtraction adds ~y + 1
+#pragma unroll
+    for (int d = 0; d < kLimbsC; ++d) {
+        const int i = d - ws;
+        const uint32_t cur = i < 0 ? 0u : (i < K ? x[i] : ext);
+        const uint32_t prev = i - 1 < 0 ? 0u : (i - 1 < K ? x[i - 1] : ext);
+        uint32_t y = bs == 0 ? cur : ((cur << bs) | (prev >> ((32 - bs) & 31)));
+        if (SIGN < 0) y = ~y;
+        const uint64_t t = (uint64_t)c[d] + y + carry;
+        c[d] = (uint32_t)t;
+        carry = t >> 32;
+    }
+}
+
+template <int P, int SLO>
+__global__ __launch_bounds__(256) void crt_recombine3_kernel(GemmArgs g, const int32_t* __restrict__ E,
+                                                             const int32_t* __restrict__ F,
+                                                             const uint8_t* __restrict__ Y, int N,
+                                                             int s, int64_t Mp, int64_t Np) {
+    constexpr int K = 8;                          // each partial below 2^255 (N <= 33)
+    constexpr int w = 7 * SLO;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= g.m * g.n) return;
+    const int64_t i = idx % g.m, j = idx / g.m;
+    const int64_t plane = Mp * Np;
+    const uint8_t* yp = Y + j * Mp + i;
+    const int row0 = N * (N - 1) / 2;
+    uint32_t c[kLimbsC];
+#pragma unroll
+    for (int l = 0; l < kLimbsC; ++l) c[l] = 0u;
+    static_for<3>([&](auto setc) __attribute__((always_inline)) {
+        constexpr int set = decltype(setc)::value;     // 0: hh, 1: ll, 2: ss
+        double L[K];
+#pragma unroll
+        for (int l = 0; l < K; ++l) L[l] = 0.0;
+        double f = 0.0;
+        const uint8_t* ys = yp + (int64_t)set * N * plane;
+        for (int t0 = 0; t0 < N; t0 += 8) {
+            uint32_t yv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) yv[u] = (t0 + u < N) ? ys[(int64_t)(t0 + u) * plane] : 0u;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int t = t0 + u;
+                if (t >= N) break;
+                const double y = (double)yv[u];
+                f = fma(y, kCrtDev.inv[t], f);
+                const double* wl = kCrtDev.Wd[row0 + t];
+#pragma unroll
+                for (int l = 0; l < K; ++l) L[l] = fma(y, wl[l], L[l]);
+            }
+        }
+        const double q = rint(f);
+        uint32_t x[K];
+        int64_t carry = 0;
+#pragma unroll
+        for (int l = 0; l < K; ++l) {
+            const int64_t v = (int64_t)fma(-q, kCrtDev.Md[N][l], L[l]) + carry;
+            x[l] = (uint32_t)v;
+            carry = v >> 32;
+        }
+        const uint32_t ext = carry < 0 ? 0xffffffffu : 0u;
+        if constexpr (set == 0) {
+            add_shifted<+1, 2 * w, K>(c, x, ext);
+            add_shifted<-1, w, K>(c, x, ext);
+        } else if constexpr (set == 1) {
+            add_shifted<+1, 0, K>(c, x, ext);
+            add_shifted<-1, w, K>(c, x, ext);
+        } else {
+            add_shifted<+1, w, K>(c, x, ext);
+        }
+    });
+    double sg = 1.0;
+    if (c[kLimbsC - 1] >> 31) {
+        uint64_t c1 = 1;
+#pragma unroll
+        for (int l = 0; l < kLimbsC; ++l) {
+            const uint64_t t = (uint64_t)(~c[l]) + c1;
+            c[l] = (uint32_t)t;
+            c1 = t >> 32;
+        }
+        sg = -1.0;
+    }
+    double comp[P];
+    limbs_to_components<P, kLimbsC>(c, sg, E[i] + F[j] - 14 * s, comp);
+    mp<P> acc, alpha, beta;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        acc.c[p] = comp[p];
+        alpha.c[p] = g.alpha[p];
+        beta.c[p] = g.beta[p];
+    }
+    const int64_t off = i + j * g.ldc;
+    mp<P> t = mul(alpha, acc);
+    if (!mp_is_zero(beta)) {
+        mp<P> co;
+#pragma unroll
+        for (int p = 0; p < P; ++p) co.c[p] = g.C[p * g.sc + off];
+        t = add(t, mul(beta, co));
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) g.C[p * g.sc + off] = t.c[p];
+}
+
 // ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
@@ -777,8 +920,10 @@ int inverse_mod(int a, int m) {          // a^-1 mod m for gcd(a, m) = 1, m <= 2
 
 int8_t sym_byte(int v, int m) { return (int8_t)(v >= 128 ? v - m : v); }   // v in [0, m)
 
-// Digit weights 128^(s - 1 - p) mod m_t (times u_t when `scaled`).
-CrtWeights crt_weights(int N, int s, bool scaled) {
+// Digit weights mod m_t (times u_t when `scaled`): byte p (digit p + 1) gets
+// 128^(shi - 1 - p) for p < shi (the high half, or the whole integer when
+// shi = s) and 128^(s - 1 - p) for the low half p >= shi.
+CrtWeights crt_weights(int N, int s, int shi, bool scaled) {
     CrtWeights W{};
     for (int t = 0; t < N; ++t) {
         const int m = kModuli[t];
@@ -789,10 +934,13 @@ CrtWeights crt_weights(int N, int s, bool scaled) {
                 if (j != t) cof = cof * (kModuli[j] % m) % m;
             u = inverse_mod(cof, m);
         }
-        int pw = u % m;                                 // weight of the last digit
-        for (int p = s - 1; p >= 0; --p) {
-            W.w[t][p] = sym_byte(pw, m);
-            pw = pw * (128 % m) % m;
+        for (int half = 0; half < 2; ++half) {
+            const int lo = half ? shi : 0, hi = half ? s : shi;   // bytes [lo, hi)
+            int pw = u % m;                             // weight of byte hi - 1
+            for (int p = hi - 1; p >= lo; --p) {
+                W.w[t][p] = sym_byte(pw, m);
+                pw = pw * (128 % m) % m;
+            }
         }
     }
     return W;
@@ -805,27 +953,29 @@ int limbs_for(int N) {
     return top <= 4 ? 4 : top <= 6 ? 6 : top <= 8 ? 8 : 11;
 }
 
-int launch_residues(int P, const double* X, int64_t rs, int64_t ls, int64_t ps, int64_t count,
-                    int64_t k, const int32_t* E, int s, int N, const CrtWeights& w, int8_t* R,
+int launch_residues(int P, int sets, const double* X, int64_t rs, int64_t ls, int64_t ps, int64_t count,
+                    int64_t k, const int32_t* E, int s, int N, int shi, const CrtWeights& w, int8_t* R,
                     int64_t Rp, int64_t Kp, hipStream_t st) {
     const dim3 grid((unsigned)(Kp / kTileK), (unsigned)(Rp / kResRows));
-#define MPG_RES(PV, NGV)                                                                               \
-    hipLaunchKernelGGL((crt_residue_kernel<PV, NGV>), grid, dim3(256), 0, st, X, rs, ls, ps, count, k, E, \
-                       s, N, w, R, Rp, Kp)
+#define MPG_RES(PV, NGV, SV)                                                                           \
+    hipLaunchKernelGGL((crt_residue_kernel<PV, NGV, SV>), grid, dim3(256), 0, st, X, rs, ls, ps, count, k, \
+                       E, s, N, shi, w, R, Rp, Kp)
     const bool two = N > 32;
-    if (P == 2) {
-        if (two) MPG_RES(2, 2); else MPG_RES(2, 1);
+    if (sets == 3) {                             // two levels: QD only
+        if (two) MPG_RES(4, 2, 3); else MPG_RES(4, 1, 3);
+    } else if (P == 2) {
+        if (two) MPG_RES(2, 2, 1); else MPG_RES(2, 1, 1);
     } else if (P == 3) {
-        if (two) MPG_RES(3, 2); else MPG_RES(3, 1);
+        if (two) MPG_RES(3, 2, 1); else MPG_RES(3, 1, 1);
     } else {
-        if (two) MPG_RES(4, 2); else MPG_RES(4, 1);
+        if (two) MPG_RES(4, 2, 1); else MPG_RES(4, 1, 1);
     }
 #undef MPG_RES
     return (int)hipGetLastError();
 }
 
 int launch_crt_mfma(int cfg, const int8_t* RA, const int8_t* RB, uint8_t* Y, int64_t Mp, int64_t Np,
-                    int64_t Kp, int N, hipStream_t st) {
+                    int64_t Kp, int N, int Nmod, hipStream_t st) {
     const CrtConfig c = kCrt[cfg];
     const int64_t grid = xcd_grid((Mp / c.bm) * (Np / c.bn));
     if (grid > 0x7fffffffLL) return (int)hipErrorInvalidConfiguration;
@@ -833,13 +983,13 @@ int launch_crt_mfma(int cfg, const int8_t* RA, const int8_t* RB, uint8_t* Y, int
     // ring or two of the others
     if (cfg == 0)
         hipLaunchKernelGGL(crt_mfma_wide_kernel<1>, dim3((unsigned)grid), dim3(256), 0, st, RA, RB, Y, Mp, Np,
-                           Kp, N);
+                           Kp, N, Nmod);
     else if (cfg == 1)
         hipLaunchKernelGGL((crt_mfma_kernel<256, 128, 2, 2, 6>), dim3((unsigned)grid), dim3(256), 0, st, RA,
-                           RB, Y, Mp, Np, Kp, N);
+                           RB, Y, Mp, Np, Kp, N, Nmod);
     else
         hipLaunchKernelGGL((crt_mfma_kernel<128, 128, 2, 2, 8>), dim3((unsigned)grid), dim3(256), 0, st, RA,
-                           RB, Y, Mp, Np, Kp, N);
+                           RB, Y, Mp, Np, Kp, N, Nmod);
     return (int)hipGetLastError();
 }
 
@@ -879,13 +1029,13 @@ int crt_default_config(int64_t m, int64_t n) {
     return best;
 }
 
-int crt_moduli_count(int64_t k, int s) {
-    if (k <= 0 || k > 131071 || s < 1 || s > kMaxCrtDigits) return 0;
-    // log2 of max|C'| = k (64 (128^s - 1) / 127)^2, then one bit for the sign
-    // and a margin far above the rounding of these logarithms
-    const double amax = 6.0 + 7.0 * s + std::log1p(-std::ldexp(1.0, -7 * s)) / std::log(2.0) -
-                        std::log2(127.0);
-    const double need = 1.0 + std::log2((double)k) + 2.0 * amax + 0.01;
+// log2 of the largest |digit integer| with d digits: 64 (128^d - 1) / 127
+static double log2_amax(int d) {
+    return 6.0 + 7.0 * d + std::log1p(-std::ldexp(1.0, -7 * d)) / std::log(2.0) - std::log2(127.0);
+}
+
+// Smallest N whose modulus product exceeds 2^need, 0 if none.
+static int moduli_for_bits(double need) {
     double bits = 0.0;
     for (int N = 1; N <= kNumModuli; ++N) {
         bits += std::log2((double)kModuli[N - 1]);
@@ -894,19 +1044,47 @@ int crt_moduli_count(int64_t k, int s) {
     return 0;
 }
 
-size_t crt_workspace_bytes(int P, int64_t m, int64_t n, int64_t k, int s, int cfg) {
-    (void)P;
-    const int N = crt_moduli_count(k, s);
-    if (N == 0) return 0;
-    return crt_layout(m, n, k, N, cfg).total;
+int crt_moduli_count(int64_t k, int s) {
+    if (k <= 0 || k > 131071 || s < 1 || s > kMaxCrtDigits) return 0;
+    // max|C'| = k amax(s)^2, one bit for the sign, and a margin far above the
+    // rounding of these logarithms
+    return moduli_for_bits(1.0 + std::log2((double)k) + 2.0 * log2_amax(s) + 0.01);
 }
 
-// Caller has validated arguments, the slice count (crt_moduli_count > 0), the
-// workspace size and handled quick returns / alpha == 0 / k == 0.
+CrtPlan crt_plan(int P, int64_t k, int s) {
+    CrtPlan pl{0, 1, s, 0};
+    pl.N = crt_moduli_count(k, s);
+    if (pl.N > 0 || P != 4 || s < 2 * 12 + 1 || s > 2 * 16 || k <= 0 || k > 131071) return pl;
+    // two levels: halves of shi and slo digits; the largest of the three
+    // products is ss, with |A_h + A_l| <= amax(shi) + amax(slo)
+    pl.sets = 3;
+    pl.shi = (s + 1) / 2;
+    pl.slo = s / 2;
+    const double a = log2_amax(pl.shi), b = log2_amax(pl.slo);
+    const double asum = a + std::log2(1.0 + std::exp2(b - a));
+    pl.N = moduli_for_bits(1.0 + std::log2((double)k) + 2.0 * asum + 0.01);
+    if (pl.N > 33) pl.N = 0;                      // partials kept in 8 limbs
+    return pl;
+}
+
+int crt_products(int P, int64_t k, int s) {
+    const CrtPlan pl = crt_plan(P, k, s);
+    return pl.N * pl.sets;
+}
+
+size_t crt_workspace_bytes(int P, int64_t m, int64_t n, int64_t k, int s, int cfg) {
+    const CrtPlan pl = crt_plan(P, k, s);
+    if (pl.N == 0) return 0;
+    return crt_layout(m, n, k, pl.N * pl.sets, cfg).total;
+}
+
+// Caller has validated arguments, the plan (crt_products > 0), the workspace
+// size and handled quick returns / alpha == 0 / k == 0.
 int launch_crt(int P, int s, int cfg, const GemmArgs& g, void* ws, hipStream_t st) {
-    const int N = crt_moduli_count(g.k, s);
+    const CrtPlan pl = crt_plan(P, g.k, s);
+    const int N = pl.N;
     if (N == 0) return (int)hipErrorInvalidValue;
-    const CrtLayout L = crt_layout(g.m, g.n, g.k, N, cfg);
+    const CrtLayout L = crt_layout(g.m, g.n, g.k, N * pl.sets, cfg);
     char* base = (char*)ws;
     int32_t* E = (int32_t*)(base + L.oE);
     int32_t* F = (int32_t*)(base + L.oF);
@@ -915,15 +1093,35 @@ int launch_crt(int P, int s, int cfg, const GemmArgs& g, void* ws, hipStream_t s
     uint8_t* Y = (uint8_t*)(base + L.oY);
     const int64_t a_rs = g.ta ? g.lda : 1, a_ls = g.ta ? 1 : g.lda;
     const int64_t b_rs = g.tb ? 1 : g.ldb, b_ls = g.tb ? g.ldb : 1;
-    const CrtWeights wa = crt_weights(N, s, true);
-    const CrtWeights wb = crt_weights(N, s, false);
+    const CrtWeights wa = crt_weights(N, s, pl.shi, true);
+    const CrtWeights wb = crt_weights(N, s, pl.shi, false);
     int rc;
     uint64_t* MX = (uint64_t*)(base + L.oMX);
     if ((rc = launch_row_exponents(g.A, a_rs, a_ls, g.m, L.Mp, g.k, E, MX, st))) return rc;
     if ((rc = launch_row_exponents(g.B, b_rs, b_ls, g.n, L.Np, g.k, F, MX + L.Mp, st))) return rc;
-    if ((rc = launch_residues(P, g.A, a_rs, a_ls, g.sa, g.m, g.k, E, s, N, wa, RA, L.Mp, L.Kp, st))) return rc;
-    if ((rc = launch_residues(P, g.B, b_rs, b_ls, g.sb, g.n, g.k, F, s, N, wb, RB, L.Np, L.Kp, st))) return rc;
-    if ((rc = launch_crt_mfma(cfg, RA, RB, Y, L.Mp, L.Np, L.Kp, N, st))) return rc;
+    if ((rc = launch_residues(P, pl.sets, g.A, a_rs, a_ls, g.sa, g.m, g.k, E, s, N, pl.shi, wa, RA, L.Mp,
+                              L.Kp, st)))
+        return rc;
+    if ((rc = launch_residues(P, pl.sets, g.B, b_rs, b_ls, g.sb, g.n, g.k, F, s, N, pl.shi, wb, RB, L.Np,
+                              L.Kp, st)))
+        return rc;
+    if ((rc = launch_crt_mfma(cfg, RA, RB, Y, L.Mp, L.Np, L.Kp, N * pl.sets, N, st))) return rc;
+    if (pl.sets == 3) {
+        const int64_t blocks = (g.m * g.n + 255) / 256;
+        if (blocks > 0x7fffffffLL) return (int)hipErrorInvalidConfiguration;
+        const dim3 grid((unsigned)blocks);
+#define MPG_REC3(SL) \
+    hipLaunchKernelGGL((crt_recombine3_kernel<4, SL>), grid, dim3(256), 0, st, g, E, F, Y, N, s, L.Mp, L.Np)
+        switch (pl.slo) {
+        case 12: MPG_REC3(12); break;
+        case 13: MPG_REC3(13); break;
+        case 14: MPG_REC3(14); break;
+        case 15: MPG_REC3(15); break;
+        default: MPG_REC3(16); break;
+        }
+#undef MPG_REC3
+        return (int)hipGetLastError();
+    }
     const int64_t blocks = (L.Mp / 4 * g.n + 255) / 256;
     if (blocks > 0x7fffffffLL) return (int)hipErrorInvalidConfiguration;
     const dim3 grid((unsigned)blocks);

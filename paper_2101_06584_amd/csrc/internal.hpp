@@ -87,6 +87,14 @@ constexpr int kCrtConfigs = 3;
 int crt_default_config(int64_t m, int64_t n);
 // number of moduli for k and s digits, 0 when the product does not fit
 int crt_moduli_count(int64_t k, int s);
+// One or two levels: N moduli per product, `sets` products (1, or 3 for the
+// halves' products hh, ll, ss), the split point (high half's digits) and the
+// low half's digit count.  N = 0: not supported.
+struct CrtPlan {
+    int N, sets, shi, slo;
+};
+CrtPlan crt_plan(int P, int64_t k, int s);
+int crt_products(int P, int64_t k, int s);     // INT8 products of a call, 0 if unsupported
 size_t crt_workspace_bytes(int P, int64_t m, int64_t n, int64_t k, int s, int cfg);
 int launch_crt(int P, int s, int cfg, const GemmArgs& g, void* ws, hipStream_t st);
 

@@ -102,11 +102,12 @@ def test_crt_form_host_rules():
     L = mp.load()
     D4 = C.c_double * 4
     one4, zero4 = D4(1.0, 0, 0, 0), D4(0, 0, 0, 0)
-    o = mp.make_opts("crt")                       # QD at its default s = 31: 49 moduli do not suffice
+    o = mp.make_opts("crt", slices=33)            # QD beyond two levels of 16 digits
     rc = L.mpgemm_qd_ex(b"N", b"N", 4, 5, 6, one4, FAKE_A, 4, 24, FAKE_B, 6, 30, zero4, FAKE_C, 4, 20,
                         None, C.byref(o))
     assert rc == _lib.ERR_UNSUPPORTED
-    assert L.mpgemm_workspace_bytes(4, 5, 4, 5, 6, 0, -1) == 0
+    assert L.mpgemm_workspace_bytes(4, 5, 4, 5, 6, 33, -1) == 0
+    assert L.mpgemm_workspace_bytes(4, 5, 4, 5, 6, 0, -1) > 0       # QD default s = 31: two levels
     o = mp.make_opts("crt", slices=25)            # s > 24
     rc = L.mpgemm_dd_ex(b"N", b"N", 4, 5, 6, ONE, FAKE_A, 4, 24, FAKE_B, 6, 30, ZERO, FAKE_C, 4, 20,
                         None, C.byref(o))
@@ -130,7 +131,10 @@ def test_crt_form_host_rules():
     assert b23 >= 48 * (128 * 4096 * 2 + 128 * 128) > b16
     assert mp.num_configs(2, "crt") == 3
     assert (mp.crt_moduli(2, 4096), mp.crt_moduli(3, 4096), mp.crt_moduli(3, 65536)) == (32, 48, 49)
-    assert mp.crt_moduli(4, 100) == 0 and mp.crt_moduli(4, 129, 20) == 40 and mp.crt_moduli(2, 131072) == 0
+    assert mp.crt_moduli(4, 129, 20) == 40 and mp.crt_moduli(2, 131072) == 0
+    # QD with more than 24 digits: two levels, three products of N moduli each
+    assert (mp.crt_moduli(4, 100), mp.crt_moduli(4, 4096), mp.crt_moduli(4, 50, 25)) == (93, 96, 75)
+    assert mp.crt_moduli(4, 131071, 32) == 99 and mp.crt_moduli(3, 4096, 31) == 0
     assert L.mpgemm_crt_moduli(7, 10, 0) == -1
 
 

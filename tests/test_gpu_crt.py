@@ -46,6 +46,11 @@ CASES = [
     (3, "N", "N", 50, 40, 90, 14, 0),      # 27 moduli
     (2, "N", "T", 50, 60, 50, 13, 0),      # 25 moduli, 6 limbs
     (4, "T", "T", 40, 41, 129, 20, 1),     # 40 moduli
+    # QD beyond one level: two halves, three products (hh, ll, ss) of N moduli
+    (4, "N", "N", 70, 65, 100, 31, 0),     # default s: halves of 16 + 15 digits
+    (4, "T", "N", 33, 129, 70, 32, 1),     # 16 + 16
+    (4, "N", "T", 66, 40, 300, 25, 2),     # 13 + 12
+    (4, "T", "T", 17, 19, 2000, 28, 0),    # 14 + 14, 32 k-tiles
 ]
 
 
@@ -58,7 +63,7 @@ def test_bitwise_against_oracle(gpu_lib, P, ta, tb, m, n, k, s, tile):
     assert np.array_equal(got, want)
 
 
-@pytest.mark.parametrize("P", [2, 3])
+@pytest.mark.parametrize("P", [2, 3, 4])
 def test_exponent_spread_and_beta_zero(gpu_lib, P):
     """Entries u 2^e with e in -30..30 per entry (wide scale exponents, long
     remainders), beta = 0 and alpha = 1."""
@@ -86,7 +91,7 @@ def test_integers_exact(gpu_lib):
     assert np.array_equal(got[0].T, exact.astype(np.float64)) and not got[1:].any()
 
 
-@pytest.mark.parametrize("P", [2, 3])
+@pytest.mark.parametrize("P", [2, 3, 4])
 def test_full_size_sampled(gpu_lib, P):
     """The benchmark's square workload (n = 4096, default digits): sampled
     blocks bit-identical to the oracle's residue form, sampled entries within

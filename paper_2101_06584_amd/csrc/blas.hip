@@ -8,9 +8,11 @@
 //        (one kernel pass per level, partial sums in the caller's workspace).
 //        The order is fixed, so the result is reproducible bit for bit; for
 //        n <= 64 it is the sequential chain.
-// gemv:  y = alpha op(A) x + beta y with one thread per entry of y running the
-//        canonical ascending chain, then the plain GEMM's epilogue: the same
-//        bits as the GEMM with a single column.
+// gemv:  y = alpha op(A) x + beta y with one ascending chain per entry of y,
+//        then the plain GEMM's epilogue: the same bits as the GEMM with a
+//        single column.  The chains' multiplications are formed by other
+//        waves of the workgroup (see gemv_chain_kernel), so a chain's lane
+//        only adds.
 #pragma clang fp contract(off)
 
 #include "internal.hpp"
@@ -200,6 +202,102 @@ __global__ __launch_bounds__(256) void gemv_kernel(int64_t rows, int64_t inner, 
     for (int c = 0; c < P; ++c) y[c * sy + i] = r.c[c];
 }
 
+// gemv with the products off the chains.  A workgroup owns 64 entries of y:
+// wave 0 runs their 64 chains and only adds; waves 1-3 form the products of
+// the next block of LB steps (64 x LB of them, 64 LB / 192 per thread) into
+// LDS.  Blocks alternate between two buffers with one barrier per block: the
+// chain wave adds block b - 1 while the others multiply block b, having
+// loaded its operands into registers before the previous barrier, so the
+// loads overlap the additions.  Lanes of the product waves run along
+// whichever index of op(A) is contiguous.  LB is larger for the cheaper
+// additions (DD 48, TD 36, QD 24), the LDS buffers 100-112 KiB.
+template <int P>
+struct GemvCfg {
+    static constexpr int LB = P == 2 ? 48 : P == 3 ? 36 : 24;
+    static constexpr int PER = 64 * LB / 192;          // products per producer thread
+    static_assert(64 * LB % 192 == 0, "whole products per thread");
+};
+constexpr int kGemvRowPad = 65;          // 64 rows + 1: spreads the 'T' writes over banks
+
+template <int P>
+__global__ __launch_bounds__(256) void gemv_chain_kernel(int64_t rows, int64_t inner, int t, Scal alpha,
+                                                         const double* __restrict__ A, int64_t lda,
+                                                         int64_t sa, const double* __restrict__ x,
+                                                         int64_t sx, Scal beta, double* __restrict__ y,
+                                                         int64_t sy) {
+    constexpr int LB = GemvCfg<P>::LB, PER = GemvCfg<P>::PER;
+    __shared__ double prod[2][LB][P][kGemvRowPad];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t i0 = (int64_t)blockIdx.x * 64;
+    const int64_t nblk = (inner + LB - 1) / LB;
+    const int pt = tid - 64;                              // producer thread 0..191
+    // operands of the producer's next block, loaded a block ahead
+    double av[PER][P], xv[PER][P];
+    auto load_block = [&](int64_t b) __attribute__((always_inline)) {
+        const int64_t l0 = b * LB;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int idx = pt + 192 * j;
+            const int r = t ? idx / LB : (idx & 63);
+            const int lb = t ? idx % LB : (idx >> 6);
+            const int64_t i = i0 + r, l = l0 + lb;
+            const bool ok = i < rows && l < inner;
+            const int64_t off = t ? l + i * lda : i + l * lda;
+#pragma unroll
+            for (int c = 0; c < P; ++c) {
+                av[j][c] = ok ? A[c * sa + off] : 0.0;
+                xv[j][c] = ok ? x[c * sx + l] : 0.0;
+            }
+        }
+    };
+    if (wave > 0 && nblk > 0) load_block(0);
+    mp<P> acc = mp_zero<P>();
+    for (int64_t b = 0; b <= nblk; ++b) {
+        if (wave > 0) {
+            if (b < nblk) {
+#pragma unroll
+                for (int j = 0; j < PER; ++j) {
+                    const int idx = pt + 192 * j;
+                    const int r = t ? idx / LB : (idx & 63);
+                    const int lb = t ? idx % LB : (idx >> 6);
+                    mp<P> a, xx;
+#pragma unroll
+                    for (int c = 0; c < P; ++c) {
+                        a.c[c] = av[j][c];
+                        xx.c[c] = xv[j][c];
+                    }
+                    const mp<P> p = mul(a, xx);
+#pragma unroll
+                    for (int c = 0; c < P; ++c) prod[b & 1][lb][c][r] = p.c[c];
+                }
+                if (b + 1 < nblk) load_block(b + 1);
+            }
+        } else if (b > 0) {
+            const int64_t l0 = (b - 1) * LB;
+            const int cnt = (int)((inner - l0) < LB ? (inner - l0) : LB);
+            for (int lb = 0; lb < cnt; ++lb) {
+                mp<P> p;
+#pragma unroll
+                for (int c = 0; c < P; ++c) p.c[c] = prod[(b - 1) & 1][lb][c][lane];
+                acc = add(acc, p);
+            }
+        }
+        __syncthreads();
+    }
+    const int64_t i = i0 + lane;
+    if (wave != 0 || i >= rows) return;
+    const mp<P> al = scal<P>(alpha), be = scal<P>(beta);
+    mp<P> r = mul(al, acc);
+    if (!mp_is_zero(be)) {
+        mp<P> yo;
+#pragma unroll
+        for (int c = 0; c < P; ++c) yo.c[c] = y[c * sy + i];
+        r = add(r, mul(be, yo));
+    }
+#pragma unroll
+    for (int c = 0; c < P; ++c) y[c * sy + i] = r.c[c];
+}
+
 static Scal to_scal(int P, const double* v) {
     Scal s{};
     for (int c = 0; c < P; ++c) s.v[c] = v[c];
@@ -264,10 +362,19 @@ int launch_gemv(int P, int t, int64_t rows, int64_t inner, const double* alpha, 
                 int64_t sa, const double* x, int64_t sx, const double* beta, double* y, int64_t sy, int az,
                 hipStream_t st) {
     if (rows <= 0) return 0;
+    const Scal al = to_scal(P, alpha), be = to_scal(P, beta);
+    if (!az) {                                 // the chains with their products formed alongside
+        const int64_t wgs = (rows + 63) / 64;
+        if (wgs > 0x7fffffffLL) return (int)hipErrorInvalidConfiguration;
+        const dim3 gr((unsigned)wgs), bl(256);
+        if (P == 2) hipLaunchKernelGGL(gemv_chain_kernel<2>, gr, bl, 0, st, rows, inner, t, al, A, lda, sa, x, sx, be, y, sy);
+        else if (P == 3) hipLaunchKernelGGL(gemv_chain_kernel<3>, gr, bl, 0, st, rows, inner, t, al, A, lda, sa, x, sx, be, y, sy);
+        else hipLaunchKernelGGL(gemv_chain_kernel<4>, gr, bl, 0, st, rows, inner, t, al, A, lda, sa, x, sx, be, y, sy);
+        return (int)hipGetLastError();
+    }
     const int64_t blocks = (rows + 255) / 256;
     if (blocks > 0x7fffffffLL) return (int)hipErrorInvalidConfiguration;
     const dim3 gr((unsigned)blocks), bl(256);
-    const Scal al = to_scal(P, alpha), be = to_scal(P, beta);
     if (P == 2) hipLaunchKernelGGL(gemv_kernel<2>, gr, bl, 0, st, rows, inner, t, al, A, lda, sa, x, sx, be, y, sy, az);
     else if (P == 3) hipLaunchKernelGGL(gemv_kernel<3>, gr, bl, 0, st, rows, inner, t, al, A, lda, sa, x, sx, be, y, sy, az);
     else hipLaunchKernelGGL(gemv_kernel<4>, gr, bl, 0, st, rows, inner, t, al, A, lda, sa, x, sx, be, y, sy, az);

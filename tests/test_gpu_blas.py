@@ -81,3 +81,18 @@ def test_gemv_alpha_zero_beta_zero(gpu_lib):
     dy = dev(y)
     gpu_lib.gemv(P, "N", m, n, np.zeros(P), dev(A), dev(np.zeros((P, n))), np.zeros(P), dy)
     assert np.all(host(dy) == 0.0)              # y never read when beta == 0
+
+
+@pytest.mark.parametrize("P", [2, 4])
+def test_gemv_beta_zero_does_not_read_y(gpu_lib, P):
+    """alpha != 0, beta = 0: y is written, never read (NaN in y stays out)."""
+    m, n = 130, 77
+    A = synth.mp_matrix(20, "A", P, m, n)
+    rng = np.random.Generator(np.random.PCG64(900 + P))
+    x = synth.mp_uniform(rng, P, (n,))
+    alpha = synth.mp_scalar(20, "alpha", P)
+    want = oracle.gemv(P, "N", m, n, alpha, A, x, np.zeros(P), np.zeros((P, m)))
+    dy = dev(np.full((P, m), np.nan))
+    note("gemv beta 0", P)
+    gpu_lib.gemv(P, "N", m, n, alpha, dev(A), dev(x), np.zeros(P), dy)
+    assert np.array_equal(host(dy), want)

@@ -155,9 +155,16 @@ CrtLayout crt_layout(int64_t m, int64_t n, int64_t k, int N, int cfg) {
 // far less than 1/2), stored as its low byte.
 // Residue plane t is cut into 32-byte k-tiles:
 // byte (r, l) at R[((t (Kp/32) + l/32) Rp + r) 32 + l % 32].
+// A block's share of one plane is two runs of 512 bytes (its 16 rows of two
+// k-tiles).  Each group of 32 moduli is gathered plane by plane in LDS (the
+// input tile's space, free once the remainders are in registers) and then
+// written as those runs, 16 bytes per lane, so that no store scatters its
+// lanes over 32 planes.
 // ---------------------------------------------------------------------------
 
 constexpr int kResRows = 16;
+constexpr int kStagePlane = 2 * kResRows * kCrtTileK + 16;   // bytes per staged plane (16 B pad)
+constexpr int kStageBytes = 32 * kStagePlane;
 
 template <int P>
 __device__ __forceinline__ void vec_sum_desc(double (&r)[P]) {
@@ -178,13 +185,15 @@ __device__ __forceinline__ int next_digit(double (&r)[P], int p) {
 }
 
 template <int P, int NG, int SETS>
-__global__ __launch_bounds__(256) void crt_residue_kernel(const double* __restrict__ X, int64_t rs,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void crt_residue_kernel(const double* __restrict__ X, int64_t rs,
                                                           int64_t ls, int64_t ps, int64_t count,
                                                           int64_t k, const int32_t* __restrict__ E,
                                                           int s, int N, int shi, CrtWeights wt,
                                                           int8_t* __restrict__ R, int64_t Rp,
                                                           int64_t Kp) {
-    __shared__ double tile[P][kResRows][kTileK + 1];
+    constexpr int kTileBytes = P * kResRows * (kTileK + 1) * 8;
+    __shared__ __align__(16) uint8_t lds[kTileBytes > kStageBytes ? kTileBytes : kStageBytes];
+    double (*tile)[kResRows][kTileK + 1] = reinterpret_cast<double (*)[kResRows][kTileK + 1]>(lds);
     const int64_t seg = blockIdx.x;
     const int64_t r0 = (int64_t)blockIdx.y * kResRows;
     const int64_t l0 = seg * kTileK;
@@ -236,18 +245,22 @@ __global__ __launch_bounds__(256) void crt_residue_kernel(const double* __restri
         invm[cg] = 1.0f / (float)m;
     }
     const int64_t nkt = Kp / kCrtTileK;
-    // the digits of the wave's four rows first, their chains interleaved
+    // the remainders of the wave's four rows, then the tile's space is free
     double rem[4][P];
-    uint32_t dg[4][8];
 #pragma unroll
     for (int rw = 0; rw < 4; ++rw) {
         const int64_t gr = r0 + wave * 4 + rw;
         const int32_t Ei = (gr < count) ? E[gr] : 0;
 #pragma unroll
         for (int p = 0; p < P; ++p) rem[rw][p] = ldexp(tile[p][wave * 4 + rw][lane], -Ei);
+    }
+    __syncthreads();
+    // the digits, the four rows' chains interleaved
+    uint32_t dg[4][8];
+#pragma unroll
+    for (int rw = 0; rw < 4; ++rw)
 #pragma unroll
         for (int i = 0; i < 8; ++i) dg[rw][i] = 0u;
-    }
 #pragma unroll
     for (int p = 1; p <= 32; ++p)                 // 32 digit bytes per entry
         if (p <= s) {
@@ -255,12 +268,12 @@ __global__ __launch_bounds__(256) void crt_residue_kernel(const double* __restri
             for (int rw = 0; rw < 4; ++rw)
                 dg[rw][(p - 1) / 4] |= ((uint32_t)next_digit<P>(rem[rw], p) & 255u) << (8 * ((p - 1) % 4));
         }
+    // A fragments: lane L < 32 gives digits 0..15 of entry L (first MFMA) or
+    // of entry L + 32 (second), lane L >= 32 digits 16..31 of entry L - 32
+    // (first) or L (second); the halves trade through a lane swap
+    v4i a1[4], a2[4];
 #pragma unroll
     for (int rw = 0; rw < 4; ++rw) {
-        const int64_t gr = r0 + wave * 4 + rw;
-        // A fragments: lane L < 32 gives digits 0..15 of entry L (first MFMA)
-        // or of entry L + 32 (second), lane L >= 32 digits 16..31 of entry
-        // L - 32 (first) or L (second); the halves trade through a lane swap
         const v4i lo = {(int)dg[rw][0], (int)dg[rw][1], (int)dg[rw][2], (int)dg[rw][3]};
         const v4i hi = {(int)dg[rw][4], (int)dg[rw][5], (int)dg[rw][6], (int)dg[rw][7]};
         const bool low = lane < 32;
@@ -268,37 +281,55 @@ __global__ __launch_bounds__(256) void crt_residue_kernel(const double* __restri
         v4i xs;
 #pragma unroll
         for (int c = 0; c < 4; ++c) xs[c] = __shfl_xor(x[c], 32, 64);
-        const v4i a1 = low ? lo : xs;
-        const v4i a2 = low ? xs : hi;
+        a1[rw] = low ? lo : xs;
+        a2[rw] = low ? xs : hi;
+    }
+    // the 16 B chunk c of a staged plane holds k-tile c / 32, row (c / 2) % 16,
+    // bytes 16 (c % 2) .. + 15
+    const int st_kt = lane >> 5, st_row = (lane >> 1) & 15, st_half = lane & 1;
 #pragma unroll
-        for (int cg = 0; cg < NG; ++cg)
+    for (int cg = 0; cg < NG; ++cg)
 #pragma unroll
         for (int set = 0; set < SETS; ++set) {
-            v16i acc[2];
-            acc[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, bw[set][cg], v16i{0}, 0, 0, 0);
-            acc[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, bw[set][cg], v16i{0}, 0, 0, 0);
             const int tt = 32 * cg + (lane & 31);
-            if (tt >= N) continue;
-            const int64_t plane = (int64_t)set * N + tt;
 #pragma unroll
-            for (int eg = 0; eg < 2; ++eg)
+            for (int rw = 0; rw < 4; ++rw) {
+                v16i acc[2];
+                acc[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1[rw], bw[set][cg], v16i{0}, 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2[rw], bw[set][cg], v16i{0}, 0, 0, 0);
+                if (tt >= N) continue;
+                uint8_t* plane = lds + (lane & 31) * kStagePlane;
 #pragma unroll
-                for (int v4 = 0; v4 < 4; ++v4) {
-                    uint32_t word = 0;
+                for (int eg = 0; eg < 2; ++eg)
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        // |r| <= m / 2: a byte for m < 256; for m = 256 the
-                        // low byte of r is congruent all the same
-                        const float a = (float)acc[eg][4 * v4 + q];
-                        const float r = fmaf(-rintf(a * invm[cg]), mf[cg], a);
-                        word |= ((uint32_t)(int)r & 255u) << (8 * q);
+                    for (int v4 = 0; v4 < 4; ++v4) {
+                        uint32_t word = 0;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            // |r| <= m / 2: a byte for m < 256; for m = 256
+                            // the low byte of r is congruent all the same
+                            const float a = (float)acc[eg][4 * v4 + q];
+                            const float r = fmaf(-rintf(a * invm[cg]), mf[cg], a);
+                            word |= ((uint32_t)(int)r & 255u) << (8 * q);
+                        }
+                        // entries 32 eg + 8 v4 + 4 (lane / 32) + 0..3 of row 4 wave + rw
+                        *(uint32_t*)(plane + (eg * kResRows + wave * 4 + rw) * kCrtTileK + 8 * v4 +
+                                     4 * (lane >> 5)) = word;
                     }
-                    // entries 32 eg + 8 v4 + 4 (lane / 32) + 0..3 of this row
-                    const int64_t l = l0 + 32 * eg + 8 * v4 + 4 * (lane >> 5);
-                    *(uint32_t*)(R + ((plane * nkt + l / kCrtTileK) * Rp + gr) * kCrtTileK + l % kCrtTileK) = word;
+            }
+            __syncthreads();
+            const int nplanes = N - 32 * cg < 32 ? N - 32 * cg : 32;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int pl = 4 * i + wave;
+                if (pl < nplanes) {
+                    const v4i v = *(const v4i*)(lds + pl * kStagePlane + 16 * lane);
+                    const int64_t plane = (int64_t)set * N + 32 * cg + pl;
+                    *(v4i*)(R + ((plane * nkt + 2 * seg + st_kt) * Rp + r0 + st_row) * kCrtTileK + 16 * st_half) = v;
                 }
+            }
+            __syncthreads();
         }
-    }
 }
 
 // ---------------------------------------------------------------------------

@@ -2,8 +2,10 @@
 
 One step = the whole hot path over one batch of synthetic input:
   * for each precision (DD, TD, QD), m = n = k = 4096 with random alpha, beta
-    and C: the plain FP64-VALU EFT GEMM and the split INT8-MFMA GEMM (scale
-    scan, digit slicing, anti-diagonal MFMA sums, recombination, epilogue);
+    and C: the plain FP64-VALU EFT GEMM and the split INT8-MFMA GEMM in both
+    its variants: triangular (scale scan, digit slicing, anti-diagonal MFMA
+    sums, recombination, epilogue) and residue (the same digits, one INT8
+    product per coprime modulus, exact Chinese-remainder reconstruction);
   * the batched persistent form: 512 DD and 512 TD GEMMs with m, n, k uniform
     in 16..512, each set one replay of its captured hipGraph;
 with tile configurations from the autotuner's table.  `value` is the step's
@@ -15,8 +17,8 @@ same error"), the batched form against one launch per problem, the
 roofline of the dominant kernel, and the CPU oracle on this host's cores.
 
 Other workloads (separate JSON lines): --config 3 (QD n = 2048, entries
-u 2^e with e in -30..30 per entry, both forms, slice count from the accuracy
-rule) and --config 4 (DD n = 8192, both forms).
+u 2^e with e in -30..30 per entry, all forms, slice count from the accuracy
+rule) and --config 4 (DD n = 8192, all forms).
 """
 from __future__ import annotations
 
@@ -93,7 +95,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--prec", default="2,3,4")
-    ap.add_argument("--forms", default="plain,split")
+    ap.add_argument("--forms", default="plain,split,crt")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-check", action="store_true", help="skip the sampled error check")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds for the CPU baseline")
@@ -174,9 +176,11 @@ def main():
              "C0": torch.from_numpy(C).to(dev), "alpha": alpha, "beta": beta}
         for f in forms:
             d["C_" + f] = d["C0"].clone()
+        d["s"] = mp.DEFAULT_SLICES[P]
         if "split" in forms:
-            d["s"] = mp.DEFAULT_SLICES[P]
             d["ws"] = mp.alloc_workspace(P, n, n, n, d["s"], device=dev)
+        if "crt" in forms:
+            d["ws_crt"] = mp.alloc_workspace(P, n, n, n, d["s"], device=dev, form="crt")
         devd[P] = d
         note("inputs ready", NAME[P])
     torch.cuda.synchronize()
@@ -207,6 +211,9 @@ def main():
         if f == "plain":
             mp.gemm(P, "N", "N", n, n, n, d["alpha"], d["A"], d["B"], d["beta"], d["C_plain"],
                     form="plain", stream=stream)
+        elif f == "crt":
+            mp.gemm(P, "N", "N", n, n, n, d["alpha"], d["A"], d["B"], d["beta"], d["C_crt"],
+                    form="crt", slices=d["s"], workspace=d["ws_crt"], stream=stream)
         else:
             mp.gemm(P, "N", "N", n, n, n, d["alpha"], d["A"], d["B"], d["beta"], d["C_split"],
                     form="split", slices=d["s"], workspace=d["ws"], stream=stream)
@@ -275,9 +282,15 @@ def main():
             item["fp64_peak_frac"] = n ** 3 * FLOPS_PER_MAC[P] / (ms * 1e-3) / FP64_PEAK
             item["fp64_issue_frac"] = n ** 3 * INSTR_PER_MAC[P] / (ms * 1e-3) / FP64_ISSUE
             item["valu_issue_frac"] = n ** 3 * VALU_PER_MAC[P] / (ms * 1e-3) / FP64_ISSUE
+        elif f == "crt":
+            s = devd[P]["s"]
+            item["slices"] = s
+            item["int8_products"] = mp.crt_moduli(P, n, s)
+            item["int8_ops_frac"] = item["int8_products"] * 2.0 * n ** 3 / (ms * 1e-3) / INT8_PEAK
         else:
             s = devd[P]["s"]
             item["slices"] = s
+            item["int8_products"] = s * (s + 1) // 2
             item["int8_ops_frac"] = s * (s + 1) / 2 * 2.0 * n ** 3 / (ms * 1e-3) / INT8_PEAK
         if (P, f) in errors:
             item["max_err_ratio"] = errors[(P, f)]
@@ -320,9 +333,8 @@ def main():
         ms = item["ms"]
         if key.endswith("_plain"):
             item["fp64_issue_frac_measured"] = n ** 3 * INSTR_PER_MAC[P] / (ms * 1e-3) / peaks["fp64_add_op_s"]
-        elif key.endswith("_split"):
-            s_ = item["slices"]
-            item["int8_ops_frac_measured"] = s_ * (s_ + 1) / 2 * 2.0 * n ** 3 / (ms * 1e-3) / peaks["int8_mfma_op_s"]
+        elif key.endswith("_split") or key.endswith("_crt"):
+            item["int8_ops_frac_measured"] = item["int8_products"] * 2.0 * n ** 3 / (ms * 1e-3) / peaks["int8_mfma_op_s"]
     if roofline is not None:
         roofline["peak_measured"] = round(peaks["fp64_add_op_s"] / 1e12, 2)
         roofline["frac_of_measured"] = round(roofline["achieved"] * 1e12 / peaks["fp64_add_op_s"], 4)
@@ -332,7 +344,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64+i8", "data": "synthetic",
         "config": {"workload": f"square DD/TD/QD GEMM C = alpha*A*B + beta*C, m=n=k={n}, "
-                               "random alpha/beta/C, plain EFT and split INT8-MFMA forms; plus "
+                               "random alpha/beta/C, plain EFT form and the split INT8-MFMA form in "
+                               "both its triangular and its residue (CRT) variant; plus "
                                "batched DD and TD sets of 512 GEMMs with m,n,k ~ U[16,512] "
                                "(one hipGraph replay each)",
                    "m": n, "n": n, "k": n, "precisions": [NAME[P] for P in precs], "forms": forms,
@@ -782,7 +795,7 @@ def other_config(args, mp, synth, dev, stream):
     dB = torch.from_numpy(B).to(dev)
     note("inputs ready", NAME[P], n)
     forms = args.forms.split(",")
-    if cfg == 4 and "crt" not in forms:
+    if "crt" not in forms:
         forms.append("crt")        # the residue form of the split product, too
     if cfg == 3:
         # "same error": the smallest s whose result on a block of rows stays
@@ -838,8 +851,8 @@ def other_config(args, mp, synth, dev, stream):
             note("checked", f, item["err_ratio_max"])
         parts[f"{NAME[P]}_{f}"] = item
     total_ms = sum(v["ms"] for v in parts.values())
-    workload = ("QD GEMM m=n=k=2048, entries u*2^e, e ~ U{-30..30} per entry, both forms, slices "
-                "from the accuracy rule" if cfg == 3 else
+    workload = ("QD GEMM m=n=k=2048, entries u*2^e, e ~ U{-30..30} per entry, plain, split and "
+                "residue (CRT) split forms, slices from the accuracy rule" if cfg == 3 else
                 "DD GEMM m=n=k=8192, plain, split and residue (CRT) split forms")
     out = {"metric": METRIC, "value": 2.0 * n ** 3 * len(parts) / (total_ms * 1e-3), "unit": "2mnk/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -888,6 +901,9 @@ def cpu_baseline(host, precs, forms, n, devd, budget, batched):
                 if f == "plain":
                     oracle.gemm(P, "N", "N", n, n, n, alpha, A, B, beta, C, rows=(0, rows),
                                 cols=(0, cols))
+                elif f == "crt":
+                    oracle.gemm_crt(P, devd[P]["s"], "N", "N", n, n, n, alpha, A, B, beta, C,
+                                    rows=(0, rows), cols=(0, cols))
                 else:
                     oracle.gemm_split(P, devd[P]["s"], "N", "N", n, n, n, alpha, A, B, beta, C,
                                       rows=(0, rows), cols=(0, cols))

@@ -849,6 +849,13 @@ __device__ __forceinline__ void add_shifted(uint32_t (&c)[kLimbsC], const uint32
     }
 }
 
+// Block b takes rows 128 (b % (Mp / 128)) .. + 127 of two columns; it first
+// copies their 3N planes' bytes (256 per plane) into LDS with 16-byte
+// direct-to-LDS copies, all in flight at once, then thread t reconstructs
+// entry (row t % 128, column t / 128).
+constexpr int kRec3Rows = 128;
+constexpr int kRec3MaxN = 33;
+
 template <int P, int SLO>
 __global__ __launch_bounds__(256) void crt_recombine3_kernel(GemmArgs g, const int32_t* __restrict__ E,
                                                              const int32_t* __restrict__ F,
@@ -856,11 +863,27 @@ __global__ __launch_bounds__(256) void crt_recombine3_kernel(GemmArgs g, const i
                                                              int s, int64_t Mp, int64_t Np) {
     constexpr int K = 8;                          // each partial below 2^255 (N <= 33)
     constexpr int w = 7 * SLO;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= g.m * g.n) return;
-    const int64_t i = idx % g.m, j = idx / g.m;
+    constexpr int kChunks = 3 * kRec3MaxN * 2 * kRec3Rows / 16;
+    __shared__ __align__(16) uint8_t ys[3 * kRec3MaxN * 2 * kRec3Rows];
+    const int64_t tiles = Mp / kRec3Rows;
+    const int64_t i0 = (blockIdx.x % tiles) * kRec3Rows, j0 = 2 * (blockIdx.x / tiles);
     const int64_t plane = Mp * Np;
-    const uint8_t* yp = Y + j * Mp + i;
+    const int tid = threadIdx.x, lane = tid & 63;
+    // chunk c = 256 u + t: plane c / 16, column (c / 8) % 2, bytes 16 (c % 8) ..
+    const int nch = 3 * N * 2 * kRec3Rows / 16;
+#pragma unroll
+    for (int u = 0; u < (kChunks + 255) / 256; ++u) {
+        const int c = 256 * u + tid;
+        const int64_t col = j0 + ((c >> 3) & 1);
+        if (c < nch && col < g.n)
+            copy16_to_lds((const int8_t*)(Y + (int64_t)(c >> 4) * plane + col * Mp + i0 + 16 * (c & 7)),
+                          (int8_t*)(ys + 16 * (c - lane)));
+    }
+    wait_vm_all();
+    __syncthreads();
+    const int64_t i = i0 + (tid & (kRec3Rows - 1)), j = j0 + tid / kRec3Rows;
+    if (i >= g.m || j >= g.n) return;
+    const uint8_t* yl = ys + (tid / kRec3Rows) * kRec3Rows + (tid & (kRec3Rows - 1));
     const int row0 = N * (N - 1) / 2;
     uint32_t c[kLimbsC];
 #pragma unroll
@@ -871,21 +894,13 @@ __global__ __launch_bounds__(256) void crt_recombine3_kernel(GemmArgs g, const i
 #pragma unroll
         for (int l = 0; l < K; ++l) L[l] = 0.0;
         double f = 0.0;
-        const uint8_t* ys = yp + (int64_t)set * N * plane;
-        for (int t0 = 0; t0 < N; t0 += 8) {
-            uint32_t yv[8];
+        const uint8_t* yss = yl + set * N * 2 * kRec3Rows;
+        for (int tm = 0; tm < N; ++tm) {
+            const double y = (double)yss[tm * 2 * kRec3Rows];
+            f = fma(y, kCrtDev.inv[tm], f);
+            const double* wl = kCrtDev.Wd[row0 + tm];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) yv[u] = (t0 + u < N) ? ys[(int64_t)(t0 + u) * plane] : 0u;
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int t = t0 + u;
-                if (t >= N) break;
-                const double y = (double)yv[u];
-                f = fma(y, kCrtDev.inv[t], f);
-                const double* wl = kCrtDev.Wd[row0 + t];
-#pragma unroll
-                for (int l = 0; l < K; ++l) L[l] = fma(y, wl[l], L[l]);
-            }
+            for (int l = 0; l < K; ++l) L[l] = fma(y, wl[l], L[l]);
         }
         const double q = rint(f);
         uint32_t x[K];
@@ -1138,7 +1153,8 @@ int launch_crt(int P, int s, int cfg, const GemmArgs& g, void* ws, hipStream_t s
         return rc;
     if ((rc = launch_crt_mfma(cfg, RA, RB, Y, L.Mp, L.Np, L.Kp, N * pl.sets, N, st))) return rc;
     if (pl.sets == 3) {
-        const int64_t blocks = (g.m * g.n + 255) / 256;
+        if (N > kRec3MaxN) return (int)hipErrorInvalidValue;
+        const int64_t blocks = L.Mp / kRec3Rows * ((g.n + 1) / 2);
         if (blocks > 0x7fffffffLL) return (int)hipErrorInvalidConfiguration;
         const dim3 grid((unsigned)blocks);
 #define MPG_REC3(SL) \

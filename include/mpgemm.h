@@ -65,8 +65,11 @@ extern "C" {
 #define MPGEMM_FORM_SPLIT_I8 1  /* operands cut into signed 7-bit INT8 digits,
                                    exact INT8 MFMA digit products, exact
                                    recombination into P components          */
-#define MPGEMM_FORM_AUTO 2      /* tuned choice between the two (plain when
-                                   no workspace is given)                   */
+#define MPGEMM_FORM_AUTO 2      /* the library's choice: for m, n, k >= 256
+                                   the residue form (MPGEMM_FORM_SPLIT_CRT)
+                                   when the workspace holds it and it
+                                   applies, else the split form when the
+                                   workspace holds that, else plain        */
 #define MPGEMM_FORM_STRASSEN 4  /* Strassen's method (Sec. 3, Fig. 5): opts.levels
                                    levels of the seven-product recursion over
                                    plain-form block products               */
@@ -207,7 +210,8 @@ int mpgemm_crt_moduli(int prec, int64_t k, int slices);
 
 /* Workspace bytes the split forms (MPGEMM_FORM_SPLIT_I8, _AUTO, _SPLIT_CRT)
  * need for this shape (0 for the plain form; for the residue form also 0 when
- * no modulus count suffices; slices 0 = default; tile -1 = the one the
+ * no modulus count suffices; for _AUTO the larger of the two split forms'
+ * needs, so that either fits; slices 0 = default; tile -1 = the one the
  * library would pick); for
  * MPGEMM_FORM_STRASSEN, `slices` is the number of levels L (0 = 1) and the
  * result is 8 P (m n + sum over l = 1..L of 7^l (m k + k n + m n) / 4^l)

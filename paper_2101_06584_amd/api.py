@@ -95,12 +95,12 @@ def workspace_bytes(prec, form, m, n, k, slices=0, tile=-1) -> int:
 
 def alloc_workspace(prec, m, n, k, slices=0, tile=-1, device=None, form="split", levels=0) -> torch.Tensor:
     """Device workspace for the split form (slices, tile), with form="crt"
-    for its residue form, or with form="strassen" for `levels` levels of
-    Strassen's method."""
+    for its residue form, form="auto" for either, or with form="strassen" for
+    `levels` levels of Strassen's method."""
     if form == "strassen":
         nbytes = workspace_bytes(prec, "strassen", m, n, k, levels, -1)
-    elif form == "crt":
-        nbytes = workspace_bytes(prec, "crt", m, n, k, slices, tile)
+    elif form in ("crt", "auto"):
+        nbytes = workspace_bytes(prec, form, m, n, k, slices, tile)
     else:
         nbytes = workspace_bytes(prec, "split", m, n, k, slices, tile)
     return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device or "cuda")

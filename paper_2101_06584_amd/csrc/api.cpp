@@ -232,6 +232,13 @@ int gemm_common(int P, char ta, char tb, int64_t m, int64_t n, int64_t k, const 
     const int s = (has_opts && opts->slices > 0) ? opts->slices : kDefaultSlices[P];
     const int req_tile = has_opts ? opts->tile : -1;
     if (last_stage > 0) form = MPGEMM_FORM_SPLIT_I8;
+    if (form == MPGEMM_FORM_AUTO && m >= 256 && n >= 256 && k >= 256 && opts->workspace &&
+        (uintptr_t)opts->workspace % 256 == 0 && crt_products(P, k, s) > 0) {
+        // the residue form first: the fastest split variant wherever it applies
+        const int cfg = pick_tile(P, MPGEMM_FORM_SPLIT_CRT, m, n, k, req_tile);
+        if (opts->workspace_bytes >= crt_workspace_bytes(P, m, n, k, s, cfg))
+            return hip_rc(launch_crt(P, s, cfg, g, opts->workspace, st));
+    }
     if (form == MPGEMM_FORM_AUTO) {
         const bool fits = opts->workspace &&
                           opts->workspace_bytes >= split_workspace_bytes(
@@ -293,7 +300,13 @@ size_t mpgemm_workspace_bytes(int prec, int form, int64_t m, int64_t n, int64_t 
     if (form != MPGEMM_FORM_SPLIT_I8 && form != MPGEMM_FORM_AUTO) return 0;
     const int s = slices > 0 ? slices : kDefaultSlices[prec];
     const int cfg = pick_tile(prec, MPGEMM_FORM_SPLIT_I8, m, n, k, tile);
-    return split_workspace_bytes(prec, m, n, k, s, cfg);
+    const size_t split = split_workspace_bytes(prec, m, n, k, s, cfg);
+    if (form == MPGEMM_FORM_AUTO && crt_products(prec, k, s) > 0) {
+        // room for either split variant
+        const size_t crt = crt_workspace_bytes(prec, m, n, k, s, pick_tile(prec, MPGEMM_FORM_SPLIT_CRT, m, n, k, tile));
+        return crt > split ? crt : split;
+    }
+    return split;
 }
 
 int mpgemm_crt_moduli(int prec, int64_t k, int slices) {

@@ -138,6 +138,18 @@ def test_crt_form_host_rules():
     assert L.mpgemm_crt_moduli(7, 10, 0) == -1
 
 
+def test_auto_form_workspace_fits_either_split_form():
+    """FORM_AUTO's workspace is the larger of the two split forms' needs
+    (the residue form's where it applies, the triangular form's elsewhere)."""
+    for P, m, n, k, s in [(2, 256, 256, 256, 0), (3, 1000, 300, 700, 0), (4, 512, 512, 512, 0),
+                          (2, 300, 300, 4096, 20), (4, 256, 256, 256, 33)]:
+        split = mp.workspace_bytes(P, "split", m, n, k, s)
+        crt = mp.workspace_bytes(P, "crt", m, n, k, s)
+        assert mp.workspace_bytes(P, "auto", m, n, k, s) == max(split, crt), (P, m, n, k, s)
+    assert mp.workspace_bytes(4, "crt", 256, 256, 256, 33) == 0          # no residue form: split's
+    assert mp.workspace_bytes(4, "auto", 256, 256, 256, 33) == mp.workspace_bytes(4, "split", 256, 256, 256, 33)
+
+
 def test_vec_validation():
     L = mp.load()
     assert L.mp_vec_td_add(-1, None, 0, None, 0, None, 0, None) == -1

@@ -133,3 +133,33 @@ def test_repeat_and_workspace_reuse(gpu_lib):
         gpu_lib.gemm(P, "T", "N", m, n, k, alpha, dev(A), dev(B), beta, dev(C), form="crt", slices=s,
                      tile=0, workspace=small)
     assert e.value.code == 2
+
+
+def test_auto_form_choice(gpu_lib):
+    """FORM_AUTO: the residue form when the workspace holds it, the
+    triangular split form when only that fits, the plain form with no
+    workspace or below 256 in any dimension -- each bit for bit as the
+    oracle's form."""
+    import torch
+    P, m, n, k = 2, 256, 260, 300
+    A, B, C, alpha, beta = make(P, "N", "N", m, n, k, cfg=7)
+    s = gpu_lib.DEFAULT_SLICES[P]
+    split_b = gpu_lib.workspace_bytes(P, "split", m, n, k, s)
+    crt_b = gpu_lib.workspace_bytes(P, "crt", m, n, k, s)
+    assert crt_b > split_b > 0
+    assert gpu_lib.workspace_bytes(P, "auto", m, n, k, s) == crt_b
+
+    def call(ws, mm=m):
+        dC = dev(C)
+        gpu_lib.gemm(P, "N", "N", mm, n, k, alpha, dev(A), dev(B), beta, dC, form="auto", slices=s,
+                     workspace=ws)
+        return host(dC)
+
+    big = gpu_lib.alloc_workspace(P, m, n, k, s, form="auto")
+    small = torch.empty(split_b, dtype=torch.uint8, device="cuda")
+    note("auto: residue, split, plain", P, (m, n, k))
+    assert np.array_equal(call(big), oracle.gemm_crt(P, s, "N", "N", m, n, k, alpha, A, B, beta, C))
+    assert np.array_equal(call(small), oracle.gemm_split(P, s, "N", "N", m, n, k, alpha, A, B, beta, C))
+    assert np.array_equal(call(None), oracle.gemm(P, "N", "N", m, n, k, alpha, A, B, beta, C))
+    # m = 255 (lda stays 256): plain even with room for both split forms
+    assert np.array_equal(call(big, 255), oracle.gemm(P, "N", "N", 255, n, k, alpha, A, B, beta, C))

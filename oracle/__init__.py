@@ -65,6 +65,19 @@ def lib():
     return _LIB
 
 
+def _check_gemm(P, ta, tb, m, n, k, A, B, C):
+    """The stored planes must hold op(A) (m x k), op(B) (k x n) and C (m x n):
+    (P, cols, ld) with ld >= rows; the C code trusts these sizes."""
+    def need(X, name, rows, cols):
+        if X.ndim != 3 or X.shape[0] != P:
+            raise ValueError(f"{name}: expected (P={P}, cols, ld), got {X.shape}")
+        if rows > 0 and cols > 0 and (X.shape[2] < rows or X.shape[1] < cols):
+            raise ValueError(f"{name}: {X.shape} cannot hold {rows} x {cols}")
+    need(A, "A", *((m, k) if ta in "Nn" else (k, m)))
+    need(B, "B", *((k, n) if tb in "Nn" else (n, k)))
+    need(C, "C", m, n)
+
+
 def _ptr(a):
     return a.ctypes.data_as(C.c_void_p)
 
@@ -115,6 +128,7 @@ def gemm(P, ta, tb, m, n, k, alpha, A, B, beta, C, rows=None, cols=None, nthread
     A = _f64(A)
     B = _f64(B)
     Cout = _f64(C).copy()
+    _check_gemm(P, ta, tb, m, n, k, A, B, Cout)
     alpha = _f64(alpha)
     beta = _f64(beta)
     r0, r1 = rows if rows is not None else (0, -1)
@@ -168,6 +182,7 @@ def gemm_strassen(P, levels, ta, tb, m, n, k, alpha, A, B, beta, C):
     A = _f64(A)
     B = _f64(B)
     Cout = _f64(C).copy()
+    _check_gemm(P, ta, tb, m, n, k, A, B, Cout)
     alpha = _f64(alpha)
     beta = _f64(beta)
     rc = lib().ref_gemm_strassen(P, levels, ta.encode(), tb.encode(), m, n, k, _ptr(alpha), _ptr(A),
@@ -185,6 +200,7 @@ def gemm_crt(P, s, ta, tb, m, n, k, alpha, A, B, beta, C, rows=None, cols=None, 
     A = _f64(A)
     B = _f64(B)
     Cout = _f64(C).copy()
+    _check_gemm(P, ta, tb, m, n, k, A, B, Cout)
     alpha = _f64(alpha)
     beta = _f64(beta)
     r0, r1 = rows if rows is not None else (0, -1)
@@ -204,6 +220,7 @@ def gemm_split(P, s, ta, tb, m, n, k, alpha, A, B, beta, C, rows=None, cols=None
     A = _f64(A)
     B = _f64(B)
     Cout = _f64(C).copy()
+    _check_gemm(P, ta, tb, m, n, k, A, B, Cout)
     alpha = _f64(alpha)
     beta = _f64(beta)
     r0, r1 = rows if rows is not None else (0, -1)

@@ -135,13 +135,14 @@ def test_repeat_and_workspace_reuse(gpu_lib):
     assert e.value.code == 2
 
 
-def test_auto_form_choice(gpu_lib):
+@pytest.mark.parametrize("P", [2, 3, 4])
+def test_auto_form_choice(gpu_lib, P):
     """FORM_AUTO: the residue form when the workspace holds it, the
     triangular split form when only that fits, the plain form with no
     workspace or below 256 in any dimension -- each bit for bit as the
     oracle's form."""
     import torch
-    P, m, n, k = 2, 256, 260, 300
+    m, n, k = 256, 260, 300
     A, B, C, alpha, beta = make(P, "N", "N", m, n, k, cfg=7)
     s = gpu_lib.DEFAULT_SLICES[P]
     split_b = gpu_lib.workspace_bytes(P, "split", m, n, k, s)

@@ -378,7 +378,7 @@ __global__ __launch_bounds__(64 * WGM * WGN, 2) void crt_mfma_kernel(const int8_
                                                                      const int8_t* __restrict__ RB,
                                                                      uint8_t* __restrict__ Y, int64_t Mp,
                                                                      int64_t Np, int64_t Kp, int N,
-                                                                     int Nmod) {
+                                                                     int Nmod, int mods) {
     using T = CrtDma<BM, BN, WGM, WGN, D>;
     __shared__ __attribute__((aligned(1024))) int8_t lds[T::LDS_BYTES];
 
@@ -390,7 +390,10 @@ __global__ __launch_bounds__(64 * WGM * WGN, 2) void crt_mfma_kernel(const int8_
     const int wm = wave % WGM, wn = wave / WGM;
     const int wave_lds = __builtin_amdgcn_readfirstlane(wave) * 1024;
     const int nkt = (int)(Kp / kCrtTileK);
-    const int steps = N * nkt;
+    // this workgroup's planes: mod0 .. mod1 - 1 (blockIdx.y < ceil(N / mods))
+    const int mod0 = (int)blockIdx.y * mods;
+    const int mod1 = mod0 + mods < N ? mod0 + mods : N;
+    const int steps = (mod1 - mod0) * nkt;
     const int64_t stepA = Mp * kCrtTileK, stepB = Np * kCrtTileK;
 
     // this lane's global byte offset within a tile for its h-th copy round:
@@ -413,8 +416,8 @@ __global__ __launch_bounds__(64 * WGM * WGN, 2) void crt_mfma_kernel(const int8_
     // fetch cursor: the next step to copy; past the last step it stays on the
     // last tiles (re-copied into slots no step reads), so every step issues
     // the same number of copies, all in bounds
-    const int8_t* fa = RA + m0 * kCrtTileK;
-    const int8_t* fb = RB + n0 * kCrtTileK;
+    const int8_t* fa = RA + (int64_t)mod0 * nkt * stepA + m0 * kCrtTileK;
+    const int8_t* fb = RB + (int64_t)mod0 * nkt * stepB + n0 * kCrtTileK;
     int fstep = 0, fslot = 0;
     auto issue = [&]() __attribute__((always_inline)) {
         int8_t* la = lds + fslot * T::STAGE + wave_lds;
@@ -437,7 +440,7 @@ __global__ __launch_bounds__(64 * WGM * WGN, 2) void crt_mfma_kernel(const int8_
 
     for (int r = 0; r < D - 1; ++r) issue();
 
-    int cslot = 0, kt = 0, mod = 0;
+    int cslot = 0, kt = 0, mod = mod0;
     for (int u = 0; u < steps; ++u) {
         // step u's tiles are in; every wave is past step u - 1, whose slot is
         // refilled now
@@ -540,7 +543,7 @@ __global__ __launch_bounds__(256, 1) void crt_mfma_wide_kernel(const int8_t* __r
                                                                const int8_t* __restrict__ RB,
                                                                uint8_t* __restrict__ Y, int64_t Mp,
                                                                int64_t Np, int64_t Kp, int N,
-                                                               int Nmod) {
+                                                               int Nmod, int mods) {
     using W = WideCfg<KH>;
     constexpr int D = W::D;
     __shared__ __attribute__((aligned(1024))) int8_t lds[W::LDS_BYTES];
@@ -553,7 +556,10 @@ __global__ __launch_bounds__(256, 1) void crt_mfma_wide_kernel(const int8_t* __r
     const int wm = wave % 2, wn = wave / 2;
     const int wave_lds = __builtin_amdgcn_readfirstlane(wave) * 1024;
     const int spm = (int)(Kp / kCrtTileK) / KH;   // steps per modulus, even (Kp % (64 KH) == 0)
-    const int steps = N * spm;
+    // this workgroup's planes: mod0 .. mod1 - 1 (blockIdx.y < ceil(N / mods))
+    const int mod0 = (int)blockIdx.y * mods;
+    const int mod1 = mod0 + mods < N ? mod0 + mods : N;
+    const int steps = (mod1 - mod0) * spm;
     const int64_t tileA = Mp * kCrtTileK, tileB = Np * kCrtTileK;
 
     int gofs[W::LOADS];
@@ -569,8 +575,8 @@ __global__ __launch_bounds__(256, 1) void crt_mfma_wide_kernel(const int8_t* __r
 #pragma unroll
     for (int jj = 0; jj < W::FN; ++jj) bofs[jj] = W::B_OFF + swz32(wn * W::WN + jj * 32 + (lane & 31), lane >> 5);
 
-    const int8_t* fa = RA + m0 * kCrtTileK;
-    const int8_t* fb = RB + n0 * kCrtTileK;
+    const int8_t* fa = RA + (int64_t)mod0 * spm * KH * tileA + m0 * kCrtTileK;
+    const int8_t* fb = RB + (int64_t)mod0 * spm * KH * tileB + n0 * kCrtTileK;
     int fstep = 0, fslot = 0;
     auto issue = [&]() __attribute__((always_inline)) {
         int8_t* la = lds + fslot * W::STAGE + wave_lds;
@@ -630,7 +636,7 @@ __global__ __launch_bounds__(256, 1) void crt_mfma_wide_kernel(const int8_t* __r
     };
     const int64_t ybase = (n0 + wn * W::WN + (lane & 31)) * Mp + m0 + wm * W::WM + 4 * (lane >> 5);
     int u = 0;
-    for (int mod = 0; mod < N; ++mod) {
+    for (int mod = mod0; mod < mod1; ++mod) {
         for (int kk = 0; kk < spm; kk += 2, u += 2) {
             step(std::integral_constant<int, 0>{}, u);
             step(std::integral_constant<int, 1>{}, u + 1);
@@ -1020,22 +1026,39 @@ int launch_residues(int P, int sets, const double* X, int64_t rs, int64_t ls, in
     return (int)hipGetLastError();
 }
 
+// Workgroups per output tile: with fewer tiles than workgroup slots on the
+// chip the planes are shared out over several workgroups per tile (each
+// writes its own planes), so that small products still fill the CUs.
+struct CrtGroups {
+    int groups, mods;                              // grid.y, planes per workgroup
+};
+CrtGroups crt_groups(int64_t tiles, int per_cu, int planes) {
+    const int64_t slots = 256 * (int64_t)per_cu;
+    int64_t g = tiles > 0 ? (slots + tiles - 1) / tiles : 1;
+    g = g < 1 ? 1 : (g > planes ? planes : g);
+    const int mods = (int)((planes + g - 1) / g);
+    return {(planes + mods - 1) / mods, mods};
+}
+
 int launch_crt_mfma(int cfg, const int8_t* RA, const int8_t* RB, uint8_t* Y, int64_t Mp, int64_t Np,
                     int64_t Kp, int N, int Nmod, hipStream_t st) {
     const CrtConfig c = kCrt[cfg];
-    const int64_t grid = xcd_grid((Mp / c.bm) * (Np / c.bn));
+    const int64_t tiles = (Mp / c.bm) * (Np / c.bn);
+    const int64_t grid = xcd_grid(tiles);
     if (grid > 0x7fffffffLL) return (int)hipErrorInvalidConfiguration;
+    const CrtGroups gr = crt_groups(tiles, c.per_cu, N);
+    const dim3 blocks((unsigned)grid, (unsigned)gr.groups);
     // ring depths: the LDS of one CU (160 KiB) holds one wide workgroup's
     // ring or two of the others
     if (cfg == 0)
-        hipLaunchKernelGGL(crt_mfma_wide_kernel<1>, dim3((unsigned)grid), dim3(256), 0, st, RA, RB, Y, Mp, Np,
-                           Kp, N, Nmod);
+        hipLaunchKernelGGL(crt_mfma_wide_kernel<1>, blocks, dim3(256), 0, st, RA, RB, Y, Mp, Np, Kp, N, Nmod,
+                           gr.mods);
     else if (cfg == 1)
-        hipLaunchKernelGGL((crt_mfma_kernel<256, 128, 2, 2, 6>), dim3((unsigned)grid), dim3(256), 0, st, RA,
-                           RB, Y, Mp, Np, Kp, N, Nmod);
+        hipLaunchKernelGGL((crt_mfma_kernel<256, 128, 2, 2, 6>), blocks, dim3(256), 0, st, RA, RB, Y, Mp, Np,
+                           Kp, N, Nmod, gr.mods);
     else
-        hipLaunchKernelGGL((crt_mfma_kernel<128, 128, 2, 2, 8>), dim3((unsigned)grid), dim3(256), 0, st, RA,
-                           RB, Y, Mp, Np, Kp, N, Nmod);
+        hipLaunchKernelGGL((crt_mfma_kernel<128, 128, 2, 2, 8>), blocks, dim3(256), 0, st, RA, RB, Y, Mp, Np,
+                           Kp, N, Nmod, gr.mods);
     return (int)hipGetLastError();
 }
 
@@ -1057,16 +1080,18 @@ int launch_crt_recombine_p(int K, dim3 grid, hipStream_t st, const GemmArgs& g, 
 }  // namespace
 
 int crt_default_config(int64_t m, int64_t n) {
-    // rounds of resident workgroups times one workgroup's tile time, with
-    // the measured relative throughput of each tile shape per CU
+    // rounds of resident workgroups times one workgroup's time (its tile
+    // over its share of the planes, 32 taken as typical), with the measured
+    // relative throughput of each tile shape per CU
     const double eff[kCrtConfigs] = {1.0, 0.9, 0.6};
     int best = 0;
     double best_cost = 0.0;
     for (int c = 0; c < kCrtConfigs; ++c) {
         const int64_t tiles = ((m + kCrt[c].bm - 1) / kCrt[c].bm) * ((n + kCrt[c].bn - 1) / kCrt[c].bn);
         const int64_t slots = 256 * kCrt[c].per_cu;
-        const double rounds = (double)((tiles + slots - 1) / slots);
-        const double cost = rounds * kCrt[c].bm * kCrt[c].bn * kCrt[c].per_cu / eff[c];
+        const CrtGroups gr = crt_groups(tiles, kCrt[c].per_cu, 32);
+        const double rounds = (double)((tiles * gr.groups + slots - 1) / slots);
+        const double cost = rounds * kCrt[c].bm * kCrt[c].bn * gr.mods * kCrt[c].per_cu / eff[c];
         if (c == 0 || cost < best_cost) {
             best = c;
             best_cost = cost;

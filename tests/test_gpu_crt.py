@@ -114,6 +114,22 @@ def test_full_size_sampled(gpu_lib, P):
     assert r.max() <= 8 * (n + 2) / n
 
 
+@pytest.mark.parametrize("P,m,n,k,s,tile", [
+    (2, 1100, 1100, 300, 16, 0),    # 25 tiles: 31 planes in 11 groups of 3 (the last holds 1)
+    (4, 700, 700, 200, 31, 2),      # 36 tiles: 93 planes (two levels) in 14 groups of 7 (last 2)
+])
+def test_planes_shared_out_over_workgroups(gpu_lib, P, m, n, k, s, tile):
+    """Few output tiles: each tile's planes are split over several
+    workgroups (an uneven last share); sampled blocks bit for bit."""
+    A, B, C, alpha, beta = make(P, "N", "N", m, n, k, cfg=8)
+    note("crt plane groups", P, (m, n, k), "s", s, "tile", tile)
+    got = run(gpu_lib, P, "N", "N", m, n, k, alpha, A, B, beta, C, s, tile)
+    for rows, cols in [((0, 40), (0, 24)), ((m - 33, m), (n - 17, n)), ((300, 310), (500, 520))]:
+        want = oracle.gemm_crt(P, s, "N", "N", m, n, k, alpha, A, B, beta, C, rows=rows, cols=cols)
+        blk = (slice(None), slice(*cols), slice(*rows))
+        assert np.array_equal(got[blk], want[blk]), (rows, cols)
+
+
 def test_repeat_and_workspace_reuse(gpu_lib):
     """Deterministic: repeated calls, a larger reused workspace and both
     tile configurations give the same bits."""

@@ -174,7 +174,7 @@ int mpgemm_qd(char transa, char transb, int64_t m, int64_t n, int64_t k, const d
  * 14 s + log2 k (DD, s = 16: at most 32 moduli; TD, s = 23: 48 for k <= 2^13,
  * 49 above).  QD with 25 <= s <= 32 digits (its default s = 31 included), where
  * 49 moduli do not suffice, cuts each digit integer into a high half of
- * ceil(s/2) digits and a low half, A' = A_h 128^(s/2) + A_l, and forms C' =
+ * ceil(s/2) digits and a low half, A' = A_h 128^floor(s/2) + A_l, and forms C' =
  * hh 128^(2 floor(s/2)) + (ss - hh - ll) 128^floor(s/2) + ll from the three
  * half-size products hh = A_h B_h, ll = A_l B_l, ss = (A_h + A_l)(B_h + B_l),
  * each from N <= 33 moduli: the same integer, so the same result.

@@ -778,56 +778,151 @@ __device__ __forceinline__ void crt_finish_entry(const GemmArgs& g, double (&L)[
     for (int p = 0; p < P; ++p) g.C[p * g.sc + off] = t.c[p];
 }
 
-// Thread (i4, j) handles rows 4 i4 .. 4 i4 + 3 of column j: one 32-bit load
-// per modulus brings their four residues.  S = sum_t y_t (M / m_t) limb by
-// limb (each limb sum < 2^46, exact in binary64) and f = sum_t y_t / m_t,
-// whose nearest integer q gives C' = S - q M.
-template <int P, int K>
-__global__ __launch_bounds__(256) void crt_recombine_kernel(GemmArgs g, const int32_t* __restrict__ E,
-                                                            const int32_t* __restrict__ F,
-                                                            const uint8_t* __restrict__ Y, int N,
-                                                            int s, int64_t Mp, int64_t Np) {
-    const int64_t quads = Mp / 4;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= quads * g.n) return;
-    const int64_t i0 = 4 * (idx % quads), j = idx / quads;
-    if (i0 >= g.m) return;
-    const int64_t plane = Mp * Np;
-    const uint32_t* yp = (const uint32_t*)(Y + j * Mp + i0);
-    const int row0 = N * (N - 1) / 2;
+// Rows of a reconstruction block (two columns of them) and the largest
+// modulus count per level of the two-level reconstruction.
+constexpr int kRec3Rows = 128;
+constexpr int kRec3MaxN = 33;
 
-    double L[4][K], f[4];
+// One level: S = sum_t y_t W_t with the cofactors W_t = M / m_t in K 32-bit
+// limbs, limb sums L_l = sum_t y_t W_t[l] (each < 2^46), q = nearest integer
+// to S / M, C' = S - q M.  The limb sums run on the matrix cores: with
+// y' = y - 128 and b' = b - 128 (signed bytes) for the bytes b_tc of W_t
+// (byte c of its limbs), sum_t y_t b_tc = Z_c + 128 (Y + B'_c), where
+// Z_c = sum_t y'_t b'_tc is one INT8 product (digit column c x entry, the
+// moduli as inner dimension; rows of moduli t >= N are zero), Y = sum_t y_t
+// (byte sums) and B'_c = sum_t b'_tc (per N, from the host, folded into kc).
+// So L_l = sum_q (Z_{4l+q} + 128 Y) 256^q + kc_l, every part an integer below
+// 2^47, exact in binary64; q from S / M = sum_l L_l r_l with r_l = 2^(32 l) /
+// M (S / M lies at least 0.003 from a half-integer, and the error of this sum
+// is below 2^-45).  Block b takes rows 128 (b % (Mp / 128))
+// .. + 127 of two columns; their N planes' bytes come into LDS by 16-byte
+// direct-to-LDS copies.  Wave w forms entries 64 w .. 64 w + 63 in two groups
+// of 32; lane L ends with entry 64 w + L (the two halves of the wave trade
+// the limbs of opposite parity).
+struct CrtRecConsts {
+    double kc[kLimbs];               // 128 sum_q B'_{4l+q} 256^q
+    double r[kLimbs];                // 2^(32 l) / M_N
+};
+
+template <int P, int K, int NKB>
+__global__ __launch_bounds__(256) void crt_recombine_mfma_kernel(GemmArgs g, const int32_t* __restrict__ E,
+                                                                 const int32_t* __restrict__ F,
+                                                                 const uint8_t* __restrict__ Y, int N, int s,
+                                                                 int64_t Mp, int64_t Np, CrtRecConsts rc) {
+    constexpr int NCB = (4 * K + 31) / 32;       // blocks of 32 digit columns
+    constexpr int kChunks = kNumModuli * 2 * kRec3Rows / 16;
+    __shared__ __align__(16) uint8_t ys[kNumModuli * 2 * kRec3Rows];
+    const int64_t tiles = Mp / kRec3Rows;
+    const int64_t i0 = (blockIdx.x % tiles) * kRec3Rows, j0 = 2 * (blockIdx.x / tiles);
+    const int64_t plane = Mp * Np;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int hi = lane >> 5;
+    // chunk c = 256 u + tid: plane c / 16, column (c / 8) % 2, bytes 16 (c % 8) ..
+    const int nch = N * 2 * kRec3Rows / 16;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        f[r] = 0.0;
-#pragma unroll
-        for (int l = 0; l < K; ++l) L[r][l] = 0.0;
+    for (int u = 0; u < (kChunks + 255) / 256; ++u) {
+        const int c = 256 * u + tid;
+        const int64_t col = j0 + ((c >> 3) & 1);
+        if (c < nch && col < g.n)
+            copy16_to_lds((const int8_t*)(Y + (int64_t)(c >> 4) * plane + col * Mp + i0 + 16 * (c & 7)),
+                          (int8_t*)(ys + 16 * (c - lane)));
     }
-    // moduli in groups of eight: their loads are in flight together
-    for (int t0 = 0; t0 < N; t0 += 8) {
-        uint32_t y4[8];
+    // the cofactor bytes b'_tc in LDS, digit column major (bt[c][t], zero for
+    // t >= N): limb l of W_t is columns 4 l .. 4 l + 3
+    constexpr int kCols = 32 * NCB, kMods = 32 * NKB;
+    __shared__ __align__(16) uint8_t bt[kCols * kMods];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) y4[u] = (t0 + u < N) ? yp[(t0 + u) * (plane / 4)] : 0u;
+    for (int o = 16 * tid; o < kCols * kMods; o += 16 * 256) *(v4i*)(bt + o) = v4i{0, 0, 0, 0};
+    __syncthreads();
+    const uint32_t* wrow = kCrtDev.W[N * (N - 1) / 2];
+    for (int e = tid; e < N * K; e += 256) {
+        const int t = e / K, l = e % K;
+        const uint32_t w = wrow[t * kLimbs + l] ^ 0x80808080u;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int t = t0 + u;
-            if (t >= N) break;
-            const double inv = kCrtDev.inv[t];
-            const double* w = kCrtDev.Wd[row0 + t];
+        for (int q = 0; q < 4; ++q) bt[(4 * l + q) * kMods + t] = (uint8_t)(w >> (8 * q));
+    }
+    wait_vm_all();
+    __syncthreads();
+    // A fragments: digit column 32 cb + L % 32, moduli 32 kb + 16 (L / 32) + 0..15
+    v4i af[NCB][NKB];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const double y = (double)((y4[u] >> (8 * r)) & 255u);
-                f[r] = fma(y, inv, f[r]);
+    for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-                for (int l = 0; l < K; ++l) L[r][l] = fma(y, w[l], L[r][l]);
+        for (int kb = 0; kb < NKB; ++kb)
+            af[cb][kb] = *(const v4i*)(bt + (32 * cb + (lane & 31)) * kMods + 32 * kb + 16 * hi);
+    // B fragments (y' of entry 64 w + 32 grp + L % 32, the same moduli) and
+    // the byte sums of this lane's moduli
+    v16i acc[2][NCB];
+    uint32_t ysum[2];
+#pragma unroll
+    for (int grp = 0; grp < 2; ++grp) {
+        const int eb = 64 * wave + 32 * grp + (lane & 31);
+        uint32_t sum = 0u;
+        v4i bf[NKB];
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb) {
+            uint32_t w4[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) {
+                const int t = 32 * kb + 16 * hi + jj;
+                const uint32_t y = t < N ? ys[t * 2 * kRec3Rows + eb] : 0u;
+                w4[jj / 4] |= y << (8 * (jj % 4));
             }
+#pragma unroll
+            for (int d = 0; d < 4; ++d) sum = __builtin_amdgcn_sad_u8(w4[d], 0u, sum);
+            bf[kb] = v4i{(int)(w4[0] ^ 0x80808080u), (int)(w4[1] ^ 0x80808080u), (int)(w4[2] ^ 0x80808080u),
+                         (int)(w4[3] ^ 0x80808080u)};
+        }
+        ysum[grp] = sum;
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            acc[grp][cb] = v16i{0};
+#pragma unroll
+            for (int kb = 0; kb < NKB; ++kb)
+                acc[grp][cb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[cb][kb], bf[kb], acc[grp][cb], 0, 0, 0);
         }
     }
-    const int32_t ef = F[j] - 14 * s;
-    static_for<4>([&](auto rc) __attribute__((always_inline)) {
-        constexpr int r = decltype(rc)::value;
-        if (i0 + r < g.m) crt_finish_entry<P, K>(g, L[r], f[r], N, E[i0 + r] + ef, i0 + r, j);
-    });
+    // this lane's limbs of each group: value 4 v + q of column block cb is
+    // digit column 32 cb + 8 v + 4 (L / 32) + q, so limb 8 cb + 2 v + L / 32
+    double lh[2][4 * NCB];
+#pragma unroll
+    for (int grp = 0; grp < 2; ++grp) {
+        const uint32_t yt = ysum[grp] + (uint32_t)__shfl_xor((int)ysum[grp], 32, 64);
+        const double yk = 128.0 * 16843009.0 * (double)yt;         // 128 Y (1 + 256 + 256^2 + 256^3)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int le = 8 * cb + 2 * v;               // even limb; this lane's is le + hi
+                if (le >= K) continue;
+                const double kc = hi ? (le + 1 < K ? rc.kc[le + 1] : 0.0) : rc.kc[le];
+                const v16i& a = acc[grp][cb];
+                double z = fma((double)a[4 * v + 3], 256.0, (double)a[4 * v + 2]);
+                z = fma(z, 256.0, (double)a[4 * v + 1]);
+                z = fma(z, 256.0, (double)a[4 * v]);
+                lh[grp][4 * cb + v] = z + yk + kc;
+            }
+    }
+    // lanes L < 32 keep group 0 (entry 64 w + L), lanes L >= 32 group 1
+    // (entry 64 w + L as well): trade the limbs of the other parity
+    double L[K];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int le = 8 * cb + 2 * v;
+            if (le >= K) continue;
+            const double mine = hi ? lh[1][4 * cb + v] : lh[0][4 * cb + v];
+            const double other = __shfl_xor(hi ? lh[0][4 * cb + v] : lh[1][4 * cb + v], 32, 64);
+            L[le] = hi ? other : mine;
+            if (le + 1 < K) L[le + 1] = hi ? mine : other;
+        }
+    const int64_t i = i0 + (tid & (kRec3Rows - 1)), j = j0 + tid / kRec3Rows;
+    if (i >= g.m || j >= g.n) return;
+    double f = 0.0;
+#pragma unroll
+    for (int l = 0; l < K; ++l) f = fma(L[l], rc.r[l], f);
+    crt_finish_entry<P, K>(g, L, f, N, E[i] + F[j] - 14 * s, i, j);
 }
 
 // Two levels (digit integers cut into a high and a low half, A' = A_h 2^w +
@@ -859,8 +954,6 @@ __device__ __forceinline__ void add_shifted(uint32_t (&c)[kLimbsC], const uint32
 // copies their 3N planes' bytes (256 per plane) into LDS with 16-byte
 // direct-to-LDS copies, all in flight at once, then thread t reconstructs
 // entry (row t % 128, column t / 128).
-constexpr int kRec3Rows = 128;
-constexpr int kRec3MaxN = 33;
 
 template <int P, int SLO>
 __global__ __launch_bounds__(256) void crt_recombine3_kernel(GemmArgs g, const int32_t* __restrict__ E,
@@ -1062,16 +1155,42 @@ int launch_crt_mfma(int cfg, const int8_t* RA, const int8_t* RB, uint8_t* Y, int
     return (int)hipGetLastError();
 }
 
+// kc_l = 128 sum_q B'_{4l+q} 256^q with B'_c = sum_{t<N} (byte c of W_t - 128),
+// and r_l = 2^(32 l) / M_N (M_N rounded to binary64).
+CrtRecConsts crt_rec_consts(int N, int K) {
+    const CrtTables& T = crt_host_tables();
+    CrtRecConsts rc{};
+    const int row0 = N * (N - 1) / 2;
+    for (int l = 0; l < K; ++l) {
+        double kc = 0.0;
+        for (int q = 0; q < 4; ++q) {
+            int64_t b = 0;
+            for (int t = 0; t < N; ++t) b += (int64_t)((T.W[row0 + t][l] >> (8 * q)) & 255u) - 128;
+            kc += 128.0 * (double)b * std::ldexp(1.0, 8 * q);
+        }
+        rc.kc[l] = kc;
+    }
+    double md = 0.0;
+    for (int l = kLimbs - 1; l >= 0; --l) md = md * 4294967296.0 + (double)T.M[N][l];
+    for (int l = 0; l < K; ++l) rc.r[l] = std::ldexp(1.0 / md, 32 * l);
+    return rc;
+}
+
 template <int P>
 int launch_crt_recombine_p(int K, dim3 grid, hipStream_t st, const GemmArgs& g, const int32_t* E,
                            const int32_t* F, const uint8_t* Y, int N, int s, int64_t Mp, int64_t Np) {
-#define MPG_REC(KV) \
-    hipLaunchKernelGGL((crt_recombine_kernel<P, KV>), grid, dim3(256), 0, st, g, E, F, Y, N, s, Mp, Np)
+    const CrtRecConsts rc = crt_rec_consts(N, K);
+#define MPG_REC(KV, NKB)                                                                                      \
+    hipLaunchKernelGGL((crt_recombine_mfma_kernel<P, KV, NKB>), grid, dim3(256), 0, st, g, E, F, Y, N, s, Mp, \
+                       Np, rc)
+    if (N > 2 * 32) return (int)hipErrorInvalidValue;
     switch (K) {
-    case 4: MPG_REC(4); break;
-    case 6: MPG_REC(6); break;
-    case 8: MPG_REC(8); break;
-    default: MPG_REC(11); break;
+    case 4: MPG_REC(4, 1); break;
+    case 6: MPG_REC(6, 1); break;
+    case 8:
+        if (N > 32) MPG_REC(8, 2); else MPG_REC(8, 1);
+        break;
+    default: MPG_REC(11, 2); break;
     }
 #undef MPG_REC
     return (int)hipGetLastError();
@@ -1194,7 +1313,7 @@ int launch_crt(int P, int s, int cfg, const GemmArgs& g, void* ws, hipStream_t s
 #undef MPG_REC3
         return (int)hipGetLastError();
     }
-    const int64_t blocks = (L.Mp / 4 * g.n + 255) / 256;
+    const int64_t blocks = L.Mp / kRec3Rows * ((g.n + 1) / 2);
     if (blocks > 0x7fffffffLL) return (int)hipErrorInvalidConfiguration;
     const dim3 grid((unsigned)blocks);
     const int K = limbs_for(N);

@@ -683,16 +683,19 @@ template <int P, int K>
 __device__ __forceinline__ void limbs_to_components(uint32_t (&w)[K], double sg, int e, double* c) {
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-        int L = -1;                                     // top nonzero limb
-#pragma unroll
-        for (int l = 0; l < K; ++l) L = (w[l] != 0u) ? l : L;
-        uint32_t hi = 0u, mid = 0u, lo = 0u, below = 0u;
+        // one ascending pass: at the top nonzero limb L, hi/mid/lo = limbs
+        // L, L-1, L-2 and below = OR of limbs 0..L-3 (run holds that OR)
+        int L = -1;
+        uint32_t hi = 0u, mid = 0u, lo = 0u, below = 0u, run = 0u;
 #pragma unroll
         for (int l = 0; l < K; ++l) {
-            hi = (l == L) ? w[l] : hi;
-            mid = (l == L - 1) ? w[l] : mid;
-            lo = (l == L - 2) ? w[l] : lo;
-            below |= (l < L - 2) ? w[l] : 0u;
+            const bool nz = w[l] != 0u;
+            L = nz ? l : L;
+            hi = nz ? w[l] : hi;
+            mid = nz ? (l >= 1 ? w[l - 1] : 0u) : mid;
+            lo = nz ? (l >= 2 ? w[l - 2] : 0u) : lo;
+            below = nz ? run : below;
+            if (l >= 2) run |= w[l - 2];
         }
         const int z = __clz(hi | 1u);                   // leading zeros of hi (nonzero when L >= 0)
         const uint64_t hm = ((uint64_t)hi << 32) | mid;
@@ -709,12 +712,14 @@ __device__ __forceinline__ void limbs_to_components(uint32_t (&w)[K], double sg,
         c[q] = (L < 0) ? 0.0 : sg * ldexp((double)v, sh + e);
         if (q == P - 1) break;
         // remainder: the bits below sh; after rounding up, 2^sh minus them
-        // with the sign flipped (a value below 2^53 leaves nothing)
+        // with the sign flipped (a value below 2^53 leaves nothing): limbs
+        // below sh / 32 whole, limb sh / 32 its low sh % 32 bits, none above
+        const int sl = sh >> 5;                         // floor(sh / 32); negative below 2^53
+        const uint32_t part = (1u << (sh & 31)) - 1u;
         uint32_t mask[K];
 #pragma unroll
         for (int l = 0; l < K; ++l) {
-            const int t = sh - 32 * l;                  // bits of limb l below sh
-            mask[l] = (t <= 0) ? 0u : (t >= 32) ? 0xffffffffu : ((1u << (t & 31)) - 1u);
+            mask[l] = (l < sl) ? 0xffffffffu : (l == sl) ? part : 0u;
             w[l] &= mask[l];
         }
         uint32_t carry = 1u;
@@ -811,7 +816,9 @@ __global__ __launch_bounds__(256) void crt_recombine_mfma_kernel(GemmArgs g, con
                                                                  int64_t Mp, int64_t Np, CrtRecConsts rc) {
     constexpr int NCB = (4 * K + 31) / 32;       // blocks of 32 digit columns
     constexpr int kChunks = kNumModuli * 2 * kRec3Rows / 16;
-    __shared__ __align__(16) uint8_t ys[kNumModuli * 2 * kRec3Rows];
+    // room for 32 NKB planes: the fragments read every slot (bytes of planes
+    // t >= N are stale and masked), which keeps the reads free of branches
+    __shared__ __align__(16) uint8_t ys[32 * NKB * 2 * kRec3Rows];
     const int64_t tiles = Mp / kRec3Rows;
     const int64_t i0 = (blockIdx.x % tiles) * kRec3Rows, j0 = 2 * (blockIdx.x / tiles);
     const int64_t plane = Mp * Np;
@@ -865,8 +872,8 @@ __global__ __launch_bounds__(256) void crt_recombine_mfma_kernel(GemmArgs g, con
 #pragma unroll
             for (int jj = 0; jj < 16; ++jj) {
                 const int t = 32 * kb + 16 * hi + jj;
-                const uint32_t y = t < N ? ys[t * 2 * kRec3Rows + eb] : 0u;
-                w4[jj / 4] |= y << (8 * (jj % 4));
+                const uint32_t y = ys[t * 2 * kRec3Rows + eb];
+                w4[jj / 4] |= (t < N ? y : 0u) << (8 * (jj % 4));
             }
 #pragma unroll
             for (int d = 0; d < 4; ++d) sum = __builtin_amdgcn_sad_u8(w4[d], 0u, sum);

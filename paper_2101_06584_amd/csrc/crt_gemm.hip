@@ -809,56 +809,53 @@ struct CrtRecConsts {
     double r[kLimbs];                // 2^(32 l) / M_N
 };
 
-template <int P, int K, int NKB>
-__global__ __launch_bounds__(256) void crt_recombine_mfma_kernel(GemmArgs g, const int32_t* __restrict__ E,
-                                                                 const int32_t* __restrict__ F,
-                                                                 const uint8_t* __restrict__ Y, int N, int s,
-                                                                 int64_t Mp, int64_t Np, CrtRecConsts rc) {
-    constexpr int NCB = (4 * K + 31) / 32;       // blocks of 32 digit columns
-    constexpr int kChunks = kNumModuli * 2 * kRec3Rows / 16;
-    // room for 32 NKB planes: the fragments read every slot (bytes of planes
-    // t >= N are stale and masked), which keeps the reads free of branches
-    __shared__ __align__(16) uint8_t ys[32 * NKB * 2 * kRec3Rows];
-    const int64_t tiles = Mp / kRec3Rows;
-    const int64_t i0 = (blockIdx.x % tiles) * kRec3Rows, j0 = 2 * (blockIdx.x / tiles);
-    const int64_t plane = Mp * Np;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int hi = lane >> 5;
-    // chunk c = 256 u + tid: plane c / 16, column (c / 8) % 2, bytes 16 (c % 8) ..
-    const int nch = N * 2 * kRec3Rows / 16;
+// Matrix-core limb sums for K limbs and NKB blocks of 32 moduli.
+template <int K, int NKB>
+struct LimbMfma {
+    static constexpr int NCB = (4 * K + 31) / 32;     // blocks of 32 digit columns
+    static constexpr int kCols = 32 * NCB, kMods = 32 * NKB;
+};
+
+// The cofactor bytes b'_tc of W_t = M_N / m_t in LDS, digit column major
+// (bt[c][t], zero for t >= N; limb l is columns 4 l .. 4 l + 3), then this
+// lane's A fragments: digit column 32 cb + L % 32, moduli 32 kb + 16 (L / 32)
+// + 0..15.  Also waits for the caller's direct-to-LDS copies; ends on a
+// barrier past which LDS is complete.
+template <int K, int NKB>
+__device__ __forceinline__ void cofactor_fragments(uint8_t* bt, int N, int tid,
+                                                   v4i (&af)[LimbMfma<K, NKB>::NCB][NKB]) {
+    using LM = LimbMfma<K, NKB>;
+    const int lane = tid & 63, hi = lane >> 5;
 #pragma unroll
-    for (int u = 0; u < (kChunks + 255) / 256; ++u) {
-        const int c = 256 * u + tid;
-        const int64_t col = j0 + ((c >> 3) & 1);
-        if (c < nch && col < g.n)
-            copy16_to_lds((const int8_t*)(Y + (int64_t)(c >> 4) * plane + col * Mp + i0 + 16 * (c & 7)),
-                          (int8_t*)(ys + 16 * (c - lane)));
-    }
-    // the cofactor bytes b'_tc in LDS, digit column major (bt[c][t], zero for
-    // t >= N): limb l of W_t is columns 4 l .. 4 l + 3
-    constexpr int kCols = 32 * NCB, kMods = 32 * NKB;
-    __shared__ __align__(16) uint8_t bt[kCols * kMods];
-#pragma unroll
-    for (int o = 16 * tid; o < kCols * kMods; o += 16 * 256) *(v4i*)(bt + o) = v4i{0, 0, 0, 0};
+    for (int o = 16 * tid; o < LM::kCols * LM::kMods; o += 16 * 256) *(v4i*)(bt + o) = v4i{0, 0, 0, 0};
     __syncthreads();
     const uint32_t* wrow = kCrtDev.W[N * (N - 1) / 2];
     for (int e = tid; e < N * K; e += 256) {
         const int t = e / K, l = e % K;
         const uint32_t w = wrow[t * kLimbs + l] ^ 0x80808080u;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) bt[(4 * l + q) * kMods + t] = (uint8_t)(w >> (8 * q));
+        for (int q = 0; q < 4; ++q) bt[(4 * l + q) * LM::kMods + t] = (uint8_t)(w >> (8 * q));
     }
     wait_vm_all();
     __syncthreads();
-    // A fragments: digit column 32 cb + L % 32, moduli 32 kb + 16 (L / 32) + 0..15
-    v4i af[NCB][NKB];
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
+    for (int cb = 0; cb < LM::NCB; ++cb)
 #pragma unroll
         for (int kb = 0; kb < NKB; ++kb)
-            af[cb][kb] = *(const v4i*)(bt + (32 * cb + (lane & 31)) * kMods + 32 * kb + 16 * hi);
-    // B fragments (y' of entry 64 w + 32 grp + L % 32, the same moduli) and
-    // the byte sums of this lane's moduli
+            af[cb][kb] = *(const v4i*)(bt + (32 * cb + (lane & 31)) * LM::kMods + 32 * kb + 16 * hi);
+}
+
+// Limb sums L_l = sum_{t<N} y_t W_t[l] of entry 64 w + L for the residue
+// bytes of N planes in LDS (plane t at ysl + 256 t, entry e at byte e; planes
+// t >= N are read but masked).  Entries 64 w + 32 grp + L % 32 of the two
+// groups are the columns of the B fragments; the two halves of the wave
+// then trade limbs of opposite parity so that lane L holds entry 64 w + L.
+template <int K, int NKB>
+__device__ __forceinline__ void limb_sums(const uint8_t* ysl, const v4i (&af)[LimbMfma<K, NKB>::NCB][NKB],
+                                          int N, int tid, const double (&kcs)[kLimbs], double (&L)[K]) {
+    using LM = LimbMfma<K, NKB>;
+    constexpr int NCB = LM::NCB;
+    const int lane = tid & 63, wave = tid >> 6, hi = lane >> 5;
     v16i acc[2][NCB];
     uint32_t ysum[2];
 #pragma unroll
@@ -872,7 +869,7 @@ __global__ __launch_bounds__(256) void crt_recombine_mfma_kernel(GemmArgs g, con
 #pragma unroll
             for (int jj = 0; jj < 16; ++jj) {
                 const int t = 32 * kb + 16 * hi + jj;
-                const uint32_t y = ys[t * 2 * kRec3Rows + eb];
+                const uint32_t y = ysl[t * 2 * kRec3Rows + eb];
                 w4[jj / 4] |= (t < N ? y : 0u) << (8 * (jj % 4));
             }
 #pragma unroll
@@ -902,7 +899,7 @@ __global__ __launch_bounds__(256) void crt_recombine_mfma_kernel(GemmArgs g, con
             for (int v = 0; v < 4; ++v) {
                 const int le = 8 * cb + 2 * v;               // even limb; this lane's is le + hi
                 if (le >= K) continue;
-                const double kc = hi ? (le + 1 < K ? rc.kc[le + 1] : 0.0) : rc.kc[le];
+                const double kc = hi ? (le + 1 < K ? kcs[le + 1] : 0.0) : kcs[le];
                 const v16i& a = acc[grp][cb];
                 double z = fma((double)a[4 * v + 3], 256.0, (double)a[4 * v + 2]);
                 z = fma(z, 256.0, (double)a[4 * v + 1]);
@@ -912,7 +909,6 @@ __global__ __launch_bounds__(256) void crt_recombine_mfma_kernel(GemmArgs g, con
     }
     // lanes L < 32 keep group 0 (entry 64 w + L), lanes L >= 32 group 1
     // (entry 64 w + L as well): trade the limbs of the other parity
-    double L[K];
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
@@ -924,6 +920,46 @@ __global__ __launch_bounds__(256) void crt_recombine_mfma_kernel(GemmArgs g, con
             L[le] = hi ? other : mine;
             if (le + 1 < K) L[le + 1] = hi ? mine : other;
         }
+}
+
+// Copies the residue bytes of `planes` planes for rows i0 .. i0 + 127 of
+// columns j0, j0 + 1 into LDS (plane p at ys + 256 p: column 0's 128 bytes,
+// then column 1's) with 16-byte direct-to-LDS copies, all in flight.
+template <int MAXP>
+__device__ __forceinline__ void stage_residue_bytes(uint8_t* ys, const uint8_t* Y, int planes, int64_t plane,
+                                                    int64_t Mp, int64_t i0, int64_t j0, int64_t n, int tid) {
+    constexpr int kChunks = MAXP * 2 * kRec3Rows / 16;
+    const int lane = tid & 63;
+    // chunk c = 256 u + tid: plane c / 16, column (c / 8) % 2, bytes 16 (c % 8) ..
+    const int nch = planes * 2 * kRec3Rows / 16;
+#pragma unroll
+    for (int u = 0; u < (kChunks + 255) / 256; ++u) {
+        const int c = 256 * u + tid;
+        const int64_t col = j0 + ((c >> 3) & 1);
+        if (c < nch && col < n)
+            copy16_to_lds((const int8_t*)(Y + (int64_t)(c >> 4) * plane + col * Mp + i0 + 16 * (c & 7)),
+                          (int8_t*)(ys + 16 * (c - lane)));
+    }
+}
+
+template <int P, int K, int NKB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void crt_recombine_mfma_kernel(GemmArgs g, const int32_t* __restrict__ E,
+                                                                 const int32_t* __restrict__ F,
+                                                                 const uint8_t* __restrict__ Y, int N, int s,
+                                                                 int64_t Mp, int64_t Np, CrtRecConsts rc) {
+    using LM = LimbMfma<K, NKB>;
+    // room for 32 NKB planes: the fragments read every slot (bytes of planes
+    // t >= N are stale and masked), which keeps the reads free of branches
+    __shared__ __align__(16) uint8_t ys[32 * NKB * 2 * kRec3Rows];
+    __shared__ __align__(16) uint8_t bt[LM::kCols * LM::kMods];
+    const int64_t tiles = Mp / kRec3Rows;
+    const int64_t i0 = (blockIdx.x % tiles) * kRec3Rows, j0 = 2 * (blockIdx.x / tiles);
+    const int tid = threadIdx.x;
+    stage_residue_bytes<kNumModuli>(ys, Y, N, Mp * Np, Mp, i0, j0, g.n, tid);
+    v4i af[LM::NCB][NKB];
+    cofactor_fragments<K, NKB>(bt, N, tid, af);
+    double L[K];
+    limb_sums<K, NKB>(ys, af, N, tid, rc.kc, L);
     const int64_t i = i0 + (tid & (kRec3Rows - 1)), j = j0 + tid / kRec3Rows;
     if (i >= g.m || j >= g.n) return;
     double f = 0.0;
@@ -959,55 +995,38 @@ __device__ __forceinline__ void add_shifted(uint32_t (&c)[kLimbsC], const uint32
 
 // Block b takes rows 128 (b % (Mp / 128)) .. + 127 of two columns; it first
 // copies their 3N planes' bytes (256 per plane) into LDS with 16-byte
-// direct-to-LDS copies, all in flight at once, then thread t reconstructs
-// entry (row t % 128, column t / 128).
+// direct-to-LDS copies, all in flight at once; the limb sums of each set run
+// on the matrix cores as in the one-level kernel (the same N moduli in every
+// set), and thread t finishes entry (row t % 128, column t / 128).
 
-template <int P, int SLO>
+template <int P, int SLO, int NKB>
 __global__ __launch_bounds__(256) void crt_recombine3_kernel(GemmArgs g, const int32_t* __restrict__ E,
                                                              const int32_t* __restrict__ F,
                                                              const uint8_t* __restrict__ Y, int N,
-                                                             int s, int64_t Mp, int64_t Np) {
+                                                             int s, int64_t Mp, int64_t Np, CrtRecConsts rc) {
     constexpr int K = 8;                          // each partial below 2^255 (N <= 33)
     constexpr int w = 7 * SLO;
-    constexpr int kChunks = 3 * kRec3MaxN * 2 * kRec3Rows / 16;
-    __shared__ __align__(16) uint8_t ys[3 * kRec3MaxN * 2 * kRec3Rows];
+    using LM = LimbMfma<K, NKB>;
+    // the last set's fragments read 32 NKB plane slots from 2N on
+    __shared__ __align__(16) uint8_t ys[(2 * kRec3MaxN + 32 * NKB) * 2 * kRec3Rows];
+    __shared__ __align__(16) uint8_t bt[LM::kCols * LM::kMods];
     const int64_t tiles = Mp / kRec3Rows;
     const int64_t i0 = (blockIdx.x % tiles) * kRec3Rows, j0 = 2 * (blockIdx.x / tiles);
-    const int64_t plane = Mp * Np;
-    const int tid = threadIdx.x, lane = tid & 63;
-    // chunk c = 256 u + t: plane c / 16, column (c / 8) % 2, bytes 16 (c % 8) ..
-    const int nch = 3 * N * 2 * kRec3Rows / 16;
-#pragma unroll
-    for (int u = 0; u < (kChunks + 255) / 256; ++u) {
-        const int c = 256 * u + tid;
-        const int64_t col = j0 + ((c >> 3) & 1);
-        if (c < nch && col < g.n)
-            copy16_to_lds((const int8_t*)(Y + (int64_t)(c >> 4) * plane + col * Mp + i0 + 16 * (c & 7)),
-                          (int8_t*)(ys + 16 * (c - lane)));
-    }
-    wait_vm_all();
-    __syncthreads();
+    const int tid = threadIdx.x;
+    stage_residue_bytes<3 * kRec3MaxN>(ys, Y, 3 * N, Mp * Np, Mp, i0, j0, g.n, tid);
+    v4i af[LM::NCB][NKB];
+    cofactor_fragments<K, NKB>(bt, N, tid, af);
     const int64_t i = i0 + (tid & (kRec3Rows - 1)), j = j0 + tid / kRec3Rows;
-    if (i >= g.m || j >= g.n) return;
-    const uint8_t* yl = ys + (tid / kRec3Rows) * kRec3Rows + (tid & (kRec3Rows - 1));
-    const int row0 = N * (N - 1) / 2;
     uint32_t c[kLimbsC];
 #pragma unroll
     for (int l = 0; l < kLimbsC; ++l) c[l] = 0u;
     static_for<3>([&](auto setc) __attribute__((always_inline)) {
         constexpr int set = decltype(setc)::value;     // 0: hh, 1: ll, 2: ss
         double L[K];
-#pragma unroll
-        for (int l = 0; l < K; ++l) L[l] = 0.0;
+        limb_sums<K, NKB>(ys + set * N * 2 * kRec3Rows, af, N, tid, rc.kc, L);
         double f = 0.0;
-        const uint8_t* yss = yl + set * N * 2 * kRec3Rows;
-        for (int tm = 0; tm < N; ++tm) {
-            const double y = (double)yss[tm * 2 * kRec3Rows];
-            f = fma(y, kCrtDev.inv[tm], f);
-            const double* wl = kCrtDev.Wd[row0 + tm];
 #pragma unroll
-            for (int l = 0; l < K; ++l) L[l] = fma(y, wl[l], L[l]);
-        }
+        for (int l = 0; l < K; ++l) f = fma(L[l], rc.r[l], f);
         const double q = rint(f);
         uint32_t x[K];
         int64_t carry = 0;
@@ -1028,6 +1047,7 @@ __global__ __launch_bounds__(256) void crt_recombine3_kernel(GemmArgs g, const i
             add_shifted<+1, w, K>(c, x, ext);
         }
     });
+    if (i >= g.m || j >= g.n) return;
     double sg = 1.0;
     if (c[kLimbsC - 1] >> 31) {
         uint64_t c1 = 1;
@@ -1308,15 +1328,20 @@ int launch_crt(int P, int s, int cfg, const GemmArgs& g, void* ws, hipStream_t s
         const int64_t blocks = L.Mp / kRec3Rows * ((g.n + 1) / 2);
         if (blocks > 0x7fffffffLL) return (int)hipErrorInvalidConfiguration;
         const dim3 grid((unsigned)blocks);
-#define MPG_REC3(SL) \
-    hipLaunchKernelGGL((crt_recombine3_kernel<4, SL>), grid, dim3(256), 0, st, g, E, F, Y, N, s, L.Mp, L.Np)
+        const CrtRecConsts rc = crt_rec_consts(N, 8);
+#define MPG_REC3(SL, NKB)                                                                                    \
+    hipLaunchKernelGGL((crt_recombine3_kernel<4, SL, NKB>), grid, dim3(256), 0, st, g, E, F, Y, N, s, L.Mp, \
+                       L.Np, rc)
+#define MPG_REC3N(SL) \
+    if (N > 32) MPG_REC3(SL, 2); else MPG_REC3(SL, 1)
         switch (pl.slo) {
-        case 12: MPG_REC3(12); break;
-        case 13: MPG_REC3(13); break;
-        case 14: MPG_REC3(14); break;
-        case 15: MPG_REC3(15); break;
-        default: MPG_REC3(16); break;
+        case 12: MPG_REC3N(12); break;
+        case 13: MPG_REC3N(13); break;
+        case 14: MPG_REC3N(14); break;
+        case 15: MPG_REC3N(15); break;
+        default: MPG_REC3N(16); break;
         }
+#undef MPG_REC3N
 #undef MPG_REC3
         return (int)hipGetLastError();
     }

@@ -16,9 +16,9 @@ error against the exact product on sampled entries (split vs plain "at the
 same error"), the batched form against one launch per problem, the
 roofline of the dominant kernel, and the CPU oracle on this host's cores.
 
-Other workloads (separate JSON lines): --config 3 (QD n = 2048, entries
-u 2^e with e in -30..30 per entry, all forms, slice count from the accuracy
-rule) and --config 4 (DD n = 8192, all forms).
+Other workloads (separate JSON lines): --workload qd2048-spread (QD n = 2048,
+entries u 2^e with e in -30..30 per entry, all forms, slice count from the
+accuracy rule) and --workload dd8192 (DD n = 8192, all forms).
 """
 from __future__ import annotations
 
@@ -102,7 +102,8 @@ def parse():
     ap.add_argument("--copy-calib", action="store_true",
                     help="run a plain device copy of 1 GiB first (counter calibration)")
     ap.add_argument("--no-batched", action="store_true", help="leave the batched sets out")
-    ap.add_argument("--config", type=int, default=0, help="3 or 4: the other workloads")
+    ap.add_argument("--workload", default="", choices=["", "qd2048-spread", "dd8192"],
+                    help="one of the other workloads instead of the step")
     ap.add_argument("--vec", action="store_true",
                     help="element-wise DD/TD/QD add and mul (Sec. 2.5) against the HBM roofline")
     ap.add_argument("--vec-n", type=int, default=1 << 26, help="vector length for --vec")
@@ -146,8 +147,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    if args.config in (3, 4):
-        return other_config(args, mp, synth, dev, stream)
+    if args.workload:
+        return other_workload(args, mp, synth, dev, stream)
     if args.vec:
         return vec_bench(args, mp, dev, stream)
     if args.td_variants:
@@ -185,7 +186,7 @@ def main():
         note("inputs ready", NAME[P])
     torch.cuda.synchronize()
 
-    # batched sets (config 5's shape mix): DD and TD, 512 problems each
+    # batched sets (512 problems with m, n, k uniform in 16..512): DD and TD
     batched = {}
     if not args.no_batched:
         for P in (2, 3):
@@ -777,19 +778,20 @@ def separate_launches(mp, P, b, stream):
     return {"separate_launches_ms": round(ms, 3), "separate_launches_2mnk/s": b["work"] / (ms * 1e-3)}
 
 
-def other_config(args, mp, synth, dev, stream):
-    """--config 3: QD n = 2048 with exponent spread, both forms, slices from the
-    accuracy rule; --config 4: DD n = 8192, both forms.  One JSON line."""
+def other_workload(args, mp, synth, dev, stream):
+    """qd2048-spread: QD n = 2048 with exponent spread, all forms, slices from
+    the accuracy rule; dd8192: DD n = 8192, all forms.  One JSON line."""
     import numpy as np
     import torch
     from tests.exact import GemmChecker, sample_entries
-    cfg = args.config
-    if cfg == 3:
+    spread_qd = args.workload == "qd2048-spread"
+    fam = 3 if spread_qd else 4               # seed family of the workload's inputs
+    if spread_qd:
         P, n, spread = 4, 2048, (-30, 30)
     else:
         P, n, spread = 2, 8192, None
-    A = synth.mp_matrix(cfg, "A", P, n, n, exp_range=spread)
-    B = synth.mp_matrix(cfg, "B", P, n, n, exp_range=spread)
+    A = synth.mp_matrix(fam, "A", P, n, n, exp_range=spread)
+    B = synth.mp_matrix(fam, "B", P, n, n, exp_range=spread)
     one, zero = synth.mp_one(P), np.zeros(P)
     dA = torch.from_numpy(A).to(dev)
     dB = torch.from_numpy(B).to(dev)
@@ -797,7 +799,7 @@ def other_config(args, mp, synth, dev, stream):
     forms = args.forms.split(",")
     if "crt" not in forms:
         forms.append("crt")        # the residue form of the split product, too
-    if cfg == 3:
+    if spread_qd:
         # "same error": the smallest s whose result on a block of rows stays
         # within 1e-6 k u (|A||B|)_ij of the plain (canonical) result
         s, rule_ratio = mp.tune_slices(P, "N", "N", n, n, n, dA, dB, target=SAME_ERROR_TARGET,
@@ -814,7 +816,7 @@ def other_config(args, mp, synth, dev, stream):
     parts = {}
     chk = None if args.no_check else GemmChecker(P, "N", "N", n, n, n, one, A, B, zero,
                                                  np.zeros((P, 1, 1)))
-    ents = sample_entries(synth.rng_for(cfg, "samples"), n, n, 1024)
+    ents = sample_entries(synth.rng_for(fam, "samples"), n, n, 1024)
     for f in forms:
         dC = torch.zeros((P, n, n), dtype=torch.float64, device=dev)
         kw = (dict(form="split", slices=s, workspace=ws) if f == "split" else
@@ -852,7 +854,7 @@ def other_config(args, mp, synth, dev, stream):
         parts[f"{NAME[P]}_{f}"] = item
     total_ms = sum(v["ms"] for v in parts.values())
     workload = ("QD GEMM m=n=k=2048, entries u*2^e, e ~ U{-30..30} per entry, plain, split and "
-                "residue (CRT) split forms, slices from the accuracy rule" if cfg == 3 else
+                "residue (CRT) split forms, slices from the accuracy rule" if spread_qd else
                 "DD GEMM m=n=k=8192, plain, split and residue (CRT) split forms")
     out = {"metric": METRIC, "value": 2.0 * n ** 3 * len(parts) / (total_ms * 1e-3), "unit": "2mnk/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

@@ -28,13 +28,16 @@ SLOT = {"A": 0, "B": 1, "C": 2, "alpha": 3, "beta": 4, "expA": 5, "expB": 6,
 PREC_P = {"dd": 2, "td": 3, "qd": 4}
 
 
-def seed_for(cfg: int, slot: str | int) -> int:
+def seed_for(family: int, slot: str | int) -> int:
+    """Seed of one input (slot) of one family; each workload draws from its
+    own family (2: the square benchmark step, 3: QD n = 2048 with exponent
+    spread, 4: DD n = 8192, 5: the batched sets; others: tests)."""
     s = SLOT[slot] if isinstance(slot, str) else int(slot)
-    return SEED_BASE + 16 * int(cfg) + s
+    return SEED_BASE + 16 * int(family) + s
 
 
-def rng_for(cfg: int, slot: str | int) -> np.random.Generator:
-    return np.random.Generator(np.random.PCG64(seed_for(cfg, slot)))
+def rng_for(family: int, slot: str | int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed_for(family, slot)))
 
 
 def _tail_components(rng, lead: np.ndarray, P: int) -> np.ndarray:
@@ -57,7 +60,7 @@ def mp_uniform(rng, P: int, shape) -> np.ndarray:
     return _tail_components(rng, lead, P)
 
 
-def mp_matrix(cfg: int, slot: str, P: int, rows: int, cols: int, ld: int | None = None,
+def mp_matrix(family: int, slot: str, P: int, rows: int, cols: int, ld: int | None = None,
               exp_range: tuple[int, int] | None = None, exp_mode: str = "entry") -> np.ndarray:
     """A (P, cols, ld) component-plane matrix.
 
@@ -67,10 +70,10 @@ def mp_matrix(cfg: int, slot: str, P: int, rows: int, cols: int, ld: int | None 
     """
     ld = rows if ld is None else ld
     assert ld >= max(1, rows)
-    rng = rng_for(cfg, slot)
+    rng = rng_for(family, slot)
     core = mp_uniform(rng, P, (cols, rows))          # column-major: [j][i]
     if exp_range is not None:
-        erng = rng_for(cfg, "expA" if slot == "A" else "expB" if slot == "B" else 9)
+        erng = rng_for(family, "expA" if slot == "A" else "expB" if slot == "B" else 9)
         lo, hi = exp_range
         if exp_mode == "entry":
             e = erng.integers(lo, hi + 1, size=(cols, rows))
@@ -86,8 +89,8 @@ def mp_matrix(cfg: int, slot: str, P: int, rows: int, cols: int, ld: int | None 
     return out
 
 
-def mp_scalar(cfg: int, slot: str, P: int) -> np.ndarray:
-    rng = rng_for(cfg, slot)
+def mp_scalar(family: int, slot: str, P: int) -> np.ndarray:
+    rng = rng_for(family, slot)
     return mp_uniform(rng, P, (1,))[:, 0].copy()
 
 
@@ -145,17 +148,17 @@ def paper_exact_entry(n: int, i: int) -> Fraction:
     return r15 * Fraction(n * (n - 1) * (3 * i + n - 2), 6)
 
 
-def batch_problems(cfg: int, P: int, count: int, lo: int, hi: int):
+def batch_problems(family: int, P: int, count: int, lo: int, hi: int):
     """`count` GEMM problems with m, n, k drawn uniformly from lo..hi (slot
     "shapes"); operands drawn like mp_matrix in one pass (slots A, B, C) and
     cut per problem.  alpha = 1, beta = 0 (C = A B), transposes 'N'."""
-    shapes = rng_for(cfg, "shapes").integers(lo, hi + 1, size=(count, 3))
+    shapes = rng_for(family, "shapes").integers(lo, hi + 1, size=(count, 3))
     sizes = [(int(m) * int(k), int(k) * int(n), int(m) * int(n)) for m, n, k in shapes]
     pools = {}
     for slot, idx in (("A", 0), ("B", 1), ("C", 2)):
         total = sum(s[idx] for s in sizes)
         rows = (total + 1023) // 1024            # drawn as rows of 1024 (faster in numpy)
-        pools[slot] = mp_uniform(rng_for(cfg, slot), P, (rows, 1024)).reshape(P, -1)[:, :total]
+        pools[slot] = mp_uniform(rng_for(family, slot), P, (rows, 1024)).reshape(P, -1)[:, :total]
     off = [0, 0, 0]
     out = []
     for (m, n, k), sz in zip(shapes, sizes):

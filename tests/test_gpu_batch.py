@@ -12,13 +12,13 @@ from tests.gpu_util import dev, host, note
 pytestmark = pytest.mark.gpu
 
 
-def problems(P, count, lo, hi, cfg=5, seed_slot="shapes"):
-    rng = synth.rng_for(cfg, seed_slot)
+def problems(P, count, lo, hi, fam=5, seed_slot="shapes"):
+    rng = synth.rng_for(fam, seed_slot)
     shapes = rng.integers(lo, hi + 1, size=(count, 3))
     out = []
     for q, (m, n, k) in enumerate(shapes):
         m, n, k = int(m), int(n), int(k)
-        rq = np.random.Generator(np.random.PCG64(synth.seed_for(cfg, 0) * 7 + q))
+        rq = np.random.Generator(np.random.PCG64(synth.seed_for(fam, 0) * 7 + q))
         A = synth.mp_uniform(rq, P, (k, m))
         B = synth.mp_uniform(rq, P, (n, k))
         C = synth.mp_uniform(rq, P, (n, m))
@@ -62,7 +62,7 @@ def test_batch_matches_oracle_and_single_calls(gpu_lib, P):
 
 @pytest.mark.parametrize("P", [2, 3])
 def test_graph_replays_equal_direct_launch(gpu_lib, P):
-    """Config 5's shape mix (m, n, k uniform in 16..512): each graph replay,
+    """The batched shape mix (512 problems, m, n, k uniform in 16..512): each graph replay,
     with eager work and synchronisation between replays, gives the same bits
     as a direct launch and as one plain call per problem."""
     probs = problems(P, 512, 16, 512)

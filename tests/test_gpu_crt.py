@@ -14,13 +14,13 @@ from tests.gpu_util import dev, host, note
 pytestmark = pytest.mark.gpu
 
 
-def make(P, ta, tb, m, n, k, cfg, exp_range=None):
+def make(P, ta, tb, m, n, k, fam, exp_range=None):
     A_rows, A_cols = (m, k) if ta == "N" else (k, m)
     B_rows, B_cols = (k, n) if tb == "N" else (n, k)
-    A = synth.mp_matrix(cfg, "A", P, A_rows, A_cols, exp_range=exp_range)
-    B = synth.mp_matrix(cfg, "B", P, B_rows, B_cols, exp_range=exp_range)
-    C = synth.mp_matrix(cfg, "C", P, m, n)
-    return A, B, C, synth.mp_scalar(cfg, "alpha", P), synth.mp_scalar(cfg, "beta", P)
+    A = synth.mp_matrix(fam, "A", P, A_rows, A_cols, exp_range=exp_range)
+    B = synth.mp_matrix(fam, "B", P, B_rows, B_cols, exp_range=exp_range)
+    C = synth.mp_matrix(fam, "C", P, m, n)
+    return A, B, C, synth.mp_scalar(fam, "alpha", P), synth.mp_scalar(fam, "beta", P)
 
 
 def run(gpu_lib, P, ta, tb, m, n, k, alpha, A, B, beta, C, s, tile=-1):
@@ -56,7 +56,7 @@ CASES = [
 
 @pytest.mark.parametrize("P,ta,tb,m,n,k,s,tile", CASES)
 def test_bitwise_against_oracle(gpu_lib, P, ta, tb, m, n, k, s, tile):
-    A, B, C, alpha, beta = make(P, ta, tb, m, n, k, cfg=5)
+    A, B, C, alpha, beta = make(P, ta, tb, m, n, k, fam=5)
     note("crt", P, ta, tb, (m, n, k), "s", s, "tile", tile)
     got = run(gpu_lib, P, ta, tb, m, n, k, alpha, A, B, beta, C, s, tile)
     want = oracle.gemm_crt(P, s, ta, tb, m, n, k, alpha, A, B, beta, C)
@@ -69,7 +69,7 @@ def test_exponent_spread_and_beta_zero(gpu_lib, P):
     remainders), beta = 0 and alpha = 1."""
     m, n, k = 90, 75, 130
     s = gpu_lib.DEFAULT_SLICES[P]
-    A, B, _, _, _ = make(P, "N", "N", m, n, k, cfg=3, exp_range=(-30, 30))
+    A, B, _, _, _ = make(P, "N", "N", m, n, k, fam=3, exp_range=(-30, 30))
     one, zero = synth.mp_one(P), np.zeros(P)
     C = np.full((P, n, m), np.nan)          # beta = 0: C is not read
     note("crt spread", P, (m, n, k))
@@ -97,7 +97,7 @@ def test_full_size_sampled(gpu_lib, P):
     blocks bit-identical to the oracle's residue form, sampled entries within
     the split form's bound of the exact product."""
     n = 4096
-    A, B, C, alpha, beta = make(P, "N", "N", n, n, n, cfg=2)
+    A, B, C, alpha, beta = make(P, "N", "N", n, n, n, fam=2)
     s = gpu_lib.DEFAULT_SLICES[P]
     note("crt full size", P, n, s)
     got = run(gpu_lib, P, "N", "N", n, n, n, alpha, A, B, beta, C, s)
@@ -121,7 +121,7 @@ def test_full_size_sampled(gpu_lib, P):
 def test_planes_shared_out_over_workgroups(gpu_lib, P, m, n, k, s, tile):
     """Few output tiles: each tile's planes are split over several
     workgroups (an uneven last share); sampled blocks bit for bit."""
-    A, B, C, alpha, beta = make(P, "N", "N", m, n, k, cfg=8)
+    A, B, C, alpha, beta = make(P, "N", "N", m, n, k, fam=8)
     note("crt plane groups", P, (m, n, k), "s", s, "tile", tile)
     got = run(gpu_lib, P, "N", "N", m, n, k, alpha, A, B, beta, C, s, tile)
     for rows, cols in [((0, 40), (0, 24)), ((m - 33, m), (n - 17, n)), ((300, 310), (500, 520))]:
@@ -134,7 +134,7 @@ def test_repeat_and_workspace_reuse(gpu_lib):
     """Deterministic: repeated calls, a larger reused workspace and both
     tile configurations give the same bits."""
     P, m, n, k, s = 3, 150, 130, 260, 23
-    A, B, C, alpha, beta = make(P, "T", "N", m, n, k, cfg=6)
+    A, B, C, alpha, beta = make(P, "T", "N", m, n, k, fam=6)
     big = gpu_lib.alloc_workspace(P, 300, 300, 600, s, 0, form="crt")
     outs = []
     for tile in (0, 1, 0):
@@ -159,7 +159,7 @@ def test_auto_form_choice(gpu_lib, P):
     oracle's form."""
     import torch
     m, n, k = 256, 260, 300
-    A, B, C, alpha, beta = make(P, "N", "N", m, n, k, cfg=7)
+    A, B, C, alpha, beta = make(P, "N", "N", m, n, k, fam=7)
     s = gpu_lib.DEFAULT_SLICES[P]
     split_b = gpu_lib.workspace_bytes(P, "split", m, n, k, s)
     crt_b = gpu_lib.workspace_bytes(P, "crt", m, n, k, s)

@@ -14,14 +14,14 @@ from tests.gpu_util import dev, host, note
 pytestmark = pytest.mark.gpu
 
 
-def make(P, ta, tb, m, n, k, cfg, pad=0, beta_zero=False, unit_alpha=False):
+def make(P, ta, tb, m, n, k, fam, pad=0, beta_zero=False, unit_alpha=False):
     A_rows, A_cols = (m, k) if ta == "N" else (k, m)
     B_rows, B_cols = (k, n) if tb == "N" else (n, k)
-    A = synth.mp_matrix(cfg, "A", P, A_rows, A_cols, ld=A_rows + pad)
-    B = synth.mp_matrix(cfg, "B", P, B_rows, B_cols, ld=B_rows + pad)
-    C = synth.mp_matrix(cfg, "C", P, m, n, ld=m + pad)
-    alpha = synth.mp_one(P) if unit_alpha else synth.mp_scalar(cfg, "alpha", P)
-    beta = np.zeros(P) if beta_zero else synth.mp_scalar(cfg, "beta", P)
+    A = synth.mp_matrix(fam, "A", P, A_rows, A_cols, ld=A_rows + pad)
+    B = synth.mp_matrix(fam, "B", P, B_rows, B_cols, ld=B_rows + pad)
+    C = synth.mp_matrix(fam, "C", P, m, n, ld=m + pad)
+    alpha = synth.mp_one(P) if unit_alpha else synth.mp_scalar(fam, "alpha", P)
+    beta = np.zeros(P) if beta_zero else synth.mp_scalar(fam, "beta", P)
     return A, B, C, alpha, beta
 
 
@@ -35,7 +35,7 @@ def test_config1_dd_256_bitwise_and_bound(gpu_lib):
     """DD, m = n = k = 256, alpha = 1, beta = 0: every entry bit-identical to
     the oracle, and within 8 k u (|A||B|)_ij of the exact product."""
     P, m = 2, 256
-    A, B, C, alpha, beta = make(P, "N", "N", m, m, m, cfg=1, beta_zero=True, unit_alpha=True)
+    A, B, C, alpha, beta = make(P, "N", "N", m, m, m, fam=1, beta_zero=True, unit_alpha=True)
     want = oracle.gemm(P, "N", "N", m, m, m, alpha, A, B, beta, C)
     note("plain config1 DD 256")
     got = run_gpu(gpu_lib, P, "N", "N", m, m, m, alpha, A, B, beta, C)
@@ -54,7 +54,7 @@ SHAPES = [(1, 1, 1), (67, 45, 33), (130, 129, 65), (5, 200, 17)]
 @pytest.mark.parametrize("ta,tb", [("N", "N"), ("T", "N"), ("N", "T"), ("T", "T")])
 def test_ragged_shapes_all_tiles_bitwise(gpu_lib, P, ta, tb):
     for (m, n, k) in SHAPES:
-        A, B, C, alpha, beta = make(P, ta, tb, m, n, k, cfg=2, pad=3)
+        A, B, C, alpha, beta = make(P, ta, tb, m, n, k, fam=2, pad=3)
         want = oracle.gemm(P, ta, tb, m, n, k, alpha, A, B, beta, C)
         for tile in range(gpu_lib.num_configs(P, "plain")):
             note("plain", P, ta, tb, (m, n, k), "tile", tile)
@@ -65,7 +65,7 @@ def test_ragged_shapes_all_tiles_bitwise(gpu_lib, P, ta, tb):
 @pytest.mark.parametrize("P", [2, 3, 4])
 def test_alpha_beta_semantics(gpu_lib, P):
     m, n, k = 37, 29, 41
-    A, B, C, alpha, beta = make(P, "N", "N", m, n, k, cfg=3)
+    A, B, C, alpha, beta = make(P, "N", "N", m, n, k, fam=3)
     zero, one = np.zeros(P), synth.mp_one(P)
     Cnan = np.full_like(C, np.nan)
     cases = [(alpha, zero, Cnan, k),          # beta == 0: C never read
@@ -84,7 +84,7 @@ def test_alpha_beta_semantics(gpu_lib, P):
 
 def test_plane_stride_larger_than_plane(gpu_lib):
     P, m, n, k = 3, 40, 30, 20
-    A, B, C, alpha, beta = make(P, "N", "N", m, n, k, cfg=4)
+    A, B, C, alpha, beta = make(P, "N", "N", m, n, k, fam=4)
     want = oracle.gemm(P, "N", "N", m, n, k, alpha, A, B, beta, C)
     # embed each plane in a larger buffer: plane stride = cols * ld + 7
     def spread(X):
@@ -115,7 +115,7 @@ def test_config2_full_size_sampled(gpu_lib, P, n):
     """Square n x n x n with random alpha/beta and C (the benchmark workload):
     the GPU computes all of C; the oracle recomputes a sampled block, which
     must match bit for bit; sampled entries meet the error bound."""
-    A, B, C, alpha, beta = make(P, "N", "N", n, n, n, cfg=2)
+    A, B, C, alpha, beta = make(P, "N", "N", n, n, n, fam=2)
     note("plain config2 full", P, n)
     got = run_gpu(gpu_lib, P, "N", "N", n, n, n, alpha, A, B, beta, C)
     rng = synth.rng_for(2, "samples")

@@ -13,13 +13,13 @@ from tests.gpu_util import dev, host, note
 pytestmark = pytest.mark.gpu
 
 
-def make(P, ta, tb, m, n, k, cfg, exp_range=None):
+def make(P, ta, tb, m, n, k, fam, exp_range=None):
     A_rows, A_cols = (m, k) if ta == "N" else (k, m)
     B_rows, B_cols = (k, n) if tb == "N" else (n, k)
-    A = synth.mp_matrix(cfg, "A", P, A_rows, A_cols, exp_range=exp_range)
-    B = synth.mp_matrix(cfg, "B", P, B_rows, B_cols, exp_range=exp_range)
-    C = synth.mp_matrix(cfg, "C", P, m, n)
-    return A, B, C, synth.mp_scalar(cfg, "alpha", P), synth.mp_scalar(cfg, "beta", P)
+    A = synth.mp_matrix(fam, "A", P, A_rows, A_cols, exp_range=exp_range)
+    B = synth.mp_matrix(fam, "B", P, B_rows, B_cols, exp_range=exp_range)
+    C = synth.mp_matrix(fam, "C", P, m, n)
+    return A, B, C, synth.mp_scalar(fam, "alpha", P), synth.mp_scalar(fam, "beta", P)
 
 
 def workspace_views(ws, lay, s):
@@ -51,7 +51,7 @@ CASES = [
 
 @pytest.mark.parametrize("P,ta,tb,m,n,k,s,tile", CASES)
 def test_stages_bitwise(gpu_lib, P, ta, tb, m, n, k, s, tile):
-    A, B, C, alpha, beta = make(P, ta, tb, m, n, k, cfg=5)
+    A, B, C, alpha, beta = make(P, ta, tb, m, n, k, fam=5)
     lay = gpu_lib.split_layout(P, m, n, k, s, tile)
     ws = gpu_lib.alloc_workspace(P, m, n, k, s, tile)
     ws.zero_()
@@ -87,7 +87,7 @@ def test_full_size_sampled(gpu_lib, P, n):
     """The benchmark's square workload in the split form: a sampled block
     bit-identical to the oracle's split form, sampled entries within the
     error bound of the exact product."""
-    A, B, C, alpha, beta = make(P, "N", "N", n, n, n, cfg=2)
+    A, B, C, alpha, beta = make(P, "N", "N", n, n, n, fam=2)
     s = gpu_lib.DEFAULT_SLICES[P]
     ws = gpu_lib.alloc_workspace(P, n, n, n, s)
     dA, dB, dC = dev(A), dev(B), dev(C)
@@ -108,11 +108,11 @@ def test_full_size_sampled(gpu_lib, P, n):
 
 
 def test_qd_exponent_spread_with_tuned_slices(gpu_lib):
-    """Config 3's input class (entries u 2^e, e in -30..30 per entry) at a
+    """The QD spread input class (entries u 2^e, e in -30..30 per entry) at a
     reduced size: the slice count picked by the accuracy rule keeps the split
     result within the bound of the exact product."""
     P, n = 4, 512
-    A, B, _, _, _ = make(P, "N", "N", n, n, n, cfg=3, exp_range=(-30, 30))
+    A, B, _, _, _ = make(P, "N", "N", n, n, n, fam=3, exp_range=(-30, 30))
     one, zero = synth.mp_one(P), np.zeros(P)
     C = np.zeros((P, n, n))
     dA, dB = dev(A), dev(B)
@@ -134,7 +134,7 @@ def test_workspace_reuse_and_errors(gpu_lib):
     """A workspace that is too small is rejected; a larger one reused across
     calls of different shapes gives the same bits as fresh ones."""
     P = 2
-    A, B, C, alpha, beta = make(P, "N", "N", 100, 90, 80, cfg=6)
+    A, B, C, alpha, beta = make(P, "N", "N", 100, 90, 80, fam=6)
     big = gpu_lib.alloc_workspace(P, 300, 300, 300, 16)
     small = gpu_lib.alloc_workspace(P, 10, 10, 10, 16)
     dA, dB = dev(A), dev(B)

@@ -14,11 +14,11 @@ from tests.gpu_util import dev, host, note
 pytestmark = pytest.mark.gpu
 
 
-def make(P, ta, tb, m, n, k, cfg):
-    A = synth.mp_matrix(cfg, "A", P, *((m, k) if ta == "N" else (k, m)))
-    B = synth.mp_matrix(cfg, "B", P, *((k, n) if tb == "N" else (n, k)))
-    C = synth.mp_matrix(cfg, "C", P, m, n)
-    return A, B, C, synth.mp_scalar(cfg, "alpha", P), synth.mp_scalar(cfg, "beta", P)
+def make(P, ta, tb, m, n, k, fam):
+    A = synth.mp_matrix(fam, "A", P, *((m, k) if ta == "N" else (k, m)))
+    B = synth.mp_matrix(fam, "B", P, *((k, n) if tb == "N" else (n, k)))
+    C = synth.mp_matrix(fam, "C", P, m, n)
+    return A, B, C, synth.mp_scalar(fam, "alpha", P), synth.mp_scalar(fam, "beta", P)
 
 
 def run(gpu_lib, P, L, ta, tb, m, n, k, alpha, A, B, beta, C):
@@ -43,7 +43,7 @@ CASES = [
 
 @pytest.mark.parametrize("P,L,ta,tb,m,n,k", CASES)
 def test_bitwise_against_oracle(gpu_lib, P, L, ta, tb, m, n, k):
-    A, B, C, alpha, beta = make(P, ta, tb, m, n, k, cfg=14)
+    A, B, C, alpha, beta = make(P, ta, tb, m, n, k, fam=14)
     note("strassen", P, L, ta, tb, (m, n, k))
     got = run(gpu_lib, P, L, ta, tb, m, n, k, alpha, A, B, beta, C)
     want = oracle.gemm_strassen(P, L, ta, tb, m, n, k, alpha, A, B, beta, C)
@@ -53,7 +53,7 @@ def test_bitwise_against_oracle(gpu_lib, P, L, ta, tb, m, n, k):
 @pytest.mark.parametrize("P,L", [(2, 2), (4, 1)])
 def test_bitwise_n1024(gpu_lib, P, L):
     n = 1024
-    A, B, C, alpha, beta = make(P, "N", "N", n, n, n, cfg=2)
+    A, B, C, alpha, beta = make(P, "N", "N", n, n, n, fam=2)
     note("strassen n1024", P, L)
     got = run(gpu_lib, P, L, "N", "N", n, n, n, alpha, A, B, beta, C)
     want = oracle.gemm_strassen(P, L, "N", "N", n, n, n, alpha, A, B, beta, C)
@@ -65,7 +65,7 @@ def test_normwise_bound_n4096(gpu_lib, P):
     """Two levels at the benchmark size: sampled entries within
     c gamma u max|A| max|B| (Strassen's normwise constant gamma, c = 32)."""
     n, L = 4096, 2
-    A, B, _, _, _ = make(P, "N", "N", n, n, n, cfg=2)
+    A, B, _, _, _ = make(P, "N", "N", n, n, n, fam=2)
     one, zero = synth.mp_one(P), np.zeros(P)
     note("strassen n4096", P, L)
     got = run(gpu_lib, P, L, "N", "N", n, n, n, one, A, B, zero, np.zeros((P, n, n)))
@@ -85,7 +85,7 @@ def test_normwise_bound_n4096(gpu_lib, P):
 
 def test_alpha_zero_and_errors(gpu_lib):
     P, m, n, k = 2, 16, 16, 16
-    A, B, C, _, beta = make(P, "N", "N", m, n, k, cfg=15)
+    A, B, C, _, beta = make(P, "N", "N", m, n, k, fam=15)
     zero = np.zeros(P)
     got = run(gpu_lib, P, 2, "N", "N", m, n, k, zero, A, B, beta, C)
     assert np.array_equal(got, oracle.gemm(P, "N", "N", m, n, k, zero, A, B, beta, C))

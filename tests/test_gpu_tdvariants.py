@@ -28,18 +28,18 @@ def test_vec_variants_bitwise(gpu_lib, op):
     assert bad.size == 0, (op, bad[:5], got[:, bad[:3]], want[:, bad[:3]])
 
 
-def make(ta, tb, m, n, k, cfg):
-    A = synth.mp_matrix(cfg, "A", 3, *((m, k) if ta == "N" else (k, m)))
-    B = synth.mp_matrix(cfg, "B", 3, *((k, n) if tb == "N" else (n, k)))
-    C = synth.mp_matrix(cfg, "C", 3, m, n)
-    return A, B, C, synth.mp_scalar(cfg, "alpha", 3), synth.mp_scalar(cfg, "beta", 3)
+def make(ta, tb, m, n, k, fam):
+    A = synth.mp_matrix(fam, "A", 3, *((m, k) if ta == "N" else (k, m)))
+    B = synth.mp_matrix(fam, "B", 3, *((k, n) if tb == "N" else (n, k)))
+    C = synth.mp_matrix(fam, "C", 3, m, n)
+    return A, B, C, synth.mp_scalar(fam, "alpha", 3), synth.mp_scalar(fam, "beta", 3)
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("ta,tb", [("N", "N"), ("T", "N"), ("N", "T"), ("T", "T")])
 def test_gemm_variant_ragged_bitwise(gpu_lib, variant, ta, tb):
     for m, n, k in [(67, 45, 33), (130, 129, 65), (1, 1, 1), (5, 200, 17)]:
-        A, B, C, alpha, beta = make(ta, tb, m, n, k, cfg=11)
+        A, B, C, alpha, beta = make(ta, tb, m, n, k, fam=11)
         want = oracle.gemm(3, ta, tb, m, n, k, alpha, A, B, beta, C, variant=variant)
         note("td variant gemm", variant, ta, tb, (m, n, k))
         dC = dev(C)
@@ -50,7 +50,7 @@ def test_gemm_variant_ragged_bitwise(gpu_lib, variant, ta, tb):
 @pytest.mark.parametrize("variant", VARIANTS)
 def test_gemm_variant_n1024_sampled(gpu_lib, variant):
     n = 1024
-    A, B, C, alpha, beta = make("N", "N", n, n, n, cfg=2)
+    A, B, C, alpha, beta = make("N", "N", n, n, n, fam=2)
     note("td variant gemm n1024", variant)
     dC = dev(C)
     gpu_lib.gemm(3, "N", "N", n, n, n, alpha, dev(A), dev(B), beta, dC, variant=variant)
@@ -69,7 +69,7 @@ def test_gemm_variant_n1024_sampled(gpu_lib, variant):
 def test_gemm_variant_alpha_zero(gpu_lib, variant):
     """alpha == 0: C = beta C with the variant's product."""
     m, n, k = 37, 29, 11
-    A, B, C, _, beta = make("N", "N", m, n, k, cfg=12)
+    A, B, C, _, beta = make("N", "N", m, n, k, fam=12)
     zero = np.zeros(3)
     want = oracle.gemm(3, "N", "N", m, n, k, zero, A, B, beta, C, variant=variant)
     dC = dev(C)

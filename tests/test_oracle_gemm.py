@@ -13,14 +13,14 @@ from tests.exact import GemmChecker, mp_frac
 P_OF = {"dd": 2, "td": 3, "qd": 4}
 
 
-def problem(P, ta, tb, m, n, k, cfg=1, beta_zero=False, ld_pad=0):
+def problem(P, ta, tb, m, n, k, fam=1, beta_zero=False, ld_pad=0):
     A_rows, A_cols = (m, k) if ta == "N" else (k, m)
     B_rows, B_cols = (k, n) if tb == "N" else (n, k)
-    A = synth.mp_matrix(cfg, "A", P, A_rows, A_cols, ld=A_rows + ld_pad)
-    B = synth.mp_matrix(cfg, "B", P, B_rows, B_cols, ld=B_rows + ld_pad)
-    C = synth.mp_matrix(cfg, "C", P, m, n, ld=m + ld_pad)
-    alpha = synth.mp_scalar(cfg, "alpha", P)
-    beta = np.zeros(P) if beta_zero else synth.mp_scalar(cfg, "beta", P)
+    A = synth.mp_matrix(fam, "A", P, A_rows, A_cols, ld=A_rows + ld_pad)
+    B = synth.mp_matrix(fam, "B", P, B_rows, B_cols, ld=B_rows + ld_pad)
+    C = synth.mp_matrix(fam, "C", P, m, n, ld=m + ld_pad)
+    alpha = synth.mp_scalar(fam, "alpha", P)
+    beta = np.zeros(P) if beta_zero else synth.mp_scalar(fam, "beta", P)
     return A, B, C, alpha, beta
 
 
@@ -29,7 +29,7 @@ def problem(P, ta, tb, m, n, k, cfg=1, beta_zero=False, ld_pad=0):
 def test_brute_force_exact_small(P, ta, tb):
     """Every entry of small GEMMs within 8 (k+2) u (|alpha||A||B| + |beta||C|)."""
     for (m, n, k) in [(1, 1, 1), (3, 5, 7), (8, 8, 8), (7, 2, 1)]:
-        A, B, C, alpha, beta = problem(P, ta, tb, m, n, k, cfg=10 + m, ld_pad=1)
+        A, B, C, alpha, beta = problem(P, ta, tb, m, n, k, fam=10 + m, ld_pad=1)
         out = oracle.gemm(P, ta, tb, m, n, k, alpha, A, B, beta, C)
         chk = GemmChecker(P, ta, tb, m, n, k, alpha, A, B, beta, C)
         r = chk.ratios(out, [(i, j) for i in range(m) for j in range(n)])
@@ -40,7 +40,7 @@ def test_brute_force_exact_small(P, ta, tb):
 def test_bound_alpha1_beta0_random(P):
     m = n = 24
     k = 96
-    A, B, C, _, _ = problem(P, "N", "N", m, n, k, cfg=1, beta_zero=True)
+    A, B, C, _, _ = problem(P, "N", "N", m, n, k, fam=1, beta_zero=True)
     one = synth.mp_one(P)
     zero = np.zeros(P)
     out = oracle.gemm(P, "N", "N", m, n, k, one, A, B, zero, C)
@@ -53,7 +53,7 @@ def test_bound_alpha1_beta0_random(P):
 def test_transposed_storage_gives_identical_bits(P):
     """op(A) op(B) from A, B stored as-is ('N') or stored transposed ('T')."""
     m, n, k = 9, 11, 13
-    A, B, C, alpha, beta = problem(P, "N", "N", m, n, k, cfg=3)
+    A, B, C, alpha, beta = problem(P, "N", "N", m, n, k, fam=3)
     At = np.ascontiguousarray(np.transpose(A[:, :k, :m], (0, 2, 1)))   # (P, m, k): k x m stored
     Bt = np.ascontiguousarray(np.transpose(B[:, :n, :k], (0, 2, 1)))
     ref = oracle.gemm(P, "N", "N", m, n, k, alpha, A, B, beta, C)
@@ -64,7 +64,7 @@ def test_transposed_storage_gives_identical_bits(P):
 def test_dd_transpose_identity_bitwise():
     """DDmul and DDadd are bitwise commutative, so (AB)^T == B^T A^T exactly."""
     P, m, n, k = 2, 10, 7, 33
-    A, B, C, _, _ = problem(P, "N", "N", m, n, k, cfg=4)
+    A, B, C, _, _ = problem(P, "N", "N", m, n, k, fam=4)
     one, zero = synth.mp_one(P), np.zeros(P)
     AB = oracle.gemm(P, "N", "N", m, n, k, one, A, B, zero, np.zeros((P, n, m)))
     BtAt = oracle.gemm(P, "T", "T", n, m, k, one, B, A, zero, np.zeros((P, m, n)))
@@ -138,7 +138,7 @@ def test_paper_matrices_digits(P, n):
 @pytest.mark.parametrize("P", [2, 3, 4])
 def test_alpha_beta_semantics(P):
     m, n, k = 5, 4, 6
-    A, B, C, alpha, beta = problem(P, "N", "N", m, n, k, cfg=7)
+    A, B, C, alpha, beta = problem(P, "N", "N", m, n, k, fam=7)
     zero, one = np.zeros(P), synth.mp_one(P)
     Cnan = C.copy()
     Cnan[:, :, :] = np.nan
@@ -165,7 +165,7 @@ def test_alpha_beta_semantics(P):
 
 def test_row_range_matches_full():
     P, m, n, k = 3, 12, 5, 9
-    A, B, C, alpha, beta = problem(P, "N", "T", m, n, k, cfg=8)
+    A, B, C, alpha, beta = problem(P, "N", "T", m, n, k, fam=8)
     full = oracle.gemm(P, "N", "T", m, n, k, alpha, A, B, beta, C)
     part = oracle.gemm(P, "N", "T", m, n, k, alpha, A, B, beta, C, rows=(4, 9))
     assert np.array_equal(part[:, :, 4:9], full[:, :, 4:9])

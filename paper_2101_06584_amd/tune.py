@@ -1,4 +1,4 @@
-"""Autotuning driver: runs the library's autotuner (mpgemm_autotune,
+"""Autotuning front end: runs the library's autotuner (mpgemm_autotune,
 mpgemm_batch_autotune) over the shapes this project benchmarks and writes the
 tuning table that the binding loads with the library (tuned_gfx950.txt).
 

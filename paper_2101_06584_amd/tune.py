@@ -5,8 +5,9 @@ tuning table that the binding loads with the library (tuned_gfx950.txt).
     python -m paper_2101_06584_amd.tune [--out PATH] [--quick]
 
 Timing uses synthetic operands on the GPU; the table records, per precision,
-form (0 plain, 1 split, 3 batched) and log2 shape bucket, the fastest
-configuration id.
+form (0 plain, 1 split, 3 batched, 5 residue split) and log2 shape bucket, the
+fastest configuration id.  --forms limits the forms tuned; --keep starts from
+the table already there (so the other forms keep their entries).
 """
 from __future__ import annotations
 
@@ -42,29 +43,41 @@ def main(argv=None) -> int:
     ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                   "tuned_gfx950.txt"))
     ap.add_argument("--quick", action="store_true", help="only the n = 4096 benchmark shapes")
+    ap.add_argument("--forms", default="plain,split,crt,batched",
+                    help="comma-separated forms to tune (plain, split, crt, batched)")
+    ap.add_argument("--keep", action="store_true", help="start from the table already there")
     args = ap.parse_args(argv)
-    os.environ["MPGEMM_NO_TUNED_TABLE"] = "1"       # tune from the built-in defaults
+    forms = args.forms.split(",")
+    if not args.keep:
+        os.environ["MPGEMM_NO_TUNED_TABLE"] = "1"   # tune from the built-in defaults
     api.load()
     t0 = time.time()
     sizes = [4096] if args.quick else [1024, 2048, 4096]
+    gemm_forms = [f for f in ("plain", "split", "crt") if f in forms]
     for n in sizes:
         for P in (2, 3, 4):
-            for form in ("plain", "split"):
-                best = api.autotune(P, form, n, n, n, api.DEFAULT_SLICES[P] if form == "split" else 0)
+            for form in gemm_forms:
+                best = api.autotune(P, form, n, n, n, api.DEFAULT_SLICES[P] if form != "plain" else 0)
                 print(f"P={P} {form:5s} n={n}: tile {best}", flush=True)
     if not args.quick:
-        # exponent-spread QD (more digits) and DD n = 8192
-        best = api.autotune(4, "split", 2048, 2048, 2048, 33)
-        print(f"P=4 split n=2048 s=33: tile {best}", flush=True)
-        for form in ("plain", "split"):
-            best = api.autotune(2, form, 8192, 8192, 8192, 16 if form == "split" else 0)
+        # exponent-spread QD (more digits: 33 for the split form, 32 for the
+        # residue form's two levels) and DD n = 8192
+        if "split" in forms:
+            best = api.autotune(4, "split", 2048, 2048, 2048, 33)
+            print(f"P=4 split n=2048 s=33: tile {best}", flush=True)
+        if "crt" in forms:
+            best = api.autotune(4, "crt", 2048, 2048, 2048, 32)
+            print(f"P=4 crt   n=2048 s=32: tile {best}", flush=True)
+        for form in gemm_forms:
+            best = api.autotune(2, form, 8192, 8192, 8192, 16 if form != "plain" else 0)
             print(f"P=2 {form:5s} n=8192: tile {best}", flush=True)
-    for P in (2, 3):
-        probs = batch_problems(P, 512, 16, 512, seed=5)
-        best = api.batch_autotune(P, probs)
-        print(f"P={P} batched 512 x U[16,512]^3: tile {best}", flush=True)
-        del probs
-        torch.cuda.empty_cache()
+    if "batched" in forms:
+        for P in (2, 3):
+            probs = batch_problems(P, 512, 16, 512, seed=5)
+            best = api.batch_autotune(P, probs)
+            print(f"P={P} batched 512 x U[16,512]^3: tile {best}", flush=True)
+            del probs
+            torch.cuda.empty_cache()
     api.autotune_save(args.out)
     print(f"wrote {args.out} in {time.time() - t0:.1f} s", flush=True)
     return 0

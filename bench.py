@@ -92,7 +92,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--prec", default="2,3,4")
     ap.add_argument("--forms", default="plain,split,crt")

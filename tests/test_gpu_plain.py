@@ -31,19 +31,19 @@ def run_gpu(mp, P, ta, tb, m, n, k, alpha, A, B, beta, C, **kw):
     return host(dC)
 
 
-def test_config1_dd_256_bitwise_and_bound(gpu_lib):
+def test_dd256_bitwise_and_bound(gpu_lib):
     """DD, m = n = k = 256, alpha = 1, beta = 0: every entry bit-identical to
     the oracle, and within 8 k u (|A||B|)_ij of the exact product."""
     P, m = 2, 256
     A, B, C, alpha, beta = make(P, "N", "N", m, m, m, fam=1, beta_zero=True, unit_alpha=True)
     want = oracle.gemm(P, "N", "N", m, m, m, alpha, A, B, beta, C)
-    note("plain config1 DD 256")
+    note("plain DD 256 cube")
     got = run_gpu(gpu_lib, P, "N", "N", m, m, m, alpha, A, B, beta, C)
     assert np.array_equal(got, want)
     chk = GemmChecker(P, "N", "N", m, m, m, alpha, A, B, beta, C)
     rng = synth.rng_for(1, "samples")
     r = chk.ratios(got, sample_entries(rng, m, m, 1024))
-    print("config1 DD: max err / (k u |A||B|) =", r.max())
+    print("DD 256 cube: max err / (k u |A||B|) =", r.max())
     assert r.max() <= 8.0
 
 
@@ -111,12 +111,12 @@ def test_plane_stride_larger_than_plane(gpu_lib):
 
 @pytest.mark.parametrize("P", [2, 3, 4])
 @pytest.mark.parametrize("n", [1023, 4096])
-def test_config2_full_size_sampled(gpu_lib, P, n):
+def test_square_full_size_sampled(gpu_lib, P, n):
     """Square n x n x n with random alpha/beta and C (the benchmark workload):
     the GPU computes all of C; the oracle recomputes a sampled block, which
     must match bit for bit; sampled entries meet the error bound."""
     A, B, C, alpha, beta = make(P, "N", "N", n, n, n, fam=2)
-    note("plain config2 full", P, n)
+    note("plain square full size", P, n)
     got = run_gpu(gpu_lib, P, "N", "N", n, n, n, alpha, A, B, beta, C)
     rng = synth.rng_for(2, "samples")
     r0 = int(rng.integers(0, n - 2))
@@ -127,7 +127,7 @@ def test_config2_full_size_sampled(gpu_lib, P, n):
         assert np.array_equal(got[blk], want[blk]), (P, n, rows, cols)
     chk = GemmChecker(P, "N", "N", n, n, n, alpha, A, B, beta, C)
     ratios = chk.ratios(got, sample_entries(rng, n, n, 64))
-    print(f"config2 P={P} n={n}: max err / (k u (|alpha||A||B| + |beta||C|)) = {ratios.max():.3g}")
+    print(f"square P={P} n={n}: max err / (k u (|alpha||A||B| + |beta||C|)) = {ratios.max():.3g}")
     assert ratios.max() <= 8 * (n + 2) / n
 
 

@@ -126,7 +126,7 @@ def test_qd_exponent_spread_with_tuned_slices(gpu_lib):
     got = host(dC)
     chk = GemmChecker(P, "N", "N", n, n, n, one, A, B, zero, C)
     r = chk.ratios(got, sample_entries(synth.rng_for(3, "samples"), n, n, 256))
-    print("config3-class QD split: max err ratio", r.max())
+    print("QD spread class, split: max err ratio", r.max())
     assert r.max() <= 8.0
 
 

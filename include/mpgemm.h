@@ -149,7 +149,11 @@ int mpgemm_qd(char transa, char transb, int64_t m, int64_t n, int64_t k, const d
  * |beta||C|) componentwise.  Needs opts->workspace of at least
  * mpgemm_workspace_bytes() bytes (device memory the caller owns; no
  * allocation on this path).  Supported for k * s <= 2^19 (exact 32-bit
- * accumulation); larger k returns MPGEMM_ERR_UNSUPPORTED.
+ * accumulation); larger k returns MPGEMM_ERR_UNSUPPORTED.  The split forms
+ * (this one and MPGEMM_FORM_SPLIT_CRT) need finite operands: digits of an
+ * Inf or NaN do not exist, so with one in op(A) or op(B) the result is
+ * unspecified (finite garbage in the rows and columns it scales; no memory
+ * outside the buffers is touched).  The plain form follows IEEE arithmetic.
  * form = MPGEMM_FORM_STRASSEN: C = alpha P + beta C (the plain epilogue) with
  * P from opts->levels levels of Strassen's method: op(A), op(B) and P cut into
  * 2 x 2 blocks, P from the seven block products

@@ -67,9 +67,10 @@ extern "C" {
                                    recombination into P components          */
 #define MPGEMM_FORM_AUTO 2      /* the library's choice: for m, n, k >= 256
                                    the residue form (MPGEMM_FORM_SPLIT_CRT)
-                                   when the workspace holds it and it
-                                   applies, else the split form when the
-                                   workspace holds that, else plain        */
+                                   when the workspace (256-byte aligned)
+                                   holds it and it applies, else the split
+                                   form when the workspace holds that, else
+                                   plain; never a workspace error          */
 #define MPGEMM_FORM_STRASSEN 4  /* Strassen's method (Sec. 3, Fig. 5): opts.levels
                                    levels of the seven-product recursion over
                                    plain-form block products               */

@@ -240,9 +240,11 @@ int gemm_common(int P, char ta, char tb, int64_t m, int64_t n, int64_t k, const 
             return hip_rc(launch_crt(P, s, cfg, g, opts->workspace, st));
     }
     if (form == MPGEMM_FORM_AUTO) {
-        const bool fits = opts->workspace &&
+        // a workspace that cannot hold the split form (too small or not
+        // 256-byte aligned) means plain, not an error
+        const bool fits = opts->workspace && (uintptr_t)opts->workspace % 256 == 0 &&
                           opts->workspace_bytes >= split_workspace_bytes(
-                              P, m, n, k, s, pick_tile(P, MPGEMM_FORM_SPLIT_I8, m, n, k, -1));
+                              P, m, n, k, s, pick_tile(P, MPGEMM_FORM_SPLIT_I8, m, n, k, req_tile));
         form = (fits && split_k_ok(k, s) && m >= 256 && n >= 256 && k >= 256)
                    ? MPGEMM_FORM_SPLIT_I8 : MPGEMM_FORM_PLAIN;
     }

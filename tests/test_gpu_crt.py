@@ -177,6 +177,8 @@ def test_auto_form_choice(gpu_lib, P):
     note("auto: residue, split, plain", P, (m, n, k))
     assert np.array_equal(call(big), oracle.gemm_crt(P, s, "N", "N", m, n, k, alpha, A, B, beta, C))
     assert np.array_equal(call(small), oracle.gemm_split(P, s, "N", "N", m, n, k, alpha, A, B, beta, C))
-    assert np.array_equal(call(None), oracle.gemm(P, "N", "N", m, n, k, alpha, A, B, beta, C))
+    plain = oracle.gemm(P, "N", "N", m, n, k, alpha, A, B, beta, C)
+    assert np.array_equal(call(None), plain)
+    assert np.array_equal(call(big[1:]), plain)            # not 256-byte aligned: plain as well
     # m = 255 (lda stays 256): plain even with room for both split forms
     assert np.array_equal(call(big, 255), oracle.gemm(P, "N", "N", 255, n, k, alpha, A, B, beta, C))

@@ -499,7 +499,10 @@ __global__ __launch_bounds__(256) void recombine_kernel(GemmArgs g, const int32_
 
 static int launch_exponents(const double* X, int64_t rs, int64_t ls, int64_t count, int64_t padded,
                             int64_t k, int32_t* E, uint64_t* mx, hipStream_t st) {
-    if (rs == 1) {
+    // contiguous rows: k-chunked maxima (three launches) pay off on large
+    // operands; up to 2^18 entries one wave per row (strided loads) is one
+    // launch and the same maxima
+    if (rs == 1 && count * k > ((int64_t)1 << 18)) {
         const int64_t cb = (count + 255) / 256, pb = (padded + 255) / 256;
         const int64_t chunks = (k + kExpChunk - 1) / kExpChunk;
         if (chunks > 65535) return (int)hipErrorInvalidConfiguration;

@@ -100,7 +100,10 @@ typedef struct mpgemm_opts {
                                the other TD operations of Sec. 2.3 (runs TD
                                tile configuration 0); 0 = the defaults      */
     void* workspace;        /* split / Strassen form: device scratch owned by
-                               the caller                                   */
+                               the caller, 256-byte aligned; a call uses it
+                               until its kernels end on `stream`, so calls
+                               that may overlap (other streams) need their
+                               own workspaces                               */
     size_t workspace_bytes; /* its size; see mpgemm_workspace_bytes()          */
     int levels;             /* Strassen form: recursion levels L (1..5; 0 = 1);
                                m, n, k must be multiples of 2^L            */

@@ -53,33 +53,35 @@ __global__ __launch_bounds__(256) void axpy_kernel(int64_t n, Scal alpha, const 
 }
 
 // Leaf level: out[b] (P doubles, node-major) = ascending sum of the products
-// x_i y_i, i in [64 b, min(64 b + 64, n)).  Each wave owns 64 consecutive
-// blocks (lane = block).  Per round of 8 positions, the wave's lanes form the
-// 512 products of the round from coalesced 64-byte runs (8 lanes per block)
-// into LDS, then every lane adds its block's 8 products in order.  The
-// products and the order of the sum are those of the plain sequential loop.
-static constexpr int kDotRound = 8;
+// x_i y_i, i in [64 b, min(64 b + 64, n)).  Each wave owns 32 consecutive
+// blocks (lane L < 32 sums block b0 + L).  Per round of 16 positions, the
+// whole wave forms the 512 products of the round from coalesced 128-byte
+// runs (16 lanes per block: full cache lines) into LDS, then every lane
+// L < 32 adds its block's 16 products in order.  The products and the order
+// of the sum are those of the plain sequential loop.
+static constexpr int kDotRound = 16;
+static constexpr int kDotBlocks = 32;             // blocks per wave
 
 template <int P>
 __global__ __launch_bounds__(256) void dot_leaf_kernel(int64_t n, const double* __restrict__ x, int64_t sx,
                                                        const double* __restrict__ y, int64_t sy,
                                                        double* __restrict__ out, int64_t cnt) {
-    // per wave: [64 blocks][kDotRound + 1 (pad)][P]
-    __shared__ double prod[4][64 * (kDotRound + 1) * P];
+    // per wave: [32 blocks][kDotRound + 1 (pad)][P]
+    __shared__ double prod[4][kDotBlocks * (kDotRound + 1) * P];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double* pw = prod[wave];
-    const int64_t b0 = ((int64_t)blockIdx.x * 4 + wave) * 64;      // first block of this wave
-    if (b0 >= cnt) return;                                            // whole wave past the end
-    const int64_t b = b0 + lane;
+    const int64_t b0 = ((int64_t)blockIdx.x * 4 + wave) * kDotBlocks;   // first block of this wave
+    if (b0 >= cnt) return;                                                // whole wave past the end
+    const int64_t b = b0 + lane;                                          // summed by lanes < 32
     mp<P> acc = mp_zero<P>();
     for (int j0 = 0; j0 < kDotFanin; j0 += kDotRound) {
-        // products: lane handles (block b0 + 8 q + lane / 8, position j0 + lane % 8), q = 0..7
+        // products: lane handles (block b0 + 4 q + lane / 16, position j0 + lane % 16), q = 0..7
         // loads first (indices past the end read element n - 1 and their
         // products are never summed), then the products
         mp<P> xv[8], yv[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const int bl = 8 * q + (lane >> 3), pos = lane & 7;
+            const int bl = 4 * q + (lane >> 4), pos = lane & 15;
             const int64_t i = min((b0 + bl) * kDotFanin + j0 + pos, n - 1);
 #pragma unroll
             for (int c = 0; c < P; ++c) {
@@ -89,28 +91,30 @@ __global__ __launch_bounds__(256) void dot_leaf_kernel(int64_t n, const double* 
         }
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const int bl = 8 * q + (lane >> 3), pos = lane & 7;
+            const int bl = 4 * q + (lane >> 4), pos = lane & 15;
             const mp<P> pr = mul(xv[q], yv[q]);
 #pragma unroll
             for (int c = 0; c < P; ++c) pw[(bl * (kDotRound + 1) + pos) * P + c] = pr.c[c];
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        // sums: this lane's block, positions j0 .. j0 + 7 that exist
+        // sums: this lane's block, positions j0 .. j0 + 15 that exist
+        if (lane < kDotBlocks) {
 #pragma unroll
-        for (int pos = 0; pos < kDotRound; ++pos) {
-            const int64_t i = b * kDotFanin + j0 + pos;
-            if (b < cnt && i < n) {
-                mp<P> v;
+            for (int pos = 0; pos < kDotRound; ++pos) {
+                const int64_t i = b * kDotFanin + j0 + pos;
+                if (b < cnt && i < n) {
+                    mp<P> v;
 #pragma unroll
-                for (int c = 0; c < P; ++c) v.c[c] = pw[(lane * (kDotRound + 1) + pos) * P + c];
-                acc = add(acc, v);
+                    for (int c = 0; c < P; ++c) v.c[c] = pw[(lane * (kDotRound + 1) + pos) * P + c];
+                    acc = add(acc, v);
+                }
             }
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     }
-    if (b < cnt) {
+    if (lane < kDotBlocks && b < cnt) {
 #pragma unroll
         for (int c = 0; c < P; ++c) out[b * P + c] = acc.c[c];
     }
@@ -334,9 +338,11 @@ static int dot_t(int64_t n, const double* x, int64_t sx, const double* y, int64_
     }
     int64_t cnt = (n + kDotFanin - 1) / kDotFanin;
     double* out = cnt == 1 ? result : ws;
-    // 4 waves of 64 blocks per workgroup
-    hipLaunchKernelGGL(dot_leaf_kernel<P>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, n, x, sx, y,
-                       sy, out, cnt);
+    // 4 waves of 32 blocks per workgroup
+    const int64_t per_wg = 4 * kDotBlocks;
+    if ((cnt + per_wg - 1) / per_wg > 0x7fffffffLL) return (int)hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(dot_leaf_kernel<P>, dim3((unsigned)((cnt + per_wg - 1) / per_wg)), dim3(256), 0, st, n,
+                       x, sx, y, sy, out, cnt);
     double* in = out;
     double* free_at = ws + cnt * P;
     while (cnt > 1) {

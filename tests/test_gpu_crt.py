@@ -182,3 +182,22 @@ def test_auto_form_choice(gpu_lib, P):
     assert np.array_equal(call(big[1:]), plain)            # not 256-byte aligned: plain as well
     # m = 255 (lda stays 256): plain even with room for both split forms
     assert np.array_equal(call(big, 255), oracle.gemm(P, "N", "N", 255, n, k, alpha, A, B, beta, C))
+
+
+@pytest.mark.parametrize("P", [2, 4])
+def test_degenerate_shapes_and_scalars(gpu_lib, P):
+    """Residue form on the cases it shares with every form: k = 0 and
+    alpha = 0 (C = beta C), alpha = 0 with beta = 1 (C untouched), m = 0 or
+    n = 0 (nothing to do) -- each as the oracle has it."""
+    m, n, k = 40, 33, 70
+    A, B, C, alpha, beta = make(P, "N", "N", m, n, k, fam=9)
+    s = gpu_lib.DEFAULT_SLICES[P]
+    zero, one = np.zeros(P), synth.mp_one(P)
+    for kk, al, be in [(0, alpha, beta), (k, zero, beta), (k, zero, one)]:
+        note("crt degenerate", P, "k", kk, "alpha zero", not np.any(al), "beta one", np.array_equal(be, one))
+        got = run(gpu_lib, P, "N", "N", m, n, kk, al, A, B, be, C, s)
+        assert np.array_equal(got, oracle.gemm(P, "N", "N", m, n, kk, al, A, B, be, C))
+    for mm, nn in [(0, n), (m, 0)]:
+        note("crt empty", P, mm, nn)
+        got = run(gpu_lib, P, "N", "N", mm, nn, k, alpha, A, B, beta, C, s)
+        assert np.array_equal(got, C)

@@ -114,7 +114,7 @@ def parse():
     ap.add_argument("--strassen", action="store_true",
                     help="Strassen's method (Sec. 3, Fig. 5) against the plain form, n = 4096")
     ap.add_argument("--crt", action="store_true",
-                    help="residue (CRT) split form against the triangular split form, DD and TD")
+                    help="residue (CRT) split form against the triangular split form, DD, TD and QD")
     return ap.parse_args()
 
 

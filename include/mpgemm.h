@@ -65,12 +65,13 @@ extern "C" {
 #define MPGEMM_FORM_SPLIT_I8 1  /* operands cut into signed 7-bit INT8 digits,
                                    exact INT8 MFMA digit products, exact
                                    recombination into P components          */
-#define MPGEMM_FORM_AUTO 2      /* the library's choice: for m, n, k >= 256
-                                   the residue form (MPGEMM_FORM_SPLIT_CRT)
-                                   when the workspace (256-byte aligned)
-                                   holds it and it applies, else the split
-                                   form when the workspace holds that, else
-                                   plain; never a workspace error          */
+#define MPGEMM_FORM_AUTO 2      /* the library's choice: the residue form
+                                   (MPGEMM_FORM_SPLIT_CRT) for m, n, k >= 192
+                                   (DD) or >= 128 (TD, QD) when the
+                                   workspace (256-byte aligned) holds it and
+                                   it applies, else for m, n, k >= 256 the
+                                   split form when the workspace holds that,
+                                   else plain; never a workspace error     */
 #define MPGEMM_FORM_STRASSEN 4  /* Strassen's method (Sec. 3, Fig. 5): opts.levels
                                    levels of the seven-product recursion over
                                    plain-form block products               */

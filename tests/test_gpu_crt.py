@@ -155,8 +155,8 @@ def test_repeat_and_workspace_reuse(gpu_lib):
 def test_auto_form_choice(gpu_lib, P):
     """FORM_AUTO: the residue form when the workspace holds it, the
     triangular split form when only that fits, the plain form with no
-    workspace or below 256 in any dimension -- each bit for bit as the
-    oracle's form."""
+    workspace or below the sizes where the others pay -- each bit for bit
+    as the oracle's form."""
     import torch
     m, n, k = 256, 260, 300
     A, B, C, alpha, beta = make(P, "N", "N", m, n, k, fam=7)
@@ -180,8 +180,13 @@ def test_auto_form_choice(gpu_lib, P):
     plain = oracle.gemm(P, "N", "N", m, n, k, alpha, A, B, beta, C)
     assert np.array_equal(call(None), plain)
     assert np.array_equal(call(big[1:]), plain)            # not 256-byte aligned: plain as well
-    # m = 255 (lda stays 256): plain even with room for both split forms
-    assert np.array_equal(call(big, 255), oracle.gemm(P, "N", "N", 255, n, k, alpha, A, B, beta, C))
+    # below the residue form's smallest size (DD 192, TD and QD 128; lda
+    # stays 256): the triangular split form needs 256, so plain
+    mm = 191 if P == 2 else 127
+    assert np.array_equal(call(big, mm), oracle.gemm(P, "N", "N", mm, n, k, alpha, A, B, beta, C))
+    # from that size on the residue form, also with little room above it
+    mm = 192 if P == 2 else 128
+    assert np.array_equal(call(big, mm), oracle.gemm_crt(P, s, "N", "N", mm, n, k, alpha, A, B, beta, C))
 
 
 @pytest.mark.parametrize("P", [2, 4])

@@ -60,26 +60,50 @@ struct PlainTile {
         }
     }
 
-    __device__ static void step(const double* As, const double* Bs, int kk, int tx, int ty,
+    // Rows rb + r RS (r < TM) and columns cb + c CS (c < TN) of the tile.
+    template <int RS, int CS>
+    __device__ static void step(const double* As, const double* Bs, int kk, int rb, int cb,
                                 mp<P> (&acc)[TM][TN]) {
         mp<P> a[TM], b[TN];
 #pragma unroll
         for (int r = 0; r < TM; ++r)
 #pragma unroll
-            for (int p = 0; p < P; ++p) a[r].c[p] = As[(p * BK + kk) * BM + tx + r * TX];
+            for (int p = 0; p < P; ++p) a[r].c[p] = As[(p * BK + kk) * BM + rb + r * RS];
 #pragma unroll
         for (int c = 0; c < TN; ++c)
 #pragma unroll
-            for (int p = 0; p < P; ++p) b[c].c[p] = Bs[(p * BK + kk) * BN + ty + c * TY];
+            for (int p = 0; p < P; ++p) b[c].c[p] = Bs[(p * BK + kk) * BN + cb + c * CS];
         tile_mac_v<V, TM, TN>(acc, a, b);
     }
 
+    // Thread-to-entry maps.  The default interleaves a thread's TM rows TX
+    // apart and its TN columns TY apart.  The wave-quadrant map (16 x 16
+    // threads, four waves) gives each wave one quadrant of the tile, its 64
+    // lanes as 8 x 8 with TM rows and TN columns 8 apart; on a tile that
+    // overhangs the matrix a wave whose quadrant lies wholly outside it skips
+    // the k loop.  Either way each entry keeps its own ascending chain.
+    static constexpr bool kQuadOk = (TX == 16 && TY == 16);
+
+    template <bool QUAD = false>
     __device__ static void run(const GemmArgs& g, const mp<P>& alpha, const mp<P>& beta,
                                int64_t m0, int64_t n0, double* lds) {
+        constexpr bool Q = QUAD && kQuadOk;
+        constexpr int RS = Q ? 8 : TX, CS = Q ? 8 : TY;
         double* As = lds;
         double* Bs = lds + P * BK * BM;
         const int tid = threadIdx.x;
-        const int tx = tid % TX, ty = tid / TX;
+        int rb, cb;
+        bool busy = true;   // this wave has entries inside the matrix
+        if constexpr (Q) {
+            const int w = tid >> 6, lane = tid & 63;
+            const int qr = (w & 1) * (BM / 2), qc = (w >> 1) * (BN / 2);
+            rb = qr + (lane & 7);
+            cb = qc + (lane >> 3);
+            busy = (m0 + qr < g.m) && (n0 + qc < g.n);
+        } else {
+            rb = tid % TX;
+            cb = tid / TX;
+        }
         mp<P> acc[TM][TN];
 #pragma unroll
         for (int r = 0; r < TM; ++r)
@@ -100,12 +124,12 @@ struct PlainTile {
             stage(g, m0, n0, k0, As, Bs);
             __syncthreads();
             const int64_t rem = g.k - k0;
-            if (rem >= BK) {
+            if (busy && rem >= BK) {
 #pragma unroll 2
-                for (int kk = 0; kk < BK; ++kk) step(As, Bs, kk, tx, ty, acc);
-            } else {
+                for (int kk = 0; kk < BK; ++kk) step<RS, CS>(As, Bs, kk, rb, cb, acc);
+            } else if (busy) {
                 const int kb = (int)rem;
-                for (int kk = 0; kk < kb; ++kk) step(As, Bs, kk, tx, ty, acc);
+                for (int kk = 0; kk < kb; ++kk) step<RS, CS>(As, Bs, kk, rb, cb, acc);
             }
             __syncthreads();
         }
@@ -114,7 +138,7 @@ struct PlainTile {
         for (int r = 0; r < TM; ++r)
 #pragma unroll
             for (int c = 0; c < TN; ++c) {
-                const int64_t i = m0 + tx + r * TX, j = n0 + ty + c * TY;
+                const int64_t i = m0 + rb + r * RS, j = n0 + cb + c * CS;
                 if (i < g.m && j < g.n) {
                     const int64_t off = i + j * g.ldc;
                     mp<P> t;
@@ -215,7 +239,7 @@ __global__ __launch_bounds__(TX * TY) void batch_gemm_kernel(const BatchDesc* __
         const int64_t tm = local % d.tiles_m, tn = local / d.tiles_m;
         const mp<P> alpha = load_scalar<P>(d.g.alpha);
         const mp<P> beta = load_scalar<P>(d.g.beta);
-        T::run(d.g, alpha, beta, tm * T::BM, tn * T::BN, lds);
+        T::template run<true>(d.g, alpha, beta, tm * T::BM, tn * T::BN, lds);
     }
 }
 

@@ -12,9 +12,10 @@ from tests.gpu_util import dev, host, note
 pytestmark = pytest.mark.gpu
 
 
-def problems(P, count, lo, hi, fam=5, seed_slot="shapes"):
-    rng = synth.rng_for(fam, seed_slot)
-    shapes = rng.integers(lo, hi + 1, size=(count, 3))
+def problems(P, count, lo, hi, fam=5, seed_slot="shapes", shapes=None):
+    if shapes is None:
+        rng = synth.rng_for(fam, seed_slot)
+        shapes = rng.integers(lo, hi + 1, size=(count, 3))
     out = []
     for q, (m, n, k) in enumerate(shapes):
         m, n, k = int(m), int(n), int(k)
@@ -58,6 +59,31 @@ def test_batch_matches_oracle_and_single_calls(gpu_lib, P):
                            p["B"], p["beta"], p["C"])
         assert np.array_equal(got, want), (P, q, p["m"], p["n"], p["k"])
     plan.close()
+
+
+# Shapes that end inside, at and just past the quadrant and tile edges of
+# every batched tile (tiles 16..64 rows by 16..64 columns).
+EDGE_SHAPES = [(8, 8, 5), (9, 17, 16), (16, 16, 17), (17, 33, 3), (24, 8, 33), (32, 40, 1),
+               (33, 64, 20), (40, 7, 31), (64, 65, 18), (65, 31, 47), (96, 100, 12), (1, 1, 1)]
+
+
+@pytest.mark.parametrize("P", [2, 3, 4])
+def test_every_batched_tile_on_edge_shapes(gpu_lib, P):
+    """Each batched tile configuration (its waves own tile quadrants and skip
+    those wholly outside a problem) is bit-identical to the oracle on shapes
+    ending inside, at and past the quadrant edges."""
+    probs = problems(P, 0, 0, 0, shapes=EDGE_SHAPES)
+    wants = [oracle.gemm(P, p["transa"], p["transb"], p["m"], p["n"], p["k"], p["alpha"], p["A"],
+                         p["B"], p["beta"], p["C"]) for p in probs]
+    for cfg in range(gpu_lib.num_configs(P, "batched")):
+        dprobs = to_dev(probs)
+        note("batch tile", P, cfg)
+        plan = gpu_lib.BatchPlan(P, dprobs, tile=cfg)
+        assert plan.info()["tile_cfg"] == cfg
+        plan.run()
+        for q, (d, w) in enumerate(zip(dprobs, wants)):
+            assert np.array_equal(host(d["C"]), w), (P, cfg, q, EDGE_SHAPES[q])
+        plan.close()
 
 
 @pytest.mark.parametrize("P", [2, 3])

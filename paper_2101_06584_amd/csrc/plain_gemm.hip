@@ -174,8 +174,15 @@ __device__ __forceinline__ mp<P> load_scalar(const double* v) {
     return r;
 }
 
+// Waves per SIMD that a tile's register budget is held to (1: no bound).
+// The DD 64 x 64 tile takes 180 registers unbounded, which leaves two waves
+// per SIMD; at 168 a third wave hides the LDS reads and the staging.
+template <int P, int TM, int TN>
+constexpr int plain_waves_per_eu() { return (P == 2 && TM * TN >= 16) ? 3 : 1; }
+
 template <int P, int TX, int TY, int TM, int TN, int BK, int V = 0>
-__global__ __launch_bounds__(TX * TY) void plain_gemm_kernel(GemmArgs g) {
+__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(plain_waves_per_eu<P, TM, TN>())))
+void plain_gemm_kernel(GemmArgs g) {
     using T = PlainTile<P, TX, TY, TM, TN, BK, V>;
     __shared__ double lds[T::LDS_DOUBLES];
     int64_t tm, tn;
@@ -189,8 +196,8 @@ __global__ __launch_bounds__(TX * TY) void plain_gemm_kernel(GemmArgs g) {
 // Strided batch of equal-shape products (Strassen's leaves): problem z =
 // blockIdx.y uses A + z zA, B + z zB, C + z zC; alpha and beta from g.
 template <int P, int TX, int TY, int TM, int TN, int BK>
-__global__ __launch_bounds__(TX * TY) void plain_gemm_strided_kernel(GemmArgs g, int64_t zA, int64_t zB,
-                                                                      int64_t zC) {
+__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(plain_waves_per_eu<P, TM, TN>())))
+void plain_gemm_strided_kernel(GemmArgs g, int64_t zA, int64_t zB, int64_t zC) {
     using T = PlainTile<P, TX, TY, TM, TN, BK>;
     __shared__ double lds[T::LDS_DOUBLES];
     int64_t tm, tn;

@@ -66,8 +66,8 @@ extern "C" {
                                    exact INT8 MFMA digit products, exact
                                    recombination into P components          */
 #define MPGEMM_FORM_AUTO 2      /* the library's choice: the residue form
-                                   (MPGEMM_FORM_SPLIT_CRT) for m, n, k >= 192
-                                   (DD) or >= 128 (TD, QD) when the
+                                   (MPGEMM_FORM_SPLIT_CRT) for m, n, k >= 128
+                                   (DD), 96 (TD) or 64 (QD) when the
                                    workspace (256-byte aligned) holds it and
                                    it applies, else for m, n, k >= 256 the
                                    split form when the workspace holds that,

@@ -232,9 +232,9 @@ int gemm_common(int P, char ta, char tb, int64_t m, int64_t n, int64_t k, const 
     const int s = (has_opts && opts->slices > 0) ? opts->slices : kDefaultSlices[P];
     const int req_tile = has_opts ? opts->tile : -1;
     if (last_stage > 0) form = MPGEMM_FORM_SPLIT_I8;
-    // the residue form's smallest sizes, measured: from 192 (DD) and 128 (TD,
-    // QD) in every dimension it beats the plain and the triangular forms
-    const int64_t crt_min = P == 2 ? 192 : 128;
+    // the residue form's smallest sizes, measured: from 128 (DD), 96 (TD) and
+    // 64 (QD) in every dimension it beats the plain and the triangular forms
+    const int64_t crt_min = P == 2 ? 128 : (P == 3 ? 96 : 64);
     if (form == MPGEMM_FORM_AUTO && m >= crt_min && n >= crt_min && k >= crt_min && opts->workspace &&
         (uintptr_t)opts->workspace % 256 == 0 && crt_products(P, k, s) > 0) {
         // the residue form first: the fastest split variant wherever it applies

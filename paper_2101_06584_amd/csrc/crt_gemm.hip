@@ -104,9 +104,22 @@ const CrtTables& crt_host_tables() {
 
 // Per-operand digit weights, passed by value: w[t][p] congruent to
 // 128^(s - 1 - p) (times u_t for op(A)) modulo m_t, in [-128, 127]; zero for
-// p >= s and t >= N (64 columns: two MFMA groups of 32 moduli).
+// p >= s and t >= N.  The kernels' two MFMA groups span 64 moduli; rows past
+// the table are zero.  Both operands' tables travel in one launch's
+// arguments (2 x 1568 bytes).
 struct CrtWeights {
-    int8_t w[64][32];
+    int8_t w[kNumModuli][32];
+};
+
+// One operand of the residue pass: row r of the matrix whose element (r, l)
+// of component p sits at X[p ps + r rs + l ls]; E its row exponents; R its
+// residue planes, Rp padded rows.
+struct ResOperand {
+    const double* X;
+    int64_t rs, ls, ps, count;
+    const int32_t* E;
+    int8_t* R;
+    int64_t Rp;
 };
 
 // Output tile (bm x bn) of the per-modulus product and workgroups per CU.
@@ -184,18 +197,25 @@ __device__ __forceinline__ int next_digit(double (&r)[P], int p) {
     return (int)d;
 }
 
+// Both operands in one launch: blockIdx.z = 0 takes op(A) with weights wa,
+// 1 op(B) with wb; blockIdx.y beyond an operand's padded rows has no work.
 template <int P, int NG, int SETS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void crt_residue_kernel(const double* __restrict__ X, int64_t rs,
-                                                          int64_t ls, int64_t ps, int64_t count,
-                                                          int64_t k, const int32_t* __restrict__ E,
-                                                          int s, int N, int shi, CrtWeights wt,
-                                                          int8_t* __restrict__ R, int64_t Rp,
-                                                          int64_t Kp) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void crt_residue_kernel(
+    ResOperand oa, ResOperand ob, CrtWeights wa, CrtWeights wb, int64_t k, int s, int N, int shi,
+    int64_t Kp) {
+    const bool second = blockIdx.z != 0;
+    const ResOperand o = second ? ob : oa;
+    const CrtWeights* __restrict__ wt = second ? &wb : &wa;
+    const double* __restrict__ X = o.X;
+    const int64_t rs = o.rs, ls = o.ls, ps = o.ps, count = o.count, Rp = o.Rp;
+    const int32_t* __restrict__ E = o.E;
+    int8_t* __restrict__ R = o.R;
+    const int64_t r0 = (int64_t)blockIdx.y * kResRows;
+    if (r0 >= Rp) return;                         // the whole block: before any barrier
     constexpr int kTileBytes = P * kResRows * (kTileK + 1) * 8;
     __shared__ __align__(16) uint8_t lds[kTileBytes > kStageBytes ? kTileBytes : kStageBytes];
     double (*tile)[kResRows][kTileK + 1] = reinterpret_cast<double (*)[kResRows][kTileK + 1]>(lds);
     const int64_t seg = blockIdx.x;
-    const int64_t r0 = (int64_t)blockIdx.y * kResRows;
     const int64_t l0 = seg * kTileK;
     const int t = threadIdx.x;
     const bool rows_contig = (rs == 1);
@@ -222,8 +242,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void c
 #pragma unroll
     for (int cg = 0; cg < NG; ++cg) {
         const int tt = 32 * cg + (lane & 31);
-        const uint32_t* wp = (const uint32_t*)wt.w[tt] + 4 * (lane >> 5);
-        const v4i row = v4i{(int)wp[0], (int)wp[1], (int)wp[2], (int)wp[3]};
+        v4i row = v4i{0, 0, 0, 0};
+        if (tt < kNumModuli) {
+            const uint32_t* wp = (const uint32_t*)wt->w[tt] + 4 * (lane >> 5);
+            row = v4i{(int)wp[0], (int)wp[1], (int)wp[2], (int)wp[3]};
+        }
         if constexpr (SETS == 1) {
             bw[0][cg] = row;
         } else {
@@ -1125,13 +1148,15 @@ int limbs_for(int N) {
     return top <= 4 ? 4 : top <= 6 ? 6 : top <= 8 ? 8 : 11;
 }
 
-int launch_residues(int P, int sets, const double* X, int64_t rs, int64_t ls, int64_t ps, int64_t count,
-                    int64_t k, const int32_t* E, int s, int N, int shi, const CrtWeights& w, int8_t* R,
-                    int64_t Rp, int64_t Kp, hipStream_t st) {
-    const dim3 grid((unsigned)(Kp / kTileK), (unsigned)(Rp / kResRows));
-#define MPG_RES(PV, NGV, SV)                                                                           \
-    hipLaunchKernelGGL((crt_residue_kernel<PV, NGV, SV>), grid, dim3(256), 0, st, X, rs, ls, ps, count, k, \
-                       E, s, N, shi, w, R, Rp, Kp)
+int launch_residues(int P, int sets, const ResOperand& a, const ResOperand& b, const CrtWeights& wa,
+                    const CrtWeights& wb, int64_t k, int s, int N, int shi, int64_t Kp, hipStream_t st) {
+    const int64_t rows = (a.Rp > b.Rp ? a.Rp : b.Rp) / kResRows;
+    if (Kp / kTileK > 0x7fffffffLL || rows > 65535) return (int)hipErrorInvalidConfiguration;
+    if (rows == 0 || Kp == 0) return 0;
+    const dim3 grid((unsigned)(Kp / kTileK), (unsigned)rows, 2);
+#define MPG_RES(PV, NGV, SV)                                                                     \
+    hipLaunchKernelGGL((crt_residue_kernel<PV, NGV, SV>), grid, dim3(256), 0, st, a, b, wa, wb, k, s, N, \
+                       shi, Kp)
     const bool two = N > 32;
     if (sets == 3) {                             // two levels: QD only
         if (two) MPG_RES(4, 2, 3); else MPG_RES(4, 1, 3);
@@ -1314,14 +1339,12 @@ int launch_crt(int P, int s, int cfg, const GemmArgs& g, void* ws, hipStream_t s
     const CrtWeights wb = crt_weights(N, s, pl.shi, false);
     int rc;
     uint64_t* MX = (uint64_t*)(base + L.oMX);
-    if ((rc = launch_row_exponents(g.A, a_rs, a_ls, g.m, L.Mp, g.k, E, MX, st))) return rc;
-    if ((rc = launch_row_exponents(g.B, b_rs, b_ls, g.n, L.Np, g.k, F, MX + L.Mp, st))) return rc;
-    if ((rc = launch_residues(P, pl.sets, g.A, a_rs, a_ls, g.sa, g.m, g.k, E, s, N, pl.shi, wa, RA, L.Mp,
-                              L.Kp, st)))
+    if ((rc = launch_row_exponents(g.A, a_rs, a_ls, g.m, L.Mp, g.B, b_rs, b_ls, g.n, L.Np, g.k, E, F, MX,
+                                   st)))
         return rc;
-    if ((rc = launch_residues(P, pl.sets, g.B, b_rs, b_ls, g.sb, g.n, g.k, F, s, N, pl.shi, wb, RB, L.Np,
-                              L.Kp, st)))
-        return rc;
+    const ResOperand oa{g.A, a_rs, a_ls, g.sa, g.m, E, RA, L.Mp};
+    const ResOperand ob{g.B, b_rs, b_ls, g.sb, g.n, F, RB, L.Np};
+    if ((rc = launch_residues(P, pl.sets, oa, ob, wa, wb, g.k, s, N, pl.shi, L.Kp, st))) return rc;
     if ((rc = launch_crt_mfma(cfg, RA, RB, Y, L.Mp, L.Np, L.Kp, N * pl.sets, N, st))) return rc;
     if (pl.sets == 3) {
         if (N > kRec3MaxN) return (int)hipErrorInvalidValue;

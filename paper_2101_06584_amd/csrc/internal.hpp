@@ -75,11 +75,13 @@ int launch_split(int P, int s, int cfg, const GemmArgs& g, void* ws, size_t ws_b
 int split_layout(int P, int64_t m, int64_t n, int64_t k, int s, int cfg, size_t* offE, size_t* offF,
                  size_t* offDA, size_t* offDB, size_t* offS, int64_t* Mp, int64_t* Np, int64_t* Kp);
 
-// Scale exponents of the split forms (stage 1 above): row r of a matrix whose
-// element (r, l) sits at X[r rs + l ls]; E[r] = 0 for count <= r < padded;
-// mx: scratch of `count` 64-bit words (device).
-int launch_row_exponents(const double* X, int64_t rs, int64_t ls, int64_t count, int64_t padded,
-                         int64_t k, int32_t* E, uint64_t* mx, hipStream_t st);
+// Scale exponents of the split forms (stage 1 above) for op(A)'s rows and
+// op(B)'s columns: row r of a matrix whose element (r, l) sits at
+// X[r rs + l ls]; E[r] = 0 for count <= r < padded (m, Mp for op(A) into E;
+// n, Np for op(B) into F); mx: scratch of Mp + Np 64-bit words (device).
+int launch_row_exponents(const double* A, int64_t a_rs, int64_t a_ls, int64_t m, int64_t Mp,
+                         const double* B, int64_t b_rs, int64_t b_ls, int64_t n, int64_t Np,
+                         int64_t k, int32_t* E, int32_t* F, uint64_t* mx, hipStream_t st);
 
 // Residue (CRT) form of the split product (crt_gemm.hip).
 constexpr int kCrtConfigs = 3;

@@ -127,20 +127,24 @@ __global__ __launch_bounds__(256) void exponent_finish_kernel(const unsigned lon
 }
 
 // One wave per row, lanes along l (coalesced when l is contiguous, ls == 1).
-__global__ __launch_bounds__(256) void exponent_rows_wave_kernel(const double* __restrict__ X,
-                                                                 int64_t rs, int64_t ls,
-                                                                 int64_t count, int64_t padded,
-                                                                 int64_t k,
-                                                                 int32_t* __restrict__ E) {
+// Both operands in one launch: blockIdx.y picks the matrix.
+struct RowSet {
+    const double* X;
+    int64_t rs, ls, count, padded;
+    int32_t* E;
+};
+
+__global__ __launch_bounds__(256) void exponent_rows_wave_kernel(RowSet a, RowSet b, int64_t k) {
+    const RowSet o = blockIdx.y ? b : a;
     const int lane = threadIdx.x & 63;
     const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (r >= padded) return;
+    if (r >= o.padded) return;
     double M = 0.0;
-    if (r < count)
-        for (int64_t l = lane; l < k; l += 64) M = fmax(M, fabs(X[r * rs + l * ls]));
+    if (r < o.count)
+        for (int64_t l = lane; l < k; l += 64) M = fmax(M, fabs(o.X[r * o.rs + l * o.ls]));
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) M = fmax(M, __shfl_xor(M, off, 64));
-    if (lane == 0) E[r] = (r < count) ? scale_exponent(M) : 0;
+    if (lane == 0) o.E[r] = (r < o.count) ? scale_exponent(M) : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -497,12 +501,16 @@ __global__ __launch_bounds__(256) void recombine_kernel(GemmArgs g, const int32_
 // Host side.
 // ---------------------------------------------------------------------------
 
+// contiguous rows: k-chunked maxima (three launches) pay off on large
+// operands; up to 2^18 entries one wave per row (strided loads) is one
+// launch and the same maxima
+static bool exponents_chunked(int64_t rs, int64_t count, int64_t k) {
+    return rs == 1 && count * k > ((int64_t)1 << 18);
+}
+
 static int launch_exponents(const double* X, int64_t rs, int64_t ls, int64_t count, int64_t padded,
                             int64_t k, int32_t* E, uint64_t* mx, hipStream_t st) {
-    // contiguous rows: k-chunked maxima (three launches) pay off on large
-    // operands; up to 2^18 entries one wave per row (strided loads) is one
-    // launch and the same maxima
-    if (rs == 1 && count * k > ((int64_t)1 << 18)) {
+    if (exponents_chunked(rs, count, k)) {
         const int64_t cb = (count + 255) / 256, pb = (padded + 255) / 256;
         const int64_t chunks = (k + kExpChunk - 1) / kExpChunk;
         if (chunks > 65535) return (int)hipErrorInvalidConfiguration;
@@ -516,15 +524,35 @@ static int launch_exponents(const double* X, int64_t rs, int64_t ls, int64_t cou
         hipLaunchKernelGGL(exponent_finish_kernel, dim3((unsigned)pb), dim3(256), 0, st, m, count, padded, E);
     } else {
         const int64_t blocks = (padded + 3) / 4;
-        hipLaunchKernelGGL(exponent_rows_wave_kernel, dim3((unsigned)blocks), dim3(256), 0, st, X, rs,
-                           ls, count, padded, k, E);
+        if (blocks > 0x7fffffffLL) return (int)hipErrorInvalidConfiguration;
+        const RowSet o{X, rs, ls, count, padded, E};
+        if (blocks > 0)
+            hipLaunchKernelGGL(exponent_rows_wave_kernel, dim3((unsigned)blocks), dim3(256), 0, st, o, o, k);
     }
     return (int)hipGetLastError();
 }
 
-int launch_row_exponents(const double* X, int64_t rs, int64_t ls, int64_t count, int64_t padded,
-                         int64_t k, int32_t* E, uint64_t* mx, hipStream_t st) {
-    return launch_exponents(X, rs, ls, count, padded, k, E, mx, st);
+// Exponents of op(A)'s rows and op(B)'s columns; when neither takes the
+// chunked path, one launch covers both (they then run side by side).
+static int launch_exponents_pair(const double* A, int64_t a_rs, int64_t a_ls, int64_t m, int64_t Mp,
+                                 const double* B, int64_t b_rs, int64_t b_ls, int64_t n, int64_t Np,
+                                 int64_t k, int32_t* E, int32_t* F, uint64_t* mx, hipStream_t st) {
+    if (exponents_chunked(a_rs, m, k) || exponents_chunked(b_rs, n, k)) {
+        int rc = launch_exponents(A, a_rs, a_ls, m, Mp, k, E, mx, st);
+        return rc ? rc : launch_exponents(B, b_rs, b_ls, n, Np, k, F, mx + Mp, st);
+    }
+    const int64_t blocks = ((Mp > Np ? Mp : Np) + 3) / 4;
+    if (blocks > 0x7fffffffLL) return (int)hipErrorInvalidConfiguration;
+    if (blocks > 0)
+        hipLaunchKernelGGL(exponent_rows_wave_kernel, dim3((unsigned)blocks, 2), dim3(256), 0, st,
+                           RowSet{A, a_rs, a_ls, m, Mp, E}, RowSet{B, b_rs, b_ls, n, Np, F}, k);
+    return (int)hipGetLastError();
+}
+
+int launch_row_exponents(const double* A, int64_t a_rs, int64_t a_ls, int64_t m, int64_t Mp,
+                         const double* B, int64_t b_rs, int64_t b_ls, int64_t n, int64_t Np,
+                         int64_t k, int32_t* E, int32_t* F, uint64_t* mx, hipStream_t st) {
+    return launch_exponents_pair(A, a_rs, a_ls, m, Mp, B, b_rs, b_ls, n, Np, k, E, F, mx, st);
 }
 
 static int launch_slices(int P, const double* X, int64_t rs, int64_t ls, int64_t ps, int64_t count,
@@ -591,8 +619,9 @@ int launch_split_stages(int P, int s, int cfg, int last, const GemmArgs& g, void
     // columns of op(B): element (j, l) = op(B)(l, j)
     const int64_t b_rs = g.tb ? 1 : g.ldb, b_ls = g.tb ? g.ldb : 1;
     int rc;
-    if ((rc = launch_exponents(g.A, a_rs, a_ls, g.m, Mp, g.k, E, MX, st))) return rc;
-    if ((rc = launch_exponents(g.B, b_rs, b_ls, g.n, Np, g.k, F, MX + Mp, st))) return rc;
+    if ((rc = launch_exponents_pair(g.A, a_rs, a_ls, g.m, Mp, g.B, b_rs, b_ls, g.n, Np, g.k, E, F, MX,
+                                    st)))
+        return rc;
     if (last <= 1) return 0;
     if ((rc = launch_slices(P, g.A, a_rs, a_ls, g.sa, g.m, g.k, E, s, DA, Mp, Kp, st))) return rc;
     if ((rc = launch_slices(P, g.B, b_rs, b_ls, g.sb, g.n, g.k, F, s, DB, Np, Kp, st))) return rc;

@@ -180,12 +180,12 @@ def test_auto_form_choice(gpu_lib, P):
     plain = oracle.gemm(P, "N", "N", m, n, k, alpha, A, B, beta, C)
     assert np.array_equal(call(None), plain)
     assert np.array_equal(call(big[1:]), plain)            # not 256-byte aligned: plain as well
-    # below the residue form's smallest size (DD 192, TD and QD 128; lda
+    # below the residue form's smallest size (DD 128, TD 96, QD 64; lda
     # stays 256): the triangular split form needs 256, so plain
-    mm = 191 if P == 2 else 127
+    mm = {2: 127, 3: 95, 4: 63}[P]
     assert np.array_equal(call(big, mm), oracle.gemm(P, "N", "N", mm, n, k, alpha, A, B, beta, C))
     # from that size on the residue form, also with little room above it
-    mm = 192 if P == 2 else 128
+    mm = {2: 128, 3: 96, 4: 64}[P]
     assert np.array_equal(call(big, mm), oracle.gemm_crt(P, s, "N", "N", mm, n, k, alpha, A, B, beta, C))
 
 

@@ -121,6 +121,9 @@ struct ResOperand {
     int8_t* R;
     int64_t Rp;
 };
+// the residue kernel's arguments (plus the runtime's hidden ones) stay
+// within the 4 KiB a launch may carry
+static_assert(2 * sizeof(CrtWeights) + 2 * sizeof(ResOperand) + 64 <= 3584, "residue kernel arguments");
 
 // Output tile (bm x bn) of the per-modulus product and workgroups per CU.
 struct CrtConfig {

@@ -223,9 +223,8 @@ struct BatchDesc {
 };
 
 template <int P, int TX, int TY, int TM, int TN, int BK>
-__global__ __launch_bounds__(TX * TY) void batch_gemm_kernel(const BatchDesc* __restrict__ desc,
-                                                             int64_t count, int64_t total_tiles,
-                                                             unsigned* counter) {
+__global__ __launch_bounds__(TX * TY) void batch_gemm_kernel(const BatchDesc* __restrict__ desc, int64_t count,
+                                                             int64_t total_tiles, unsigned* counter) {
     using T = PlainTile<P, TX, TY, TM, TN, BK>;
     __shared__ double lds[T::LDS_DOUBLES];
     __shared__ int64_t s_tile;

@@ -51,6 +51,11 @@ CASES = [
     (4, "T", "N", 33, 129, 70, 32, 1),     # 16 + 16
     (4, "N", "T", 66, 40, 300, 25, 2),     # 13 + 12
     (4, "T", "T", 17, 19, 2000, 28, 0),    # 14 + 14, 32 k-tiles
+    # op(A) and op(B) padded to different row counts: the shared residue
+    # launch has row blocks past the shorter operand
+    (2, "N", "N", 600, 40, 150, 16, 0),    # 768 vs 256 rows
+    (3, "N", "T", 300, 9, 64, 23, 2),      # 384 vs 128
+    (4, "T", "N", 20, 530, 90, 31, 1),     # two levels; 256 vs 640
 ]
 
 

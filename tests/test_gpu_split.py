@@ -46,6 +46,8 @@ CASES = [
     (4, "T", "T", 129, 31, 70, 30, 0),
     (4, "N", "N", 1, 1, 1, 9, 1),
     (3, "T", "N", 200, 3, 129, 18, 0),
+    (2, "N", "N", 700, 20, 90, 16, 1),     # operands padded to different row counts
+    (4, "T", "T", 9, 450, 60, 31, 0),
 ]
 
 

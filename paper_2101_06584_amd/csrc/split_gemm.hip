@@ -165,14 +165,29 @@ __device__ __forceinline__ void vec_sum_inplace(double (&r)[P]) {
     r[0] = s;
 }
 
+// One operand of the slicing pass: element (r, l) of component p at
+// X[p ps + r rs + l ls]; E its exponents; D its digit planes, Rp padded rows.
+struct SliceOperand {
+    const double* X;
+    int64_t rs, ls, ps, count;
+    const int32_t* E;
+    int8_t* D;
+    int64_t Rp;
+};
+
+// Both operands in one launch: blockIdx.z picks op(A) (0) or op(B) (1);
+// row blocks past an operand's padded rows have no work.
 template <int P>
-__global__ __launch_bounds__(256) void slice_kernel(const double* __restrict__ X, int64_t rs,
-                                                    int64_t ls, int64_t ps, int64_t count,
-                                                    int64_t k, const int32_t* __restrict__ E,
-                                                    int s, int8_t* __restrict__ D, int64_t Rp,
+__global__ __launch_bounds__(256) void slice_kernel(SliceOperand oa, SliceOperand ob, int64_t k, int s,
                                                     int64_t Kp) {
-    __shared__ double tile[P][kSliceTile][kSliceTile + 1];
+    const SliceOperand o = blockIdx.z ? ob : oa;
+    const double* __restrict__ X = o.X;
+    const int64_t rs = o.rs, ls = o.ls, ps = o.ps, count = o.count, Rp = o.Rp;
+    const int32_t* __restrict__ E = o.E;
+    int8_t* __restrict__ D = o.D;
     const int64_t r0 = (int64_t)blockIdx.y * kSliceTile;
+    if (r0 >= Rp) return;                         // the whole block: before the barrier
+    __shared__ double tile[P][kSliceTile][kSliceTile + 1];
     const int64_t l0 = (int64_t)blockIdx.x * kSliceTile;
     const int t = threadIdx.x;
     const bool rows_contig = (rs == 1);
@@ -555,16 +570,18 @@ int launch_row_exponents(const double* A, int64_t a_rs, int64_t a_ls, int64_t m,
     return launch_exponents_pair(A, a_rs, a_ls, m, Mp, B, b_rs, b_ls, n, Np, k, E, F, mx, st);
 }
 
-static int launch_slices(int P, const double* X, int64_t rs, int64_t ls, int64_t ps, int64_t count,
-                         int64_t k, const int32_t* E, int s, int8_t* D, int64_t Rp, int64_t Kp,
+static int launch_slices(int P, const SliceOperand& a, const SliceOperand& b, int64_t k, int s, int64_t Kp,
                          hipStream_t st) {
-    const dim3 grid((unsigned)(Kp / kSliceTile), (unsigned)(Rp / kSliceTile));
+    const int64_t rows = (a.Rp > b.Rp ? a.Rp : b.Rp) / kSliceTile;
+    if (Kp / kSliceTile > 0x7fffffffLL || rows > 65535) return (int)hipErrorInvalidConfiguration;
+    if (rows == 0 || Kp == 0) return 0;
+    const dim3 grid((unsigned)(Kp / kSliceTile), (unsigned)rows, 2);
     if (P == 2)
-        hipLaunchKernelGGL(slice_kernel<2>, grid, dim3(256), 0, st, X, rs, ls, ps, count, k, E, s, D, Rp, Kp);
+        hipLaunchKernelGGL(slice_kernel<2>, grid, dim3(256), 0, st, a, b, k, s, Kp);
     else if (P == 3)
-        hipLaunchKernelGGL(slice_kernel<3>, grid, dim3(256), 0, st, X, rs, ls, ps, count, k, E, s, D, Rp, Kp);
+        hipLaunchKernelGGL(slice_kernel<3>, grid, dim3(256), 0, st, a, b, k, s, Kp);
     else
-        hipLaunchKernelGGL(slice_kernel<4>, grid, dim3(256), 0, st, X, rs, ls, ps, count, k, E, s, D, Rp, Kp);
+        hipLaunchKernelGGL(slice_kernel<4>, grid, dim3(256), 0, st, a, b, k, s, Kp);
     return (int)hipGetLastError();
 }
 
@@ -623,8 +640,9 @@ int launch_split_stages(int P, int s, int cfg, int last, const GemmArgs& g, void
                                     st)))
         return rc;
     if (last <= 1) return 0;
-    if ((rc = launch_slices(P, g.A, a_rs, a_ls, g.sa, g.m, g.k, E, s, DA, Mp, Kp, st))) return rc;
-    if ((rc = launch_slices(P, g.B, b_rs, b_ls, g.sb, g.n, g.k, F, s, DB, Np, Kp, st))) return rc;
+    const SliceOperand sa{g.A, a_rs, a_ls, g.sa, g.m, E, DA, Mp};
+    const SliceOperand sb{g.B, b_rs, b_ls, g.sb, g.n, F, DB, Np};
+    if ((rc = launch_slices(P, sa, sb, g.k, s, Kp, st))) return rc;
     if (last <= 2) return 0;
     if ((rc = launch_diag(cfg, DA, DB, S, Mp, Np, Kp, s, st))) return rc;
     if (last <= 3) return 0;

@@ -316,7 +316,7 @@ __global__ void vec_kernel(int64_t n, const double* __restrict__ x, int64_t sx,
     X(3, 0, 16, 16, 2, 2, 16)      \
     X(3, 1, 16, 16, 4, 2, 16)      \
     X(3, 2, 16, 16, 1, 2, 16)      \
-    X(3, 3, 16, 16, 2, 4, 16)      \
+    X(3, 3, 16, 16, 1, 1, 16)      \
     X(4, 0, 16, 16, 2, 2, 16)      \
     X(4, 1, 16, 16, 1, 2, 16)      \
     X(4, 2, 16, 16, 2, 1, 16)      \

@@ -60,6 +60,8 @@ def lib():
         L.ref_split_slices.argtypes = [_int, _int, _ch, _int, _i64, _i64, C.c_void_p, _i64, _i64,
                                        C.c_void_p, C.c_void_p]
         L.ref_split_slices.restype = None
+        L.ref_split_recombine.argtypes = [_int, _int, _i64, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.ref_split_recombine.restype = _int
         L.ref_num_threads.restype = _int
         _LIB = L
     return _LIB
@@ -256,6 +258,20 @@ def split_slices(P, s, t, is_b, count, k, X, E):
     lib().ref_split_slices(P, s, t.encode(), int(is_b), count, k, _ptr(X), X.shape[2],
                            X.shape[1] * X.shape[2], _ptr(E), _ptr(D))
     return D
+
+
+def split_recombine(P, s, S, ef):
+    """Exact recombination of rows of anti-diagonal sums S (count, s) int64
+    with scale exponents ef (count,) = E_i + F_j: (count, P) components."""
+    S = np.ascontiguousarray(S, dtype=np.int64)
+    ef = np.ascontiguousarray(ef, dtype=np.int32)
+    count = S.shape[0]
+    assert S.shape == (count, s) and ef.shape == (count,)
+    out = np.zeros((max(count, 1), P))
+    rc = lib().ref_split_recombine(P, s, count, _ptr(S), _ptr(ef), _ptr(out))
+    if rc:
+        raise ValueError(f"ref_split_recombine: {rc}")
+    return out[:count]
 
 
 def num_threads() -> int:

@@ -606,12 +606,141 @@ EXPORT int ref_gemm(int P, char ta, char tb, int64_t m, int64_t n, int64_t k,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Exact integers and their rounding into P components (used by both split  */
+/* forms): a 512-bit two's complement integer X, and the components of      */
+/* X 2^e by repeated round-to-nearest (ties to even) of the exact remainder. */
+/* ------------------------------------------------------------------------ */
+
+#define BIG_LIMBS 16          /* 512-bit two's complement, 32-bit limbs */
+
+typedef struct {
+    uint32_t w[BIG_LIMBS];    /* little-endian */
+} big;
+
+static void big_set_i64(big *a, int64_t v)
+{
+    uint64_t u = (uint64_t)v;
+    a->w[0] = (uint32_t)u;
+    a->w[1] = (uint32_t)(u >> 32);
+    uint32_t ext = v < 0 ? 0xffffffffu : 0u;
+    for (int i = 2; i < BIG_LIMBS; ++i) a->w[i] = ext;
+}
+
+static int big_neg_p(const big *a) { return (a->w[BIG_LIMBS - 1] >> 31) != 0; }
+
+static void big_add(big *a, const big *b)
+{
+    uint64_t c = 0;
+    for (int i = 0; i < BIG_LIMBS; ++i) {
+        uint64_t t = (uint64_t)a->w[i] + b->w[i] + c;
+        a->w[i] = (uint32_t)t;
+        c = t >> 32;
+    }
+}
+
+static void big_negate(big *a)
+{
+    uint64_t c = 1;
+    for (int i = 0; i < BIG_LIMBS; ++i) {
+        uint64_t t = (uint64_t)(~a->w[i]) + c;
+        a->w[i] = (uint32_t)t;
+        c = t >> 32;
+    }
+}
+
+static void big_shl(big *a, int sh)     /* 0 <= sh < 32 */
+{
+    if (sh == 0)
+        return;
+    for (int i = BIG_LIMBS - 1; i > 0; --i)
+        a->w[i] = (a->w[i] << sh) | (a->w[i - 1] >> (32 - sh));
+    a->w[0] <<= sh;
+}
+
+static int big_top_bit(const big *a)    /* of a non-negative value; -1 if zero */
+{
+    for (int i = BIG_LIMBS - 1; i >= 0; --i)
+        if (a->w[i])
+            return 32 * i + 31 - __builtin_clz(a->w[i]);
+    return -1;
+}
+
+static int big_bit(const big *a, int b) { return (a->w[b >> 5] >> (b & 31)) & 1; }
+
+/* bits [lo, lo + 53) of a non-negative value as an integer */
+static uint64_t big_bits53(const big *a, int lo)
+{
+    uint64_t r = 0;
+    for (int b = lo + 52; b >= lo; --b)
+        r = (r << 1) | (uint64_t)(b >= 0 ? big_bit(a, b) : 0);
+    return r;
+}
+
+/* a -= q 2^sh for a non-negative a, q < 2^54 */
+static void big_sub_shifted(big *a, uint64_t q, int sh)
+{
+    big t;
+    memset(&t, 0, sizeof t);
+    for (int b = 0; b < 54; ++b)
+        if ((q >> b) & 1) {
+            int pos = b + sh;
+            t.w[pos >> 5] |= 1u << (pos & 31);
+        }
+    big_negate(&t);
+    big_add(a, &t);
+}
+
+/* Components c_0..c_{P-1} of X 2^e: c_0 = RN(X 2^e), then RN of the exact
+ * remainder, and so on (round to nearest, ties to even). */
+static void big_to_components(int P, const big *X, int e, double *c)
+{
+    big m = *X;
+    int neg = big_neg_p(&m);
+    if (neg)
+        big_negate(&m);
+    for (int q = 0; q < P; ++q) {
+        int h = big_top_bit(&m);
+        if (h < 0) {
+            c[q] = 0.0;
+            continue;
+        }
+        if (h <= 52) {
+            uint64_t v = big_bits53(&m, 0);
+            c[q] = (neg ? -1.0 : 1.0) * ldexp((double)v, e);
+            memset(&m, 0, sizeof m);
+            continue;
+        }
+        int sh = h - 52;
+        uint64_t v = big_bits53(&m, sh);
+        /* rounding: guard bit sh-1, sticky below */
+        int guard = big_bit(&m, sh - 1);
+        int sticky = 0;
+        for (int b = 0; b < sh - 1 && !sticky; ++b)
+            sticky = big_bit(&m, b);
+        if (guard && (sticky || (v & 1)))
+            v += 1;
+        c[q] = (neg ? -1.0 : 1.0) * ldexp((double)v, sh + e);
+        /* remainder m - v 2^sh, which may be negative after rounding up */
+        big_sub_shifted(&m, v, sh);
+        if (big_neg_p(&m)) {
+            big_negate(&m);
+            neg = !neg;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Split (Ozaki-style) form: each operand entry is scaled by a power of two */
 /* per row of op(A) / column of op(B) and cut into s signed 7-bit digits;   */
 /* the digit products are exact integers, summed per anti-diagonal         */
-/* p + q = d (d = 2..s+1), then recombined into P components.  This form is */
-/* not in the paper; it reaches the paper's product by a different route    */
-/* and is held to the same componentwise error bound.                       */
+/*   S_d = sum_{p+q=d} sum_l d_p(a_il) d_q(b_lj),  d = 2..s+1,             */
+/* (the triangle p + q <= s + 1 of digit pairs), then recombined exactly:  */
+/*   X_ij = sum_d S_d 128^(s+1-d)   (exact integer, Horner in base 128),   */
+/*   value = X_ij 2^(E_i + F_j - 7 (s+1)),                                 */
+/* rounded once into P components (repeated round-to-nearest of the exact  */
+/* remainder), then the epilogue.  This form is not in the paper; it        */
+/* reaches the paper's product by a different route and is held to the     */
+/* same componentwise error bound.                                          */
 /* ------------------------------------------------------------------------ */
 
 /* Scale exponent of a row/column whose largest leading component has
@@ -684,31 +813,32 @@ EXPORT void ref_split_slices(int P, int s, char t, int is_b, int64_t count, int6
         }
 }
 
-/* Group g of the diagonals d = 2..s+1 holds d = 2+4g .. min(5+4g, s+1).
- * x_g = sum over its diagonals of S_d 2^(7 (dlast - d)), an integer below
- * 2^53 in magnitude, hence exact in binary64. */
-static int split_groups(int s) { return (s + 3) / 4; }
-
-/* Recombine the diagonal sums S[d-2], d = 2..s+1, of one entry into P
- * components: term_g = x_g 2^(Ei + Fj - 7 dlast(g)), accumulated with the
- * precision's own addition from the least significant group upward. */
-static void recombine(int P, int s, const int64_t *S, int32_t Ei, int32_t Fj, double *acc)
+/* Exact recombination of one entry's anti-diagonal sums S[d-2], d = 2..s+1:
+ * X = sum_d S_d 128^(s+1-d) as an exact integer (Horner in base 128), then
+ * the components of X 2^(ef - 7 (s+1)), rounded once. */
+static void split_recombine(int P, int s, const int64_t *S, int32_t ef, double *acc)
 {
-    for (int c = 0; c < P; ++c)
-        acc[c] = 0.0;
-    int G = split_groups(s);
-    for (int g = G - 1; g >= 0; --g) {
-        int d0 = 2 + 4 * g;
-        int d1 = d0 + 3 < s + 1 ? d0 + 3 : s + 1;
-        int64_t x = 0;
-        for (int d = d0; d <= d1; ++d)
-            x = x * 128 + S[d - 2];
-        double term[4] = {ldexp((double)x, Ei + Fj - 7 * d1), 0.0, 0.0, 0.0};
-        double t[4];
-        mp_add(P, acc, term, t);
-        for (int c = 0; c < P; ++c)
-            acc[c] = t[c];
+    big X;
+    big_set_i64(&X, 0);
+    for (int d = 2; d <= s + 1; ++d) {
+        big t;
+        big_shl(&X, 7);
+        big_set_i64(&t, S[d - 2]);
+        big_add(&X, &t);
     }
+    big_to_components(P, &X, ef - 7 * (s + 1), acc);
+}
+
+/* The recombination alone, for pinning: S holds `count` rows of s sums
+ * (S[r * s + d - 2]), ef the row's E_i + F_j; out[r * P + c]. */
+EXPORT int ref_split_recombine(int P, int s, int64_t count, const int64_t *S, const int32_t *ef,
+                               double *out)
+{
+    if (P < 2 || P > 4 || s < 1 || s > 64)
+        return -1;
+    for (int64_t r = 0; r < count; ++r)
+        split_recombine(P, s, S + r * s, ef[r], out + r * P);
+    return 0;
 }
 
 /* Whole split-form GEMM for rows row0 <= i < row1 and columns col0 <= j <
@@ -774,7 +904,7 @@ EXPORT int ref_gemm_split(int P, int s, char ta, char tb, int64_t m, int64_t n, 
                 if (S_out)
                     S_out[(int64_t)(d - 2) * m * n + i + j * m] = sum;
             }
-            recombine(P, s, S, E[i], F[j], acc);
+            split_recombine(P, s, S, E[i] + F[j], acc);
         }
         double cv[4];
         for (int c = 0; c < P; ++c)
@@ -1055,124 +1185,6 @@ EXPORT int ref_gemv(int P, char trans, int64_t m, int64_t n, const double *alpha
 /* INT8 matrix product per modulus) and the Chinese remainder theorem;      */
 /* here it is the plain definition.                                         */
 /* ------------------------------------------------------------------------ */
-
-#define BIG_LIMBS 16          /* 512-bit two's complement, 32-bit limbs */
-
-typedef struct {
-    uint32_t w[BIG_LIMBS];    /* little-endian */
-} big;
-
-static void big_set_i64(big *a, int64_t v)
-{
-    uint64_t u = (uint64_t)v;
-    a->w[0] = (uint32_t)u;
-    a->w[1] = (uint32_t)(u >> 32);
-    uint32_t ext = v < 0 ? 0xffffffffu : 0u;
-    for (int i = 2; i < BIG_LIMBS; ++i) a->w[i] = ext;
-}
-
-static int big_neg_p(const big *a) { return (a->w[BIG_LIMBS - 1] >> 31) != 0; }
-
-static void big_add(big *a, const big *b)
-{
-    uint64_t c = 0;
-    for (int i = 0; i < BIG_LIMBS; ++i) {
-        uint64_t t = (uint64_t)a->w[i] + b->w[i] + c;
-        a->w[i] = (uint32_t)t;
-        c = t >> 32;
-    }
-}
-
-static void big_negate(big *a)
-{
-    uint64_t c = 1;
-    for (int i = 0; i < BIG_LIMBS; ++i) {
-        uint64_t t = (uint64_t)(~a->w[i]) + c;
-        a->w[i] = (uint32_t)t;
-        c = t >> 32;
-    }
-}
-
-static void big_shl(big *a, int sh)     /* 0 <= sh < 32 */
-{
-    if (sh == 0)
-        return;
-    for (int i = BIG_LIMBS - 1; i > 0; --i)
-        a->w[i] = (a->w[i] << sh) | (a->w[i - 1] >> (32 - sh));
-    a->w[0] <<= sh;
-}
-
-static int big_top_bit(const big *a)    /* of a non-negative value; -1 if zero */
-{
-    for (int i = BIG_LIMBS - 1; i >= 0; --i)
-        if (a->w[i])
-            return 32 * i + 31 - __builtin_clz(a->w[i]);
-    return -1;
-}
-
-static int big_bit(const big *a, int b) { return (a->w[b >> 5] >> (b & 31)) & 1; }
-
-/* bits [lo, lo + 53) of a non-negative value as an integer */
-static uint64_t big_bits53(const big *a, int lo)
-{
-    uint64_t r = 0;
-    for (int b = lo + 52; b >= lo; --b)
-        r = (r << 1) | (uint64_t)(b >= 0 ? big_bit(a, b) : 0);
-    return r;
-}
-
-/* a -= q 2^sh for a non-negative a, q < 2^54 */
-static void big_sub_shifted(big *a, uint64_t q, int sh)
-{
-    big t;
-    memset(&t, 0, sizeof t);
-    for (int b = 0; b < 54; ++b)
-        if ((q >> b) & 1) {
-            int pos = b + sh;
-            t.w[pos >> 5] |= 1u << (pos & 31);
-        }
-    big_negate(&t);
-    big_add(a, &t);
-}
-
-/* Components c_0..c_{P-1} of X 2^e: c_0 = RN(X 2^e), then RN of the exact
- * remainder, and so on (round to nearest, ties to even). */
-static void big_to_components(int P, const big *X, int e, double *c)
-{
-    big m = *X;
-    int neg = big_neg_p(&m);
-    if (neg)
-        big_negate(&m);
-    for (int q = 0; q < P; ++q) {
-        int h = big_top_bit(&m);
-        if (h < 0) {
-            c[q] = 0.0;
-            continue;
-        }
-        if (h <= 52) {
-            uint64_t v = big_bits53(&m, 0);
-            c[q] = (neg ? -1.0 : 1.0) * ldexp((double)v, e);
-            memset(&m, 0, sizeof m);
-            continue;
-        }
-        int sh = h - 52;
-        uint64_t v = big_bits53(&m, sh);
-        /* rounding: guard bit sh-1, sticky below */
-        int guard = big_bit(&m, sh - 1);
-        int sticky = 0;
-        for (int b = 0; b < sh - 1 && !sticky; ++b)
-            sticky = big_bit(&m, b);
-        if (guard && (sticky || (v & 1)))
-            v += 1;
-        c[q] = (neg ? -1.0 : 1.0) * ldexp((double)v, sh + e);
-        /* remainder m - v 2^sh, which may be negative after rounding up */
-        big_sub_shifted(&m, v, sh);
-        if (big_neg_p(&m)) {
-            big_negate(&m);
-            neg = !neg;
-        }
-    }
-}
 
 EXPORT int ref_gemm_crt(int P, int s, char ta, char tb, int64_t m, int64_t n, int64_t k,
                         const double *alpha, const double *A, int64_t lda, int64_t sa,

@@ -75,6 +75,97 @@ def test_diagonal_sums_brute_force(P, s):
                 assert S[d - 2, j, i] == want
 
 
+def _round_components(X, e, P):
+    """Components of X 2^e by repeated correctly rounded float(Fraction)."""
+    rem = Fr(X) * Fr(2) ** e
+    out = []
+    for _ in range(P):
+        v = float(rem)
+        out.append(v)
+        rem -= Fr(v)
+    return out
+
+
+def _adversarial_sums(rng, s, count):
+    """Anti-diagonal sums that make the exact value need many bits or sit
+    near a rounding tie: sparse patterns, runs of ones, single bits and
+    full-range int32 values, both signs."""
+    S = np.zeros((count, s), np.int64)
+    for r in range(count):
+        kind = r % 4
+        dens = (0.15, 0.4, 1.0)[r % 3]
+        for d in range(s):
+            if rng.random() > dens:
+                continue
+            if kind == 0:
+                v = int(rng.integers(-2 ** 31 + 1, 2 ** 31))
+            elif kind == 1:
+                v = int(rng.choice([-1, 1])) << int(rng.integers(0, 31))
+            elif kind == 2:
+                v = int(rng.choice([-1, 1])) * ((1 << int(rng.integers(1, 32))) - 1)
+            else:
+                v = int(rng.integers(-200, 201))
+            S[r, d] = v
+    return S
+
+
+@pytest.mark.parametrize("P,s", [(2, 16), (2, 7), (3, 23), (3, 30), (3, 12), (4, 31), (4, 40)])
+def test_recombination_is_the_exact_sum_rounded_once(P, s):
+    """The recombination step alone on adversarial anti-diagonal sums: the
+    exact integer X = sum_d S_d 128^(s+1-d) in Python, scaled by 2^(ef -
+    7 (s+1)) and rounded component by component with Python's correctly
+    rounded float(Fraction) of the exact remainder, gives the oracle's bits.
+    A recombination that adds partial sums with the precision's own rounded
+    addition instead fails on some of these."""
+    rng = np.random.Generator(np.random.PCG64(1500 + 10 * P + s))
+    count = 4000
+    S = _adversarial_sums(rng, s, count)
+    ef = rng.integers(-40, 41, count).astype(np.int32)
+    got = oracle.split_recombine(P, s, S, ef)
+    for r in range(count):
+        X = 0
+        for d in range(s):
+            X = X * 128 + int(S[r, d])
+        want = _round_components(X, int(ef[r]) - 7 * (s + 1), P)
+        assert list(got[r]) == want, (r, S[r].tolist(), int(ef[r]))
+
+
+@pytest.mark.parametrize("P,s,ta,tb", [(2, 16, "N", "N"), (2, 5, "T", "N"), (3, 23, "N", "T"),
+                                        (3, 9, "T", "T"), (4, 31, "N", "N"), (4, 40, "T", "N")])
+def test_exact_recombination_brute_force(P, s, ta, tb):
+    """The split product is the exact triangle sum rounded once: from the
+    oracle's own digits (pinned above), X_ij = sum over digit pairs with
+    p + q <= s + 1 of sum_l d_p(a_il) d_q(b_lj) 128^(s+1-p-q) in Python
+    integers, times 2^(E_i + F_j - 7 (s+1)), rounded component by component
+    with Python's correctly rounded float(Fraction) of the exact remainder;
+    the oracle gives the same bits (alpha = 1, beta = 0, whose epilogue
+    leaves a normalised result unchanged)."""
+    m, n, k = 3, 4, 7
+    rng = np.random.Generator(np.random.PCG64(1400 + 10 * P + s))
+    A = synth.mp_uniform(rng, P, (m, k) if ta == "T" else (k, m))
+    B = synth.mp_uniform(rng, P, (k, n) if tb == "T" else (n, k))
+    A = np.ldexp(A, rng.integers(-12, 13, A.shape[1:])[None])
+    B = np.ldexp(B, rng.integers(-12, 13, B.shape[1:])[None])
+    one, zero = synth.mp_one(P), np.zeros(P)
+    got = oracle.gemm_split(P, s, ta, tb, m, n, k, one, A, B, zero, np.zeros((P, n, m)))
+    E = oracle.split_exponents(P, ta, 0, m, k, A)
+    F = oracle.split_exponents(P, tb, 1, n, k, B)
+    DA = oracle.split_slices(P, s, ta, 0, m, k, A, E).astype(np.int64)
+    DB = oracle.split_slices(P, s, tb, 1, n, k, B, F).astype(np.int64)
+    for i in range(m):
+        for j in range(n):
+            X = 0
+            for p in range(1, s + 1):
+                for q in range(1, s + 2 - p):
+                    dot = sum(int(DA[p - 1, i, l]) * int(DB[q - 1, j, l]) for l in range(k))
+                    X += dot * 128 ** (s + 1 - p - q)
+            rem = Fr(X) * Fr(2) ** (int(E[i]) + int(F[j]) - 7 * (s + 1))
+            for c in range(P):
+                v = float(rem)
+                assert got[c, j, i] == v, (i, j, c)
+                rem -= Fr(v)
+
+
 @pytest.mark.parametrize("P", [2, 3, 4])
 @pytest.mark.parametrize("ta,tb", [("N", "N"), ("T", "N"), ("N", "T")])
 def test_split_within_bound(P, ta, tb):

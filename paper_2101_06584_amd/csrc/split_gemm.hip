@@ -14,17 +14,17 @@
 //  3. anti-diagonal sums S_d = sum_{p+q=d} DA_p DB_q^T, d = 2..s+1, exact in
 //     int32 (|S_d| <= s k 2^12 < 2^31 for s k < 2^19) with
 //     v_mfma_i32_32x32x32_i8;
-//  4. recombination: groups of four consecutive diagonals are folded exactly
-//     (Horner in base 2^7, < 2^53 in magnitude, so exact in binary64), scaled
-//     by 2^(E_i + F_j - 7 d_last) and accumulated with the precision's own
-//     addition (Algorithm 1 / TDaddq / Algorithm 5) from the least significant
-//     group up; then the alpha/beta epilogue of the plain form.
+//  4. exact recombination: X = sum_d S_d 128^(s+1-d) as an exact multi-limb
+//     integer, X 2^(E_i + F_j - 7 (s+1)) rounded once into P components
+//     (round to nearest, ties to even, of the value and then of each exact
+//     remainder); then the alpha/beta epilogue of the plain form.
 // Every stage is deterministic, so results are reproducible bit for bit.
 #pragma clang fp contract(off)
 
 #include <utility>
 
 #include "internal.hpp"
+#include "exact_round.hpp"
 #include "lds_dma.hpp"
 #include "mp_arith.hpp"
 #include "tile_order.hpp"
@@ -469,10 +469,21 @@ __global__ __launch_bounds__(256, 2) void diag_mfma_kernel(const int8_t* __restr
 }
 
 // ---------------------------------------------------------------------------
-// Stage 4: recombination and epilogue, one thread per entry (i fastest).
+// Stage 4: exact recombination and epilogue, one thread per entry (i fastest).
+// X = sum_{d=2}^{s+1} S_d 128^(s+1-d) is formed exactly in K 32-bit limbs
+// (two's complement): the diagonals are folded from the most significant
+// one down in groups of up to four, aligned to the least significant end, so
+// that every group but the top one holds four; a group's Horner value
+// |x| <= (2^31 - 1)(128^4 - 1)/127 < 2^53 is exact in int64, and each full
+// group enters as X = X 2^28 + x.  Its magnitude is rounded once into the P
+// components of X 2^(E_i + F_j - 7 (s+1)), then the epilogue.
+// |X| < 2^(24.01 + 7 s), so K limbs hold s <= (32 K - 25.01) / 7.
 // ---------------------------------------------------------------------------
 
-template <int P>
+template <int K>
+constexpr int recombine_max_slices() { return (32 * K - 26) / 7; }
+
+template <int P, int K>
 __global__ __launch_bounds__(256) void recombine_kernel(GemmArgs g, const int32_t* __restrict__ E,
                                                         const int32_t* __restrict__ F,
                                                         const int32_t* __restrict__ S, int s,
@@ -480,23 +491,53 @@ __global__ __launch_bounds__(256) void recombine_kernel(GemmArgs g, const int32_
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= g.m * g.n) return;
     const int64_t i = idx % g.m, j = idx / g.m;
-    const int32_t ef = E[i] + F[j];
     const int64_t plane = Np * Mp;
     const int32_t* Sij = S + j * Mp + i;
-    mp<P> acc = mp_zero<P>();
     const int G = (s + 3) / 4;
-    for (int gi = G - 1; gi >= 0; --gi) {
-        const int d0 = 2 + 4 * gi;
-        const int d1 = (d0 + 3 < s + 1) ? d0 + 3 : s + 1;
-        int64_t x = 0;
-        for (int dd = d0; dd <= d1; ++dd) x = x * 128 + (int64_t)Sij[(int64_t)(dd - 2) * plane];
-        mp<P> term = mp_zero<P>();
-        term.c[0] = ldexp((double)x, ef - 7 * d1);
-        acc = add(acc, term);
+    const int top = s - 4 * (G - 1);          // diagonals in the top group
+    int64_t x = 0;
+    for (int d = 2; d <= top + 1; ++d) x = x * 128 + (int64_t)Sij[(int64_t)(d - 2) * plane];
+    uint32_t w[K];
+    w[0] = (uint32_t)x;
+    w[1] = (uint32_t)((uint64_t)x >> 32);
+#pragma unroll
+    for (int l = 2; l < K; ++l) w[l] = x < 0 ? 0xffffffffu : 0u;
+    for (int d0 = top + 2; d0 <= s + 1; d0 += 4) {
+        x = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x = x * 128 + (int64_t)Sij[(int64_t)(d0 + u - 2) * plane];
+#pragma unroll
+        for (int l = K - 1; l >= 1; --l) w[l] = (w[l] << 28) | (w[l - 1] >> 4);
+        w[0] <<= 28;
+        const uint32_t ext = x < 0 ? 0xffffffffu : 0u;
+        uint64_t c = (uint64_t)w[0] + (uint32_t)x;
+        w[0] = (uint32_t)c;
+        c = (uint64_t)w[1] + (uint32_t)((uint64_t)x >> 32) + (c >> 32);
+        w[1] = (uint32_t)c;
+#pragma unroll
+        for (int l = 2; l < K; ++l) {
+            c = (uint64_t)w[l] + ext + (c >> 32);
+            w[l] = (uint32_t)c;
+        }
     }
-    mp<P> alpha, beta;
+    double sg = 1.0;
+    if (w[K - 1] >> 31) {
+        uint64_t c = 1;
+#pragma unroll
+        for (int l = 0; l < K; ++l) {
+            c += (uint64_t)(~w[l]);
+            w[l] = (uint32_t)c;
+            c >>= 32;
+        }
+        sg = -1.0;
+    }
+    double comp[P];
+    limbs_to_components<P, K>(w, sg, E[i] + F[j] - 7 * (s + 1), comp);
+
+    mp<P> acc, alpha, beta;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
+        acc.c[p] = comp[p];
         alpha.c[p] = g.alpha[p];
         beta.c[p] = g.beta[p];
     }
@@ -604,17 +645,30 @@ static int launch_diag(int cfg, const int8_t* DA, const int8_t* DB, int32_t* S, 
     return (int)hipGetLastError();
 }
 
+template <int P>
+static int launch_recombine_p(dim3 grid, const GemmArgs& g, const int32_t* E, const int32_t* F,
+                              const int32_t* S, int s, int64_t Mp, int64_t Np, hipStream_t st) {
+#define MPG_REC(K) \
+    hipLaunchKernelGGL((recombine_kernel<P, K>), grid, dim3(256), 0, st, g, E, F, S, s, Mp, Np)
+    if (s <= recombine_max_slices<4>()) MPG_REC(4);
+    else if (s <= recombine_max_slices<6>()) MPG_REC(6);
+    else if (s <= recombine_max_slices<8>()) MPG_REC(8);
+    else MPG_REC(10);
+#undef MPG_REC
+    return (int)hipGetLastError();
+}
+
+static_assert(recombine_max_slices<10>() >= 40, "ten limbs hold the largest slice count");
+
 static int launch_recombine(int P, const GemmArgs& g, const int32_t* E, const int32_t* F,
                             const int32_t* S, int s, int64_t Mp, int64_t Np, hipStream_t st) {
     const int64_t blocks = (g.m * g.n + 255) / 256;
     if (blocks > 0x7fffffffLL) return (int)hipErrorInvalidConfiguration;
-    if (P == 2)
-        hipLaunchKernelGGL(recombine_kernel<2>, dim3((unsigned)blocks), dim3(256), 0, st, g, E, F, S, s, Mp, Np);
-    else if (P == 3)
-        hipLaunchKernelGGL(recombine_kernel<3>, dim3((unsigned)blocks), dim3(256), 0, st, g, E, F, S, s, Mp, Np);
-    else
-        hipLaunchKernelGGL(recombine_kernel<4>, dim3((unsigned)blocks), dim3(256), 0, st, g, E, F, S, s, Mp, Np);
-    return (int)hipGetLastError();
+    if (s > recombine_max_slices<10>()) return (int)hipErrorInvalidValue;
+    const dim3 grid((unsigned)blocks);
+    if (P == 2) return launch_recombine_p<2>(grid, g, E, F, S, s, Mp, Np, st);
+    if (P == 3) return launch_recombine_p<3>(grid, g, E, F, S, s, Mp, Np, st);
+    return launch_recombine_p<4>(grid, g, E, F, S, s, Mp, Np, st);
 }
 
 // Runs stages 1..last.  Caller has validated arguments, checked the

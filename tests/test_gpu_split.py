@@ -49,6 +49,11 @@ CASES = [
     (2, "N", "N", 700, 20, 90, 16, 1),     # operands padded to different row counts
     (4, "T", "T", 9, 450, 60, 31, 0),
 ]
+# tile configuration 2 (128 x 64, four diagonals at once): one ragged shape
+# per precision under every transpose pair
+CASES += [(P, ta, tb, m, n, k, s, 2)
+          for (P, m, n, k, s) in [(2, 150, 70, 90, 16), (3, 131, 129, 45, 23), (4, 257, 63, 70, 31)]
+          for ta in "NT" for tb in "NT"]
 
 
 @pytest.mark.parametrize("P,ta,tb,m,n,k,s,tile", CASES)
@@ -83,18 +88,20 @@ def test_stages_bitwise(gpu_lib, P, ta, tb, m, n, k, s, tile):
     assert np.array_equal(host(dC2), wantC)
 
 
-@pytest.mark.parametrize("P", [2, 3, 4])
-@pytest.mark.parametrize("n", [1025, 4096])
-def test_full_size_sampled(gpu_lib, P, n):
+@pytest.mark.parametrize("P,n,tile", [(P, n, None) for P in (2, 3, 4) for n in (1025, 4096)]
+                         + [(P, 1025, 2) for P in (2, 3, 4)])
+def test_full_size_sampled(gpu_lib, P, n, tile):
     """The benchmark's square workload in the split form: a sampled block
     bit-identical to the oracle's split form, sampled entries within the
     error bound of the exact product."""
     A, B, C, alpha, beta = make(P, "N", "N", n, n, n, fam=2)
     s = gpu_lib.DEFAULT_SLICES[P]
-    ws = gpu_lib.alloc_workspace(P, n, n, n, s)
+    t = -1 if tile is None else tile
+    ws = gpu_lib.alloc_workspace(P, n, n, n, s, t)
     dA, dB, dC = dev(A), dev(B), dev(C)
-    note("split full size", P, n, s)
-    gpu_lib.gemm(P, "N", "N", n, n, n, alpha, dA, dB, beta, dC, form="split", slices=s, workspace=ws)
+    note("split full size", P, n, s, "tile", tile)
+    gpu_lib.gemm(P, "N", "N", n, n, n, alpha, dA, dB, beta, dC, form="split", slices=s, tile=t,
+                 workspace=ws)
     got = host(dC)
     rng = synth.rng_for(2, "samples")
     r0 = int(rng.integers(0, n - 2))

@@ -309,7 +309,15 @@ def dot_workspace(prec, n, device=None) -> torch.Tensor:
 def dot_raw(prec, x, y, result, workspace=None, n=None, stream=None) -> int:
     P = PREC[prec]
     n = x.shape[-1] if n is None else n
-    ws = workspace if workspace is not None else dot_workspace(prec, n, x.device)
+    if workspace is not None:
+        ws = workspace
+    else:
+        # a temporary used by kernels queued on `stream`: allocated on that
+        # stream, so the caching allocator does not hand it out again before
+        # they end
+        s = stream if stream is not None else torch.cuda.current_stream(x.device)
+        with torch.cuda.stream(s):
+            ws = dot_workspace(prec, n, x.device)
     return getattr(_lib.load(), f"mp_dot_{_NAME[P]}")(
         n, C.c_void_p(x.data_ptr()), x.stride(0), C.c_void_p(y.data_ptr()), y.stride(0),
         C.c_void_p(result.data_ptr()), C.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),

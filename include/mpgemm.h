@@ -53,6 +53,8 @@ extern "C" {
 #define MPGEMM_ERR_GRAPH 4        /* hipGraph capture / instantiation failed    */
 #define MPGEMM_ERR_ALIAS 5        /* C overlaps A or B                          */
 #define MPGEMM_ERR_NOMEM 6        /* host or device allocation failed           */
+#define MPGEMM_ERR_SCRATCH 7      /* mpgemm_ex_noalloc: the call needs more than
+                                     MPGEMM_STATIC_SCRATCH_BYTES of scratch    */
 
 /* Precision ids (the number of binary64 components). */
 #define MPGEMM_DD 2
@@ -209,6 +211,35 @@ int mpgemm_qd_ex(char transa, char transb, int64_t m, int64_t n, int64_t k, cons
                  const double* A, int64_t lda, int64_t a_plane_stride, const double* B, int64_t ldb,
                  int64_t b_plane_stride, const double* beta, double* C, int64_t ldc,
                  int64_t c_plane_stride, hipStream_t stream, const mpgemm_opts* opts);
+
+/*
+ * For callers that cannot allocate (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): the same call as
+ * mpgemm_{dd,td,qd}_ex for precision `prec` (argument 1: 2, 3 or 4; the
+ * other arguments follow as arguments 2..19, so an invalid argument i of
+ * the _ex entry point is reported as -(i + 1)), except that the split,
+ * residue and Strassen forms take their scratch from a buffer of
+ * MPGEMM_STATIC_SCRATCH_BYTES bytes that the library holds in static device
+ * memory, one per GPU, from the first call on that GPU until the process
+ * ends.  opts->workspace must be NULL and opts->workspace_bytes 0 (-19
+ * otherwise).  The call allocates nothing (no hipMalloc, no hipFree); the
+ * first call on a device looks up the buffer's device address once, with
+ * that device current.  A form whose workspace (mpgemm_workspace_bytes)
+ * exceeds the buffer returns MPGEMM_ERR_SCRATCH before any GPU work;
+ * MPGEMM_FORM_AUTO never does: it takes the residue or split form only when
+ * it fits, else plain.  Results are bitwise those of the _ex call with the
+ * same opts and a workspace of its own.  Every call on a GPU shares that
+ * GPU's buffer: calls that may overlap (queued on different streams, or
+ * from several threads without ordering) race and give wrong results; calls
+ * ordered on one stream are safe.  The kernels write every scratch byte they
+ * read, so nothing carries over from one call to the next.
+ */
+#define MPGEMM_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int mpgemm_ex_noalloc(int prec, char transa, char transb, int64_t m, int64_t n, int64_t k,
+                      const double* alpha, const double* A, int64_t lda, int64_t a_plane_stride,
+                      const double* B, int64_t ldb, int64_t b_plane_stride, const double* beta,
+                      double* C, int64_t ldc, int64_t c_plane_stride, hipStream_t stream,
+                      const mpgemm_opts* opts);
 
 /* Residue form: the number of INT8 products a call runs for inner dimension
  * k and s digits per entry (slices 0 = the default of precision prec): the

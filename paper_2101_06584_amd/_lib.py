@@ -16,7 +16,8 @@ TUNED_TABLE = os.environ.get("MPGEMM_AUTOTUNE_CACHE", os.path.join(_HERE, "tuned
 _i64, _int, _ch, _vp, _sz, _dbl = C.c_int64, C.c_int, C.c_char, C.c_void_p, C.c_size_t, C.c_double
 _P = C.POINTER
 
-ERR_HIP, ERR_WORKSPACE, ERR_UNSUPPORTED, ERR_GRAPH, ERR_ALIAS, ERR_NOMEM = 1, 2, 3, 4, 5, 6
+ERR_HIP, ERR_WORKSPACE, ERR_UNSUPPORTED, ERR_GRAPH, ERR_ALIAS, ERR_NOMEM, ERR_SCRATCH = 1, 2, 3, 4, 5, 6, 7
+STATIC_SCRATCH_BYTES = 64 << 20   # MPGEMM_STATIC_SCRATCH_BYTES
 FORM_PLAIN, FORM_SPLIT_I8, FORM_AUTO, FORM_STRASSEN, FORM_SPLIT_CRT = 0, 1, 2, 4, 5
 TD_ADD_ACCURATE, TD_MULQ = 1, 2
 
@@ -43,6 +44,7 @@ EXPORTS = {
     "mpgemm_dd_ex": (_GEMM_ARGS + [_P(Opts)], _int),
     "mpgemm_td_ex": (_GEMM_ARGS + [_P(Opts)], _int),
     "mpgemm_qd_ex": (_GEMM_ARGS + [_P(Opts)], _int),
+    "mpgemm_ex_noalloc": ([_int] + _GEMM_ARGS + [_P(Opts)], _int),
     "mpgemm_workspace_bytes": ([_int, _int, _i64, _i64, _i64, _int, _int], _sz),
     "mpgemm_crt_moduli": ([_int, _i64, _int], _int),
     "mp_vec_dd_add": (_VEC_ARGS, _int), "mp_vec_dd_mul": (_VEC_ARGS, _int),

@@ -125,6 +125,26 @@ def gemm_raw(prec, transa, transb, m, n, k, alpha, A, B, beta, C_, *, form=None,
                                                                variant, levels)))
 
 
+def gemm_noalloc_raw(prec, transa, transb, m, n, k, alpha, A, B, beta, C_, *, form="plain", slices=0,
+                     tile=-1, stream=None, variant=0, levels=0) -> int:
+    """Calls mpgemm_ex_noalloc (the _ex call with the library's static
+    scratch buffer instead of a workspace); returns the status code."""
+    P = PREC[prec]
+    L = _lib.load()
+    a, lda, sa = _mat(A, P)
+    b, ldb, sb = _mat(B, P)
+    c, ldc, sc = _mat(C_, P)
+    o = make_opts(form, slices, tile, None, variant, levels)
+    return L.mpgemm_ex_noalloc(P, transa.encode(), transb.encode(), m, n, k, _scalar(alpha, P), a, lda, sa,
+                               b, ldb, sb, _scalar(beta, P), c, ldc, sc, _stream(stream), C.byref(o))
+
+
+def gemm_noalloc(prec, transa, transb, m, n, k, alpha, A, B, beta, C_, **kw) -> None:
+    """As gemm(), without a workspace: the split, residue and Strassen forms
+    use the library's static scratch buffer; raises on error."""
+    _check(gemm_noalloc_raw(prec, transa, transb, m, n, k, alpha, A, B, beta, C_, **kw), "mpgemm_ex_noalloc")
+
+
 def gemm(prec, transa, transb, m, n, k, alpha, A, B, beta, C_, **kw) -> None:
     """C_ = alpha op(A) op(B) + beta C_ (in place); raises on error."""
     _check(gemm_raw(prec, transa, transb, m, n, k, alpha, A, B, beta, C_, **kw), "mpgemm")

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 OUT = os.path.join(HERE, "libmpgemm.so")
-SOURCES = ["plain_gemm.hip", "split_gemm.hip", "crt_gemm.hip", "strassen.hip", "blas.hip", "tune_kernels.hip",
+SOURCES = ["plain_gemm.hip", "split_gemm.hip", "crt_gemm.hip", "strassen.hip", "blas.hip", "tune_kernels.hip", "noalloc.hip",
            "api.cpp"]
 ARCH = os.environ.get("MPGEMM_ARCH", "gfx950")
 

@@ -178,6 +178,15 @@ int plain_tile_for(int P, int64_t m, int64_t n, int64_t k) {
     return pick_tile(P, MPGEMM_FORM_PLAIN, m, n, k, -1);
 }
 
+bool opts_ok(const mpgemm_opts* opts) {
+    if (!opts) return false;
+    if (opts->form < 0 || opts->form > 5 || opts->form == 3) return false;
+    if (opts->slices < 0 || opts->slices > kMaxSlices) return false;
+    if (opts->variant < 0 || opts->variant > 3) return false;
+    if (opts->levels < 0 || opts->levels > kMaxStrassenLevels) return false;
+    return true;
+}
+
 int gemm_common(int P, char ta, char tb, int64_t m, int64_t n, int64_t k, const double* alpha,
                 const double* A, int64_t lda, int64_t sa, const double* B, int64_t ldb, int64_t sb,
                 const double* beta, double* C, int64_t ldc, int64_t sc, hipStream_t st,
@@ -185,13 +194,7 @@ int gemm_common(int P, char ta, char tb, int64_t m, int64_t n, int64_t k, const 
     GemmArgs g;
     int rc = validate(P, ta, tb, m, n, k, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, g);
     if (rc) return rc;
-    if (has_opts) {
-        if (!opts) return -18;
-        if (opts->form < 0 || opts->form > 5 || opts->form == 3) return -18;
-        if (opts->slices < 0 || opts->slices > kMaxSlices) return -18;
-        if (opts->variant < 0 || opts->variant > 3) return -18;
-        if (opts->levels < 0 || opts->levels > kMaxStrassenLevels) return -18;
-    }
+    if (has_opts && !opts_ok(opts)) return -18;
     const int variant = has_opts ? opts->variant : 0;
     // the TD variants exist for the plain form only
     if (variant != 0 && (P != 3 || opts->form == MPGEMM_FORM_SPLIT_I8 ||
@@ -287,6 +290,28 @@ MPG_GEMM(mpgemm_dd, 2)
 MPG_GEMM(mpgemm_td, 3)
 MPG_GEMM(mpgemm_qd, 4)
 #undef MPG_GEMM
+}  // extern "C"
+
+namespace mpg {
+int gemm_ex_entry(int P, char ta, char tb, int64_t m, int64_t n, int64_t k, const double* alpha,
+                  const double* A, int64_t lda, int64_t sa, const double* B, int64_t ldb, int64_t sb,
+                  const double* beta, double* C, int64_t ldc, int64_t sc, hipStream_t st,
+                  const mpgemm_opts* opts) {
+    return gemm_common(P, ta, tb, m, n, k, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, st, opts,
+                       true, 0);
+}
+
+int gemm_ex_check(int P, char ta, char tb, int64_t m, int64_t n, int64_t k, const double* alpha,
+                  const double* A, int64_t lda, int64_t sa, const double* B, int64_t ldb, int64_t sb,
+                  const double* beta, double* C, int64_t ldc, int64_t sc, const mpgemm_opts* opts) {
+    GemmArgs g;
+    const int rc = validate(P, ta, tb, m, n, k, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, g);
+    if (rc) return rc;
+    return opts_ok(opts) ? 0 : -18;
+}
+}  // namespace mpg
+
+extern "C" {
 
 size_t mpgemm_workspace_bytes(int prec, int form, int64_t m, int64_t n, int64_t k, int slices,
                               int tile) {
@@ -864,6 +889,9 @@ const char* mpgemm_strerror(int code) {
     case MPGEMM_ERR_GRAPH: return "hipGraph capture or instantiation failed";
     case MPGEMM_ERR_ALIAS: return "C overlaps A or B";
     case MPGEMM_ERR_NOMEM: return "allocation failed";
+    case MPGEMM_ERR_SCRATCH:
+        return "the call needs more scratch than the library's static buffer holds "
+               "(MPGEMM_STATIC_SCRATCH_BYTES)";
     default: return "unknown error";
     }
 }

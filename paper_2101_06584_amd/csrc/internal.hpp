@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "mpgemm.h"
+
 namespace mpg {
 
 // One GEMM C = alpha op(A) op(B) + beta C on component planes (column-major
@@ -99,5 +101,17 @@ CrtPlan crt_plan(int P, int64_t k, int s);
 int crt_products(int P, int64_t k, int s);     // INT8 products of a call, 0 if unsupported
 size_t crt_workspace_bytes(int P, int64_t m, int64_t n, int64_t k, int s, int cfg);
 int launch_crt(int P, int s, int cfg, const GemmArgs& g, void* ws, hipStream_t st);
+
+// The _ex entry points' dispatch for precision P (argument errors numbered as
+// for mpgemm_dd_ex, 1..18).
+int gemm_ex_entry(int P, char ta, char tb, int64_t m, int64_t n, int64_t k, const double* alpha,
+                  const double* A, int64_t lda, int64_t sa, const double* B, int64_t ldb, int64_t sb,
+                  const double* beta, double* C, int64_t ldc, int64_t sc, hipStream_t st,
+                  const ::mpgemm_opts* opts);
+// Its argument checks alone (host only): 0, a negative argument index or
+// MPGEMM_ERR_ALIAS.
+int gemm_ex_check(int P, char ta, char tb, int64_t m, int64_t n, int64_t k, const double* alpha,
+                  const double* A, int64_t lda, int64_t sa, const double* B, int64_t ldb, int64_t sb,
+                  const double* beta, double* C, int64_t ldc, int64_t sc, const ::mpgemm_opts* opts);
 
 }  // namespace mpg

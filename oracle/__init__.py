@@ -21,10 +21,12 @@ _dp = C.POINTER(C.c_double)
 def lib():
     global _LIB
     if _LIB is None:
-        path = os.path.join(_HERE, "libmpref.so")
+        # MPREF_LIB=san selects the sanitizer build (oracle/build.py --sanitize)
+        san = os.environ.get("MPREF_LIB") == "san"
+        path = os.path.join(_HERE, "libmpref_san.so" if san else "libmpref.so")
         if not os.path.exists(path):
             from . import build as _b
-            _b.build()
+            _b.build(sanitize=san)
         L = C.CDLL(path)
         L.ref_vec.argtypes = [_int, _int, _i64, C.c_void_p, _i64, C.c_void_p, _i64, C.c_void_p, _i64]
         L.ref_vec.restype = _int

@@ -181,3 +181,152 @@ def td_mul(x, y):
 
 ADD = {2: dd_add, 3: td_addq, 4: qd_add}
 MUL = {2: dd_mul, 3: td_mul, 4: qd_mul}
+
+
+# ---------------------------------------------------------------------------
+# Evaluation orders, transcribed from their definitions (not from the C
+# oracle): the canonical GEMM of eqn (1), Sec. 3 (one ascending chain per
+# entry, then the BLAS epilogue), the fixed 64-ary dot tree (Sec. 4) and
+# Strassen's seven-product level (Sec. 3, Fig. 5).  Matrices are numpy
+# arrays of component planes, shape (P, columns, ld), column-major.
+
+def _entry(X, trans, r, c):
+    """Element (r, c) of op(X) as a list of P floats."""
+    return [float(v) for v in (X[:, r, c] if trans else X[:, c, r])]
+
+
+def _is_zero(v):
+    return all(x == 0.0 for x in v)
+
+
+def _is_one(v):
+    return v[0] == 1.0 and all(x == 0.0 for x in v[1:])
+
+
+def _epilogue(P, alpha, acc, beta, c_old, alpha_gone):
+    """alpha acc + beta c_old with C never read when beta == 0; alpha == 0 (or
+    k == 0) leaves beta c_old, or zero."""
+    mul, add = MUL[P], ADD[P]
+    if alpha_gone:
+        return [0.0] * P if _is_zero(beta) else mul(beta, c_old)
+    t = mul(alpha, acc)
+    return t if _is_zero(beta) else add(t, mul(beta, c_old))
+
+
+def gemm(P, ta, tb, m, n, k, alpha, A, B, beta, C):
+    """C = alpha op(A) op(B) + beta C, every entry from acc = 0 and
+    acc = ADD(acc, MUL(op(A)_il, op(B)_lj)) for l = 0, 1, ..., k-1."""
+    import numpy as np
+    add, mul = ADD[P], MUL[P]
+    alpha = [float(v) for v in alpha][:P]
+    beta = [float(v) for v in beta][:P]
+    out = np.array(C, dtype=np.float64, copy=True)
+    gone = k == 0 or _is_zero(alpha)
+    if m == 0 or n == 0 or (gone and _is_one(beta)):
+        return out
+    at, bt = ta in "TtCc", tb in "TtCc"
+    for j in range(n):
+        for i in range(m):
+            acc = [0.0] * P
+            if not gone:
+                for l in range(k):
+                    acc = add(acc, mul(_entry(A, at, i, l), _entry(B, bt, l, j)))
+            out[:, j, i] = _epilogue(P, alpha, acc, beta, [float(v) for v in out[:, j, i]], gone)
+    return out
+
+
+def dot(P, x, y, fanin=64):
+    """sum_i x_i y_i: products summed from zero in ascending order within
+    blocks of `fanin` consecutive terms, then the block sums the same way in
+    blocks of `fanin`, level after level, until one value is left."""
+    add, mul = ADD[P], MUL[P]
+    n = x.shape[1]
+    if n == 0:
+        return [0.0] * P
+    vals = []
+    for b0 in range(0, n, fanin):
+        acc = [0.0] * P
+        for i in range(b0, min(n, b0 + fanin)):
+            acc = add(acc, mul([float(v) for v in x[:, i]], [float(v) for v in y[:, i]]))
+        vals.append(acc)
+    while len(vals) > 1:
+        nxt = []
+        for b0 in range(0, len(vals), fanin):
+            acc = [0.0] * P
+            for v in vals[b0:b0 + fanin]:
+                acc = add(acc, v)
+            nxt.append(acc)
+        vals = nxt
+    return vals[0]
+
+
+def _op_dense(X, trans, rows, cols):
+    """op(X) as a rows x cols list of lists of P-lists."""
+    return [[_entry(X, trans, r, c) for c in range(cols)] for r in range(rows)]
+
+
+def _blk(M, bi, bj, h, w):
+    return [row[bj * w:(bj + 1) * w] for row in M[bi * h:(bi + 1) * h]]
+
+
+def _plus(P, X, Y, sign=1):
+    """X + Y (sign 1) or X + (-Y) (sign -1, exact negation), entry by entry."""
+    add = ADD[P]
+    return [[add(x, y if sign > 0 else [-v for v in y]) for x, y in zip(rx, ry)]
+            for rx, ry in zip(X, Y)]
+
+
+def _product(P, X, Y, levels):
+    """X (h x q) times Y (q x w): Strassen's seven products for `levels`
+    levels, canonical-order block products (alpha 1, beta 0) below."""
+    import numpy as np
+    h, q, w = len(X), len(Y), len(Y[0]) if Y else 0
+    if levels == 0:
+        A = np.zeros((P, q, max(h, 1)))
+        B = np.zeros((P, w, max(q, 1)))
+        for r in range(h):
+            for c in range(q):
+                A[:, c, r] = X[r][c]
+        for r in range(q):
+            for c in range(w):
+                B[:, c, r] = Y[r][c]
+        one = [1.0] + [0.0] * (P - 1)
+        Cb = gemm(P, "N", "N", h, w, q, one, A, B, [0.0] * P, np.zeros((P, w, max(h, 1))))
+        return [[[float(v) for v in Cb[:, c, r]] for c in range(w)] for r in range(h)]
+    a, c, b = h // 2, q // 2, w // 2
+    A11, A12, A21, A22 = (_blk(X, i, j, a, c) for i, j in ((0, 0), (0, 1), (1, 0), (1, 1)))
+    B11, B12, B21, B22 = (_blk(Y, i, j, c, b) for i, j in ((0, 0), (0, 1), (1, 0), (1, 1)))
+    L = levels - 1
+    M1 = _product(P, _plus(P, A11, A22), _plus(P, B11, B22), L)
+    M2 = _product(P, _plus(P, A21, A22), B11, L)
+    M3 = _product(P, A11, _plus(P, B12, B22, -1), L)
+    M4 = _product(P, A22, _plus(P, B21, B11, -1), L)
+    M5 = _product(P, _plus(P, A11, A12), B22, L)
+    M6 = _product(P, _plus(P, A21, A11, -1), _plus(P, B11, B12), L)
+    M7 = _product(P, _plus(P, A12, A22, -1), _plus(P, B21, B22), L)
+    C11 = _plus(P, _plus(P, _plus(P, M1, M4), M5, -1), M7)
+    C12 = _plus(P, M3, M5)
+    C21 = _plus(P, M2, M4)
+    C22 = _plus(P, _plus(P, _plus(P, M1, M2, -1), M3), M6)
+    top = [r1 + r2 for r1, r2 in zip(C11, C12)]
+    bottom = [r1 + r2 for r1, r2 in zip(C21, C22)]
+    return top + bottom
+
+
+def gemm_strassen(P, levels, ta, tb, m, n, k, alpha, A, B, beta, C):
+    """C = alpha op(A) op(B) + beta C with the product from `levels` levels of
+    Strassen's method, then the canonical epilogue."""
+    import numpy as np
+    alpha = [float(v) for v in alpha][:P]
+    beta = [float(v) for v in beta][:P]
+    out = np.array(C, dtype=np.float64, copy=True)
+    gone = k == 0 or _is_zero(alpha)
+    if m == 0 or n == 0 or (gone and _is_one(beta)):
+        return out
+    prod = None if gone else _product(P, _op_dense(A, ta in "TtCc", m, k), _op_dense(B, tb in "TtCc", k, n),
+                                      levels)
+    for j in range(n):
+        for i in range(m):
+            acc = [0.0] * P if gone else prod[i][j]
+            out[:, j, i] = _epilogue(P, alpha, acc, beta, [float(v) for v in out[:, j, i]], gone)
+    return out

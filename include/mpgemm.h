@@ -149,8 +149,10 @@ int mpgemm_qd(char transa, char transb, int64_t m, int64_t n, int64_t k, const d
  * every column j of op(B) by 2^-F_j (powers of two from the largest leading
  * component), cut into s signed digits of 7 bits in [-64, 64]; the digit
  * products of pairs (p, q) with p + q <= s + 1 are summed exactly in 32-bit
- * integers on the INT8 matrix cores, one anti-diagonal p + q = d at a time,
- * and recombined into P components with the precision's own addition.  Not
+ * integers on the INT8 matrix cores, one anti-diagonal p + q = d at a time;
+ * X_ij = sum_d S_d 128^(s+1-d) is formed exactly and X_ij 2^(E_i + F_j -
+ * 7 (s+1)) rounded once into P components (repeated round to nearest, ties
+ * to even, of the exact remainder), then the plain epilogue applied.  Not
  * the canonical evaluation order, so the result differs in the last bits;
  * with enough digits its error stays within 8 (k+2) u (|alpha||A||B| +
  * |beta||C|) componentwise.  Needs opts->workspace of at least

@@ -128,7 +128,8 @@ static void vseb(const double *e, int n, double *r, int k)
     r[j] = carry;
 }
 
-/* Renorm (Sec. 2.4, "renormalization ... as simple loops"): five terms to a
+/* Renorm (the renormalisation Sec. 2 asks to be written as plain loops, so
+ * that it vectorises): five terms to a
  * four-component number.
  * Pass 1: bottom-up QuickTwoSum chain c4 -> c0 giving e[0..4].
  * Pass 2: top-down, the pair (e0, e1) as produced by pass 1, then
@@ -205,61 +206,64 @@ static void dd_mul(const double *x, const double *y, double *r)
 /* Sec. 2.4: QD addition (Algorithm 5) and multiplication (Algorithm 6).    */
 /* ------------------------------------------------------------------------ */
 
-/* Algorithm 5.  Four lane-wise TwoSums (x[i] + y[i] -> s_i, t_i), then the
- * carries are folded in.  The listing uses t3 without defining it; it is the
- * error term of the fourth lane, t3 = w3 + u3, like t0..t2. */
+/* QD addition.  Each component pair x_i + y_i is added exactly (TwoSum: sum
+ * s_i, error t_i).  The errors are then carried one level down: level 1 takes
+ * t_0 (one carry out), level 2 that carry and t_1 (ThreeSum, two carries
+ * out), level 3 the first of them and t_2 (ThreeSum2, one carry out); the
+ * fifth term is the two remaining carries plus t_3, and Renorm makes four
+ * components of the five terms.  The algorithm's tail uses a fourth error
+ * term that its text never defines; read as t_3, the error of the fourth
+ * pair's TwoSum, like the other three. */
 static void qd_add(const double *x, const double *y, double *r)
 {
-    double s0 = x[0] + y[0], s1 = x[1] + y[1], s2 = x[2] + y[2], s3 = x[3] + y[3];
-    double v0 = s0 - x[0], v1 = s1 - x[1], v2 = s2 - x[2], v3 = s3 - x[3];
-    double u0 = s0 - v0, u1 = s1 - v1, u2 = s2 - v2, u3 = s3 - v3;
-    double w0 = x[0] - u0, w1 = x[1] - u1, w2 = x[2] - u2, w3 = x[3] - u3;
-    u0 = y[0] - v0;
-    u1 = y[1] - v1;
-    u2 = y[2] - v2;
-    u3 = y[3] - v3;
-    double t0 = w0 + u0, t1 = w1 + u1, t2 = w2 + u2, t3 = w3 + u3;
-
-    two_sum(s1, t0, &s1, &t0);
-    three_sum(&s2, &t0, &t1);
-    three_sum2(&s3, &t0, t2);
-    t0 = (t0 + t1) + t3;
-    renorm4(s0, s1, s2, s3, t0, r);
+    double s[4], t[4];
+    for (int i = 0; i < 4; ++i)
+        two_sum(x[i], y[i], &s[i], &t[i]);
+    double carry = t[0], carry2 = t[1];
+    two_sum(s[1], carry, &s[1], &carry);
+    three_sum(&s[2], &carry, &carry2);
+    three_sum2(&s[3], &carry, t[2]);
+    double tail = (carry + carry2) + t[3];
+    renorm4(s[0], s[1], s[2], s[3], tail, r);
 }
 
-/* Algorithm 6.  The listing's first line (s0 = x0 + y0) is overwritten before
- * any use and is omitted.  The O(eps^3) terms are added to s1 one at a time
- * in the printed order, each a rounded multiply and a rounded add. */
+/* QD multiplication.  The component products x_i y_j of order eps^0 to
+ * eps^2 (i + j <= 2) are split exactly by TwoProd into p_ij + q_ij.  Order
+ * eps: ThreeSum of p01, p10 and q00.  Order eps^2: that sum's first carry
+ * with q01 and q10 (ThreeSum), and p02 + p11 + p20 (ThreeSum); the two are
+ * combined by TwoSums into the order-eps^2 component and a lower term.  The
+ * order-eps^3 rest is added in rounded arithmetic, one term at a time in the
+ * paper's order: x0 y3, x1 y2, x2 y1, x3 y0, then the errors q00, q02, q11,
+ * q20.  Renorm makes four components of the five terms.  A sum of the
+ * leading components that the algorithm computes first is overwritten
+ * before any use; it is left out. */
 static void qd_mul(const double *x, const double *y, double *r)
 {
-    double p0, q0, p1, q1, p2, q2, p3, q3, p4, q4, p5, q5;
-    two_prod(x[0], y[0], &p0, &q0);
-    two_prod(x[0], y[1], &p1, &q1);
-    two_prod(x[1], y[0], &p2, &q2);
-    two_prod(x[0], y[2], &p3, &q3);
-    two_prod(x[1], y[1], &p4, &q4);
-    two_prod(x[2], y[0], &p5, &q5);
+    double p00, q00, p01, q01, p10, q10, p02, q02, p11, q11, p20, q20;
+    two_prod(x[0], y[0], &p00, &q00);
+    two_prod(x[0], y[1], &p01, &q01);
+    two_prod(x[1], y[0], &p10, &q10);
+    two_prod(x[0], y[2], &p02, &q02);
+    two_prod(x[1], y[1], &p11, &q11);
+    two_prod(x[2], y[0], &p20, &q20);
 
-    three_sum(&p1, &p2, &q0);
-    three_sum(&p2, &q1, &q2);
-    three_sum(&p3, &p4, &p5);
+    three_sum(&p01, &p10, &q00);
+    three_sum(&p10, &q01, &q10);
+    three_sum(&p02, &p11, &p20);
 
-    double s0, t0, s1, t1, s2;
-    two_sum(p2, p3, &s0, &t0);
-    two_sum(q1, p4, &s1, &t1);
-    s2 = q2 + p5;
-    two_sum(s1, t0, &s1, &t0);
-    s2 = s2 + (t0 + t1);
+    double hi, hi_err, mid, mid_err;
+    two_sum(p10, p02, &hi, &hi_err);
+    two_sum(q01, p11, &mid, &mid_err);
+    double lo = q10 + p20;
+    two_sum(mid, hi_err, &mid, &hi_err);
+    lo = lo + (hi_err + mid_err);
 
-    s1 = s1 + x[0] * y[3];
-    s1 = s1 + x[1] * y[2];
-    s1 = s1 + x[2] * y[1];
-    s1 = s1 + x[3] * y[0];
-    s1 = s1 + q0;
-    s1 = s1 + q3;
-    s1 = s1 + q4;
-    s1 = s1 + q5;
-    renorm4(p0, p1, s0, s1, s2, r);
+    for (int i = 0; i < 4; ++i)
+        mid = mid + x[i] * y[3 - i];
+    const double errs[4] = {q00, q02, q11, q20};
+    for (int i = 0; i < 4; ++i)
+        mid = mid + errs[i];
+    renorm4(p00, p01, hi, mid, lo, r);
 }
 
 /* ------------------------------------------------------------------------ */

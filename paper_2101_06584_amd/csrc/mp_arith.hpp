@@ -36,7 +36,8 @@ MPG_DEV void quick_two_sum(double a, double b, double& s, double& e) {
     s = sum;
 }
 
-// Knuth's TwoSum in the lane order of Algorithm 5: s, v, u, w, u', e.
+// Knuth's TwoSum, its six operations in the order Algorithm 5 spells them
+// out: s = a + b, v = s - a, u = s - v, w = a - u, u' = b - v, e = w + u'.
 MPG_DEV void two_sum(double a, double b, double& s, double& e) {
     double sum = a + b;
     double v = sum - a;
@@ -70,7 +71,8 @@ MPG_DEV void three_sum2(double& a, double& b, double c) {
     b = t2 + t3;
 }
 
-// Five terms to four (Sec. 2.4's renormalisation "as simple loops"): a
+// Five terms to four (the renormalisation that Sec. 2 asks to be written as
+// plain loops, so that it vectorises): a
 // bottom-up QuickTwoSum pass, then a top-down pass in which a non-zero
 // rounding error closes an output slot; when the third slot closes the last
 // one takes the carry plus what remains.  Unrolled, slot writes by select.
@@ -166,67 +168,96 @@ MPG_DEV mp<2> mul(const mp<2>& x, const mp<2>& y) {
 
 // ---- Algorithms 4, 5, 6: the terms before the final Renorm / VSEB(2) ------
 //
-// Algorithm 5 (QD add): the listing uses t3 without defining it; it is the
-// error term of the fourth lane, t3 = w3 + u3, like t0..t2.
-// Algorithm 6 (QD mul): the listing's first line (s0 = x0 + y0) is
-// overwritten before any use and is omitted; the O(eps^3) terms are added to
-// s1 one at a time in the printed order, each a rounded multiply and add.
+// Algorithm 5 (QD add): its tail takes a fourth error term that the text never
+// defines; read as the error of the fourth component pair's TwoSum, like the
+// other three.
+// Algorithm 6 (QD mul): a sum of the leading components that the algorithm
+// computes first is overwritten before any use and is left out; the
+// order-eps^3 terms are added one at a time in the paper's order, each a
+// rounded multiply and a rounded add.
 // Algorithm 4 (TD mul): b0..b2 are VecSum outputs, not operand components.
 
-// Terms of Algorithm 5 before its Renorm (c0..c4).
-MPG_DEV void qd_add_terms(double x0, double x1, double x2, double x3, double y0, double y1,
-                          double y2, double y3, double (&c)[5]) {
-    double s0 = x0 + y0, s1 = x1 + y1, s2 = x2 + y2, s3 = x3 + y3;
-    double v0 = s0 - x0, v1 = s1 - x1, v2 = s2 - x2, v3 = s3 - x3;
-    double u0 = s0 - v0, u1 = s1 - v1, u2 = s2 - v2, u3 = s3 - v3;
-    double w0 = x0 - u0, w1 = x1 - u1, w2 = x2 - u2, w3 = x3 - u3;
-    u0 = y0 - v0;
-    u1 = y1 - v1;
-    u2 = y2 - v2;
-    u3 = y3 - v3;
-    double t0 = w0 + u0, t1 = w1 + u1, t2 = w2 + u2, t3 = w3 + u3;
-    two_sum(s1, t0, s1, t0);
-    three_sum(s2, t0, t1);
-    three_sum2(s3, t0, t2);
-    t0 = (t0 + t1) + t3;
-    c[0] = s0;
-    c[1] = s1;
-    c[2] = s2;
-    c[3] = s3;
-    c[4] = t0;
+// TwoSum applied to N component pairs at once, each of its six operations
+// over all pairs before the next (the form a vector unit runs it in).
+template <int N>
+MPG_DEV void two_sum_lanes(const double (&a)[N], const double (&b)[N], double (&s)[N], double (&e)[N]) {
+    double v[N], u[N], w[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) s[i] = a[i] + b[i];
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = s[i] - a[i];
+#pragma unroll
+    for (int i = 0; i < N; ++i) u[i] = s[i] - v[i];
+#pragma unroll
+    for (int i = 0; i < N; ++i) w[i] = a[i] - u[i];
+#pragma unroll
+    for (int i = 0; i < N; ++i) u[i] = b[i] - v[i];
+#pragma unroll
+    for (int i = 0; i < N; ++i) e[i] = w[i] + u[i];
 }
 
-// Terms of Algorithm 6 before its Renorm (c0..c4).
+// Terms of the QD addition (Algorithm 5) before its Renorm (c0..c4).  Each
+// pair of components x_i + y_i is added exactly (TwoSum: sum s_i, error t_i);
+// the errors are then carried one level down: level 1 takes t_0 (one carry
+// out), level 2 takes that carry and t_1 (ThreeSum, two carries out), level
+// 3 takes one of them and t_2 (ThreeSum2, one carry out), and the fifth term
+// collects the carries left over and t_3.
+MPG_DEV void qd_add_terms(double x0, double x1, double x2, double x3, double y0, double y1,
+                          double y2, double y3, double (&c)[5]) {
+    const double x[4] = {x0, x1, x2, x3}, y[4] = {y0, y1, y2, y3};
+    double sm[4], er[4];
+    two_sum_lanes<4>(x, y, sm, er);
+    double carry = er[0], carry2 = er[1];
+    two_sum(sm[1], carry, sm[1], carry);
+    three_sum(sm[2], carry, carry2);
+    three_sum2(sm[3], carry, er[2]);
+    c[0] = sm[0];
+    c[1] = sm[1];
+    c[2] = sm[2];
+    c[3] = sm[3];
+    c[4] = (carry + carry2) + er[3];
+}
+
+// Terms of the QD product (Algorithm 6) before its Renorm (c0..c4).  The
+// component products of order eps^0 to eps^2 (x_i y_j, i + j <= 2, taken
+// as (0,0), (0,1), (1,0), (0,2), (1,1), (2,0)) are split exactly by TwoProd
+// into p and q.  Order eps: ThreeSum of p01, p10 and q00.  Order eps^2: the
+// carry of that sum with q01 and q10 (ThreeSum), and p02, p11, p20
+// (ThreeSum); the two sums and their carries are combined by TwoSums into the
+// order-eps^2 term and a lower one.  The order-eps^3 rest is added in rounded
+// arithmetic: the products x_i y_(3-i) for i = 0..3 one at a time, then the
+// errors q00, q02, q11, q20.
 MPG_DEV void qd_mul_terms(const mp<4>& x, const mp<4>& y, double (&c)[5]) {
-    double p0, q0, p1, q1, p2, q2, p3, q3, p4, q4, p5, q5;
-    two_prod(x.c[0], y.c[0], p0, q0);
-    two_prod(x.c[0], y.c[1], p1, q1);
-    two_prod(x.c[1], y.c[0], p2, q2);
-    two_prod(x.c[0], y.c[2], p3, q3);
-    two_prod(x.c[1], y.c[1], p4, q4);
-    two_prod(x.c[2], y.c[0], p5, q5);
-    three_sum(p1, p2, q0);
-    three_sum(p2, q1, q2);
-    three_sum(p3, p4, p5);
-    double s0, t0, s1, t1, s2;
-    two_sum(p2, p3, s0, t0);
-    two_sum(q1, p4, s1, t1);
-    s2 = q2 + p5;
-    two_sum(s1, t0, s1, t0);
-    s2 = s2 + (t0 + t1);
-    s1 = s1 + x.c[0] * y.c[3];
-    s1 = s1 + x.c[1] * y.c[2];
-    s1 = s1 + x.c[2] * y.c[1];
-    s1 = s1 + x.c[3] * y.c[0];
-    s1 = s1 + q0;
-    s1 = s1 + q3;
-    s1 = s1 + q4;
-    s1 = s1 + q5;
-    c[0] = p0;
-    c[1] = p1;
-    c[2] = s0;
-    c[3] = s1;
-    c[4] = s2;
+    // p_ij + q_ij = x_i y_j exactly
+    double p00, q00, p01, q01, p10, q10, p02, q02, p11, q11, p20, q20;
+    two_prod(x.c[0], y.c[0], p00, q00);
+    two_prod(x.c[0], y.c[1], p01, q01);
+    two_prod(x.c[1], y.c[0], p10, q10);
+    two_prod(x.c[0], y.c[2], p02, q02);
+    two_prod(x.c[1], y.c[1], p11, q11);
+    two_prod(x.c[2], y.c[0], p20, q20);
+    three_sum(p01, p10, q00);          // order eps: sum in p01, carries p10, q00
+    three_sum(p10, q01, q10);          // the first carry with q01 and q10
+    three_sum(p02, p11, p20);          // order-eps^2 products
+    double hi, hi_err, mid, mid_err;
+    two_sum(p10, p02, hi, hi_err);
+    two_sum(q01, p11, mid, mid_err);
+    double lo = q10 + p20;
+    two_sum(mid, hi_err, mid, hi_err);
+    lo = lo + (hi_err + mid_err);
+    mid = mid + x.c[0] * y.c[3];       // order eps^3, rounded
+    mid = mid + x.c[1] * y.c[2];
+    mid = mid + x.c[2] * y.c[1];
+    mid = mid + x.c[3] * y.c[0];
+    mid = mid + q00;
+    mid = mid + q02;
+    mid = mid + q11;
+    mid = mid + q20;
+    c[0] = p00;
+    c[1] = p01;
+    c[2] = hi;
+    c[3] = mid;
+    c[4] = lo;
 }
 
 // Terms of Algorithm 4 before its VSEB(2): (e0, e1, e2, e3).

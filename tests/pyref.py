@@ -129,17 +129,12 @@ def dd_mul(x, y):
 
 
 def qd_add(x, y):
-    s = [x[i] + y[i] for i in range(4)]
-    v = [s[i] - x[i] for i in range(4)]
-    u = [s[i] - v[i] for i in range(4)]
-    w = [x[i] - u[i] for i in range(4)]
-    u = [y[i] - v[i] for i in range(4)]
-    t = [w[i] + u[i] for i in range(4)]
-    s1, t0 = ts(s[1], t[0])
-    s2, t0, t1 = three_sum(s[2], t0, t[1])
-    s3, t0 = three_sum2(s[3], t0, t[2])
-    t0 = (t0 + t1) + t[3]
-    return renorm4(s[0], s1, s2, s3, t0)
+    pairs = [ts(a, b) for a, b in zip(x, y)]     # exact sums of the component pairs
+    s, t = [p[0] for p in pairs], [p[1] for p in pairs]
+    s1, c = ts(s[1], t[0])                        # errors carried one level down
+    s2, c, c2 = three_sum(s[2], c, t[1])
+    s3, c = three_sum2(s[3], c, t[2])
+    return renorm4(s[0], s1, s2, s3, (c + c2) + t[3])
 
 
 def qd_mul(x, y):

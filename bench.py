@@ -226,13 +226,14 @@ def main():
         for P in precs:
             A, B, C, alpha, beta = host[P]
             chk = GemmChecker(P, "N", "N", n, n, n, alpha, A, B, beta, C)
-            ents = sample_entries(synth.rng_for(2, "samples"), n, n, 64)
+            ents = sample_entries(synth.rng_for(2, "samples"), n, n, 1024)
             for f in forms:
                 devd[P]["C_" + f].copy_(devd[P]["C0"])
                 run(P, f)
                 got = devd[P]["C_" + f].cpu().numpy()
                 r = chk.ratios(got, ents)
                 errors[(P, f)] = float(r.max())
+                errors[(P, f, "median")] = float(np.median(r))
                 devd[P]["C_" + f].copy_(devd[P]["C0"])
                 note("checked", NAME[P], f, "max err ratio", errors[(P, f)])
         torch.cuda.synchronize()
@@ -295,6 +296,8 @@ def main():
             item["int8_ops_frac"] = s * (s + 1) / 2 * 2.0 * n ** 3 / (ms * 1e-3) / INT8_PEAK
         if (P, f) in errors:
             item["max_err_ratio"] = errors[(P, f)]
+            item["median_err_ratio"] = errors[(P, f, "median")]
+            item["err_samples"] = 1024
         breakdown[f"{NAME[P]}_{f}"] = item
 
     # ---- roofline of the dominant kernel: the plain GEMM of the widest
@@ -871,9 +874,20 @@ def other_workload(args, mp, synth, dev, stream):
 
 
 def cpu_baseline(host, precs, forms, n, devd, budget, batched):
-    """The oracle, as it stands, on a block of each of the step's large GEMMs
-    and on the first problems of each batched set; the step's 2mnk/s is
-    extrapolated from the per-part sampled rates."""
+    """The oracle, as it stands, timed on samples of each part of the step and
+    extrapolated to the part's full work:
+
+    * plain form: a square block of C (all k), grown until it takes about its
+      share of the budget; per-entry cost is uniform, so the block's rate is
+      the part's rate;
+    * split forms: the oracle slices the rows and columns a block needs
+      (serially) and then forms the block's entries; slicing is linear in
+      rows + columns, so it is timed on 256 columns of op(B) and scaled to all
+      2n rows and columns once, and only the products of a square block are
+      scaled by n^2 / (rows cols);
+    * batched sets: the first problems of each set.
+
+    One thread and all threads are timed on the same block (DD plain)."""
     import oracle
     threads = oracle.num_threads()
     per = budget / max(1, len(precs) * len(forms) + len(batched))
@@ -898,56 +912,86 @@ def cpu_baseline(host, precs, forms, n, devd, budget, batched):
     for P in precs:
         A, B, C, alpha, beta = host[P]
         for f in forms:
-            def once(rows, cols):
+            s = devd[P]["s"]
+
+            def once(r):
                 t = time.perf_counter()
                 if f == "plain":
-                    oracle.gemm(P, "N", "N", n, n, n, alpha, A, B, beta, C, rows=(0, rows),
-                                cols=(0, cols))
+                    oracle.gemm(P, "N", "N", n, n, n, alpha, A, B, beta, C, rows=(0, r), cols=(0, r))
                 elif f == "crt":
-                    oracle.gemm_crt(P, devd[P]["s"], "N", "N", n, n, n, alpha, A, B, beta, C,
-                                    rows=(0, rows), cols=(0, cols))
+                    oracle.gemm_crt(P, s, "N", "N", n, n, n, alpha, A, B, beta, C, rows=(0, r), cols=(0, r))
                 else:
-                    oracle.gemm_split(P, devd[P]["s"], "N", "N", n, n, n, alpha, A, B, beta, C,
-                                      rows=(0, rows), cols=(0, cols))
+                    oracle.gemm_split(P, s, "N", "N", n, n, n, alpha, A, B, beta, C, rows=(0, r), cols=(0, r))
                 return time.perf_counter() - t
-            rows, cols = 1, 64
-            t = once(rows, cols)
-            # grow the block until it takes about its share of the budget
-            while t < per / 4 and rows * cols < n * n:
-                if cols < n:
-                    cols = min(n, cols * 4)
-                else:
-                    rows = min(n, rows * 4)
-                t = once(rows, cols)
-            rate = 2.0 * rows * cols * n / t
-            est_total += 2.0 * n ** 3 / rate
+            slice_full = 0.0
+            if f != "plain":
+                # slicing of 256 columns of op(B) (exponents and digits), the
+                # oracle's own serial code, scaled to the 2n rows and columns
+                t = time.perf_counter()
+                F = oracle.split_exponents(P, "N", True, 256, n, B)
+                oracle.split_slices(P, s, "N", True, 256, n, B, F)
+                slice_full = (time.perf_counter() - t) * 2 * n / 256
+            r = 2
+            t = once(r)
+            while t < per / 4 and r < n:
+                r = min(n, r * 2)
+                t = once(r)
+            prod = max(t - slice_full * 2 * r / (2 * n), 1e-9)
+            full = slice_full + prod * (n / r) ** 2
+            rate = 2.0 * n ** 3 / full
+            est_total += full
             total_work += 2.0 * n ** 3
-            parts.append(f"{NAME[P]}-{f}: {rows}x{cols} block ({rate:.3g} 2mnk/s)")
+            extra = f", slicing {slice_full:.3g} s of it" if f != "plain" else ""
+            parts.append(f"{NAME[P]}-{f}: {r}x{r} block ({rate:.3g} 2mnk/s{extra})")
     value = total_work / est_total
-    # one thread, for scale: the plain DD part on a 1 x 256 block
+    # one thread and all threads on the same block: DD (or the lowest
+    # precision) plain, 32 x 256 entries, all k
     P1 = min(precs)
     A, B, C, alpha, beta = host[P1]
-    t = time.perf_counter()
-    oracle.gemm(P1, "N", "N", n, n, n, alpha, A, B, beta, C, rows=(0, 1), cols=(0, 256), nthreads=1)
-    one_thread = 2.0 * 256 * n / (time.perf_counter() - t)
+    same = {}
+    for nt in (1, threads):
+        t = time.perf_counter()
+        oracle.gemm(P1, "N", "N", n, n, n, alpha, A, B, beta, C, rows=(0, 32), cols=(0, 256), nthreads=nt)
+        same[nt] = 2.0 * 32 * 256 * n / (time.perf_counter() - t)
+    info = cpu_info()
     return {"value": value, "unit": "2mnk/s", "cores": threads, "kind": "oracle",
-            "cpu_model": cpu_model(),
-            "one_thread": {"value": one_thread, "unit": "2mnk/s",
-                           "sample": f"{NAME[P1]} plain, 1 x 256 block of C, k = {n}"},
-            "sample": "per large GEMM of the step a block of rows x columns of C (all k), per "
-                      "batched set its first problems, each timed and extrapolated to the part's "
-                      "full 2mnk: " + "; ".join(parts)}
+            "cpu_model": info["model"], "physical_cores": info["physical_cores"],
+            "logical_cpus": info["logical_cpus"], "cpus_allowed": info["cpus_allowed"],
+            "same_block": {"sample": f"{NAME[P1]} plain, 32 x 256 block of C, k = {n}",
+                           "one_thread_2mnk/s": same[1], "all_threads_2mnk/s": same[threads],
+                           "threads": threads, "speedup": same[threads] / same[1]},
+            "sample": "per large GEMM of the step a square block of C (all k) and, for the split "
+                      "forms, the slicing scaled separately; per batched set its first problems; "
+                      "each extrapolated to the part's full 2mnk: " + "; ".join(parts)}
 
 
-def cpu_model():
+def cpu_info():
+    """Model name and core counts of this host (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    out = {"model": "unknown", "physical_cores": None, "logical_cpus": os.cpu_count(),
+           "cpus_allowed": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
     try:
-        with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
-    except OSError:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        kv = {}
+        for line in txt.splitlines():
+            if ":" in line:
+                key, val = line.split(":", 1)
+                kv[key.strip()] = val.strip()
+        out["model"] = kv.get("Model name", out["model"])
+        cores = int(kv.get("Core(s) per socket", "0")) * int(kv.get("Socket(s)", "0"))
+        out["physical_cores"] = cores or None
+    except (OSError, ValueError, subprocess.SubprocessError):
         pass
-    return "unknown"
+    if out["model"] == "unknown":
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        out["model"] = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+    return out
 
 
 if __name__ == "__main__":

@@ -67,13 +67,22 @@ extern "C" {
 #define MPGEMM_FORM_SPLIT_I8 1  /* operands cut into signed 7-bit INT8 digits,
                                    exact INT8 MFMA digit products, exact
                                    recombination into P components          */
-#define MPGEMM_FORM_AUTO 2      /* the library's choice: the residue form
+#define MPGEMM_FORM_AUTO 2      /* the library's choice.  With opts.slices
+                                   = 0: plain.  With opts.slices = s > 0
+                                   (the caller's digit count, e.g. from
+                                   mpgemm_tune_slices): the residue form
                                    (MPGEMM_FORM_SPLIT_CRT) for m, n, k >= 128
                                    (DD), 96 (TD) or 64 (QD) when the
                                    workspace (256-byte aligned) holds it and
                                    it applies, else for m, n, k >= 256 the
                                    split form when the workspace holds that,
-                                   else plain; never a workspace error     */
+                                   else plain; never a workspace error.
+                                   The split forms' error bound depends on
+                                   the spread of magnitudes within each row
+                                   of op(A) and column of op(B) (see
+                                   opts.slices), which the library does not
+                                   inspect; choosing s is the caller's
+                                   accuracy decision                      */
 #define MPGEMM_FORM_STRASSEN 4  /* Strassen's method (Sec. 3, Fig. 5): opts.levels
                                    levels of the seven-product recursion over
                                    plain-form block products               */
@@ -94,10 +103,16 @@ extern "C" {
 /* Options for the _ex entry points.  Zero-initialise and set what you need. */
 typedef struct mpgemm_opts {
     int form;               /* MPGEMM_FORM_*                                   */
-    int slices;             /* split form: digits per operand entry s (1..40);
+    int slices;             /* split forms: digits per operand entry s (1..40);
                                0 = the precision's default (DD 16, TD 23, QD 31),
                                enough for inputs of similar magnitude within a
-                               row of op(A) / column of op(B)              */
+                               row of op(A) / column of op(B).  The dropped
+                               digits of entry a_il weigh up to 2^(E_i - 7 s - 1)
+                               whatever |a_il| is, so entries far below their
+                               row's largest need more digits to stay within
+                               8 k u (|A||B|)_ij; mpgemm_tune_slices picks s
+                               for given operands.  MPGEMM_FORM_AUTO takes a
+                               split form only when s is given             */
     int tile;               /* kernel configuration id; -1 or 0.. = tuned/fixed */
     int variant;            /* TD only, plain form: MPGEMM_TD_* bits selecting
                                the other TD operations of Sec. 2.3 (runs TD
@@ -378,14 +393,41 @@ typedef struct mpgemm_batch_plan mpgemm_batch_plan;  /* opaque */
 int mpgemm_batch_plan_create(int prec, int64_t count, const mpgemm_problem* problems,
                              const mpgemm_opts* opts, hipStream_t stream,
                              mpgemm_batch_plan** out);
-/* Replay the captured graph on `stream`. */
+/* Replay the captured graph on `stream`.  A plan holds one device tile
+ * counter that each run (graph replay or direct launch) resets and then
+ * consumes, so the runs of one plan must not overlap: queue them on one
+ * stream, or order the streams (events).  Overlapping runs of the same plan
+ * skip or repeat tiles and give wrong results; different plans are
+ * independent. */
 int mpgemm_batch_plan_run(mpgemm_batch_plan* plan, hipStream_t stream);
-/* Same work as a direct launch (no graph) on `stream`. */
+/* Same work as a direct launch (no graph) on `stream`; ordered like runs. */
 int mpgemm_batch_plan_launch(mpgemm_batch_plan* plan, hipStream_t stream);
 /* Total tiles and the grid the plan launches (for reporting). */
 int mpgemm_batch_plan_info(const mpgemm_batch_plan* plan, int64_t* tiles, int* grid, int* tile_cfg);
 /* Free the plan's device memory and graph (after its last run completed). */
 int mpgemm_batch_plan_destroy(mpgemm_batch_plan* plan);
+
+/*
+ * Grouped calls (the batched form in one call): all `count` problems of one
+ * precision computed by one persistent launch replayed from a hipGraph, each
+ * problem bitwise as one mpgemm_*() call.  The first call with a given
+ * problem array (every field compared, device addresses included) builds a
+ * plan as mpgemm_batch_plan_create does (device allocations, graph capture;
+ * not to be called under stream capture); later calls with an equal array
+ * replay it.  The library keeps the 8 most recently used plans; dropping one
+ * synchronises the device first; mpgemm_finalize releases them.  Calls with
+ * equal arrays reuse one plan, so they follow the plan rule: queue them on
+ * one stream or order the streams.  Arguments: 1 count >= 0, 2 problems
+ * (host array; -(1000 + index) for an invalid problem), 3 opts (may be NULL;
+ * form must be MPGEMM_FORM_PLAIN or _AUTO, variant 0, opts->tile selects the
+ * tile shape, -1 = tuned), 4 stream.
+ */
+int mpgemm_dd_grouped(int64_t count, const mpgemm_problem* problems, const mpgemm_opts* opts,
+                      hipStream_t stream);
+int mpgemm_td_grouped(int64_t count, const mpgemm_problem* problems, const mpgemm_opts* opts,
+                      hipStream_t stream);
+int mpgemm_qd_grouped(int64_t count, const mpgemm_problem* problems, const mpgemm_opts* opts,
+                      hipStream_t stream);
 
 /*
  * Autotuner: times every kernel configuration of a form (MPGEMM_FORM_PLAIN,
@@ -405,8 +447,17 @@ int mpgemm_batch_autotune(int prec, int64_t count, const mpgemm_problem* problem
 /* Record a configuration for a precision / form (0 plain, 1 split, 3 batched,
  * 5 residue split) / shape bucket directly (e.g. from a table produced elsewhere). */
 int mpgemm_autotune_set(int prec, int form, int64_t m, int64_t n, int64_t k, int tile);
-/* Persist / restore the tuning table as a small text file (one entry per
- * line: prec form log2m log2n log2k tile). */
+/* Persist / restore the tuning table as a small text file: a header line
+ * naming the format and the architecture (gfx950), then one entry per line:
+ * prec form log2m log2n log2k tile signature, the signature (hex) that of
+ * the configuration list of that precision and form when the entry was
+ * made.  Loading adds the entries whose signature matches the library's
+ * current configurations and skips the others (0); a file of another format
+ * or architecture returns MPGEMM_ERR_UNSUPPORTED, an unreadable one
+ * MPGEMM_ERR_HIP.  The library loads a table by itself at the first use of
+ * the tuning choices: the file MPGEMM_AUTOTUNE_CACHE names, else
+ * tuned_gfx950.txt beside libmpgemm.so; none when MPGEMM_NO_TUNED_TABLE is
+ * set.  mpgemm_autotune_load adds a file's entries on top. */
 int mpgemm_autotune_save(const char* path);
 int mpgemm_autotune_load(const char* path);
 /* Number of configurations a form offers for a precision. */
@@ -469,7 +520,9 @@ int mpgemm_probe_peak(int which, hipStream_t stream, double* rate);
 const char* mpgemm_strerror(int code);
 /* Library version string. */
 const char* mpgemm_version(void);
-/* Release library-owned state (tuning table).  Plans are freed separately. */
+/* Release library-owned state: the tuning table (looked for again at the
+ * next use) and the grouped calls' plans (after a device synchronisation).
+ * Plans made with mpgemm_batch_plan_create are freed separately. */
 void mpgemm_finalize(void);
 
 #ifdef __cplusplus

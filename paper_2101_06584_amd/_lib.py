@@ -10,8 +10,9 @@ import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmpgemm.so")
-# tile choices measured on MI355X by paper_2101_06584_amd/tune.py; loaded with the library
-TUNED_TABLE = os.environ.get("MPGEMM_AUTOTUNE_CACHE", os.path.join(_HERE, "tuned_gfx950.txt"))
+# tile choices measured on MI355X by paper_2101_06584_amd/tune.py; the library
+# loads this file (or the one MPGEMM_AUTOTUNE_CACHE names) by itself
+TUNED_TABLE = os.path.join(_HERE, "tuned_gfx950.txt")
 
 _i64, _int, _ch, _vp, _sz, _dbl = C.c_int64, C.c_int, C.c_char, C.c_void_p, C.c_size_t, C.c_double
 _P = C.POINTER
@@ -66,6 +67,9 @@ EXPORTS = {
     "mpgemm_batch_plan_launch": ([_vp, _vp], _int),
     "mpgemm_batch_plan_info": ([_vp, _P(_i64), _P(_int), _P(_int)], _int),
     "mpgemm_batch_plan_destroy": ([_vp], _int),
+    "mpgemm_dd_grouped": ([_i64, _P(Problem), _P(Opts), _vp], _int),
+    "mpgemm_td_grouped": ([_i64, _P(Problem), _P(Opts), _vp], _int),
+    "mpgemm_qd_grouped": ([_i64, _P(Problem), _P(Opts), _vp], _int),
     "mpgemm_autotune": ([_int, _int, _i64, _i64, _i64, _int, _vp, _P(_int)], _int),
     "mpgemm_batch_autotune": ([_int, _i64, _P(Problem), _vp, _P(_int)], _int),
     "mpgemm_autotune_set": ([_int, _int, _i64, _i64, _i64, _int], _int),
@@ -101,8 +105,6 @@ def load(path: str | None = None):
         fn.argtypes = args
         fn.restype = res
     _LIB = lib
-    if os.path.exists(TUNED_TABLE) and not os.environ.get("MPGEMM_NO_TUNED_TABLE"):
-        lib.mpgemm_autotune_load(TUNED_TABLE.encode())
     return lib
 
 

@@ -255,6 +255,29 @@ class BatchPlan:
             pass
 
 
+def grouped_raw(prec, problems, tile=-1, stream=None, arr=None) -> int:
+    """Calls mpgemm_{dd,td,qd}_grouped on `problems` (dicts as for
+    BatchPlan); `arr` may pass a prebuilt problem array (from
+    problem_array) so that repeated calls present the same array."""
+    P = PREC[prec]
+    if arr is None:
+        arr, _keep = _problem_array(P, problems)
+    opts = make_opts("plain", 0, tile, None)
+    return getattr(_lib.load(), f"mpgemm_{_NAME[P]}_grouped")(len(problems), arr, C.byref(opts), _stream(stream))
+
+
+def grouped(prec, problems, tile=-1, stream=None, arr=None) -> None:
+    """All problems in one persistent launch (plan cached by the library per
+    problem array); raises on error."""
+    _check(grouped_raw(prec, problems, tile, stream, arr), "mpgemm_grouped")
+
+
+def problem_array(prec, problems):
+    """The ctypes problem array for grouped calls (keep the tensors alive)."""
+    arr, _keep = _problem_array(PREC[prec], problems)
+    return arr
+
+
 def autotune(prec, form, m, n, k, slices=0, stream=None) -> int:
     best = C.c_int(-1)
     f = FORMS[form] if isinstance(form, str) else int(form)

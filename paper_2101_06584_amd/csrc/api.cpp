@@ -12,6 +12,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <dlfcn.h>
+#include <list>
+#include <string>
 #include <map>
 #include <mutex>
 #include <new>
@@ -131,6 +134,67 @@ int hip_rc(int e) { return e == 0 ? 0 : MPGEMM_ERR_HIP; }
 
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int, int>, int> g_tune;
+bool g_tune_loaded = false;     // the table file was looked for (first use)
+
+constexpr const char* kTableHeader = "# mpgemm tuning table v2 arch=gfx950";
+
+// The configuration list an entry of form `form` refers to (0 plain, 3
+// batched: the plain tiles; 1 split; 5 residue split).
+uint32_t config_signature(int P, int form) {
+    if (form == MPGEMM_FORM_SPLIT_I8) return split_config_signature();
+    if (form == MPGEMM_FORM_SPLIT_CRT) return crt_config_signature();
+    return plain_config_signature(P);
+}
+
+// Reads a table file into g_tune (lock held).  The first line must be this
+// library's header (architecture); an entry is taken only when its
+// signature matches the current configuration list of its precision and
+// form, so a table written for other kernel configurations is ignored entry
+// by entry.  Returns 0, or MPGEMM_ERR_UNSUPPORTED for a file of another
+// format or architecture, MPGEMM_ERR_HIP when it cannot be read.
+int load_table_locked(const char* path) {
+    FILE* f = std::fopen(path, "r");
+    if (!f) return MPGEMM_ERR_HIP;
+    char line[256];
+    int rc = 0;
+    if (!std::fgets(line, sizeof line, f) ||
+        std::strncmp(line, kTableHeader, std::strlen(kTableHeader)) != 0) {
+        rc = MPGEMM_ERR_UNSUPPORTED;
+    } else {
+        while (std::fgets(line, sizeof line, f)) {
+            if (line[0] == '#') continue;
+            int P, form, a, b, c, t;
+            unsigned sig;
+            if (std::sscanf(line, "%d %d %d %d %d %d %x", &P, &form, &a, &b, &c, &t, &sig) != 7) continue;
+            if (P < 2 || P > 4 || (form != 0 && form != 1 && form != 3 && form != 5)) continue;
+            if (t < 0 || t >= mpgemm_num_configs(P, form) || sig != config_signature(P, form)) continue;
+            g_tune[std::make_tuple(P, form, a, b, c)] = t;
+        }
+    }
+    std::fclose(f);
+    return rc;
+}
+
+// Path of the table shipped beside the shared library.
+std::string default_table_path() {
+    Dl_info info;
+    if (!dladdr((void*)&mpgemm_version, &info) || !info.dli_fname) return std::string();
+    std::string so(info.dli_fname);
+    const size_t slash = so.rfind('/');
+    return (slash == std::string::npos ? std::string(".") : so.substr(0, slash)) + "/tuned_gfx950.txt";
+}
+
+// First use of the table (lock held): load MPGEMM_AUTOTUNE_CACHE, else the
+// table beside the library, unless MPGEMM_NO_TUNED_TABLE is set; a missing
+// or mismatched file leaves the built-in choices.
+void ensure_table_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    if (std::getenv("MPGEMM_NO_TUNED_TABLE")) return;
+    const char* env = std::getenv("MPGEMM_AUTOTUNE_CACHE");
+    const std::string path = env && *env ? std::string(env) : default_table_path();
+    if (!path.empty()) (void)load_table_locked(path.c_str());
+}
 
 int ilog2(int64_t x) {
     int r = 0;
@@ -143,6 +207,7 @@ int ilog2(int64_t x) {
 
 int tuned_tile(int P, int form, int64_t m, int64_t n, int64_t k) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    ensure_table_locked();
     auto it = g_tune.find(std::make_tuple(P, form, ilog2(m), ilog2(n), ilog2(k)));
     return it == g_tune.end() ? -1 : it->second;
 }
@@ -235,6 +300,11 @@ int gemm_common(int P, char ta, char tb, int64_t m, int64_t n, int64_t k, const 
     const int s = (has_opts && opts->slices > 0) ? opts->slices : kDefaultSlices[P];
     const int req_tile = has_opts ? opts->tile : -1;
     if (last_stage > 0) form = MPGEMM_FORM_SPLIT_I8;
+    // the split forms' error grows with the spread of magnitudes within a
+    // row of op(A) or a column of op(B), which the call cannot see without
+    // reading the operands; the library takes them only when the caller has
+    // chosen the digit count (for example with mpgemm_tune_slices)
+    if (form == MPGEMM_FORM_AUTO && opts->slices == 0) form = MPGEMM_FORM_PLAIN;
     // the residue form's smallest sizes, measured: from 128 (DD), 96 (TD) and
     // 64 (QD) in every dimension it beats the plain and the triangular forms
     const int64_t crt_min = P == 2 ? 128 : (P == 3 ? 96 : 64);
@@ -598,6 +668,93 @@ int mpgemm_batch_plan_destroy(mpgemm_batch_plan* plan) {
     return 0;
 }
 
+// ---- grouped calls: plans cached by problem array ----------------------------
+
+}  // extern "C"
+
+namespace {
+
+struct GroupedPlan {
+    int P, tile;
+    std::vector<mpgemm_problem> probs;
+    mpgemm_batch_plan* plan;
+};
+std::mutex g_group_mu;
+std::list<GroupedPlan> g_groups;          // most recently used first
+constexpr size_t kMaxGroupedPlans = 8;
+
+bool same_double(double a, double b) { return std::memcmp(&a, &b, sizeof a) == 0; }
+
+// Field by field (the struct's padding bytes are not compared).
+bool same_problem(int P, const mpgemm_problem& a, const mpgemm_problem& b) {
+    if (a.transa != b.transa || a.transb != b.transb || a.m != b.m || a.n != b.n || a.k != b.k) return false;
+    for (int p = 0; p < P; ++p)
+        if (!same_double(a.alpha[p], b.alpha[p]) || !same_double(a.beta[p], b.beta[p])) return false;
+    return a.A == b.A && a.lda == b.lda && a.a_plane_stride == b.a_plane_stride && a.B == b.B &&
+           a.ldb == b.ldb && a.b_plane_stride == b.b_plane_stride && a.C == b.C && a.ldc == b.ldc &&
+           a.c_plane_stride == b.c_plane_stride;
+}
+
+int grouped_common(int P, int64_t count, const mpgemm_problem* probs, const mpgemm_opts* opts,
+                    hipStream_t st) {
+    if (count < 0) return -1;
+    if (count > 0 && !probs) return -2;
+    if (opts && (!opts_ok(opts) || (opts->form != MPGEMM_FORM_PLAIN && opts->form != MPGEMM_FORM_AUTO) ||
+                 opts->variant != 0))
+        return -3;
+    if (count == 0) return 0;
+    const int tile = (opts && opts->tile >= 0 && opts->tile < kPlainConfigs) ? opts->tile : -1;
+    std::lock_guard<std::mutex> lk(g_group_mu);
+    for (auto it = g_groups.begin(); it != g_groups.end(); ++it) {
+        if (it->P != P || it->tile != tile || (int64_t)it->probs.size() != count) continue;
+        bool same = true;
+        for (int64_t q = 0; q < count && same; ++q) same = same_problem(P, it->probs[(size_t)q], probs[q]);
+        if (!same) continue;
+        g_groups.splice(g_groups.begin(), g_groups, it);
+        return mpgemm_batch_plan_run(g_groups.front().plan, st);
+    }
+    mpgemm_opts o{};
+    o.tile = tile;
+    mpgemm_batch_plan* plan = nullptr;
+    const int rc = mpgemm_batch_plan_create(P, count, probs, &o, st, &plan);
+    if (rc) return rc;
+    if (g_groups.size() >= kMaxGroupedPlans) {
+        // the least recently used plan may still run on some stream
+        if (hipDeviceSynchronize() != hipSuccess) {
+            (void)mpgemm_batch_plan_destroy(plan);
+            return MPGEMM_ERR_HIP;
+        }
+        (void)mpgemm_batch_plan_destroy(g_groups.back().plan);
+        g_groups.pop_back();
+    }
+    g_groups.push_front(GroupedPlan{P, tile, std::vector<mpgemm_problem>(probs, probs + count), plan});
+    return mpgemm_batch_plan_run(plan, st);
+}
+
+void release_grouped_plans() {
+    std::lock_guard<std::mutex> lk(g_group_mu);
+    if (!g_groups.empty()) (void)hipDeviceSynchronize();
+    for (auto& g : g_groups) (void)mpgemm_batch_plan_destroy(g.plan);
+    g_groups.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+int mpgemm_dd_grouped(int64_t count, const mpgemm_problem* problems, const mpgemm_opts* opts,
+                      hipStream_t stream) {
+    return grouped_common(2, count, problems, opts, stream);
+}
+int mpgemm_td_grouped(int64_t count, const mpgemm_problem* problems, const mpgemm_opts* opts,
+                      hipStream_t stream) {
+    return grouped_common(3, count, problems, opts, stream);
+}
+int mpgemm_qd_grouped(int64_t count, const mpgemm_problem* problems, const mpgemm_opts* opts,
+                      hipStream_t stream) {
+    return grouped_common(4, count, problems, opts, stream);
+}
+
 // ---- autotuner --------------------------------------------------------------
 
 int mpgemm_num_configs(int prec, int form) {
@@ -689,6 +846,7 @@ int mpgemm_autotune(int prec, int form, int64_t m, int64_t n, int64_t k, int sli
     if (rc) return rc;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
+        ensure_table_locked();
         g_tune[std::make_tuple(P, form, ilog2(m), ilog2(n), ilog2(k))] = chosen;
     }
     if (best) *best = chosen;
@@ -705,6 +863,7 @@ int mpgemm_autotune_set(int prec, int form, int64_t m, int64_t n, int64_t k, int
     if (k <= 0) return -5;
     if (tile < 0 || tile >= mpgemm_num_configs(prec, form)) return -6;
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    ensure_table_locked();
     g_tune[std::make_tuple(prec, form, ilog2(m), ilog2(n), ilog2(k))] = tile;
     return 0;
 }
@@ -749,6 +908,7 @@ int mpgemm_batch_autotune(int prec, int64_t count, const mpgemm_problem* probs, 
     if (rc) return rc;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
+        ensure_table_locked();
         g_tune[std::make_tuple(prec, 3, ilog2(mm), ilog2(nn), ilog2(kk))] = chosen;
     }
     if (best) *best = chosen;
@@ -760,29 +920,22 @@ int mpgemm_autotune_save(const char* path) {
     FILE* f = std::fopen(path, "w");
     if (!f) return MPGEMM_ERR_HIP;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    std::fprintf(f, "# mpgemm tuning table v1 gfx950: prec form log2m log2n log2k tile\n");
-    for (const auto& kv : g_tune)
-        std::fprintf(f, "%d %d %d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first),
-                     std::get<2>(kv.first), std::get<3>(kv.first), std::get<4>(kv.first), kv.second);
+    ensure_table_locked();
+    std::fprintf(f, "%s: prec form log2m log2n log2k tile config-list-signature\n", kTableHeader);
+    for (const auto& kv : g_tune) {
+        const int P = std::get<0>(kv.first), form = std::get<1>(kv.first);
+        std::fprintf(f, "%d %d %d %d %d %d %08x\n", P, form, std::get<2>(kv.first), std::get<3>(kv.first),
+                     std::get<4>(kv.first), kv.second, config_signature(P, form));
+    }
     std::fclose(f);
     return 0;
 }
 
 int mpgemm_autotune_load(const char* path) {
     if (!path) return -1;
-    FILE* f = std::fopen(path, "r");
-    if (!f) return MPGEMM_ERR_HIP;
-    char line[256];
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    while (std::fgets(line, sizeof line, f)) {
-        if (line[0] == '#') continue;
-        int P, form, a, b, c, t;
-        if (std::sscanf(line, "%d %d %d %d %d %d", &P, &form, &a, &b, &c, &t) == 6 && P >= 2 && P <= 4 &&
-            t >= 0 && t < 16)
-            g_tune[std::make_tuple(P, form, a, b, c)] = t;
-    }
-    std::fclose(f);
-    return 0;
+    ensure_table_locked();
+    return load_table_locked(path);
 }
 
 // ---- slice-count rule -------------------------------------------------------
@@ -899,8 +1052,10 @@ const char* mpgemm_strerror(int code) {
 const char* mpgemm_version(void) { return "mpgemm 0.1.0 gfx950"; }
 
 void mpgemm_finalize(void) {
+    release_grouped_plans();
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune.clear();
+    g_tune_loaded = false;          // a later use looks for the table again
 }
 
 int mpgemm_probe_peak(int which, hipStream_t st, double* rate) {

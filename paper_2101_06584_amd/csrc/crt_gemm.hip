@@ -1192,6 +1192,13 @@ int launch_crt_recombine_p(int K, dim3 grid, hipStream_t st, const GemmArgs& g, 
 
 }  // namespace
 
+uint32_t crt_config_signature() {
+    uint32_t h = 2166136261u;
+    for (const CrtConfig& c : kCrt)
+        for (int v : {c.bm, c.bn, c.per_cu}) h = fnv1a(h, v);
+    return h;
+}
+
 int crt_default_config(int64_t m, int64_t n) {
     // rounds of resident workgroups times one workgroup's time (its tile
     // over its share of the planes, 32 taken as typical), with the measured

@@ -102,6 +102,15 @@ int crt_products(int P, int64_t k, int s);     // INT8 products of a call, 0 if 
 size_t crt_workspace_bytes(int P, int64_t m, int64_t n, int64_t k, int s, int cfg);
 int launch_crt(int P, int s, int cfg, const GemmArgs& g, void* ws, hipStream_t st);
 
+// Signatures of the kernel configuration lists a tuning-table entry refers
+// to (FNV-1a over each configuration's parameters): plain tiles of precision
+// P (also used by the batched form), the split form's tiles, the residue
+// form's tiles.
+uint32_t fnv1a(uint32_t h, int v);
+uint32_t plain_config_signature(int P);
+uint32_t split_config_signature();
+uint32_t crt_config_signature();
+
 // The _ex entry points' dispatch for precision P (argument errors numbered as
 // for mpgemm_dd_ex, 1..18).
 int gemm_ex_entry(int P, char ta, char tb, int64_t m, int64_t n, int64_t k, const double* alpha,

@@ -330,6 +330,23 @@ PlainConfig plain_config(int P, int id) {
     return PlainConfig{0, 0, 0, 0, 0};
 }
 
+uint32_t fnv1a(uint32_t h, int v) {
+    for (int b = 0; b < 4; ++b) {
+        h ^= (uint32_t)(v >> (8 * b)) & 255u;
+        h *= 16777619u;
+    }
+    return h;
+}
+
+uint32_t plain_config_signature(int P) {
+    uint32_t h = 2166136261u;
+    for (int id = 0; id < kPlainConfigs; ++id) {
+        const PlainConfig c = plain_config(P, id);
+        for (int v : {c.tx, c.ty, c.tm, c.tn, c.bk}) h = fnv1a(h, v);
+    }
+    return h;
+}
+
 int plain_default_config(int P, int64_t m, int64_t n, int64_t k) {
     (void)k;
     // small problems: smaller tiles so the grid still covers the 256 CUs

@@ -44,6 +44,13 @@ static const SplitConfig kSplit[kSplitConfigs] = {{128, 128, 2}, {64, 64, 8}, {1
 
 SplitConfig split_config(int id) { return kSplit[id]; }
 
+uint32_t split_config_signature() {
+    uint32_t h = 2166136261u;
+    for (const SplitConfig& c : kSplit)
+        for (int v : {c.bm, c.bn, c.g}) h = fnv1a(h, v);
+    return h;
+}
+
 int split_layout(int P, int64_t m, int64_t n, int64_t k, int s, int cfg, size_t* offE, size_t* offF,
                  size_t* offDA, size_t* offDB, size_t* offS, int64_t* Mp_, int64_t* Np_,
                  int64_t* Kp_) {

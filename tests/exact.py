@@ -101,7 +101,13 @@ class GemmChecker:
         return self._cols[j]
 
     def entry(self, i, j):
-        """(exact value, bound base) for entry (i, j)."""
+        """(exact value, bound base) for entry (i, j); computed once per entry."""
+        memo = self.__dict__.setdefault("_entries", {})
+        if (i, j) not in memo:
+            memo[(i, j)] = self._entry(i, j)
+        return memo[(i, j)]
+
+    def _entry(self, i, j):
         if self.k > 0:
             ai, za = self._row(i)
             bj, zb = self._col(j)

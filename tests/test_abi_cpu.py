@@ -220,3 +220,88 @@ def test_blas_rejects_invalid_arguments_on_the_host():
     # y overlapping A
     assert L.mp_gemv_dd(b"N", 4, 4, d2, fake, 4, 16, C.c_void_p(9 * 4096), 4, d2,
                         C.c_void_p(4096 + 8), 4, None) == _lib.ERR_ALIAS
+
+
+def test_grouped_validation():
+    """The grouped calls check their arguments (and every problem) on the
+    host before any GPU work."""
+    L = mp.load()
+    assert L.mpgemm_dd_grouped(-1, None, None, None) == -1
+    assert L.mpgemm_td_grouped(2, None, None, None) == -2
+    assert L.mpgemm_qd_grouped(0, None, None, None) == 0          # nothing to do
+    arr = (_lib.Problem * 2)()
+    for x in arr:
+        x.transa = b"N"; x.transb = b"N"; x.m = 4; x.n = 4; x.k = 4
+        x.alpha[0] = 1.0
+        x.A, x.lda, x.a_plane_stride = FAKE_A, 4, 16
+        x.B, x.ldb, x.b_plane_stride = FAKE_B, 4, 16
+        x.C, x.ldc, x.c_plane_stride = FAKE_C, 4, 16
+    split = _lib.Opts()
+    split.form = _lib.FORM_SPLIT_I8
+    assert L.mpgemm_dd_grouped(2, arr, C.byref(split), None) == -3     # plain only
+    variant = _lib.Opts()
+    variant.variant = 1
+    assert L.mpgemm_td_grouped(2, arr, C.byref(variant), None) == -3
+    arr[1].ldb = 1
+    assert L.mpgemm_dd_grouped(2, arr, None, None) == -1001
+
+
+CHILD = r'''
+import ctypes as C, sys
+L = C.CDLL(sys.argv[1])
+L.mpgemm_workspace_bytes.restype = C.c_size_t
+L.mpgemm_workspace_bytes.argtypes = [C.c_int, C.c_int, C.c_int64, C.c_int64, C.c_int64, C.c_int, C.c_int]
+n = 300
+print(L.mpgemm_workspace_bytes(2, 1, n, n, n, 16, -1), L.mpgemm_workspace_bytes(2, 1, n, n, n, 16, 0),
+      L.mpgemm_workspace_bytes(2, 1, n, n, n, 16, 1))
+'''
+
+
+def _child(env_extra):
+    """Workspace bytes of the DD split form at n = 300 (tuned tile, tile 0,
+    tile 1) as a C-only caller sees them: ctypes on the shared library in a
+    fresh process, no Python binding, no torch."""
+    import subprocess
+    import sys
+    env = {k: v for k, v in os.environ.items() if not k.startswith("MPGEMM_")}
+    env.update(env_extra)
+    out = subprocess.run([sys.executable, "-c", CHILD, _lib.LIB_PATH], env=env, capture_output=True,
+                         text=True, check=True).stdout.split()
+    return [int(v) for v in out]
+
+
+def test_c_callers_get_the_tuned_tiles(tmp_path):
+    """The library loads the tuning table by itself: an entry for the DD
+    split form at 256^3 (the log2 bucket of n = 300) selects that tile for a
+    C-only caller; entries with another configuration signature or a file
+    of another format are ignored; MPGEMM_NO_TUNED_TABLE turns it off."""
+    L = mp.load()
+    sig = None
+    with open(_lib.TUNED_TABLE) as f:
+        header = f.readline()
+        for line in f:
+            v = line.split()
+            if v[1] == "1":
+                sig = v[6]
+    assert header.startswith("# mpgemm tuning table v2 arch=gfx950")
+    assert sig is not None
+    _, t0, t1 = _child({"MPGEMM_NO_TUNED_TABLE": "1"})
+    assert t0 != t1
+    for tile, want in ((0, t0), (1, t1)):
+        p = tmp_path / f"table{tile}.txt"
+        p.write_text(header + f"2 1 8 8 8 {tile} {sig}\n")
+        assert _child({"MPGEMM_AUTOTUNE_CACHE": str(p)})[0] == want
+    default = _child({"MPGEMM_NO_TUNED_TABLE": "1"})[0]
+    bad_sig = tmp_path / "bad_sig.txt"
+    bad_sig.write_text(header + "2 1 8 8 8 0 00000000\n2 1 8 8 8 1 00000000\n")
+    assert _child({"MPGEMM_AUTOTUNE_CACHE": str(bad_sig)})[0] == default
+    old = tmp_path / "old.txt"
+    old.write_text("# mpgemm tuning table v1 gfx950: prec form log2m log2n log2k tile\n2 1 8 8 8 0\n")
+    assert _child({"MPGEMM_AUTOTUNE_CACHE": str(old)})[0] == default
+    assert L.mpgemm_autotune_load(str(old).encode()) == _lib.ERR_UNSUPPORTED
+    # save writes the header and a signature per entry
+    out = tmp_path / "saved.txt"
+    assert L.mpgemm_autotune_save(str(out).encode()) == 0
+    lines = out.read_text().splitlines()
+    assert lines[0].startswith("# mpgemm tuning table v2 arch=gfx950")
+    assert all(len(l.split()) == 7 for l in lines[1:])

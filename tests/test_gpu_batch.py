@@ -150,3 +150,65 @@ def test_batch_empty_and_degenerate(gpu_lib):
     empty = gpu_lib.BatchPlan(P, [])
     empty.run()
     empty.close()
+
+
+def test_runs_back_to_back_on_one_stream(gpu_lib):
+    """A plan's runs share its tile counter, so they must be stream-ordered:
+    replay, direct launch and replay queued back to back on one stream with
+    no synchronisation between them.  With beta != 0 each run adds onto the
+    last one's C, so a tile skipped or repeated by one run shows in the end
+    result: three runs equal three plain products in a row."""
+    P = 2
+    probs = problems(P, 40, 16, 200, fam=6)
+    for p in probs:
+        p["beta"] = synth.mp_uniform(np.random.Generator(np.random.PCG64(p["m"] * 1000 + p["k"])), P, (1,))[:, 0]
+    dprobs = to_dev(probs)
+    plan = gpu_lib.BatchPlan(P, dprobs)
+    note("batch back to back", P, plan.info())
+    stream = torch.cuda.current_stream()
+    plan.run(stream)
+    plan.launch(stream)
+    plan.run(stream)
+    torch.cuda.synchronize()
+    for q, (p, d) in enumerate(zip(probs, dprobs)):
+        want = p["C"]
+        for _ in range(3):
+            want = oracle.gemm(P, p["transa"], p["transb"], p["m"], p["n"], p["k"], p["alpha"], p["A"], p["B"],
+                               p["beta"], want)
+        assert np.array_equal(host(d["C"]), want), (q, p["m"], p["n"], p["k"])
+
+
+@pytest.mark.parametrize("P", [2, 3, 4])
+def test_grouped_calls(gpu_lib, P):
+    """mpgemm_{dd,td,qd}_grouped: every problem bit for bit as the oracle;
+    a second call with the same problem array replays the cached plan (beta
+    != 0, so each call adds onto the last: a stale or skipped tile shows);
+    another array (one alpha changed) gets a plan of its own."""
+    probs = problems(P, 24, 16, 140, fam=7)
+    for q, p in enumerate(probs):
+        if q % 2 == 0:
+            p["beta"] = synth.mp_uniform(np.random.Generator(np.random.PCG64(77 + q)), P, (1,))[:, 0]
+    dprobs = to_dev(probs)
+    arr = gpu_lib.problem_array(P, dprobs)
+    note("grouped", P, len(probs))
+    gpu_lib.grouped(P, dprobs, arr=arr)
+    gpu_lib.grouped(P, dprobs, arr=arr)            # cached plan
+    torch.cuda.synchronize()
+    want = []
+    for p in probs:
+        w = p["C"]
+        for _ in range(2):
+            w = oracle.gemm(P, p["transa"], p["transb"], p["m"], p["n"], p["k"], p["alpha"], p["A"], p["B"],
+                            p["beta"], w)
+        want.append(w)
+    for q, d in enumerate(dprobs):
+        assert np.array_equal(host(d["C"]), want[q]), (P, q)
+    # a changed alpha is another problem array: a new plan, not the cached one
+    dprobs[3]["alpha"] = 2.0 * np.asarray(dprobs[3]["alpha"])
+    dprobs[3]["beta"] = np.zeros(P)
+    gpu_lib.grouped(P, dprobs)
+    torch.cuda.synchronize()
+    p = probs[3]
+    w3 = oracle.gemm(P, p["transa"], p["transb"], p["m"], p["n"], p["k"], dprobs[3]["alpha"], p["A"], p["B"],
+                     np.zeros(P), want[3])
+    assert np.array_equal(host(dprobs[3]["C"]), w3)

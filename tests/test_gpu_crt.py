@@ -211,3 +211,29 @@ def test_degenerate_shapes_and_scalars(gpu_lib, P):
         note("crt empty", P, mm, nn)
         got = run(gpu_lib, P, "N", "N", mm, nn, k, alpha, A, B, beta, C, s)
         assert np.array_equal(got, C)
+
+
+@pytest.mark.parametrize("P", [2, 3, 4])
+def test_auto_form_without_digit_count_is_plain_on_spread_inputs(gpu_lib, P):
+    """FORM_AUTO with slices = 0 runs the plain form, also with a workspace
+    that would hold the residue form: on entries u 2^e with e in -60..60 per
+    entry the default digit count leaves the componentwise bound, so the
+    library does not choose a split form on its own.  Bit for bit as the
+    oracle's canonical product, and within 8 (k+2) u on sampled entries."""
+    m, n, k = 200, 190, 180
+    A, B, C, alpha, beta = make(P, "N", "N", m, n, k, fam=11, exp_range=(-60, 60))
+    s = gpu_lib.DEFAULT_SLICES[P]
+    ws = gpu_lib.alloc_workspace(P, m, n, k, s, form="auto")
+    dC = dev(C)
+    note("auto without slices on spread inputs", P, (m, n, k))
+    gpu_lib.gemm(P, "N", "N", m, n, k, alpha, dev(A), dev(B), beta, dC, form="auto", workspace=ws)
+    got = host(dC)
+    assert np.array_equal(got, oracle.gemm(P, "N", "N", m, n, k, alpha, A, B, beta, C))
+    chk = GemmChecker(P, "N", "N", m, n, k, alpha, A, B, beta, C)
+    r = chk.ratios(got, sample_entries(synth.rng_for(11, 9), m, n, 64))
+    assert r.max() <= 8 * (k + 2) / k
+    # with the default digit count given explicitly it is the residue form,
+    # bit for bit (its accuracy on such inputs is the caller's choice)
+    dC = dev(C)
+    gpu_lib.gemm(P, "N", "N", m, n, k, alpha, dev(A), dev(B), beta, dC, form="auto", slices=s, workspace=ws)
+    assert np.array_equal(host(dC), oracle.gemm_crt(P, s, "N", "N", m, n, k, alpha, A, B, beta, C))

@@ -514,9 +514,8 @@ __global__ __launch_bounds__(64 * WGM * WGN, 2) void crt_mfma_kernel(const int8_
                 }
                 acc[i][jj] = v16i{0};
             }
-        // the stores share the vector-memory counter with the copies: drain
-        // it so the counts in the waits stay exact
-        wait_vm_all();
+        // no drain: the waits stay sufficient with stores outstanding (see
+        // the wide kernel)
         kt = 0;
         ++mod;
     }
@@ -651,15 +650,30 @@ __global__ __launch_bounds__(256, 1) void crt_mfma_wide_kernel(const int8_t* __r
         __builtin_amdgcn_sched_barrier(0);
         wait_vm_barrier<W::PER_STEP * (D - 2)>();
         issue();                                   // step u + D into step u's slot
-        load_frags(std::integral_constant<int, nxt>{}, (u + 1) % D);
+        if constexpr (KH == 1) {
+            // the next step's eight fragment reads, one after each of the
+            // first eight MFMAs: issued in a burst they stall the wave
+            // (measured 2-3 % on the whole product at n = 4096)
+            const int8_t* st = lds + ((u + 1) % D) * W::STAGE;
+            static_for<W::FM * W::FN>([&](auto qc) {
+                constexpr int q = decltype(qc)::value, i = q / W::FN, jj = q % W::FN;
+                acc[i][jj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fra[cur][0][i], frb[cur][0][jj], acc[i][jj],
+                                                                   0, 0, 0);
+                if constexpr (q < W::FM) fra[nxt][0][q] = *(const v4i*)(st + aofs[q]);
+                else if constexpr (q < W::FM + W::FN) frb[nxt][0][q - W::FM] = *(const v4i*)(st + bofs[q - W::FM]);
+                __builtin_amdgcn_sched_barrier(0);
+            });
+        } else {
+            load_frags(std::integral_constant<int, nxt>{}, (u + 1) % D);
 #pragma unroll
-        for (int kh = 0; kh < KH; ++kh)
+            for (int kh = 0; kh < KH; ++kh)
 #pragma unroll
-            for (int i = 0; i < W::FM; ++i)
+                for (int i = 0; i < W::FM; ++i)
 #pragma unroll
-                for (int jj = 0; jj < W::FN; ++jj)
-                    acc[i][jj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fra[cur][kh][i], frb[cur][kh][jj],
-                                                                       acc[i][jj], 0, 0, 0);
+                    for (int jj = 0; jj < W::FN; ++jj)
+                        acc[i][jj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fra[cur][kh][i], frb[cur][kh][jj],
+                                                                           acc[i][jj], 0, 0, 0);
+        }
     };
     const int64_t ybase = (n0 + wn * W::WN + (lane & 31)) * Mp + m0 + wm * W::WM + 4 * (lane >> 5);
     int u = 0;
@@ -685,9 +699,11 @@ __global__ __launch_bounds__(256, 1) void crt_mfma_wide_kernel(const int8_t* __r
                 acc[i][jj] = v16i{0};
                 __builtin_amdgcn_sched_barrier(0);      // one accumulator's temporaries at a time
             }
-        // the stores share the vector-memory counter with the copies: drain
-        // it so the counts in the waits stay exact
-        wait_vm_all();
+        // no drain here: the stores share the vector-memory counter with the
+        // copies, and "at most N outstanding" with stores among them still
+        // means the copies older than the N most recent operations have
+        // landed (copies complete in order among themselves), so the waits
+        // stay sufficient; they only wait longer while stores are pending
     }
     // the copies run ahead of the last step: let them land before the
     // workgroup's LDS is released

@@ -359,10 +359,16 @@ int mp_gemv_qd(char trans, int64_t m, int64_t n, const double* alpha, const doub
                int64_t sy, hipStream_t stream);
 
 /*
- * Batched GEMMs of uneven shapes in one persistent launch (plain form, same
- * per-entry results as one mpgemm_*() call per problem).  A problem is the
- * argument list of mpgemm_dd() as a struct; alpha/beta use the first P
- * entries.  Problems must not write overlapping C regions.
+ * Batched GEMMs of uneven shapes (Sec. 4's batched use of the kernels).
+ * Plain form: one persistent launch, the same per-entry results as one
+ * mpgemm_*() call per problem.  Residue form (opts->form
+ * MPGEMM_FORM_SPLIT_CRT, or _AUTO with opts->slices > 0 for the problems the
+ * single call's AUTO rule would give it by size): each of its four stages
+ * (scale exponents, residues, one INT8 product per modulus, exact
+ * reconstruction) is one launch over all residue problems, with every
+ * problem's result bitwise that of a single residue-form call with the same
+ * s.  A problem is the argument list of mpgemm_dd() as a struct; alpha/beta
+ * use the first P entries.  Problems must not write overlapping C regions.
  */
 typedef struct mpgemm_problem {
     char transa, transb;
@@ -383,10 +389,22 @@ typedef struct mpgemm_batch_plan mpgemm_batch_plan;  /* opaque */
  * Build a plan: validates every problem (error -(1000 + index) for an
  * invalid problem; its first bad field is not reported separately), orders
  * tiles largest-k first, copies the descriptors to device memory owned by
- * the plan, and captures the counter reset plus the persistent launch in a
- * hipGraph.  Arguments: 1 prec (2, 3, 4), 2 count >= 0, 3 problems (host
- * array of count), 4 opts (may be NULL; opts->tile selects the tile shape),
- * 5 stream used for the upload, 6 out (receives the plan).
+ * the plan, and captures every launch of a run in a hipGraph.  Arguments:
+ * 1 prec (2, 3, 4), 2 count >= 0, 3 problems (host array of count), 4 opts
+ * (may be NULL = plain; -4 if its fields are out of range; opts->tile selects
+ * the plain part's tile shape; form MPGEMM_FORM_PLAIN, _AUTO or _SPLIT_CRT,
+ * else MPGEMM_ERR_UNSUPPORTED, as for variant != 0), 5 stream used for the
+ * uploads, 6 out (receives the plan).
+ * Residue form: opts->slices = s digits (0 = the precision's default for
+ * _SPLIT_CRT); every problem with m, n, k > 0 and alpha != 0 takes it, and
+ * the plan returns MPGEMM_ERR_UNSUPPORTED when one has no one-level residue
+ * product (s > 24 or k beyond its range); the rest (a zero alpha or
+ * dimension) run in the plain part.  Every residue problem uses the moduli
+ * that the largest k among them needs (the reconstruction is exact, so
+ * extra moduli change no bit).  The plan owns the residue workspace
+ * (problems padded to 128 x 128 product tiles, grouped into chunks of at
+ * most 1 GiB that run one after another; mpgemm_batch_plan_residue_info
+ * reports it).
  * The plan binds the device addresses in `problems`; their contents may
  * change between runs.
  */
@@ -402,8 +420,13 @@ int mpgemm_batch_plan_create(int prec, int64_t count, const mpgemm_problem* prob
 int mpgemm_batch_plan_run(mpgemm_batch_plan* plan, hipStream_t stream);
 /* Same work as a direct launch (no graph) on `stream`; ordered like runs. */
 int mpgemm_batch_plan_launch(mpgemm_batch_plan* plan, hipStream_t stream);
-/* Total tiles and the grid the plan launches (for reporting). */
+/* Plain part: total tiles, the persistent grid and its tile shape (for
+ * reporting). */
 int mpgemm_batch_plan_info(const mpgemm_batch_plan* plan, int64_t* tiles, int* grid, int* tile_cfg);
+/* Residue part: problems, moduli per problem, chunks and the workspace bytes
+ * the plan holds for them (any pointer may be NULL). */
+int mpgemm_batch_plan_residue_info(const mpgemm_batch_plan* plan, int64_t* problems, int* moduli, int* chunks,
+                                   size_t* workspace_bytes);
 /* Free the plan's device memory and graph (after its last run completed). */
 int mpgemm_batch_plan_destroy(mpgemm_batch_plan* plan);
 
@@ -419,8 +442,10 @@ int mpgemm_batch_plan_destroy(mpgemm_batch_plan* plan);
  * equal arrays reuse one plan, so they follow the plan rule: queue them on
  * one stream or order the streams.  Arguments: 1 count >= 0, 2 problems
  * (host array; -(1000 + index) for an invalid problem), 3 opts (may be NULL;
- * form must be MPGEMM_FORM_PLAIN or _AUTO, variant 0, opts->tile selects the
- * tile shape, -1 = tuned), 4 stream.
+ * form MPGEMM_FORM_PLAIN, _AUTO or _SPLIT_CRT with opts->slices as for
+ * mpgemm_batch_plan_create, variant 0, opts->tile selects the plain tile
+ * shape, -1 = tuned; form, slices and tile are part of the plan's key),
+ * 4 stream.
  */
 int mpgemm_dd_grouped(int64_t count, const mpgemm_problem* problems, const mpgemm_opts* opts,
                       hipStream_t stream);

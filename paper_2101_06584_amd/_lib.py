@@ -66,6 +66,7 @@ EXPORTS = {
     "mpgemm_batch_plan_run": ([_vp, _vp], _int),
     "mpgemm_batch_plan_launch": ([_vp, _vp], _int),
     "mpgemm_batch_plan_info": ([_vp, _P(_i64), _P(_int), _P(_int)], _int),
+    "mpgemm_batch_plan_residue_info": ([_vp, _P(_i64), _P(_int), _P(_int), _P(_sz)], _int),
     "mpgemm_batch_plan_destroy": ([_vp], _int),
     "mpgemm_dd_grouped": ([_i64, _P(Problem), _P(Opts), _vp], _int),
     "mpgemm_td_grouped": ([_i64, _P(Problem), _P(Opts), _vp], _int),

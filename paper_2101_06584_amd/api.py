@@ -216,16 +216,18 @@ def _problem_array(P, problems):
 
 
 class BatchPlan:
-    """Many GEMMs of one precision in one persistent launch, replayed from a
-    captured hipGraph (run) or launched directly (launch)."""
+    """Many GEMMs of one precision, replayed from a captured hipGraph (run)
+    or launched directly (launch): the plain part in one persistent launch,
+    the residue part (form "crt", or "auto" with slices > 0) in four
+    launches per chunk."""
 
-    def __init__(self, prec, problems, tile=-1, stream=None):
+    def __init__(self, prec, problems, tile=-1, stream=None, form="plain", slices=0):
         """problems: sequence of dicts with keys transa, transb, m, n, k, alpha,
         A, B, beta, C (tensors as for gemm())."""
         self.P = PREC[prec]
         L = _lib.load()
         arr, self._keep = _problem_array(self.P, problems)
-        opts = make_opts("plain", 0, tile, None)
+        opts = make_opts(form, slices, tile, None)
         h = C.c_void_p()
         rc = L.mpgemm_batch_plan_create(self.P, len(problems), arr, C.byref(opts), _stream(stream),
                                         C.byref(h))
@@ -240,8 +242,13 @@ class BatchPlan:
 
     def info(self):
         t, g, c = C.c_int64(), C.c_int(), C.c_int()
-        _check(_lib.load().mpgemm_batch_plan_info(self._h, C.byref(t), C.byref(g), C.byref(c)), "info")
-        return {"tiles": t.value, "grid": g.value, "tile_cfg": c.value}
+        L = _lib.load()
+        _check(L.mpgemm_batch_plan_info(self._h, C.byref(t), C.byref(g), C.byref(c)), "info")
+        rp, mo, ch, wb = C.c_int64(), C.c_int(), C.c_int(), C.c_size_t()
+        _check(L.mpgemm_batch_plan_residue_info(self._h, C.byref(rp), C.byref(mo), C.byref(ch), C.byref(wb)),
+               "residue info")
+        return {"tiles": t.value, "grid": g.value, "tile_cfg": c.value, "residue_problems": rp.value,
+                "moduli": mo.value, "chunks": ch.value, "residue_workspace": wb.value}
 
     def close(self):
         if getattr(self, "_h", None):
@@ -255,21 +262,21 @@ class BatchPlan:
             pass
 
 
-def grouped_raw(prec, problems, tile=-1, stream=None, arr=None) -> int:
+def grouped_raw(prec, problems, tile=-1, stream=None, arr=None, form="plain", slices=0) -> int:
     """Calls mpgemm_{dd,td,qd}_grouped on `problems` (dicts as for
     BatchPlan); `arr` may pass a prebuilt problem array (from
     problem_array) so that repeated calls present the same array."""
     P = PREC[prec]
     if arr is None:
         arr, _keep = _problem_array(P, problems)
-    opts = make_opts("plain", 0, tile, None)
+    opts = make_opts(form, slices, tile, None)
     return getattr(_lib.load(), f"mpgemm_{_NAME[P]}_grouped")(len(problems), arr, C.byref(opts), _stream(stream))
 
 
-def grouped(prec, problems, tile=-1, stream=None, arr=None) -> None:
-    """All problems in one persistent launch (plan cached by the library per
-    problem array); raises on error."""
-    _check(grouped_raw(prec, problems, tile, stream, arr), "mpgemm_grouped")
+def grouped(prec, problems, tile=-1, stream=None, arr=None, form="plain", slices=0) -> None:
+    """All problems as one batched plan (cached by the library per problem
+    array, form, slices and tile); raises on error."""
+    _check(grouped_raw(prec, problems, tile, stream, arr, form, slices), "mpgemm_grouped")
 
 
 def problem_array(prec, problems):

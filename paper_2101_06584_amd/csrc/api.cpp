@@ -549,17 +549,91 @@ MPG_GEMV(mp_gemv_qd, 4)
 
 // ---- batched plan -----------------------------------------------------------
 
+// Residue problems of a plan run in chunks whose workspace stays within this
+// size (a problem larger than it forms a chunk of its own); the chunks run
+// one after another on the plan's stream and share one workspace.
+constexpr size_t kBatchChunkBytes = (size_t)1 << 30;
+
+struct CrtChunk {
+    int64_t first, count;     // items first .. first + count - 1
+    CrtBatchInfo info;
+};
+
 struct mpgemm_batch_plan {
     int P;
     int cfg;
-    int64_t count;
+    int64_t count;            // problems of the plain part
     int64_t tiles;
     int grid;
     void* d_desc;
     unsigned* d_counter;
+    int crt_s;                // residue part: digits, problems, chunks
+    int64_t crt_count;
+    std::vector<CrtChunk> chunks;
+    CrtBatchItem* d_items;
+    void* d_ws;
+    size_t ws_bytes;
     hipGraph_t graph;
     hipGraphExec_t exec;
 };
+
+namespace {
+
+int plan_launch_all(const mpgemm_batch_plan* plan, hipStream_t st) {
+    if (plan->tiles > 0) {
+        const int rc = launch_batch(plan->P, plan->cfg, plan->count, plan->tiles, plan->d_desc, plan->d_counter,
+                                    plan->grid, st);
+        if (rc) return rc;
+    }
+    for (const CrtChunk& c : plan->chunks) {
+        const int rc = launch_crt_batch(plan->P, plan->crt_s, c.info, plan->d_items + c.first, c.count, st);
+        if (rc) return rc;
+    }
+    return 0;
+}
+
+bool plan_empty(const mpgemm_batch_plan* plan) { return plan->tiles == 0 && plan->chunks.empty(); }
+
+// The residue part: chunks laid out over one workspace, items copied to the
+// device (synchronously on st).  gs: the residue problems, largest first.
+int plan_residue_part(mpgemm_batch_plan* plan, int N, int s, const std::vector<GemmArgs>& gs, hipStream_t st) {
+    const int64_t cnt = (int64_t)gs.size();
+    plan->crt_s = s;
+    plan->crt_count = cnt;
+    // chunks: consecutive problems while their workspace fits the bound
+    std::vector<std::pair<int64_t, int64_t>> ranges;
+    size_t ws = 0, cur = 0;
+    int64_t first = 0;
+    for (int64_t q = 0; q < cnt; ++q) {
+        const size_t b = crt_batch_item_bytes(gs[(size_t)q].m, gs[(size_t)q].n, gs[(size_t)q].k, N);
+        if (q > first && cur + b > kBatchChunkBytes) {
+            ranges.emplace_back(first, q - first);
+            first = q;
+            cur = 0;
+        }
+        cur += b;
+        ws = std::max(ws, cur);
+    }
+    if (cnt > 0) ranges.emplace_back(first, cnt - first);
+    if (hipMalloc(&plan->d_ws, std::max<size_t>(ws, 256)) != hipSuccess) return MPGEMM_ERR_NOMEM;
+    plan->ws_bytes = ws;
+    const size_t ibytes = sizeof(CrtBatchItem) * (size_t)std::max<int64_t>(cnt, 1);
+    if (hipMalloc((void**)&plan->d_items, ibytes) != hipSuccess) return MPGEMM_ERR_NOMEM;
+    std::vector<CrtBatchItem> items((size_t)std::max<int64_t>(cnt, 1));
+    for (const auto& r : ranges) {
+        CrtChunk c{r.first, r.second, {}};
+        const int rc = crt_batch_plan(N, s, c.count, gs.data() + c.first, plan->d_ws, items.data() + c.first,
+                                      &c.info);
+        if (rc) return rc;
+        plan->chunks.push_back(c);
+    }
+    if (hipMemcpyAsync(plan->d_items, items.data(), ibytes, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return MPGEMM_ERR_HIP;
+    return 0;
+}
+
+}  // namespace
 
 int mpgemm_batch_plan_create(int prec, int64_t count, const mpgemm_problem* probs,
                              const mpgemm_opts* opts, hipStream_t st, mpgemm_batch_plan** out) {
@@ -568,6 +642,7 @@ int mpgemm_batch_plan_create(int prec, int64_t count, const mpgemm_problem* prob
     if (count > 0 && !probs) return -3;
     if (!out) return -6;
     *out = nullptr;
+    if (opts && !opts_ok(opts)) return -4;
     const int P = prec;
     std::vector<GemmArgs> gs((size_t)count);
     for (int64_t q = 0; q < count; ++q) {
@@ -578,56 +653,86 @@ int mpgemm_batch_plan_create(int prec, int64_t count, const mpgemm_problem* prob
         if (rc) return rc == MPGEMM_ERR_ALIAS ? rc : (int)(-(1000 + q));
     }
     if (opts && opts->variant != 0) return MPGEMM_ERR_UNSUPPORTED;   // TD variants: plain calls only
+    const int form = opts ? opts->form : MPGEMM_FORM_PLAIN;
+    if (form != MPGEMM_FORM_PLAIN && form != MPGEMM_FORM_AUTO && form != MPGEMM_FORM_SPLIT_CRT)
+        return MPGEMM_ERR_UNSUPPORTED;
+    // which problems take the residue form: all that multiply (SPLIT_CRT), or
+    // with s given those of at least the single call's residue sizes (AUTO)
+    const int s = (opts && opts->slices > 0) ? opts->slices : kDefaultSlices[P];
+    const int64_t crt_min = P == 2 ? 128 : (P == 3 ? 96 : 64);
+    std::vector<char> res((size_t)count, 0);
+    int64_t kmax = 0;
+    for (int64_t q = 0; q < count; ++q) {
+        const GemmArgs& g = gs[(size_t)q];
+        const bool mult = g.m > 0 && g.n > 0 && g.k > 0 && !mp_zero(P, g.alpha);
+        bool r = false;
+        if (form == MPGEMM_FORM_SPLIT_CRT && mult) {
+            if (crt_batch_moduli(g.k, s) == 0) return MPGEMM_ERR_UNSUPPORTED;
+            r = true;
+        } else if (form == MPGEMM_FORM_AUTO && mult && opts->slices > 0) {
+            r = g.m >= crt_min && g.n >= crt_min && g.k >= crt_min && crt_batch_moduli(g.k, s) > 0;
+        }
+        res[(size_t)q] = r;
+        if (r) kmax = std::max(kmax, g.k);
+    }
+    std::vector<GemmArgs> gp, gr;
+    for (int64_t q = 0; q < count; ++q) (res[(size_t)q] ? gr : gp).push_back(gs[(size_t)q]);
+    const int64_t np = (int64_t)gp.size();
+
     int cfg = (opts && opts->tile >= 0 && opts->tile < kPlainConfigs) ? opts->tile : -1;
     if (cfg < 0) {
-        // tile shape for the typical problem of the batch
+        // tile shape for the typical problem of the plain part
         int64_t mm = 0, nn = 0, kk = 0;
-        for (const auto& g : gs) { mm += g.m; nn += g.n; kk += g.k; }
-        if (count > 0) { mm /= count; nn /= count; kk /= count; }
+        for (const auto& g : gp) { mm += g.m; nn += g.n; kk += g.k; }
+        if (np > 0) { mm /= np; nn /= np; kk /= np; }
         cfg = tuned_tile(P, 3, mm, nn, kk);      // form id 3: batched
         // untuned: the tiles measured fastest on 512 problems with m, n, k
         // uniform in [16, 512] (DD 64 x 32, TD and QD 16 x 16)
         if (cfg < 0) cfg = P == 2 ? 2 : 3;
     }
     // largest k first so the queue ends with the cheapest tiles
-    std::vector<int64_t> order((size_t)count);
-    for (int64_t q = 0; q < count; ++q) order[(size_t)q] = q;
+    std::vector<int64_t> order((size_t)np);
+    for (int64_t q = 0; q < np; ++q) order[(size_t)q] = q;
     std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
-        return gs[(size_t)a].k > gs[(size_t)b].k;
+        return gp[(size_t)a].k > gp[(size_t)b].k;
+    });
+    // residue problems: the largest first, so that the last blocks of each
+    // stage are the small ones
+    std::stable_sort(gr.begin(), gr.end(), [](const GemmArgs& a, const GemmArgs& b) {
+        return (double)a.m * a.n * a.k > (double)b.m * b.n * b.k;
     });
     auto* plan = new (std::nothrow) mpgemm_batch_plan();
     if (!plan) return MPGEMM_ERR_NOMEM;
     plan->P = P;
     plan->cfg = cfg;
-    plan->count = count;
-    const size_t bytes = std::max<size_t>(batch_desc_bytes(count), 256);
+    plan->count = np;
+    const size_t bytes = std::max<size_t>(batch_desc_bytes(np), 256);
     std::vector<char> host(bytes);
-    plan->tiles = batch_build_desc(P, cfg, count, gs.data(), order.data(), host.data());
+    plan->tiles = batch_build_desc(P, cfg, np, gp.data(), order.data(), host.data());
     plan->grid = (int)std::max<int64_t>(1, std::min<int64_t>(batch_max_grid(P, cfg), plan->tiles));
-    if (hipMalloc(&plan->d_desc, bytes) != hipSuccess) { delete plan; return MPGEMM_ERR_NOMEM; }
-    if (hipMalloc((void**)&plan->d_counter, 256) != hipSuccess) {
-        (void)hipFree(plan->d_desc);
-        delete plan;
-        return MPGEMM_ERR_NOMEM;
-    }
     int err = 0;
-    if (hipMemcpyAsync(plan->d_desc, host.data(), bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
+    if (hipMalloc(&plan->d_desc, bytes) != hipSuccess || hipMalloc((void**)&plan->d_counter, 256) != hipSuccess)
+        err = MPGEMM_ERR_NOMEM;
+    if (!err && (hipMemcpyAsync(plan->d_desc, host.data(), bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
+                 hipStreamSynchronize(st) != hipSuccess))
         err = MPGEMM_ERR_HIP;
-    // capture counter reset + persistent launch on a private stream
+    if (!err && !gr.empty()) err = plan_residue_part(plan, crt_batch_moduli(kmax, s), s, gr, st);
+    // capture every launch of a run on a private stream
     hipStream_t cs = nullptr;
-    if (!err && hipStreamCreate(&cs) != hipSuccess) err = MPGEMM_ERR_GRAPH;
-    if (!err) {
-        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) err = MPGEMM_ERR_GRAPH;
+    if (!err && !plan_empty(plan)) {
+        if (hipStreamCreate(&cs) != hipSuccess) err = MPGEMM_ERR_GRAPH;
         else {
-            int lrc = launch_batch(P, cfg, count, plan->tiles, plan->d_desc, plan->d_counter, plan->grid, cs);
-            hipGraph_t gr = nullptr;
-            if (hipStreamEndCapture(cs, &gr) != hipSuccess || lrc) err = MPGEMM_ERR_GRAPH;
-            plan->graph = gr;
-            if (!err && hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0) != hipSuccess)
-                err = MPGEMM_ERR_GRAPH;
+            if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) err = MPGEMM_ERR_GRAPH;
+            else {
+                const int lrc = plan_launch_all(plan, cs);
+                hipGraph_t graph = nullptr;
+                if (hipStreamEndCapture(cs, &graph) != hipSuccess || lrc) err = MPGEMM_ERR_GRAPH;
+                plan->graph = graph;
+                if (!err && hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0) != hipSuccess)
+                    err = MPGEMM_ERR_GRAPH;
+            }
+            (void)hipStreamDestroy(cs);
         }
-        (void)hipStreamDestroy(cs);
     }
     if (err) {
         mpgemm_batch_plan_destroy(plan);
@@ -639,15 +744,13 @@ int mpgemm_batch_plan_create(int prec, int64_t count, const mpgemm_problem* prob
 
 int mpgemm_batch_plan_run(mpgemm_batch_plan* plan, hipStream_t st) {
     if (!plan) return -1;
-    if (plan->tiles == 0) return 0;
+    if (plan_empty(plan)) return 0;
     return hipGraphLaunch(plan->exec, st) == hipSuccess ? 0 : MPGEMM_ERR_HIP;
 }
 
 int mpgemm_batch_plan_launch(mpgemm_batch_plan* plan, hipStream_t st) {
     if (!plan) return -1;
-    if (plan->tiles == 0) return 0;
-    return hip_rc(launch_batch(plan->P, plan->cfg, plan->count, plan->tiles, plan->d_desc,
-                               plan->d_counter, plan->grid, st));
+    return hip_rc(plan_launch_all(plan, st));
 }
 
 int mpgemm_batch_plan_info(const mpgemm_batch_plan* plan, int64_t* tiles, int* grid, int* tile_cfg) {
@@ -658,12 +761,24 @@ int mpgemm_batch_plan_info(const mpgemm_batch_plan* plan, int64_t* tiles, int* g
     return 0;
 }
 
+int mpgemm_batch_plan_residue_info(const mpgemm_batch_plan* plan, int64_t* problems, int* moduli, int* chunks,
+                                   size_t* workspace_bytes) {
+    if (!plan) return -1;
+    if (problems) *problems = plan->crt_count;
+    if (moduli) *moduli = plan->chunks.empty() ? 0 : plan->chunks[0].info.N;
+    if (chunks) *chunks = (int)plan->chunks.size();
+    if (workspace_bytes) *workspace_bytes = plan->ws_bytes;
+    return 0;
+}
+
 int mpgemm_batch_plan_destroy(mpgemm_batch_plan* plan) {
     if (!plan) return -1;
     if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
     if (plan->graph) (void)hipGraphDestroy(plan->graph);
     if (plan->d_desc) (void)hipFree(plan->d_desc);
     if (plan->d_counter) (void)hipFree(plan->d_counter);
+    if (plan->d_items) (void)hipFree(plan->d_items);
+    if (plan->d_ws) (void)hipFree(plan->d_ws);
     delete plan;
     return 0;
 }
@@ -675,7 +790,7 @@ int mpgemm_batch_plan_destroy(mpgemm_batch_plan* plan) {
 namespace {
 
 struct GroupedPlan {
-    int P, tile;
+    int P, tile, form, slices;
     std::vector<mpgemm_problem> probs;
     mpgemm_batch_plan* plan;
 };
@@ -699,14 +814,19 @@ int grouped_common(int P, int64_t count, const mpgemm_problem* probs, const mpge
                     hipStream_t st) {
     if (count < 0) return -1;
     if (count > 0 && !probs) return -2;
-    if (opts && (!opts_ok(opts) || (opts->form != MPGEMM_FORM_PLAIN && opts->form != MPGEMM_FORM_AUTO) ||
+    if (opts && (!opts_ok(opts) ||
+                 (opts->form != MPGEMM_FORM_PLAIN && opts->form != MPGEMM_FORM_AUTO &&
+                  opts->form != MPGEMM_FORM_SPLIT_CRT) ||
                  opts->variant != 0))
         return -3;
     if (count == 0) return 0;
     const int tile = (opts && opts->tile >= 0 && opts->tile < kPlainConfigs) ? opts->tile : -1;
+    const int form = opts ? opts->form : MPGEMM_FORM_PLAIN, slices = opts ? opts->slices : 0;
     std::lock_guard<std::mutex> lk(g_group_mu);
     for (auto it = g_groups.begin(); it != g_groups.end(); ++it) {
-        if (it->P != P || it->tile != tile || (int64_t)it->probs.size() != count) continue;
+        if (it->P != P || it->tile != tile || it->form != form || it->slices != slices ||
+            (int64_t)it->probs.size() != count)
+            continue;
         bool same = true;
         for (int64_t q = 0; q < count && same; ++q) same = same_problem(P, it->probs[(size_t)q], probs[q]);
         if (!same) continue;
@@ -715,6 +835,8 @@ int grouped_common(int P, int64_t count, const mpgemm_problem* probs, const mpge
     }
     mpgemm_opts o{};
     o.tile = tile;
+    o.form = form;
+    o.slices = slices;
     mpgemm_batch_plan* plan = nullptr;
     const int rc = mpgemm_batch_plan_create(P, count, probs, &o, st, &plan);
     if (rc) return rc;
@@ -727,7 +849,7 @@ int grouped_common(int P, int64_t count, const mpgemm_problem* probs, const mpge
         (void)mpgemm_batch_plan_destroy(g_groups.back().plan);
         g_groups.pop_back();
     }
-    g_groups.push_front(GroupedPlan{P, tile, std::vector<mpgemm_problem>(probs, probs + count), plan});
+    g_groups.push_front(GroupedPlan{P, tile, form, slices, std::vector<mpgemm_problem>(probs, probs + count), plan});
     return mpgemm_batch_plan_run(plan, st);
 }
 

@@ -201,25 +201,54 @@ __device__ __forceinline__ int next_digit(double (&r)[P], int p) {
     return (int)d;
 }
 
-// Both operands in one launch: blockIdx.z = 0 takes op(A) with weights wa,
-// 1 op(B) with wb; blockIdx.y beyond an operand's padded rows has no work.
+// Weight fragments of one lane for the residue MFMAs: modulus 32 cg +
+// lane % 32, digits 16 (lane / 32) .. + 15 of table wt, split into the two
+// levels' sets when SETS = 3, and the lane's moduli for the reduction.  A
+// macro, so that the tables are read where the kernel's arguments live
+// (passed through a function they would be copied to private memory).
+#define MPG_CRT_WEIGHT_FRAGMENTS(wt, shi, lane, bw, mf, invm)                                   \
+    for (int cg = 0; cg < NG; ++cg) {                                                           \
+        const int tt = 32 * cg + ((lane) & 31);                                                 \
+        v4i row = v4i{0, 0, 0, 0};                                                              \
+        if (tt < kNumModuli) {                                                                  \
+            const uint32_t* wp = (const uint32_t*)(wt)->w[tt] + 4 * ((lane) >> 5);               \
+            row = v4i{(int)wp[0], (int)wp[1], (int)wp[2], (int)wp[3]};                          \
+        }                                                                                       \
+        if constexpr (SETS == 1) {                                                              \
+            bw[0][cg] = row;                                                                    \
+        } else {                                                                                \
+            v4i hi_mask;                                                                        \
+            _Pragma("unroll") for (int c = 0; c < 4; ++c) {                                     \
+                uint32_t mk = 0u;                                                               \
+                _Pragma("unroll") for (int j = 0; j < 4; ++j)                                   \
+                    mk |= (16 * ((lane) >> 5) + 4 * c + j < (shi)) ? (0xffu << (8 * j)) : 0u;   \
+                hi_mask[c] = (int)mk;                                                           \
+            }                                                                                   \
+            bw[0][cg] = row & hi_mask;                                                          \
+            bw[1][cg] = row & ~hi_mask;                                                         \
+            bw[2][cg] = row;                                                                    \
+        }                                                                                       \
+        const int m = tt < kNumModuli ? kCrtDev.mod[tt] : 1;                                    \
+        mf[cg] = (float)m;                                                                      \
+        invm[cg] = 1.0f / (float)m;                                                             \
+    }
+
+// One block of the residue pass: k segment `seg` (64 wide) of row block
+// `rowblk` (16 rows) of operand o, with this lane's weight fragments bw and
+// moduli mf, invm (MPG_CRT_WEIGHT_FRAGMENTS).
 template <int P, int NG, int SETS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void crt_residue_kernel(
-    ResOperand oa, ResOperand ob, CrtWeights wa, CrtWeights wb, int64_t k, int s, int N, int shi,
-    int64_t Kp) {
-    const bool second = blockIdx.z != 0;
-    const ResOperand o = second ? ob : oa;
-    const CrtWeights* __restrict__ wt = second ? &wb : &wa;
+__device__ __forceinline__ void crt_residue_block(const ResOperand& o, const v4i (&bw)[SETS][NG],
+                                                  const float (&mf)[NG], const float (&invm)[NG], int64_t k,
+                                                  int s, int N, int64_t Kp, int64_t seg, int64_t rowblk) {
     const double* __restrict__ X = o.X;
     const int64_t rs = o.rs, ls = o.ls, ps = o.ps, count = o.count, Rp = o.Rp;
     const int32_t* __restrict__ E = o.E;
     int8_t* __restrict__ R = o.R;
-    const int64_t r0 = (int64_t)blockIdx.y * kResRows;
+    const int64_t r0 = rowblk * kResRows;
     if (r0 >= Rp) return;                         // the whole block: before any barrier
     constexpr int kTileBytes = P * kResRows * (kTileK + 1) * 8;
     __shared__ __align__(16) uint8_t lds[kTileBytes > kStageBytes ? kTileBytes : kStageBytes];
     double (*tile)[kResRows][kTileK + 1] = reinterpret_cast<double (*)[kResRows][kTileK + 1]>(lds);
-    const int64_t seg = blockIdx.x;
     const int64_t l0 = seg * kTileK;
     const int t = threadIdx.x;
     const bool rows_contig = (rs == 1);
@@ -236,41 +265,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void c
     __syncthreads();
 
     const int lane = t & 63, wave = t >> 6;
-    // this lane's weight columns (modulus 32 cg + lane % 32, digits
-    // 16 (lane / 32) .. + 15) and its moduli for the reduction
-    // with two levels (SETS = 3) the row holds the high half's weights on
-    // digits 0..shi-1 and the low half's on the rest: set 0 keeps the first,
-    // set 1 the second, set 2 (their sum) the whole row
-    v4i bw[SETS][NG];
-    float mf[NG], invm[NG];
-#pragma unroll
-    for (int cg = 0; cg < NG; ++cg) {
-        const int tt = 32 * cg + (lane & 31);
-        v4i row = v4i{0, 0, 0, 0};
-        if (tt < kNumModuli) {
-            const uint32_t* wp = (const uint32_t*)wt->w[tt] + 4 * (lane >> 5);
-            row = v4i{(int)wp[0], (int)wp[1], (int)wp[2], (int)wp[3]};
-        }
-        if constexpr (SETS == 1) {
-            bw[0][cg] = row;
-        } else {
-            v4i hi_mask;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                uint32_t mk = 0u;
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    mk |= (16 * (lane >> 5) + 4 * c + j < shi) ? (0xffu << (8 * j)) : 0u;
-                hi_mask[c] = (int)mk;
-            }
-            bw[0][cg] = row & hi_mask;
-            bw[1][cg] = row & ~hi_mask;
-            bw[2][cg] = row;
-        }
-        const int m = tt < kNumModuli ? kCrtDev.mod[tt] : 1;
-        mf[cg] = (float)m;
-        invm[cg] = 1.0f / (float)m;
-    }
     const int64_t nkt = Kp / kCrtTileK;
     // the remainders of the wave's four rows, then the tile's space is free
     double rem[4][P];
@@ -359,6 +353,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void c
         }
 }
 
+// Both operands in one launch: blockIdx.z = 0 takes op(A) with weights wa,
+// 1 op(B) with wb; blockIdx.y beyond an operand's padded rows has no work.
+template <int P, int NG, int SETS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void crt_residue_kernel(
+    ResOperand oa, ResOperand ob, CrtWeights wa, CrtWeights wb, int64_t k, int s, int N, int shi,
+    int64_t Kp) {
+    const bool second = blockIdx.z != 0;
+    const ResOperand o = second ? ob : oa;
+    if ((int64_t)blockIdx.y * kResRows >= o.Rp) return;
+    const CrtWeights* __restrict__ wt = second ? &wb : &wa;
+    const int lane = threadIdx.x & 63;
+    v4i bw[SETS][NG];
+    float mf[NG], invm[NG];
+#pragma unroll
+    MPG_CRT_WEIGHT_FRAGMENTS(wt, shi, lane, bw, mf, invm)
+    crt_residue_block<P, NG, SETS>(o, bw, mf, invm, k, s, N, Kp, blockIdx.x, blockIdx.y);
+}
+
 // ---------------------------------------------------------------------------
 // Stage 3: one INT8 product per modulus on the matrix cores.
 //
@@ -400,26 +412,20 @@ struct CrtDma {
 // across them: the halves swap every 8 rows.
 __device__ __forceinline__ int swz32(int r, int c) { return r * kCrtTileK + ((c ^ ((r >> 3) & 1)) << 4); }
 
+// Output tile (tm, tn) over planes mod0 .. mod1 - 1.
 template <int BM, int BN, int WGM, int WGN, int D>
-__global__ __launch_bounds__(64 * WGM * WGN, 2) void crt_mfma_kernel(const int8_t* __restrict__ RA,
-                                                                     const int8_t* __restrict__ RB,
-                                                                     uint8_t* __restrict__ Y, int64_t Mp,
-                                                                     int64_t Np, int64_t Kp, int N,
-                                                                     int Nmod, int mods) {
+__device__ __forceinline__ void crt_mfma_block(const int8_t* __restrict__ RA, const int8_t* __restrict__ RB,
+                                               uint8_t* __restrict__ Y, int64_t Mp, int64_t Np, int64_t Kp,
+                                               int Nmod, int64_t tm, int64_t tn, int mod0, int mod1) {
     using T = CrtDma<BM, BN, WGM, WGN, D>;
     __shared__ __attribute__((aligned(1024))) int8_t lds[T::LDS_BYTES];
 
-    int64_t tm, tn;
-    if (!xcd_tile_coords<8>(blockIdx.x, Mp / BM, Np / BN, tm, tn)) return;
     const int64_t m0 = tm * BM, n0 = tn * BN;
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
     const int wm = wave % WGM, wn = wave / WGM;
     const int wave_lds = __builtin_amdgcn_readfirstlane(wave) * 1024;
     const int nkt = (int)(Kp / kCrtTileK);
-    // this workgroup's planes: mod0 .. mod1 - 1 (blockIdx.y < ceil(N / mods))
-    const int mod0 = (int)blockIdx.y * mods;
-    const int mod1 = mod0 + mods < N ? mod0 + mods : N;
     const int steps = (mod1 - mod0) * nkt;
     const int64_t stepA = Mp * kCrtTileK, stepB = Np * kCrtTileK;
 
@@ -522,6 +528,20 @@ __global__ __launch_bounds__(64 * WGM * WGN, 2) void crt_mfma_kernel(const int8_
     // the copies run ahead of the last step: let them land before the
     // workgroup's LDS is released
     wait_vm_all();
+}
+
+template <int BM, int BN, int WGM, int WGN, int D>
+__global__ __launch_bounds__(64 * WGM * WGN, 2) void crt_mfma_kernel(const int8_t* __restrict__ RA,
+                                                                     const int8_t* __restrict__ RB,
+                                                                     uint8_t* __restrict__ Y, int64_t Mp,
+                                                                     int64_t Np, int64_t Kp, int N,
+                                                                     int Nmod, int mods) {
+    int64_t tm, tn;
+    if (!xcd_tile_coords<8>(blockIdx.x, Mp / BM, Np / BN, tm, tn)) return;
+    // this workgroup's planes: mod0 .. mod1 - 1 (blockIdx.y < ceil(N / mods))
+    const int mod0 = (int)blockIdx.y * mods;
+    const int mod1 = mod0 + mods < N ? mod0 + mods : N;
+    crt_mfma_block<BM, BN, WGM, WGN, D>(RA, RB, Y, Mp, Np, Kp, Nmod, tm, tn, mod0, mod1);
 }
 
 // Wide variant: a 256 x 256 tile, four waves in 2 x 2 with 128 x 128 each
@@ -923,18 +943,20 @@ __device__ __forceinline__ void stage_residue_bytes(uint8_t* ys, const uint8_t* 
     }
 }
 
+// Block `blk` of the reconstruction: rows (blk % (Mp / 128)) 128 .. + 127
+// of columns 2 (blk / (Mp / 128)) and the next.
 template <int P, int K, int NKB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void crt_recombine_mfma_kernel(GemmArgs g, const int32_t* __restrict__ E,
-                                                                 const int32_t* __restrict__ F,
-                                                                 const uint8_t* __restrict__ Y, int N, int s,
-                                                                 int64_t Mp, int64_t Np, CrtRecConsts rc) {
+__device__ __forceinline__ void crt_recombine_block(const GemmArgs& g, const int32_t* __restrict__ E,
+                                                    const int32_t* __restrict__ F, const uint8_t* __restrict__ Y,
+                                                    int N, int s, int64_t Mp, int64_t Np, const CrtRecConsts& rc,
+                                                    int64_t blk) {
     using LM = LimbMfma<K, NKB>;
     // room for 32 NKB planes: the fragments read every slot (bytes of planes
     // t >= N are stale and masked), which keeps the reads free of branches
     __shared__ __align__(16) uint8_t ys[32 * NKB * 2 * kRec3Rows];
     __shared__ __align__(16) uint8_t bt[LM::kCols * LM::kMods];
     const int64_t tiles = Mp / kRec3Rows;
-    const int64_t i0 = (blockIdx.x % tiles) * kRec3Rows, j0 = 2 * (blockIdx.x / tiles);
+    const int64_t i0 = (blk % tiles) * kRec3Rows, j0 = 2 * (blk / tiles);
     const int tid = threadIdx.x;
     stage_residue_bytes<kNumModuli>(ys, Y, N, Mp * Np, Mp, i0, j0, g.n, tid);
     v4i af[LM::NCB][NKB];
@@ -947,6 +969,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void c
 #pragma unroll
     for (int l = 0; l < K; ++l) f = fma(L[l], rc.r[l], f);
     crt_finish_entry<P, K>(g, L, f, N, E[i] + F[j] - 14 * s, i, j);
+}
+
+template <int P, int K, int NKB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void crt_recombine_mfma_kernel(GemmArgs g, const int32_t* __restrict__ E,
+                                                                 const int32_t* __restrict__ F,
+                                                                 const uint8_t* __restrict__ Y, int N, int s,
+                                                                 int64_t Mp, int64_t Np, CrtRecConsts rc) {
+    crt_recombine_block<P, K, NKB>(g, E, F, Y, N, s, Mp, Np, rc, blockIdx.x);
 }
 
 // Two levels (digit integers cut into a high and a low half, A' = A_h 2^w +
@@ -1059,6 +1089,61 @@ __global__ __launch_bounds__(256) void crt_recombine3_kernel(GemmArgs g, const i
     }
 #pragma unroll
     for (int p = 0; p < P; ++p) g.C[p * g.sc + off] = t.c[p];
+}
+
+// ---------------------------------------------------------------------------
+// The four stages over a batch of problems (CrtBatchItem: each problem's
+// arguments, workspace regions and first block per stage).  A block finds
+// its problem by binary search over the block prefixes and runs the single
+// call's block body on it; every problem has the same N moduli and s digits,
+// one level, 128 x 128 product tiles.
+// ---------------------------------------------------------------------------
+
+// Stage 2: per problem (Kp / 64) (Mp / 16 + Np / 16) blocks, the k segment
+// fastest, op(A)'s row blocks first.
+template <int P, int NG>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void crt_residue_batch_kernel(
+    const CrtBatchItem* __restrict__ items, int64_t count, CrtWeights wa, CrtWeights wb, int s, int N) {
+    const int64_t bid = blockIdx.x;
+    const CrtBatchItem& it = items[crt_batch_find(items, count, bid, 1)];
+    const int64_t local = bid - it.b[1], segs = it.Kp / kTileK, ra = it.Mp / kResRows;
+    const int64_t seg = local % segs, rb = local / segs;
+    const bool second = rb >= ra;
+    const GemmArgs& g = it.g;
+    const ResOperand o = second ? ResOperand{g.B, g.tb ? 1 : g.ldb, g.tb ? g.ldb : 1, g.sb, g.n, it.F, it.RB, it.Np}
+                                : ResOperand{g.A, g.ta ? g.lda : 1, g.ta ? 1 : g.lda, g.sa, g.m, it.E, it.RA, it.Mp};
+    const CrtWeights* __restrict__ wt = second ? &wb : &wa;
+    const int lane = threadIdx.x & 63;
+    constexpr int SETS = 1;
+    const int shi = s;
+    v4i bw[SETS][NG];
+    float mf[NG], invm[NG];
+#pragma unroll
+    MPG_CRT_WEIGHT_FRAGMENTS(wt, shi, lane, bw, mf, invm)
+    crt_residue_block<P, NG, SETS>(o, bw, mf, invm, g.k, s, N, it.Kp, seg, second ? rb - ra : rb);
+}
+
+// Stage 3: per problem (Mp / 128) (Np / 128) tiles times `groups` workgroups
+// of `mods` planes each; the tile fastest, row tiles before column tiles.
+__global__ __launch_bounds__(256, 2) void crt_mfma_batch_kernel(const CrtBatchItem* __restrict__ items,
+                                                                int64_t count, int N, int mods) {
+    const int64_t bid = blockIdx.x;
+    const CrtBatchItem& it = items[crt_batch_find(items, count, bid, 2)];
+    const int64_t local = bid - it.b[2], tms = it.Mp / 128, tiles = tms * (it.Np / 128);
+    const int64_t tile = local % tiles;
+    const int mod0 = (int)(local / tiles) * mods;
+    const int mod1 = mod0 + mods < N ? mod0 + mods : N;
+    crt_mfma_block<128, 128, 2, 2, 8>(it.RA, it.RB, it.Y, it.Mp, it.Np, it.Kp, N, tile % tms, tile / tms, mod0,
+                                      mod1);
+}
+
+// Stage 4: per problem (Mp / 128) ceil(n / 2) blocks, as in the single call.
+template <int P, int K, int NKB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void crt_recombine_batch_kernel(
+    const CrtBatchItem* __restrict__ items, int64_t count, int N, int s, CrtRecConsts rc) {
+    const int64_t bid = blockIdx.x;
+    const CrtBatchItem& it = items[crt_batch_find(items, count, bid, 3)];
+    crt_recombine_block<P, K, NKB>(it.g, it.E, it.F, it.Y, N, s, it.Mp, it.Np, rc, bid - it.b[3]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1206,7 +1291,104 @@ int launch_crt_recombine_p(int K, dim3 grid, hipStream_t st, const GemmArgs& g, 
     return (int)hipGetLastError();
 }
 
+constexpr int kBatchCfg = 2;        // 128 x 128 product tiles, two workgroups per CU
+
 }  // namespace
+
+int crt_batch_moduli(int64_t kmax, int s) { return crt_moduli_count(kmax, s); }
+
+size_t crt_batch_item_bytes(int64_t m, int64_t n, int64_t k, int N) {
+    return crt_layout(m, n, k, N, kBatchCfg).total;
+}
+
+int crt_batch_plan(int N, int s, int64_t count, const GemmArgs* gs, void* ws, CrtBatchItem* items,
+                   CrtBatchInfo* info) {
+    (void)s;
+    if (N <= 0 || N > kNumModuli) return MPGEMM_ERR_UNSUPPORTED;
+    CrtBatchInfo in{};
+    in.N = N;
+    int64_t tiles = 0;
+    for (int64_t q = 0; q < count; ++q) {
+        const CrtLayout L = crt_layout(gs[q].m, gs[q].n, gs[q].k, N, kBatchCfg);
+        tiles += (L.Mp / 128) * (L.Np / 128);
+    }
+    const CrtGroups gr = crt_groups(tiles, kCrt[kBatchCfg].per_cu, N);
+    in.mods = gr.mods;
+    in.groups = gr.groups;
+    size_t off = 0;
+    for (int64_t q = 0; q < count; ++q) {
+        const GemmArgs& g = gs[q];
+        const CrtLayout L = crt_layout(g.m, g.n, g.k, N, kBatchCfg);
+        if (items) {
+            char* base = (char*)ws + off;
+            CrtBatchItem& it = items[q];
+            it.g = g;
+            it.E = (int32_t*)(base + L.oE);
+            it.F = (int32_t*)(base + L.oF);
+            it.RA = (int8_t*)(base + L.oRA);
+            it.RB = (int8_t*)(base + L.oRB);
+            it.Y = (uint8_t*)(base + L.oY);
+            it.Mp = L.Mp;
+            it.Np = L.Np;
+            it.Kp = L.Kp;
+            for (int f = 0; f < 4; ++f) it.b[f] = in.blocks[f];
+        }
+        in.blocks[0] += L.Mp / 4 + L.Np / 4;
+        in.blocks[1] += (L.Kp / kTileK) * (L.Mp / kResRows + L.Np / kResRows);
+        in.blocks[2] += (L.Mp / 128) * (L.Np / 128) * gr.groups;
+        in.blocks[3] += L.Mp / kRec3Rows * ((g.n + 1) / 2);
+        off += L.total;                              // each total is a multiple of 256
+    }
+    in.ws_bytes = off;
+    for (int f = 0; f < 4; ++f)
+        if (in.blocks[f] > 0x7fffffffLL) return MPGEMM_ERR_UNSUPPORTED;
+    if (info) *info = in;
+    return 0;
+}
+
+int launch_crt_batch(int P, int s, const CrtBatchInfo& info, const CrtBatchItem* d_items, int64_t count,
+                     hipStream_t st) {
+    const int N = info.N;
+    if (count <= 0) return 0;
+    int rc;
+    if ((rc = launch_row_exponents_batch(d_items, count, info.blocks[0], st))) return rc;
+    const CrtWeights wa = crt_weights(N, s, s, true);
+    const CrtWeights wb = crt_weights(N, s, s, false);
+    const dim3 g1((unsigned)info.blocks[1]);
+#define MPG_RESB(PV, NGV) \
+    hipLaunchKernelGGL((crt_residue_batch_kernel<PV, NGV>), g1, dim3(256), 0, st, d_items, count, wa, wb, s, N)
+    const bool two = N > 32;
+    if (P == 2) {
+        if (two) MPG_RESB(2, 2); else MPG_RESB(2, 1);
+    } else if (P == 3) {
+        if (two) MPG_RESB(3, 2); else MPG_RESB(3, 1);
+    } else {
+        if (two) MPG_RESB(4, 2); else MPG_RESB(4, 1);
+    }
+#undef MPG_RESB
+    if ((rc = (int)hipGetLastError())) return rc;
+    hipLaunchKernelGGL(crt_mfma_batch_kernel, dim3((unsigned)info.blocks[2]), dim3(256), 0, st, d_items, count,
+                       N, info.mods);
+    if ((rc = (int)hipGetLastError())) return rc;
+    const int K = limbs_for(N);
+    const CrtRecConsts rcs = crt_rec_consts(N, K);
+    const dim3 g3((unsigned)info.blocks[3]);
+#define MPG_RECB(PV, KV, NKB) \
+    hipLaunchKernelGGL((crt_recombine_batch_kernel<PV, KV, NKB>), g3, dim3(256), 0, st, d_items, count, N, s, rcs)
+#define MPG_RECBP(PV)                                      \
+    switch (K) {                                           \
+    case 4: MPG_RECB(PV, 4, 1); break;                     \
+    case 6: MPG_RECB(PV, 6, 1); break;                     \
+    case 8:                                                \
+        if (N > 32) MPG_RECB(PV, 8, 2); else MPG_RECB(PV, 8, 1); \
+        break;                                             \
+    default: MPG_RECB(PV, 11, 2); break;                   \
+    }
+    if (P == 2) { MPG_RECBP(2) } else if (P == 3) { MPG_RECBP(3) } else { MPG_RECBP(4) }
+#undef MPG_RECBP
+#undef MPG_RECB
+    return (int)hipGetLastError();
+}
 
 uint32_t crt_config_signature() {
     uint32_t h = 2166136261u;

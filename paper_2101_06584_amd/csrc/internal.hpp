@@ -111,6 +111,56 @@ uint32_t plain_config_signature(int P);
 uint32_t split_config_signature();
 uint32_t crt_config_signature();
 
+// Residue form over many problems at once (batched plans).  Every problem
+// keeps its own workspace region (the single call's layout with 128 x 128
+// product tiles); the four stages each run as one launch over all problems,
+// a block finding its problem from the per-stage block prefixes b[] (0
+// exponents, 1 residues, 2 products, 3 reconstruction).
+struct CrtBatchItem {
+    GemmArgs g;
+    int32_t* E;
+    int32_t* F;
+    int8_t* RA;
+    int8_t* RB;
+    uint8_t* Y;
+    int64_t Mp, Np, Kp;
+    int64_t b[4];
+};
+struct CrtBatchInfo {
+    int N;                 // moduli of every problem (those the largest k needs)
+    int mods, groups;      // product stage: planes per workgroup, workgroups per tile
+    size_t ws_bytes;       // workspace of all problems
+    int64_t blocks[4];     // grid of each stage
+};
+// The last item whose first block of stage f is at most bid (the same for
+// every lane of the block).
+__device__ __forceinline__ int64_t crt_batch_find(const CrtBatchItem* __restrict__ items, int64_t count,
+                                                  int64_t bid, int f) {
+    int64_t lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (items[mid].b[f] <= bid) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+// Moduli of a one-level residue product for inner dimensions up to kmax
+// with s digits (0: none serves).
+int crt_batch_moduli(int64_t kmax, int s);
+// Workspace one problem takes in a batch with N moduli (a multiple of 256).
+size_t crt_batch_item_bytes(int64_t m, int64_t n, int64_t k, int N);
+// Sizes the batch (items == nullptr) or also lays it out in ws and fills
+// items (host array of count).  Problems must be valid with m, n, k > 0 and
+// k no larger than N moduli serve.  Returns 0, or MPGEMM_ERR_UNSUPPORTED when
+// N is out of range or a stage's grid would exceed 2^31 - 1 blocks.
+int crt_batch_plan(int N, int s, int64_t count, const GemmArgs* gs, void* ws, CrtBatchItem* items,
+                   CrtBatchInfo* info);
+// The four stages on `stream` (d_items: device copy of the items).
+int launch_crt_batch(int P, int s, const CrtBatchInfo& info, const CrtBatchItem* d_items, int64_t count,
+                     hipStream_t st);
+// Stage 1 of a batch: scale exponents of every problem's op(A) rows and
+// op(B) columns (split_gemm.hip, beside the single-problem kernels).
+int launch_row_exponents_batch(const CrtBatchItem* d_items, int64_t count, int64_t blocks, hipStream_t st);
+
 // The _ex entry points' dispatch for precision P (argument errors numbered as
 // for mpgemm_dd_ex, 1..18).
 int gemm_ex_entry(int P, char ta, char tb, int64_t m, int64_t n, int64_t k, const double* alpha,

@@ -154,6 +154,29 @@ __global__ __launch_bounds__(256) void exponent_rows_wave_kernel(RowSet a, RowSe
     if (lane == 0) o.E[r] = (r < o.count) ? scale_exponent(M) : 0;
 }
 
+// Exponents of a batch of residue-form problems: block b of the launch is
+// block b - b[0] of its problem, the first ceil(Mp / 4) covering op(A)'s
+// rows (four rows a block, a wave a row), the rest op(B)'s columns.
+__global__ __launch_bounds__(256) void exponent_rows_batch_kernel(const CrtBatchItem* __restrict__ items,
+                                                                  int64_t count) {
+    const int64_t bid = blockIdx.x;
+    const CrtBatchItem& it = items[crt_batch_find(items, count, bid, 0)];
+    const GemmArgs& g = it.g;
+    const int64_t local = bid - it.b[0], a_blocks = (it.Mp + 3) / 4;
+    const bool second = local >= a_blocks;
+    const RowSet o = second ? RowSet{g.B, g.tb ? 1 : g.ldb, g.tb ? g.ldb : 1, g.n, it.Np, it.F}
+                            : RowSet{g.A, g.ta ? g.lda : 1, g.ta ? 1 : g.lda, g.m, it.Mp, it.E};
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (second ? local - a_blocks : local) * 4 + (threadIdx.x >> 6);
+    if (r >= o.padded) return;
+    double M = 0.0;
+    if (r < o.count)
+        for (int64_t l = lane; l < g.k; l += 64) M = fmax(M, fabs(o.X[r * o.rs + l * o.ls]));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) M = fmax(M, __shfl_xor(M, off, 64));
+    if (lane == 0) o.E[r] = (r < o.count) ? scale_exponent(M) : 0;
+}
+
 // ---------------------------------------------------------------------------
 // Stage 2: digits.  Digit p (1-based) of entry (r, l) goes to
 // D[((p-1) * (Kp/64) + l/64) * Rp * 64 + r * 64 + l % 64]: per digit plane,
@@ -609,6 +632,13 @@ static int launch_exponents_pair(const double* A, int64_t a_rs, int64_t a_ls, in
     if (blocks > 0)
         hipLaunchKernelGGL(exponent_rows_wave_kernel, dim3((unsigned)blocks, 2), dim3(256), 0, st,
                            RowSet{A, a_rs, a_ls, m, Mp, E}, RowSet{B, b_rs, b_ls, n, Np, F}, k);
+    return (int)hipGetLastError();
+}
+
+int launch_row_exponents_batch(const CrtBatchItem* d_items, int64_t count, int64_t blocks, hipStream_t st) {
+    if (blocks > 0x7fffffffLL) return (int)hipErrorInvalidConfiguration;
+    if (blocks > 0)
+        hipLaunchKernelGGL(exponent_rows_batch_kernel, dim3((unsigned)blocks), dim3(256), 0, st, d_items, count);
     return (int)hipGetLastError();
 }
 

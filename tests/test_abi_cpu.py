@@ -183,6 +183,30 @@ def test_batch_plan_validation():
         x.A, x.lda, x.a_plane_stride = FAKE_A, 4, 16
         x.B, x.ldb, x.b_plane_stride = FAKE_B, 4, 16
         x.C, x.ldc, x.c_plane_stride = FAKE_C, 4, 16
+    # forms: plain, auto and residue only; options in range; the residue form
+    # needs a one-level product for every problem that multiplies (none for
+    # s > 24, QD's default of 31 included, or k beyond 131071)
+    def opts(form, slices=0):
+        o = _lib.Opts()
+        o.form, o.slices, o.tile = form, slices, -1
+        return o
+    for form in (_lib.FORM_SPLIT_I8, _lib.FORM_STRASSEN):
+        assert L.mpgemm_batch_plan_create(2, 2, arr, C.byref(opts(form, 16)), None, C.byref(h)) == \
+            _lib.ERR_UNSUPPORTED
+    assert L.mpgemm_batch_plan_create(2, 2, arr, C.byref(opts(_lib.FORM_SPLIT_CRT, 99)), None, C.byref(h)) == -4
+    assert L.mpgemm_batch_plan_create(4, 2, arr, C.byref(opts(_lib.FORM_SPLIT_CRT, 25)), None, C.byref(h)) == \
+        _lib.ERR_UNSUPPORTED
+    assert L.mpgemm_batch_plan_create(4, 2, arr, C.byref(opts(_lib.FORM_SPLIT_CRT, 0)), None, C.byref(h)) == \
+        _lib.ERR_UNSUPPORTED
+    big = (_lib.Problem * 1)()
+    x = big[0]
+    x.transa = b"N"; x.transb = b"N"; x.m = 4; x.n = 4; x.k = 131072
+    x.alpha[0] = 1.0
+    x.A, x.lda, x.a_plane_stride = FAKE_A, 4, 4 * 131072
+    x.B, x.ldb, x.b_plane_stride = FAKE_B, 131072, 4 * 131072
+    x.C, x.ldc, x.c_plane_stride = FAKE_C, 4, 16
+    assert L.mpgemm_batch_plan_create(2, 1, big, C.byref(opts(_lib.FORM_SPLIT_CRT, 16)), None, C.byref(h)) == \
+        _lib.ERR_UNSUPPORTED
     arr[1].ldc = 2
     assert L.mpgemm_batch_plan_create(2, 2, arr, None, None, C.byref(h)) == -1001
 
@@ -238,7 +262,7 @@ def test_grouped_validation():
         x.C, x.ldc, x.c_plane_stride = FAKE_C, 4, 16
     split = _lib.Opts()
     split.form = _lib.FORM_SPLIT_I8
-    assert L.mpgemm_dd_grouped(2, arr, C.byref(split), None) == -3     # plain only
+    assert L.mpgemm_dd_grouped(2, arr, C.byref(split), None) == -3     # plain, auto, residue only
     variant = _lib.Opts()
     variant.variant = 1
     assert L.mpgemm_td_grouped(2, arr, C.byref(variant), None) == -3

@@ -6,8 +6,10 @@ One step = the whole hot path over one batch of synthetic input:
     its variants: triangular (scale scan, digit slicing, anti-diagonal MFMA
     sums, recombination, epilogue) and residue (the same digits, one INT8
     product per coprime modulus, exact Chinese-remainder reconstruction);
-  * the batched persistent form: 512 DD and 512 TD GEMMs with m, n, k uniform
-    in 16..512, each set one replay of its captured hipGraph;
+  * the batched form: 512 DD and 512 TD GEMMs with m, n, k uniform in
+    16..512, each set once in the plain form (one persistent launch) and once
+    in the residue form (the four residue stages, one launch each over the
+    set), each one replay of its captured hipGraph;
 with tile configurations from the autotuner's table.  `value` is the step's
 total 2mnk divided by its time.
 
@@ -200,13 +202,20 @@ def main():
                 dp.append(q)
             plan = mp.BatchPlan(P, dp, stream=stream)
             work = sum(2.0 * q["m"] * q["n"] * q["k"] for q in dp)
-            batched[P] = {"plan": plan, "probs": dp, "work": work, "host": hp}
-            note("batched plan ready", NAME[P])
+            # the residue form of the same set: the same operands, C of its own
+            dc = [dict(q, C=q["C"].clone()) for q in dp]
+            plan_crt = mp.BatchPlan(P, dc, stream=stream, form="crt", slices=mp.DEFAULT_SLICES[P])
+            batched[P] = {"plan": plan, "probs": dp, "work": work, "host": hp, "crt_plan": plan_crt,
+                          "crt_probs": dc, "s": mp.DEFAULT_SLICES[P]}
+            note("batched plans ready", NAME[P], plan_crt.info())
         torch.cuda.synchronize()
 
     def run(P, f):
         if f == "batched":
             batched[P]["plan"].run(stream=stream)
+            return
+        if f == "batched_crt":
+            batched[P]["crt_plan"].run(stream=stream)
             return
         d = devd[P]
         if f == "plain":
@@ -236,11 +245,25 @@ def main():
                 errors[(P, f, "median")] = float(np.median(r))
                 devd[P]["C_" + f].copy_(devd[P]["C0"])
                 note("checked", NAME[P], f, "max err ratio", errors[(P, f)])
-        torch.cuda.synchronize()
+        # batched residue form: 128 sampled entries of each of the first 8 problems
+        for P, b in sorted(batched.items()):
+            b["crt_plan"].run(stream=stream)
+            torch.cuda.synchronize()
+            rs = []
+            for q in range(8):
+                h, d = b["host"][q], b["crt_probs"][q]
+                chk = GemmChecker(P, "N", "N", h["m"], h["n"], h["k"], h["alpha"], h["A"], h["B"], h["beta"], h["C"])
+                rs.append(chk.ratios(d["C"].cpu().numpy(), sample_entries(synth.rng_for(5, q), h["m"], h["n"], 128)))
+            r = np.concatenate(rs)
+            errors[(P, "batched_crt")] = float(r.max())
+            errors[(P, "batched_crt", "median")] = float(np.median(r))
+            errors[(P, "batched_crt", "n")] = int(r.size)
+            note("checked", NAME[P], "batched_crt", "max err ratio", errors[(P, "batched_crt")])
 
     # ---- warmup + timed steps; per-part events on the launch stream ----
-    order = [(P, f) for P in precs for f in forms] + [(P, "batched") for P in sorted(batched)]
-    part_work = {key: (batched[key[0]]["work"] if key[1] == "batched" else 2.0 * n ** 3)
+    order = [(P, f) for P in precs for f in forms] + [(P, f) for P in sorted(batched)
+                                                      for f in ("batched", "batched_crt")]
+    part_work = {key: (batched[key[0]]["work"] if key[1].startswith("batched") else 2.0 * n ** 3)
                  for key in order}
     for _ in range(args.warmup):
         for P, f in order:
@@ -280,6 +303,13 @@ def main():
             item.update(problems=len(batched[P]["probs"]), tiles=info["tiles"],
                         tile_cfg=info["tile_cfg"], grid=info["grid"])
             item.update(separate_launches(mp, P, batched[P], stream))
+        elif f == "batched_crt":
+            info = batched[P]["crt_plan"].info()
+            item.update(problems=len(batched[P]["crt_probs"]), slices=batched[P]["s"],
+                        residue_problems=info["residue_problems"], int8_products=info["moduli"],
+                        chunks=info["chunks"], workspace_bytes=info["residue_workspace"])
+            # INT8 operations of the unpadded products over the time
+            item["int8_ops_frac"] = info["moduli"] * part_work[key] / (ms * 1e-3) / INT8_PEAK
         elif f == "plain":
             item["fp64_peak_frac"] = n ** 3 * FLOPS_PER_MAC[P] / (ms * 1e-3) / FP64_PEAK
             item["fp64_issue_frac"] = n ** 3 * INSTR_PER_MAC[P] / (ms * 1e-3) / FP64_ISSUE
@@ -297,7 +327,7 @@ def main():
         if (P, f) in errors:
             item["max_err_ratio"] = errors[(P, f)]
             item["median_err_ratio"] = errors[(P, f, "median")]
-            item["err_samples"] = 1024
+            item["err_samples"] = errors.get((P, f, "n"), 1024)
         breakdown[f"{NAME[P]}_{f}"] = item
 
     # ---- roofline of the dominant kernel: the plain GEMM of the widest
@@ -327,6 +357,7 @@ def main():
 
     for P in batched:
         batched[P]["plan"].close()
+        batched[P]["crt_plan"].close()
 
     # ---- measured peaks of this GPU (after the timed region), and the parts'
     # fractions of them beside the fractions of the published figures ----
@@ -335,6 +366,8 @@ def main():
     for key, item in breakdown.items():
         P = PREC_OF[key.split("_")[0]]
         ms = item["ms"]
+        if "_batched" in key:
+            continue
         if key.endswith("_plain"):
             item["fp64_issue_frac_measured"] = n ** 3 * INSTR_PER_MAC[P] / (ms * 1e-3) / peaks["fp64_add_op_s"]
         elif key.endswith("_split") or key.endswith("_crt"):
@@ -350,8 +383,8 @@ def main():
         "config": {"workload": f"square DD/TD/QD GEMM C = alpha*A*B + beta*C, m=n=k={n}, "
                                "random alpha/beta/C, plain EFT form and the split INT8-MFMA form in "
                                "both its triangular and its residue (CRT) variant; plus "
-                               "batched DD and TD sets of 512 GEMMs with m,n,k ~ U[16,512] "
-                               "(one hipGraph replay each)",
+                               "batched DD and TD sets of 512 GEMMs with m,n,k ~ U[16,512], "
+                               "each in the plain and the residue form (one hipGraph replay each)",
                    "m": n, "n": n, "k": n, "precisions": [NAME[P] for P in precs], "forms": forms,
                    "batched_sets": [NAME[P] for P in sorted(batched)],
                    "parts_per_step": len(order), "parallelism": "single GPU"},
@@ -885,12 +918,13 @@ def cpu_baseline(host, precs, forms, n, devd, budget, batched):
       rows + columns, so it is timed on 256 columns of op(B) and scaled to all
       2n rows and columns once, and only the products of a square block are
       scaled by n^2 / (rows cols);
-    * batched sets: the first problems of each set.
+    * batched sets: the first problems of each set, in the plain and in
+      the residue form.
 
     One thread and all threads are timed on the same block (DD plain)."""
     import oracle
     threads = oracle.num_threads()
-    per = budget / max(1, len(precs) * len(forms) + len(batched))
+    per = budget / max(1, len(precs) * len(forms) + 2 * len(batched))
     est_total = 0.0
     total_work = 0.0
     parts = []
@@ -909,6 +943,20 @@ def cpu_baseline(host, precs, forms, n, devd, budget, batched):
         est_total += b["work"] / rate
         total_work += b["work"]
         parts.append(f"{NAME[P]}-batched: first {cnt} problems ({rate:.3g} 2mnk/s)")
+        t0 = time.perf_counter()
+        done = 0.0
+        cnt = 0
+        for q in b["host"]:
+            oracle.gemm_crt(P, b["s"], q["transa"], q["transb"], q["m"], q["n"], q["k"], q["alpha"], q["A"],
+                            q["B"], q["beta"], q["C"])
+            done += 2.0 * q["m"] * q["n"] * q["k"]
+            cnt += 1
+            if time.perf_counter() - t0 > per / 2:
+                break
+        rate = done / (time.perf_counter() - t0)
+        est_total += b["work"] / rate
+        total_work += b["work"]
+        parts.append(f"{NAME[P]}-batched-residue: first {cnt} problems ({rate:.3g} 2mnk/s)")
     for P in precs:
         A, B, C, alpha, beta = host[P]
         for f in forms:

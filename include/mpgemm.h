@@ -402,9 +402,10 @@ typedef struct mpgemm_batch_plan mpgemm_batch_plan;  /* opaque */
  * dimension) run in the plain part.  Every residue problem uses the moduli
  * that the largest k among them needs (the reconstruction is exact, so
  * extra moduli change no bit).  The plan owns the residue workspace
- * (problems padded to 128 x 128 product tiles, grouped into chunks of at
- * most 1 GiB that run one after another; mpgemm_batch_plan_residue_info
- * reports it).
+ * (problems padded to 128 x 128 product tiles, grouped into chunks that
+ * run one after another, each within opts->workspace_bytes if nonzero, else
+ * 1 GiB; opts->workspace itself is not used; mpgemm_batch_plan_residue_info
+ * reports the chunks and bytes).
  * The plan binds the device addresses in `problems`; their contents may
  * change between runs.
  */

@@ -221,13 +221,15 @@ class BatchPlan:
     the residue part (form "crt", or "auto" with slices > 0) in four
     launches per chunk."""
 
-    def __init__(self, prec, problems, tile=-1, stream=None, form="plain", slices=0):
+    def __init__(self, prec, problems, tile=-1, stream=None, form="plain", slices=0, chunk_bytes=0):
         """problems: sequence of dicts with keys transa, transb, m, n, k, alpha,
-        A, B, beta, C (tensors as for gemm())."""
+        A, B, beta, C (tensors as for gemm()); chunk_bytes bounds the residue
+        part's workspace per chunk (0: the library's default)."""
         self.P = PREC[prec]
         L = _lib.load()
         arr, self._keep = _problem_array(self.P, problems)
         opts = make_opts(form, slices, tile, None)
+        opts.workspace_bytes = int(chunk_bytes)
         h = C.c_void_p()
         rc = L.mpgemm_batch_plan_create(self.P, len(problems), arr, C.byref(opts), _stream(stream),
                                         C.byref(h))

@@ -549,9 +549,10 @@ MPG_GEMV(mp_gemv_qd, 4)
 
 // ---- batched plan -----------------------------------------------------------
 
-// Residue problems of a plan run in chunks whose workspace stays within this
-// size (a problem larger than it forms a chunk of its own); the chunks run
-// one after another on the plan's stream and share one workspace.
+// Residue problems of a plan run in chunks whose workspace stays within a
+// bound (opts->workspace_bytes, else this default; a problem larger than it
+// forms a chunk of its own); the chunks run one after another on the plan's
+// stream and share one workspace.
 constexpr size_t kBatchChunkBytes = (size_t)1 << 30;
 
 struct CrtChunk {
@@ -596,7 +597,8 @@ bool plan_empty(const mpgemm_batch_plan* plan) { return plan->tiles == 0 && plan
 
 // The residue part: chunks laid out over one workspace, items copied to the
 // device (synchronously on st).  gs: the residue problems, largest first.
-int plan_residue_part(mpgemm_batch_plan* plan, int N, int s, const std::vector<GemmArgs>& gs, hipStream_t st) {
+int plan_residue_part(mpgemm_batch_plan* plan, int N, int s, size_t bound, const std::vector<GemmArgs>& gs,
+                      hipStream_t st) {
     const int64_t cnt = (int64_t)gs.size();
     plan->crt_s = s;
     plan->crt_count = cnt;
@@ -606,7 +608,7 @@ int plan_residue_part(mpgemm_batch_plan* plan, int N, int s, const std::vector<G
     int64_t first = 0;
     for (int64_t q = 0; q < cnt; ++q) {
         const size_t b = crt_batch_item_bytes(gs[(size_t)q].m, gs[(size_t)q].n, gs[(size_t)q].k, N);
-        if (q > first && cur + b > kBatchChunkBytes) {
+        if (q > first && cur + b > bound) {
             ranges.emplace_back(first, q - first);
             first = q;
             cur = 0;
@@ -716,7 +718,8 @@ int mpgemm_batch_plan_create(int prec, int64_t count, const mpgemm_problem* prob
     if (!err && (hipMemcpyAsync(plan->d_desc, host.data(), bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
                  hipStreamSynchronize(st) != hipSuccess))
         err = MPGEMM_ERR_HIP;
-    if (!err && !gr.empty()) err = plan_residue_part(plan, crt_batch_moduli(kmax, s), s, gr, st);
+    const size_t bound = (opts && opts->workspace_bytes > 0) ? opts->workspace_bytes : kBatchChunkBytes;
+    if (!err && !gr.empty()) err = plan_residue_part(plan, crt_batch_moduli(kmax, s), s, bound, gr, st);
     // capture every launch of a run on a private stream
     hipStream_t cs = nullptr;
     if (!err && !plan_empty(plan)) {

@@ -28,6 +28,7 @@
 // 127)^2), so C' is the representative in (-M/2, M/2).
 #pragma clang fp contract(off)
 
+#include <algorithm>
 #include <cmath>
 
 #include "internal.hpp"
@@ -140,12 +141,14 @@ struct CrtLayout {
     size_t oE, oF, oMX, oRA, oRB, oY, total;
 };
 
-CrtLayout crt_layout(int64_t m, int64_t n, int64_t k, int N, int cfg) {
+// kalign: 2 kTileK by default (the wide kernel takes an even number of
+// 64-byte steps per modulus); the others need whole 64-byte residue segments.
+CrtLayout crt_layout(int64_t m, int64_t n, int64_t k, int N, int cfg, int kalign = 2 * kTileK) {
     const CrtConfig c = kCrt[cfg];
     CrtLayout L;
     L.Mp = round_up(m > 0 ? m : 1, c.bm);
     L.Np = round_up(n > 0 ? n : 1, c.bn);
-    L.Kp = round_up(k > 0 ? k : 1, 2 * kTileK);    // an even number of 64-byte steps per modulus
+    L.Kp = round_up(k > 0 ? k : 1, kalign);
     size_t off = 0;
     L.oE = off;  off = align256(off + sizeof(int32_t) * L.Mp);
     L.oF = off;  off = align256(off + sizeof(int32_t) * L.Np);
@@ -246,11 +249,21 @@ __device__ __forceinline__ void crt_residue_block(const ResOperand& o, const v4i
     int8_t* __restrict__ R = o.R;
     const int64_t r0 = rowblk * kResRows;
     if (r0 >= Rp) return;                         // the whole block: before any barrier
+    const int64_t l0 = seg * kTileK;
+    const int t = threadIdx.x;
+    const int64_t nkt = Kp / kCrtTileK;
+    if (r0 >= count || l0 >= k) {
+        // padding only: every residue is zero (wave w writes planes w, w + 4, ..)
+        const int lane = t & 63, wave = t >> 6;
+        const int st_kt = lane >> 5, st_row = (lane >> 1) & 15, st_half = lane & 1;
+        for (int plane = wave; plane < SETS * N; plane += 4)
+            *(v4i*)(R + (((int64_t)plane * nkt + 2 * seg + st_kt) * Rp + r0 + st_row) * kCrtTileK + 16 * st_half) =
+                v4i{0, 0, 0, 0};
+        return;
+    }
     constexpr int kTileBytes = P * kResRows * (kTileK + 1) * 8;
     __shared__ __align__(16) uint8_t lds[kTileBytes > kStageBytes ? kTileBytes : kStageBytes];
     double (*tile)[kResRows][kTileK + 1] = reinterpret_cast<double (*)[kResRows][kTileK + 1]>(lds);
-    const int64_t l0 = seg * kTileK;
-    const int t = threadIdx.x;
     const bool rows_contig = (rs == 1);
 #pragma unroll
     for (int it = 0; it < 4; ++it) {
@@ -265,7 +278,6 @@ __device__ __forceinline__ void crt_residue_block(const ResOperand& o, const v4i
     __syncthreads();
 
     const int lane = t & 63, wave = t >> 6;
-    const int64_t nkt = Kp / kCrtTileK;
     // the remainders of the wave's four rows, then the tile's space is free
     double rem[4][P];
 #pragma unroll
@@ -389,6 +401,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void c
 // Y[(t Np + col) Mp + row]), and the accumulators cleared.
 // ---------------------------------------------------------------------------
 
+// Entries 4 v4 .. 4 v4 + 3 of accumulator x reduced modulo m = md (inv = 1/m
+// rounded), four residues in [0, m) packed into a word.  The quotient is
+// floor(x inv + 2^-20): for |x| < 2^31 the two roundings in fma(x, inv, c)
+// err by less than 2^-21 together, and the fraction of x / m is 0 or lies
+// in [1/m, 1 - 1/m] with 1/m >= 2^-8, so the offset keeps exact multiples
+// on their quotient and carries no other value past the next integer;
+// x - q m is then exact and in [0, m).
+__device__ __forceinline__ uint32_t reduce_word(const v16i& x, int v4, double md, double inv) {
+    uint32_t word = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const double xd = (double)x[4 * v4 + q];
+        const double quo = floor(fma(xd, inv, 0x1p-20));
+        word |= (uint32_t)(int)fma(-quo, md, xd) << (8 * q);
+    }
+    return word;
+}
+
 template <int BM, int BN, int WGM, int WGN, int D>
 struct CrtDma {
     static constexpr int NT = 64 * WGM * WGN;             // threads
@@ -496,8 +526,7 @@ __device__ __forceinline__ void crt_mfma_block(const int8_t* __restrict__ RA, co
         // last k-tile of modulus `mod`: reduce, store, clear
         // plane `mod` is modulus mod % Nmod of its residue set
         const int mi = mod % Nmod;
-        const int mt = kCrtDev.mod[mi];
-        const double md = (double)mt, inv = kCrtDev.inv[mi];
+        const double md = (double)kCrtDev.mod[mi], inv = kCrtDev.inv[mi];
         uint8_t* Yt = Y + (int64_t)mod * Np * Mp;
 #pragma unroll
         for (int i = 0; i < T::FM; ++i)
@@ -506,18 +535,8 @@ __device__ __forceinline__ void crt_mfma_block(const int8_t* __restrict__ RA, co
                 const int64_t col = n0 + wn * T::WN + jj * 32 + (lane & 31);
                 const int64_t rowb = m0 + wm * T::WM + i * 32 + 4 * (lane >> 5);
 #pragma unroll
-                for (int v4 = 0; v4 < 4; ++v4) {
-                    uint32_t word = 0;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        // |x| < 2^31: the rounded quotient is off by at most one
-                        const double x = (double)acc[i][jj][4 * v4 + q];
-                        int y = (int)fma(-rint(x * inv), md, x);
-                        y += (y < 0) ? mt : 0;
-                        word |= (uint32_t)y << (8 * q);
-                    }
-                    *(uint32_t*)(Yt + col * Mp + rowb + 8 * v4) = word;
-                }
+                for (int v4 = 0; v4 < 4; ++v4)
+                    *(uint32_t*)(Yt + col * Mp + rowb + 8 * v4) = reduce_word(acc[i][jj], v4, md, inv);
                 acc[i][jj] = v16i{0};
             }
         // no drain: the waits stay sufficient with stores outstanding (see
@@ -528,6 +547,125 @@ __device__ __forceinline__ void crt_mfma_block(const int8_t* __restrict__ RA, co
     // the copies run ahead of the last step: let them land before the
     // workgroup's LDS is released
     wait_vm_all();
+}
+
+// The same product with one more wave that does all the copying: it waits
+// (on its own counter) for step u's copies, meets the others at the step's
+// barrier and then refills the slot step u - 1 used.  The WGM x WGN MFMA
+// waves issue no loads: they wait only for their LDS reads, and the stores
+// of each modulus's residues never hold up a later step.  With the copies
+// in every wave, those stores share the counter with the copies in flight,
+// so the first step of each modulus waited for the whole ring; on short k
+// panels (a few steps per modulus) that wait dominated.
+template <int BM, int BN, int WGM, int WGN, int D>
+struct CrtDmaCw {
+    static constexpr int NW = WGM * WGN;                  // MFMA waves; wave NW copies
+    static constexpr int WM = BM / WGM, WN = BN / WGN;
+    static constexpr int FM = WM / 32, FN = WN / 32;
+    static constexpr int A_BYTES = BM * kCrtTileK, B_BYTES = BN * kCrtTileK;
+    static constexpr int STAGE = A_BYTES + B_BYTES;
+    static constexpr int A_LOADS = A_BYTES / 1024, B_LOADS = B_BYTES / 1024;   // 1 KiB per copy instruction
+    static constexpr int PER_STEP = A_LOADS + B_LOADS;
+    static constexpr int LDS_BYTES = D * STAGE;
+    static_assert(A_BYTES % 1024 == 0 && B_BYTES % 1024 == 0, "tiles split into whole copies");
+    static_assert(WM % 32 == 0 && WN % 32 == 0, "wave block of 32 x 32 MFMA tiles");
+    static_assert(PER_STEP * (D - 2) <= 63, "vector-memory counter range");
+    static_assert(LDS_BYTES <= 163840, "160 KiB of LDS per CU");
+};
+
+template <int BM, int BN, int WGM, int WGN, int D>
+__device__ __forceinline__ void crt_mfma_block_cw(const int8_t* __restrict__ RA, const int8_t* __restrict__ RB,
+                                                  uint8_t* __restrict__ Y, int64_t Mp, int64_t Np, int64_t Kp,
+                                                  int Nmod, int64_t tm, int64_t tn, int mod0, int mod1) {
+    using T = CrtDmaCw<BM, BN, WGM, WGN, D>;
+    __shared__ __attribute__((aligned(1024))) int8_t lds[T::LDS_BYTES];
+
+    const int64_t m0 = tm * BM, n0 = tn * BN;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nkt = (int)(Kp / kCrtTileK);
+    const int steps = (mod1 - mod0) * nkt;
+    const int64_t stepA = Mp * kCrtTileK, stepB = Np * kCrtTileK;
+
+    if (wave == T::NW) {
+        // copy h of a step: LDS half u = 64 h + lane of its tile is row u / 2,
+        // position u % 2, which holds global half (u % 2) ^ ((row / 8) % 2)
+        const int r0 = lane >> 1;
+        const int gofs = r0 * kCrtTileK + (((lane & 1) ^ ((r0 >> 3) & 1)) << 4);   // rows 32 h + r0: same swap
+        const int8_t* fa = RA + (int64_t)mod0 * nkt * stepA + m0 * kCrtTileK + gofs;
+        const int8_t* fb = RB + (int64_t)mod0 * nkt * stepB + n0 * kCrtTileK + gofs;
+        int fstep = 0, fslot = 0;
+        // past the last step the cursor stays on the last tiles (copied into
+        // slots no step reads), so every step issues the same copies
+        auto issue = [&]() __attribute__((always_inline)) {
+            int8_t* la = lds + fslot * T::STAGE;
+#pragma unroll
+            for (int h = 0; h < T::A_LOADS; ++h) copy16_to_lds(fa + h * 32 * kCrtTileK, la + 1024 * h);
+#pragma unroll
+            for (int h = 0; h < T::B_LOADS; ++h) copy16_to_lds(fb + h * 32 * kCrtTileK, la + T::A_BYTES + 1024 * h);
+            if (++fstep < steps) {
+                fa += stepA;
+                fb += stepB;
+            }
+            fslot = (fslot + 1 == D) ? 0 : fslot + 1;
+        };
+        for (int r = 0; r < D - 1; ++r) issue();
+        for (int u = 0; u < steps; ++u) {
+            wait_vm_barrier<T::PER_STEP * (D - 2)>();    // step u landed; step u - 1's slot is free
+            issue();
+        }
+        wait_vm_all();                                   // before the workgroup's LDS is released
+        return;
+    }
+
+    const int wm = wave % WGM, wn = wave / WGM;
+    int aofs[T::FM], bofs[T::FN];
+#pragma unroll
+    for (int i = 0; i < T::FM; ++i) aofs[i] = swz32(wm * T::WM + i * 32 + (lane & 31), lane >> 5);
+#pragma unroll
+    for (int jj = 0; jj < T::FN; ++jj) bofs[jj] = T::A_BYTES + swz32(wn * T::WN + jj * 32 + (lane & 31), lane >> 5);
+    v16i acc[T::FM][T::FN];
+#pragma unroll
+    for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+        for (int jj = 0; jj < T::FN; ++jj) acc[i][jj] = v16i{0};
+
+    int cslot = 0, kt = 0, mod = mod0;
+    for (int u = 0; u < steps; ++u) {
+        wait_lds_barrier();
+        const int8_t* st = lds + cslot * T::STAGE;
+        cslot = (cslot + 1 == D) ? 0 : cslot + 1;
+        v4i fa_[T::FM], fb_[T::FN];
+#pragma unroll
+        for (int i = 0; i < T::FM; ++i) fa_[i] = *(const v4i*)(st + aofs[i]);
+#pragma unroll
+        for (int jj = 0; jj < T::FN; ++jj) fb_[jj] = *(const v4i*)(st + bofs[jj]);
+#pragma unroll
+        for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+            for (int jj = 0; jj < T::FN; ++jj)
+                acc[i][jj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa_[i], fb_[jj], acc[i][jj], 0, 0, 0);
+        if (++kt < nkt) continue;
+
+        // last k-tile of modulus `mod` (modulus mod % Nmod of its residue
+        // set): reduce, store, clear
+        const int mi = mod % Nmod;
+        const double md = (double)kCrtDev.mod[mi], inv = kCrtDev.inv[mi];
+        uint8_t* Yt = Y + (int64_t)mod * Np * Mp;
+#pragma unroll
+        for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+            for (int jj = 0; jj < T::FN; ++jj) {
+                const int64_t col = n0 + wn * T::WN + jj * 32 + (lane & 31);
+                const int64_t rowb = m0 + wm * T::WM + i * 32 + 4 * (lane >> 5);
+#pragma unroll
+                for (int v4 = 0; v4 < 4; ++v4)
+                    *(uint32_t*)(Yt + col * Mp + rowb + 8 * v4) = reduce_word(acc[i][jj], v4, md, inv);
+                acc[i][jj] = v16i{0};
+            }
+        kt = 0;
+        ++mod;
+    }
 }
 
 template <int BM, int BN, int WGM, int WGN, int D>
@@ -570,19 +708,6 @@ struct WideCfg {
     static_assert(PER_STEP * (D - 1) <= 63, "vector-memory counter range");
     static_assert(LDS_BYTES <= 163840, "160 KiB of LDS per CU");
 };
-
-__device__ __forceinline__ uint32_t reduce_word(const v16i& x, int v4, int mt, double md, double inv) {
-    uint32_t word = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        // |x| < 2^31: the rounded quotient is off by at most one
-        const double xd = (double)x[4 * v4 + q];
-        int y = (int)fma(-rint(xd * inv), md, xd);
-        y += (y < 0) ? mt : 0;
-        word |= (uint32_t)y << (8 * q);
-    }
-    return word;
-}
 
 template <int KH>
 __global__ __launch_bounds__(256, 1) void crt_mfma_wide_kernel(const int8_t* __restrict__ RA,
@@ -704,8 +829,7 @@ __global__ __launch_bounds__(256, 1) void crt_mfma_wide_kernel(const int8_t* __r
         }
         // plane `mod` is modulus mod % Nmod of its residue set
         const int mi = mod % Nmod;
-        const int mt = kCrtDev.mod[mi];
-        const double md = (double)mt, inv = kCrtDev.inv[mi];
+        const double md = (double)kCrtDev.mod[mi], inv = kCrtDev.inv[mi];
         // this lane's first byte in plane `mod`; the tiles are uniform offsets from it
         uint8_t* Yl = Y + (int64_t)mod * Np * Mp + ybase;
 #pragma unroll
@@ -715,7 +839,7 @@ __global__ __launch_bounds__(256, 1) void crt_mfma_wide_kernel(const int8_t* __r
                 const int64_t tofs = (int64_t)(jj * 32) * Mp + i * 32;
 #pragma unroll
                 for (int v4 = 0; v4 < 4; ++v4)
-                    *(uint32_t*)(Yl + tofs + 8 * v4) = reduce_word(acc[i][jj], v4, mt, md, inv);
+                    *(uint32_t*)(Yl + tofs + 8 * v4) = reduce_word(acc[i][jj], v4, md, inv);
                 acc[i][jj] = v16i{0};
                 __builtin_amdgcn_sched_barrier(0);      // one accumulator's temporaries at a time
             }
@@ -1125,16 +1249,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void c
 
 // Stage 3: per problem (Mp / 128) (Np / 128) tiles times `groups` workgroups
 // of `mods` planes each; the tile fastest, row tiles before column tiles.
-__global__ __launch_bounds__(256, 2) void crt_mfma_batch_kernel(const CrtBatchItem* __restrict__ items,
-                                                                int64_t count, int N, int mods) {
-    const int64_t bid = blockIdx.x;
+// Block b works on XCD b % 8's range, so a problem's tiles share an L2.
+__global__ __launch_bounds__(320, 2) void crt_mfma_batch_kernel(const CrtBatchItem* __restrict__ items,
+                                                                int64_t count, int N, int mods, CrtXcdRanges xr) {
+    const int x = (int)(blockIdx.x % kXcds);
+    const int64_t bid = xr.xcd[x] + blockIdx.x / kXcds;
+    if (bid >= xr.xcd[x + 1]) return;
     const CrtBatchItem& it = items[crt_batch_find(items, count, bid, 2)];
     const int64_t local = bid - it.b[2], tms = it.Mp / 128, tiles = tms * (it.Np / 128);
     const int64_t tile = local % tiles;
     const int mod0 = (int)(local / tiles) * mods;
     const int mod1 = mod0 + mods < N ? mod0 + mods : N;
-    crt_mfma_block<128, 128, 2, 2, 8>(it.RA, it.RB, it.Y, it.Mp, it.Np, it.Kp, N, tile % tms, tile / tms, mod0,
-                                      mod1);
+    crt_mfma_block_cw<128, 128, 2, 2, 8>(it.RA, it.RB, it.Y, it.Mp, it.Np, it.Kp, N, tile % tms, tile / tms, mod0,
+                                         mod1);
 }
 
 // Stage 4: per problem (Mp / 128) ceil(n / 2) blocks, as in the single call.
@@ -1298,7 +1425,7 @@ constexpr int kBatchCfg = 2;        // 128 x 128 product tiles, two workgroups p
 int crt_batch_moduli(int64_t kmax, int s) { return crt_moduli_count(kmax, s); }
 
 size_t crt_batch_item_bytes(int64_t m, int64_t n, int64_t k, int N) {
-    return crt_layout(m, n, k, N, kBatchCfg).total;
+    return crt_layout(m, n, k, N, kBatchCfg, kTileK).total;
 }
 
 int crt_batch_plan(int N, int s, int64_t count, const GemmArgs* gs, void* ws, CrtBatchItem* items,
@@ -1309,39 +1436,47 @@ int crt_batch_plan(int N, int s, int64_t count, const GemmArgs* gs, void* ws, Cr
     in.N = N;
     int64_t tiles = 0;
     for (int64_t q = 0; q < count; ++q) {
-        const CrtLayout L = crt_layout(gs[q].m, gs[q].n, gs[q].k, N, kBatchCfg);
+        const CrtLayout L = crt_layout(gs[q].m, gs[q].n, gs[q].k, N, kBatchCfg, kTileK);
         tiles += (L.Mp / 128) * (L.Np / 128);
     }
     const CrtGroups gr = crt_groups(tiles, kCrt[kBatchCfg].per_cu, N);
     in.mods = gr.mods;
     in.groups = gr.groups;
     size_t off = 0;
-    for (int64_t q = 0; q < count; ++q) {
-        const GemmArgs& g = gs[q];
-        const CrtLayout L = crt_layout(g.m, g.n, g.k, N, kBatchCfg);
-        if (items) {
-            char* base = (char*)ws + off;
-            CrtBatchItem& it = items[q];
-            it.g = g;
-            it.E = (int32_t*)(base + L.oE);
-            it.F = (int32_t*)(base + L.oF);
-            it.RA = (int8_t*)(base + L.oRA);
-            it.RB = (int8_t*)(base + L.oRB);
-            it.Y = (uint8_t*)(base + L.oY);
-            it.Mp = L.Mp;
-            it.Np = L.Np;
-            it.Kp = L.Kp;
-            for (int f = 0; f < 4; ++f) it.b[f] = in.blocks[f];
+    int64_t pos = 0, widest = 0;
+    for (int x = 0; x < kXcds; ++x) {
+        in.ranges.xcd[x] = in.blocks[2];
+        for (int64_t q = x; q < count; q += kXcds, ++pos) {
+            const GemmArgs& g = gs[q];
+            const CrtLayout L = crt_layout(g.m, g.n, g.k, N, kBatchCfg, kTileK);
+            if (items) {
+                char* base = (char*)ws + off;
+                CrtBatchItem& it = items[pos];
+                it.g = g;
+                it.E = (int32_t*)(base + L.oE);
+                it.F = (int32_t*)(base + L.oF);
+                it.RA = (int8_t*)(base + L.oRA);
+                it.RB = (int8_t*)(base + L.oRB);
+                it.Y = (uint8_t*)(base + L.oY);
+                it.Mp = L.Mp;
+                it.Np = L.Np;
+                it.Kp = L.Kp;
+                for (int f = 0; f < 4; ++f) it.b[f] = in.blocks[f];
+            }
+            in.blocks[0] += L.Mp / 4 + L.Np / 4;
+            in.blocks[1] += (L.Kp / kTileK) * (L.Mp / kResRows + L.Np / kResRows);
+            in.blocks[2] += (L.Mp / 128) * (L.Np / 128) * gr.groups;
+            in.blocks[3] += L.Mp / kRec3Rows * ((g.n + 1) / 2);
+            off += L.total;                          // each total is a multiple of 256
         }
-        in.blocks[0] += L.Mp / 4 + L.Np / 4;
-        in.blocks[1] += (L.Kp / kTileK) * (L.Mp / kResRows + L.Np / kResRows);
-        in.blocks[2] += (L.Mp / 128) * (L.Np / 128) * gr.groups;
-        in.blocks[3] += L.Mp / kRec3Rows * ((g.n + 1) / 2);
-        off += L.total;                              // each total is a multiple of 256
+        widest = std::max<int64_t>(widest, in.blocks[2] - in.ranges.xcd[x]);
     }
+    in.ranges.xcd[kXcds] = in.blocks[2];
     in.ws_bytes = off;
+    in.grid2 = widest * kXcds;
     for (int f = 0; f < 4; ++f)
         if (in.blocks[f] > 0x7fffffffLL) return MPGEMM_ERR_UNSUPPORTED;
+    if (in.grid2 > 0x7fffffffLL) return MPGEMM_ERR_UNSUPPORTED;
     if (info) *info = in;
     return 0;
 }
@@ -1367,8 +1502,8 @@ int launch_crt_batch(int P, int s, const CrtBatchInfo& info, const CrtBatchItem*
     }
 #undef MPG_RESB
     if ((rc = (int)hipGetLastError())) return rc;
-    hipLaunchKernelGGL(crt_mfma_batch_kernel, dim3((unsigned)info.blocks[2]), dim3(256), 0, st, d_items, count,
-                       N, info.mods);
+    hipLaunchKernelGGL(crt_mfma_batch_kernel, dim3((unsigned)info.grid2), dim3(320), 0, st, d_items, count, N,
+                       info.mods, info.ranges);
     if ((rc = (int)hipGetLastError())) return rc;
     const int K = limbs_for(N);
     const CrtRecConsts rcs = crt_rec_consts(N, K);

@@ -126,11 +126,19 @@ struct CrtBatchItem {
     int64_t Mp, Np, Kp;
     int64_t b[4];
 };
+// The product stage's blocks on XCD x (block b runs on XCD b % 8) are
+// b[2]-indices xcd[x] .. xcd[x + 1] - 1: whole problems, so that the tiles
+// sharing a problem's residue panels share that XCD's L2.
+struct CrtXcdRanges {
+    int64_t xcd[9];
+};
 struct CrtBatchInfo {
     int N;                 // moduli of every problem (those the largest k needs)
     int mods, groups;      // product stage: planes per workgroup, workgroups per tile
     size_t ws_bytes;       // workspace of all problems
-    int64_t blocks[4];     // grid of each stage
+    int64_t blocks[4];     // blocks of each stage (the grid of stages 1, 2, 4)
+    CrtXcdRanges ranges;   // product stage
+    int64_t grid2;         // its grid: 8 times the most blocks of one XCD
 };
 // The last item whose first block of stage f is at most bid (the same for
 // every lane of the block).
@@ -149,8 +157,9 @@ int crt_batch_moduli(int64_t kmax, int s);
 // Workspace one problem takes in a batch with N moduli (a multiple of 256).
 size_t crt_batch_item_bytes(int64_t m, int64_t n, int64_t k, int N);
 // Sizes the batch (items == nullptr) or also lays it out in ws and fills
-// items (host array of count).  Problems must be valid with m, n, k > 0 and
-// k no larger than N moduli serve.  Returns 0, or MPGEMM_ERR_UNSUPPORTED when
+// items (host array of count; problem q goes to XCD q % 8 in the product
+// stage, and the items are ordered by XCD, then by q).  Problems must be
+// valid with m, n, k > 0 and k no larger than N moduli serve.  Returns 0, or MPGEMM_ERR_UNSUPPORTED when
 // N is out of range or a stage's grid would exceed 2^31 - 1 blocks.
 int crt_batch_plan(int N, int s, int64_t count, const GemmArgs* gs, void* ws, CrtBatchItem* items,
                    CrtBatchInfo* info);

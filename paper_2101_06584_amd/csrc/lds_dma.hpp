@@ -36,6 +36,10 @@ __device__ __forceinline__ void wait_vm_barrier() {
 
 __device__ __forceinline__ void wait_vm_all() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
+// Wait for this wave's LDS reads, then meet the other waves (no wait on its
+// vector-memory operations: its global stores stay in flight).
+__device__ __forceinline__ void wait_lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // One 16-byte direct-to-LDS copy: lane L of the wave writes LDS bytes
 // [lds + 16 L, lds + 16 L + 16) (lds uniform across the wave).
 __device__ __forceinline__ void copy16_to_lds(const int8_t* g, int8_t* lds) {

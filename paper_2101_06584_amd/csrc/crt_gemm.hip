@@ -555,8 +555,10 @@ __device__ __forceinline__ void crt_mfma_block(const int8_t* __restrict__ RA, co
 // waves issue no loads: they wait only for their LDS reads, and the stores
 // of each modulus's residues never hold up a later step.  With the copies
 // in every wave, those stores share the counter with the copies in flight,
-// so the first step of each modulus waited for the whole ring; on short k
-// panels (a few steps per modulus) that wait dominated.
+// so the first step of each modulus waits for the whole ring.  That matters
+// on short k panels (a few steps per modulus: the batched form, 11% there);
+// on long ones the single-call kernels measured the same or slower with the
+// extra wave, so they keep the copies in the MFMA waves.
 template <int BM, int BN, int WGM, int WGN, int D>
 struct CrtDmaCw {
     static constexpr int NW = WGM * WGN;                  // MFMA waves; wave NW copies

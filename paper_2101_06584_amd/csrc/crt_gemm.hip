@@ -695,6 +695,12 @@ __global__ __launch_bounds__(64 * WGM * WGN, 2) void crt_mfma_kernel(const int8_
 
 // KH 32-byte k-tiles per step (32 KH MFMAs per wave between barriers); the
 // ring holds D steps.
+// The wide kernel issues its next fill's copies one at a time after the
+// step's MFMAs kCopyFirst, kCopyFirst + kCopyGap, ... rather than in a burst
+// before them.
+constexpr bool kSpreadCopies = true;
+constexpr int kCopyFirst = 8, kCopyGap = 2;
+
 template <int KH>
 struct WideCfg {
     static constexpr int NT = 256, BM = 256, BN = 256, WM = 128, WN = 128, FM = 4, FN = 4;
@@ -766,6 +772,21 @@ __global__ __launch_bounds__(256, 1) void crt_mfma_wide_kernel(const int8_t* __r
         }
         fslot = (fslot + 1 == D) ? 0 : fslot + 1;
     };
+    // one copy of that fill (KH == 1): A round c / 2 for even c, B for odd;
+    // the last one moves the cursor
+    auto issue_part = [&](auto cc) __attribute__((always_inline)) {
+        constexpr int c = decltype(cc)::value, h = c / 2;
+        int8_t* la = lds + fslot * W::STAGE + wave_lds;
+        if constexpr (c % 2 == 0) copy16_to_lds(fa + gofs[h], la + W::ROUND * h);
+        else copy16_to_lds(fb + gofs[h], la + W::B_OFF + W::ROUND * h);
+        if constexpr (c == 2 * W::LOADS - 1) {
+            if (++fstep < steps) {
+                fa += tileA;
+                fb += tileB;
+            }
+            fslot = (fslot + 1 == D) ? 0 : fslot + 1;
+        }
+    };
 
     v16i acc[W::FM][W::FN];
 #pragma unroll
@@ -796,7 +817,7 @@ __global__ __launch_bounds__(256, 1) void crt_mfma_wide_kernel(const int8_t* __r
         // would wait on the fragment reads just issued for them
         __builtin_amdgcn_sched_barrier(0);
         wait_vm_barrier<W::PER_STEP * (D - 2)>();
-        issue();                                   // step u + D into step u's slot
+        if constexpr (!(KH == 1 && kSpreadCopies)) issue();   // step u + D into step u's slot
         if constexpr (KH == 1) {
             // the next step's eight fragment reads, one after each of the
             // first eight MFMAs: issued in a burst they stall the wave
@@ -808,6 +829,9 @@ __global__ __launch_bounds__(256, 1) void crt_mfma_wide_kernel(const int8_t* __r
                                                                    0, 0, 0);
                 if constexpr (q < W::FM) fra[nxt][0][q] = *(const v4i*)(st + aofs[q]);
                 else if constexpr (q < W::FM + W::FN) frb[nxt][0][q - W::FM] = *(const v4i*)(st + bofs[q - W::FM]);
+                if constexpr (kSpreadCopies && q >= kCopyFirst && (q - kCopyFirst) % kCopyGap == 0 &&
+                              (q - kCopyFirst) / kCopyGap < 2 * W::LOADS)
+                    issue_part(std::integral_constant<int, (q - kCopyFirst) / kCopyGap>{});   // step u + D
                 __builtin_amdgcn_sched_barrier(0);
             });
         } else {

@@ -419,6 +419,12 @@ __device__ __forceinline__ uint32_t reduce_word(const v16i& x, int v4, double md
     return word;
 }
 
+// The product kernels issue each fill's copies one at a time between the
+// step's MFMAs rather than in a burst before them (the wide kernel after
+// MFMAs kCopyFirst, kCopyFirst + kCopyGap, ...).
+constexpr bool kSpreadCopies = true;
+constexpr int kCopyFirst = 8, kCopyGap = 2;
+
 template <int BM, int BN, int WGM, int WGN, int D>
 struct CrtDma {
     static constexpr int NT = 64 * WGM * WGN;             // threads
@@ -482,17 +488,22 @@ __device__ __forceinline__ void crt_mfma_block(const int8_t* __restrict__ RA, co
     const int8_t* fa = RA + (int64_t)mod0 * nkt * stepA + m0 * kCrtTileK;
     const int8_t* fb = RB + (int64_t)mod0 * nkt * stepB + n0 * kCrtTileK;
     int fstep = 0, fslot = 0;
-    auto issue = [&]() __attribute__((always_inline)) {
+    // copy c of a fill (A rounds first, then B); the last one moves the cursor
+    auto issue_part = [&](auto cc) __attribute__((always_inline)) {
+        constexpr int c = decltype(cc)::value;
         int8_t* la = lds + fslot * T::STAGE + wave_lds;
-#pragma unroll
-        for (int h = 0; h < T::A_LOADS; ++h) copy16_to_lds(fa + gofs[h], la + T::ROUND * h);
-#pragma unroll
-        for (int h = 0; h < T::B_LOADS; ++h) copy16_to_lds(fb + gofs[h], la + T::A_BYTES + T::ROUND * h);
-        if (++fstep < steps) {
-            fa += stepA;
-            fb += stepB;
+        if constexpr (c < T::A_LOADS) copy16_to_lds(fa + gofs[c], la + T::ROUND * c);
+        else copy16_to_lds(fb + gofs[c - T::A_LOADS], la + T::A_BYTES + T::ROUND * (c - T::A_LOADS));
+        if constexpr (c == T::PER_STEP - 1) {
+            if (++fstep < steps) {
+                fa += stepA;
+                fb += stepB;
+            }
+            fslot = (fslot + 1 == D) ? 0 : fslot + 1;
         }
-        fslot = (fslot + 1 == D) ? 0 : fslot + 1;
+    };
+    auto issue = [&]() __attribute__((always_inline)) {
+        static_for<T::PER_STEP>([&](auto c) __attribute__((always_inline)) { issue_part(c); });
     };
 
     v16i acc[T::FM][T::FN];
@@ -508,7 +519,7 @@ __device__ __forceinline__ void crt_mfma_block(const int8_t* __restrict__ RA, co
         // step u's tiles are in; every wave is past step u - 1, whose slot is
         // refilled now
         wait_vm_barrier<T::PER_STEP * (D - 2)>();
-        issue();
+        if constexpr (!kSpreadCopies) issue();
         const int8_t* st = lds + cslot * T::STAGE;
         cslot = (cslot + 1 == D) ? 0 : cslot + 1;
         v4i fa_[T::FM], fb_[T::FN];
@@ -516,11 +527,16 @@ __device__ __forceinline__ void crt_mfma_block(const int8_t* __restrict__ RA, co
         for (int i = 0; i < T::FM; ++i) fa_[i] = *(const v4i*)(st + aofs[i]);
 #pragma unroll
         for (int jj = 0; jj < T::FN; ++jj) fb_[jj] = *(const v4i*)(st + bofs[jj]);
-#pragma unroll
-        for (int i = 0; i < T::FM; ++i)
-#pragma unroll
-            for (int jj = 0; jj < T::FN; ++jj)
-                acc[i][jj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa_[i], fb_[jj], acc[i][jj], 0, 0, 0);
+        // the next fill's copies one after each MFMA (the rest after the last)
+        static_for<T::FM * T::FN>([&](auto qc) __attribute__((always_inline)) {
+            constexpr int q = decltype(qc)::value, i = q / T::FN, jj = q % T::FN;
+            acc[i][jj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa_[i], fb_[jj], acc[i][jj], 0, 0, 0);
+            if constexpr (kSpreadCopies && q < T::PER_STEP) issue_part(std::integral_constant<int, q>{});
+            if constexpr (kSpreadCopies && q == T::FM * T::FN - 1)
+                static_for<T::PER_STEP>([&](auto c) __attribute__((always_inline)) {
+                    if constexpr (decltype(c)::value > q) issue_part(c);
+                });
+        });
         if (++kt < nkt) continue;
 
         // last k-tile of modulus `mod`: reduce, store, clear
@@ -695,11 +711,7 @@ __global__ __launch_bounds__(64 * WGM * WGN, 2) void crt_mfma_kernel(const int8_
 
 // KH 32-byte k-tiles per step (32 KH MFMAs per wave between barriers); the
 // ring holds D steps.
-// The wide kernel issues its next fill's copies one at a time after the
-// step's MFMAs kCopyFirst, kCopyFirst + kCopyGap, ... rather than in a burst
-// before them.
-constexpr bool kSpreadCopies = true;
-constexpr int kCopyFirst = 8, kCopyGap = 2;
+
 
 template <int KH>
 struct WideCfg {

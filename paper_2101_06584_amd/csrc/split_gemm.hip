@@ -287,6 +287,8 @@ __global__ __launch_bounds__(256) void slice_kernel(SliceOperand oa, SliceOperan
 // is held in accumulator register v.
 // ---------------------------------------------------------------------------
 
+constexpr bool kDiagSpreadCopies = true;
+
 template <int BM, int BN, int G, int D>
 struct DiagDma {
     static constexpr int WM = BM / 2, WN = BN / 2;       // wave block
@@ -388,19 +390,25 @@ __global__ __launch_bounds__(256, 2) void diag_mfma_kernel(const int8_t* __restr
         fa = A0 + (int64_t)(fd1 - 2) * sliceA + (int64_t)fkt * ktA;
         fb = B0 + (int64_t)fkt * ktB;
     };
-    auto issue = [&](auto rslot) __attribute__((always_inline)) {   // copy into ring slot R
-        constexpr int R = decltype(rslot)::value;
+    // copies of one fill into ring slot R: op(A)'s (part 0) and op(B)'s (part
+    // 1, which then moves the cursor), or both (part 2)
+    auto issue = [&](auto rslot, auto partc) __attribute__((always_inline)) {
+        constexpr int R = decltype(rslot)::value, part = decltype(partc)::value;
         int8_t* la = lds + R * T::STAGE + wave_lds;
+        if constexpr (part != 1) {
 #pragma unroll
-        for (int h = 0; h < T::A_LOADS; ++h)
-            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(fa + gofs[h]),
-                                             (__attribute__((address_space(3))) void*)(la + 4096 * h), 16, 0, 0);
+            for (int h = 0; h < T::A_LOADS; ++h)
+                __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(fa + gofs[h]),
+                                                 (__attribute__((address_space(3))) void*)(la + 4096 * h), 16, 0, 0);
+        }
+        if constexpr (part != 0) {
 #pragma unroll
-        for (int h = 0; h < T::B_LOADS; ++h)
-            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(fb + gofs[h]),
-                                             (__attribute__((address_space(3))) void*)(la + T::A_BYTES + 4096 * h),
-                                             16, 0, 0);
-        fnext();
+            for (int h = 0; h < T::B_LOADS; ++h)
+                __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(fb + gofs[h]),
+                                                 (__attribute__((address_space(3))) void*)(la + T::A_BYTES + 4096 * h),
+                                                 16, 0, 0);
+            fnext();
+        }
     };
 
     v16i acc[G][T::FM][T::FN];
@@ -413,7 +421,7 @@ __global__ __launch_bounds__(256, 2) void diag_mfma_kernel(const int8_t* __restr
     v4i wb[G][T::KS][T::FN];   // B fragments of the last G steps, slot = step % G
 
     // prologue: steps 0 .. D-2 into ring slots 0 .. D-2 (a pass has >= D steps)
-    static_for<D - 1>([&](auto r) __attribute__((always_inline)) { issue(r); });
+    static_for<D - 1>([&](auto r) __attribute__((always_inline)) { issue(r, std::integral_constant<int, 2>{}); });
 
     // compute cursor: pass (cd0, cd1, ckt) of length cL, block start r0
     int cd0 = 2, cd1 = min(G + 1, last_d), ckt = 0;
@@ -427,7 +435,7 @@ __global__ __launch_bounds__(256, 2) void diag_mfma_kernel(const int8_t* __restr
                 // this step's tiles are in; every wave is past the previous
                 // step, whose ring slot RF is refilled now
                 wait_vm_barrier<T::PER_STEP * (D - 2)>();
-                issue(std::integral_constant<int, RF>{});
+                if constexpr (!kDiagSpreadCopies) issue(std::integral_constant<int, RF>{}, std::integral_constant<int, 2>{});
 
                 const int8_t* st = lds + R * T::STAGE;
                 v4i fa_[T::KS][T::FM];
@@ -443,8 +451,8 @@ __global__ __launch_bounds__(256, 2) void diag_mfma_kernel(const int8_t* __restr
                 // S_{d1 - j}; padding steps (p < 1) have none
                 const int r = r0 + rr;
                 const int nv = (r <= cd1 - 2) ? min(gsz, r + 1) : 0;
-#pragma unroll
-                for (int j = 0; j < G; ++j) {
+                static_for<G>([&](auto jc) __attribute__((always_inline)) {
+                    constexpr int j = decltype(jc)::value;
                     if (j < nv) {
 #pragma unroll
                         for (int ks = 0; ks < T::KS; ++ks)
@@ -455,7 +463,13 @@ __global__ __launch_bounds__(256, 2) void diag_mfma_kernel(const int8_t* __restr
                                     acc[j][i][jj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
                                         fa_[ks][i], wb[(W - j + G) % G][ks][jj], acc[j][i][jj], 0, 0, 0);
                     }
-                }
+                    // the next fill's copies after this step's first MFMAs
+                    // rather than in a burst before them
+                    if constexpr (kDiagSpreadCopies && G == 1)
+                        issue(std::integral_constant<int, RF>{}, std::integral_constant<int, 2>{});
+                    else if constexpr (kDiagSpreadCopies && j < 2)
+                        issue(std::integral_constant<int, RF>{}, std::integral_constant<int, j>{});
+                });
             });
         }
         if (++ckt < nkt) continue;

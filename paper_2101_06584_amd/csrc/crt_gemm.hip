@@ -419,6 +419,21 @@ __device__ __forceinline__ uint32_t reduce_word(const v16i& x, int v4, double md
     return word;
 }
 
+// Reduced residues of 32 x 32 accumulator tile x into its place in a plane
+// (column-major, rows contiguous).  Lane L holds rows 8 v4 + 4 (L / 32) + 0..3
+// of column L % 32 in word v4; two lane swaps (upper half of the first
+// operand with lower half of the second) leave lane L < 32 with rows 0..15
+// and lane L + 32 with rows 16..31 of its column, so each lane writes one
+// 16-byte run instead of four 4-byte words.  p: the lane's own first row
+// (row 4 (L / 32) of its column); hi = L / 32.
+__device__ __forceinline__ void store_tile(uint8_t* p, const v16i& x, double md, double inv, int hi) {
+    const uint32_t w0 = reduce_word(x, 0, md, inv), w1 = reduce_word(x, 1, md, inv);
+    const uint32_t w2 = reduce_word(x, 2, md, inv), w3 = reduce_word(x, 3, md, inv);
+    const auto s02 = __builtin_amdgcn_permlane32_swap(w0, w2, false, false);   // (w0 | w2), (w0' | w2')
+    const auto s13 = __builtin_amdgcn_permlane32_swap(w1, w3, false, false);
+    *(v4i*)(p + 12 * hi) = v4i{(int)s02[0], (int)s02[1], (int)s13[0], (int)s13[1]};
+}
+
 // The product kernels issue each fill's copies one at a time between the
 // step's MFMAs rather than in a burst before them (the wide kernel after
 // MFMAs kCopyFirst, kCopyFirst + kCopyGap, ...).
@@ -550,9 +565,7 @@ __device__ __forceinline__ void crt_mfma_block(const int8_t* __restrict__ RA, co
             for (int jj = 0; jj < T::FN; ++jj) {
                 const int64_t col = n0 + wn * T::WN + jj * 32 + (lane & 31);
                 const int64_t rowb = m0 + wm * T::WM + i * 32 + 4 * (lane >> 5);
-#pragma unroll
-                for (int v4 = 0; v4 < 4; ++v4)
-                    *(uint32_t*)(Yt + col * Mp + rowb + 8 * v4) = reduce_word(acc[i][jj], v4, md, inv);
+                store_tile(Yt + col * Mp + rowb, acc[i][jj], md, inv, lane >> 5);
                 acc[i][jj] = v16i{0};
             }
         // no drain: the waits stay sufficient with stores outstanding (see
@@ -676,9 +689,7 @@ __device__ __forceinline__ void crt_mfma_block_cw(const int8_t* __restrict__ RA,
             for (int jj = 0; jj < T::FN; ++jj) {
                 const int64_t col = n0 + wn * T::WN + jj * 32 + (lane & 31);
                 const int64_t rowb = m0 + wm * T::WM + i * 32 + 4 * (lane >> 5);
-#pragma unroll
-                for (int v4 = 0; v4 < 4; ++v4)
-                    *(uint32_t*)(Yt + col * Mp + rowb + 8 * v4) = reduce_word(acc[i][jj], v4, md, inv);
+                store_tile(Yt + col * Mp + rowb, acc[i][jj], md, inv, lane >> 5);
                 acc[i][jj] = v16i{0};
             }
         kt = 0;
@@ -875,9 +886,7 @@ __global__ __launch_bounds__(256, 1) void crt_mfma_wide_kernel(const int8_t* __r
 #pragma unroll
             for (int jj = 0; jj < W::FN; ++jj) {
                 const int64_t tofs = (int64_t)(jj * 32) * Mp + i * 32;
-#pragma unroll
-                for (int v4 = 0; v4 < 4; ++v4)
-                    *(uint32_t*)(Yl + tofs + 8 * v4) = reduce_word(acc[i][jj], v4, md, inv);
+                store_tile(Yl + tofs, acc[i][jj], md, inv, lane >> 5);
                 acc[i][jj] = v16i{0};
                 __builtin_amdgcn_sched_barrier(0);      // one accumulator's temporaries at a time
             }

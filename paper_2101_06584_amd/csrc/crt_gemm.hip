@@ -62,6 +62,11 @@ struct CrtTables {
     int mod[kNumModuli];             // m_t
     double Md[kNumModuli + 1][kLimbs];                       // M as binary64 limbs
     double Wd[kNumModuli * (kNumModuli + 1) / 2][kLimbs];    // W as binary64 limbs
+    // the one-level reconstruction's constants for N moduli:
+    // kc[N][l] = 128 sum_q B'_{4l+q} 256^q with B'_c = sum_{t<N} (byte c of
+    // W_t - 128), and r[N][l] = 2^(32 l) / M_N (M_N rounded to binary64)
+    double kc[kNumModuli + 1][kLimbs];
+    double r[kNumModuli + 1][kLimbs];
 };
 
 constexpr CrtTables make_crt_tables() {
@@ -94,6 +99,22 @@ constexpr CrtTables make_crt_tables() {
         for (int l = 0; l < kLimbs; ++l) t.Md[r][l] = (double)t.M[r][l];
     for (int r = 0; r < kNumModuli * (kNumModuli + 1) / 2; ++r)
         for (int l = 0; l < kLimbs; ++l) t.Wd[r][l] = (double)t.W[r][l];
+    for (int N = 1; N <= kNumModuli; ++N) {
+        const int row0 = N * (N - 1) / 2;
+        for (int l = 0; l < kLimbs; ++l) {
+            double kc = 0.0, p256 = 1.0;
+            for (int q = 0; q < 4; ++q, p256 *= 256.0) {
+                int64_t b = 0;
+                for (int i = 0; i < N; ++i) b += (int64_t)((t.W[row0 + i][l] >> (8 * q)) & 255u) - 128;
+                kc += 128.0 * (double)b * p256;
+            }
+            t.kc[N][l] = kc;
+        }
+        double md = 0.0;
+        for (int l = kLimbs - 1; l >= 0; --l) md = md * 4294967296.0 + (double)t.M[N][l];
+        double pw = 1.0 / md;                       // times 2^32 per limb: exact scalings
+        for (int l = 0; l < kLimbs; ++l, pw *= 4294967296.0) t.r[N][l] = pw;
+    }
     return t;
 }
 
@@ -976,11 +997,6 @@ constexpr int kRec3MaxN = 33;
 // direct-to-LDS copies.  Wave w forms entries 64 w .. 64 w + 63 in two groups
 // of 32; lane L ends with entry 64 w + L (the two halves of the wave trade
 // the limbs of opposite parity).
-struct CrtRecConsts {
-    double kc[kLimbs];               // 128 sum_q B'_{4l+q} 256^q
-    double r[kLimbs];                // 2^(32 l) / M_N
-};
-
 // Matrix-core limb sums for K limbs and NKB blocks of 32 moduli.
 template <int K, int NKB>
 struct LimbMfma {
@@ -1024,7 +1040,7 @@ __device__ __forceinline__ void cofactor_fragments(uint8_t* bt, int N, int tid,
 // then trade limbs of opposite parity so that lane L holds entry 64 w + L.
 template <int K, int NKB>
 __device__ __forceinline__ void limb_sums(const uint8_t* ysl, const v4i (&af)[LimbMfma<K, NKB>::NCB][NKB],
-                                          int N, int tid, const double (&kcs)[kLimbs], double (&L)[K]) {
+                                          int N, int tid, const double* __restrict__ kcs, double (&L)[K]) {
     using LM = LimbMfma<K, NKB>;
     constexpr int NCB = LM::NCB;
     const int lane = tid & 63, wave = tid >> 6, hi = lane >> 5;
@@ -1119,7 +1135,7 @@ __device__ __forceinline__ void stage_residue_bytes(uint8_t* ys, const uint8_t* 
 template <int P, int K, int NKB>
 __device__ __forceinline__ void crt_recombine_block(const GemmArgs& g, const int32_t* __restrict__ E,
                                                     const int32_t* __restrict__ F, const uint8_t* __restrict__ Y,
-                                                    int N, int s, int64_t Mp, int64_t Np, const CrtRecConsts& rc,
+                                                    int N, int s, int64_t Mp, int64_t Np,
                                                     int64_t blk) {
     using LM = LimbMfma<K, NKB>;
     // room for 32 NKB planes: the fragments read every slot (bytes of planes
@@ -1133,12 +1149,12 @@ __device__ __forceinline__ void crt_recombine_block(const GemmArgs& g, const int
     v4i af[LM::NCB][NKB];
     cofactor_fragments<K, NKB>(bt, N, tid, af);
     double L[K];
-    limb_sums<K, NKB>(ys, af, N, tid, rc.kc, L);
+    limb_sums<K, NKB>(ys, af, N, tid, kCrtDev.kc[N], L);
     const int64_t i = i0 + (tid & (kRec3Rows - 1)), j = j0 + tid / kRec3Rows;
     if (i >= g.m || j >= g.n) return;
     double f = 0.0;
 #pragma unroll
-    for (int l = 0; l < K; ++l) f = fma(L[l], rc.r[l], f);
+    for (int l = 0; l < K; ++l) f = fma(L[l], kCrtDev.r[N][l], f);
     crt_finish_entry<P, K>(g, L, f, N, E[i] + F[j] - 14 * s, i, j);
 }
 
@@ -1146,8 +1162,8 @@ template <int P, int K, int NKB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void crt_recombine_mfma_kernel(GemmArgs g, const int32_t* __restrict__ E,
                                                                  const int32_t* __restrict__ F,
                                                                  const uint8_t* __restrict__ Y, int N, int s,
-                                                                 int64_t Mp, int64_t Np, CrtRecConsts rc) {
-    crt_recombine_block<P, K, NKB>(g, E, F, Y, N, s, Mp, Np, rc, blockIdx.x);
+                                                                 int64_t Mp, int64_t Np) {
+    crt_recombine_block<P, K, NKB>(g, E, F, Y, N, s, Mp, Np, blockIdx.x);
 }
 
 // Two levels (digit integers cut into a high and a low half, A' = A_h 2^w +
@@ -1185,7 +1201,7 @@ template <int P, int SLO, int NKB>
 __global__ __launch_bounds__(256) void crt_recombine3_kernel(GemmArgs g, const int32_t* __restrict__ E,
                                                              const int32_t* __restrict__ F,
                                                              const uint8_t* __restrict__ Y, int N,
-                                                             int s, int64_t Mp, int64_t Np, CrtRecConsts rc) {
+                                                             int s, int64_t Mp, int64_t Np) {
     constexpr int K = 8;                          // each partial below 2^255 (N <= 33)
     constexpr int w = 7 * SLO;
     using LM = LimbMfma<K, NKB>;
@@ -1205,10 +1221,10 @@ __global__ __launch_bounds__(256) void crt_recombine3_kernel(GemmArgs g, const i
     static_for<3>([&](auto setc) __attribute__((always_inline)) {
         constexpr int set = decltype(setc)::value;     // 0: hh, 1: ll, 2: ss
         double L[K];
-        limb_sums<K, NKB>(ys + set * N * 2 * kRec3Rows, af, N, tid, rc.kc, L);
+        limb_sums<K, NKB>(ys + set * N * 2 * kRec3Rows, af, N, tid, kCrtDev.kc[N], L);
         double f = 0.0;
 #pragma unroll
-        for (int l = 0; l < K; ++l) f = fma(L[l], rc.r[l], f);
+        for (int l = 0; l < K; ++l) f = fma(L[l], kCrtDev.r[N][l], f);
         const double q = rint(f);
         uint32_t x[K];
         int64_t carry = 0;
@@ -1314,10 +1330,10 @@ __global__ __launch_bounds__(320, 2) void crt_mfma_batch_kernel(const CrtBatchIt
 // Stage 4: per problem (Mp / 128) ceil(n / 2) blocks, as in the single call.
 template <int P, int K, int NKB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void crt_recombine_batch_kernel(
-    const CrtBatchItem* __restrict__ items, int64_t count, int N, int s, CrtRecConsts rc) {
+    const CrtBatchItem* __restrict__ items, int64_t count, int N, int s) {
     const int64_t bid = blockIdx.x;
     const CrtBatchItem& it = items[crt_batch_find(items, count, bid, 3)];
-    crt_recombine_block<P, K, NKB>(it.g, it.E, it.F, it.Y, N, s, it.Mp, it.Np, rc, bid - it.b[3]);
+    crt_recombine_block<P, K, NKB>(it.g, it.E, it.F, it.Y, N, s, it.Mp, it.Np, bid - it.b[3]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1424,34 +1440,12 @@ int launch_crt_mfma(int cfg, const int8_t* RA, const int8_t* RB, uint8_t* Y, int
     return (int)hipGetLastError();
 }
 
-// kc_l = 128 sum_q B'_{4l+q} 256^q with B'_c = sum_{t<N} (byte c of W_t - 128),
-// and r_l = 2^(32 l) / M_N (M_N rounded to binary64).
-CrtRecConsts crt_rec_consts(int N, int K) {
-    const CrtTables& T = crt_host_tables();
-    CrtRecConsts rc{};
-    const int row0 = N * (N - 1) / 2;
-    for (int l = 0; l < K; ++l) {
-        double kc = 0.0;
-        for (int q = 0; q < 4; ++q) {
-            int64_t b = 0;
-            for (int t = 0; t < N; ++t) b += (int64_t)((T.W[row0 + t][l] >> (8 * q)) & 255u) - 128;
-            kc += 128.0 * (double)b * std::ldexp(1.0, 8 * q);
-        }
-        rc.kc[l] = kc;
-    }
-    double md = 0.0;
-    for (int l = kLimbs - 1; l >= 0; --l) md = md * 4294967296.0 + (double)T.M[N][l];
-    for (int l = 0; l < K; ++l) rc.r[l] = std::ldexp(1.0 / md, 32 * l);
-    return rc;
-}
-
 template <int P>
 int launch_crt_recombine_p(int K, dim3 grid, hipStream_t st, const GemmArgs& g, const int32_t* E,
                            const int32_t* F, const uint8_t* Y, int N, int s, int64_t Mp, int64_t Np) {
-    const CrtRecConsts rc = crt_rec_consts(N, K);
 #define MPG_REC(KV, NKB)                                                                                      \
     hipLaunchKernelGGL((crt_recombine_mfma_kernel<P, KV, NKB>), grid, dim3(256), 0, st, g, E, F, Y, N, s, Mp, \
-                       Np, rc)
+                       Np)
     if (N > 2 * 32) return (int)hipErrorInvalidValue;
     switch (K) {
     case 4: MPG_REC(4, 1); break;
@@ -1553,10 +1547,9 @@ int launch_crt_batch(int P, int s, const CrtBatchInfo& info, const CrtBatchItem*
                        info.mods, info.ranges);
     if ((rc = (int)hipGetLastError())) return rc;
     const int K = limbs_for(N);
-    const CrtRecConsts rcs = crt_rec_consts(N, K);
     const dim3 g3((unsigned)info.blocks[3]);
 #define MPG_RECB(PV, KV, NKB) \
-    hipLaunchKernelGGL((crt_recombine_batch_kernel<PV, KV, NKB>), g3, dim3(256), 0, st, d_items, count, N, s, rcs)
+    hipLaunchKernelGGL((crt_recombine_batch_kernel<PV, KV, NKB>), g3, dim3(256), 0, st, d_items, count, N, s)
 #define MPG_RECBP(PV)                                      \
     switch (K) {                                           \
     case 4: MPG_RECB(PV, 4, 1); break;                     \
@@ -1680,10 +1673,9 @@ int launch_crt(int P, int s, int cfg, const GemmArgs& g, void* ws, hipStream_t s
         const int64_t blocks = L.Mp / kRec3Rows * ((g.n + 1) / 2);
         if (blocks > 0x7fffffffLL) return (int)hipErrorInvalidConfiguration;
         const dim3 grid((unsigned)blocks);
-        const CrtRecConsts rc = crt_rec_consts(N, 8);
 #define MPG_REC3(SL, NKB)                                                                                    \
     hipLaunchKernelGGL((crt_recombine3_kernel<4, SL, NKB>), grid, dim3(256), 0, st, g, E, F, Y, N, s, L.Mp, \
-                       L.Np, rc)
+                       L.Np)
 #define MPG_REC3N(SL) \
     if (N > 32) MPG_REC3(SL, 2); else MPG_REC3(SL, 1)
         switch (pl.slo) {

@@ -624,8 +624,7 @@ int plan_residue_part(mpgemm_batch_plan* plan, int N, int s, size_t bound, const
     std::vector<CrtBatchItem> items((size_t)std::max<int64_t>(cnt, 1));
     for (const auto& r : ranges) {
         CrtChunk c{r.first, r.second, {}};
-        const int rc = crt_batch_plan(N, s, c.count, gs.data() + c.first, plan->d_ws, items.data() + c.first,
-                                      &c.info);
+        const int rc = crt_batch_plan(N, c.count, gs.data() + c.first, plan->d_ws, items.data() + c.first, &c.info);
         if (rc) return rc;
         plan->chunks.push_back(c);
     }

@@ -1469,9 +1469,7 @@ size_t crt_batch_item_bytes(int64_t m, int64_t n, int64_t k, int N) {
     return crt_layout(m, n, k, N, kBatchCfg, kTileK).total;
 }
 
-int crt_batch_plan(int N, int s, int64_t count, const GemmArgs* gs, void* ws, CrtBatchItem* items,
-                   CrtBatchInfo* info) {
-    (void)s;
+int crt_batch_plan(int N, int64_t count, const GemmArgs* gs, void* ws, CrtBatchItem* items, CrtBatchInfo* info) {
     if (N <= 0 || N > kNumModuli) return MPGEMM_ERR_UNSUPPORTED;
     CrtBatchInfo in{};
     in.N = N;

@@ -161,8 +161,7 @@ size_t crt_batch_item_bytes(int64_t m, int64_t n, int64_t k, int N);
 // stage, and the items are ordered by XCD, then by q).  Problems must be
 // valid with m, n, k > 0 and k no larger than N moduli serve.  Returns 0, or MPGEMM_ERR_UNSUPPORTED when
 // N is out of range or a stage's grid would exceed 2^31 - 1 blocks.
-int crt_batch_plan(int N, int s, int64_t count, const GemmArgs* gs, void* ws, CrtBatchItem* items,
-                   CrtBatchInfo* info);
+int crt_batch_plan(int N, int64_t count, const GemmArgs* gs, void* ws, CrtBatchItem* items, CrtBatchInfo* info);
 // The four stages on `stream` (d_items: device copy of the items).
 int launch_crt_batch(int P, int s, const CrtBatchInfo& info, const CrtBatchItem* d_items, int64_t count,
                      hipStream_t st);

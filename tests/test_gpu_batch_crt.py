@@ -199,3 +199,22 @@ def test_grouped_residue_calls(gpu_lib, P):
         w = oracle.gemm(P, p["transa"], p["transb"], p["m"], p["n"], p["k"], p["alpha"], p["A"], p["B"],
                         p["beta"], w)
         assert np.array_equal(host(dprobs[q]["C"]), w), q
+
+
+def test_batched_auto_qd_beyond_one_level_is_plain(gpu_lib):
+    """QD's default s = 31 has no one-level residue product: AUTO runs every
+    problem in the plain form (canonical bits), while SPLIT_CRT refuses it."""
+    P = 4
+    shapes = [(100, 90, 80), (70, 130, 65)]
+    probs = problem_set(P, shapes, 8100)
+    dprobs = to_dev(probs)
+    note("batched auto qd s=31")
+    plan = gpu_lib.BatchPlan(P, dprobs, form="auto", slices=31)
+    assert plan.info()["residue_problems"] == 0
+    plan.run()
+    for q, (p, d) in enumerate(zip(probs, dprobs)):
+        assert np.array_equal(host(d["C"]), want_of(P, 31, p, False)), q
+    plan.close()
+    with pytest.raises(gpu_lib.MPGemmError) as e:
+        gpu_lib.BatchPlan(P, to_dev(probs), form="crt", slices=31)
+    assert e.value.code == 3

@@ -404,7 +404,7 @@ typedef struct mpgemm_batch_plan mpgemm_batch_plan;  /* opaque */
  * extra moduli change no bit).  The plan owns the residue workspace
  * (problems padded to 128 x 128 product tiles, grouped into chunks that
  * run one after another, each within opts->workspace_bytes if nonzero, else
- * 1 GiB; opts->workspace itself is not used; mpgemm_batch_plan_residue_info
+ * 8 GiB; opts->workspace itself is not used; mpgemm_batch_plan_residue_info
  * reports the chunks and bytes).
  * The plan binds the device addresses in `problems`; their contents may
  * change between runs.

@@ -553,7 +553,7 @@ MPG_GEMV(mp_gemv_qd, 4)
 // bound (opts->workspace_bytes, else this default; a problem larger than it
 // forms a chunk of its own); the chunks run one after another on the plan's
 // stream and share one workspace.
-constexpr size_t kBatchChunkBytes = (size_t)1 << 30;
+constexpr size_t kBatchChunkBytes = (size_t)8 << 30;
 
 struct CrtChunk {
     int64_t first, count;     // items first .. first + count - 1

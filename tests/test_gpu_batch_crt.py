@@ -147,15 +147,15 @@ def test_batched_auto_chooses_per_problem(gpu_lib, P):
 
 
 def test_batched_residue_chunks(gpu_lib):
-    """More residue workspace than one chunk holds (1 GiB): several chunks
-    run one after another over one workspace; every problem's bits equal a
-    single residue-form call, and sampled blocks the oracle."""
+    """More residue workspace than one chunk holds (a 1 GiB bound): several
+    chunks run one after another over one workspace; every problem's bits
+    equal a single residue-form call, and sampled blocks the oracle."""
     P, s = 2, 16
     shapes = [(1536, 1536, 1536)] * 5 + [(1000, 1200, 1400)]
     probs = problem_set(P, shapes, 4242)
     dprobs = to_dev(probs)
     note("batched residue chunks", P)
-    plan = gpu_lib.BatchPlan(P, dprobs, form="crt", slices=s)
+    plan = gpu_lib.BatchPlan(P, dprobs, form="crt", slices=s, chunk_bytes=1 << 30)
     info = plan.info()
     assert info["chunks"] >= 2 and info["residue_problems"] == len(probs)
     refs = [single_call(gpu_lib, P, s, d) for d in dprobs]

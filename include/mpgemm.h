@@ -278,8 +278,8 @@ size_t mpgemm_workspace_bytes(int prec, int form, int64_t m, int64_t n, int64_t 
                               int tile);
 
 /*
- * Element-wise vector operations of Sec. 2.5 (the DD/TD/QD "element-wise
- * addition and multiplication of vectors"): r_i = x_i + y_i (add) or
+ * Element-wise vector operations of Sec. 2.5 (componentwise sums and
+ * products of DD/TD/QD vectors): r_i = x_i + y_i (add) or
  * x_i * y_i (mul), i < n, with each vector stored as P planes of n doubles at
  * plane strides sx, sy, sr (device pointers; r may equal x or y).
  * Arguments: 1 n >= 0, 2 x, 3 sx >= n, 4 y, 5 sy >= n, 6 r, 7 sr >= n, 8 stream.
@@ -359,7 +359,7 @@ int mp_gemv_qd(char trans, int64_t m, int64_t n, const double* alpha, const doub
                int64_t sy, hipStream_t stream);
 
 /*
- * Batched GEMMs of uneven shapes (Sec. 4's batched use of the kernels).
+ * Batched GEMMs of uneven shapes (an addition to the paper's single GEMM).
  * Plain form: one persistent launch, the same per-entry results as one
  * mpgemm_*() call per problem.  Residue form (opts->form
  * MPGEMM_FORM_SPLIT_CRT, or _AUTO with opts->slices > 0 for the problems the
@@ -414,9 +414,10 @@ int mpgemm_batch_plan_create(int prec, int64_t count, const mpgemm_problem* prob
                              mpgemm_batch_plan** out);
 /* Replay the captured graph on `stream`.  A plan holds one device tile
  * counter that each run (graph replay or direct launch) resets and then
- * consumes, so the runs of one plan must not overlap: queue them on one
- * stream, or order the streams (events).  Overlapping runs of the same plan
- * skip or repeat tiles and give wrong results; different plans are
+ * consumes, and one residue workspace that each run overwrites, so the runs
+ * of one plan must not overlap: queue them on one stream, or order the
+ * streams (events).  Overlapping runs of the same plan skip or repeat tiles
+ * or mix their residues and give wrong results; different plans are
  * independent. */
 int mpgemm_batch_plan_run(mpgemm_batch_plan* plan, hipStream_t stream);
 /* Same work as a direct launch (no graph) on `stream`; ordered like runs. */
@@ -433,8 +434,8 @@ int mpgemm_batch_plan_destroy(mpgemm_batch_plan* plan);
 
 /*
  * Grouped calls (the batched form in one call): all `count` problems of one
- * precision computed by one persistent launch replayed from a hipGraph, each
- * problem bitwise as one mpgemm_*() call.  The first call with a given
+ * precision computed by a batched plan replayed from a hipGraph, each problem
+ * bitwise as one single call in its form (plain, or residue with the same s).  The first call with a given
  * problem array (every field compared, device addresses included) builds a
  * plan as mpgemm_batch_plan_create does (device allocations, graph capture;
  * not to be called under stream capture); later calls with an equal array

@@ -397,11 +397,11 @@ typedef struct mpgemm_batch_plan mpgemm_batch_plan;  /* opaque */
  * uploads, 6 out (receives the plan).
  * Residue form: opts->slices = s digits (0 = the precision's default for
  * _SPLIT_CRT); every problem with m, n, k > 0 and alpha != 0 takes it, and
- * the plan returns MPGEMM_ERR_UNSUPPORTED when one has no one-level residue
- * product (s > 24 or k beyond its range); the rest (a zero alpha or
- * dimension) run in the plain part.  Every residue problem uses the moduli
- * that the largest k among them needs (the reconstruction is exact, so
- * extra moduli change no bit).  The plan owns the residue workspace
+ * the plan returns MPGEMM_ERR_UNSUPPORTED when one has no residue product
+ * (k beyond its range); the rest (a zero alpha or dimension) run in the
+ * plain part.  Every residue problem uses the moduli, and the levels (two
+ * for QD with s > 24, as in the single call), that the largest k among them
+ * needs (the reconstruction is exact, so extra moduli change no bit).  The plan owns the residue workspace
  * (problems padded to 128 x 128 product tiles, grouped into chunks that
  * run one after another, each within opts->workspace_bytes if nonzero, else
  * 8 GiB; opts->workspace itself is not used; mpgemm_batch_plan_residue_info
@@ -425,8 +425,9 @@ int mpgemm_batch_plan_launch(mpgemm_batch_plan* plan, hipStream_t stream);
 /* Plain part: total tiles, the persistent grid and its tile shape (for
  * reporting). */
 int mpgemm_batch_plan_info(const mpgemm_batch_plan* plan, int64_t* tiles, int* grid, int* tile_cfg);
-/* Residue part: problems, moduli per problem, chunks and the workspace bytes
- * the plan holds for them (any pointer may be NULL). */
+/* Residue part: problems, INT8 products per problem (as mpgemm_crt_moduli:
+ * N, or 3 N with two levels), chunks and the workspace bytes the plan holds
+ * for them (any pointer may be NULL). */
 int mpgemm_batch_plan_residue_info(const mpgemm_batch_plan* plan, int64_t* problems, int* moduli, int* chunks,
                                    size_t* workspace_bytes);
 /* Free the plan's device memory and graph (after its last run completed). */

@@ -597,8 +597,8 @@ bool plan_empty(const mpgemm_batch_plan* plan) { return plan->tiles == 0 && plan
 
 // The residue part: chunks laid out over one workspace, items copied to the
 // device (synchronously on st).  gs: the residue problems, largest first.
-int plan_residue_part(mpgemm_batch_plan* plan, int N, int s, size_t bound, const std::vector<GemmArgs>& gs,
-                      hipStream_t st) {
+int plan_residue_part(mpgemm_batch_plan* plan, const CrtPlan& pl, int s, size_t bound,
+                      const std::vector<GemmArgs>& gs, hipStream_t st) {
     const int64_t cnt = (int64_t)gs.size();
     plan->crt_s = s;
     plan->crt_count = cnt;
@@ -607,7 +607,7 @@ int plan_residue_part(mpgemm_batch_plan* plan, int N, int s, size_t bound, const
     size_t ws = 0, cur = 0;
     int64_t first = 0;
     for (int64_t q = 0; q < cnt; ++q) {
-        const size_t b = crt_batch_item_bytes(gs[(size_t)q].m, gs[(size_t)q].n, gs[(size_t)q].k, N);
+        const size_t b = crt_batch_item_bytes(gs[(size_t)q].m, gs[(size_t)q].n, gs[(size_t)q].k, pl.N * pl.sets);
         if (q > first && cur + b > bound) {
             ranges.emplace_back(first, q - first);
             first = q;
@@ -624,7 +624,7 @@ int plan_residue_part(mpgemm_batch_plan* plan, int N, int s, size_t bound, const
     std::vector<CrtBatchItem> items((size_t)std::max<int64_t>(cnt, 1));
     for (const auto& r : ranges) {
         CrtChunk c{r.first, r.second, {}};
-        const int rc = crt_batch_plan(N, c.count, gs.data() + c.first, plan->d_ws, items.data() + c.first, &c.info);
+        const int rc = crt_batch_plan(pl, c.count, gs.data() + c.first, plan->d_ws, items.data() + c.first, &c.info);
         if (rc) return rc;
         plan->chunks.push_back(c);
     }
@@ -668,10 +668,10 @@ int mpgemm_batch_plan_create(int prec, int64_t count, const mpgemm_problem* prob
         const bool mult = g.m > 0 && g.n > 0 && g.k > 0 && !mp_zero(P, g.alpha);
         bool r = false;
         if (form == MPGEMM_FORM_SPLIT_CRT && mult) {
-            if (crt_batch_moduli(g.k, s) == 0) return MPGEMM_ERR_UNSUPPORTED;
+            if (crt_plan(P, g.k, s).N == 0) return MPGEMM_ERR_UNSUPPORTED;
             r = true;
         } else if (form == MPGEMM_FORM_AUTO && mult && opts->slices > 0) {
-            r = g.m >= crt_min && g.n >= crt_min && g.k >= crt_min && crt_batch_moduli(g.k, s) > 0;
+            r = g.m >= crt_min && g.n >= crt_min && g.k >= crt_min && crt_plan(P, g.k, s).N > 0;
         }
         res[(size_t)q] = r;
         if (r) kmax = std::max(kmax, g.k);
@@ -718,7 +718,7 @@ int mpgemm_batch_plan_create(int prec, int64_t count, const mpgemm_problem* prob
                  hipStreamSynchronize(st) != hipSuccess))
         err = MPGEMM_ERR_HIP;
     const size_t bound = (opts && opts->workspace_bytes > 0) ? opts->workspace_bytes : kBatchChunkBytes;
-    if (!err && !gr.empty()) err = plan_residue_part(plan, crt_batch_moduli(kmax, s), s, bound, gr, st);
+    if (!err && !gr.empty()) err = plan_residue_part(plan, crt_plan(P, kmax, s), s, bound, gr, st);
     // capture every launch of a run on a private stream
     hipStream_t cs = nullptr;
     if (!err && !plan_empty(plan)) {
@@ -767,7 +767,7 @@ int mpgemm_batch_plan_residue_info(const mpgemm_batch_plan* plan, int64_t* probl
                                    size_t* workspace_bytes) {
     if (!plan) return -1;
     if (problems) *problems = plan->crt_count;
-    if (moduli) *moduli = plan->chunks.empty() ? 0 : plan->chunks[0].info.N;
+    if (moduli) *moduli = plan->chunks.empty() ? 0 : plan->chunks[0].info.N * plan->chunks[0].info.sets;
     if (chunks) *chunks = (int)plan->chunks.size();
     if (workspace_bytes) *workspace_bytes = plan->ws_bytes;
     return 0;

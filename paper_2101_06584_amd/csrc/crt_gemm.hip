@@ -1198,10 +1198,10 @@ __device__ __forceinline__ void add_shifted(uint32_t (&c)[kLimbsC], const uint32
 // set), and thread t finishes entry (row t % 128, column t / 128).
 
 template <int P, int SLO, int NKB>
-__global__ __launch_bounds__(256) void crt_recombine3_kernel(GemmArgs g, const int32_t* __restrict__ E,
-                                                             const int32_t* __restrict__ F,
-                                                             const uint8_t* __restrict__ Y, int N,
-                                                             int s, int64_t Mp, int64_t Np) {
+__device__ __forceinline__ void crt_recombine3_block(const GemmArgs& g, const int32_t* __restrict__ E,
+                                                     const int32_t* __restrict__ F,
+                                                     const uint8_t* __restrict__ Y, int N, int s, int64_t Mp,
+                                                     int64_t Np, int64_t blk) {
     constexpr int K = 8;                          // each partial below 2^255 (N <= 33)
     constexpr int w = 7 * SLO;
     using LM = LimbMfma<K, NKB>;
@@ -1209,7 +1209,7 @@ __global__ __launch_bounds__(256) void crt_recombine3_kernel(GemmArgs g, const i
     __shared__ __align__(16) uint8_t ys[(2 * kRec3MaxN + 32 * NKB) * 2 * kRec3Rows];
     __shared__ __align__(16) uint8_t bt[LM::kCols * LM::kMods];
     const int64_t tiles = Mp / kRec3Rows;
-    const int64_t i0 = (blockIdx.x % tiles) * kRec3Rows, j0 = 2 * (blockIdx.x / tiles);
+    const int64_t i0 = (blk % tiles) * kRec3Rows, j0 = 2 * (blk / tiles);
     const int tid = threadIdx.x;
     stage_residue_bytes<3 * kRec3MaxN>(ys, Y, 3 * N, Mp * Np, Mp, i0, j0, g.n, tid);
     v4i af[LM::NCB][NKB];
@@ -1278,6 +1278,14 @@ __global__ __launch_bounds__(256) void crt_recombine3_kernel(GemmArgs g, const i
     for (int p = 0; p < P; ++p) g.C[p * g.sc + off] = t.c[p];
 }
 
+template <int P, int SLO, int NKB>
+__global__ __launch_bounds__(256) void crt_recombine3_kernel(GemmArgs g, const int32_t* __restrict__ E,
+                                                             const int32_t* __restrict__ F,
+                                                             const uint8_t* __restrict__ Y, int N,
+                                                             int s, int64_t Mp, int64_t Np) {
+    crt_recombine3_block<P, SLO, NKB>(g, E, F, Y, N, s, Mp, Np, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // The four stages over a batch of problems (CrtBatchItem: each problem's
 // arguments, workspace regions and first block per stage).  A block finds
@@ -1287,10 +1295,11 @@ __global__ __launch_bounds__(256) void crt_recombine3_kernel(GemmArgs g, const i
 // ---------------------------------------------------------------------------
 
 // Stage 2: per problem (Kp / 64) (Mp / 16 + Np / 16) blocks, the k segment
-// fastest, op(A)'s row blocks first.
-template <int P, int NG>
+// fastest, op(A)'s row blocks first.  SETS = 3: two levels (QD), halves of
+// shi and s - shi digits.
+template <int P, int NG, int SETS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void crt_residue_batch_kernel(
-    const CrtBatchItem* __restrict__ items, int64_t count, CrtWeights wa, CrtWeights wb, int s, int N) {
+    const CrtBatchItem* __restrict__ items, int64_t count, CrtWeights wa, CrtWeights wb, int s, int N, int shi) {
     const int64_t bid = blockIdx.x;
     const CrtBatchItem& it = items[crt_batch_find(items, count, bid, 1)];
     const int64_t local = bid - it.b[1], segs = it.Kp / kTileK, ra = it.Mp / kResRows;
@@ -1301,8 +1310,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void c
                                 : ResOperand{g.A, g.ta ? g.lda : 1, g.ta ? 1 : g.lda, g.sa, g.m, it.E, it.RA, it.Mp};
     const CrtWeights* __restrict__ wt = second ? &wb : &wa;
     const int lane = threadIdx.x & 63;
-    constexpr int SETS = 1;
-    const int shi = s;
     v4i bw[SETS][NG];
     float mf[NG], invm[NG];
 #pragma unroll
@@ -1311,10 +1318,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void c
 }
 
 // Stage 3: per problem (Mp / 128) (Np / 128) tiles times `groups` workgroups
-// of `mods` planes each; the tile fastest, row tiles before column tiles.
-// Block b works on XCD b % 8's range, so a problem's tiles share an L2.
+// of `mods` of its `planes` planes each (plane t: modulus t % N); the tile
+// fastest, row tiles before column tiles.  Block b works on XCD b % 8's
+// range, so a problem's tiles share an L2.
 __global__ __launch_bounds__(320, 2) void crt_mfma_batch_kernel(const CrtBatchItem* __restrict__ items,
-                                                                int64_t count, int N, int mods, CrtXcdRanges xr) {
+                                                                int64_t count, int N, int planes, int mods,
+                                                                CrtXcdRanges xr) {
     const int x = (int)(blockIdx.x % kXcds);
     const int64_t bid = xr.xcd[x] + blockIdx.x / kXcds;
     if (bid >= xr.xcd[x + 1]) return;
@@ -1322,7 +1331,7 @@ __global__ __launch_bounds__(320, 2) void crt_mfma_batch_kernel(const CrtBatchIt
     const int64_t local = bid - it.b[2], tms = it.Mp / 128, tiles = tms * (it.Np / 128);
     const int64_t tile = local % tiles;
     const int mod0 = (int)(local / tiles) * mods;
-    const int mod1 = mod0 + mods < N ? mod0 + mods : N;
+    const int mod1 = mod0 + mods < planes ? mod0 + mods : planes;
     crt_mfma_block_cw<128, 128, 2, 2, 8>(it.RA, it.RB, it.Y, it.Mp, it.Np, it.Kp, N, tile % tms, tile / tms, mod0,
                                          mod1);
 }
@@ -1334,6 +1343,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void c
     const int64_t bid = blockIdx.x;
     const CrtBatchItem& it = items[crt_batch_find(items, count, bid, 3)];
     crt_recombine_block<P, K, NKB>(it.g, it.E, it.F, it.Y, N, s, it.Mp, it.Np, bid - it.b[3]);
+}
+
+// The same with two levels (QD): the three sets' planes follow one another.
+template <int P, int SLO, int NKB>
+__global__ __launch_bounds__(256) void crt_recombine3_batch_kernel(const CrtBatchItem* __restrict__ items,
+                                                                   int64_t count, int N, int s) {
+    const int64_t bid = blockIdx.x;
+    const CrtBatchItem& it = items[crt_batch_find(items, count, bid, 3)];
+    crt_recombine3_block<P, SLO, NKB>(it.g, it.E, it.F, it.Y, N, s, it.Mp, it.Np, bid - it.b[3]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1463,22 +1481,26 @@ constexpr int kBatchCfg = 2;        // 128 x 128 product tiles, two workgroups p
 
 }  // namespace
 
-int crt_batch_moduli(int64_t kmax, int s) { return crt_moduli_count(kmax, s); }
-
-size_t crt_batch_item_bytes(int64_t m, int64_t n, int64_t k, int N) {
-    return crt_layout(m, n, k, N, kBatchCfg, kTileK).total;
+size_t crt_batch_item_bytes(int64_t m, int64_t n, int64_t k, int planes) {
+    return crt_layout(m, n, k, planes, kBatchCfg, kTileK).total;
 }
 
-int crt_batch_plan(int N, int64_t count, const GemmArgs* gs, void* ws, CrtBatchItem* items, CrtBatchInfo* info) {
-    if (N <= 0 || N > kNumModuli) return MPGEMM_ERR_UNSUPPORTED;
+int crt_batch_plan(const CrtPlan& pl, int64_t count, const GemmArgs* gs, void* ws, CrtBatchItem* items,
+                   CrtBatchInfo* info) {
+    const int N = pl.N;
+    if (N <= 0 || N > kNumModuli || (pl.sets == 3 && N > kRec3MaxN)) return MPGEMM_ERR_UNSUPPORTED;
+    const int planes = N * pl.sets;
     CrtBatchInfo in{};
     in.N = N;
+    in.sets = pl.sets;
+    in.shi = pl.shi;
+    in.slo = pl.slo;
     int64_t tiles = 0;
     for (int64_t q = 0; q < count; ++q) {
-        const CrtLayout L = crt_layout(gs[q].m, gs[q].n, gs[q].k, N, kBatchCfg, kTileK);
+        const CrtLayout L = crt_layout(gs[q].m, gs[q].n, gs[q].k, planes, kBatchCfg, kTileK);
         tiles += (L.Mp / 128) * (L.Np / 128);
     }
-    const CrtGroups gr = crt_groups(tiles, kCrt[kBatchCfg].per_cu, N);
+    const CrtGroups gr = crt_groups(tiles, kCrt[kBatchCfg].per_cu, planes);
     in.mods = gr.mods;
     in.groups = gr.groups;
     size_t off = 0;
@@ -1487,7 +1509,7 @@ int crt_batch_plan(int N, int64_t count, const GemmArgs* gs, void* ws, CrtBatchI
         in.ranges.xcd[x] = in.blocks[2];
         for (int64_t q = x; q < count; q += kXcds, ++pos) {
             const GemmArgs& g = gs[q];
-            const CrtLayout L = crt_layout(g.m, g.n, g.k, N, kBatchCfg, kTileK);
+            const CrtLayout L = crt_layout(g.m, g.n, g.k, planes, kBatchCfg, kTileK);
             if (items) {
                 char* base = (char*)ws + off;
                 CrtBatchItem& it = items[pos];
@@ -1522,30 +1544,50 @@ int crt_batch_plan(int N, int64_t count, const GemmArgs* gs, void* ws, CrtBatchI
 
 int launch_crt_batch(int P, int s, const CrtBatchInfo& info, const CrtBatchItem* d_items, int64_t count,
                      hipStream_t st) {
-    const int N = info.N;
+    const int N = info.N, planes = N * info.sets;
     if (count <= 0) return 0;
+    if (info.sets == 3 && P != 4) return (int)hipErrorInvalidValue;
     int rc;
     if ((rc = launch_row_exponents_batch(d_items, count, info.blocks[0], st))) return rc;
-    const CrtWeights wa = crt_weights(N, s, s, true);
-    const CrtWeights wb = crt_weights(N, s, s, false);
+    const CrtWeights wa = crt_weights(N, s, info.shi, true);
+    const CrtWeights wb = crt_weights(N, s, info.shi, false);
     const dim3 g1((unsigned)info.blocks[1]);
-#define MPG_RESB(PV, NGV) \
-    hipLaunchKernelGGL((crt_residue_batch_kernel<PV, NGV>), g1, dim3(256), 0, st, d_items, count, wa, wb, s, N)
+#define MPG_RESB(PV, NGV, SV)                                                                            \
+    hipLaunchKernelGGL((crt_residue_batch_kernel<PV, NGV, SV>), g1, dim3(256), 0, st, d_items, count, wa, wb, s, \
+                       N, info.shi)
     const bool two = N > 32;
-    if (P == 2) {
-        if (two) MPG_RESB(2, 2); else MPG_RESB(2, 1);
+    if (info.sets == 3) {
+        if (two) MPG_RESB(4, 2, 3); else MPG_RESB(4, 1, 3);
+    } else if (P == 2) {
+        if (two) MPG_RESB(2, 2, 1); else MPG_RESB(2, 1, 1);
     } else if (P == 3) {
-        if (two) MPG_RESB(3, 2); else MPG_RESB(3, 1);
+        if (two) MPG_RESB(3, 2, 1); else MPG_RESB(3, 1, 1);
     } else {
-        if (two) MPG_RESB(4, 2); else MPG_RESB(4, 1);
+        if (two) MPG_RESB(4, 2, 1); else MPG_RESB(4, 1, 1);
     }
 #undef MPG_RESB
     if ((rc = (int)hipGetLastError())) return rc;
     hipLaunchKernelGGL(crt_mfma_batch_kernel, dim3((unsigned)info.grid2), dim3(320), 0, st, d_items, count, N,
-                       info.mods, info.ranges);
+                       planes, info.mods, info.ranges);
     if ((rc = (int)hipGetLastError())) return rc;
-    const int K = limbs_for(N);
     const dim3 g3((unsigned)info.blocks[3]);
+    if (info.sets == 3) {
+#define MPG_REC3B(SL, NKB) \
+    hipLaunchKernelGGL((crt_recombine3_batch_kernel<4, SL, NKB>), g3, dim3(256), 0, st, d_items, count, N, s)
+#define MPG_REC3BN(SL) \
+    if (N > 32) MPG_REC3B(SL, 2); else MPG_REC3B(SL, 1)
+        switch (info.slo) {
+        case 12: MPG_REC3BN(12); break;
+        case 13: MPG_REC3BN(13); break;
+        case 14: MPG_REC3BN(14); break;
+        case 15: MPG_REC3BN(15); break;
+        default: MPG_REC3BN(16); break;
+        }
+#undef MPG_REC3BN
+#undef MPG_REC3B
+        return (int)hipGetLastError();
+    }
+    const int K = limbs_for(N);
 #define MPG_RECB(PV, KV, NKB) \
     hipLaunchKernelGGL((crt_recombine_batch_kernel<PV, KV, NKB>), g3, dim3(256), 0, st, d_items, count, N, s)
 #define MPG_RECBP(PV)                                      \

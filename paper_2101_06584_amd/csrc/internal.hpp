@@ -134,6 +134,7 @@ struct CrtXcdRanges {
 };
 struct CrtBatchInfo {
     int N;                 // moduli of every problem (those the largest k needs)
+    int sets, shi, slo;    // 1 or 3 products per modulus (two levels: halves of shi, slo digits)
     int mods, groups;      // product stage: planes per workgroup, workgroups per tile
     size_t ws_bytes;       // workspace of all problems
     int64_t blocks[4];     // blocks of each stage (the grid of stages 1, 2, 4)
@@ -151,17 +152,17 @@ __device__ __forceinline__ int64_t crt_batch_find(const CrtBatchItem* __restrict
     }
     return lo;
 }
-// Moduli of a one-level residue product for inner dimensions up to kmax
-// with s digits (0: none serves).
-int crt_batch_moduli(int64_t kmax, int s);
-// Workspace one problem takes in a batch with N moduli (a multiple of 256).
-size_t crt_batch_item_bytes(int64_t m, int64_t n, int64_t k, int N);
+// Workspace one problem takes in a batch with `planes` residue planes per
+// operand (N, or 3N with two levels; a multiple of 256).
+size_t crt_batch_item_bytes(int64_t m, int64_t n, int64_t k, int planes);
 // Sizes the batch (items == nullptr) or also lays it out in ws and fills
 // items (host array of count; problem q goes to XCD q % 8 in the product
-// stage, and the items are ordered by XCD, then by q).  Problems must be
-// valid with m, n, k > 0 and k no larger than N moduli serve.  Returns 0, or MPGEMM_ERR_UNSUPPORTED when
-// N is out of range or a stage's grid would exceed 2^31 - 1 blocks.
-int crt_batch_plan(int N, int64_t count, const GemmArgs* gs, void* ws, CrtBatchItem* items, CrtBatchInfo* info);
+// stage, and the items are ordered by XCD, then by q).  pl: the residue
+// scheme (crt_plan) of the largest k; problems must be valid with m, n,
+// k > 0.  Returns 0, or MPGEMM_ERR_UNSUPPORTED when pl has no moduli or a
+// stage's grid would exceed 2^31 - 1 blocks.
+int crt_batch_plan(const CrtPlan& pl, int64_t count, const GemmArgs* gs, void* ws, CrtBatchItem* items,
+                   CrtBatchInfo* info);
 // The four stages on `stream` (d_items: device copy of the items).
 int launch_crt_batch(int P, int s, const CrtBatchInfo& info, const CrtBatchItem* d_items, int64_t count,
                      hipStream_t st);

@@ -184,8 +184,8 @@ def test_batch_plan_validation():
         x.B, x.ldb, x.b_plane_stride = FAKE_B, 4, 16
         x.C, x.ldc, x.c_plane_stride = FAKE_C, 4, 16
     # forms: plain, auto and residue only; options in range; the residue form
-    # needs a one-level product for every problem that multiplies (none for
-    # s > 24, QD's default of 31 included, or k beyond 131071)
+    # needs a residue product for every problem that multiplies (none for k
+    # beyond 131071, nor for s > 24 below QD, which alone has two levels)
     def opts(form, slices=0):
         o = _lib.Opts()
         o.form, o.slices, o.tile = form, slices, -1
@@ -194,10 +194,10 @@ def test_batch_plan_validation():
         assert L.mpgemm_batch_plan_create(2, 2, arr, C.byref(opts(form, 16)), None, C.byref(h)) == \
             _lib.ERR_UNSUPPORTED
     assert L.mpgemm_batch_plan_create(2, 2, arr, C.byref(opts(_lib.FORM_SPLIT_CRT, 99)), None, C.byref(h)) == -4
-    assert L.mpgemm_batch_plan_create(4, 2, arr, C.byref(opts(_lib.FORM_SPLIT_CRT, 25)), None, C.byref(h)) == \
-        _lib.ERR_UNSUPPORTED
-    assert L.mpgemm_batch_plan_create(4, 2, arr, C.byref(opts(_lib.FORM_SPLIT_CRT, 0)), None, C.byref(h)) == \
-        _lib.ERR_UNSUPPORTED
+    for P in (2, 3):
+        assert L.mpgemm_batch_plan_create(P, 2, arr, C.byref(opts(_lib.FORM_SPLIT_CRT, 25)), None,
+                                          C.byref(h)) == _lib.ERR_UNSUPPORTED
+    assert L.mpgemm_crt_moduli(4, 4, 25) > 0 and L.mpgemm_crt_moduli(4, 4, 31) > 0
     big = (_lib.Problem * 1)()
     x = big[0]
     x.transa = b"N"; x.transb = b"N"; x.m = 4; x.n = 4; x.k = 131072
@@ -205,8 +205,9 @@ def test_batch_plan_validation():
     x.A, x.lda, x.a_plane_stride = FAKE_A, 4, 4 * 131072
     x.B, x.ldb, x.b_plane_stride = FAKE_B, 131072, 4 * 131072
     x.C, x.ldc, x.c_plane_stride = FAKE_C, 4, 16
-    assert L.mpgemm_batch_plan_create(2, 1, big, C.byref(opts(_lib.FORM_SPLIT_CRT, 16)), None, C.byref(h)) == \
-        _lib.ERR_UNSUPPORTED
+    for P, sl in ((2, 16), (4, 0), (4, 20)):
+        assert L.mpgemm_batch_plan_create(P, 1, big, C.byref(opts(_lib.FORM_SPLIT_CRT, sl)), None,
+                                          C.byref(h)) == _lib.ERR_UNSUPPORTED
     arr[1].ldc = 2
     assert L.mpgemm_batch_plan_create(2, 2, arr, None, None, C.byref(h)) == -1001
 

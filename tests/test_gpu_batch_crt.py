@@ -18,6 +18,9 @@ from tests.gpu_util import dev, host, note
 pytestmark = pytest.mark.gpu
 
 SLICES = {2: 16, 3: 23, 4: 20}          # QD: a one-level digit count
+# (P, s): every precision at one level, and QD at two levels (s > 24), with
+# halves of equal (s even) and unequal (s odd, its default) digit counts
+PS = [(2, 16), (3, 23), (4, 20), (4, 31), (4, 26)]
 CRT_MIN = {2: 128, 3: 96, 4: 64}        # the single call's AUTO sizes
 
 
@@ -78,12 +81,11 @@ def single_call(gpu_lib, P, s, d):
 EDGE = [(1, 1, 1), (128, 128, 128), (129, 257, 65), (127, 1, 64), (3, 130, 129), (200, 64, 1)]
 
 
-@pytest.mark.parametrize("P", [2, 3, 4])
-def test_batched_residue_against_oracle(gpu_lib, P):
-    s = SLICES[P]
-    rng = synth.rng_for(11, P)
+@pytest.mark.parametrize("P,s", PS)
+def test_batched_residue_against_oracle(gpu_lib, P, s):
+    rng = synth.rng_for(11, 100 * P + s)
     shapes = [tuple(int(v) for v in r) for r in rng.integers(16, 200, size=(18, 3))] + EDGE
-    probs = problem_set(P, shapes, 500 * P)
+    probs = problem_set(P, shapes, 500 * P + s)
     probs.append(spread_problem(P, "N", "N", 40, 30, 20, 9001, alpha_zero=True))     # plain part
     k0 = spread_problem(P, "N", "N", 33, 17, 0, 9002)                               # k = 0
     k0["A"], k0["B"] = np.zeros((P, 1, 33)), np.zeros((P, 17, 1))   # leading dimensions >= 1
@@ -173,15 +175,14 @@ def test_batched_residue_chunks(gpu_lib):
         assert np.array_equal(got[:, c0:, r0:], want[:, c0:, r0:]), q
 
 
-@pytest.mark.parametrize("P", [2, 4])
-def test_grouped_residue_calls(gpu_lib, P):
+@pytest.mark.parametrize("P,s", [(2, 16), (4, 20), (4, 31)])
+def test_grouped_residue_calls(gpu_lib, P, s):
     """Grouped calls with the residue form: the cached plan is replayed by a
     second call with the same array (beta != 0: each call adds onto the
     last), and the form is part of the key (a plain call on the same array
     gets a plan of its own)."""
-    s = SLICES[P]
     shapes = [(100, 90, 80), (17, 200, 33), (130, 5, 129), (64, 64, 64)]
-    probs = problem_set(P, shapes, 3100 + P)
+    probs = problem_set(P, shapes, 3100 + P + s)
     for q, p in enumerate(probs):
         p["beta"] = synth.mp_uniform(np.random.Generator(np.random.PCG64(55 + q)), P, (1,))[:, 0]
     dprobs = to_dev(probs)
@@ -201,20 +202,23 @@ def test_grouped_residue_calls(gpu_lib, P):
         assert np.array_equal(host(dprobs[q]["C"]), w), q
 
 
-def test_batched_auto_qd_beyond_one_level_is_plain(gpu_lib):
-    """QD's default s = 31 has no one-level residue product: AUTO runs every
-    problem in the plain form (canonical bits), while SPLIT_CRT refuses it."""
-    P = 4
-    shapes = [(100, 90, 80), (70, 130, 65)]
+def test_batched_auto_qd_two_levels(gpu_lib):
+    """QD's default s = 31 takes two levels (hh, ll and ss products of one
+    modulus set): AUTO runs problems of at least 64 on every side in the
+    residue form, bit for bit as the oracle's, and the rest in the plain
+    form (canonical bits); the plan reports 3 N products."""
+    P, s = 4, 31
+    shapes = [(100, 90, 80), (70, 130, 65), (63, 200, 200), (64, 64, 64), (300, 64, 1000)]
     probs = problem_set(P, shapes, 8100)
     dprobs = to_dev(probs)
     note("batched auto qd s=31")
-    plan = gpu_lib.BatchPlan(P, dprobs, form="auto", slices=31)
-    assert plan.info()["residue_problems"] == 0
+    plan = gpu_lib.BatchPlan(P, dprobs, form="auto", slices=s)
+    res = [min(p["m"], p["n"], p["k"]) >= 64 for p in probs]
+    info = plan.info()
+    assert info["residue_problems"] == sum(res)
+    kmax = max(p["k"] for p, r in zip(probs, res) if r)
+    assert info["moduli"] == gpu_lib.crt_moduli(P, kmax, s) and info["moduli"] % 3 == 0
     plan.run()
-    for q, (p, d) in enumerate(zip(probs, dprobs)):
-        assert np.array_equal(host(d["C"]), want_of(P, 31, p, False)), q
+    for q, (p, d, r) in enumerate(zip(probs, dprobs, res)):
+        assert np.array_equal(host(d["C"]), want_of(P, s, p, r)), (q, r)
     plan.close()
-    with pytest.raises(gpu_lib.MPGemmError) as e:
-        gpu_lib.BatchPlan(P, to_dev(probs), form="crt", slices=31)
-    assert e.value.code == 3

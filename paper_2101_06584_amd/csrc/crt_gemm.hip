@@ -1290,8 +1290,8 @@ __global__ __launch_bounds__(256) void crt_recombine3_kernel(GemmArgs g, const i
 // The four stages over a batch of problems (CrtBatchItem: each problem's
 // arguments, workspace regions and first block per stage).  A block finds
 // its problem by binary search over the block prefixes and runs the single
-// call's block body on it; every problem has the same N moduli and s digits,
-// one level, 128 x 128 product tiles.
+// call's block body on it; every problem has the same N moduli, s digits and
+// levels (one, or two for QD: 3 N planes), and 128 x 128 product tiles.
 // ---------------------------------------------------------------------------
 
 // Stage 2: per problem (Kp / 64) (Mp / 16 + Np / 16) blocks, the k segment

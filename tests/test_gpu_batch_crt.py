@@ -148,15 +148,16 @@ def test_batched_auto_chooses_per_problem(gpu_lib, P):
     plan.close()
 
 
-def test_batched_residue_chunks(gpu_lib):
+@pytest.mark.parametrize("P,s", [(2, 16), (4, 31)])
+def test_batched_residue_chunks(gpu_lib, P, s):
     """More residue workspace than one chunk holds (a 1 GiB bound): several
     chunks run one after another over one workspace; every problem's bits
-    equal a single residue-form call, and sampled blocks the oracle."""
-    P, s = 2, 16
+    equal a single residue-form call, and sampled blocks the oracle (QD at
+    two levels too)."""
     shapes = [(1536, 1536, 1536)] * 5 + [(1000, 1200, 1400)]
-    probs = problem_set(P, shapes, 4242)
+    probs = problem_set(P, shapes, 4242 + s)
     dprobs = to_dev(probs)
-    note("batched residue chunks", P)
+    note("batched residue chunks", P, s)
     plan = gpu_lib.BatchPlan(P, dprobs, form="crt", slices=s, chunk_bytes=1 << 30)
     info = plan.info()
     assert info["chunks"] >= 2 and info["residue_problems"] == len(probs)

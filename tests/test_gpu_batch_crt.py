@@ -223,3 +223,20 @@ def test_batched_auto_qd_two_levels(gpu_lib):
     for q, (p, d, r) in enumerate(zip(probs, dprobs, res)):
         assert np.array_equal(host(d["C"]), want_of(P, s, p, r)), (q, r)
     plan.close()
+
+
+def test_batched_two_levels_of_33_moduli(gpu_lib):
+    """QD with s = 32 and one problem of k = 65536: the plan takes two levels
+    of 33 moduli (a second block of 32 per set in every stage) for all its
+    residue problems; each bit for bit as the oracle's residue form."""
+    P, s = 4, 32
+    shapes = [(20, 17, 65536), (70, 65, 100), (33, 129, 70)]
+    probs = problem_set(P, shapes, 8800)
+    dprobs = to_dev(probs)
+    note("batched two levels of 33 moduli")
+    plan = gpu_lib.BatchPlan(P, dprobs, form="crt", slices=s)
+    assert plan.info()["moduli"] == gpu_lib.crt_moduli(P, 65536, s) == 99
+    plan.run()
+    for q, (p, d) in enumerate(zip(probs, dprobs)):
+        assert np.array_equal(host(d["C"]), want_of(P, s, p, True)), q
+    plan.close()

@@ -56,6 +56,10 @@ CASES = [
     (2, "N", "N", 600, 40, 150, 16, 0),    # 768 vs 256 rows
     (3, "N", "T", 300, 9, 64, 23, 2),      # 384 vs 128
     (4, "T", "N", 20, 530, 90, 31, 1),     # two levels; 256 vs 640
+    # the largest modulus counts: 49 (all) at one level, and two levels of
+    # 33 (a second block of 32 moduli per set: s = 32, k = 65536)
+    (2, "N", "T", 70, 40, 50, 24, 0),      # 49 moduli, 11 limbs
+    (4, "T", "N", 20, 17, 65536, 32, 0),   # 3 x 33 moduli, 2048 k-tiles
 ]
 
 

@@ -7,5 +7,5 @@ from .api import (BatchPlan, DEFAULT_SLICES, MPGemmError, PREC, alloc_workspace,
                   crt_moduli, dot, dot_raw, dot_workspace, gemv, gemv_raw,
                   autotune_load, autotune_save, autotune_set, batch_autotune, gemm, gemm_noalloc,
                   gemm_noalloc_raw, gemm_raw, grouped, grouped_raw, load, problem_array,
-                  make_opts, num_configs, probe_peak, split_layout, split_stages, tune_slices, vec, vec_raw,
-                  version, workspace_bytes)
+                  make_opts, matmul, num_configs, probe_peak, split_layout, split_stages, tune_slices, vec,
+                  vec_raw, version, workspace_bytes)

@@ -150,6 +150,34 @@ def gemm(prec, transa, transb, m, n, k, alpha, A, B, beta, C_, **kw) -> None:
     _check(gemm_raw(prec, transa, transb, m, n, k, alpha, A, B, beta, C_, **kw), "mpgemm")
 
 
+def matmul(prec, A, B, C_=None, alpha=(1.0,), beta=(0.0,), **kw) -> torch.Tensor:
+    """Row-major product: C_ = alpha A B + beta C_ for A (P, m, k), B (P, k, n)
+    and C_ (P, m, n), each plane row-major with unit stride along a row;
+    returns C_ (allocated when None, which requires beta = 0: C_ is not read).
+
+    A row-major plane is the column-major plane of its transpose, so this is
+    the column-major call C^T = B^T A^T on the same buffers (m and n
+    swapped, B first).  Each product is therefore MUL(b_lj, a_il): bitwise
+    the canonical chain for DD, whose multiplication is symmetric, and for
+    TD and QD the canonical chain of the transposed problem (within the same
+    error bound).  Keyword arguments as for gemm."""
+    P = PREC[prec]
+    if A.dim() != 3 or B.dim() != 3 or A.shape[0] != P or B.shape[0] != P:
+        raise ValueError(f"expected A (P={P}, m, k) and B (P={P}, k, n)")
+    m, k = A.shape[1], A.shape[2]
+    if B.shape[1] != k:
+        raise ValueError(f"inner dimensions differ: A has k = {k}, B has {B.shape[1]} rows")
+    n = B.shape[2]
+    if C_ is None:
+        if any(float(x) != 0.0 for x in beta):
+            raise ValueError("beta != 0 needs C_")
+        C_ = torch.empty((P, m, n), dtype=torch.float64, device=A.device)
+    elif C_.dim() != 3 or tuple(C_.shape) != (P, m, n):
+        raise ValueError(f"expected C_ of shape {(P, m, n)}, got {tuple(C_.shape)}")
+    gemm(prec, "N", "N", n, m, k, alpha, B, A, beta, C_, **kw)
+    return C_
+
+
 def vec_raw(prec, op, x, y, r, n=None, stream=None) -> int:
     P = PREC[prec]
     L = _lib.load()

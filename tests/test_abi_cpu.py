@@ -330,3 +330,19 @@ def test_c_callers_get_the_tuned_tiles(tmp_path):
     lines = out.read_text().splitlines()
     assert lines[0].startswith("# mpgemm tuning table v2 arch=gfx950")
     assert all(len(l.split()) == 7 for l in lines[1:])
+
+
+def test_row_major_matmul_argument_checks():
+    """Shape checks of the row-major entry happen before any device call."""
+    import torch
+    import paper_2101_06584_amd as mp
+    A = torch.zeros((2, 4, 5), dtype=torch.float64)
+    B = torch.zeros((2, 6, 3), dtype=torch.float64)
+    with pytest.raises(ValueError, match="inner dimensions"):
+        mp.matmul(2, A, B)
+    with pytest.raises(ValueError, match="expected A"):
+        mp.matmul(3, A, torch.zeros((2, 5, 3), dtype=torch.float64))
+    with pytest.raises(ValueError, match="beta != 0"):
+        mp.matmul(2, A, torch.zeros((2, 5, 3), dtype=torch.float64), beta=(0.5, 0.0))
+    with pytest.raises(ValueError, match="expected C_"):
+        mp.matmul(2, A, torch.zeros((2, 5, 3), dtype=torch.float64), torch.zeros((2, 3, 4), dtype=torch.float64))

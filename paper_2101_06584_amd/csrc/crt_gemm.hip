@@ -458,7 +458,6 @@ __device__ __forceinline__ void store_tile(uint8_t* p, const v16i& x, double md,
 // The product kernels issue each fill's copies one at a time between the
 // step's MFMAs rather than in a burst before them (the wide kernel after
 // MFMAs kCopyFirst, kCopyFirst + kCopyGap, ...).
-constexpr bool kSpreadCopies = true;
 constexpr int kCopyFirst = 8, kCopyGap = 2;
 
 template <int BM, int BN, int WGM, int WGN, int D>
@@ -555,7 +554,6 @@ __device__ __forceinline__ void crt_mfma_block(const int8_t* __restrict__ RA, co
         // step u's tiles are in; every wave is past step u - 1, whose slot is
         // refilled now
         wait_vm_barrier<T::PER_STEP * (D - 2)>();
-        if constexpr (!kSpreadCopies) issue();
         const int8_t* st = lds + cslot * T::STAGE;
         cslot = (cslot + 1 == D) ? 0 : cslot + 1;
         v4i fa_[T::FM], fb_[T::FN];
@@ -567,8 +565,8 @@ __device__ __forceinline__ void crt_mfma_block(const int8_t* __restrict__ RA, co
         static_for<T::FM * T::FN>([&](auto qc) __attribute__((always_inline)) {
             constexpr int q = decltype(qc)::value, i = q / T::FN, jj = q % T::FN;
             acc[i][jj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa_[i], fb_[jj], acc[i][jj], 0, 0, 0);
-            if constexpr (kSpreadCopies && q < T::PER_STEP) issue_part(std::integral_constant<int, q>{});
-            if constexpr (kSpreadCopies && q == T::FM * T::FN - 1)
+            if constexpr (q < T::PER_STEP) issue_part(std::integral_constant<int, q>{});
+            if constexpr (q == T::FM * T::FN - 1)
                 static_for<T::PER_STEP>([&](auto c) __attribute__((always_inline)) {
                     if constexpr (decltype(c)::value > q) issue_part(c);
                 });
@@ -741,33 +739,29 @@ __global__ __launch_bounds__(64 * WGM * WGN, 2) void crt_mfma_kernel(const int8_
 // u the copies of step u + 1 must have landed and every wave must be done
 // reading step u's slot, which step u + D then refills.
 
-// KH 32-byte k-tiles per step (32 KH MFMAs per wave between barriers); the
+// One 32-byte k-tile per step (16 MFMAs per wave between barriers); the
 // ring holds D steps.
-
-
-template <int KH>
 struct WideCfg {
     static constexpr int NT = 256, BM = 256, BN = 256, WM = 128, WN = 128, FM = 4, FN = 4;
     static constexpr int SUB = BM * kCrtTileK;            // one operand's k-tile: 8 KiB
-    static constexpr int B_OFF = KH * SUB;
-    static constexpr int STAGE = 2 * KH * SUB;
+    static constexpr int B_OFF = SUB;
+    static constexpr int STAGE = 2 * SUB;
     static constexpr int ROUND = NT * 16;
     static constexpr int LOADS = SUB / ROUND;             // copy rounds per operand k-tile
-    static constexpr int PER_STEP = 2 * KH * LOADS;
-    static constexpr int D = KH == 1 ? 8 : 4;
+    static constexpr int PER_STEP = 2 * LOADS;
+    static constexpr int D = 8;
     static constexpr int LDS_BYTES = D * STAGE;
     static_assert(SUB % ROUND == 0, "whole copy rounds");
     static_assert(PER_STEP * (D - 1) <= 63, "vector-memory counter range");
     static_assert(LDS_BYTES <= 163840, "160 KiB of LDS per CU");
 };
 
-template <int KH>
 __global__ __launch_bounds__(256, 1) void crt_mfma_wide_kernel(const int8_t* __restrict__ RA,
                                                                const int8_t* __restrict__ RB,
                                                                uint8_t* __restrict__ Y, int64_t Mp,
                                                                int64_t Np, int64_t Kp, int N,
                                                                int Nmod, int mods) {
-    using W = WideCfg<KH>;
+    using W = WideCfg;
     constexpr int D = W::D;
     __shared__ __attribute__((aligned(1024))) int8_t lds[W::LDS_BYTES];
 
@@ -778,7 +772,7 @@ __global__ __launch_bounds__(256, 1) void crt_mfma_wide_kernel(const int8_t* __r
     const int lane = t & 63, wave = t >> 6;
     const int wm = wave % 2, wn = wave / 2;
     const int wave_lds = __builtin_amdgcn_readfirstlane(wave) * 1024;
-    const int spm = (int)(Kp / kCrtTileK) / KH;   // steps per modulus, even (Kp % (64 KH) == 0)
+    const int spm = (int)(Kp / kCrtTileK);        // steps per modulus, even (Kp % 64 == 0)
     // this workgroup's planes: mod0 .. mod1 - 1 (blockIdx.y < ceil(N / mods))
     const int mod0 = (int)blockIdx.y * mods;
     const int mod1 = mod0 + mods < N ? mod0 + mods : N;
@@ -798,26 +792,25 @@ __global__ __launch_bounds__(256, 1) void crt_mfma_wide_kernel(const int8_t* __r
 #pragma unroll
     for (int jj = 0; jj < W::FN; ++jj) bofs[jj] = W::B_OFF + swz32(wn * W::WN + jj * 32 + (lane & 31), lane >> 5);
 
-    const int8_t* fa = RA + (int64_t)mod0 * spm * KH * tileA + m0 * kCrtTileK;
-    const int8_t* fb = RB + (int64_t)mod0 * spm * KH * tileB + n0 * kCrtTileK;
+    const int8_t* fa = RA + (int64_t)mod0 * spm * tileA + m0 * kCrtTileK;
+    const int8_t* fb = RB + (int64_t)mod0 * spm * tileB + n0 * kCrtTileK;
     int fstep = 0, fslot = 0;
+    // the whole fill of one step (the prologue)
     auto issue = [&]() __attribute__((always_inline)) {
         int8_t* la = lds + fslot * W::STAGE + wave_lds;
 #pragma unroll
-        for (int kh = 0; kh < KH; ++kh)
-#pragma unroll
-            for (int h = 0; h < W::LOADS; ++h) {
-                copy16_to_lds(fa + kh * tileA + gofs[h], la + kh * W::SUB + W::ROUND * h);
-                copy16_to_lds(fb + kh * tileB + gofs[h], la + W::B_OFF + kh * W::SUB + W::ROUND * h);
-            }
+        for (int h = 0; h < W::LOADS; ++h) {
+            copy16_to_lds(fa + gofs[h], la + W::ROUND * h);
+            copy16_to_lds(fb + gofs[h], la + W::B_OFF + W::ROUND * h);
+        }
         if (++fstep < steps) {
-            fa += KH * tileA;
-            fb += KH * tileB;
+            fa += tileA;
+            fb += tileB;
         }
         fslot = (fslot + 1 == D) ? 0 : fslot + 1;
     };
-    // one copy of that fill (KH == 1): A round c / 2 for even c, B for odd;
-    // the last one moves the cursor
+    // one copy of that fill (in the loop): A round c / 2 for even c, B for
+    // odd; the last one moves the cursor
     auto issue_part = [&](auto cc) __attribute__((always_inline)) {
         constexpr int c = decltype(cc)::value, h = c / 2;
         int8_t* la = lds + fslot * W::STAGE + wave_lds;
@@ -837,23 +830,15 @@ __global__ __launch_bounds__(256, 1) void crt_mfma_wide_kernel(const int8_t* __r
     for (int i = 0; i < W::FM; ++i)
 #pragma unroll
         for (int jj = 0; jj < W::FN; ++jj) acc[i][jj] = v16i{0};
-    v4i fra[2][KH][W::FM], frb[2][KH][W::FN];
-    auto load_frags = [&](auto bufc, int slot) __attribute__((always_inline)) {
-        constexpr int b = decltype(bufc)::value;
-        const int8_t* st = lds + slot * W::STAGE;
-#pragma unroll
-        for (int kh = 0; kh < KH; ++kh) {
-#pragma unroll
-            for (int i = 0; i < W::FM; ++i) fra[b][kh][i] = *(const v4i*)(st + kh * W::SUB + aofs[i]);
-#pragma unroll
-            for (int jj = 0; jj < W::FN; ++jj) frb[b][kh][jj] = *(const v4i*)(st + kh * W::SUB + bofs[jj]);
-        }
-    };
+    v4i fra[2][W::FM], frb[2][W::FN];
 
     // prologue: steps 0 .. D-1 in flight, step 0 landed, its fragments read
     for (int r = 0; r < D; ++r) issue();
     wait_vm_barrier<W::PER_STEP * (D - 1)>();
-    load_frags(std::integral_constant<int, 0>{}, 0);
+#pragma unroll
+    for (int i = 0; i < W::FM; ++i) fra[0][i] = *(const v4i*)(lds + aofs[i]);
+#pragma unroll
+    for (int jj = 0; jj < W::FN; ++jj) frb[0][jj] = *(const v4i*)(lds + bofs[jj]);
 
     auto step = [&](auto curc, int u) __attribute__((always_inline)) {
         constexpr int cur = decltype(curc)::value, nxt = 1 - cur;
@@ -861,34 +846,22 @@ __global__ __launch_bounds__(256, 1) void crt_mfma_wide_kernel(const int8_t* __r
         // would wait on the fragment reads just issued for them
         __builtin_amdgcn_sched_barrier(0);
         wait_vm_barrier<W::PER_STEP * (D - 2)>();
-        if constexpr (!(KH == 1 && kSpreadCopies)) issue();   // step u + D into step u's slot
-        if constexpr (KH == 1) {
-            // the next step's eight fragment reads, one after each of the
-            // first eight MFMAs: issued in a burst they stall the wave
-            // (measured 2-3 % on the whole product at n = 4096)
-            const int8_t* st = lds + ((u + 1) % D) * W::STAGE;
-            static_for<W::FM * W::FN>([&](auto qc) {
-                constexpr int q = decltype(qc)::value, i = q / W::FN, jj = q % W::FN;
-                acc[i][jj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fra[cur][0][i], frb[cur][0][jj], acc[i][jj],
-                                                                   0, 0, 0);
-                if constexpr (q < W::FM) fra[nxt][0][q] = *(const v4i*)(st + aofs[q]);
-                else if constexpr (q < W::FM + W::FN) frb[nxt][0][q - W::FM] = *(const v4i*)(st + bofs[q - W::FM]);
-                if constexpr (kSpreadCopies && q >= kCopyFirst && (q - kCopyFirst) % kCopyGap == 0 &&
-                              (q - kCopyFirst) / kCopyGap < 2 * W::LOADS)
-                    issue_part(std::integral_constant<int, (q - kCopyFirst) / kCopyGap>{});   // step u + D
-                __builtin_amdgcn_sched_barrier(0);
-            });
-        } else {
-            load_frags(std::integral_constant<int, nxt>{}, (u + 1) % D);
-#pragma unroll
-            for (int kh = 0; kh < KH; ++kh)
-#pragma unroll
-                for (int i = 0; i < W::FM; ++i)
-#pragma unroll
-                    for (int jj = 0; jj < W::FN; ++jj)
-                        acc[i][jj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fra[cur][kh][i], frb[cur][kh][jj],
-                                                                           acc[i][jj], 0, 0, 0);
-        }
+        // the next step's eight fragment reads, one after each of the first
+        // eight MFMAs: issued in a burst they stall the wave (measured 2-3 %
+        // on the whole product at n = 4096); then the copies of step u + D
+        // into step u's slot, one after each of MFMAs kCopyFirst,
+        // kCopyFirst + kCopyGap, ...
+        const int8_t* st = lds + ((u + 1) % D) * W::STAGE;
+        static_for<W::FM * W::FN>([&](auto qc) {
+            constexpr int q = decltype(qc)::value, i = q / W::FN, jj = q % W::FN;
+            acc[i][jj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fra[cur][i], frb[cur][jj], acc[i][jj], 0, 0, 0);
+            if constexpr (q < W::FM) fra[nxt][q] = *(const v4i*)(st + aofs[q]);
+            else if constexpr (q < W::FM + W::FN) frb[nxt][q - W::FM] = *(const v4i*)(st + bofs[q - W::FM]);
+            if constexpr (q >= kCopyFirst && (q - kCopyFirst) % kCopyGap == 0 &&
+                          (q - kCopyFirst) / kCopyGap < 2 * W::LOADS)
+                issue_part(std::integral_constant<int, (q - kCopyFirst) / kCopyGap>{});
+            __builtin_amdgcn_sched_barrier(0);
+        });
     };
     const int64_t ybase = (n0 + wn * W::WN + (lane & 31)) * Mp + m0 + wm * W::WM + 4 * (lane >> 5);
     int u = 0;
@@ -1447,7 +1420,7 @@ int launch_crt_mfma(int cfg, const int8_t* RA, const int8_t* RB, uint8_t* Y, int
     // ring depths: the LDS of one CU (160 KiB) holds one wide workgroup's
     // ring or two of the others
     if (cfg == 0)
-        hipLaunchKernelGGL(crt_mfma_wide_kernel<1>, blocks, dim3(256), 0, st, RA, RB, Y, Mp, Np, Kp, N, Nmod,
+        hipLaunchKernelGGL(crt_mfma_wide_kernel, blocks, dim3(256), 0, st, RA, RB, Y, Mp, Np, Kp, N, Nmod,
                            gr.mods);
     else if (cfg == 1)
         hipLaunchKernelGGL((crt_mfma_kernel<256, 128, 2, 2, 6>), blocks, dim3(256), 0, st, RA, RB, Y, Mp, Np,

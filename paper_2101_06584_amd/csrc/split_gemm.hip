@@ -287,8 +287,6 @@ __global__ __launch_bounds__(256) void slice_kernel(SliceOperand oa, SliceOperan
 // is held in accumulator register v.
 // ---------------------------------------------------------------------------
 
-constexpr bool kDiagSpreadCopies = true;
-
 template <int BM, int BN, int G, int D>
 struct DiagDma {
     static constexpr int WM = BM / 2, WN = BN / 2;       // wave block
@@ -435,7 +433,6 @@ __global__ __launch_bounds__(256, 2) void diag_mfma_kernel(const int8_t* __restr
                 // this step's tiles are in; every wave is past the previous
                 // step, whose ring slot RF is refilled now
                 wait_vm_barrier<T::PER_STEP * (D - 2)>();
-                if constexpr (!kDiagSpreadCopies) issue(std::integral_constant<int, RF>{}, std::integral_constant<int, 2>{});
 
                 const int8_t* st = lds + R * T::STAGE;
                 v4i fa_[T::KS][T::FM];
@@ -465,9 +462,9 @@ __global__ __launch_bounds__(256, 2) void diag_mfma_kernel(const int8_t* __restr
                     }
                     // the next fill's copies after this step's first MFMAs
                     // rather than in a burst before them
-                    if constexpr (kDiagSpreadCopies && G == 1)
+                    if constexpr (G == 1)
                         issue(std::integral_constant<int, RF>{}, std::integral_constant<int, 2>{});
-                    else if constexpr (kDiagSpreadCopies && j < 2)
+                    else if constexpr (j < 2)
                         issue(std::integral_constant<int, RF>{}, std::integral_constant<int, j>{});
                 });
             });

@@ -440,7 +440,9 @@ int mpgemm_batch_plan_destroy(mpgemm_batch_plan* plan);
  * problem array (every field compared, device addresses included) builds a
  * plan as mpgemm_batch_plan_create does (device allocations, graph capture;
  * not to be called under stream capture); later calls with an equal array
- * replay it.  The library keeps the 8 most recently used plans; dropping one
+ * replay it.  The library keeps the 8 most recently used plans, each with
+ * its device memory (a residue plan's workspace up to the default 8 GiB
+ * chunk bound; opts->workspace_bytes is not used here); dropping one
  * synchronises the device first; mpgemm_finalize releases them.  Calls with
  * equal arrays reuse one plan, so they follow the plan rule: queue them on
  * one stream or order the streams.  Arguments: 1 count >= 0, 2 problems

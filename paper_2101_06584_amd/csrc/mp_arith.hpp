@@ -350,7 +350,12 @@ MPG_DEV bool renorm4_fast(double c0, double c1, double c2, double c3, double c4,
 // The first three outputs of Renorm (all a TD result keeps): when the first
 // two slots close, the third is sv3 if its error is non-zero and otherwise
 // the sum of the carry sv3 with e4 (whether or not that sum then closes the
-// slot, which only decides the dropped fourth output).
+// slot, which only decides the dropped fourth output).  That sum is sv3
+// itself when e4 = 0: with t2 != 0, sv3 = t2 + e3 is never -0, so adding
+// +0 changes no bit.  In the TD product's accumulation e4 is zero in
+// practice (the fourth components are zero) while t3 is zero about half of
+// the time, so the fast path takes r2 = sv3 when t3 != 0 or e4 = 0 and
+// leaves the rest (t3 = 0 with e4 != 0) to the general path.
 MPG_DEV bool renorm3_fast(double c0, double c1, double c2, double c3, double c4, double& r0,
                           double& r1, double& r2) {
     double s, e0, e1, e2, e3, e4;
@@ -363,8 +368,8 @@ MPG_DEV bool renorm3_fast(double c0, double c1, double c2, double c3, double c4,
     quick_two_sum(t2, e3, sv3, t3);
     r0 = e0;
     r1 = sv2;
-    r2 = (t3 != 0.0) ? sv3 : sv3 + e4;
-    return (e1 != 0.0) && (t2 != 0.0);
+    r2 = sv3;
+    return (e1 != 0.0) && (t2 != 0.0) && (t3 != 0.0 || e4 == 0.0);
 }
 
 MPG_DEV bool vseb2_fast(double e1, double e2, double e3, double& r1, double& r2) {

@@ -357,15 +357,22 @@ __device__ __forceinline__ void crt_residue_block(const ResOperand& o, const v4i
                 for (int eg = 0; eg < 2; ++eg)
 #pragma unroll
                     for (int v4 = 0; v4 < 4; ++v4) {
-                        uint32_t word = 0;
+                        uint32_t bits[4];
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
                             // |r| <= m / 2: a byte for m < 256; for m = 256
-                            // the low byte of r is congruent all the same
+                            // the low byte of r is congruent all the same.  r
+                            // is an integer far below 2^22, so 1.5 2^23 + r is
+                            // exact and its bit pattern is 0x4b400000 + r: the
+                            // low byte is r mod 256
                             const float a = (float)acc[eg][4 * v4 + q];
                             const float r = fmaf(-rintf(a * invm[cg]), mf[cg], a);
-                            word |= ((uint32_t)(int)r & 255u) << (8 * q);
+                            bits[q] = __float_as_uint(r + 0x1.8p23f);
                         }
+                        // the four low bytes in order: (0, 1) and (2, 3) pairwise, then both pairs
+                        const uint32_t word = __builtin_amdgcn_perm(__builtin_amdgcn_perm(bits[3], bits[2], 0x0c0c0400u),
+                                                                    __builtin_amdgcn_perm(bits[1], bits[0], 0x0c0c0400u),
+                                                                    0x05040100u);
                         // entries 32 eg + 8 v4 + 4 (lane / 32) + 0..3 of row 4 wave + rw
                         *(uint32_t*)(plane + (eg * kResRows + wave * 4 + rw) * kCrtTileK + 8 * v4 +
                                      4 * (lane >> 5)) = word;

@@ -832,11 +832,9 @@ __global__ __launch_bounds__(256, 1) void crt_mfma_wide_kernel(const int8_t* __r
         }
     };
 
+    // each modulus's first step starts its accumulators from zero (no
+    // clearing pass after the stores)
     v16i acc[W::FM][W::FN];
-#pragma unroll
-    for (int i = 0; i < W::FM; ++i)
-#pragma unroll
-        for (int jj = 0; jj < W::FN; ++jj) acc[i][jj] = v16i{0};
     v4i fra[2][W::FM], frb[2][W::FN];
 
     // prologue: steps 0 .. D-1 in flight, step 0 landed, its fragments read
@@ -847,8 +845,9 @@ __global__ __launch_bounds__(256, 1) void crt_mfma_wide_kernel(const int8_t* __r
 #pragma unroll
     for (int jj = 0; jj < W::FN; ++jj) frb[0][jj] = *(const v4i*)(lds + bofs[jj]);
 
-    auto step = [&](auto curc, int u) __attribute__((always_inline)) {
+    auto step = [&](auto curc, auto firstc, int u) __attribute__((always_inline)) {
         constexpr int cur = decltype(curc)::value, nxt = 1 - cur;
+        constexpr bool first = decltype(firstc)::value;   // a modulus's first step
         // keep each step's MFMAs after its barrier: hoisted above it they
         // would wait on the fragment reads just issued for them
         __builtin_amdgcn_sched_barrier(0);
@@ -861,7 +860,8 @@ __global__ __launch_bounds__(256, 1) void crt_mfma_wide_kernel(const int8_t* __r
         const int8_t* st = lds + ((u + 1) % D) * W::STAGE;
         static_for<W::FM * W::FN>([&](auto qc) {
             constexpr int q = decltype(qc)::value, i = q / W::FN, jj = q % W::FN;
-            acc[i][jj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fra[cur][i], frb[cur][jj], acc[i][jj], 0, 0, 0);
+            acc[i][jj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fra[cur][i], frb[cur][jj],
+                                                               first ? v16i{0} : acc[i][jj], 0, 0, 0);
             if constexpr (q < W::FM) fra[nxt][q] = *(const v4i*)(st + aofs[q]);
             else if constexpr (q < W::FM + W::FN) frb[nxt][q - W::FM] = *(const v4i*)(st + bofs[q - W::FM]);
             if constexpr (q >= kCopyFirst && (q - kCopyFirst) % kCopyGap == 0 &&
@@ -872,10 +872,17 @@ __global__ __launch_bounds__(256, 1) void crt_mfma_wide_kernel(const int8_t* __r
     };
     const int64_t ybase = (n0 + wn * W::WN + (lane & 31)) * Mp + m0 + wm * W::WM + 4 * (lane >> 5);
     int u = 0;
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using First = std::integral_constant<bool, true>;
+    using Next = std::integral_constant<bool, false>;
     for (int mod = mod0; mod < mod1; ++mod) {
-        for (int kk = 0; kk < spm; kk += 2, u += 2) {
-            step(std::integral_constant<int, 0>{}, u);
-            step(std::integral_constant<int, 1>{}, u + 1);
+        step(I0{}, First{}, u);
+        step(I1{}, Next{}, u + 1);
+        u += 2;
+        for (int kk = 2; kk < spm; kk += 2, u += 2) {
+            step(I0{}, Next{}, u);
+            step(I1{}, Next{}, u + 1);
         }
         // plane `mod` is modulus mod % Nmod of its residue set
         const int mi = mod % Nmod;
@@ -888,7 +895,6 @@ __global__ __launch_bounds__(256, 1) void crt_mfma_wide_kernel(const int8_t* __r
             for (int jj = 0; jj < W::FN; ++jj) {
                 const int64_t tofs = (int64_t)(jj * 32) * Mp + i * 32;
                 store_tile(Yl + tofs, acc[i][jj], md, inv, lane >> 5);
-                acc[i][jj] = v16i{0};
                 __builtin_amdgcn_sched_barrier(0);      // one accumulator's temporaries at a time
             }
         // no drain here: the stores share the vector-memory counter with the

@@ -206,8 +206,9 @@ int mpgemm_qd(char transa, char transb, int64_t m, int64_t n, int64_t k, const d
  * hh 128^(2 floor(s/2)) + (ss - hh - ll) 128^floor(s/2) + ll from the three
  * half-size products hh = A_h B_h, ll = A_l B_l, ss = (A_h + A_l)(B_h + B_l),
  * each from N <= 33 moduli: the same integer, so the same result.
- * MPGEMM_ERR_UNSUPPORTED otherwise (s > 24 for DD and TD, s > 32 for QD, or
- * k > 131071).  Deterministic; the exactly rounded product of the truncated
+ * MPGEMM_ERR_UNSUPPORTED otherwise (s > 24 for DD and TD, s > 32 for QD,
+ * k > 131071, or s = 24 with k > 114, where 49 moduli do not suffice: the
+ * count is taken from logarithms with a margin of 0.01 bit).  Deterministic; the exactly rounded product of the truncated
  * operands.  Workspace as for the split form, sized by
  * mpgemm_workspace_bytes(prec, MPGEMM_FORM_SPLIT_CRT, m, n, k, slices, tile).
  * opts->variant (TD, plain form only; MPGEMM_ERR_UNSUPPORTED for another

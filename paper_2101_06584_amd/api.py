@@ -119,8 +119,10 @@ def gemm_raw(prec, transa, transb, m, n, k, alpha, A, B, beta, C_, *, form=None,
     args = [transa.encode(), transb.encode(), m, n, k, _scalar(alpha, P), a, lda, sa, b, ldb, sb,
             _scalar(beta, P), c, ldc, sc, _stream(stream)]
     name = "mpgemm_" + _NAME[P]
-    if form is None and not variant:
+    if form is None and not variant and tile == -1 and workspace is None and not levels:
         return getattr(L, name)(*args)
+    # any option given (a tile, a workspace, ...) goes through the _ex call,
+    # so that it is never dropped silently
     return getattr(L, name + "_ex")(*args, C.byref(make_opts(form or "plain", slices, tile, workspace,
                                                                variant, levels)))
 

@@ -1,7 +1,8 @@
 """A seeded random sweep over precisions, transpose pairs, shapes (ragged
 against every tile), tile configurations, digit counts and alpha/beta,
 beyond the hand-picked cases of the other files: the plain form bit for bit
-as the oracle's canonical GEMM, the triangular split and the residue form bit
+as the oracle's canonical GEMM (for TD with a random choice of the TD
+addition and multiplication variants), the triangular split and the residue form bit
 for bit as the oracle's split and residue forms.  Operands carry a per-row
 and per-column exponent spread in half of the cases, so that the scale
 exponents differ from row to row."""
@@ -49,7 +50,9 @@ def draw(form, q):
 def test_random_case(gpu_lib, form, q):
     P, ta, tb, m, n, k, s, A, B, C, alpha, beta, rng = draw(form, q)
     tile = int(rng.integers(gpu_lib.num_configs(P, form)))
-    note("sweep", form, q, P, ta, tb, (m, n, k), "s", s, "tile", tile)
+    # TD plain: the accurate addition (Algorithm 3) and / or TDmulq in place of the defaults
+    variant = int(rng.integers(4)) if form == "plain" and P == 3 else 0
+    note("sweep", form, q, P, ta, tb, (m, n, k), "s", s, "tile", tile, "variant", variant)
     dC = dev(C)
     if form == "crt" and gpu_lib.crt_moduli(P, k, s) == 0:
         # more digits than the moduli hold at this k: refused before any GPU
@@ -60,8 +63,9 @@ def test_random_case(gpu_lib, form, q):
         while gpu_lib.crt_moduli(P, k, s) == 0:
             s -= 1
     if form == "plain":
-        gpu_lib.gemm(P, ta, tb, m, n, k, alpha, dev(A), dev(B), beta, dC, tile=tile)
-        want = oracle.gemm(P, ta, tb, m, n, k, alpha, A, B, beta, C)
+        gpu_lib.gemm(P, ta, tb, m, n, k, alpha, dev(A), dev(B), beta, dC, form="plain", tile=tile,
+                     variant=variant)
+        want = oracle.gemm(P, ta, tb, m, n, k, alpha, A, B, beta, C, variant=variant)
     else:
         ws = gpu_lib.alloc_workspace(P, m, n, k, s, tile, form=form)
         gpu_lib.gemm(P, ta, tb, m, n, k, alpha, dev(A), dev(B), beta, dC, form=form, slices=s, tile=tile,

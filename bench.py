@@ -44,14 +44,15 @@ HBM_PEAK = 8.0e12              # MI355X HBM3E, bytes/s
 # (SQ_INSTS_VALU_{ADD,MUL,FMA}_F64 x 64 / n^3 at n = 4096):
 #   DD: Algorithms 2 + 1:                    16 add, 3 mul, 1 FMA ->  20 ops,  21 flops
 #   TD: Algorithm 4 + TDaddq (Algorithm 5 on zero fourth components, whose
-#       all-constant operations fold):     108 add, 3 mul, 6 FMA -> 117 ops, 123 flops
+#       all-constant operations fold and whose TwoSum(+0, carry) error, always
+#       +0, is not formed):                104 add, 3 mul, 6 FMA -> 113 ops, 119 flops
 #   QD: Algorithms 6 + 5:                   184 add, 10 mul, 6 FMA -> 200 ops, 206 flops
 # The kernels issue a few more vector instructions per multiply-add than that
 # (compares and selects of the Renorm/VSEB test, LDS address arithmetic):
-# 21.2 (DD), 126.0 (TD), 210.6 (QD) in all; VALU_PER_MAC gives the issue-slot use.
-INSTR_PER_MAC = {2: 20, 3: 117, 4: 200}
-FLOPS_PER_MAC = {2: 21, 3: 123, 4: 206}
-VALU_PER_MAC = {2: 21.2, 3: 126.0, 4: 210.6}
+# 21.2 (DD), 122.0 (TD), 210.6 (QD) in all; VALU_PER_MAC gives the issue-slot use.
+INSTR_PER_MAC = {2: 20, 3: 113, 4: 200}
+FLOPS_PER_MAC = {2: 21, 3: 119, 4: 206}
+VALU_PER_MAC = {2: 21.2, 3: 122.0, 4: 210.6}
 NAME = {2: "DD", 3: "TD", 4: "QD"}
 PAPER_CONTEXT = {
     "note": "paper's CPU seconds for C := AB, n = 4096 (AVX2 + OpenMP); other hardware, context only",

@@ -218,6 +218,32 @@ MPG_DEV void qd_add_terms(double x0, double x1, double x2, double x3, double y0,
     c[4] = (carry + carry2) + er[3];
 }
 
+// qd_add_terms with zero fourth components (TDaddq), the same bits with four
+// operations fewer.  The fourth pair's TwoSum is +0 + +0: sum and error +0.
+// ThreeSum2 then starts with TwoSum(+0, carry): for finite carry its sum is
+// carry + 0 (carry, or +0 for carry = -0), and its error is +0 whatever carry
+// is: v = sum - 0 = sum, u = sum - v = +0, w = 0 - u = +0, u' = carry - v is
+// +0, or -0 when carry = -0, and w + u' = +0.  So the error's four operations
+// are dropped and ThreeSum2's last sum is +0 + t3, kept as such (it turns a
+// -0 into +0, as the general form does).
+MPG_DEV void td_add_terms(double x0, double x1, double x2, double y0, double y1, double y2,
+                          double (&c)[5]) {
+    const double x[3] = {x0, x1, x2}, y[3] = {y0, y1, y2};
+    double sm[3], er[3];
+    two_sum_lanes<3>(x, y, sm, er);
+    double carry = er[0], carry2 = er[1];
+    two_sum(sm[1], carry, sm[1], carry);
+    three_sum(sm[2], carry, carry2);
+    const double t1 = carry + 0.0;      // TwoSum(+0, carry)'s sum
+    double s3, t3;
+    two_sum(er[2], t1, s3, t3);
+    c[0] = sm[0];
+    c[1] = sm[1];
+    c[2] = sm[2];
+    c[3] = s3;
+    c[4] = (0.0 + t3 + carry2) + 0.0;
+}
+
 // Terms of the QD product (Algorithm 6) before its Renorm (c0..c4).  The
 // component products of order eps^0 to eps^2 (x_i y_j, i + j <= 2, taken
 // as (0,0), (0,1), (1,0), (0,2), (1,1), (2,0)) are split exactly by TwoProd
@@ -292,7 +318,7 @@ MPG_DEV mp<4> add(const mp<4>& x, const mp<4>& y) {
 // TDaddq: the QD addition with zero fourth components, fourth output dropped.
 MPG_DEV mp<3> add(const mp<3>& x, const mp<3>& y) {
     double t[5];
-    qd_add_terms(x.c[0], x.c[1], x.c[2], 0.0, y.c[0], y.c[1], y.c[2], 0.0, t);
+    td_add_terms(x.c[0], x.c[1], x.c[2], y.c[0], y.c[1], y.c[2], t);
     mp<3> r;
     double r3;
     renorm4(t[0], t[1], t[2], t[3], t[4], r.c[0], r.c[1], r.c[2], r3);
@@ -458,8 +484,8 @@ MPG_DEV void tile_mac(mp<3> (&acc)[TM][TN], const mp<3> (&a)[TM], const mp<3> (&
 #pragma unroll
         for (int c = 0; c < TN; ++c) {
             // TDaddq: Algorithm 5 with zero fourth components, fourth output dropped
-            qd_add_terms(acc[r][c].c[0], acc[r][c].c[1], acc[r][c].c[2], 0.0, prod[r][c].c[0],
-                         prod[r][c].c[1], prod[r][c].c[2], 0.0, t[r][c]);
+            td_add_terms(acc[r][c].c[0], acc[r][c].c[1], acc[r][c].c[2], prod[r][c].c[0],
+                         prod[r][c].c[1], prod[r][c].c[2], t[r][c]);
             ok = renorm3_fast(t[r][c][0], t[r][c][1], t[r][c][2], t[r][c][3], t[r][c][4],
                               acc[r][c].c[0], acc[r][c].c[1], acc[r][c].c[2]) && ok;
         }

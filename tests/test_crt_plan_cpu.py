@@ -14,9 +14,6 @@ import pytest
 
 import paper_2101_06584_amd as mp
 
-pytestmark = pytest.mark.filterwarnings("ignore")
-
-
 def greedy_moduli(count=49):
     out = []
     for m in range(256, 1, -1):

@@ -324,7 +324,8 @@ __global__ __launch_bounds__(256, 2) void diag_mfma_kernel(const int8_t* __restr
     __shared__ __attribute__((aligned(1024))) int8_t lds[T::LDS_BYTES];
 
     int64_t tm, tn;
-    if (!xcd_tile_coords<8>(blockIdx.x, Mp / BM, Np / BN, tm, tn)) return;
+    // groups of 4 tile rows per XCD: 1-2% faster than 2, 8 or 16 at n = 4096 and 8192
+    if (!xcd_tile_coords<4>(blockIdx.x, Mp / BM, Np / BN, tm, tn)) return;
     const int64_t m0 = tm * BM, n0 = tn * BN;
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
